@@ -1,0 +1,521 @@
+/*
+ * oracle.c - CPU oracle for binned triangle (3pCF) and 4-clique parity (4pCF)
+ * counts on the periodic r < rmax point graph.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library calls, links or
+ * loads this file; only the tests, the smoke check and the bench's CPU
+ * baseline do. It shares no code, header or table with the GPU library.
+ *
+ * It is deliberately plain and slow: full symmetric neighbour rows from a
+ * cell list, then for every hub the v1-style membership test by binary
+ * search (paper Sec. 2.2: "a binary search on N(j), costing O(log m)"), not
+ * the merge-walk the paper introduces in Sec. 3.1. The counts it produces are
+ * the plain definitions below; the merge-walk reaches the same sets faster.
+ *
+ * Definitions (floating point: IEEE binary64, round to nearest, no FMA
+ * contraction; compile with -ffp-contract=off and without -ffast-math):
+ *
+ * D1 separation a->b: per axis d = x_b - x_a; if d > L/2 then d -= L, else
+ *    if d < -L/2 then d += L (periodic box of the paper's test catalogue,
+ *    Sec. 4.1; the minimum-image rule is our reading). sep(b,a) = -sep(a,b)
+ *    exactly.
+ * D2 squared length q = (dx*dx + dy*dy) + dz*dz.
+ * D3 bins: equal-width radial bins from rmin to rmax (Sec. 4.1). With
+ *    D = (rmax - rmin)/nb, e_0 = rmin, e_k = rmin + k*D (0<k<nb), e_nb = rmax,
+ *    t_k = e_k*e_k: a pair is an edge iff t_0 <= q < t_nb, and its bin is the
+ *    number of k in 1..nb-1 with q >= t_k. The bin is one byte per edge as in
+ *    the paper's adjacency lists (Sec. 2.1), so nb <= 255.
+ * D5 3pCF: every unordered triangle (all three pairs edges) counts once into
+ *    the bin of its sorted side bins b1 <= b2 <= b3, indexed lexicographically
+ *    (the sorted-side configurations r1 <= r2 <= r3 of Sec. 5; C(nb+2,3) of
+ *    them). Weighted: t = (w1*w2)*w3 with the three weights in ascending
+ *    order; per bin the exact sum of t as a 128-bit integer multiple of
+ *    2^-s, where s = 52 - floor(log2(((wmin*wmin)*wmin))).
+ * D6 4pCF parity (Sec. 3.2, Eq. 2 and the degenerate rule): every 4-clique
+ *    contributes once per hub h (each of its four vertices): spokes r = sep(h,.)
+ *    ordered by q (qa <= qb <= qc); even[idx(bins)] += 1; c = ra x rb,
+ *    V = (cx*rcx + cy*rcy) + cz*rcz. Degenerate (no odd contribution) iff
+ *    qa == qb or qb == qc or V*V <= 1e-18*((qa*qb)*qc) (the paper's |V| < 1e-9
+ *    taken on the normalised volume); otherwise V > 0 -> pos, V < 0 -> neg.
+ *
+ * Anchors: only tuples whose smallest original point index lies in
+ * [anchor_lo, anchor_hi) are counted.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-3)
+
+typedef unsigned __int128 u128;
+
+typedef struct {
+    double L, half, rmin, rmax;
+    int nb;
+    double t[256]; /* squared bin edges t_0 .. t_nb */
+} params_t;
+
+static int make_params(params_t *p, double box, double rmin, double rmax, int nb) {
+    if (!(box > 0) || !isfinite(box)) return OR_EINVAL;
+    if (nb < 1 || nb > 255) return OR_EINVAL;
+    if (!(rmin >= 0) || !(rmin < rmax) || !(rmax < 0.5 * box)) return OR_EINVAL;
+    p->L = box;
+    p->half = 0.5 * box;
+    p->rmin = rmin;
+    p->rmax = rmax;
+    p->nb = nb;
+    double D = (rmax - rmin) / (double)nb;
+    for (int k = 0; k <= nb; ++k) {
+        double e = (k == 0) ? rmin : (k == nb ? rmax : rmin + (double)k * D);
+        p->t[k] = e * e;
+    }
+    return OR_OK;
+}
+
+static int check_points(const double *xyz, int64_t n, double box) {
+    if (n < 0) return OR_EINVAL;
+    if (n > 0 && !xyz) return OR_EINVAL;
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!(xyz[i] >= 0.0 && xyz[i] < box)) return OR_EINVAL; /* also rejects NaN */
+    return OR_OK;
+}
+
+/* D1 */
+static void separation(const params_t *p, const double *a, const double *b, double r[3]) {
+    for (int c = 0; c < 3; ++c) {
+        double d = b[c] - a[c];
+        if (d > p->half) d = d - p->L;
+        else if (d < -p->half) d = d + p->L;
+        r[c] = d;
+    }
+}
+
+/* D2 */
+static double sqlen(const double r[3]) { return (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]; }
+
+/* D3: bin of squared length q, or -1 when the pair is not an edge */
+static int edge_bin(const params_t *p, double q) {
+    if (!(q >= p->t[0] && q < p->t[p->nb])) return -1;
+    int b = 0;
+    for (int k = 1; k < p->nb; ++k)
+        if (q >= p->t[k]) ++b;
+    return b;
+}
+
+static int64_t binom2(int64_t n) { return n < 2 ? 0 : n * (n - 1) / 2; }
+static int64_t binom3(int64_t n) { return n < 3 ? 0 : n * (n - 1) * (n - 2) / 6; }
+
+/* lexicographic rank of the non-decreasing triple b1 <= b2 <= b3 among all
+ * such triples over 0..nb-1 */
+static int64_t config_index(int nb, int b1, int b2, int b3) {
+    return binom3(nb + 2) - binom3(nb - b1 + 2) + binom2(nb - b1 + 1) - binom2(nb - b2 + 1) +
+           (b3 - b2);
+}
+
+static void sort3i(int *a, int *b, int *c) {
+    int t;
+    if (*a > *b) { t = *a; *a = *b; *b = t; }
+    if (*b > *c) { t = *b; *b = *c; *c = t; }
+    if (*a > *b) { t = *a; *a = *b; *b = t; }
+}
+
+/* ---------------------------------------------------------------- graph -- */
+
+typedef struct {
+    int64_t n;
+    int64_t *ptr;   /* n+1 */
+    int32_t *col;   /* sorted ascending per row */
+    uint8_t *bin;
+} rows_t;
+
+static void rows_free(rows_t *g) {
+    free(g->ptr);
+    free(g->col);
+    free(g->bin);
+    memset(g, 0, sizeof *g);
+}
+
+typedef struct { int32_t j; uint8_t b; } entry_t;
+
+static int entry_cmp(const void *x, const void *y) {
+    int32_t a = ((const entry_t *)x)->j, b = ((const entry_t *)y)->j;
+    return (a > b) - (a < b);
+}
+
+/* Cell list with cells at least rmax*(1+1e-9) wide, so every pair closer than
+ * rmax sits in the same or a periodically adjacent cell. */
+static int build_rows(const params_t *p, const double *xyz, int64_t n, int nthreads, rows_t *g) {
+    memset(g, 0, sizeof *g);
+    g->n = n;
+    int nc = (int)floor(p->L / (p->rmax * (1.0 + 1e-9)));
+    if (nc > 128) nc = 128;
+    if (nc < 3) nc = 1;
+    int64_t ncell = (int64_t)nc * nc * nc;
+    int64_t *cstart = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t *cfill = (int64_t *)calloc((size_t)ncell, sizeof(int64_t));
+    int64_t *cellof = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    int32_t *members = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    g->ptr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!cstart || !cfill || !cellof || !members || !g->ptr) goto nomem;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c3[3];
+        for (int a = 0; a < 3; ++a) {
+            int64_t c = (int64_t)floor(xyz[3 * i + a] * (double)nc / p->L);
+            if (c > nc - 1) c = nc - 1;
+            if (c < 0) c = 0;
+            c3[a] = c;
+        }
+        cellof[i] = (c3[0] * nc + c3[1]) * nc + c3[2];
+        cstart[cellof[i] + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) cstart[c + 1] += cstart[c];
+    for (int64_t i = 0; i < n; ++i) members[cstart[cellof[i]] + cfill[cellof[i]]++] = (int32_t)i;
+
+    /* pass 1 counts, pass 2 fills */
+    for (int pass = 0; pass < 2; ++pass) {
+        int failed = 0;
+#pragma omp parallel for schedule(dynamic, 256) num_threads(nthreads)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t ci = cellof[i];
+            int cx = (int)(ci / ((int64_t)nc * nc)), cy = (int)((ci / nc) % nc), cz = (int)(ci % nc);
+            int64_t cells[27];
+            int ncells = 0;
+            if (nc == 1) {
+                cells[ncells++] = 0;
+            } else {
+                for (int dx = -1; dx <= 1; ++dx)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dz = -1; dz <= 1; ++dz) {
+                            int x = (cx + dx + nc) % nc, y = (cy + dy + nc) % nc, z = (cz + dz + nc) % nc;
+                            cells[ncells++] = ((int64_t)x * nc + y) * nc + z;
+                        }
+            }
+            int64_t cnt = 0;
+            entry_t *row = NULL;
+            if (pass == 1) {
+                int64_t m = g->ptr[i + 1] - g->ptr[i];
+                row = (entry_t *)malloc(sizeof(entry_t) * (size_t)(m ? m : 1));
+                if (!row) { failed = 1; continue; }
+            }
+            for (int u = 0; u < ncells; ++u) {
+                int64_t c = cells[u];
+                for (int64_t s = cstart[c]; s < cstart[c + 1]; ++s) {
+                    int32_t j = members[s];
+                    if (j == i) continue;
+                    double r[3];
+                    separation(p, &xyz[3 * i], &xyz[3 * (int64_t)j], r);
+                    int b = edge_bin(p, sqlen(r));
+                    if (b < 0) continue;
+                    if (pass == 1) { row[cnt].j = j; row[cnt].b = (uint8_t)b; }
+                    ++cnt;
+                }
+            }
+            if (pass == 0) {
+                g->ptr[i + 1] = cnt;
+            } else {
+                qsort(row, (size_t)cnt, sizeof(entry_t), entry_cmp);
+                for (int64_t e = 0; e < cnt; ++e) {
+                    g->col[g->ptr[i] + e] = row[e].j;
+                    g->bin[g->ptr[i] + e] = row[e].b;
+                }
+                free(row);
+            }
+        }
+        if (failed) goto nomem;
+        if (pass == 0) {
+            for (int64_t i = 0; i < n; ++i) g->ptr[i + 1] += g->ptr[i];
+            int64_t E = g->ptr[n];
+            g->col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(E ? E : 1));
+            g->bin = (uint8_t *)malloc((size_t)(E ? E : 1));
+            if (!g->col || !g->bin) goto nomem;
+        }
+    }
+    free(cstart);
+    free(cfill);
+    free(cellof);
+    free(members);
+    return OR_OK;
+nomem:
+    free(cstart);
+    free(cfill);
+    free(cellof);
+    free(members);
+    rows_free(g);
+    return OR_ENOMEM;
+}
+
+/* position of j in row i, or -1 (binary search: the membership test of the
+ * paper's original algorithm) */
+static int64_t find(const rows_t *g, int64_t i, int32_t j) {
+    int64_t lo = g->ptr[i], hi = g->ptr[i + 1];
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (g->col[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < g->ptr[i + 1] && g->col[lo] == j) ? lo : -1;
+}
+
+static int resolve_threads(int nthreads) {
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+}
+
+/* ---------------------------------------------------------------- API ---- */
+
+int oracle_version(void) { return 1; }
+
+int64_t oracle_config_index(int nbins, int b1, int b2, int b3) {
+    return config_index(nbins, b1, b2, b3);
+}
+
+/* D3 on a given squared length (exposed for exact bin-edge tests) */
+int oracle_edge_bin(double q, double box, double rmin, double rmax, int nbins) {
+    params_t p;
+    if (make_params(&p, box, rmin, rmax, nbins) != OR_OK) return -2;
+    return edge_bin(&p, q);
+}
+
+/* D1+D2 for two points (exposed for antisymmetry tests) */
+int oracle_separation(const double *a, const double *b, double box, double *r_out, double *q_out) {
+    params_t p;
+    if (make_params(&p, box, 0.0, 0.25 * box, 1) != OR_OK) return OR_EINVAL;
+    separation(&p, a, b, r_out);
+    *q_out = sqlen(r_out);
+    return OR_OK;
+}
+
+/* Full symmetric neighbour rows, sorted by original index. If cap is smaller
+ * than the number of entries, only *n_entries is written. */
+int oracle_graph(const double *xyz, int64_t n, double box, double rmin, double rmax, int nbins,
+                 int64_t *row_ptr, int32_t *col, uint8_t *bin, int64_t cap, int64_t *n_entries) {
+    params_t p;
+    int rc = make_params(&p, box, rmin, rmax, nbins);
+    if (rc == OR_OK) rc = check_points(xyz, n, box);
+    if (rc != OR_OK) return rc;
+    if (n >= ((int64_t)1 << 31)) return OR_EINVAL;
+    rows_t g;
+    rc = build_rows(&p, xyz, n, resolve_threads(0), &g);
+    if (rc != OR_OK) return rc;
+    *n_entries = g.ptr[n];
+    if (cap >= g.ptr[n]) {
+        memcpy(row_ptr, g.ptr, sizeof(int64_t) * (size_t)(n + 1));
+        memcpy(col, g.col, sizeof(int32_t) * (size_t)g.ptr[n]);
+        memcpy(bin, g.bin, (size_t)g.ptr[n]);
+    }
+    rows_free(&g);
+    return OR_OK;
+}
+
+/* scale s of the exact weighted sums: every product t >= t_lo is an integer
+ * multiple of 2^-s. Rejects weights whose products would not fit 64 bits. */
+static int weight_scale(const double *w, int64_t n, int *s_out) {
+    double wmin = INFINITY, wmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(w[i] > 0.0) || !isfinite(w[i])) return OR_EINVAL;
+        if (w[i] < wmin) wmin = w[i];
+        if (w[i] > wmax) wmax = w[i];
+    }
+    if (n == 0) { *s_out = 0; return OR_OK; }
+    double tlo = (wmin * wmin) * wmin, thi = (wmax * wmax) * wmax;
+    if (!(tlo >= 0x1.0p-1022) || !isfinite(thi)) return OR_EINVAL;
+    int s = 52 - ilogb(tlo);
+    if (ilogb(thi) + s >= 64) return OR_EINVAL;
+    *s_out = s;
+    return OR_OK;
+}
+
+int oracle_count_3pcf(const double *xyz, int64_t n, const double *w, double box, double rmin,
+                      double rmax, int nbins, int64_t anchor_lo, int64_t anchor_hi, int nthreads,
+                      uint64_t *hist, uint64_t *wsum, int *wscale, uint64_t *n_tri,
+                      int *threads_used) {
+    params_t p;
+    int rc = make_params(&p, box, rmin, rmax, nbins);
+    if (rc == OR_OK) rc = check_points(xyz, n, box);
+    if (rc != OR_OK) return rc;
+    if (n >= ((int64_t)1 << 31) || !hist || !n_tri) return OR_EINVAL;
+    int s = 0;
+    if (w) {
+        if (!wsum) return OR_EINVAL;
+        rc = weight_scale(w, n, &s);
+        if (rc != OR_OK) return rc;
+        if (wscale) *wscale = s;
+    }
+    if (anchor_lo < 0) anchor_lo = 0;
+    if (anchor_hi > n) anchor_hi = n;
+    int nt = resolve_threads(nthreads);
+    if (threads_used) *threads_used = nt;
+    rows_t g;
+    rc = build_rows(&p, xyz, n, nt, &g);
+    if (rc != OR_OK) return rc;
+    int64_t nconf = binom3(nbins + 2);
+    uint64_t *th = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));
+    u128 *tw = w ? (u128 *)calloc((size_t)(nt * nconf), sizeof(u128)) : NULL;
+    uint64_t *tn = (uint64_t *)calloc((size_t)nt, sizeof(uint64_t));
+    if (!th || !tn || (w && !tw)) { free(th); free(tw); free(tn); rows_free(&g); return OR_ENOMEM; }
+    double scale = ldexp(1.0, s);
+
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = omp_get_thread_num();
+        uint64_t *H = th + (int64_t)tid * nconf;
+        u128 *Wt = w ? tw + (int64_t)tid * nconf : NULL;
+        uint64_t cnt = 0;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = anchor_lo; i < anchor_hi; ++i) {
+            for (int64_t a = g.ptr[i]; a < g.ptr[i + 1]; ++a) {
+                int32_t j = g.col[a];
+                if (j <= i) continue;
+                for (int64_t b = a + 1; b < g.ptr[i + 1]; ++b) {
+                    int32_t k = g.col[b];
+                    int64_t f = find(&g, j, k);
+                    if (f < 0) continue;
+                    int b1 = g.bin[a], b2 = g.bin[b], b3 = g.bin[f];
+                    sort3i(&b1, &b2, &b3);
+                    int64_t idx = config_index(nbins, b1, b2, b3);
+                    H[idx] += 1;
+                    ++cnt;
+                    if (Wt) {
+                        double x = w[i], y = w[j], z = w[k], t;
+                        if (x > y) { t = x; x = y; y = t; }
+                        if (y > z) { t = y; y = z; z = t; }
+                        if (x > y) { t = x; x = y; y = t; }
+                        double prod = (x * y) * z;
+                        Wt[idx] += (u128)(prod * scale);
+                    }
+                }
+            }
+        }
+        tn[tid] = cnt;
+    }
+    memset(hist, 0, sizeof(uint64_t) * (size_t)nconf);
+    *n_tri = 0;
+    for (int t = 0; t < nt; ++t) {
+        *n_tri += tn[t];
+        for (int64_t c = 0; c < nconf; ++c) hist[c] += th[(int64_t)t * nconf + c];
+    }
+    if (w) {
+        for (int64_t c = 0; c < nconf; ++c) {
+            u128 acc = 0;
+            for (int t = 0; t < nt; ++t) acc += tw[(int64_t)t * nconf + c];
+            wsum[2 * c] = (uint64_t)acc;
+            wsum[2 * c + 1] = (uint64_t)(acc >> 64);
+        }
+    }
+    free(th);
+    free(tw);
+    free(tn);
+    rows_free(&g);
+    return OR_OK;
+}
+
+/* one hub's contribution to the parity histograms (D6) */
+static void hub_parity(const params_t *p, const double *xyz, int64_t h, const int64_t s[3],
+                       uint64_t *E, uint64_t *P, uint64_t *N) {
+    double r[3][3], q[3];
+    int ord[3] = {0, 1, 2};
+    for (int u = 0; u < 3; ++u) {
+        separation(p, &xyz[3 * h], &xyz[3 * s[u]], r[u]);
+        q[u] = sqlen(r[u]);
+    }
+    /* order spokes by squared length */
+    for (int u = 1; u < 3; ++u)
+        for (int v = u; v > 0 && q[ord[v - 1]] > q[ord[v]]; --v) {
+            int t = ord[v];
+            ord[v] = ord[v - 1];
+            ord[v - 1] = t;
+        }
+    const double *ra = r[ord[0]], *rb = r[ord[1]], *rc = r[ord[2]];
+    double qa = q[ord[0]], qb = q[ord[1]], qc = q[ord[2]];
+    int b1 = edge_bin(p, qa), b2 = edge_bin(p, qb), b3 = edge_bin(p, qc);
+    int64_t idx = config_index(p->nb, b1, b2, b3);
+    E[idx] += 1;
+    double cx = ra[1] * rb[2] - ra[2] * rb[1];
+    double cy = ra[2] * rb[0] - ra[0] * rb[2];
+    double cz = ra[0] * rb[1] - ra[1] * rb[0];
+    double V = (cx * rc[0] + cy * rc[1]) + cz * rc[2];
+    if (qa == qb || qb == qc) return;
+    if (V * V <= 1e-18 * ((qa * qb) * qc)) return;
+    if (V > 0) P[idx] += 1;
+    else N[idx] += 1;
+}
+
+int oracle_count_4pcf_parity(const double *xyz, int64_t n, double box, double rmin, double rmax,
+                             int nbins, int64_t anchor_lo, int64_t anchor_hi, int nthreads,
+                             uint64_t *even, uint64_t *pos, uint64_t *neg, uint64_t *n_cliques,
+                             int *threads_used) {
+    params_t p;
+    int rc = make_params(&p, box, rmin, rmax, nbins);
+    if (rc == OR_OK) rc = check_points(xyz, n, box);
+    if (rc != OR_OK) return rc;
+    if (n >= ((int64_t)1 << 31) || !even || !pos || !neg || !n_cliques) return OR_EINVAL;
+    if (anchor_lo < 0) anchor_lo = 0;
+    if (anchor_hi > n) anchor_hi = n;
+    int nt = resolve_threads(nthreads);
+    if (threads_used) *threads_used = nt;
+    rows_t g;
+    rc = build_rows(&p, xyz, n, nt, &g);
+    if (rc != OR_OK) return rc;
+    int64_t nconf = binom3(nbins + 2);
+    uint64_t *tE = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));
+    uint64_t *tP = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));
+    uint64_t *tN = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));
+    uint64_t *tn = (uint64_t *)calloc((size_t)nt, sizeof(uint64_t));
+    if (!tE || !tP || !tN || !tn) {
+        free(tE); free(tP); free(tN); free(tn); rows_free(&g);
+        return OR_ENOMEM;
+    }
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = omp_get_thread_num();
+        uint64_t *E = tE + (int64_t)tid * nconf, *P = tP + (int64_t)tid * nconf,
+                 *N = tN + (int64_t)tid * nconf;
+        uint64_t cnt = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = anchor_lo; i < anchor_hi; ++i) {
+            for (int64_t a = g.ptr[i]; a < g.ptr[i + 1]; ++a) {
+                int32_t j = g.col[a];
+                if (j <= i) continue;
+                for (int64_t b = a + 1; b < g.ptr[i + 1]; ++b) {
+                    int32_t k = g.col[b];
+                    if (find(&g, j, k) < 0) continue;
+                    for (int64_t c = b + 1; c < g.ptr[i + 1]; ++c) {
+                        int32_t l = g.col[c];
+                        if (find(&g, j, l) < 0 || find(&g, k, l) < 0) continue;
+                        ++cnt;
+                        int64_t v[4] = {i, j, k, l};
+                        for (int h = 0; h < 4; ++h) {
+                            int64_t sp[3];
+                            int u = 0;
+                            for (int o = 0; o < 4; ++o)
+                                if (o != h) sp[u++] = v[o];
+                            hub_parity(&p, xyz, v[h], sp, E, P, N);
+                        }
+                    }
+                }
+            }
+        }
+        tn[tid] = cnt;
+    }
+    memset(even, 0, sizeof(uint64_t) * (size_t)nconf);
+    memset(pos, 0, sizeof(uint64_t) * (size_t)nconf);
+    memset(neg, 0, sizeof(uint64_t) * (size_t)nconf);
+    *n_cliques = 0;
+    for (int t = 0; t < nt; ++t) {
+        *n_cliques += tn[t];
+        for (int64_t c = 0; c < nconf; ++c) {
+            even[c] += tE[(int64_t)t * nconf + c];
+            pos[c] += tP[(int64_t)t * nconf + c];
+            neg[c] += tN[(int64_t)t * nconf + c];
+        }
+    }
+    free(tE);
+    free(tP);
+    free(tN);
+    free(tn);
+    rows_free(&g);
+    return OR_OK;
+}

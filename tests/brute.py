@@ -1,0 +1,121 @@
+"""Brute-force tuple enumeration for tiny catalogues (test helper).
+
+Independent of oracle/ and of the GPU library: no cell list, no sorted rows,
+no membership search. It forms the full N x N pair matrix with numpy and
+visits every triple (O(N^3)) or quadruple (O(N^4)) of points. The pair rule
+(minimum image, squared length, equal-width squared bin thresholds) and the
+per-hub signed volume are restated here from the paper's definitions
+(Sec. 2.1, 2.2, 3.2 Eq. 2); float64 numpy arithmetic without fused
+operations, in the same evaluation order.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def pair_matrix(xyz, L, rmin, rmax, nb):
+    x = np.asarray(xyz, dtype=np.float64)
+    d = x[None, :, :] - x[:, None, :]          # d[a, b] = x_b - x_a
+    half = 0.5 * L
+    d = np.where(d > half, d - L, np.where(d < -half, d + L, d))
+    q = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+    D = (rmax - rmin) / nb
+    e = [rmin] + [rmin + k * D for k in range(1, nb)] + [rmax]
+    t = [v * v for v in e]
+    adj = (q >= t[0]) & (q < t[nb])
+    np.fill_diagonal(adj, False)
+    b = np.zeros(q.shape, dtype=np.int64)
+    for k in range(1, nb):
+        b += (q >= t[k])
+    return d, q, adj, b
+
+
+def lex_configs(nb):
+    """All b1 <= b2 <= b3 in lexicographic order -> {triple: rank}."""
+    out = {}
+    for a in range(nb):
+        for bb in range(a, nb):
+            for c in range(bb, nb):
+                out[(a, bb, c)] = len(out)
+    return out
+
+
+def triangles(xyz, L, rmin, rmax, nb, weights=None, anchors=None):
+    """Returns (hist by lexicographic rank, n_triangles, exact weighted sums as
+    Python ints in units of 2^-s, s)."""
+    n = len(xyz)
+    _, _, adj, b = pair_matrix(xyz, L, rmin, rmax, nb)
+    rank = lex_configs(nb)
+    hist = np.zeros(len(rank), dtype=np.int64)
+    wsum = [0] * len(rank)
+    s = None
+    if weights is not None:
+        w = [float(v) for v in weights]
+        wmin = min(w)
+        s = 52 - math.frexp((wmin * wmin) * wmin)[1] + 1
+    lo, hi = (0, n) if anchors is None else anchors
+    count = 0
+    for i in range(lo, hi):
+        for j in range(i + 1, n):
+            if not adj[i, j]:
+                continue
+            ks = np.nonzero(adj[i, j + 1:] & adj[j, j + 1:])[0] + j + 1
+            for k in ks:
+                key = tuple(sorted((int(b[i, j]), int(b[i, k]), int(b[j, k]))))
+                hist[rank[key]] += 1
+                count += 1
+                if weights is not None:
+                    a3 = sorted((w[i], w[j], w[int(k)]))
+                    t = (a3[0] * a3[1]) * a3[2]
+                    wsum[rank[key]] += int(t * 2.0 ** s)
+    return hist, count, wsum, s
+
+
+def hub_volume(r_a, r_b, r_c):
+    cx = r_a[1] * r_b[2] - r_a[2] * r_b[1]
+    cy = r_a[2] * r_b[0] - r_a[0] * r_b[2]
+    cz = r_a[0] * r_b[1] - r_a[1] * r_b[0]
+    return (cx * r_c[0] + cy * r_c[1]) + cz * r_c[2]
+
+
+def cliques4(xyz, L, rmin, rmax, nb, anchors=None):
+    """Returns (even, pos, neg, n_cliques) for 4-cliques, one contribution per
+    hub (each vertex of the clique in turn)."""
+    n = len(xyz)
+    d, q, adj, b = pair_matrix(xyz, L, rmin, rmax, nb)
+    rank = lex_configs(nb)
+    E = np.zeros(len(rank), dtype=np.int64)
+    P = np.zeros(len(rank), dtype=np.int64)
+    N = np.zeros(len(rank), dtype=np.int64)
+    lo, hi = (0, n) if anchors is None else anchors
+    count = 0
+    for i in range(lo, hi):
+        for j in range(i + 1, n):
+            if not adj[i, j]:
+                continue
+            common = adj[i] & adj[j]
+            ks = [k for k in np.nonzero(common)[0] if k > j]
+            for k in ks:
+                ls = [l for l in np.nonzero(common & adj[k])[0] if l > k]
+                for l in ls:
+                    count += 1
+                    v = (i, j, int(k), int(l))
+                    for h in v:
+                        sp = [s for s in v if s != h]
+                        sp.sort(key=lambda s: q[h, s])     # stable; ties are degenerate anyway
+                        qa, qb, qc = (float(q[h, s]) for s in sp)
+                        key = tuple(int(b[h, s]) for s in sp)
+                        r = rank[key]
+                        E[r] += 1
+                        V = hub_volume(*(tuple(float(c) for c in d[h, s]) for s in sp))
+                        if qa == qb or qb == qc:
+                            continue
+                        if V * V <= 1e-18 * ((qa * qb) * qc):
+                            continue
+                        if V > 0:
+                            P[r] += 1
+                        else:
+                            N[r] += 1
+    return E, P, N, count

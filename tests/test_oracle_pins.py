@@ -1,0 +1,428 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test ties the oracle to a fact fixed outside it: configuration counts the
+paper prints, hand-derived lattice and chiral-unit closed forms
+(tests/golden/), the Poisson closed form for uniform boxes, O(N^3)/O(N^4)
+brute force (tests/brute.py), exact reflection/relabelling/translation
+symmetries, and exact weighted-sum identities.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import brute
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def _golden(golden_dir, name):
+    with open(os.path.join(golden_dir, name)) as f:
+        return json.load(f)
+
+
+# ------------------------------------------------------- configuration index --
+
+@pytest.mark.parametrize("nb", [1, 2, 3, 8, 10, 15, 20, 40])
+def test_config_index_is_lexicographic_rank(nb):
+    rank = brute.lex_configs(nb)
+    assert len(rank) == oracle.n_configs(nb) == math.comb(nb + 2, 3)
+    for (a, b, c), r in rank.items():
+        assert oracle.config_index(nb, a, b, c) == r
+
+
+def test_config_counts_printed_in_paper(golden_dir):
+    g = _golden(golden_dir, "paper_config_counts.json")
+    for nb, count in g["counts"].items():
+        assert oracle.n_configs(int(nb)) == count
+        assert len(brute.lex_configs(int(nb))) == count
+
+
+# ------------------------------------------------------------- pair rule -----
+
+def test_bin_rule_half_open_on_exact_edges():
+    # rmin 0, rmax 1.5, 6 bins of 0.25: all edges are exact binary fractions
+    L = 6.0
+    eb = lambda q: oracle.edge_bin(q, L, 0.0, 1.5, 6)
+    assert eb(0.0) == 0                      # rmin = 0: coincident points are edges in bin 0
+    assert eb(0.0625) == 1                   # d = 0.25 exactly on e_1
+    assert eb(np.nextafter(0.0625, 0)) == 0
+    assert eb(1.0) == 4                      # d = 1 exactly on e_4 -> upper bin
+    assert eb(np.nextafter(1.0, 0)) == 3
+    assert eb(2.0) == 5
+    assert eb(np.nextafter(2.25, 0)) == 5
+    assert eb(2.25) == -1                    # d = rmax is not an edge (strict < rmax)
+    # rmin > 0: pairs closer than rmin are not edges
+    assert oracle.edge_bin(0.25, L, 0.5, 1.5, 2) == 0
+    assert oracle.edge_bin(np.nextafter(0.25, 0), L, 0.5, 1.5, 2) == -1
+    assert oracle.edge_bin(1.0, L, 0.5, 1.5, 2) == 1
+
+
+def test_separation_minimum_image_antisymmetric():
+    L = 10.0
+    rng_pts = synth.uniform(400, L, 11)
+    # include components exactly at +-L/2
+    rng_pts[0] = [0.0, 0.0, 0.0]
+    rng_pts[1] = [5.0, 5.0, 2.5]
+    for a in range(0, 400, 7):
+        for b in range(1, 400, 13):
+            r_ab, q_ab = oracle.separation(rng_pts[a], rng_pts[b], L)
+            r_ba, q_ba = oracle.separation(rng_pts[b], rng_pts[a], L)
+            assert np.array_equal(r_ab, -r_ba)
+            assert q_ab == q_ba
+            assert np.all(np.abs(r_ab) <= 0.5 * L)
+    r, _ = oracle.separation(rng_pts[0], rng_pts[1], L)
+    assert list(r) == [5.0, 5.0, 2.5]
+    r, _ = oracle.separation(rng_pts[1], rng_pts[0], L)
+    assert list(r) == [-5.0, -5.0, -2.5]
+    r, _ = oracle.separation([0.5, 9.5, 1.0], [9.5, 0.5, 1.0], L)
+    assert list(r) == [-1.0, 1.0, 0.0]
+
+
+def test_invalid_inputs_rejected():
+    x = synth.uniform(50, 10.0, 3)
+    with pytest.raises(oracle.OracleError):
+        oracle.count_3pcf(x, 10.0, 0.0, 5.0, 4)        # rmax >= L/2
+    with pytest.raises(oracle.OracleError):
+        oracle.count_3pcf(x, 10.0, 2.0, 2.0, 4)        # rmin >= rmax
+    with pytest.raises(oracle.OracleError):
+        oracle.count_3pcf(x, 10.0, 0.0, 2.0, 0)        # nbins < 1
+    with pytest.raises(oracle.OracleError):
+        oracle.count_3pcf(x, 10.0, 0.0, 2.0, 256)      # nbins > 255
+    y = x.copy()
+    y[3, 1] = 10.0
+    with pytest.raises(oracle.OracleError):
+        oracle.count_3pcf(y, 10.0, 0.0, 2.0, 4)        # coordinate == L
+    y[3, 1] = np.nan
+    with pytest.raises(oracle.OracleError):
+        oracle.count_3pcf(y, 10.0, 0.0, 2.0, 4)
+    with pytest.raises(oracle.OracleError):
+        oracle.count_3pcf(x, 10.0, 0.0, 2.0, 4, weights=np.zeros(50))
+
+
+# ------------------------------------------------------------ brute force ----
+
+TINY = [
+    # (name, xyz, L, rmin, rmax, nb)
+    ("uniform_dense", lambda: synth.uniform(260, 10.0, 21), 10.0, 0.0, 2.4, 5),
+    ("uniform_rmin", lambda: synth.uniform(240, 10.0, 22), 10.0, 0.7, 2.6, 4),
+    ("clustered", lambda: synth.neyman_scott(250, 25, 0.8, 12.0, 23), 12.0, 0.0, 2.0, 6),
+    ("single_cell", lambda: synth.uniform(150, 9.0, 24), 9.0, 0.0, 3.9, 3),   # L/rmax < 3: one cell
+    ("many_bins", lambda: synth.uniform(200, 8.0, 25), 8.0, 0.0, 2.2, 21),
+]
+
+
+@pytest.mark.parametrize("case", TINY, ids=[c[0] for c in TINY])
+def test_oracle_graph_matches_brute_pairs(case):
+    _, mk, L, rmin, rmax, nb = case
+    x = mk()
+    rp, col, b = oracle.graph(x, L, rmin, rmax, nb)
+    _, _, adj, bins = brute.pair_matrix(x, L, rmin, rmax, nb)
+    for i in range(len(x)):
+        js = np.nonzero(adj[i])[0]
+        assert np.array_equal(col[rp[i]:rp[i + 1]], js)
+        assert np.array_equal(b[rp[i]:rp[i + 1]], bins[i, js])
+
+
+@pytest.mark.parametrize("case", TINY, ids=[c[0] for c in TINY])
+def test_oracle_3pcf_matches_brute_force(case):
+    _, mk, L, rmin, rmax, nb = case
+    x = mk()
+    w = synth.uniform_values(len(x), 0.5, 1.0, 99)
+    bh, bcount, bw, bs = brute.triangles(x, L, rmin, rmax, nb, weights=w)
+    r = oracle.count_3pcf(x, L, rmin, rmax, nb, weights=w, threads=3)
+    assert bcount > 50
+    assert r.n_triangles == bcount
+    assert np.array_equal(r.hist.astype(np.int64), bh)
+    assert r.wscale == bs
+    assert r.wsum_int() == bw
+
+
+@pytest.mark.parametrize("case", TINY[:4], ids=[c[0] for c in TINY[:4]])
+def test_oracle_3pcf_anchors_match_brute_force(case):
+    _, mk, L, rmin, rmax, nb = case
+    x = mk()
+    n = len(x)
+    parts = [(0, n // 3), (n // 3, n // 2), (n // 2, n)]
+    tot = np.zeros(oracle.n_configs(nb), dtype=np.uint64)
+    for lo, hi in parts:
+        bh, bcount, _, _ = brute.triangles(x, L, rmin, rmax, nb, anchors=(lo, hi))
+        r = oracle.count_3pcf(x, L, rmin, rmax, nb, anchors=(lo, hi))
+        assert r.n_triangles == bcount
+        assert np.array_equal(r.hist.astype(np.int64), bh)
+        tot += r.hist
+    assert np.array_equal(tot, oracle.count_3pcf(x, L, rmin, rmax, nb).hist)
+
+
+TINY4 = [
+    ("uniform_dense", lambda: synth.uniform(110, 8.0, 31), 8.0, 0.0, 2.6, 4),
+    ("clustered", lambda: synth.neyman_scott(110, 22, 0.7, 10.0, 32), 10.0, 0.0, 2.0, 5),
+    ("rmin", lambda: synth.uniform(100, 7.0, 33), 7.0, 0.5, 2.5, 3),
+]
+
+
+@pytest.mark.parametrize("case", TINY4, ids=[c[0] for c in TINY4])
+def test_oracle_4pcf_parity_matches_brute_force(case):
+    _, mk, L, rmin, rmax, nb = case
+    x = mk()
+    E, P, N, cnt = brute.cliques4(x, L, rmin, rmax, nb)
+    r = oracle.count_4pcf_parity(x, L, rmin, rmax, nb, threads=3)
+    assert cnt > 20
+    assert r.n_cliques == cnt
+    assert np.array_equal(r.even.astype(np.int64), E)
+    assert np.array_equal(r.pos.astype(np.int64), P)
+    assert np.array_equal(r.neg.astype(np.int64), N)
+    assert r.pos.sum() + r.neg.sum() > 0
+
+
+def test_oracle_4pcf_anchor_split():
+    x = synth.uniform(110, 8.0, 31)
+    full = oracle.count_4pcf_parity(x, 8.0, 0.0, 2.6, 4)
+    acc = [np.zeros_like(full.even) for _ in range(3)]
+    nk = 0
+    for lo, hi in [(0, 20), (20, 77), (77, 110)]:
+        r = oracle.count_4pcf_parity(x, 8.0, 0.0, 2.6, 4, anchors=(lo, hi))
+        E, P, N, cnt = brute.cliques4(x, 8.0, 0.0, 2.6, 4, anchors=(lo, hi))
+        assert r.n_cliques == cnt and np.array_equal(r.even.astype(np.int64), E)
+        assert np.array_equal(r.pos.astype(np.int64), P) and np.array_equal(r.neg.astype(np.int64), N)
+        for a, v in zip(acc, (r.even, r.pos, r.neg)):
+            a += v
+        nk += r.n_cliques
+    assert nk == full.n_cliques
+    assert np.array_equal(acc[0], full.even)
+    assert np.array_equal(acc[1], full.pos)
+    assert np.array_equal(acc[2], full.neg)
+
+
+# ------------------------------------------------------------ lattice --------
+
+def _lattice(g, shift=(0.0, 0.0, 0.0)):
+    m = g["sites_per_axis"]
+    a = np.arange(m, dtype=np.float64)
+    X, Y, Z = np.meshgrid(a, a, a, indexing="ij")
+    xyz = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    return np.mod(xyz + np.array(shift), g["box"])
+
+
+@pytest.mark.parametrize("shift", [(0.0, 0.0, 0.0), (0.25, 0.5, 0.125), (5.5, 0.75, 3.0)])
+def test_lattice_closed_forms(golden_dir, shift):
+    g = _golden(golden_dir, "lattice_sc.json")
+    x = _lattice(g, shift)
+    nsite = len(x)
+    L, rmin, rmax, nb = g["box"], g["rmin"], g["rmax"], g["nbins"]
+    rp, col, b = oracle.graph(x, L, rmin, rmax, nb)
+    assert np.all(np.diff(rp) == 18)
+    pair = np.bincount(b, minlength=nb)
+    for k, v in g["edges_per_site_by_bin"].items():
+        assert pair[int(k)] == v * nsite
+    assert pair.sum() == 18 * nsite
+    r3 = oracle.count_3pcf(x, L, rmin, rmax, nb)
+    exp3 = np.zeros(oracle.n_configs(nb), dtype=np.uint64)
+    for key, v in g["triangles_per_site"].items():
+        exp3[oracle.config_index(nb, *map(int, key.split(",")))] = v * nsite
+    assert np.array_equal(r3.hist, exp3)
+    assert r3.n_triangles == 20 * nsite
+    r4 = oracle.count_4pcf_parity(x, L, rmin, rmax, nb)
+    assert r4.n_cliques == g["cliques_per_site"] * nsite
+    exp4 = np.zeros(oracle.n_configs(nb), dtype=np.uint64)
+    for key, v in g["hub_contributions_per_site"].items():
+        exp4[oracle.config_index(nb, *map(int, key.split(",")))] = v * nsite
+    assert np.array_equal(r4.even, exp4)
+    assert r4.pos.sum() == 0 and r4.neg.sum() == 0
+
+
+# -------------------------------------------------------- chiral injection ---
+
+def _chiral_catalogue(g, handed, spacing=8.0, origin=(2.25, 2.5, 2.75)):
+    """Units on a grid `spacing` apart (> rmax + unit size); handed[u] = +1
+    original, -1 mirrored (x offsets negated)."""
+    L = g["box"]
+    per = int(L // spacing)
+    pts = []
+    off = g["offsets"]
+    for u, h in enumerate(handed):
+        a, bb, c = u // (per * per), (u // per) % per, u % per
+        O = np.array([a * spacing, bb * spacing, c * spacing]) + np.array(origin)
+        pts.append(O)
+        for name in ("A", "B", "C"):
+            v = np.array(off[name], dtype=np.float64)
+            v[0] *= h
+            pts.append(O + v)
+    return np.mod(np.array(pts), L)
+
+
+def test_chiral_unit_hand_derived_signs(golden_dir):
+    g = _golden(golden_dir, "chiral_unit.json")
+    L, rmin, rmax, nb = g["box"], g["rmin"], g["rmax"], g["nbins"]
+    idx = lambda t: oracle.config_index(nb, *t)
+    for h in (+1, -1):
+        x = _chiral_catalogue(g, [h])
+        r = oracle.count_4pcf_parity(x, L, rmin, rmax, nb)
+        assert r.n_cliques == 1
+        exp_pos = np.zeros(oracle.n_configs(nb), dtype=np.int64)
+        for t in g["pos_configs"]:
+            exp_pos[idx(t)] += 1
+        for t in g["neg_configs"]:
+            exp_pos[idx(t)] -= 1
+        assert np.array_equal(r.odd, h * exp_pos)
+        assert r.even.sum() == 4
+        r3 = oracle.count_3pcf(x, L, rmin, rmax, nb)
+        exp3 = np.zeros(oracle.n_configs(nb), dtype=np.uint64)
+        for t in g["triangle_configs"]:
+            exp3[idx(t)] += 1
+        assert np.array_equal(r3.hist, exp3)
+
+
+@pytest.mark.parametrize("n_left,n_right", [(300, 200), (250, 250), (500, 0)])
+def test_chiral_injection_count_level_prediction(golden_dir, n_left, n_right):
+    """Odd channel = (N_L - N_R) x single-unit pattern (paper Sec. 4.9)."""
+    g = _golden(golden_dir, "chiral_unit.json")
+    L, rmin, rmax, nb = g["box"], g["rmin"], g["rmax"], g["nbins"]
+    unit = oracle.count_4pcf_parity(_chiral_catalogue(g, [1]), L, rmin, rmax, nb)
+    handed = [1] * n_left + [-1] * n_right
+    order = synth.permutation(len(handed), 7)
+    handed = [handed[i] for i in order]
+    x = _chiral_catalogue(g, handed)
+    r = oracle.count_4pcf_parity(x, L, rmin, rmax, nb)
+    assert r.n_cliques == n_left + n_right
+    assert np.array_equal(r.odd, (n_left - n_right) * unit.odd)
+    assert np.array_equal(r.even, (n_left + n_right) * unit.even)
+
+
+# --------------------------------------------------- exact symmetries ---------
+
+def test_reflection_swaps_parity_channels_exactly():
+    L = 16.0
+    x = synth.dyadic_uniform(700, L, 41)
+    y = x.copy()
+    y[:, 0] = np.mod(L - y[:, 0], L)         # exact on the dyadic grid
+    a = oracle.count_4pcf_parity(x, L, 0.0, 2.2, 4)
+    b = oracle.count_4pcf_parity(y, L, 0.0, 2.2, 4)
+    assert a.n_cliques > 100
+    assert np.array_equal(a.even, b.even)
+    assert np.array_equal(a.pos, b.neg)
+    assert np.array_equal(a.neg, b.pos)
+    assert a.pos.sum() > 0
+
+
+def test_relabelling_invariance():
+    L = 12.0
+    x = synth.neyman_scott(900, 30, 1.0, L, 42)
+    w = synth.uniform_values(900, 0.5, 1.0, 43)
+    p = synth.permutation(900, 44)
+    a3 = oracle.count_3pcf(x, L, 0.0, 2.0, 5, weights=w)
+    b3 = oracle.count_3pcf(x[p], L, 0.0, 2.0, 5, weights=w[p])
+    assert np.array_equal(a3.hist, b3.hist) and np.array_equal(a3.wsum, b3.wsum)
+    a4 = oracle.count_4pcf_parity(x, L, 0.0, 1.6, 4)
+    b4 = oracle.count_4pcf_parity(x[p], L, 0.0, 1.6, 4)
+    assert np.array_equal(a4.even, b4.even) and np.array_equal(a4.pos, b4.pos)
+    assert np.array_equal(a4.neg, b4.neg)
+
+
+def test_dyadic_translation_invariance():
+    L = 16.0
+    x = synth.dyadic_uniform(800, L, 45)
+    y = np.mod(x + np.array([3.25, 15.5, 7.125]), L)
+    a3 = oracle.count_3pcf(x, L, 0.0, 2.4, 6)
+    b3 = oracle.count_3pcf(y, L, 0.0, 2.4, 6)
+    assert np.array_equal(a3.hist, b3.hist)
+    a4 = oracle.count_4pcf_parity(x, L, 0.0, 2.2, 4)
+    b4 = oracle.count_4pcf_parity(y, L, 0.0, 2.2, 4)
+    assert np.array_equal(a4.even, b4.even) and np.array_equal(a4.pos, b4.pos)
+    assert np.array_equal(a4.neg, b4.neg)
+
+
+# --------------------------------------------------------- weighted sums -----
+
+def test_weighted_identities():
+    L = 12.0
+    x = synth.uniform(1500, L, 51)
+    n = len(x)
+    r1 = oracle.count_3pcf(x, L, 0.0, 2.0, 6, weights=np.ones(n))
+    assert r1.wscale == 52
+    assert r1.wsum_int() == [int(h) << 52 for h in r1.hist]
+    assert np.array_equal(r1.whist(), r1.hist.astype(np.float64))
+    w = synth.uniform_values(n, 0.5, 1.0, 52)
+    ra = oracle.count_3pcf(x, L, 0.0, 2.0, 6, weights=w)
+    rb = oracle.count_3pcf(x, L, 0.0, 2.0, 6, weights=2.0 * w)
+    assert ra.wscale == 55 and rb.wscale == 52
+    assert ra.wsum_int() == rb.wsum_int()          # same integers, scale 2^3 larger
+    assert np.array_equal(rb.whist(), 8.0 * ra.whist())
+    # against a naive extended-precision sum of the same products
+    _, _, adj, bins = brute.pair_matrix(x, L, 0.0, 2.0, 6)
+    naive = np.zeros(oracle.n_configs(6), dtype=np.longdouble)
+    rank = brute.lex_configs(6)
+    ii, jj = np.nonzero(np.triu(adj, 1))
+    for i, j in zip(ii, jj):
+        for k in np.nonzero(adj[i, j + 1:] & adj[j, j + 1:])[0] + j + 1:
+            s = sorted((w[i], w[j], w[k]))
+            naive[rank[tuple(sorted((bins[i, j], bins[i, k], bins[j, k])))]] += np.longdouble((s[0] * s[1]) * s[2])
+    got = ra.whist()
+    nz = naive > 0
+    assert np.all(np.abs(got[nz] - naive[nz].astype(np.float64)) <= 1e-12 * naive[nz].astype(np.float64))
+
+
+# ------------------------------------------------ Poisson closed forms ------
+
+def _expected_config_fraction(L, rmax, nb, h_steps=240):
+    """For three uniform points in a periodic box with rmax <= L/4: expected
+    fraction of labelled triples in each sorted-bin configuration. Side-length
+    density 8 pi^2 r1 r2 r3 / L^6 on the triangle-inequality region; the r3
+    integral is done in closed form, (r1, r2) by a midpoint rule."""
+    D = rmax / nb
+    rank = brute.lex_configs(nb)
+    out = np.zeros(len(rank))
+    u = (np.arange(h_steps) + 0.5) / h_steps * D
+    for b1 in range(nb):
+        r1 = b1 * D + u
+        for b2 in range(nb):
+            r2 = b2 * D + u
+            R1, R2 = np.meshgrid(r1, r2, indexing="ij")
+            for b3 in range(nb):
+                lo = np.maximum(b3 * D, np.abs(R1 - R2))
+                hi = np.minimum((b3 + 1) * D, R1 + R2)
+                inner = np.where(hi > lo, 0.5 * (hi * hi - lo * lo), 0.0)
+                val = 8 * math.pi ** 2 * np.sum(R1 * R2 * inner) * (D / h_steps) ** 2 / L ** 6
+                out[rank[tuple(sorted((b1, b2, b3)))]] += val
+    return out
+
+
+def test_poisson_closed_form_total_and_bins():
+    """Mean over 20 uniform seeds against E[n_T] = C(N,3) (5 pi^2/6) (R/L)^6
+    and the per-configuration integrals, within 4 standard errors."""
+    N, L, R, nb = 3000, 100.0, 10.0, 4
+    frac = _expected_config_fraction(L, R, nb)
+    ntrip = N * (N - 1) * (N - 2) / 6
+    assert abs(frac.sum() - 5 * math.pi ** 2 / 6 * (R / L) ** 6) < 1e-4 * frac.sum()
+    hs, ts = [], []
+    for seed in range(20):
+        r = oracle.count_3pcf(synth.uniform(N, L, 1000 + seed), L, 0.0, R, nb)
+        hs.append(r.hist.astype(np.float64))
+        ts.append(r.n_triangles)
+    hs = np.array(hs)
+    ts = np.array(ts, dtype=np.float64)
+    exp_total = ntrip * 5 * math.pi ** 2 / 6 * (R / L) ** 6
+    se = ts.std(ddof=1) / math.sqrt(len(ts))
+    assert abs(ts.mean() - exp_total) < 4 * se, (ts.mean(), exp_total, se)
+    m = hs.mean(axis=0)
+    s = hs.std(axis=0, ddof=1) / math.sqrt(len(hs))
+    e = ntrip * frac
+    big = e > 50
+    z = np.abs(m[big] - e[big]) / np.maximum(s[big], 1e-9)
+    assert z.max() < 4.5, z
+
+
+def test_sum_over_bins_invariants():
+    w = synth.workload("uniform_3pcf", volume_fraction=0.125)
+    r = oracle.count_3pcf(w.xyz, w.box, w.rmin, w.rmax, w.nbins)
+    assert int(r.hist.sum()) == r.n_triangles
+    r4 = oracle.count_4pcf_parity(w.xyz, w.box, w.rmin, w.rmax, w.nbins)
+    assert int(r4.even.sum()) == 4 * r4.n_cliques
+    assert np.all(r4.pos + r4.neg <= r4.even)
+    # parity-symmetric field: odd channel consistent with zero
+    tot = float(r4.pos.sum() + r4.neg.sum())
+    assert abs(float(r4.pos.sum()) - float(r4.neg.sum())) < 4 * math.sqrt(max(tot, 1.0)) * 2
