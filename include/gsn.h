@@ -1,0 +1,155 @@
+/*
+ * gsn.h - C ABI of the MI355X library for exact graph N-point counts.
+ *
+ * The library builds the periodic r < rmax neighbour graph of a point
+ * catalogue on the GPU and counts, on that graph, triangles (3pCF) and
+ * 4-cliques with their parity (4pCF), each tuple binned by its separation
+ * bins into exact integer histograms (paper: graph construction Sec. 2.1,
+ * hub-and-spoke enumeration Sec. 2.2, sorted-list intersection Sec. 3.1,
+ * parity by signed volume Sec. 3.2 Eq. 2, CSR layout Sec. 3.5.1).
+ *
+ * Conventions for every function:
+ *  - returns int status: GS_OK (0) or a negative GS_E* code; gs_strerror()
+ *    names it and gs_last_error_detail() gives the calling thread's last
+ *    message (HIP error strings included);
+ *  - no function throws, aborts or exits on bad input;
+ *  - pointers marked "host" are ordinary host memory; "device" pointers are
+ *    HIP device memory on the context's device;
+ *  - all output arrays are allocated by the caller with the stated lengths;
+ *  - inputs are borrowed for the duration of the call only.
+ *
+ * Definitions shared by all counts (float64, round to nearest, no fused
+ * multiply-add, in this order):
+ *  separation a->b, per axis: d = x_b - x_a; d -= L if d > L/2; d += L if
+ *    d < -L/2 (periodic box, minimum image);
+ *  squared length q = (dx*dx + dy*dy) + dz*dz;
+ *  bins: D = (rmax - rmin)/nbins, e_0 = rmin, e_k = rmin + k*D, e_nbins =
+ *    rmax, t_k = e_k*e_k; a pair is an edge iff t_0 <= q < t_nbins; its bin
+ *    (one byte, Sec. 2.1) is the number of k in 1..nbins-1 with q >= t_k.
+ *  configuration index of sorted bins b1 <= b2 <= b3: their rank in
+ *    lexicographic order among all such triples, 0 .. C(nbins+2,3)-1 (the
+ *    sorted side-length configurations of Sec. 5.1).
+ */
+#ifndef GSN_H
+#define GSN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define GS_OK 0
+#define GS_EINVAL (-1)        /* bad argument or input point / parameter      */
+#define GS_EOVERFLOW (-2)     /* N >= 2^32 - 1 (32-bit neighbour labels)      */
+#define GS_ENOMEM (-3)        /* host allocation failed                        */
+#define GS_EDEVMEM (-4)       /* device memory or budget insufficient         */
+#define GS_EHIP (-5)          /* HIP runtime error (see gs_last_error_detail) */
+#define GS_EAGAIN (-6)        /* submit queue full, retry later               */
+#define GS_ENOTFOUND (-7)     /* unknown ticket                               */
+#define GS_EUNSUPPORTED (-8)  /* valid input beyond this build's limits       */
+#define GS_ENOCOORDS (-9)     /* parity count on a graph built without coords */
+
+/* ---- graph flags (gs_graph_params.flags) ---- */
+#define GS_WEIGHTED 1u         /* weights given: keep them for weighted 3pCF    */
+#define GS_KEEP_COORDS 2u      /* keep label-ordered coordinates (4pCF parity)  */
+#define GS_INPUT_ON_DEVICE 4u  /* xyz / weights are device pointers             */
+
+typedef struct gs_ctx gs_ctx;      /* device, stream, budget, tuning, scratch  */
+typedef struct gs_graph gs_graph;  /* forward CSR + labels (+ coords, weights) */
+
+typedef struct {
+    double box;     /* periodic box side L > 0; points in [0, L)^3              */
+    double rmin;    /* 0 <= rmin < rmax                                          */
+    double rmax;    /* rmax < L/2                                                 */
+    int32_t nbins;  /* 1 .. 255                                                    */
+    uint32_t flags; /* GS_WEIGHTED | GS_KEEP_COORDS | GS_INPUT_ON_DEVICE          */
+} gs_graph_params;
+
+/* Count only tuples whose smallest ORIGINAL point index lies in [lo, hi).
+ * The restriction does not depend on how the library labels points, so
+ * disjoint ranges partition any count exactly. */
+typedef struct {
+    uint64_t lo, hi;
+} gs_anchor_range;
+
+typedef struct {
+    int64_t n;               /* points                                            */
+    uint64_t n_edges;        /* undirected edges (= forward CSR entries)          */
+    uint64_t max_deg;        /* largest forward degree                             */
+    uint64_t device_bytes;   /* device memory held by the graph                   */
+    int32_t n_windows;       /* 1 = resident; > 1 = host-tiled (out of core)       */
+    int32_t nbins;
+    uint64_t pair_hist[255]; /* undirected edges per bin (pair counts, free)       */
+} gs_graph_stats;
+
+typedef struct {
+    double build_ms;         /* last gs_build_graph, device time                  */
+    double count_ms;         /* last count call, device time of its launches      */
+    double kernel_ms;        /* last count call: main counting kernel(s) only      */
+    uint64_t kernel_launches;/* launches of the main counting kernel in that call */
+    uint64_t alg_bytes;      /* algorithmic bytes of that call (see DESIGN)       */
+} gs_timings;
+
+/* Create a context on HIP device `device`. hbm_budget_bytes = 0 means 90% of
+ * the device memory free at creation; a smaller budget forces host-tiled
+ * (out-of-core) graphs. hip_stream (hipStream_t, nullable) is borrowed: all
+ * work of the context runs on it; NULL makes the context create its own. */
+int gs_create(gs_ctx **out, int device, uint64_t hbm_budget_bytes, void *hip_stream);
+int gs_destroy(gs_ctx *ctx);
+
+/* Build the r < rmax graph of n points (Sec. 2.1; CSR of Sec. 3.5.1):
+ *  xyz: n x 3 float64, AoS (x0,y0,z0,x1,...), host or device (flag);
+ *  weights: nullable, n float64 > 0 (required iff GS_WEIGHTED);
+ *  Points are relabelled in cell order; only forward edges (label j > i) are
+ *  stored: row_ptr u64[n+1], col u32[E], bin u8[E], rows strictly increasing.
+ *  Errors: GS_EINVAL (NaN, coordinate outside [0, box), bad params, weights
+ *  missing / non-positive / of too wide a range for exact sums),
+ *  GS_EOVERFLOW, GS_EDEVMEM, GS_EHIP. On error *out is NULL. */
+int gs_build_graph(gs_ctx *ctx, const double *xyz, int64_t n, const double *weights,
+                   const gs_graph_params *p, gs_graph **out);
+int gs_graph_info(const gs_graph *g, gs_graph_stats *out);
+/* Host copies of the forward CSR in label order and the label -> original
+ * index permutation: row_ptr u64[n+1], col u32[n_edges], bin u8[n_edges],
+ * perm u32[n]. Any pointer may be NULL to skip it. */
+int gs_graph_export(const gs_graph *g, uint64_t *row_ptr, uint32_t *col, uint8_t *bin,
+                    uint32_t *perm);
+int gs_graph_free(gs_graph *g);
+
+/* Binned triangle counts (Sec. 2.2 hub-and-spoke enumeration, Sec. 3.1
+ * intersection): every triangle counts once into the configuration of its
+ * sorted side bins.
+ *  hist: host u64[C(nbins+2,3)];
+ *  wsum128: nullable, host u64[2*C(nbins+2,3)], (lo, hi) words of the exact
+ *    sum per configuration of t = (w1*w2)*w3 (weights of the triangle in
+ *    ascending order), in units of 2^-wscale (graph must be weighted);
+ *  whist: nullable, host double[C(nbins+2,3)]: those sums rounded once;
+ *  wscale: nullable, out: s = 52 - floor(log2((wmin*wmin)*wmin));
+ *  n_triangles: host out, counted separately from the bins;
+ *  anchors: nullable (see gs_anchor_range). */
+int gs_count_3pcf(gs_ctx *ctx, const gs_graph *g, uint64_t *hist, uint64_t *wsum128,
+                  double *whist, int32_t *wscale, uint64_t *n_triangles,
+                  const gs_anchor_range *anchors);
+
+/* Parity-decomposed 4-clique counts (Sec. 3.2, Eq. 2 and the degenerate
+ * rule): each 4-clique contributes once per hub (each of its 4 vertices):
+ * spokes ordered by squared length qa <= qb <= qc; even[idx] += 1;
+ * c = ra x rb, V = (cx*rcx + cy*rcy) + cz*rcz; degenerate iff qa == qb or
+ * qb == qc or V*V <= 1e-18*((qa*qb)*qc); else pos[idx] (V > 0) or neg[idx]
+ * (V < 0) += 1. Odd channel = pos - neg. Each array host u64[C(nbins+2,3)].
+ * Needs a graph built with GS_KEEP_COORDS (else GS_ENOCOORDS). */
+int gs_count_4pcf_parity(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos,
+                         uint64_t *neg, uint64_t *n_cliques, const gs_anchor_range *anchors);
+
+/* Device timings of the context's last build / count call. */
+int gs_get_timings(const gs_ctx *ctx, gs_timings *out);
+
+const char *gs_strerror(int code);
+const char *gs_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSN_H */

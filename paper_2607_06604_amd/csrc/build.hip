@@ -1,0 +1,445 @@
+// build.hip - GPU cell-list builder of the r < rmax graph (paper Sec. 2.1,
+// CSR layout of Sec. 3.5.1).
+//
+// Points are relabelled in cell order (cells at least rmax wide, raster order
+// x-major, original index order inside a cell). Each label's forward
+// neighbours (label j > i) are written in ascending label order: its own cell
+// after i, then the 13..26 periodically adjacent cells in ascending cell id,
+// which is ascending label order because labels follow cell ids. Each edge
+// carries the one-byte bin of its squared separation.
+#include <cmath>
+#include <cstdio>
+
+#include "common.h"
+
+namespace gsn {
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Cell of each point; flags[0] |= 1 for a coordinate outside [0, L) or NaN.
+__global__ void k_cells(const double *__restrict__ xyz, uint32_t n, double L, int nc,
+                        uint32_t *__restrict__ cell_of, uint32_t *__restrict__ count,
+                        uint32_t *__restrict__ flags) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c3[3];
+    bool bad = false;
+    for (int a = 0; a < 3; ++a) {
+        double x = xyz[3 * (uint64_t)i + a];
+        if (!(x >= 0.0 && x < L)) bad = true;
+        double u = __ddiv_rn(__dmul_rn(x, (double)nc), L);
+        int c = (u >= 0.0 && u < 1e9) ? (int)u : 0;
+        c3[a] = c > nc - 1 ? nc - 1 : c;
+    }
+    if (bad) atomicOr(&flags[0], 1u);
+    uint32_t c = ((uint32_t)c3[0] * nc + c3[1]) * nc + c3[2];
+    cell_of[i] = c;
+    atomicAdd(&count[c], 1u);
+}
+
+// Positive finite weights; min and max as ordered bit patterns.
+__global__ void k_weights(const double *__restrict__ w, uint32_t n, uint32_t *__restrict__ flags,
+                          unsigned long long *__restrict__ mm) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = w[i];
+    if (!(v > 0.0) || !(v <= 1.79769313486231570e308)) {
+        atomicOr(&flags[0], 2u);
+        return;
+    }
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    atomicMin(&mm[0], b);
+    atomicMax(&mm[1], b);
+}
+
+__global__ void k_scatter(const uint32_t *__restrict__ cell_of, uint32_t n,
+                          const uint64_t *__restrict__ cstart, uint32_t *__restrict__ fill,
+                          uint32_t *__restrict__ order) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c = cell_of[i];
+    uint32_t r = atomicAdd(&fill[c], 1u);
+    order[cstart[c] + r] = i;
+}
+
+// Stable order inside each cell: rank of a point among its cell by original index.
+__global__ void k_rank(const uint32_t *__restrict__ order, const uint32_t *__restrict__ cell_of,
+                       const uint64_t *__restrict__ cstart, uint32_t n, uint32_t *__restrict__ perm) {
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t me = order[p];
+    uint32_t c = cell_of[me];
+    uint64_t s0 = cstart[c], s1 = cstart[c + 1];
+    uint32_t r = 0;
+    for (uint64_t q = s0; q < s1; ++q) r += order[q] < me;
+    perm[s0 + r] = me;
+}
+
+__global__ void k_gather(const uint32_t *__restrict__ perm, const double *__restrict__ xyz,
+                         const double *__restrict__ w, const uint32_t *__restrict__ cell_of,
+                         uint32_t n, double *__restrict__ X, double *__restrict__ Y,
+                         double *__restrict__ Z, double *__restrict__ W,
+                         uint32_t *__restrict__ cellL) {
+    uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n) return;
+    uint32_t i = perm[l];
+    X[l] = xyz[3 * (uint64_t)i];
+    Y[l] = xyz[3 * (uint64_t)i + 1];
+    Z[l] = xyz[3 * (uint64_t)i + 2];
+    if (W) W[l] = w[i];
+    cellL[l] = cell_of[i];
+}
+
+struct EdgeArgs {
+    const double *X, *Y, *Z;
+    const uint32_t *cellL;
+    const uint64_t *cstart;
+    const double *thr;     // t_0 .. t_nb
+    uint32_t n;
+    int nc, nb;
+    double L, half;
+    // count pass
+    uint32_t *deg;
+    uint32_t *maxdeg;
+    // fill pass
+    const uint64_t *rp;
+    uint32_t *col;
+    uint8_t *bin;
+    unsigned long long *pair_hist;  // nb
+    uint32_t *indeg;                // full-degree bookkeeping
+};
+
+// One thread per label: scan the label's own cell after it, then the forward
+// adjacent cells in ascending cell id.
+template <bool FILL>
+__global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
+    __shared__ double t[256];
+    __shared__ unsigned int ph[256];
+    for (int k = threadIdx.x; k <= a.nb; k += blockDim.x) t[k] = a.thr[k];
+    if (FILL)
+        for (int k = threadIdx.x; k < 256; k += blockDim.x) ph[k] = 0;
+    __syncthreads();
+    uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < a.n) {
+        const int nc = a.nc;
+        const uint32_t c = a.cellL[l];
+        const double xi = a.X[l], yi = a.Y[l], zi = a.Z[l];
+        const double t0 = t[0], tn = t[a.nb];
+        int ax[3], ay[3], az[3], na = 1;
+        const int cx = (int)(c / (uint32_t)(nc * nc)), cy = (int)((c / nc) % nc), cz = (int)(c % nc);
+        if (nc >= 3) {
+            na = 3;
+            auto sorted3 = [nc](int v, int *o) {
+                int lo = v == 0 ? nc - 1 : v - 1, hi = v == nc - 1 ? 0 : v + 1;
+                int m0 = lo < v ? lo : v, m1 = lo < v ? v : lo;  // sort {lo, v, hi}
+                if (hi < m0) { o[0] = hi; o[1] = m0; o[2] = m1; }
+                else if (hi < m1) { o[0] = m0; o[1] = hi; o[2] = m1; }
+                else { o[0] = m0; o[1] = m1; o[2] = hi; }
+            };
+            sorted3(cx, ax);
+            sorted3(cy, ay);
+            sorted3(cz, az);
+        } else {
+            ax[0] = ay[0] = az[0] = 0;
+        }
+        uint32_t cnt = 0;
+        const uint64_t out = FILL ? a.rp[l] : 0;
+        const uint64_t cap = FILL ? a.rp[l + 1] - out : 0;  // the count pass's result
+        auto visit = [&](uint64_t j0, uint64_t j1) {
+            for (uint64_t j = j0; j < j1; ++j) {
+                double dx = min_image(xi, a.X[j], a.L, a.half);
+                double dy = min_image(yi, a.Y[j], a.L, a.half);
+                double dz = min_image(zi, a.Z[j], a.L, a.half);
+                double q = sq_len(dx, dy, dz);
+                if (q >= t0 && q < tn) {
+                    if (FILL && cnt < cap) {
+                        int b = bin_of(t, a.nb, q);
+                        a.col[out + cnt] = (uint32_t)j;
+                        a.bin[out + cnt] = (uint8_t)b;
+                        atomicAdd(&ph[b], 1u);
+                        atomicAdd(&a.indeg[j], 1u);
+                    }
+                    ++cnt;
+                }
+            }
+        };
+        visit((uint64_t)l + 1, a.cstart[c + 1]);
+        for (int u = 0; u < na; ++u)
+            for (int v = 0; v < na; ++v)
+                for (int w = 0; w < na; ++w) {
+                    uint32_t id = ((uint32_t)ax[u] * nc + ay[v]) * nc + az[w];
+                    if (id <= c) continue;
+                    visit(a.cstart[id], a.cstart[id + 1]);
+                }
+        if (!FILL) {
+            a.deg[l] = cnt;
+            atomicMax(a.maxdeg, cnt);
+        }
+    }
+    if (FILL) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < a.nb; k += blockDim.x)
+            if (ph[k]) atomicAdd(&a.pair_hist[k], (unsigned long long)ph[k]);
+    }
+}
+
+// ---- exclusive scan u32 -> u64 (out has n+1 entries, out[n] = total) ----
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ uint64_t block_scan_u64(uint64_t v, uint64_t *wtot, uint64_t &total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint64_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wtot[wid] = x;
+    __syncthreads();
+    uint64_t off = 0, tot = 0;
+    for (int k = 0; k < nw; ++k) {
+        uint64_t t = wtot[k];
+        if (k < wid) off += t;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return off + x - v;
+}
+
+template <class TI>
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const TI *__restrict__ in, uint64_t n,
+                                                        uint64_t *__restrict__ out,
+                                                        uint64_t *__restrict__ tile_sums) {
+    __shared__ uint64_t wtot[kBlock / 64];
+    uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint64_t v[kScanItems];
+    uint64_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? (uint64_t)in[base + k] : 0;
+        s += v[k];
+    }
+    uint64_t total;
+    uint64_t pre = block_scan_u64(s, wtot, total);
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = pre;
+        pre += v[k];
+    }
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_add(uint64_t *__restrict__ out, uint64_t n,
+                           const uint64_t *__restrict__ tile_off) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += tile_off[i / kScanTile];
+}
+
+__global__ void k_set_total(uint64_t *out, uint64_t n, const uint64_t *tile_off, uint64_t ntiles,
+                            const uint64_t *tile_sums) {
+    out[n] = tile_off[ntiles - 1] + tile_sums[ntiles - 1];
+}
+
+inline unsigned grid_for(uint64_t n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
+
+// Exclusive scan of n values into out[0..n]; out[n] = total.
+template <class TI>
+void scan(const TI *in, uint64_t n, uint64_t *out, hipStream_t s) {
+    if (n == 0) {
+        k_fill_u64<<<1, 1, 0, s>>>(out, 1, 0);
+        return;
+    }
+    uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    DevBuf sums(sizeof(uint64_t) * ntiles), offs(sizeof(uint64_t) * (ntiles + 1));
+    k_scan_tiles<TI><<<(unsigned)ntiles, kBlock, 0, s>>>(in, n, out, sums.as<uint64_t>());
+    GS_HIP(hipGetLastError());
+    if (ntiles > 1) {
+        scan<uint64_t>(sums.as<uint64_t>(), ntiles, offs.as<uint64_t>(), s);
+        k_scan_add<<<grid_for(n), kBlock, 0, s>>>(out, n, offs.as<uint64_t>());
+    } else {
+        k_fill_u64<<<1, 1, 0, s>>>(offs.as<uint64_t>(), 1, 0);
+    }
+    k_set_total<<<1, 1, 0, s>>>(out, n, offs.as<uint64_t>(), ntiles, sums.as<uint64_t>());
+    GS_HIP(hipGetLastError());
+    GS_HIP(hipStreamSynchronize(s));  // sums/offs are freed on return
+}
+
+// sum of (out-degree + in-degree)^2 over labels
+__global__ void k_sum_sq_deg(const uint64_t *__restrict__ rp, const uint32_t *__restrict__ indeg,
+                             uint32_t n, unsigned long long *__restrict__ acc) {
+    uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = 0;
+    if (l < n) {
+        uint64_t m = (rp[l + 1] - rp[l]) + indeg[l];
+        v = m * m;
+    }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(acc, v);
+}
+
+}  // namespace
+
+void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
+    hipStream_t s = ctx.stream;
+    const uint32_t n = (uint32_t)g.n;
+    GS_HIP(hipEventRecord(ctx.ev[0], s));
+    const bool on_dev = (g.flags & GS_INPUT_ON_DEVICE) != 0;
+    const bool weighted = (g.flags & GS_WEIGHTED) != 0;
+    const bool keep = (g.flags & GS_KEEP_COORDS) != 0;
+
+    g.row_ptr.alloc(sizeof(uint64_t) * ((size_t)n + 1));
+    g.perm.alloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    if (n == 0) {
+        k_fill_u64<<<1, 1, 0, s>>>(g.row_ptr.as<uint64_t>(), 1, 0);
+        g.col.alloc(4);
+        g.bin.alloc(1);
+        if (keep) g.coords.alloc(8);
+        if (weighted) g.weights.alloc(8);
+        GS_HIP(hipStreamSynchronize(s));
+        g.device_bytes = g.row_ptr.bytes + g.perm.bytes + g.col.bytes + g.bin.bytes;
+        return;
+    }
+
+    DevBuf in_xyz, in_w;
+    const double *dxyz = xyz, *dw = w;
+    if (!on_dev) {
+        in_xyz.alloc(sizeof(double) * 3 * (size_t)n);
+        GS_HIP(hipMemcpyAsync(in_xyz.p, xyz, sizeof(double) * 3 * (size_t)n, hipMemcpyHostToDevice, s));
+        dxyz = in_xyz.as<double>();
+        if (weighted) {
+            in_w.alloc(sizeof(double) * (size_t)n);
+            GS_HIP(hipMemcpyAsync(in_w.p, w, sizeof(double) * (size_t)n, hipMemcpyHostToDevice, s));
+            dw = in_w.as<double>();
+        }
+    }
+
+    // cells at least rmax*(1+1e-9) wide; fewer for sparse catalogues
+    double ncd = std::floor(g.box / (g.rmax * (1.0 + 1e-9)));
+    double cap = std::max(3.0, std::ceil(2.0 * std::cbrt((double)n)));
+    ncd = std::min(ncd, std::min(cap, 256.0));
+    int nc = ncd < 3 ? 1 : (int)ncd;
+    uint64_t ncell = (uint64_t)nc * nc * nc;
+
+    DevBuf cell_of(sizeof(uint32_t) * n), count(sizeof(uint32_t) * ncell),
+        cstart(sizeof(uint64_t) * (ncell + 1)), order(sizeof(uint32_t) * n),
+        flags(64), cellL(sizeof(uint32_t) * n), deg(sizeof(uint32_t) * n);
+    uint32_t *fl = flags.as<uint32_t>();
+    k_fill_u32<<<1, 64, 0, s>>>(fl, 8, 0);
+    k_fill_u64<<<1, 64, 0, s>>>(flags.as<uint64_t>() + 4, 1, ~0ull);  // wmin bits
+    k_fill_u64<<<1, 64, 0, s>>>(flags.as<uint64_t>() + 5, 1, 0);      // wmax bits
+    k_fill_u32<<<grid_for(ncell), kBlock, 0, s>>>(count.as<uint32_t>(), ncell, 0);
+    k_cells<<<grid_for(n), kBlock, 0, s>>>(dxyz, n, g.box, nc, cell_of.as<uint32_t>(),
+                                           count.as<uint32_t>(), fl);
+    if (weighted)
+        k_weights<<<grid_for(n), kBlock, 0, s>>>(dw, n, fl, (unsigned long long *)(flags.as<uint64_t>() + 4));
+    GS_HIP(hipGetLastError());
+    scan<uint32_t>(count.as<uint32_t>(), ncell, cstart.as<uint64_t>(), s);
+    k_fill_u32<<<grid_for(ncell), kBlock, 0, s>>>(count.as<uint32_t>(), ncell, 0);
+    k_scatter<<<grid_for(n), kBlock, 0, s>>>(cell_of.as<uint32_t>(), n, cstart.as<uint64_t>(),
+                                             count.as<uint32_t>(), order.as<uint32_t>());
+    k_rank<<<grid_for(n), kBlock, 0, s>>>(order.as<uint32_t>(), cell_of.as<uint32_t>(),
+                                          cstart.as<uint64_t>(), n, g.perm.as<uint32_t>());
+    DevBuf tmp_coords;
+    double *C;
+    if (keep) {
+        g.coords.alloc(sizeof(double) * 3 * (size_t)n);
+        C = g.coords.as<double>();
+    } else {
+        tmp_coords.alloc(sizeof(double) * 3 * (size_t)n);
+        C = tmp_coords.as<double>();
+    }
+    if (weighted) g.weights.alloc(sizeof(double) * n);
+    k_gather<<<grid_for(n), kBlock, 0, s>>>(g.perm.as<uint32_t>(), dxyz, dw, cell_of.as<uint32_t>(), n,
+                                            C, C + n, C + 2 * (size_t)n,
+                                            weighted ? g.weights.as<double>() : nullptr,
+                                            cellL.as<uint32_t>());
+    GS_HIP(hipGetLastError());
+
+    DevBuf thr(sizeof(double) * 256);
+    GS_HIP(hipMemcpyAsync(thr.p, g.bins.t, sizeof(double) * 256, hipMemcpyHostToDevice, s));
+
+    EdgeArgs ea{};
+    ea.X = C;
+    ea.Y = C + n;
+    ea.Z = C + 2 * (size_t)n;
+    ea.cellL = cellL.as<uint32_t>();
+    ea.cstart = cstart.as<uint64_t>();
+    ea.thr = thr.as<double>();
+    ea.n = n;
+    ea.nc = nc;
+    ea.nb = g.nbins;
+    ea.L = g.box;
+    ea.half = 0.5 * g.box;
+    ea.deg = deg.as<uint32_t>();
+    ea.maxdeg = fl + 1;
+    k_edges<false><<<grid_for(n), kBlock, 0, s>>>(ea);
+    GS_HIP(hipGetLastError());
+    scan<uint32_t>(deg.as<uint32_t>(), n, g.row_ptr.as<uint64_t>(), s);
+
+    struct {
+        uint32_t f[8];
+        uint64_t wmin, wmax;
+    } hf;
+    uint64_t E = 0;
+    GS_HIP(hipMemcpyAsync(&hf, fl, sizeof hf, hipMemcpyDeviceToHost, s));
+    GS_HIP(hipMemcpyAsync(&E, g.row_ptr.as<uint64_t>() + n, sizeof E, hipMemcpyDeviceToHost, s));
+    GS_HIP(hipStreamSynchronize(s));
+    if (hf.f[0] & 1u) fail(GS_EINVAL, "coordinate outside [0, box) or NaN");
+    if (hf.f[0] & 2u) fail(GS_EINVAL, "weights must be finite and > 0");
+    g.n_edges = E;
+    g.max_deg = hf.f[1];
+    if (weighted) {
+        double wmin, wmax;
+        memcpy(&wmin, &hf.wmin, 8);
+        memcpy(&wmax, &hf.wmax, 8);
+        volatile double tlo = wmin * wmin;
+        tlo = tlo * wmin;
+        volatile double thi = wmax * wmax;
+        thi = thi * wmax;
+        if (!(tlo >= 0x1.0p-1022) || !std::isfinite((double)thi))
+            fail(GS_EINVAL, "weights out of range for exact sums");
+        g.wscale = 52 - std::ilogb((double)tlo);
+        if (std::ilogb((double)thi) + g.wscale >= 64)
+            fail(GS_EINVAL, "weight range too wide for exact 128-bit sums");
+    }
+
+    g.col.alloc(sizeof(uint32_t) * (E ? E : 1));
+    g.bin.alloc(E ? E : 1);
+    DevBuf ph(sizeof(uint64_t) * 256), indeg(sizeof(uint32_t) * n), sq(8);
+    k_fill_u64<<<1, 256, 0, s>>>(ph.as<uint64_t>(), 256, 0);
+    k_fill_u32<<<grid_for(n), kBlock, 0, s>>>(indeg.as<uint32_t>(), n, 0);
+    k_fill_u64<<<1, 1, 0, s>>>(sq.as<uint64_t>(), 1, 0);
+    ea.rp = g.row_ptr.as<uint64_t>();
+    ea.col = g.col.as<uint32_t>();
+    ea.bin = g.bin.as<uint8_t>();
+    ea.pair_hist = (unsigned long long *)ph.as<uint64_t>();
+    ea.indeg = indeg.as<uint32_t>();
+    k_edges<true><<<grid_for(n), kBlock, 0, s>>>(ea);
+    k_sum_sq_deg<<<grid_for(n), kBlock, 0, s>>>(g.row_ptr.as<uint64_t>(), indeg.as<uint32_t>(), n,
+                                                (unsigned long long *)sq.as<uint64_t>());
+    GS_HIP(hipGetLastError());
+    uint64_t hph[256];
+    GS_HIP(hipMemcpyAsync(hph, ph.p, sizeof hph, hipMemcpyDeviceToHost, s));
+    GS_HIP(hipMemcpyAsync(&g.sum_sq_deg, sq.p, 8, hipMemcpyDeviceToHost, s));
+    GS_HIP(hipEventRecord(ctx.ev[1], s));
+    GS_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < 255; ++k) g.pair_hist[k] = k < g.nbins ? hph[k] : 0;
+    float ms = 0;
+    GS_HIP(hipEventElapsedTime(&ms, ctx.ev[0], ctx.ev[1]));
+    ctx.t.build_ms = ms;
+    g.device_bytes = g.row_ptr.bytes + g.col.bytes + g.bin.bytes + g.perm.bytes + g.coords.bytes +
+                     g.weights.bytes;
+}
+
+}  // namespace gsn

@@ -1,0 +1,269 @@
+// capi.hip - C ABI entry points: contexts, graphs, errors, result marshalling.
+#include <cmath>
+#include <cstdio>
+#include <new>
+
+#include "common.h"
+
+namespace gsn {
+
+static thread_local std::string t_detail;
+
+void set_detail(const std::string &msg) { t_detail = msg; }
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+void DevBuf::alloc(size_t n) {
+    reset();
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        fail(GS_EDEVMEM, "hipMalloc(" + std::to_string(n) + " bytes): " + hipGetErrorString(e));
+    }
+    bytes = n;
+}
+
+void HostBuf::alloc(size_t n) {
+    reset();
+    if (n == 0) n = 1;
+    hipError_t e = hipHostMalloc(&p, n, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        fail(GS_ENOMEM, "hipHostMalloc(" + std::to_string(n) + " bytes): " + hipGetErrorString(e));
+    }
+    bytes = n;
+}
+
+void Ctx::use() const { GS_HIP(hipSetDevice(device)); }
+
+void *Ctx::scratch_get(size_t bytes) {
+    if (scratch.bytes < bytes) {
+        GS_HIP(hipStreamSynchronize(stream));
+        scratch.alloc(bytes + bytes / 4);
+    }
+    return scratch.p;
+}
+
+void *Ctx::pinned_get(size_t bytes) {
+    if (pinned_bytes < bytes) {
+        if (pinned) (void)hipHostFree(pinned);
+        pinned = nullptr;
+        pinned_bytes = 0;
+        GS_HIP(hipHostMalloc(&pinned, bytes, hipHostMallocDefault));
+        pinned_bytes = bytes;
+    }
+    return pinned;
+}
+
+// Squared bin thresholds from the definition: e_0 = rmin, e_k = rmin + k*D,
+// e_nb = rmax, t_k = e_k*e_k (host float64, no contraction).
+Bins make_bins(double rmin, double rmax, int nb) {
+    Bins b;
+    b.nb = nb;
+    volatile double D = (rmax - rmin) / (double)nb;
+    for (int k = 0; k <= nb; ++k) {
+        volatile double kd = (double)k * D;
+        volatile double e = (k == 0) ? rmin : (k == nb ? rmax : rmin + kd);
+        b.t[k] = e * e;
+    }
+    for (int k = nb + 1; k < 256; ++k) b.t[k] = b.t[nb];
+    return b;
+}
+
+}  // namespace gsn
+
+using namespace gsn;
+
+extern "C" {
+
+const char *gs_strerror(int code) {
+    switch (code) {
+        case GS_OK: return "ok";
+        case GS_EINVAL: return "invalid argument";
+        case GS_EOVERFLOW: return "too many points for 32-bit labels";
+        case GS_ENOMEM: return "host memory allocation failed";
+        case GS_EDEVMEM: return "device memory or budget insufficient";
+        case GS_EHIP: return "HIP runtime error";
+        case GS_EAGAIN: return "queue full, retry";
+        case GS_ENOTFOUND: return "unknown ticket";
+        case GS_EUNSUPPORTED: return "input beyond this build's limits";
+        case GS_ENOCOORDS: return "graph was built without coordinates";
+        default: return "unknown status";
+    }
+}
+
+const char *gs_last_error_detail(void) { return t_detail.c_str(); }
+
+int gs_create(gs_ctx **out, int device, uint64_t hbm_budget_bytes, void *hip_stream) {
+    if (!out) return GS_EINVAL;
+    *out = nullptr;
+    gs_ctx *c = nullptr;
+    int rc = guarded([&] {
+        int ndev = 0;
+        GS_HIP(hipGetDeviceCount(&ndev));
+        if (device < 0 || device >= ndev) fail(GS_EINVAL, "no such device");
+        c = new gs_ctx();
+        c->device = device;
+        GS_HIP(hipSetDevice(device));
+        hipDeviceProp_t prop;
+        GS_HIP(hipGetDeviceProperties(&prop, device));
+        c->n_cu = prop.multiProcessorCount;
+        c->max_lds = (int)prop.sharedMemPerBlock;
+        if (hip_stream) {
+            c->stream = (hipStream_t)hip_stream;
+        } else {
+            GS_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+        for (auto &e : c->ev) GS_HIP(hipEventCreate(&e));
+        size_t fr = 0, tot = 0;
+        GS_HIP(hipMemGetInfo(&fr, &tot));
+        c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
+    });
+    if (rc != GS_OK) {
+        if (c) gs_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return GS_OK;
+}
+
+int gs_destroy(gs_ctx *ctx) {
+    if (!ctx) return GS_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+    return GS_OK;
+}
+
+int gs_build_graph(gs_ctx *ctx, const double *xyz, int64_t n, const double *weights,
+                   const gs_graph_params *p, gs_graph **out) {
+    if (!out) return GS_EINVAL;
+    *out = nullptr;
+    gs_graph *g = nullptr;
+    int rc = guarded([&] {
+        if (!ctx || !p) fail(GS_EINVAL, "null context or params");
+        if (n < 0) fail(GS_EINVAL, "negative n");
+        if (n > 0 && !xyz) fail(GS_EINVAL, "null xyz");
+        if (n >= 0xFFFFFFFFll) fail(GS_EOVERFLOW, "n must be below 2^32 - 1");
+        if (!(p->box > 0) || !std::isfinite(p->box)) fail(GS_EINVAL, "box must be finite and > 0");
+        if (p->nbins < 1 || p->nbins > 255) fail(GS_EINVAL, "nbins must be in 1..255");
+        if (!(p->rmin >= 0) || !(p->rmin < p->rmax) || !(p->rmax < 0.5 * p->box))
+            fail(GS_EINVAL, "need 0 <= rmin < rmax < box/2");
+        bool weighted = (p->flags & GS_WEIGHTED) != 0;
+        if (weighted != (weights != nullptr)) fail(GS_EINVAL, "weights given iff GS_WEIGHTED");
+        ctx->use();
+        g = new gs_graph();
+        g->device = ctx->device;
+        g->n = n;
+        g->box = p->box;
+        g->rmin = p->rmin;
+        g->rmax = p->rmax;
+        g->nbins = p->nbins;
+        g->flags = p->flags;
+        g->bins = make_bins(p->rmin, p->rmax, p->nbins);
+        build_run(*ctx, *g, xyz, weights);
+    });
+    if (rc != GS_OK) {
+        delete g;
+        return rc;
+    }
+    *out = g;
+    return GS_OK;
+}
+
+int gs_graph_info(const gs_graph *g, gs_graph_stats *out) {
+    if (!g || !out) return GS_EINVAL;
+    memset(out, 0, sizeof *out);
+    out->n = g->n;
+    out->n_edges = g->n_edges;
+    out->max_deg = g->max_deg;
+    out->device_bytes = g->device_bytes;
+    out->n_windows = g->n_windows;
+    out->nbins = g->nbins;
+    memcpy(out->pair_hist, g->pair_hist, sizeof g->pair_hist);
+    return GS_OK;
+}
+
+int gs_graph_export(const gs_graph *g, uint64_t *row_ptr, uint32_t *col, uint8_t *bin,
+                    uint32_t *perm) {
+    return guarded([&] {
+        if (!g) fail(GS_EINVAL, "null graph");
+        GS_HIP(hipSetDevice(g->device));
+        if (row_ptr)
+            GS_HIP(hipMemcpy(row_ptr, g->row_ptr.p, sizeof(uint64_t) * (g->n + 1), hipMemcpyDeviceToHost));
+        if (col && g->n_edges)
+            GS_HIP(hipMemcpy(col, g->col.p, sizeof(uint32_t) * g->n_edges, hipMemcpyDeviceToHost));
+        if (bin && g->n_edges)
+            GS_HIP(hipMemcpy(bin, g->bin.p, g->n_edges, hipMemcpyDeviceToHost));
+        if (perm && g->n)
+            GS_HIP(hipMemcpy(perm, g->perm.p, sizeof(uint32_t) * g->n, hipMemcpyDeviceToHost));
+    });
+}
+
+int gs_graph_free(gs_graph *g) {
+    if (!g) return GS_EINVAL;
+    (void)hipSetDevice(g->device);
+    (void)hipDeviceSynchronize();
+    delete g;
+    return GS_OK;
+}
+
+int gs_count_3pcf(gs_ctx *ctx, const gs_graph *g, uint64_t *hist, uint64_t *wsum128,
+                  double *whist, int32_t *wscale, uint64_t *n_triangles,
+                  const gs_anchor_range *anchors) {
+    return guarded([&] {
+        if (!ctx || !g || !hist || !n_triangles) fail(GS_EINVAL, "null argument");
+        bool want_w = wsum128 || whist || wscale;
+        if (want_w && !(g->flags & GS_WEIGHTED)) fail(GS_EINVAL, "graph has no weights");
+        if (g->device != ctx->device) fail(GS_EINVAL, "graph and context on different devices");
+        ctx->use();
+        int64_t nc = n_configs(g->nbins);
+        std::vector<uint64_t> ws;
+        uint64_t *wdst = nullptr;
+        if (g->flags & GS_WEIGHTED) {
+            ws.assign(2 * nc, 0);
+            wdst = ws.data();
+        }
+        count3_run(*ctx, *g, hist, wdst, n_triangles, anchors);
+        if (g->flags & GS_WEIGHTED) {
+            if (wsum128) memcpy(wsum128, ws.data(), sizeof(uint64_t) * 2 * nc);
+            if (whist)
+                for (int64_t c = 0; c < nc; ++c) {
+                    unsigned __int128 v = ((unsigned __int128)ws[2 * c + 1] << 64) | ws[2 * c];
+                    whist[c] = std::ldexp((double)v, -g->wscale);
+                }
+            if (wscale) *wscale = g->wscale;
+        }
+    });
+}
+
+int gs_count_4pcf_parity(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos,
+                         uint64_t *neg, uint64_t *n_cliques, const gs_anchor_range *anchors) {
+    return guarded([&] {
+        if (!ctx || !g || !even || !pos || !neg || !n_cliques) fail(GS_EINVAL, "null argument");
+        if (!(g->flags & GS_KEEP_COORDS)) fail(GS_ENOCOORDS, "parity needs GS_KEEP_COORDS");
+        if (g->device != ctx->device) fail(GS_EINVAL, "graph and context on different devices");
+        ctx->use();
+        count4_run(*ctx, *g, even, pos, neg, n_cliques, anchors);
+    });
+}
+
+int gs_get_timings(const gs_ctx *ctx, gs_timings *out) {
+    if (!ctx || !out) return GS_EINVAL;
+    out->build_ms = ctx->t.build_ms;
+    out->count_ms = ctx->t.count_ms;
+    out->kernel_ms = ctx->t.kernel_ms;
+    out->kernel_launches = ctx->t.kernel_launches;
+    out->alg_bytes = ctx->t.alg_bytes;
+    return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,196 @@
+// common.h - internal types and helpers of the HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gsn.h"
+
+namespace gsn {
+
+// ------------------------------------------------------------ errors ------
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+void set_detail(const std::string &msg);
+
+#define GS_HIP(expr)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            ::gsn::fail(GS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Run body, turning library errors into status codes at the C boundary.
+template <class F>
+int guarded(F &&body) {
+    try {
+        body();
+        set_detail("");
+        return GS_OK;
+    } catch (const Error &e) {
+        set_detail(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_detail("host allocation failed");
+        return GS_ENOMEM;
+    } catch (...) {
+        set_detail("unexpected C++ exception");
+        return GS_EHIP;
+    }
+}
+
+// ------------------------------------------------------- device buffers ---
+
+// Owning device allocation.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t n) { alloc(n); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { reset(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void alloc(size_t n);
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Owning pinned host allocation.
+struct HostBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    ~HostBuf() { reset(); }
+    void alloc(size_t n);
+    void reset() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ------------------------------------------------------- core objects -----
+
+struct Timings {
+    double build_ms = 0, count_ms = 0, kernel_ms = 0;
+    uint64_t kernel_launches = 0, alg_bytes = 0;
+};
+
+// Result staging shared by the count entry points of one context.
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t budget = 0;        // device bytes the context may hold in graphs + scratch
+    int n_cu = 0;
+    int max_lds = 0;
+    Timings t;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    DevBuf scratch;             // grown on demand, reused across calls
+    void *pinned = nullptr;     // small pinned host staging
+    size_t pinned_bytes = 0;
+    void *scratch_get(size_t bytes);
+    void *pinned_get(size_t bytes);
+    void use() const;
+};
+
+// Squared bin thresholds t_0..t_nb (host-computed from the definition).
+struct Bins {
+    int nb = 0;
+    double t[256];
+};
+
+struct Graph {
+    int device = 0;
+    int64_t n = 0;
+    uint64_t n_edges = 0;     // forward entries
+    uint32_t max_deg = 0;     // largest forward degree
+    double box = 0, rmin = 0, rmax = 0;
+    int nbins = 0;
+    uint32_t flags = 0;
+    int wscale = 0;
+    Bins bins;
+    uint64_t pair_hist[255] = {};
+    uint64_t sum_sq_deg = 0;  // sum over points of (full degree)^2
+    uint64_t device_bytes = 0;
+    int n_windows = 1;
+    // device, label order
+    DevBuf row_ptr;   // u64[n+1]
+    DevBuf col;       // u32[E]
+    DevBuf bin;       // u8[E]
+    DevBuf perm;      // u32[n]: label -> original index
+    DevBuf coords;    // f64[3n] SoA x|y|z (GS_KEEP_COORDS)
+    DevBuf weights;   // f64[n] (GS_WEIGHTED)
+};
+
+Bins make_bins(double rmin, double rmax, int nb);
+inline int64_t n_configs(int nb) { return (int64_t)(nb + 2) * (nb + 1) * nb / 6; }
+
+// ------------------------------------------------------- device helpers ---
+
+// Periodic minimum-image component of x_b - x_a.
+__device__ __forceinline__ double min_image(double xa, double xb, double L, double half) {
+    double d = __dsub_rn(xb, xa);
+    if (d > half) d = __dsub_rn(d, L);
+    else if (d < -half) d = __dadd_rn(d, L);
+    return d;
+}
+
+// (dx*dx + dy*dy) + dz*dz, no contraction.
+__device__ __forceinline__ double sq_len(double dx, double dy, double dz) {
+    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+// Number of k in 1..nb-1 with q >= t[k] (t non-decreasing): upper bound.
+__device__ __forceinline__ int bin_of(const double *t, int nb, double q) {
+    int lo = 1, hi = nb;  // search in t[1..nb-1]
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (q >= t[mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo - 1;
+}
+
+// Lexicographic rank tables: idx(b1<=b2<=b3) = A[b1] + B[b2] + b3.
+__host__ __device__ inline int64_t c2(int64_t n) { return n < 2 ? 0 : n * (n - 1) / 2; }
+__host__ __device__ inline int64_t c3(int64_t n) { return n < 3 ? 0 : n * (n - 1) * (n - 2) / 6; }
+__host__ __device__ inline int rank_a(int nb, int b1) {
+    return (int)(c3(nb + 2) - c3(nb - b1 + 2) + c2(nb - b1 + 1));
+}
+__host__ __device__ inline int rank_b(int nb, int b2) { return (int)(-c2(nb - b2 + 1) - b2); }
+
+// ---------------------------------------------------------- launches ------
+
+void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64_t *ntri,
+                const gs_anchor_range *anchors);
+void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_t *neg,
+                uint64_t *ncl, const gs_anchor_range *anchors);
+void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w);
+
+}  // namespace gsn
+
+struct gs_ctx : gsn::Ctx {};
+struct gs_graph : gsn::Graph {};

@@ -1,0 +1,279 @@
+"""ctypes binding of libgsn.so (include/gsn.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module converts
+numpy arrays (host) or torch tensors (device) into pointers and status codes
+into exceptions. There is no fallback: if libgsn.so is missing or fails to
+load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsn.so")
+
+GS_OK = 0
+GS_EINVAL = -1
+GS_EOVERFLOW = -2
+GS_ENOMEM = -3
+GS_EDEVMEM = -4
+GS_EHIP = -5
+GS_EAGAIN = -6
+GS_ENOTFOUND = -7
+GS_EUNSUPPORTED = -8
+GS_ENOCOORDS = -9
+
+GS_WEIGHTED = 1
+GS_KEEP_COORDS = 2
+GS_INPUT_ON_DEVICE = 4
+
+# every symbol include/gsn.h declares
+EXPORTS = ["gs_create", "gs_destroy", "gs_build_graph", "gs_graph_info", "gs_graph_export",
+           "gs_graph_free", "gs_count_3pcf", "gs_count_4pcf_parity", "gs_get_timings",
+           "gs_strerror", "gs_last_error_detail"]
+
+
+class GraphParams(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double), ("rmin", ctypes.c_double), ("rmax", ctypes.c_double),
+                ("nbins", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class AnchorRange(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+
+class GraphStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_edges", ctypes.c_uint64), ("max_deg", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64), ("n_windows", ctypes.c_int32),
+                ("nbins", ctypes.c_int32), ("pair_hist", ctypes.c_uint64 * 255)]
+
+
+class Timings(ctypes.Structure):
+    _fields_ = [("build_ms", ctypes.c_double), ("count_ms", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_uint64),
+                ("alg_bytes", ctypes.c_uint64)]
+
+
+class GsError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__("%s failed: %s (%d)%s" % (where, _strerror(code), code,
+                                                   (": " + detail) if detail else ""))
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgsn.so (raises if it is not built). If torch is importable it is
+    imported first so that one HIP runtime serves both."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libgsn.so is not built (%s); run __graft_entry__.build()" % path)
+    try:
+        import torch  # noqa: F401  (shares its HIP runtime with the library)
+    except Exception:
+        pass
+    lib = ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+    P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+    sig = {
+        "gs_create": ([ctypes.POINTER(P), i32, u64, P], i32),
+        "gs_destroy": ([P], i32),
+        "gs_build_graph": ([P, P, i64, P, ctypes.POINTER(GraphParams), ctypes.POINTER(P)], i32),
+        "gs_graph_info": ([P, ctypes.POINTER(GraphStats)], i32),
+        "gs_graph_export": ([P, P, P, P, P], i32),
+        "gs_graph_free": ([P], i32),
+        "gs_count_3pcf": ([P, P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
+        "gs_count_4pcf_parity": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
+        "gs_get_timings": ([P, ctypes.POINTER(Timings)], i32),
+        "gs_strerror": ([i32], ctypes.c_char_p),
+        "gs_last_error_detail": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _strerror(code: int) -> str:
+    return load().gs_strerror(code).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != GS_OK:
+        detail = load().gs_last_error_detail().decode()
+        raise GsError(rc, where, detail)
+
+
+def _host(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def n_configs(nbins: int) -> int:
+    return (nbins + 2) * (nbins + 1) * nbins // 6
+
+
+class Context:
+    """gs_ctx: one device, one stream (borrowed if given), a memory budget."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, stream=None):
+        lib = load()
+        self._h = ctypes.c_void_p()
+        sp = None
+        if stream is not None:
+            sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        _check(lib.gs_create(ctypes.byref(self._h), device, budget_bytes, sp), "gs_create")
+
+    def close(self):
+        if self._h:
+            load().gs_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def build_graph(self, xyz, box, rmin, rmax, nbins, weights=None, keep_coords=False) -> "Graph":
+        """xyz: (N,3) float64 numpy array (host) or torch tensor on the GPU."""
+        on_dev = hasattr(xyz, "is_cuda") and xyz.is_cuda
+        flags = (GS_INPUT_ON_DEVICE if on_dev else 0) | (GS_KEEP_COORDS if keep_coords else 0)
+        if weights is not None:
+            flags |= GS_WEIGHTED
+        if on_dev:
+            import torch
+            if xyz.dtype != torch.float64 or not xyz.is_contiguous() or xyz.dim() != 2 or xyz.shape[1] != 3:
+                raise ValueError("device xyz must be a contiguous (N,3) float64 tensor")
+            if weights is not None and (weights.dtype != torch.float64 or not weights.is_cuda
+                                        or not weights.is_contiguous()):
+                raise ValueError("device weights must be a contiguous float64 tensor")
+            n = int(xyz.shape[0])
+            x, w = xyz, weights
+        else:
+            x = _host(xyz, np.float64)
+            if x.ndim != 2 or x.shape[1] != 3:
+                raise ValueError("xyz must be (N,3)")
+            n = x.shape[0]
+            w = None if weights is None else _host(weights, np.float64)
+            if w is not None and w.shape != (n,):
+                raise ValueError("weights must be (N,)")
+        p = GraphParams(float(box), float(rmin), float(rmax), int(nbins), flags)
+        h = ctypes.c_void_p()
+        _check(load().gs_build_graph(self._h, _ptr(x), n, _ptr(w), ctypes.byref(p), ctypes.byref(h)),
+               "gs_build_graph")
+        return Graph(h, nbins, n)
+
+    def count_3pcf(self, g: "Graph", anchors=None, weighted=False):
+        nc = n_configs(g.nbins)
+        hist = np.zeros(nc, dtype=np.uint64)
+        ntri = np.zeros(1, dtype=np.uint64)
+        wsum = np.zeros((nc, 2), dtype=np.uint64) if weighted else None
+        whist = np.zeros(nc, dtype=np.float64) if weighted else None
+        ws = np.zeros(1, dtype=np.int32) if weighted else None
+        ar = None if anchors is None else ctypes.byref(AnchorRange(int(anchors[0]), int(anchors[1])))
+        _check(load().gs_count_3pcf(self._h, g.handle, _ptr(hist), _ptr(wsum), _ptr(whist), _ptr(ws),
+                                    _ptr(ntri), ar), "gs_count_3pcf")
+        return Count3(hist, int(ntri[0]), wsum, whist, int(ws[0]) if weighted else None)
+
+    def count_4pcf_parity(self, g: "Graph", anchors=None):
+        nc = n_configs(g.nbins)
+        e, p, m = (np.zeros(nc, dtype=np.uint64) for _ in range(3))
+        nk = np.zeros(1, dtype=np.uint64)
+        ar = None if anchors is None else ctypes.byref(AnchorRange(int(anchors[0]), int(anchors[1])))
+        _check(load().gs_count_4pcf_parity(self._h, g.handle, _ptr(e), _ptr(p), _ptr(m), _ptr(nk), ar),
+               "gs_count_4pcf_parity")
+        return Count4(e, p, m, int(nk[0]))
+
+    def timings(self) -> Timings:
+        t = Timings()
+        _check(load().gs_get_timings(self._h, ctypes.byref(t)), "gs_get_timings")
+        return t
+
+
+@dataclass
+class Count3:
+    hist: np.ndarray
+    n_triangles: int
+    wsum: np.ndarray | None
+    whist: np.ndarray | None
+    wscale: int | None
+
+    def wsum_int(self):
+        return [int(lo) + (int(hi) << 64) for lo, hi in self.wsum]
+
+
+@dataclass
+class Count4:
+    even: np.ndarray
+    pos: np.ndarray
+    neg: np.ndarray
+    n_cliques: int
+
+    @property
+    def odd(self):
+        return self.pos.astype(np.int64) - self.neg.astype(np.int64)
+
+
+class Graph:
+    """gs_graph handle (device CSR, labels, optional coords/weights)."""
+
+    def __init__(self, handle, nbins, n):
+        self._h = handle
+        self.nbins = nbins
+        self.n = n
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> GraphStats:
+        s = GraphStats()
+        _check(load().gs_graph_info(self._h, ctypes.byref(s)), "gs_graph_info")
+        return s
+
+    def export(self):
+        s = self.info()
+        rp = np.zeros(s.n + 1, dtype=np.uint64)
+        col = np.zeros(max(s.n_edges, 1), dtype=np.uint32)
+        b = np.zeros(max(s.n_edges, 1), dtype=np.uint8)
+        perm = np.zeros(max(s.n, 1), dtype=np.uint32)
+        _check(load().gs_graph_export(self._h, _ptr(rp), _ptr(col), _ptr(b), _ptr(perm)), "gs_graph_export")
+        return rp, col[:s.n_edges], b[:s.n_edges], perm[:s.n]
+
+    def free(self):
+        if self._h:
+            load().gs_graph_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

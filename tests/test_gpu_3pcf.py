@@ -1,0 +1,257 @@
+"""GPU graph builder and triangle counts against the CPU oracle (bit-exact).
+
+All calls go through the C ABI (ctypes binding). Sizes span several hub
+tiles and ragged tails; the full-size Neyman-Scott workload is compared with
+stored oracle values (tests/golden/ns_3pcf_full.json).
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gsn():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2607_06604_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(gsn):
+    c = gsn.Context(0)
+    yield c
+    c.close()
+
+
+def undirected_edges_gpu(rp, col, b, perm):
+    n = len(rp) - 1
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp.astype(np.int64)))
+    a = perm[rows].astype(np.int64)
+    c = perm[col].astype(np.int64)
+    lo, hi = np.minimum(a, c), np.maximum(a, c)
+    key = lo * (1 << 32) + hi
+    o = np.argsort(key, kind="stable")
+    return key[o], b[o]
+
+
+def undirected_edges_oracle(rp, col, b):
+    n = len(rp) - 1
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    m = col.astype(np.int64) > rows
+    key = rows[m] * (1 << 32) + col[m].astype(np.int64)
+    o = np.argsort(key, kind="stable")
+    return key[o], b[m][o]
+
+
+CASES = [
+    ("uniform_tiny", lambda: synth.uniform(300, 10.0, 21), 10.0, 0.0, 2.4, 5, None),
+    ("uniform_rmin", lambda: synth.uniform(3000, 30.0, 22), 30.0, 0.7, 2.6, 4, None),
+    ("clustered", lambda: synth.neyman_scott(4000, 25, 0.8, 25.0, 23), 25.0, 0.0, 2.0, 6, None),
+    ("single_cell", lambda: synth.uniform(500, 9.0, 24), 9.0, 0.0, 3.9, 3, None),
+    ("two_cells_per_axis", lambda: synth.uniform(700, 10.0, 26), 10.0, 0.0, 4.2, 7, None),
+    ("many_bins", lambda: synth.uniform(2000, 16.0, 25), 16.0, 0.0, 2.2, 21, None),
+    ("dyadic_ties", lambda: synth.dyadic_uniform(3000, 16.0, 27, bits=6), 16.0, 0.0, 1.5, 6, None),
+    ("uniform_c1", None, None, None, None, None, ("uniform_3pcf", 1.0)),
+    ("ns_c2_eighth", None, None, None, None, None, ("ns_3pcf", 0.125)),
+    ("ns_c3_full", None, None, None, None, None, ("ns_4pcf_parity", 1.0)),
+]
+
+
+def _case(c):
+    name, mk, L, rmin, rmax, nb, wl = c
+    if wl is not None:
+        w = synth.workload(*wl)
+        return w.xyz, w.box, w.rmin, w.rmax, w.nbins
+    return mk(), L, rmin, rmax, nb
+
+
+@pytest.mark.parametrize("case", CASES[:8], ids=[c[0] for c in CASES[:8]])
+def test_graph_edges_and_bins_match_oracle(ctx, case):
+    x, L, rmin, rmax, nb = _case(case)
+    say("graph", case[0], len(x))
+    g = ctx.build_graph(x, L, rmin, rmax, nb)
+    rp, col, b, perm = g.export()
+    info = g.info()
+    g.free()
+    assert sorted(perm.tolist()) == list(range(len(x)))
+    # rows strictly increasing, forward only
+    for i in range(len(x)):
+        r = col[rp[i]:rp[i + 1]].astype(np.int64)
+        assert np.all(r > i) and np.all(np.diff(r) > 0)
+    orp, ocol, ob = oracle.graph(x, L, rmin, rmax, nb)
+    kg, bg = undirected_edges_gpu(rp, col, b, perm)
+    ko, bo = undirected_edges_oracle(orp, ocol, ob)
+    assert np.array_equal(kg, ko)
+    assert np.array_equal(bg, bo)
+    assert info.n_edges == len(ko)
+    assert list(info.pair_hist[:nb]) == np.bincount(bo, minlength=nb).tolist()
+    assert info.max_deg == int(np.diff(rp.astype(np.int64)).max(initial=0))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_count3_matches_oracle(ctx, case):
+    x, L, rmin, rmax, nb = _case(case)
+    say("count3", case[0], len(x))
+    g = ctx.build_graph(x, L, rmin, rmax, nb)
+    got = ctx.count_3pcf(g)
+    g.free()
+    ref = oracle.count_3pcf(x, L, rmin, rmax, nb)
+    assert got.n_triangles == ref.n_triangles
+    assert np.array_equal(got.hist, ref.hist)
+    assert int(got.hist.sum()) == got.n_triangles
+
+
+def test_count3_full_size_ns_against_stored_oracle(ctx):
+    with open(os.path.join(HERE, "golden", "ns_3pcf_full.json")) as f:
+        gold = json.load(f)
+    w = synth.workload("ns_3pcf")
+    assert hashlib.sha256(np.ascontiguousarray(w.xyz).tobytes()).hexdigest() == gold["xyz_sha256"]
+    say("count3 full ns", w.n)
+    g = ctx.build_graph(w.xyz, w.box, w.rmin, w.rmax, w.nbins)
+    got = ctx.count_3pcf(g)
+    again = ctx.count_3pcf(g)
+    g.free()
+    assert got.n_triangles == gold["n_triangles"]
+    assert got.hist.tolist() == gold["hist"]
+    assert np.array_equal(again.hist, got.hist)
+
+
+def test_count3_device_input_matches_host_input(ctx):
+    import torch
+    w = synth.workload("ns_3pcf", volume_fraction=0.125)
+    say("count3 device input", w.n)
+    gh = ctx.build_graph(w.xyz, w.box, w.rmin, w.rmax, w.nbins)
+    a = ctx.count_3pcf(gh)
+    gh.free()
+    xd = torch.from_numpy(w.xyz).to("cuda:0")
+    gd = ctx.build_graph(xd, w.box, w.rmin, w.rmax, w.nbins)
+    b = ctx.count_3pcf(gd)
+    gd.free()
+    assert a.n_triangles == b.n_triangles and np.array_equal(a.hist, b.hist)
+
+
+def test_count3_anchor_ranges_partition_and_match_oracle(ctx):
+    w = synth.workload("uniform_3pcf")
+    say("count3 anchors", w.n)
+    g = ctx.build_graph(w.xyz, w.box, w.rmin, w.rmax, w.nbins)
+    full = ctx.count_3pcf(g)
+    cuts = [0, 1, 4999, 5000, 13333, 20000]
+    acc = np.zeros_like(full.hist)
+    tot = 0
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        part = ctx.count_3pcf(g, anchors=(lo, hi))
+        ref = oracle.count_3pcf(w.xyz, w.box, w.rmin, w.rmax, w.nbins, anchors=(lo, hi))
+        assert part.n_triangles == ref.n_triangles and np.array_equal(part.hist, ref.hist)
+        acc += part.hist
+        tot += part.n_triangles
+    empty = ctx.count_3pcf(g, anchors=(7, 7))
+    g.free()
+    assert np.array_equal(acc, full.hist) and tot == full.n_triangles
+    assert empty.n_triangles == 0 and empty.hist.sum() == 0
+
+
+WEIGHTED = [
+    # lognormal-like field, weights 0.5 + U[0,1): (n, L, rmax, nbins, mesh)
+    (30_000, 1000.0, 60.0, 20, 32),
+    (60_000, 800.0, 45.0, 12, 32),
+]
+
+
+@pytest.mark.parametrize("case", WEIGHTED, ids=["ln30k", "ln60k"])
+def test_weighted_count3_exact_sums(ctx, case):
+    n, L, rmax, nb, mesh = case
+    x = synth.lognormal(n, L, 81, mesh=mesh, sigma_s=L / 40)
+    wt = synth.uniform_values(n, 0.5, 1.0, 82)
+    say("weighted count3", n)
+    g = ctx.build_graph(x, L, 0.0, rmax, nb, weights=wt)
+    got = ctx.count_3pcf(g, weighted=True)
+    g.free()
+    ref = oracle.count_3pcf(x, L, 0.0, rmax, nb, weights=wt)
+    assert got.n_triangles == ref.n_triangles and np.array_equal(got.hist, ref.hist)
+    assert got.wscale == ref.wscale
+    assert got.wsum_int() == ref.wsum_int()
+    assert np.array_equal(got.whist, ref.whist())
+
+
+def test_weighted_unit_weights_equal_counts(ctx):
+    x = synth.uniform(5000, 30.0, 61)
+    g = ctx.build_graph(x, 30.0, 0.0, 3.0, 6, weights=np.ones(len(x)))
+    got = ctx.count_3pcf(g, weighted=True)
+    g.free()
+    assert got.wscale == 52
+    assert np.array_equal(got.whist, got.hist.astype(np.float64))
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3])
+def test_tiny_and_empty_catalogues(ctx, n):
+    x = synth.uniform(n, 10.0, 70 + n) if n else np.zeros((0, 3))
+    g = ctx.build_graph(x, 10.0, 0.0, 4.0, 3)
+    got = ctx.count_3pcf(g)
+    info = g.info()
+    g.free()
+    ref = oracle.count_3pcf(x, 10.0, 0.0, 4.0, 3)
+    assert got.n_triangles == ref.n_triangles and np.array_equal(got.hist, ref.hist)
+    assert info.n == n
+
+
+def test_no_edges(ctx):
+    x = synth.uniform(1000, 1000.0, 71)
+    g = ctx.build_graph(x, 1000.0, 0.0, 0.5, 4)
+    got = ctx.count_3pcf(g)
+    assert g.info().n_edges == 0
+    g.free()
+    assert got.n_triangles == 0 and got.hist.sum() == 0
+
+
+def test_maximum_bins_uses_global_histogram(ctx):
+    x = synth.uniform(3000, 20.0, 72)
+    g = ctx.build_graph(x, 20.0, 0.0, 2.5, 255)
+    got = ctx.count_3pcf(g)
+    g.free()
+    ref = oracle.count_3pcf(x, 20.0, 0.0, 2.5, 255)
+    assert got.n_triangles == ref.n_triangles and np.array_equal(got.hist, ref.hist)
+
+
+def test_invalid_inputs_rejected(ctx, gsn):
+    x = synth.uniform(100, 10.0, 73)
+    for args in [(10.0, 0.0, 5.0, 4), (10.0, 2.0, 2.0, 4), (10.0, 0.0, 2.0, 0), (10.0, 0.0, 2.0, 256)]:
+        with pytest.raises(gsn.GsError) as e:
+            ctx.build_graph(x, *args)
+        assert e.value.code == gsn.GS_EINVAL
+    y = x.copy()
+    y[5, 2] = 10.0
+    with pytest.raises(gsn.GsError) as e:
+        ctx.build_graph(y, 10.0, 0.0, 2.0, 4)
+    assert e.value.code == gsn.GS_EINVAL
+    y[5, 2] = np.nan
+    with pytest.raises(gsn.GsError) as e:
+        ctx.build_graph(y, 10.0, 0.0, 2.0, 4)
+    assert e.value.code == gsn.GS_EINVAL
+    with pytest.raises(gsn.GsError) as e:
+        ctx.build_graph(x, 10.0, 0.0, 2.0, 4, weights=-np.ones(100))
+    assert e.value.code == gsn.GS_EINVAL
+    g = ctx.build_graph(x, 10.0, 0.0, 2.0, 4)
+    with pytest.raises(gsn.GsError) as e:
+        ctx.count_3pcf(g, weighted=True)
+    assert e.value.code == gsn.GS_EINVAL
+    with pytest.raises(gsn.GsError) as e:
+        ctx.count_4pcf_parity(g)
+    assert e.value.code == gsn.GS_ENOCOORDS
+    g.free()
