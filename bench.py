@@ -1,0 +1,181 @@
+"""Benchmark of the hot path on one MI355X.
+
+One step = the whole path over one catalogue already resident in HBM:
+build the r < rmax graph (cell list, sorted forward CSR, bin bytes) and
+count binned triangles (3pCF) -- or, for the parity workload, binned
+4-cliques with parity. Prints ONE JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload ns_3pcf|ns_4pcf_parity]
+
+value = tuples counted per second of step time (build + count);
+roofline = the counting kernel's algorithmic bytes per launch over its
+average launch duration (HIP events recorded by the library on the stream
+it launches on), against the 8 TB/s HBM peak; cpu_baseline = the CPU
+oracle on a bounded sample of the same catalogue (anchor range), on the
+host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "binned triangles/s and 4-cliques/s on 1 GPU; batched catalogues/hour + p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+WORKLOADS = {
+    "ns_3pcf": dict(kind="3pcf", unit="triangles/s",
+                    desc="1,000,000 Neyman-Scott points (20,000 parents x 50, sigma 3 Mpc/h) in a periodic "
+                         "1000 Mpc/h box, rmax 30 Mpc/h, 15 bins, uint64 counts"),
+    "ns_4pcf_parity": dict(kind="4pcf", unit="4-cliques/s",
+                           desc="200,000 Neyman-Scott points (4,000 x 50, sigma 3) in a periodic 400 Mpc/h "
+                                "box, rmax 20 Mpc/h, 8 bins, even/odd uint64 counts"),
+}
+
+
+def kernel_source_digest(kind: str) -> str:
+    name = "count3.hip" if kind == "3pcf" else "count4.hip"
+    p = os.path.join(ROOT, "paper_2607_06604_amd", "csrc", name)
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(workload: str, kind: str):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source (else null)."""
+    p = os.path.join(PROFILES, "traffic_%s.json" % workload)
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha256_16") != kernel_source_digest(kind):
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ns_3pcf", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=float, default=0.0,
+                    help="fraction of anchor points for the oracle baseline (0 = default per workload)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one device copy of this size (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the counts would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2607_06604_amd as gsn
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    spec = WORKLOADS[args.workload]
+    w = synth.workload(args.workload)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    xd = torch.from_numpy(w.xyz).to(dev)
+    torch.cuda.synchronize()
+
+    if args.copy_probe_mib:
+        a = torch.empty(args.copy_probe_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        a.fill_(1.0)
+        b = a.clone()
+        torch.cuda.synchronize()
+        del a, b
+
+    ctx = gsn.Context(0, stream=stream)
+    keep = spec["kind"] == "4pcf"
+
+    def step():
+        g = ctx.build_graph(xd, w.box, w.rmin, w.rmax, w.nbins, keep_coords=keep)
+        t_build = ctx.timings().build_ms
+        if spec["kind"] == "3pcf":
+            r = ctx.count_3pcf(g)
+            tuples = r.n_triangles
+        else:
+            r = ctx.count_4pcf_parity(g)
+            tuples = r.n_cliques
+        t = ctx.timings()
+        g.free()
+        return tuples, t_build, t
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern_ms, launches, count_ms, build_ms, alg_bytes = 0.0, 0, 0.0, 0.0, 0
+    tuples = 0
+    for _ in range(args.steps):
+        tuples, tb, t = step()
+        kern_ms += t.kernel_ms
+        launches += t.kernel_launches
+        count_ms += t.count_ms
+        build_ms += tb
+        alg_bytes = t.alg_bytes
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = tuples / (ms_per_step / 1e3)
+
+    avg_launch_ms = kern_ms / max(launches, 1)
+    achieved = alg_bytes / (avg_launch_ms / 1e3) / 1e9 if avg_launch_ms > 0 else 0.0
+    traffic = stored_traffic(args.workload, spec["kind"])
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_count3" if spec["kind"] == "3pcf" else "k_count4",
+                "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_launch_ms, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        frac = args.cpu_sample or (0.25 if spec["kind"] == "3pcf" else 0.002)
+        hi = max(1, int(round(w.n * frac)))
+        tc = time.perf_counter()
+        if spec["kind"] == "3pcf":
+            rr = oracle.count_3pcf(w.xyz, w.box, w.rmin, w.rmax, w.nbins, anchors=(0, hi))
+            cnt = rr.n_triangles
+        else:
+            rr = oracle.count_4pcf_parity(w.xyz, w.box, w.rmin, w.rmax, w.nbins, anchors=(0, hi))
+            cnt = rr.n_cliques
+        dt = time.perf_counter() - tc
+        cpu = {"value": round(cnt / dt, 1), "unit": spec["unit"], "cores": rr.threads, "kind": "oracle",
+               "sample": "tuples whose smallest original index is in [0, %d) of %d points (graph rows "
+                         "built for all points), %.1f s" % (hi, w.n, dt)}
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": spec["unit"], "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+int",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": spec["desc"], "n_points": w.n,
+                   "box": w.box, "rmax": w.rmax, "nbins": w.nbins, "tuples_per_step": tuples},
+        "query_only": {"value": round(tuples / (count_ms / args.steps / 1e3), 1), "unit": spec["unit"],
+                       "count_ms": round(count_ms / args.steps, 4),
+                       "build_ms": round(build_ms / args.steps, 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
