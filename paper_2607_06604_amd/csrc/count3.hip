@@ -16,6 +16,7 @@
 // hardware's round-robin placement) so nearby hubs share that XCD's L2, and
 // moves on to the other queues once its own is empty.
 #include <cstdio>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -36,6 +37,7 @@ struct C3Args {
     uint32_t maxdeg;
     uint32_t anchor_lo, anchor_hi;
     double wmul;            // 2^wscale
+    uint64_t flush_limit;   // flush LDS counters before this many increments
     uint32_t *queue;        // kQueues counters
     unsigned long long *hist;   // nconf
     unsigned long long *wsum;   // 2*nconf (lo, hi)
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             mstart[tid] = st;
             mpref[tid] = pre;
             if (tid == 0) mpref[BLOCK] = total;
-            if (acc + total >= 0xFFFFFFFFull) {
+            if (acc + total >= a.flush_limit) {
                 __syncthreads();
                 flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm);
                 acc = 0;
@@ -356,6 +358,11 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.anchor_lo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
     a.anchor_hi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;
     a.wmul = std::ldexp(1.0, g.wscale);
+    // GS_FLUSH_LIMIT lowers the flush threshold (exercises the flush path)
+    const char *fl = getenv("GS_FLUSH_LIMIT");
+    a.flush_limit = fl ? strtoull(fl, nullptr, 10) : 0xFFFFFFFFull;
+    if (a.flush_limit < (uint64_t)block * (maxdeg + 1) || a.flush_limit > 0xFFFFFFFFull)
+        a.flush_limit = 0xFFFFFFFFull;
     a.hist = dv;
     a.wsum = dv + nconf;
     a.ntri = dv + 3 * (size_t)nconf;
@@ -389,9 +396,5 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     ctx.t.alg_bytes = (uint64_t)(2.5 * (double)g.sum_sq_deg);
 }
 
-void count4_run(Ctx &, const Graph &, uint64_t *, uint64_t *, uint64_t *, uint64_t *,
-                const gs_anchor_range *) {
-    fail(GS_EUNSUPPORTED, "4pCF parity counting is not built yet");
-}
 
 }  // namespace gsn
