@@ -34,6 +34,9 @@ WORKLOADS = {
     "ns_3pcf": dict(kind="3pcf", unit="triangles/s",
                     desc="1,000,000 Neyman-Scott points (20,000 parents x 50, sigma 3 Mpc/h) in a periodic "
                          "1000 Mpc/h box, rmax 30 Mpc/h, 15 bins, uint64 counts"),
+    "lognormal_w3pcf": dict(kind="w3pcf", unit="triangles/s",
+                            desc="2,000,000 lognormal-like points in a periodic 2000 Mpc/h box, rmax 150 "
+                                 "Mpc/h, 20 bins, float64 weights U(0.5,1.5), exact weighted sums"),
     "ns_4pcf_parity": dict(kind="4pcf", unit="4-cliques/s",
                            desc="200,000 Neyman-Scott points (4,000 x 50, sigma 3) in a periodic 400 Mpc/h "
                                 "box, rmax 20 Mpc/h, 8 bins, even/odd uint64 counts"),
@@ -41,7 +44,7 @@ WORKLOADS = {
 
 
 def kernel_source_digest(kind: str) -> str:
-    name = "count3.hip" if kind == "3pcf" else "count4.hip"
+    name = "count4.hip" if kind == "4pcf" else "count3.hip"
     p = os.path.join(ROOT, "paper_2607_06604_amd", "csrc", name)
     with open(p, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -69,6 +72,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=0.0,
                     help="fraction of anchor points for the oracle baseline (0 = default per workload)")
+    ap.add_argument("--windows", type=int, default=0,
+                    help="force a host-tiled graph with this many windows (out-of-core path)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -101,14 +106,20 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    if args.windows:
+        os.environ["GS_WINDOWS"] = str(args.windows)
     ctx = gsn.Context(0, stream=stream)
     keep = spec["kind"] == "4pcf"
+    wd = torch.from_numpy(w.weights).to(dev) if spec["kind"] == "w3pcf" else None
 
     def step():
-        g = ctx.build_graph(xd, w.box, w.rmin, w.rmax, w.nbins, keep_coords=keep)
+        g = ctx.build_graph(xd, w.box, w.rmin, w.rmax, w.nbins, keep_coords=keep, weights=wd)
         t_build = ctx.timings().build_ms
         if spec["kind"] == "3pcf":
             r = ctx.count_3pcf(g)
+            tuples = r.n_triangles
+        elif spec["kind"] == "w3pcf":
+            r = ctx.count_3pcf(g, weighted=True)
             tuples = r.n_triangles
         else:
             r = ctx.count_4pcf_parity(g)
@@ -117,14 +128,18 @@ def main():
         g.free()
         return tuples, t_build, t
 
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
+        tw = time.perf_counter()
         step()
+        print("warmup step %d: %.1f ms" % (k, (time.perf_counter() - tw) * 1e3), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     kern_ms, launches, count_ms, build_ms, alg_bytes = 0.0, 0, 0.0, 0.0, 0
     tuples = 0
-    for _ in range(args.steps):
+    for k in range(args.steps):
         tuples, tb, t = step()
+        if t.count_ms > 1000 or tb > 1000:
+            print("step %d: build %.1f ms, count %.1f ms" % (k, tb, t.count_ms), file=sys.stderr, flush=True)
         kern_ms += t.kernel_ms
         launches += t.kernel_launches
         count_ms += t.count_ms
@@ -140,25 +155,28 @@ def main():
     traffic = stored_traffic(args.workload, spec["kind"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_count3" if spec["kind"] == "3pcf" else "k_count4",
+                "kernel": "k_count4" if spec["kind"] == "4pcf" else "k_count3",
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_launch_ms, 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        frac = args.cpu_sample or (0.25 if spec["kind"] == "3pcf" else 0.002)
+        frac = args.cpu_sample or {"3pcf": 0.25, "4pcf": 0.002, "w3pcf": 0.00002}[spec["kind"]]
         hi = max(1, int(round(w.n * frac)))
         tc = time.perf_counter()
         if spec["kind"] == "3pcf":
             rr = oracle.count_3pcf(w.xyz, w.box, w.rmin, w.rmax, w.nbins, anchors=(0, hi))
+            cnt = rr.n_triangles
+        elif spec["kind"] == "w3pcf":
+            rr = oracle.count_3pcf(w.xyz, w.box, w.rmin, w.rmax, w.nbins, weights=w.weights, anchors=(0, hi))
             cnt = rr.n_triangles
         else:
             rr = oracle.count_4pcf_parity(w.xyz, w.box, w.rmin, w.rmax, w.nbins, anchors=(0, hi))
             cnt = rr.n_cliques
         dt = time.perf_counter() - tc
         cpu = {"value": round(cnt / dt, 1), "unit": spec["unit"], "cores": rr.threads, "kind": "oracle",
-               "sample": "tuples whose smallest original index is in [0, %d) of %d points (graph rows "
-                         "built for all points), %.1f s" % (hi, w.n, dt)}
+               "sample": "tuples whose smallest original index is in [0, %d) of %d points (rows "
+                         "built for those anchors and their neighbours), %.1f s" % (hi, w.n, dt)}
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": spec["unit"], "n_gpus": 1,
@@ -166,7 +184,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+int",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": spec["desc"], "n_points": w.n,
-                   "box": w.box, "rmax": w.rmax, "nbins": w.nbins, "tuples_per_step": tuples},
+                   "box": w.box, "rmax": w.rmax, "nbins": w.nbins, "tuples_per_step": tuples,
+                   "windows": args.windows or 1},
         "query_only": {"value": round(tuples / (count_ms / args.steps / 1e3), 1), "unit": spec["unit"],
                        "count_ms": round(count_ms / args.steps, 4),
                        "build_ms": round(build_ms / args.steps, 4)},

@@ -147,8 +147,10 @@ static int entry_cmp(const void *x, const void *y) {
 }
 
 /* Cell list with cells at least rmax*(1+1e-9) wide, so every pair closer than
- * rmax sits in the same or a periodically adjacent cell. */
-static int build_rows(const params_t *p, const double *xyz, int64_t n, int nthreads, rows_t *g) {
+ * rmax sits in the same or a periodically adjacent cell. If need is not NULL,
+ * only rows i with need[i] != 0 are filled; the others are left empty. */
+static int build_rows(const params_t *p, const double *xyz, int64_t n, int nthreads,
+                      const uint8_t *need, rows_t *g) {
     memset(g, 0, sizeof *g);
     g->n = n;
     int nc = (int)floor(p->L / (p->rmax * (1.0 + 1e-9)));
@@ -180,6 +182,10 @@ static int build_rows(const params_t *p, const double *xyz, int64_t n, int nthre
         int failed = 0;
 #pragma omp parallel for schedule(dynamic, 256) num_threads(nthreads)
         for (int64_t i = 0; i < n; ++i) {
+            if (need && !need[i]) {
+                if (pass == 0) g->ptr[i + 1] = 0;
+                continue;
+            }
             int64_t ci = cellof[i];
             int cx = (int)(ci / ((int64_t)nc * nc)), cy = (int)((ci / nc) % nc), cz = (int)(ci % nc);
             int64_t cells[27];
@@ -260,6 +266,26 @@ static int64_t find(const rows_t *g, int64_t i, int32_t j) {
     return (lo < g->ptr[i + 1] && g->col[lo] == j) ? lo : -1;
 }
 
+/* Rows for every point, or -- when only anchors [lo, hi) are counted -- for
+ * the anchors and all their neighbours (every vertex of a counted tuple is an
+ * anchor or a neighbour of one, and membership tests only read those rows). */
+static int rows_for_anchors(const params_t *p, const double *xyz, int64_t n, int nt, int64_t lo,
+                            int64_t hi, rows_t *g) {
+    if (lo <= 0 && hi >= n) return build_rows(p, xyz, n, nt, NULL, g);
+    uint8_t *need = (uint8_t *)calloc((size_t)(n ? n : 1), 1);
+    if (!need) return OR_ENOMEM;
+    for (int64_t i = lo; i < hi; ++i) need[i] = 1;
+    rows_t first;
+    int rc = build_rows(p, xyz, n, nt, need, &first);
+    if (rc != OR_OK) { free(need); return rc; }
+    for (int64_t i = lo; i < hi; ++i)
+        for (int64_t e = first.ptr[i]; e < first.ptr[i + 1]; ++e) need[first.col[e]] = 1;
+    rows_free(&first);
+    rc = build_rows(p, xyz, n, nt, need, g);
+    free(need);
+    return rc;
+}
+
 static int resolve_threads(int nthreads) {
     return nthreads > 0 ? nthreads : omp_get_max_threads();
 }
@@ -298,7 +324,7 @@ int oracle_graph(const double *xyz, int64_t n, double box, double rmin, double r
     if (rc != OR_OK) return rc;
     if (n >= ((int64_t)1 << 31)) return OR_EINVAL;
     rows_t g;
-    rc = build_rows(&p, xyz, n, resolve_threads(0), &g);
+    rc = build_rows(&p, xyz, n, resolve_threads(0), NULL, &g);
     if (rc != OR_OK) return rc;
     *n_entries = g.ptr[n];
     if (cap >= g.ptr[n]) {
@@ -349,7 +375,7 @@ int oracle_count_3pcf(const double *xyz, int64_t n, const double *w, double box,
     int nt = resolve_threads(nthreads);
     if (threads_used) *threads_used = nt;
     rows_t g;
-    rc = build_rows(&p, xyz, n, nt, &g);
+    rc = rows_for_anchors(&p, xyz, n, nt, anchor_lo, anchor_hi, &g);
     if (rc != OR_OK) return rc;
     int64_t nconf = binom3(nbins + 2);
     uint64_t *th = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));
@@ -457,7 +483,7 @@ int oracle_count_4pcf_parity(const double *xyz, int64_t n, double box, double rm
     int nt = resolve_threads(nthreads);
     if (threads_used) *threads_used = nt;
     rows_t g;
-    rc = build_rows(&p, xyz, n, nt, &g);
+    rc = rows_for_anchors(&p, xyz, n, nt, anchor_lo, anchor_hi, &g);
     if (rc != OR_OK) return rc;
     int64_t nconf = binom3(nbins + 2);
     uint64_t *tE = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));

@@ -7,8 +7,10 @@
 // after i, then the 13..26 periodically adjacent cells in ascending cell id,
 // which is ascending label order because labels follow cell ids. Each edge
 // carries the one-byte bin of its squared separation.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -107,6 +109,8 @@ struct EdgeArgs {
     const uint64_t *cstart;
     const double *thr;     // t_0 .. t_nb
     uint32_t n;
+    uint32_t l0, l1;    // labels handled by this launch
+    uint64_t obase;     // fill pass: rp[l] - obase indexes col / bin
     int nc, nb;
     double L, half;
     // count pass
@@ -130,8 +134,8 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
     if (FILL)
         for (int k = threadIdx.x; k < 256; k += blockDim.x) ph[k] = 0;
     __syncthreads();
-    uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l < a.n) {
+    uint32_t l = a.l0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < a.l1) {
         const int nc = a.nc;
         const uint32_t c = a.cellL[l];
         const double xi = a.X[l], yi = a.Y[l], zi = a.Z[l];
@@ -154,8 +158,8 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
             ax[0] = ay[0] = az[0] = 0;
         }
         uint32_t cnt = 0;
-        const uint64_t out = FILL ? a.rp[l] : 0;
-        const uint64_t cap = FILL ? a.rp[l + 1] - out : 0;  // the count pass's result
+        const uint64_t out = FILL ? a.rp[l] - a.obase : 0;
+        const uint64_t cap = FILL ? a.rp[l + 1] - a.rp[l] : 0;  // the count pass's result
         auto visit = [&](uint64_t j0, uint64_t j1) {
             for (uint64_t j = j0; j < j1; ++j) {
                 double dx = min_image(xi, a.X[j], a.L, a.half);
@@ -377,6 +381,9 @@ void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
     ea.cstart = cstart.as<uint64_t>();
     ea.thr = thr.as<double>();
     ea.n = n;
+    ea.l0 = 0;
+    ea.l1 = n;
+    ea.obase = 0;
     ea.nc = nc;
     ea.nb = g.nbins;
     ea.L = g.box;
@@ -414,18 +421,70 @@ void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
             fail(GS_EINVAL, "weight range too wide for exact 128-bit sums");
     }
 
-    g.col.alloc(sizeof(uint32_t) * (E ? E : 1));
-    g.bin.alloc(E ? E : 1);
+    // resident, or host-tiled windows when the CSR would not fit the budget
+    // (GS_WINDOWS forces a window count, as the paper's environment override)
+    const uint64_t fixed = g.row_ptr.bytes + g.perm.bytes + g.coords.bytes + g.weights.bytes;
+    const uint64_t csr = 5 * E;
+    int W = 1;
+    if (const char *ew = getenv("GS_WINDOWS")) W = std::max(1, atoi(ew));
+    if (W == 1 && fixed + csr > ctx.budget) {
+        if (ctx.budget <= fixed + (1u << 20)) fail(GS_EDEVMEM, "budget below the graph's per-point arrays");
+        const uint64_t per_win = (ctx.budget - fixed) / 4;  // 4 window buffers while counting
+        W = (int)std::min<uint64_t>((csr + per_win - 1) / per_win, 1u << 20);
+    }
+    if (W > 1 && (uint64_t)W > (uint64_t)n) W = (int)std::max<uint32_t>(1, n);
+
     DevBuf ph(sizeof(uint64_t) * 256), indeg(sizeof(uint32_t) * n), sq(8);
     k_fill_u64<<<1, 256, 0, s>>>(ph.as<uint64_t>(), 256, 0);
     k_fill_u32<<<grid_for(n), kBlock, 0, s>>>(indeg.as<uint32_t>(), n, 0);
     k_fill_u64<<<1, 1, 0, s>>>(sq.as<uint64_t>(), 1, 0);
     ea.rp = g.row_ptr.as<uint64_t>();
-    ea.col = g.col.as<uint32_t>();
-    ea.bin = g.bin.as<uint8_t>();
     ea.pair_hist = (unsigned long long *)ph.as<uint64_t>();
     ea.indeg = indeg.as<uint32_t>();
-    k_edges<true><<<grid_for(n), kBlock, 0, s>>>(ea);
+    if (W == 1) {
+        g.col.alloc(sizeof(uint32_t) * (E ? E : 1));
+        g.bin.alloc(E ? E : 1);
+        ea.col = g.col.as<uint32_t>();
+        ea.bin = g.bin.as<uint8_t>();
+        k_edges<true><<<grid_for(n), kBlock, 0, s>>>(ea);
+    } else {
+        // row-aligned windows of about E/W entries each
+        std::vector<uint64_t> hrp((size_t)n + 1);
+        GS_HIP(hipMemcpyAsync(hrp.data(), g.row_ptr.p, sizeof(uint64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+        GS_HIP(hipStreamSynchronize(s));
+        g.win.assign(1, 0);
+        for (int w = 1; w < W; ++w) {
+            const uint64_t target = E / W * w;
+            uint64_t l = (uint64_t)(std::lower_bound(hrp.begin(), hrp.end(), target) - hrp.begin());
+            l = std::min<uint64_t>(l, n);
+            if (l > g.win.back() && l < n) g.win.push_back(l);
+        }
+        g.win.push_back(n);
+        W = (int)g.win.size() - 1;
+        g.win_edge.resize(W + 1);
+        uint64_t maxE = 1;
+        for (int w = 0; w <= W; ++w) g.win_edge[w] = hrp[g.win[w]];
+        for (int w = 0; w < W; ++w) maxE = std::max<uint64_t>(maxE, g.win_edge[w + 1] - g.win_edge[w]);
+        g.hcol.alloc(sizeof(uint32_t) * (E ? E : 1));
+        g.hbin.alloc(E ? E : 1);
+        g.col.alloc(4);
+        g.bin.alloc(1);
+        DevBuf stc(sizeof(uint32_t) * maxE), stb(maxE);
+        ea.col = stc.as<uint32_t>();
+        ea.bin = stb.as<uint8_t>();
+        for (int w = 0; w < W; ++w) {
+            ea.l0 = (uint32_t)g.win[w];
+            ea.l1 = (uint32_t)g.win[w + 1];
+            ea.obase = g.win_edge[w];
+            const uint64_t ne = g.win_edge[w + 1] - g.win_edge[w];
+            k_edges<true><<<grid_for(ea.l1 - ea.l0), kBlock, 0, s>>>(ea);
+            GS_HIP(hipGetLastError());
+            GS_HIP(hipMemcpyAsync(g.hcol.as<uint32_t>() + g.win_edge[w], stc.p, ne * 4, hipMemcpyDeviceToHost, s));
+            GS_HIP(hipMemcpyAsync(g.hbin.as<uint8_t>() + g.win_edge[w], stb.p, ne, hipMemcpyDeviceToHost, s));
+            GS_HIP(hipStreamSynchronize(s));
+        }
+    }
+    g.n_windows = W;
     k_sum_sq_deg<<<grid_for(n), kBlock, 0, s>>>(g.row_ptr.as<uint64_t>(), indeg.as<uint32_t>(), n,
                                                 (unsigned long long *)sq.as<uint64_t>());
     GS_HIP(hipGetLastError());

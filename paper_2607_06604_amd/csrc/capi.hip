@@ -118,6 +118,7 @@ int gs_create(gs_ctx **out, int device, uint64_t hbm_budget_bytes, void *hip_str
             GS_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
             c->own_stream = true;
         }
+        GS_HIP(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
         for (auto &e : c->ev) GS_HIP(hipEventCreate(&e));
         size_t fr = 0, tot = 0;
         GS_HIP(hipMemGetInfo(&fr, &tot));
@@ -137,6 +138,10 @@ int gs_destroy(gs_ctx *ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    if (ctx->copy_stream) {
+        (void)hipStreamSynchronize(ctx->copy_stream);
+        (void)hipStreamDestroy(ctx->copy_stream);
+    }
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
@@ -199,10 +204,15 @@ int gs_graph_export(const gs_graph *g, uint64_t *row_ptr, uint32_t *col, uint8_t
         GS_HIP(hipSetDevice(g->device));
         if (row_ptr)
             GS_HIP(hipMemcpy(row_ptr, g->row_ptr.p, sizeof(uint64_t) * (g->n + 1), hipMemcpyDeviceToHost));
-        if (col && g->n_edges)
-            GS_HIP(hipMemcpy(col, g->col.p, sizeof(uint32_t) * g->n_edges, hipMemcpyDeviceToHost));
-        if (bin && g->n_edges)
-            GS_HIP(hipMemcpy(bin, g->bin.p, g->n_edges, hipMemcpyDeviceToHost));
+        if (g->n_windows > 1) {
+            if (col && g->n_edges) memcpy(col, g->hcol.p, sizeof(uint32_t) * g->n_edges);
+            if (bin && g->n_edges) memcpy(bin, g->hbin.p, g->n_edges);
+        } else {
+            if (col && g->n_edges)
+                GS_HIP(hipMemcpy(col, g->col.p, sizeof(uint32_t) * g->n_edges, hipMemcpyDeviceToHost));
+            if (bin && g->n_edges)
+                GS_HIP(hipMemcpy(bin, g->bin.p, g->n_edges, hipMemcpyDeviceToHost));
+        }
         if (perm && g->n)
             GS_HIP(hipMemcpy(perm, g->perm.p, sizeof(uint32_t) * g->n, hipMemcpyDeviceToHost));
     });
@@ -250,6 +260,7 @@ int gs_count_4pcf_parity(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_
     return guarded([&] {
         if (!ctx || !g || !even || !pos || !neg || !n_cliques) fail(GS_EINVAL, "null argument");
         if (!(g->flags & GS_KEEP_COORDS)) fail(GS_ENOCOORDS, "parity needs GS_KEEP_COORDS");
+        if (g->n_windows > 1) fail(GS_EUNSUPPORTED, "parity counts need a device-resident graph");
         if (g->device != ctx->device) fail(GS_EINVAL, "graph and context on different devices");
         ctx->use();
         count4_run(*ctx, *g, even, pos, neg, n_cliques, anchors);

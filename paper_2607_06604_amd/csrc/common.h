@@ -102,6 +102,7 @@ struct Timings {
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t copy_stream = nullptr;  // host<->device window copies (own)
     bool own_stream = false;
     uint64_t budget = 0;        // device bytes the context may hold in graphs + scratch
     int n_cu = 0;
@@ -136,6 +137,12 @@ struct Graph {
     uint64_t sum_sq_deg = 0;  // sum over points of (full degree)^2
     uint64_t device_bytes = 0;
     int n_windows = 1;
+    // host-tiled graphs (n_windows > 1): the forward CSR lives in pinned host
+    // memory, split into row-aligned windows [win[w], win[w+1]) of labels
+    // whose entries start at win_edge[w]
+    std::vector<uint64_t> win, win_edge;
+    HostBuf hcol;     // u32[E]
+    HostBuf hbin;     // u8[E]
     // device, label order
     DevBuf row_ptr;   // u64[n+1]
     DevBuf col;       // u32[E]

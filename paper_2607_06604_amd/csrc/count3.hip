@@ -1,44 +1,51 @@
 // count3.hip - binned triangle counts on the forward CSR (paper Sec. 2.2
 // hub-and-spoke enumeration, Sec. 3.1 sorted-list intersection, Sec. 3.5.2
-// one work group per hub with lanes on the inner loop).
+// one work group per hub with lanes on the inner loop, Sec. 3.5.3 tiles).
 //
 // Every triangle {i < j < k} (labels) is found exactly once: at hub i, spoke
 // j in N+(i), third vertex k in N+(i) and N+(j). The work group of a hub
 // stages N+(i) in an LDS hash table (label -> bin of edge (i,k)), then
-// streams the forward rows of all its spokes as one flat, coalesced sequence;
+// streams the forward rows of its spokes as one flat, coalesced sequence;
 // each lane probes one candidate k. A hit has its three bins (ij from the
 // spoke, ik from the table, jk from the row), which are sorted and ranked
 // into an LDS histogram of 32-bit counters, flushed into the 64-bit result
-// before any counter could wrap.
+// before any counter could wrap. Weighted counts add the exact integer
+// t * 2^s of each triangle into 64-bit LDS halves, merged into 128-bit sums.
 //
-// Hubs are pulled from eight queues, one per XCD-sized slice of the label
-// range; a work group starts on the queue of its own XCD (blockIdx % 8, the
-// hardware's round-robin placement) so nearby hubs share that XCD's L2, and
-// moves on to the other queues once its own is empty.
+// A launch covers one tile: hubs in [h0, h1) and spokes in [s0, s1). A
+// resident graph is a single tile; a host-tiled graph runs every (hub
+// window, spoke window >= hub window) pair, so each spoke (i, j) -- and with
+// it every triangle -- belongs to exactly one tile.
+//
+// Hubs are pulled from eight queues, one per slice of the tile's hub range;
+// a work group starts on the queue of its own XCD so nearby hubs share that
+// XCD's L2, and moves on to the other queues once its own is empty.
 #include <cstdio>
 #include <cstdlib>
 
-#include "common.h"
+#include "kern_util.h"
 
 namespace gsn {
 namespace {
 
-constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-constexpr int kQueues = 8;
-
 struct C3Args {
     const uint64_t *rp;
-    const uint32_t *col;
-    const uint8_t *bin;
+    const uint32_t *hcol;   // hub rows (entry e of row i at rp[i] - hbase + e)
+    const uint8_t *hbin;
+    const uint32_t *scol;   // spoke rows (row j at rp[j] - sbase)
+    const uint8_t *sbin;
+    uint64_t hbase, sbase;
+    uint32_t h0, h1, s0, s1;
     const double *w;        // label-ordered weights (weighted)
     const uint32_t *perm;   // label -> original index (anchored)
-    uint32_t n;
+    const uint8_t *mark;    // anchored: hubs that can own an anchored triangle (nullable)
     int nb, nconf, log2h;
+    int trunc;              // cut spoke rows at the hub row's largest label
     uint32_t maxdeg;
     uint32_t anchor_lo, anchor_hi;
     double wmul;            // 2^wscale
     uint64_t flush_limit;   // flush LDS counters before this many increments
-    uint32_t *queue;        // kQueues counters
+    uint32_t *queue;        // kNumQueues counters
     unsigned long long *hist;   // nconf
     unsigned long long *wsum;   // 2*nconf (lo, hi)
     unsigned long long *ntri;   // 1
@@ -49,56 +56,27 @@ struct Layout3 {
     uint32_t hkey, hbin, hslot, mstart, mpref, mbin, mw, mperm, hist, wlo, whi, tab, wtot, misc, total;
 };
 
-__host__ __device__ inline uint32_t align_up(uint32_t x, uint32_t a) { return (x + a - 1) / a * a; }
-
 __host__ __device__ inline Layout3 layout3(int block, uint32_t H, uint32_t maxdeg, int nconf, int nb,
                                            bool weighted, bool anchored, bool lds_hist) {
     if (!lds_hist) nconf = 0;
     Layout3 L{};
     uint32_t o = 0;
-    L.hkey = o;   o = align_up(o + 4 * H, 16);
-    L.hbin = o;   o = align_up(o + H, 16);
-    L.hslot = o;  o = align_up(o + 2 * (maxdeg + 1), 16);
-    L.mstart = o; o = align_up(o + 8 * block, 16);
-    L.mpref = o;  o = align_up(o + 4 * (block + 1), 16);
-    L.mbin = o;   o = align_up(o + block, 16);
-    L.mw = o;     if (weighted) o = align_up(o + 8 * block, 16);
-    L.mperm = o;  if (anchored) o = align_up(o + 4 * block, 16);
-    L.hist = o;   o = align_up(o + 4 * nconf, 16);
-    L.wlo = o;    if (weighted) o = align_up(o + 8 * nconf, 16);
-    L.whi = o;    if (weighted) o = align_up(o + 8 * nconf, 16);
-    L.tab = o;    o = align_up(o + 8 * (nb + 1), 16);
-    L.wtot = o;   o = align_up(o + 4 * (block / 64 + 1), 16);
-    L.misc = o;   o = align_up(o + 16, 16);
+    L.mstart = o; o = lds_align(o + 8 * block, 16);
+    L.mw = o;     if (weighted) o = lds_align(o + 8 * block, 16);
+    L.wlo = o;    if (weighted) o = lds_align(o + 8 * nconf, 16);
+    L.whi = o;    if (weighted) o = lds_align(o + 8 * nconf, 16);
+    L.hkey = o;   o = lds_align(o + 4 * H, 16);
+    L.mpref = o;  o = lds_align(o + 4 * (block + 1), 16);
+    L.mperm = o;  if (anchored) o = lds_align(o + 4 * block, 16);
+    L.hist = o;   o = lds_align(o + 4 * nconf, 16);
+    L.tab = o;    o = lds_align(o + 8 * (nb + 1), 16);
+    L.wtot = o;   o = lds_align(o + 4 * (block / 64 + 1), 16);
+    L.misc = o;   o = lds_align(o + 16, 16);
+    L.hslot = o;  o = lds_align(o + 2 * (maxdeg + 1), 16);
+    L.hbin = o;   o = lds_align(o + H, 16);
+    L.mbin = o;   o = lds_align(o + block, 16);
     L.total = o;
     return L;
-}
-
-__device__ __forceinline__ uint32_t hash_slot(uint32_t k, int log2h) {
-    return (k * 2654435769u) >> (32 - log2h);
-}
-
-// Exclusive block scan of u32 values (block a multiple of 64).
-template <int BLOCK>
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wtot, uint32_t &total) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) wtot[wid] = x;
-    __syncthreads();
-    uint32_t off = 0, tot = 0;
-#pragma unroll
-    for (int k = 0; k < BLOCK / 64; ++k) {
-        uint32_t t = wtot[k];
-        off += (k < wid) ? t : 0u;
-        tot += t;
-    }
-    total = tot;
-    return off + x - v;
 }
 
 // 128-bit add into a (lo, hi) pair of global words.
@@ -133,6 +111,19 @@ __device__ void flush3(const C3Args &a, const Layout3 &L, unsigned char *sm) {
     }
 }
 
+__device__ __forceinline__ uint32_t next_hub_in(uint32_t *queue, uint32_t h0, uint32_t h1, int *qv) {
+    const int q0 = blockIdx.x % kNumQueues;
+    const uint64_t n = (uint64_t)(h1 - h0);
+    while (*qv < kNumQueues) {
+        const int q = (q0 + *qv) % kNumQueues;
+        const uint64_t lo = h0 + n * q / kNumQueues, hi = h0 + n * (q + 1) / kNumQueues;
+        const uint32_t v = atomicAdd(&queue[q], 1u);
+        if (lo + v < hi) return (uint32_t)(lo + v);
+        ++*qv;
+    }
+    return kEmptyKey;
+}
+
 template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
 __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     extern __shared__ __align__(16) unsigned char sm[];
@@ -156,7 +147,7 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     unsigned long long *s_cnt = (unsigned long long *)(sm + L.misc + 8);
     const int tid = threadIdx.x;
 
-    for (uint32_t s = tid; s < H; s += BLOCK) hkey[s] = kEmpty;
+    for (uint32_t s = tid; s < H; s += BLOCK) hkey[s] = kEmptyKey;
     if (LDS_HIST)
         for (int b = tid; b < a.nconf; b += BLOCK) {
             hist[b] = 0;
@@ -171,27 +162,17 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
 
     unsigned long long mytri = 0;
     uint64_t acc = 0;   // upper bound on increments since the last flush (uniform)
-    const int q0 = blockIdx.x % kQueues;
-    int qv = 0;         // queues exhausted so far (thread 0)
+    int qv = 0;         // queues found empty (thread 0)
 
     while (true) {
-        if (tid == 0) {
-            uint32_t hub = kEmpty;
-            while (qv < kQueues) {
-                const int q = (q0 + qv) % kQueues;
-                const uint64_t lo = (uint64_t)a.n * q / kQueues, hi = (uint64_t)a.n * (q + 1) / kQueues;
-                const uint32_t v = atomicAdd(&a.queue[q], 1u);
-                if (lo + v < hi) { hub = (uint32_t)(lo + v); break; }
-                ++qv;
-            }
-            *s_hub = hub;
-        }
+        if (tid == 0) *s_hub = next_hub_in(a.queue, a.h0, a.h1, &qv);
         __syncthreads();
         const uint32_t i = *s_hub;
-        if (i == kEmpty) break;
-        const uint64_t beg = a.rp[i];
-        const uint32_t d = (uint32_t)(a.rp[i + 1] - beg);
-        if (d < 2) { __syncthreads(); continue; }
+        if (i == kEmptyKey) break;
+        const uint64_t beg = a.rp[i] - a.hbase;
+        const uint32_t d = (uint32_t)(a.rp[i + 1] - a.rp[i]);
+        if (d < 2 || (ANCHORED && a.mark && !a.mark[i])) { __syncthreads(); continue; }
+        const uint32_t kmax = a.hcol[beg + d - 1];  // largest label of N+(i)
         double wi = 0.0;
         uint32_t pi = 0;
         if (WEIGHTED) wi = a.w[i];
@@ -199,34 +180,46 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
 
         // stage N+(i): label -> bin of (i, k)
         for (uint32_t e = tid; e < d; e += BLOCK) {
-            const uint32_t k = a.col[beg + e];
-            uint32_t s = hash_slot(k, a.log2h);
-            while (atomicCAS(&hkey[s], kEmpty, k) != kEmpty) s = (s + 1) & mask;
-            hbin[s] = a.bin[beg + e];
+            const uint32_t k = a.hcol[beg + e];
+            uint32_t s = label_hash(k, a.log2h);
+            while (atomicCAS(&hkey[s], kEmptyKey, k) != kEmptyKey) s = (s + 1) & mask;
+            hbin[s] = a.hbin[beg + e];
             hslot[e] = (uint16_t)s;
         }
         __syncthreads();
 
-        // spokes in chunks of BLOCK; the last spoke cannot close a triangle
+        // spokes in chunks of BLOCK; the last spoke cannot close a triangle;
+        // spokes outside this tile's spoke range contribute nothing here
         for (uint32_t c0 = 0; c0 + 1 < d; c0 += BLOCK) {
             const uint32_t sidx = c0 + tid;
             uint32_t len = 0;
             uint64_t st = 0;
             if (sidx + 1 < d) {
-                const uint32_t j = a.col[beg + sidx];
-                st = a.rp[j];
-                len = (uint32_t)(a.rp[j + 1] - st);
-                mbin[tid] = a.bin[beg + sidx];
-                if (WEIGHTED) mw[tid] = a.w[j];
-                if (ANCHORED) mperm[tid] = a.perm[j];
+                const uint32_t j = a.hcol[beg + sidx];
+                if (j >= a.s0 && j < a.s1) {
+                    st = a.rp[j] - a.sbase;
+                    len = (uint32_t)(a.rp[j + 1] - a.rp[j]);
+                    // entries of N+(j) above the largest label of N+(i) cannot match
+                    if (a.trunc && len > 16 && a.scol[st + len - 1] > kmax) {
+                        uint32_t lo = 0, hi = len;  // first entry > kmax
+                        while (lo < hi) {
+                            const uint32_t mid = (lo + hi) >> 1;
+                            if (a.scol[st + mid] <= kmax) lo = mid + 1;
+                            else hi = mid;
+                        }
+                        len = lo;
+                    }
+                    mbin[tid] = a.hbin[beg + sidx];
+                    if (WEIGHTED) mw[tid] = a.w[j];
+                    if (ANCHORED) mperm[tid] = a.perm[j];
+                }
             }
             uint32_t total;
-            const uint32_t pre = block_excl_scan<BLOCK>(len, wtot, total);
+            const uint32_t pre = wg_excl_scan<BLOCK>(len, wtot, total);
             mstart[tid] = st;
             mpref[tid] = pre;
             if (tid == 0) mpref[BLOCK] = total;
             if (acc + total >= a.flush_limit) {
-                __syncthreads();
                 flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm);
                 acc = 0;
             }
@@ -239,10 +232,10 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
                 if (e < total) {
                     while (mpref[sp + 1] <= e) ++sp;
                     const uint64_t pos = mstart[sp] + (e - mpref[sp]);
-                    const uint32_t k = a.col[pos];
-                    uint32_t h = hash_slot(k, a.log2h);
+                    const uint32_t k = a.scol[pos];
+                    uint32_t h = label_hash(k, a.log2h);
                     uint32_t key;
-                    while ((key = hkey[h]) != k && key != kEmpty) h = (h + 1) & mask;
+                    while ((key = hkey[h]) != k && key != kEmptyKey) h = (h + 1) & mask;
                     if (key == k) {
                         bool take = true;
                         if (ANCHORED) {
@@ -250,7 +243,7 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
                             take = m >= a.anchor_lo && m < a.anchor_hi;
                         }
                         if (take) {
-                            const int x = mbin[sp], y = hbin[h], z = a.bin[pos];
+                            const int x = mbin[sp], y = hbin[h], z = a.sbin[pos];
                             const int lo = min(x, min(y, z)), hi = max(x, max(y, z));
                             const int mid = x + y + z - lo - hi;
                             const int idx = ta[lo] + tb[mid] + hi;
@@ -278,7 +271,7 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             }
             __syncthreads();
         }
-        for (uint32_t e = tid; e < d; e += BLOCK) hkey[hslot[e]] = kEmpty;
+        for (uint32_t e = tid; e < d; e += BLOCK) hkey[hslot[e]] = kEmptyKey;
         __syncthreads();
     }
 
@@ -295,26 +288,94 @@ __global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
         p[i] = 0;
 }
 
-template <int BLOCK, bool W, bool A, bool LH>
-void launch3(Ctx &ctx, const C3Args &a, uint32_t lds) {
-    const void *kern = reinterpret_cast<const void *>(&k_count3<BLOCK, W, A, LH>);
+template <int B, bool W, bool A, bool LH>
+void launch3(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds) {
+    const void *kern = reinterpret_cast<const void *>(&k_count3<B, W, A, LH>);
     if (lds > 65536)
         GS_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
-    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count3<BLOCK, W, A, LH>, BLOCK, lds));
+    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count3<B, W, A, LH>, B, lds));
     if (per_cu < 1) fail(GS_EUNSUPPORTED, "count kernel does not fit a compute unit");
     uint32_t grid = (uint32_t)ctx.n_cu * (uint32_t)per_cu;
-    grid = (grid + kQueues - 1) / kQueues * kQueues;
-    k_count3<BLOCK, W, A, LH><<<dim3(grid), dim3(BLOCK), lds, ctx.stream>>>(a);
+    grid = (grid + kNumQueues - 1) / kNumQueues * kNumQueues;
+    k_count3<B, W, A, LH><<<dim3(grid), dim3(B), lds, s>>>(a);
     GS_HIP(hipGetLastError());
 }
 
-template <int BLOCK, bool LH>
-void launch3_any(Ctx &ctx, const C3Args &a, uint32_t lds, bool w, bool an) {
-    if (!w && !an) launch3<BLOCK, false, false, LH>(ctx, a, lds);
-    else if (w && !an) launch3<BLOCK, true, false, LH>(ctx, a, lds);
-    else if (!w && an) launch3<BLOCK, false, true, LH>(ctx, a, lds);
-    else launch3<BLOCK, true, true, LH>(ctx, a, lds);
+template <int B>
+void launch3_b(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds, bool w, bool an, bool lh) {
+    if (lh) {
+        if (!w && !an) launch3<B, false, false, true>(ctx, s, a, lds);
+        else if (w && !an) launch3<B, true, false, true>(ctx, s, a, lds);
+        else if (!w && an) launch3<B, false, true, true>(ctx, s, a, lds);
+        else launch3<B, true, true, true>(ctx, s, a, lds);
+    } else {
+        if (!w && !an) launch3<B, false, false, false>(ctx, s, a, lds);
+        else if (w && !an) launch3<B, true, false, false>(ctx, s, a, lds);
+        else if (!w && an) launch3<B, false, true, false>(ctx, s, a, lds);
+        else launch3<B, true, true, false>(ctx, s, a, lds);
+    }
+}
+
+struct Plan3 {
+    int block = 256;
+    int trunc = 0;
+    int log2h = 6;
+    bool lds_hist = true;
+    uint32_t lds = 0;
+};
+
+void launch3_any(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P, bool w, bool an) {
+    if (P.block == 512) launch3_b<512>(ctx, s, a, P.lds, w, an, P.lds_hist);
+    else launch3_b<256>(ctx, s, a, P.lds, w, an, P.lds_hist);
+}
+
+// Work-group size and LDS plan: hash table at load factor <= 0.7, 512
+// threads per hub for long rows (more waves per CU when LDS limits groups).
+Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchored) {
+    Plan3 p;
+    const int nconf = (int)n_configs(nb);
+    if (maxdeg > 16384) fail(GS_EUNSUPPORTED, "forward degree above 16384");
+    if (const char *eb = getenv("GS_BLOCK3")) p.block = atoi(eb) == 512 ? 512 : 256;
+    else p.block = maxdeg >= 1024 ? 512 : 256;
+    // the per-spoke binary search pays off on long rows only
+    if (const char *et = getenv("GS_TRUNC")) p.trunc = atoi(et) != 0;
+    else p.trunc = maxdeg >= 1024;
+    uint32_t H = 64;
+    while ((uint64_t)H * 7 < (uint64_t)maxdeg * 10) { H <<= 1; ++p.log2h; }
+    // per-work-group LDS histograms while they fit; global atomics beyond
+    p.lds_hist = nconf <= 8192;
+    Layout3 L = layout3(p.block, H, maxdeg, nconf, nb, weighted, anchored, p.lds_hist);
+    if ((int)L.total > ctx.max_lds && p.lds_hist) {
+        p.lds_hist = false;
+        L = layout3(p.block, H, maxdeg, nconf, nb, weighted, anchored, false);
+    }
+    if ((int)L.total > ctx.max_lds) fail(GS_EUNSUPPORTED, "LDS footprint too large for this degree");
+    p.lds = L.total;
+    return p;
+}
+
+// Anchored counts: only hubs that are anchors or have an anchor in their
+// forward row can own a triangle whose smallest original index is an anchor.
+__global__ void k_mark_anchor_hubs(const uint64_t *__restrict__ rp, const uint32_t *__restrict__ col,
+                                   const uint32_t *__restrict__ perm, uint32_t n, uint32_t lo,
+                                   uint32_t hi, uint8_t *__restrict__ mark) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint8_t m = (perm[i] >= lo && perm[i] < hi) ? 1 : 0;
+    for (uint64_t e = rp[i]; e < rp[i + 1] && !m; ++e) {
+        const uint32_t p = perm[col[e]];
+        m = (p >= lo && p < hi) ? 1 : 0;
+    }
+    mark[i] = m;
+}
+
+uint64_t flush_limit_for(uint32_t maxdeg, uint64_t per_chunk_factor) {
+    // GS_FLUSH_LIMIT lowers the flush threshold (exercises the flush path)
+    const char *fl = getenv("GS_FLUSH_LIMIT");
+    uint64_t v = fl ? strtoull(fl, nullptr, 10) : 0xFFFFFFFFull;
+    if (v < per_chunk_factor * (maxdeg + 1) || v > 0xFFFFFFFFull) v = 0xFFFFFFFFull;
+    return v;
 }
 
 }  // namespace
@@ -324,57 +385,139 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     const int nb = g.nbins;
     const int nconf = (int)n_configs(nb);
     const bool weighted = wsum != nullptr;
-    bool anchored = anchors != nullptr;
+    const bool anchored = anchors != nullptr;
     if (anchored && (anchors->lo > anchors->hi)) fail(GS_EINVAL, "anchor range lo > hi");
     const uint32_t maxdeg = g.max_deg;
-    if (maxdeg > 16384) fail(GS_EUNSUPPORTED, "forward degree above 16384");
-    uint32_t H = 64;
-    int log2h = 6;
-    while (H < 2 * maxdeg) { H <<= 1; ++log2h; }
-    const int block = 256;
-    // per-work-group LDS histograms while they fit; global atomics beyond
-    bool lds_hist = nconf <= 8192;
-    Layout3 L = layout3(block, H, maxdeg, nconf, nb, weighted, anchored, lds_hist);
-    if ((int)L.total > ctx.max_lds && lds_hist) {
-        lds_hist = false;
-        L = layout3(block, H, maxdeg, nconf, nb, weighted, anchored, lds_hist);
-    }
-    if ((int)L.total > ctx.max_lds) fail(GS_EUNSUPPORTED, "LDS footprint too large for this degree");
+    const Plan3 P = plan3(ctx, maxdeg, nb, weighted, anchored);
+    const int W = g.n_windows;
+    const int ntiles = W * (W + 1) / 2;
 
-    // device staging: hist | wsum | ntri | queues
-    const size_t words = (size_t)nconf + 2 * (size_t)nconf + 1 + kQueues;
+    // device staging: hist | wsum | ntri | queues (8 per tile)
+    const size_t qwords = (size_t)ntiles * kNumQueues / 2 + 1;
+    const size_t words = 3 * (size_t)nconf + 1 + qwords;
     unsigned long long *dv = (unsigned long long *)ctx.scratch_get(words * 8);
     C3Args a{};
     a.rp = g.row_ptr.as<uint64_t>();
-    a.col = g.col.as<uint32_t>();
-    a.bin = g.bin.as<uint8_t>();
     a.w = weighted ? g.weights.as<double>() : nullptr;
     a.perm = g.perm.as<uint32_t>();
-    a.n = (uint32_t)g.n;
     a.nb = nb;
     a.nconf = nconf;
-    a.log2h = log2h;
+    a.log2h = P.log2h;
+    a.trunc = P.trunc;
     a.maxdeg = maxdeg;
     a.anchor_lo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
     a.anchor_hi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;
     a.wmul = std::ldexp(1.0, g.wscale);
-    // GS_FLUSH_LIMIT lowers the flush threshold (exercises the flush path)
-    const char *fl = getenv("GS_FLUSH_LIMIT");
-    a.flush_limit = fl ? strtoull(fl, nullptr, 10) : 0xFFFFFFFFull;
-    if (a.flush_limit < (uint64_t)block * (maxdeg + 1) || a.flush_limit > 0xFFFFFFFFull)
-        a.flush_limit = 0xFFFFFFFFull;
+    a.flush_limit = flush_limit_for(maxdeg, P.block);
     a.hist = dv;
     a.wsum = dv + nconf;
     a.ntri = dv + 3 * (size_t)nconf;
-    a.queue = (uint32_t *)(dv + 3 * (size_t)nconf + 1);
+    uint32_t *queues = (uint32_t *)(dv + 3 * (size_t)nconf + 1);
 
     hipStream_t s = ctx.stream;
     GS_HIP(hipEventRecord(ctx.ev[0], s));
     k_zero_u64<<<64, 256, 0, s>>>(dv, words);
     GS_HIP(hipEventRecord(ctx.ev[2], s));
-    if (g.n > 0) {
-        if (lds_hist) launch3_any<256, true>(ctx, a, L.total, weighted, anchored);
-        else launch3_any<256, false>(ctx, a, L.total, weighted, anchored);
+    DevBuf mark;
+    if (anchored && W == 1 && g.n > 0) {
+        mark.alloc((size_t)g.n);
+        k_mark_anchor_hubs<<<(unsigned)((g.n + 255) / 256), 256, 0, s>>>(
+            g.row_ptr.as<uint64_t>(), g.col.as<uint32_t>(), g.perm.as<uint32_t>(), (uint32_t)g.n,
+            a.anchor_lo, a.anchor_hi, mark.as<uint8_t>());
+        GS_HIP(hipGetLastError());
+        a.mark = mark.as<uint8_t>();
+    }
+    if (g.n > 0 && W == 1) {
+        a.hcol = a.scol = g.col.as<uint32_t>();
+        a.hbin = a.sbin = g.bin.as<uint8_t>();
+        a.hbase = a.sbase = 0;
+        a.h0 = a.s0 = 0;
+        a.h1 = a.s1 = (uint32_t)g.n;
+        a.queue = queues;
+        launch3_any(ctx, s, a, P, weighted, anchored);
+    } else if (g.n > 0) {
+        // host-tiled graph: spoke window S resident, hub windows H <= S
+        // streamed through; copies of the next tile's windows overlap the
+        // current tile's kernel on the copy stream
+        uint64_t maxE = 1;
+        for (int w = 0; w < W; ++w) maxE = std::max<uint64_t>(maxE, g.win_edge[w + 1] - g.win_edge[w]);
+        DevBuf scol[2], sbin[2], hcol[2], hbin[2];
+        for (int k = 0; k < 2; ++k) {
+            scol[k].alloc(maxE * 4);
+            sbin[k].alloc(maxE);
+            hcol[k].alloc(maxE * 4);
+            hbin[k].alloc(maxE);
+        }
+        struct Tile { int S, H, hslot; bool first_of_S, last_of_S; };
+        std::vector<Tile> tiles;
+        int hk = 0;
+        for (int S = 0; S < W; ++S)
+            for (int H = 0; H <= S; ++H)
+                tiles.push_back(Tile{S, H, H == S ? -1 : (hk++ % 2), H == 0, H == S});
+        hipEvent_t ev_sload[2], ev_sfree[2], ev_hload[2], ev_hfree[2];
+        for (int k = 0; k < 2; ++k) {
+            GS_HIP(hipEventCreateWithFlags(&ev_sload[k], hipEventDisableTiming));
+            GS_HIP(hipEventCreateWithFlags(&ev_sfree[k], hipEventDisableTiming));
+            GS_HIP(hipEventCreateWithFlags(&ev_hload[k], hipEventDisableTiming));
+            GS_HIP(hipEventCreateWithFlags(&ev_hfree[k], hipEventDisableTiming));
+        }
+        hipStream_t cs = ctx.copy_stream;
+        const uint32_t *hc = g.hcol.as<uint32_t>();
+        const uint8_t *hb = g.hbin.as<uint8_t>();
+        auto enqueue_load = [&](const Tile &t) {
+            if (t.first_of_S) {
+                const int k = t.S % 2;
+                const uint64_t e0 = g.win_edge[t.S], ne = g.win_edge[t.S + 1] - e0;
+                GS_HIP(hipStreamWaitEvent(cs, ev_sfree[k], 0));
+                GS_HIP(hipMemcpyAsync(scol[k].p, hc + e0, ne * 4, hipMemcpyHostToDevice, cs));
+                GS_HIP(hipMemcpyAsync(sbin[k].p, hb + e0, ne, hipMemcpyHostToDevice, cs));
+                GS_HIP(hipEventRecord(ev_sload[k], cs));
+            }
+            if (t.hslot >= 0) {
+                const int k = t.hslot;
+                const uint64_t e0 = g.win_edge[t.H], ne = g.win_edge[t.H + 1] - e0;
+                GS_HIP(hipStreamWaitEvent(cs, ev_hfree[k], 0));
+                GS_HIP(hipMemcpyAsync(hcol[k].p, hc + e0, ne * 4, hipMemcpyHostToDevice, cs));
+                GS_HIP(hipMemcpyAsync(hbin[k].p, hb + e0, ne, hipMemcpyHostToDevice, cs));
+                GS_HIP(hipEventRecord(ev_hload[k], cs));
+            }
+        };
+        enqueue_load(tiles[0]);
+        for (size_t ti = 0; ti < tiles.size(); ++ti) {
+            const Tile &t = tiles[ti];
+            if (ti + 1 < tiles.size()) enqueue_load(tiles[ti + 1]);
+            const int sk = t.S % 2;
+            GS_HIP(hipStreamWaitEvent(s, ev_sload[sk], 0));
+            C3Args b = a;
+            b.scol = scol[sk].as<uint32_t>();
+            b.sbin = sbin[sk].as<uint8_t>();
+            b.sbase = g.win_edge[t.S];
+            b.s0 = (uint32_t)g.win[t.S];
+            b.s1 = (uint32_t)g.win[t.S + 1];
+            if (t.hslot >= 0) {
+                GS_HIP(hipStreamWaitEvent(s, ev_hload[t.hslot], 0));
+                b.hcol = hcol[t.hslot].as<uint32_t>();
+                b.hbin = hbin[t.hslot].as<uint8_t>();
+            } else {
+                b.hcol = b.scol;
+                b.hbin = b.sbin;
+            }
+            b.hbase = g.win_edge[t.H];
+            b.h0 = (uint32_t)g.win[t.H];
+            b.h1 = (uint32_t)g.win[t.H + 1];
+            b.queue = queues + ti * kNumQueues;
+            launch3_any(ctx, s, b, P, weighted, anchored);
+            if (t.hslot >= 0) GS_HIP(hipEventRecord(ev_hfree[t.hslot], s));
+            if (t.last_of_S) GS_HIP(hipEventRecord(ev_sfree[sk], s));
+        }
+        GS_HIP(hipStreamSynchronize(s));
+        GS_HIP(hipStreamSynchronize(cs));
+        for (int k = 0; k < 2; ++k) {
+            (void)hipEventDestroy(ev_sload[k]);
+            (void)hipEventDestroy(ev_sfree[k]);
+            (void)hipEventDestroy(ev_hload[k]);
+            (void)hipEventDestroy(ev_hfree[k]);
+        }
     }
     GS_HIP(hipEventRecord(ctx.ev[3], s));
     std::vector<unsigned long long> h(3 * (size_t)nconf + 1);
@@ -390,11 +533,10 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     GS_HIP(hipEventElapsedTime(&kms, ctx.ev[2], ctx.ev[3]));
     ctx.t.count_ms = ms;
     ctx.t.kernel_ms = kms;
-    ctx.t.kernel_launches = g.n > 0 ? 1 : 0;
+    ctx.t.kernel_launches = g.n > 0 ? (uint64_t)ntiles : 0;
     // merge-walk bytes: each hub-spoke step reads both forward half-lists,
     // 5 bytes per entry: 2.5 B x sum_i m_i^2 over full degrees m_i
     ctx.t.alg_bytes = (uint64_t)(2.5 * (double)g.sum_sq_deg);
 }
-
 
 }  // namespace gsn

@@ -1,0 +1,148 @@
+"""Host-tiled (out-of-core) graphs: forced window counts and budget caps give
+histograms bit-identical to the resident graph and to the oracle; each spoke
+is owned by exactly one (hub window, spoke window) tile (paper Sec. 3.5.3).
+Includes the full-size 2e6-point weighted lognormal workload against stored
+oracle values for sampled anchor ranges."""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gsn():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2607_06604_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(gsn):
+    c = gsn.Context(0)
+    yield c
+    c.close()
+
+
+def _ln(n, L, seed):
+    x = synth.lognormal(n, L, seed, mesh=32, sigma_s=L / 40)
+    w = synth.uniform_values(n, 0.5, 1.0, seed + 1)
+    return x, w
+
+
+@pytest.mark.parametrize("windows", [2, 3, 5, 8])
+def test_forced_windows_match_resident_and_oracle(ctx, monkeypatch, windows):
+    x, w = _ln(60_000, 800.0, 91)
+    L, rmax, nb = 800.0, 45.0, 12
+    say("ooc windows", windows)
+    g = ctx.build_graph(x, L, 0.0, rmax, nb, weights=w)
+    res = ctx.count_3pcf(g, weighted=True)
+    rp0, col0, b0, perm0 = g.export()
+    g.free()
+    monkeypatch.setenv("GS_WINDOWS", str(windows))
+    gt = ctx.build_graph(x, L, 0.0, rmax, nb, weights=w)
+    info = gt.info()
+    assert info.n_windows == windows
+    rp1, col1, b1, perm1 = gt.export()
+    tiled = ctx.count_3pcf(gt, weighted=True)
+    part = ctx.count_3pcf(gt, anchors=(1000, 31000), weighted=True)
+    gt.free()
+    assert np.array_equal(rp0, rp1) and np.array_equal(col0, col1)
+    assert np.array_equal(b0, b1) and np.array_equal(perm0, perm1)
+    assert np.array_equal(tiled.hist, res.hist) and tiled.n_triangles == res.n_triangles
+    assert tiled.wsum_int() == res.wsum_int()
+    ref = oracle.count_3pcf(x, L, 0.0, rmax, nb, weights=w)
+    assert np.array_equal(tiled.hist, ref.hist) and tiled.wsum_int() == ref.wsum_int()
+    refp = oracle.count_3pcf(x, L, 0.0, rmax, nb, weights=w, anchors=(1000, 31000))
+    assert np.array_equal(part.hist, refp.hist) and part.wsum_int() == refp.wsum_int()
+
+
+def test_budget_cap_forces_tiling(gsn):
+    w = synth.workload("ns_3pcf", volume_fraction=0.125)
+    with gsn.Context(0) as full:
+        g = full.build_graph(w.xyz, w.box, w.rmin, w.rmax, w.nbins)
+        ref = full.count_3pcf(g)
+        info = g.info()
+        g.free()
+    fixed = 8 * (w.n + 1) + 4 * w.n
+    budget = fixed + (5 * info.n_edges) // 3
+    say("budget cap", budget)
+    with gsn.Context(0, budget_bytes=budget) as small:
+        g = small.build_graph(w.xyz, w.box, w.rmin, w.rmax, w.nbins)
+        ti = g.info()
+        got = small.count_3pcf(g)
+        g.free()
+    assert ti.n_windows > 1
+    assert np.array_equal(got.hist, ref.hist) and got.n_triangles == ref.n_triangles
+
+
+def test_parity_on_tiled_graph_is_refused(ctx, gsn, monkeypatch):
+    monkeypatch.setenv("GS_WINDOWS", "2")
+    x = synth.uniform(3000, 20.0, 93)
+    g = ctx.build_graph(x, 20.0, 0.0, 2.0, 4, keep_coords=True)
+    with pytest.raises(gsn.GsError) as e:
+        ctx.count_4pcf_parity(g)
+    g.free()
+    assert e.value.code == gsn.GS_EUNSUPPORTED
+
+
+def test_full_size_lognormal_weighted_sampled_anchors(ctx):
+    """Full-size weighted workload (2e6 points, rmax 150): exact 128-bit sums
+    for sampled anchor ranges against stored oracle values."""
+    gold = json.load(open(os.path.join(HERE, "golden", "lognormal_w3pcf_sampled.json")))
+    w = synth.workload("lognormal_w3pcf")
+    assert hashlib.sha256(np.ascontiguousarray(w.xyz).tobytes()).hexdigest() == gold["xyz_sha256"]
+    assert hashlib.sha256(np.ascontiguousarray(w.weights).tobytes()).hexdigest() == gold["weights_sha256"]
+    say("full lognormal sampled", w.n)
+    g = ctx.build_graph(w.xyz, w.box, w.rmin, w.rmax, w.nbins, weights=w.weights)
+    for s in gold["samples"]:
+        say("  sample", s["lo"], s["hi"])
+        got = ctx.count_3pcf(g, anchors=(s["lo"], s["hi"]), weighted=True)
+        assert got.n_triangles == s["n_triangles"]
+        assert got.hist.tolist() == s["hist"]
+        assert got.wscale == s["wscale"]
+        assert got.wsum.tolist() == s["wsum"]
+    g.free()
+
+
+@pytest.mark.skipif(os.environ.get("GS_LONG_TESTS") != "1",
+                    reason="two full 2e12-triangle counts (minutes); set GS_LONG_TESTS=1")
+def test_full_size_lognormal_weighted_resident_tiled_and_sampled(ctx, monkeypatch):
+    gold = json.load(open(os.path.join(HERE, "golden", "lognormal_w3pcf_sampled.json")))
+    w = synth.workload("lognormal_w3pcf")
+    assert hashlib.sha256(np.ascontiguousarray(w.xyz).tobytes()).hexdigest() == gold["xyz_sha256"]
+    assert hashlib.sha256(np.ascontiguousarray(w.weights).tobytes()).hexdigest() == gold["weights_sha256"]
+    say("full lognormal resident", w.n)
+    g = ctx.build_graph(w.xyz, w.box, w.rmin, w.rmax, w.nbins, weights=w.weights)
+    res = ctx.count_3pcf(g, weighted=True)
+    for s in gold["samples"]:
+        say("  sample", s["lo"], s["hi"])
+        got = ctx.count_3pcf(g, anchors=(s["lo"], s["hi"]), weighted=True)
+        assert got.n_triangles == s["n_triangles"]
+        assert got.hist.tolist() == s["hist"]
+        assert got.wscale == s["wscale"]
+        assert got.wsum.tolist() == s["wsum"]
+    g.free()
+    assert int(res.hist.sum()) == res.n_triangles
+    say("full lognormal tiled", 4)
+    monkeypatch.setenv("GS_WINDOWS", "4")
+    gt = ctx.build_graph(w.xyz, w.box, w.rmin, w.rmax, w.nbins, weights=w.weights)
+    assert gt.info().n_windows == 4
+    tiled = ctx.count_3pcf(gt, weighted=True)
+    gt.free()
+    assert np.array_equal(tiled.hist, res.hist) and tiled.wsum_int() == res.wsum_int()
