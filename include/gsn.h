@@ -142,6 +142,60 @@ int gs_count_3pcf(gs_ctx *ctx, const gs_graph *g, uint64_t *hist, uint64_t *wsum
 int gs_count_4pcf_parity(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos,
                          uint64_t *neg, uint64_t *n_cliques, const gs_anchor_range *anchors);
 
+/* Binned triangle counts of several resident graphs (same nbins) in ONE
+ * persistent launch: hubs of all graphs form one queue, so small and large
+ * catalogues balance across the device (paper Sec. 3.5.2 hub parallelism,
+ * applied to many catalogues).
+ *  graphs: host array of ng graph handles (unweighted counts);
+ *  hists: host u64[ng * C(nbins+2,3)], graph g's histogram at g*C(nbins+2,3);
+ *  n_triangles: host u64[ng].
+ * Results are identical to ng separate gs_count_3pcf calls.
+ * Errors: GS_EINVAL (differing nbins, null), GS_EUNSUPPORTED (host-tiled). */
+int gs_count_3pcf_batch(gs_ctx *ctx, const gs_graph *const *graphs, int ng, uint64_t *hists,
+                        uint64_t *n_triangles);
+
+/* ---- serving: continuous batching of triangle-count requests ----
+ * gs_submit copies the catalogue and returns a ticket at once. A scheduler
+ * thread of the context admits queued requests while device memory (the
+ * context budget, checked against each graph's exact footprint once its edge
+ * count is known) and batch slots allow, builds their graphs while the
+ * previous count step runs, and counts all built graphs in one batched
+ * launch per step; requests arriving meanwhile join the next step. Results
+ * are identical to a lone gs_build_graph + gs_count_3pcf.
+ * submit / poll / cancel are thread-safe. */
+#define GS_PENDING 1      /* queued, building or counting                       */
+#define GS_DONE 0         /* result available (returned once, then forgotten)   */
+#define GS_FAILED 2       /* request failed: error holds the status code        */
+#define GS_CANCELLED 3
+
+typedef struct {
+    const double *xyz;      /* host n x 3 float64, copied by gs_submit          */
+    int64_t n;
+    gs_graph_params p;      /* flags must be 0 (host input, unweighted)          */
+} gs_request;
+
+typedef struct {
+    int32_t status;         /* GS_PENDING / GS_DONE / GS_FAILED / GS_CANCELLED   */
+    int32_t error;          /* status code when GS_FAILED                        */
+    uint64_t n_triangles;
+    uint64_t *hist;         /* caller-provided u64[C(nbins+2,3)], filled on DONE */
+    double t_queue_s;       /* submit -> graph build started                     */
+    double t_build_s;       /* graph build                                       */
+    double t_count_s;       /* the batched count step that held this request     */
+    double t_total_s;       /* submit -> result ready                            */
+    uint32_t step_size;     /* catalogues counted in that step                   */
+    uint32_t reserved;
+} gs_result;
+
+/* Errors: GS_EINVAL (bad request), GS_EAGAIN (queue full), GS_EUNSUPPORTED. */
+int gs_submit(gs_ctx *ctx, const gs_request *req, uint64_t *ticket);
+/* status GS_PENDING leaves *out's arrays untouched; DONE / FAILED / CANCELLED
+ * retire the ticket. Error: GS_ENOTFOUND for an unknown or retired ticket. */
+int gs_poll(gs_ctx *ctx, uint64_t ticket, gs_result *out);
+/* Cancel a request not yet finished: it is dropped if still queued, its
+ * result discarded if already building or counting. GS_ENOTFOUND if unknown. */
+int gs_cancel(gs_ctx *ctx, uint64_t ticket);
+
 /* Device timings of the context's last build / count call. */
 int gs_get_timings(const gs_ctx *ctx, gs_timings *out);
 

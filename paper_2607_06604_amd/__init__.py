@@ -6,4 +6,5 @@ include/gsn.h; gsn.py is its ctypes binding.
 from .gsn import (Context, Graph, GsError, Count3, Count4, n_configs, load, EXPORTS,  # noqa: F401
                   GS_OK, GS_EINVAL, GS_EOVERFLOW, GS_ENOMEM, GS_EDEVMEM, GS_EHIP, GS_EAGAIN,
                   GS_ENOTFOUND, GS_EUNSUPPORTED, GS_ENOCOORDS, GS_WEIGHTED, GS_KEEP_COORDS,
-                  GS_INPUT_ON_DEVICE, LIB_PATH)
+                  GS_INPUT_ON_DEVICE, LIB_PATH, GS_DONE, GS_PENDING, GS_FAILED,
+                  GS_CANCELLED)

@@ -292,9 +292,32 @@ __global__ void k_sum_sq_deg(const uint64_t *__restrict__ rp, const uint32_t *__
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(acc, v);
 }
 
+// Builder arguments shared by the count and fill passes.
+EdgeArgs edge_args(const Graph &g, const BuildJob &job) {
+    const uint32_t n = (uint32_t)g.n;
+    EdgeArgs ea{};
+    ea.X = job.C;
+    ea.Y = job.C + n;
+    ea.Z = job.C + 2 * (size_t)n;
+    ea.cellL = job.cellL.as<uint32_t>();
+    ea.cstart = job.cstart.as<uint64_t>();
+    ea.thr = job.thr.as<double>();
+    ea.n = n;
+    ea.l0 = 0;
+    ea.l1 = n;
+    ea.obase = 0;
+    ea.nc = job.nc;
+    ea.nb = g.nbins;
+    ea.L = g.box;
+    ea.half = 0.5 * g.box;
+    return ea;
+}
+
 }  // namespace
 
-void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
+// Phase 1: cells, relabelling, degree pass and row offsets. Afterwards the
+// exact edge count (hence the CSR footprint) is known; no edge memory is held.
+void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJob &job) {
     hipStream_t s = ctx.stream;
     const uint32_t n = (uint32_t)g.n;
     GS_HIP(hipEventRecord(ctx.ev[0], s));
@@ -304,14 +327,13 @@ void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
 
     g.row_ptr.alloc(sizeof(uint64_t) * ((size_t)n + 1));
     g.perm.alloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    job.E = 0;
+    job.empty = n == 0;
     if (n == 0) {
         k_fill_u64<<<1, 1, 0, s>>>(g.row_ptr.as<uint64_t>(), 1, 0);
-        g.col.alloc(4);
-        g.bin.alloc(1);
         if (keep) g.coords.alloc(8);
         if (weighted) g.weights.alloc(8);
         GS_HIP(hipStreamSynchronize(s));
-        g.device_bytes = g.row_ptr.bytes + g.perm.bytes + g.col.bytes + g.bin.bytes;
         return;
     }
 
@@ -335,9 +357,12 @@ void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
     int nc = ncd < 3 ? 1 : (int)ncd;
     uint64_t ncell = (uint64_t)nc * nc * nc;
 
-    DevBuf cell_of(sizeof(uint32_t) * n), count(sizeof(uint32_t) * ncell),
-        cstart(sizeof(uint64_t) * (ncell + 1)), order(sizeof(uint32_t) * n),
-        flags(64), cellL(sizeof(uint32_t) * n), deg(sizeof(uint32_t) * n);
+    DevBuf cell_of(sizeof(uint32_t) * n), count(sizeof(uint32_t) * ncell), order(sizeof(uint32_t) * n),
+        flags(64), deg(sizeof(uint32_t) * n);
+    job.cstart.alloc(sizeof(uint64_t) * (ncell + 1));
+    job.cellL.alloc(sizeof(uint32_t) * n);
+    DevBuf &cstart = job.cstart, &cellL = job.cellL;
+    job.nc = nc;
     uint32_t *fl = flags.as<uint32_t>();
     k_fill_u32<<<1, 64, 0, s>>>(fl, 8, 0);
     k_fill_u64<<<1, 64, 0, s>>>(flags.as<uint64_t>() + 4, 1, ~0ull);  // wmin bits
@@ -354,15 +379,15 @@ void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
                                              count.as<uint32_t>(), order.as<uint32_t>());
     k_rank<<<grid_for(n), kBlock, 0, s>>>(order.as<uint32_t>(), cell_of.as<uint32_t>(),
                                           cstart.as<uint64_t>(), n, g.perm.as<uint32_t>());
-    DevBuf tmp_coords;
     double *C;
     if (keep) {
         g.coords.alloc(sizeof(double) * 3 * (size_t)n);
         C = g.coords.as<double>();
     } else {
-        tmp_coords.alloc(sizeof(double) * 3 * (size_t)n);
-        C = tmp_coords.as<double>();
+        job.tmp_coords.alloc(sizeof(double) * 3 * (size_t)n);
+        C = job.tmp_coords.as<double>();
     }
+    job.C = C;
     if (weighted) g.weights.alloc(sizeof(double) * n);
     k_gather<<<grid_for(n), kBlock, 0, s>>>(g.perm.as<uint32_t>(), dxyz, dw, cell_of.as<uint32_t>(), n,
                                             C, C + n, C + 2 * (size_t)n,
@@ -370,24 +395,10 @@ void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
                                             cellL.as<uint32_t>());
     GS_HIP(hipGetLastError());
 
-    DevBuf thr(sizeof(double) * 256);
-    GS_HIP(hipMemcpyAsync(thr.p, g.bins.t, sizeof(double) * 256, hipMemcpyHostToDevice, s));
+    job.thr.alloc(sizeof(double) * 256);
+    GS_HIP(hipMemcpyAsync(job.thr.p, g.bins.t, sizeof(double) * 256, hipMemcpyHostToDevice, s));
 
-    EdgeArgs ea{};
-    ea.X = C;
-    ea.Y = C + n;
-    ea.Z = C + 2 * (size_t)n;
-    ea.cellL = cellL.as<uint32_t>();
-    ea.cstart = cstart.as<uint64_t>();
-    ea.thr = thr.as<double>();
-    ea.n = n;
-    ea.l0 = 0;
-    ea.l1 = n;
-    ea.obase = 0;
-    ea.nc = nc;
-    ea.nb = g.nbins;
-    ea.L = g.box;
-    ea.half = 0.5 * g.box;
+    EdgeArgs ea = edge_args(g, job);
     ea.deg = deg.as<uint32_t>();
     ea.maxdeg = fl + 1;
     k_edges<false><<<grid_for(n), kBlock, 0, s>>>(ea);
@@ -399,6 +410,7 @@ void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
         uint64_t wmin, wmax;
     } hf;
     uint64_t E = 0;
+    GS_HIP(hipEventRecord(ctx.ev[1], s));
     GS_HIP(hipMemcpyAsync(&hf, fl, sizeof hf, hipMemcpyDeviceToHost, s));
     GS_HIP(hipMemcpyAsync(&E, g.row_ptr.as<uint64_t>() + n, sizeof E, hipMemcpyDeviceToHost, s));
     GS_HIP(hipStreamSynchronize(s));
@@ -420,6 +432,31 @@ void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
         if (std::ilogb((double)thi) + g.wscale >= 64)
             fail(GS_EINVAL, "weight range too wide for exact 128-bit sums");
     }
+    job.E = E;
+    float ms = 0;
+    GS_HIP(hipEventElapsedTime(&ms, ctx.ev[0], ctx.ev[1]));
+    job.begin_ms = ms;
+}
+
+// CSR bytes the graph will hold once build_end runs resident.
+uint64_t build_footprint(const Graph &g, const BuildJob &job) {
+    return g.row_ptr.bytes + g.perm.bytes + g.coords.bytes + g.weights.bytes + 5 * job.E + 8;
+}
+
+// Phase 2: the CSR itself, resident or in host-pinned windows (tile_ok).
+void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok) {
+    hipStream_t s = ctx.stream;
+    const uint32_t n = (uint32_t)g.n;
+    const uint64_t E = job.E;
+    GS_HIP(hipEventRecord(ctx.ev[0], s));
+    if (job.empty) {
+        g.col.alloc(4);
+        g.bin.alloc(1);
+        g.device_bytes = g.row_ptr.bytes + g.perm.bytes + g.col.bytes + g.bin.bytes;
+        ctx.t.build_ms = job.begin_ms;
+        return;
+    }
+    EdgeArgs ea = edge_args(g, job);
 
     // resident, or host-tiled windows when the CSR would not fit the budget
     // (GS_WINDOWS forces a window count, as the paper's environment override)
@@ -427,7 +464,7 @@ void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
     const uint64_t csr = 5 * E;
     int W = 1;
     if (const char *ew = getenv("GS_WINDOWS")) W = std::max(1, atoi(ew));
-    if (W == 1 && fixed + csr > ctx.budget) {
+    if (W == 1 && tile_ok && fixed + csr > ctx.budget) {
         if (ctx.budget <= fixed + (1u << 20)) fail(GS_EDEVMEM, "budget below the graph's per-point arrays");
         const uint64_t per_win = (ctx.budget - fixed) / 4;  // 4 window buffers while counting
         W = (int)std::min<uint64_t>((csr + per_win - 1) / per_win, 1u << 20);
@@ -496,9 +533,15 @@ void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
     for (int k = 0; k < 255; ++k) g.pair_hist[k] = k < g.nbins ? hph[k] : 0;
     float ms = 0;
     GS_HIP(hipEventElapsedTime(&ms, ctx.ev[0], ctx.ev[1]));
-    ctx.t.build_ms = ms;
+    ctx.t.build_ms = job.begin_ms + ms;
     g.device_bytes = g.row_ptr.bytes + g.col.bytes + g.bin.bytes + g.perm.bytes + g.coords.bytes +
                      g.weights.bytes;
+}
+
+void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {
+    BuildJob job;
+    build_begin(ctx, g, xyz, w, job);
+    build_end(ctx, g, job, true);
 }
 
 }  // namespace gsn

@@ -135,6 +135,7 @@ int gs_create(gs_ctx **out, int device, uint64_t hbm_budget_bytes, void *hip_str
 int gs_destroy(gs_ctx *ctx) {
     if (!ctx) return GS_EINVAL;
     (void)hipSetDevice(ctx->device);
+    server_stop(*ctx);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -264,6 +265,36 @@ int gs_count_4pcf_parity(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_
         if (g->device != ctx->device) fail(GS_EINVAL, "graph and context on different devices");
         ctx->use();
         count4_run(*ctx, *g, even, pos, neg, n_cliques, anchors);
+    });
+}
+
+int gs_count_3pcf_batch(gs_ctx *ctx, const gs_graph *const *graphs, int ng, uint64_t *hists,
+                        uint64_t *n_triangles) {
+    return guarded([&] {
+        if (!ctx || !graphs || ng < 1 || !hists || !n_triangles) fail(GS_EINVAL, "null argument");
+        ctx->use();
+        std::vector<const Graph *> gs(ng);
+        for (int g = 0; g < ng; ++g) gs[g] = graphs[g];
+        Batch3 b;
+        GS_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
+        count3_batch_enqueue(*ctx, ctx->stream, gs.data(), ng, b);
+        GS_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
+        GS_HIP(hipEventSynchronize(b.done));
+        GS_HIP(hipStreamSynchronize(ctx->stream));
+        const unsigned long long *o = b.out.as<unsigned long long>();
+        const size_t per = (size_t)b.nconf + 1;
+        for (int g = 0; g < ng; ++g) {
+            for (int c = 0; c < b.nconf; ++c) hists[(size_t)g * b.nconf + c] = o[g * per + c];
+            n_triangles[g] = o[g * per + b.nconf];
+        }
+        float ms = 0;
+        GS_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+        ctx->t.count_ms = ms;
+        ctx->t.kernel_ms = ms;
+        ctx->t.kernel_launches = 1;
+        uint64_t sq = 0;
+        for (int g = 0; g < ng; ++g) sq += gs[g]->sum_sq_deg;
+        ctx->t.alg_bytes = (uint64_t)(2.5 * (double)sq);
     });
 }
 

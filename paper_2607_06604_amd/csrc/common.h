@@ -98,6 +98,8 @@ struct Timings {
     uint64_t kernel_launches = 0, alg_bytes = 0;
 };
 
+struct Server;
+
 // Result staging shared by the count entry points of one context.
 struct Ctx {
     int device = 0;
@@ -112,6 +114,7 @@ struct Ctx {
     DevBuf scratch;             // grown on demand, reused across calls
     void *pinned = nullptr;     // small pinned host staging
     size_t pinned_bytes = 0;
+    Server *server = nullptr;   // continuous-batching scheduler (gs_submit)
     void *scratch_get(size_t bytes);
     void *pinned_get(size_t bytes);
     void use() const;
@@ -150,6 +153,19 @@ struct Graph {
     DevBuf perm;      // u32[n]: label -> original index
     DevBuf coords;    // f64[3n] SoA x|y|z (GS_KEEP_COORDS)
     DevBuf weights;   // f64[n] (GS_WEIGHTED)
+};
+
+// State carried between the two build phases (temporaries of the degree pass).
+struct BuildJob {
+    DevBuf cstart;       // u64[ncell+1]
+    DevBuf cellL;        // u32[n]: cell of each label
+    DevBuf thr;          // f64[256] squared thresholds
+    DevBuf tmp_coords;   // f64[3n] when the graph does not keep coordinates
+    double *C = nullptr; // label-ordered SoA coordinates
+    int nc = 1;
+    bool empty = false;
+    uint64_t E = 0;      // forward entries, known after build_begin
+    double begin_ms = 0;
 };
 
 Bins make_bins(double rmin, double rmax, int nb);
@@ -196,6 +212,25 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
 void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_t *neg,
                 uint64_t *ncl, const gs_anchor_range *anchors);
 void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w);
+void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJob &job);
+uint64_t build_footprint(const Graph &g, const BuildJob &job);
+void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok);
+
+// Batched triangle counts over resident graphs with equal bin counts: one
+// persistent launch. Results land in host memory `out` (ng x (nconf+1) u64:
+// each graph's histogram then its triangle count) once `done` has fired.
+struct Batch3 {
+    DevBuf dv;          // device results + queues
+    DevBuf gd;          // descriptors
+    HostBuf hostdesc;   // staging of descriptors
+    HostBuf out;        // pinned results
+    hipEvent_t done = nullptr;
+    int ng = 0, nconf = 0;
+    ~Batch3();
+};
+void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int ng, Batch3 &b);
+
+void server_stop(Ctx &ctx);
 
 }  // namespace gsn
 

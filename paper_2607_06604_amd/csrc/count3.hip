@@ -28,7 +28,23 @@
 namespace gsn {
 namespace {
 
+// One catalogue of a batched launch: its forward CSR, its first virtual hub
+// index and where its counts go.
+struct GDesc {
+    const uint64_t *rp;
+    const uint32_t *col;
+    const uint8_t *bin;
+    uint64_t v0;              // virtual hub index of label 0
+    uint32_t n;
+    uint32_t pad;
+    unsigned long long *hist; // nconf
+    unsigned long long *ntri; // 1
+};
+
 struct C3Args {
+    const GDesc *gd;        // batched launch: ngraph descriptors (else null)
+    int ngraph;
+    uint32_t nvirt;         // batched launch: total hubs over all catalogues
     const uint64_t *rp;
     const uint32_t *hcol;   // hub rows (entry e of row i at rp[i] - hbase + e)
     const uint8_t *hbin;
@@ -88,13 +104,14 @@ __device__ __forceinline__ void add128(unsigned long long *dst, unsigned __int12
 }
 
 template <int BLOCK, bool WEIGHTED, bool LDS_HIST>
-__device__ void flush3(const C3Args &a, const Layout3 &L, unsigned char *sm) {
+__device__ void flush3(const C3Args &a, const Layout3 &L, unsigned char *sm,
+                       unsigned long long *hout) {
     if (!LDS_HIST) return;
     uint32_t *hist = (uint32_t *)(sm + L.hist);
     for (int b = threadIdx.x; b < a.nconf; b += BLOCK) {
         uint32_t v = hist[b];
         if (v) {
-            atomicAdd(&a.hist[b], (unsigned long long)v);
+            atomicAdd(&hout[b], (unsigned long long)v);
             hist[b] = 0;
         }
         if (WEIGHTED) {
@@ -124,7 +141,18 @@ __device__ __forceinline__ uint32_t next_hub_in(uint32_t *queue, uint32_t h0, ui
     return kEmptyKey;
 }
 
-template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
+// Catalogue of virtual hub v: the last descriptor with v0 <= v.
+__device__ __forceinline__ int graph_of(const GDesc *gd, int ng, uint32_t v) {
+    int lo = 0, hi = ng;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (gd[mid].v0 <= v) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const uint32_t H = 1u << a.log2h, mask = H - 1;
@@ -163,16 +191,65 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     unsigned long long mytri = 0;
     uint64_t acc = 0;   // upper bound on increments since the last flush (uniform)
     int qv = 0;         // queues found empty (thread 0)
+    int cur = -1;       // batched launch: catalogue whose counts the LDS holds
+    int *s_g = (int *)(sm + L.misc + 4);
+    // the CSR view of the current hub: the launch's tile, or one catalogue
+    const uint64_t *rp = a.rp;
+    const uint32_t *hcol = a.hcol, *scol = a.scol;
+    const uint8_t *hbinp = a.hbin, *sbinp = a.sbin;
+    uint64_t hbase = a.hbase, sbase = a.sbase;
+    uint32_t s0 = a.s0, s1 = a.s1;
+    unsigned long long *hout = a.hist, *tout = a.ntri;
 
     while (true) {
-        if (tid == 0) *s_hub = next_hub_in(a.queue, a.h0, a.h1, &qv);
+        if (tid == 0) {
+            if (BATCH) {
+                const uint32_t v = next_hub_in(a.queue, 0, a.nvirt, &qv);
+                if (v != kEmptyKey) {
+                    const int g = graph_of(a.gd, a.ngraph, v);
+                    *s_g = g;
+                    *s_hub = (uint32_t)(v - a.gd[g].v0);
+                } else {
+                    *s_hub = kEmptyKey;
+                }
+            } else {
+                *s_hub = next_hub_in(a.queue, a.h0, a.h1, &qv);
+            }
+        }
         __syncthreads();
         const uint32_t i = *s_hub;
         if (i == kEmptyKey) break;
-        const uint64_t beg = a.rp[i] - a.hbase;
-        const uint32_t d = (uint32_t)(a.rp[i + 1] - a.rp[i]);
+        if (BATCH) {
+            const int g = *s_g;
+            if (g != cur) {
+                // a new catalogue: hand the previous one its counts first
+                if (cur >= 0) {
+                    flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout);
+                    if (mytri) atomicAdd(s_cnt, mytri);
+                    mytri = 0;
+                    acc = 0;
+                    __syncthreads();
+                    if (tid == 0 && *s_cnt) {
+                        atomicAdd(tout, *s_cnt);
+                        *s_cnt = 0;
+                    }
+                }
+                cur = g;
+                const GDesc &G = a.gd[g];
+                rp = G.rp;
+                hcol = scol = G.col;
+                hbinp = sbinp = G.bin;
+                hbase = sbase = 0;
+                s0 = 0;
+                s1 = G.n;
+                hout = G.hist;
+                tout = G.ntri;
+            }
+        }
+        const uint64_t beg = rp[i] - hbase;
+        const uint32_t d = (uint32_t)(rp[i + 1] - rp[i]);
         if (d < 2 || (ANCHORED && a.mark && !a.mark[i])) { __syncthreads(); continue; }
-        const uint32_t kmax = a.hcol[beg + d - 1];  // largest label of N+(i)
+        const uint32_t kmax = hcol[beg + d - 1];  // largest label of N+(i)
         double wi = 0.0;
         uint32_t pi = 0;
         if (WEIGHTED) wi = a.w[i];
@@ -180,10 +257,10 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
 
         // stage N+(i): label -> bin of (i, k)
         for (uint32_t e = tid; e < d; e += BLOCK) {
-            const uint32_t k = a.hcol[beg + e];
+            const uint32_t k = hcol[beg + e];
             uint32_t s = label_hash(k, a.log2h);
             while (atomicCAS(&hkey[s], kEmptyKey, k) != kEmptyKey) s = (s + 1) & mask;
-            hbin[s] = a.hbin[beg + e];
+            hbin[s] = hbinp[beg + e];
             hslot[e] = (uint16_t)s;
         }
         __syncthreads();
@@ -195,21 +272,21 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             uint32_t len = 0;
             uint64_t st = 0;
             if (sidx + 1 < d) {
-                const uint32_t j = a.hcol[beg + sidx];
-                if (j >= a.s0 && j < a.s1) {
-                    st = a.rp[j] - a.sbase;
-                    len = (uint32_t)(a.rp[j + 1] - a.rp[j]);
+                const uint32_t j = hcol[beg + sidx];
+                if (j >= s0 && j < s1) {
+                    st = rp[j] - sbase;
+                    len = (uint32_t)(rp[j + 1] - rp[j]);
                     // entries of N+(j) above the largest label of N+(i) cannot match
-                    if (a.trunc && len > 16 && a.scol[st + len - 1] > kmax) {
+                    if (a.trunc && len > 16 && scol[st + len - 1] > kmax) {
                         uint32_t lo = 0, hi = len;  // first entry > kmax
                         while (lo < hi) {
                             const uint32_t mid = (lo + hi) >> 1;
-                            if (a.scol[st + mid] <= kmax) lo = mid + 1;
+                            if (scol[st + mid] <= kmax) lo = mid + 1;
                             else hi = mid;
                         }
                         len = lo;
                     }
-                    mbin[tid] = a.hbin[beg + sidx];
+                    mbin[tid] = hbinp[beg + sidx];
                     if (WEIGHTED) mw[tid] = a.w[j];
                     if (ANCHORED) mperm[tid] = a.perm[j];
                 }
@@ -220,7 +297,7 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             mpref[tid] = pre;
             if (tid == 0) mpref[BLOCK] = total;
             if (acc + total >= a.flush_limit) {
-                flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm);
+                flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout);
                 acc = 0;
             }
             acc += total;
@@ -232,7 +309,7 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
                 if (e < total) {
                     while (mpref[sp + 1] <= e) ++sp;
                     const uint64_t pos = mstart[sp] + (e - mpref[sp]);
-                    const uint32_t k = a.scol[pos];
+                    const uint32_t k = scol[pos];
                     uint32_t h = label_hash(k, a.log2h);
                     uint32_t key;
                     while ((key = hkey[h]) != k && key != kEmptyKey) h = (h + 1) & mask;
@@ -243,12 +320,12 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
                             take = m >= a.anchor_lo && m < a.anchor_hi;
                         }
                         if (take) {
-                            const int x = mbin[sp], y = hbin[h], z = a.sbin[pos];
+                            const int x = mbin[sp], y = hbin[h], z = sbinp[pos];
                             const int lo = min(x, min(y, z)), hi = max(x, max(y, z));
                             const int mid = x + y + z - lo - hi;
                             const int idx = ta[lo] + tb[mid] + hi;
                             if (LDS_HIST) atomicAdd(&hist[idx], 1u);
-                            else atomicAdd(&a.hist[idx], 1ull);
+                            else atomicAdd(&hout[idx], 1ull);
                             ++mytri;
                             if (WEIGHTED) {
                                 double p = wi, q = mw[sp], r = a.w[k], t;
@@ -276,10 +353,10 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     }
 
     __syncthreads();
-    flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm);
+    flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout);
     if (mytri) atomicAdd(s_cnt, mytri);
     __syncthreads();
-    if (tid == 0 && *s_cnt) atomicAdd(a.ntri, *s_cnt);
+    if (tid == 0 && *s_cnt && tout) atomicAdd(tout, *s_cnt);
 }
 
 __global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
@@ -288,17 +365,17 @@ __global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
         p[i] = 0;
 }
 
-template <int B, bool W, bool A, bool LH>
+template <int B, bool W, bool A, bool LH, bool BATCH = false>
 void launch3(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds) {
-    const void *kern = reinterpret_cast<const void *>(&k_count3<B, W, A, LH>);
+    const void *kern = reinterpret_cast<const void *>(&k_count3<B, W, A, LH, BATCH>);
     if (lds > 65536)
         GS_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
-    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count3<B, W, A, LH>, B, lds));
+    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count3<B, W, A, LH, BATCH>, B, lds));
     if (per_cu < 1) fail(GS_EUNSUPPORTED, "count kernel does not fit a compute unit");
     uint32_t grid = (uint32_t)ctx.n_cu * (uint32_t)per_cu;
     grid = (grid + kNumQueues - 1) / kNumQueues * kNumQueues;
-    k_count3<B, W, A, LH><<<dim3(grid), dim3(B), lds, s>>>(a);
+    k_count3<B, W, A, LH, BATCH><<<dim3(grid), dim3(B), lds, s>>>(a);
     GS_HIP(hipGetLastError());
 }
 
@@ -378,7 +455,77 @@ uint64_t flush_limit_for(uint32_t maxdeg, uint64_t per_chunk_factor) {
     return v;
 }
 
+template <int B>
+void launch3_batch(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P) {
+    if (P.lds_hist) launch3<B, false, false, true, true>(ctx, s, a, P.lds);
+    else launch3<B, false, false, false, true>(ctx, s, a, P.lds);
+}
+
 }  // namespace
+
+Batch3::~Batch3() {
+    if (done) (void)hipEventDestroy(done);
+}
+
+void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int ng, Batch3 &b) {
+    if (ng < 1) fail(GS_EINVAL, "empty batch");
+    const int nb = gs[0]->nbins;
+    uint32_t maxdeg = 0;
+    uint64_t nvirt = 0;
+    for (int g = 0; g < ng; ++g) {
+        if (!gs[g]) fail(GS_EINVAL, "null graph in batch");
+        if (gs[g]->nbins != nb) fail(GS_EINVAL, "graphs of a batch must share nbins");
+        if (gs[g]->n_windows != 1) fail(GS_EUNSUPPORTED, "batched counts need device-resident graphs");
+        if (gs[g]->device != ctx.device) fail(GS_EINVAL, "graph on another device");
+        maxdeg = std::max(maxdeg, gs[g]->max_deg);
+        nvirt += (uint64_t)gs[g]->n;
+    }
+    if (nvirt >= 0xFFFFFFFFull) fail(GS_EUNSUPPORTED, "batch holds 2^32 or more points");
+    const int nconf = (int)n_configs(nb);
+    const Plan3 P = plan3(ctx, maxdeg, nb, false, false);
+    b.ng = ng;
+    b.nconf = nconf;
+    const size_t per = (size_t)nconf + 1;
+    const size_t words = (size_t)ng * per + kNumQueues / 2 + 1;
+    b.dv.alloc(words * 8);
+    unsigned long long *dv = b.dv.as<unsigned long long>();
+    b.hostdesc.alloc(sizeof(GDesc) * ng);
+    GDesc *hd = b.hostdesc.as<GDesc>();
+    uint64_t v0 = 0;
+    for (int g = 0; g < ng; ++g) {
+        hd[g].rp = gs[g]->row_ptr.as<uint64_t>();
+        hd[g].col = gs[g]->col.as<uint32_t>();
+        hd[g].bin = gs[g]->bin.as<uint8_t>();
+        hd[g].v0 = v0;
+        hd[g].n = (uint32_t)gs[g]->n;
+        hd[g].pad = 0;
+        hd[g].hist = dv + (size_t)g * per;
+        hd[g].ntri = dv + (size_t)g * per + nconf;
+        v0 += (uint64_t)gs[g]->n;
+    }
+    b.gd.alloc(sizeof(GDesc) * ng);
+    GS_HIP(hipMemcpyAsync(b.gd.p, hd, sizeof(GDesc) * ng, hipMemcpyHostToDevice, s));
+    k_zero_u64<<<64, 256, 0, s>>>(dv, words);
+    C3Args a{};
+    a.gd = b.gd.as<GDesc>();
+    a.ngraph = ng;
+    a.nvirt = (uint32_t)nvirt;
+    a.nb = nb;
+    a.nconf = nconf;
+    a.log2h = P.log2h;
+    a.trunc = P.trunc;
+    a.maxdeg = maxdeg;
+    a.flush_limit = flush_limit_for(maxdeg, P.block);
+    a.queue = (uint32_t *)(dv + (size_t)ng * per);
+    if (nvirt > 0) {
+        if (P.block == 512) launch3_batch<512>(ctx, s, a, P);
+        else launch3_batch<256>(ctx, s, a, P);
+    }
+    b.out.alloc(sizeof(unsigned long long) * (size_t)ng * per);
+    GS_HIP(hipMemcpyAsync(b.out.p, dv, sizeof(unsigned long long) * (size_t)ng * per, hipMemcpyDeviceToHost, s));
+    if (!b.done) GS_HIP(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
+    GS_HIP(hipEventRecord(b.done, s));
+}
 
 void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64_t *ntri,
                 const gs_anchor_range *anchors) {

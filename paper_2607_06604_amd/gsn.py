@@ -31,10 +31,16 @@ GS_WEIGHTED = 1
 GS_KEEP_COORDS = 2
 GS_INPUT_ON_DEVICE = 4
 
+GS_DONE = 0
+GS_PENDING = 1
+GS_FAILED = 2
+GS_CANCELLED = 3
+
 # every symbol include/gsn.h declares
 EXPORTS = ["gs_create", "gs_destroy", "gs_build_graph", "gs_graph_info", "gs_graph_export",
-           "gs_graph_free", "gs_count_3pcf", "gs_count_4pcf_parity", "gs_get_timings",
-           "gs_strerror", "gs_last_error_detail"]
+           "gs_graph_free", "gs_count_3pcf", "gs_count_4pcf_parity", "gs_count_3pcf_batch",
+           "gs_submit", "gs_poll", "gs_cancel", "gs_get_timings", "gs_strerror",
+           "gs_last_error_detail"]
 
 
 class GraphParams(ctypes.Structure):
@@ -56,6 +62,17 @@ class Timings(ctypes.Structure):
     _fields_ = [("build_ms", ctypes.c_double), ("count_ms", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_uint64),
                 ("alg_bytes", ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("n", ctypes.c_int64), ("p", GraphParams)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("error", ctypes.c_int32), ("n_triangles", ctypes.c_uint64),
+                ("hist", ctypes.c_void_p), ("t_queue_s", ctypes.c_double), ("t_build_s", ctypes.c_double),
+                ("t_count_s", ctypes.c_double), ("t_total_s", ctypes.c_double),
+                ("step_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class GsError(RuntimeError):
@@ -91,6 +108,10 @@ def load(path: str = LIB_PATH):
         "gs_graph_free": ([P], i32),
         "gs_count_3pcf": ([P, P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_count_4pcf_parity": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
+        "gs_count_3pcf_batch": ([P, P, i32, P, P], i32),
+        "gs_submit": ([P, ctypes.POINTER(Request), ctypes.POINTER(u64)], i32),
+        "gs_poll": ([P, u64, ctypes.POINTER(Result)], i32),
+        "gs_cancel": ([P, u64], i32),
         "gs_get_timings": ([P, ctypes.POINTER(Timings)], i32),
         "gs_strerror": ([i32], ctypes.c_char_p),
         "gs_last_error_detail": ([], ctypes.c_char_p),
@@ -210,6 +231,46 @@ class Context:
         _check(load().gs_count_4pcf_parity(self._h, g.handle, _ptr(e), _ptr(p), _ptr(m), _ptr(nk), ar),
                "gs_count_4pcf_parity")
         return Count4(e, p, m, int(nk[0]))
+
+    def count_3pcf_batch(self, graphs):
+        """One persistent launch over several resident graphs (same nbins)."""
+        ng = len(graphs)
+        nb = graphs[0].nbins
+        nc = n_configs(nb)
+        hs = np.zeros((ng, nc), dtype=np.uint64)
+        nt = np.zeros(ng, dtype=np.uint64)
+        arr = (ctypes.c_void_p * ng)(*[g.handle.value for g in graphs])
+        _check(load().gs_count_3pcf_batch(self._h, ctypes.cast(arr, ctypes.c_void_p), ng, _ptr(hs), _ptr(nt)),
+               "gs_count_3pcf_batch")
+        return [Count3(hs[k], int(nt[k]), None, None, None) for k in range(ng)]
+
+    def submit(self, xyz, box, rmin, rmax, nbins) -> int:
+        """Queue a triangle count of host catalogue xyz; returns a ticket."""
+        x = _host(xyz, np.float64)
+        if x.ndim != 2 or x.shape[1] != 3:
+            raise ValueError("xyz must be (N,3)")
+        req = Request(ctypes.c_void_p(x.ctypes.data), x.shape[0],
+                      GraphParams(float(box), float(rmin), float(rmax), int(nbins), 0))
+        t = ctypes.c_uint64()
+        _check(load().gs_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "gs_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int, nbins: int):
+        """None while pending; else a dict with status, histogram and timings
+        (the ticket is retired)."""
+        hist = np.zeros(n_configs(nbins), dtype=np.uint64)
+        r = Result()
+        r.hist = hist.ctypes.data
+        _check(load().gs_poll(self._h, ticket, ctypes.byref(r)), "gs_poll")
+        if r.status == GS_PENDING:
+            return None
+        return dict(status=int(r.status), error=int(r.error), n_triangles=int(r.n_triangles),
+                    hist=hist if r.status == GS_DONE else None, t_queue_s=r.t_queue_s,
+                    t_build_s=r.t_build_s, t_count_s=r.t_count_s, t_total_s=r.t_total_s,
+                    step_size=int(r.step_size))
+
+    def cancel(self, ticket: int):
+        _check(load().gs_cancel(self._h, ticket), "gs_cancel")
 
     def timings(self) -> Timings:
         t = Timings()

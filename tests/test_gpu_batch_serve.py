@@ -1,0 +1,174 @@
+"""Batched counts over many catalogues and the continuous-batching server:
+every catalogue's histogram is bit-identical alone and in the mix, and equal
+to the oracle's."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+L, RMAX, NB = 200.0, 10.0, 10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gsn():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2607_06604_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(gsn):
+    c = gsn.Context(0)
+    yield c
+    c.close()
+
+
+def catalogues(count, seed, lo=2_000, hi=30_000):
+    """Uneven sizes, alternating clustered data and uniform randoms."""
+    sizes = np.floor(np.exp(np.log(lo) + synth.uniform_values(count, 0.0, 1.0, seed) *
+                            (np.log(hi) - np.log(lo)))).astype(int)
+    out = []
+    for k, n in enumerate(sizes):
+        if k % 2 == 0:
+            out.append(synth.neyman_scott(int(n), 50, 2.0, L, seed * 1000 + k))
+        else:
+            out.append(synth.uniform(int(n), L, seed * 1000 + k))
+    return out
+
+
+def alone(ctx, x):
+    g = ctx.build_graph(x, L, 0.0, RMAX, NB)
+    r = ctx.count_3pcf(g)
+    g.free()
+    return r
+
+
+def test_batch_matches_individual_and_oracle(ctx):
+    cats = catalogues(14, 3)
+    gs = [ctx.build_graph(x, L, 0.0, RMAX, NB) for x in cats]
+    say("batch of", len(gs))
+    got = ctx.count_3pcf_batch(gs)
+    for g in gs:
+        g.free()
+    for k, x in enumerate(cats):
+        a = alone(ctx, x)
+        assert got[k].n_triangles == a.n_triangles and np.array_equal(got[k].hist, a.hist)
+        if k < 4:
+            ref = oracle.count_3pcf(x, L, 0.0, RMAX, NB)
+            assert np.array_equal(got[k].hist, ref.hist)
+
+
+def test_batch_of_one_and_with_empty_catalogue(ctx):
+    x = synth.uniform(5000, L, 5)
+    g = ctx.build_graph(x, L, 0.0, RMAX, NB)
+    e = ctx.build_graph(np.zeros((0, 3)), L, 0.0, RMAX, NB)
+    one = ctx.count_3pcf_batch([g])
+    two = ctx.count_3pcf_batch([e, g, e])
+    a = ctx.count_3pcf(g)
+    g.free()
+    e.free()
+    assert np.array_equal(one[0].hist, a.hist)
+    assert np.array_equal(two[1].hist, a.hist) and two[0].n_triangles == 0 and two[2].hist.sum() == 0
+
+
+def test_batch_rejects_mixed_bins(ctx, gsn):
+    x = synth.uniform(1000, L, 6)
+    a = ctx.build_graph(x, L, 0.0, RMAX, NB)
+    b = ctx.build_graph(x, L, 0.0, RMAX, NB + 1)
+    with pytest.raises(gsn.GsError) as e:
+        ctx.count_3pcf_batch([a, b])
+    a.free()
+    b.free()
+    assert e.value.code == gsn.GS_EINVAL
+
+
+def drain(ctx, tickets, timeout=120.0):
+    res = {}
+    t0 = time.time()
+    while len(res) < len(tickets):
+        assert time.time() - t0 < timeout, "serving did not finish"
+        for t in tickets:
+            if t not in res:
+                r = ctx.poll(t, NB)
+                if r is not None:
+                    res[t] = r
+        time.sleep(0.002)
+    return res
+
+
+def test_serving_alone_vs_mix(gsn):
+    cats = catalogues(24, 7)
+    with gsn.Context(0) as c:
+        want = [alone(c, x) for x in cats]
+    with gsn.Context(0) as s:
+        say("serving", len(cats))
+        tickets = []
+        for k, x in enumerate(cats):
+            tickets.append(s.submit(x, L, 0.0, RMAX, NB))
+            if k % 5 == 4:
+                time.sleep(0.003)   # arrivals spread over several steps
+        res = drain(s, tickets)
+    steps = []
+    for t, x, a in zip(tickets, cats, want):
+        r = res[t]
+        assert r["status"] == gsn.GS_DONE
+        assert r["n_triangles"] == a.n_triangles
+        assert np.array_equal(r["hist"], a.hist)
+        assert r["t_total_s"] >= r["t_count_s"] >= 0
+        steps.append(r["step_size"])
+    assert max(steps) > 1, "no request was batched with another"
+
+
+def test_serving_failures_cancel_and_unknown(gsn):
+    cats = catalogues(6, 9)
+    bad = cats[2].copy()
+    bad[10, 0] = L          # outside [0, L)
+    with gsn.Context(0) as s:
+        ts = [s.submit(x, L, 0.0, RMAX, NB) for x in cats[:2]]
+        tb = s.submit(bad, L, 0.0, RMAX, NB)
+        tc = [s.submit(x, L, 0.0, RMAX, NB) for x in cats[3:]]
+        s.cancel(tc[-1])
+        res = drain(s, ts + [tb] + tc)
+        with pytest.raises(gsn.GsError) as e:
+            s.poll(ts[0], NB)       # retired
+        assert e.value.code == gsn.GS_ENOTFOUND
+        with pytest.raises(gsn.GsError) as e:
+            s.poll(123456789, NB)
+        assert e.value.code == gsn.GS_ENOTFOUND
+        with pytest.raises(gsn.GsError) as e:
+            s.submit(cats[0], L, 0.0, L, NB)   # rmax >= L/2
+        assert e.value.code == gsn.GS_EINVAL
+    assert res[tb]["status"] == gsn.GS_FAILED and res[tb]["error"] == gsn.GS_EINVAL
+    assert res[tc[-1]]["status"] in (gsn.GS_CANCELLED, gsn.GS_DONE)
+    with gsn.Context(0) as c:
+        for t, x in zip(ts + tc[:-1], cats[:2] + cats[3:-1]):
+            assert res[t]["status"] == gsn.GS_DONE
+            assert np.array_equal(res[t]["hist"], alone(c, x).hist)
+
+
+def test_serving_small_budget_admits_one_at_a_time(gsn):
+    cats = catalogues(8, 11, lo=20_000, hi=25_000)
+    with gsn.Context(0) as c:
+        want = [alone(c, x) for x in cats]
+        g = c.build_graph(cats[0], L, 0.0, RMAX, NB)
+        fp = g.info().device_bytes
+        g.free()
+    with gsn.Context(0, budget_bytes=int(fp * 1.3)) as s:
+        ts = [s.submit(x, L, 0.0, RMAX, NB) for x in cats]
+        res = drain(s, ts)
+    for t, a in zip(ts, want):
+        assert res[t]["status"] == gsn.GS_DONE and np.array_equal(res[t]["hist"], a.hist)
+        assert res[t]["step_size"] <= 2
