@@ -63,12 +63,114 @@ def stored_traffic(workload: str, kind: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def percentile(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=float), q))
+
+
+def run_stream(args):
+    """Serving workload: a stream of catalogues of uneven size (log-uniform
+    5e4..5e5 points; even index clustered data, odd index uniform randoms) in
+    periodic 600 Mpc/h boxes, 3pCF at rmax 40 Mpc/h in 10 bins. Measures the
+    plain path (each catalogue built and counted alone, back to back), the
+    server with every request arriving at once, and the server under Poisson
+    arrivals at 0.8 of the measured batched capacity."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2607_06604_amd as gsn
+
+    L, rmax, nb = 600.0, 40.0, 10
+    sizes = synth.stream_sizes(args.stream_count, seed=5)
+    cats = [synth.stream_catalogue(k, int(n), L=L, seed=5) for k, n in enumerate(sizes)]
+    print("generated %d catalogues, %d points" % (len(cats), int(sizes.sum())), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+
+    # plain path: one catalogue at a time, host input, build + count
+    with gsn.Context(0) as c:
+        for x in cats[:2]:
+            g = c.build_graph(x, L, 0.0, rmax, nb)
+            c.count_3pcf(g)
+            g.free()
+        lat_seq, want, tri = [], [], 0
+        t0 = time.perf_counter()
+        for x in cats:
+            ts = time.perf_counter()
+            g = c.build_graph(x, L, 0.0, rmax, nb)
+            r = c.count_3pcf(g)
+            g.free()
+            lat_seq.append(time.perf_counter() - ts)
+            want.append(r.hist)
+            tri += r.n_triangles
+        t_seq = time.perf_counter() - t0
+    print("sequential %.3f s" % t_seq, file=sys.stderr, flush=True)
+
+    def serve(arrivals):
+        with gsn.Context(0) as s:
+            # warm the server (thread, streams, kernels) on a small request
+            t = s.submit(cats[1][:1000], L, 0.0, rmax, nb)
+            while s.poll(t, nb) is None:
+                time.sleep(0.001)
+            tickets = [None] * len(cats)
+            res = {}
+            t0 = time.perf_counter()
+            k = 0
+            while len(res) < len(cats):
+                now = time.perf_counter() - t0
+                while k < len(cats) and arrivals[k] <= now:
+                    tickets[k] = s.submit(cats[k], L, 0.0, rmax, nb)
+                    k += 1
+                for j in range(k):
+                    if j not in res:
+                        r = s.poll(tickets[j], nb)
+                        if r is not None:
+                            res[j] = r
+                time.sleep(0.0005)
+            makespan = time.perf_counter() - t0
+        for j in range(len(cats)):
+            assert res[j]["status"] == gsn.GS_DONE and np.array_equal(res[j]["hist"], want[j]), j
+        lat = [res[j]["t_total_s"] for j in range(len(cats))]
+        steps = [res[j]["step_size"] for j in range(len(cats))]
+        return makespan, lat, steps
+
+    span_all, lat_all, steps_all = serve(np.zeros(len(cats)))
+    print("served, all at t=0: %.3f s" % span_all, file=sys.stderr, flush=True)
+    rate = 0.8 * len(cats) / span_all
+    gaps = -np.log(1.0 - synth.uniform_values(len(cats), 0.0, 1.0, 55)) / rate
+    arr = np.cumsum(gaps) - gaps[0]
+    span_p, lat_p, steps_p = serve(arr)
+    print("served, Poisson at %.1f/s: %.3f s" % (rate, span_p), file=sys.stderr, flush=True)
+
+    per_hour = len(cats) / span_all * 3600.0
+    line = {
+        "metric": METRIC, "value": round(per_hour, 1), "unit": "catalogues/hour", "n_gpus": 1,
+        "steps": 1, "warmup": 2, "ms_per_step": round(span_all * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+int", "data": "synthetic",
+        "config": {"workload": "stream_3pcf", "catalogues": len(cats), "points": int(sizes.sum()),
+                   "sizes": "log-uniform 5e4..5e5, even clustered (Neyman-Scott 50, sigma 3), odd uniform",
+                   "box": L, "rmax": rmax, "nbins": nb, "triangles": int(tri)},
+        "all_at_once": {"catalogues_per_hour": round(per_hour, 1), "p50_s": round(percentile(lat_all, 50), 4),
+                        "p99_s": round(percentile(lat_all, 99), 4), "mean_step": round(float(np.mean(steps_all)), 2),
+                        "triangles_per_s": round(tri / span_all, 1)},
+        "poisson": {"rate_per_s": round(rate, 2), "catalogues_per_hour": round(len(cats) / span_p * 3600, 1),
+                    "p50_s": round(percentile(lat_p, 50), 4), "p99_s": round(percentile(lat_p, 99), 4),
+                    "mean_step": round(float(np.mean(steps_p)), 2)},
+        "sequential": {"catalogues_per_hour": round(len(cats) / t_seq * 3600, 1),
+                       "p50_s": round(percentile(lat_seq, 50), 4), "p99_s": round(percentile(lat_seq, 99), 4),
+                       "triangles_per_s": round(tri / t_seq, 1)},
+        "speedup_vs_sequential": round(t_seq / span_all, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="ns_3pcf", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="ns_3pcf", choices=sorted(WORKLOADS) + ["stream_3pcf"])
+    ap.add_argument("--stream-count", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=0.0,
                     help="fraction of anchor points for the oracle baseline (0 = default per workload)")
@@ -92,6 +194,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "stream_3pcf":
+        run_stream(args)
+        return
     spec = WORKLOADS[args.workload]
     w = synth.workload(args.workload)
     dev = torch.device("cuda:0")
