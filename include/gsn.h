@@ -81,7 +81,8 @@ typedef struct {
     uint64_t device_bytes;   /* device memory held by the graph                   */
     int32_t n_windows;       /* 1 = resident; > 1 = host-tiled (out of core)       */
     int32_t nbins;
-    uint64_t pair_hist[255]; /* undirected edges per bin (pair counts, free)       */
+    uint64_t pair_hist[255]; /* undirected edges per bin (the pair counts)         */
+    uint64_t sum_sq_degree;  /* sum over points of (neighbour count)^2             */
 } gs_graph_stats;
 
 typedef struct {
@@ -89,7 +90,9 @@ typedef struct {
     double count_ms;         /* last count call, device time of its launches      */
     double kernel_ms;        /* last count call: main counting kernel(s) only      */
     uint64_t kernel_launches;/* launches of the main counting kernel in that call */
-    uint64_t alg_bytes;      /* algorithmic bytes of that call (see DESIGN)       */
+    uint64_t alg_bytes;      /* 2.5 B x sum_sq_degree of the counted graph(s), the
+                                bytes a merge walk reads; 0 until gs_graph_info
+                                has computed the degree statistics               */
 } gs_timings;
 
 /* Create a context on HIP device `device`. hbm_budget_bytes = 0 means 90% of
@@ -109,6 +112,9 @@ int gs_destroy(gs_ctx *ctx);
  *  GS_EOVERFLOW, GS_EDEVMEM, GS_EHIP. On error *out is NULL. */
 int gs_build_graph(gs_ctx *ctx, const double *xyz, int64_t n, const double *weights,
                    const gs_graph_params *p, gs_graph **out);
+/* Size, degree and pair statistics of a graph. The pair histogram and the
+ * squared-degree sum are computed on the first call (one pass over the CSR)
+ * and cached. */
 int gs_graph_info(const gs_graph *g, gs_graph_stats *out);
 /* Host copies of the forward CSR in label order and the label -> original
  * index permutation: row_ptr u64[n+1], col u32[n_edges], bin u8[n_edges],

@@ -129,10 +129,7 @@ struct EdgeArgs {
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
     __shared__ double t[256];
-    __shared__ unsigned int ph[256];
     for (int k = threadIdx.x; k <= a.nb; k += blockDim.x) t[k] = a.thr[k];
-    if (FILL)
-        for (int k = threadIdx.x; k < 256; k += blockDim.x) ph[k] = 0;
     __syncthreads();
     uint32_t l = a.l0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (l < a.l1) {
@@ -168,11 +165,8 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
                 double q = sq_len(dx, dy, dz);
                 if (q >= t0 && q < tn) {
                     if (FILL && cnt < cap) {
-                        int b = bin_of(t, a.nb, q);
                         a.col[out + cnt] = (uint32_t)j;
-                        a.bin[out + cnt] = (uint8_t)b;
-                        atomicAdd(&ph[b], 1u);
-                        atomicAdd(&a.indeg[j], 1u);
+                        a.bin[out + cnt] = (uint8_t)bin_of(t, a.nb, q);
                     }
                     ++cnt;
                 }
@@ -186,15 +180,42 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
                     if (id <= c) continue;
                     visit(a.cstart[id], a.cstart[id + 1]);
                 }
-        if (!FILL) {
-            a.deg[l] = cnt;
-            atomicMax(a.maxdeg, cnt);
+        if (!FILL) a.deg[l] = cnt;
+    }
+    if (!FILL) {
+        // one atomic per wave for the largest forward degree
+        uint32_t m = (l < a.l1) ? a.deg[l] : 0u;
+        for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+        if ((threadIdx.x & 63) == 0) atomicMax(a.maxdeg, m);
+    }
+}
+
+// Graph statistics outside the build: in-degrees (for the full degrees) and
+// the undirected pair count per bin, over rows [l0, l1) whose entries start
+// at obase in col / bin.
+__global__ __launch_bounds__(kBlock) void k_stats(const uint64_t *__restrict__ rp,
+                                                  const uint32_t *__restrict__ col,
+                                                  const uint8_t *__restrict__ bin, uint32_t l0,
+                                                  uint32_t l1, uint64_t obase, int nb,
+                                                  uint32_t *__restrict__ indeg,
+                                                  unsigned long long *__restrict__ pair_hist) {
+    constexpr int kCopies = 8;
+    __shared__ unsigned int ph[kCopies][256];
+    for (int k = threadIdx.x; k < kCopies * 256; k += blockDim.x) (&ph[0][0])[k] = 0;
+    __syncthreads();
+    const uint32_t l = l0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < l1) {
+        unsigned int *mine = ph[threadIdx.x % kCopies];
+        for (uint64_t e = rp[l] - obase; e < rp[l + 1] - obase; ++e) {
+            atomicAdd(&indeg[col[e]], 1u);
+            atomicAdd(&mine[bin[e]], 1u);
         }
     }
-    if (FILL) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < a.nb; k += blockDim.x)
-            if (ph[k]) atomicAdd(&a.pair_hist[k], (unsigned long long)ph[k]);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        unsigned long long v = 0;
+        for (int c = 0; c < kCopies; ++c) v += ph[c][k];
+        if (v) atomicAdd(&pair_hist[k], v);
     }
 }
 
@@ -471,13 +492,7 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok) {
     }
     if (W > 1 && (uint64_t)W > (uint64_t)n) W = (int)std::max<uint32_t>(1, n);
 
-    DevBuf ph(sizeof(uint64_t) * 256), indeg(sizeof(uint32_t) * n), sq(8);
-    k_fill_u64<<<1, 256, 0, s>>>(ph.as<uint64_t>(), 256, 0);
-    k_fill_u32<<<grid_for(n), kBlock, 0, s>>>(indeg.as<uint32_t>(), n, 0);
-    k_fill_u64<<<1, 1, 0, s>>>(sq.as<uint64_t>(), 1, 0);
     ea.rp = g.row_ptr.as<uint64_t>();
-    ea.pair_hist = (unsigned long long *)ph.as<uint64_t>();
-    ea.indeg = indeg.as<uint32_t>();
     if (W == 1) {
         g.col.alloc(sizeof(uint32_t) * (E ? E : 1));
         g.bin.alloc(E ? E : 1);
@@ -522,20 +537,64 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok) {
         }
     }
     g.n_windows = W;
-    k_sum_sq_deg<<<grid_for(n), kBlock, 0, s>>>(g.row_ptr.as<uint64_t>(), indeg.as<uint32_t>(), n,
-                                                (unsigned long long *)sq.as<uint64_t>());
     GS_HIP(hipGetLastError());
-    uint64_t hph[256];
-    GS_HIP(hipMemcpyAsync(hph, ph.p, sizeof hph, hipMemcpyDeviceToHost, s));
-    GS_HIP(hipMemcpyAsync(&g.sum_sq_deg, sq.p, 8, hipMemcpyDeviceToHost, s));
     GS_HIP(hipEventRecord(ctx.ev[1], s));
     GS_HIP(hipStreamSynchronize(s));
-    for (int k = 0; k < 255; ++k) g.pair_hist[k] = k < g.nbins ? hph[k] : 0;
     float ms = 0;
     GS_HIP(hipEventElapsedTime(&ms, ctx.ev[0], ctx.ev[1]));
     ctx.t.build_ms = job.begin_ms + ms;
     g.device_bytes = g.row_ptr.bytes + g.col.bytes + g.bin.bytes + g.perm.bytes + g.coords.bytes +
                      g.weights.bytes;
+}
+
+// Pair histogram and sum of squared full degrees, computed once on demand
+// (they are reported, not needed by the counts).
+void graph_stats(Graph &g) {
+    if (g.stats_ready) return;
+    const uint32_t n = (uint32_t)g.n;
+    std::fill(g.pair_hist, g.pair_hist + 255, 0ull);
+    g.sum_sq_deg = 0;
+    if (n == 0) {
+        g.stats_ready = true;
+        return;
+    }
+    hipStream_t s = nullptr;
+    GS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
+    } guard{s};
+    DevBuf ph(sizeof(uint64_t) * 256), indeg(sizeof(uint32_t) * n), sq(8);
+    k_fill_u64<<<1, 256, 0, s>>>(ph.as<uint64_t>(), 256, 0);
+    k_fill_u32<<<grid_for(n), kBlock, 0, s>>>(indeg.as<uint32_t>(), n, 0);
+    k_fill_u64<<<1, 1, 0, s>>>(sq.as<uint64_t>(), 1, 0);
+    const uint64_t *rp = g.row_ptr.as<uint64_t>();
+    unsigned long long *hp = (unsigned long long *)ph.as<uint64_t>();
+    if (g.n_windows == 1) {
+        k_stats<<<grid_for(n), kBlock, 0, s>>>(rp, g.col.as<uint32_t>(), g.bin.as<uint8_t>(), 0, n, 0,
+                                               g.nbins, indeg.as<uint32_t>(), hp);
+    } else {
+        uint64_t maxE = 1;
+        for (int w = 0; w < g.n_windows; ++w) maxE = std::max<uint64_t>(maxE, g.win_edge[w + 1] - g.win_edge[w]);
+        DevBuf wc(maxE * 4), wb(maxE);
+        for (int w = 0; w < g.n_windows; ++w) {
+            const uint64_t e0 = g.win_edge[w], ne = g.win_edge[w + 1] - e0;
+            GS_HIP(hipMemcpyAsync(wc.p, g.hcol.as<uint32_t>() + e0, ne * 4, hipMemcpyHostToDevice, s));
+            GS_HIP(hipMemcpyAsync(wb.p, g.hbin.as<uint8_t>() + e0, ne, hipMemcpyHostToDevice, s));
+            const uint32_t l0 = (uint32_t)g.win[w], l1 = (uint32_t)g.win[w + 1];
+            k_stats<<<grid_for(l1 - l0), kBlock, 0, s>>>(rp, wc.as<uint32_t>(), wb.as<uint8_t>(), l0, l1, e0,
+                                                         g.nbins, indeg.as<uint32_t>(), hp);
+            GS_HIP(hipStreamSynchronize(s));
+        }
+    }
+    k_sum_sq_deg<<<grid_for(n), kBlock, 0, s>>>(rp, indeg.as<uint32_t>(), n, (unsigned long long *)sq.as<uint64_t>());
+    GS_HIP(hipGetLastError());
+    uint64_t hph[256];
+    GS_HIP(hipMemcpyAsync(hph, ph.p, sizeof hph, hipMemcpyDeviceToHost, s));
+    GS_HIP(hipMemcpyAsync(&g.sum_sq_deg, sq.p, 8, hipMemcpyDeviceToHost, s));
+    GS_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < 255; ++k) g.pair_hist[k] = k < g.nbins ? hph[k] : 0;
+    g.stats_ready = true;
 }
 
 void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {

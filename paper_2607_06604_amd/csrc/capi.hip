@@ -187,7 +187,13 @@ int gs_build_graph(gs_ctx *ctx, const double *xyz, int64_t n, const double *weig
 
 int gs_graph_info(const gs_graph *g, gs_graph_stats *out) {
     if (!g || !out) return GS_EINVAL;
+    int rc = guarded([&] {
+        GS_HIP(hipSetDevice(g->device));
+        graph_stats(*const_cast<gs_graph *>(g));
+    });
+    if (rc != GS_OK) return rc;
     memset(out, 0, sizeof *out);
+    out->sum_sq_degree = g->sum_sq_deg;
     out->n = g->n;
     out->n_edges = g->n_edges;
     out->max_deg = g->max_deg;
@@ -293,8 +299,12 @@ int gs_count_3pcf_batch(gs_ctx *ctx, const gs_graph *const *graphs, int ng, uint
         ctx->t.kernel_ms = ms;
         ctx->t.kernel_launches = 1;
         uint64_t sq = 0;
-        for (int g = 0; g < ng; ++g) sq += gs[g]->sum_sq_deg;
-        ctx->t.alg_bytes = (uint64_t)(2.5 * (double)sq);
+        bool known = true;
+        for (int g = 0; g < ng; ++g) {
+            sq += gs[g]->sum_sq_deg;
+            known = known && gs[g]->stats_ready;
+        }
+        ctx->t.alg_bytes = known ? (uint64_t)(2.5 * (double)sq) : 0;
     });
 }
 

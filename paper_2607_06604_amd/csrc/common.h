@@ -138,6 +138,7 @@ struct Graph {
     Bins bins;
     uint64_t pair_hist[255] = {};
     uint64_t sum_sq_deg = 0;  // sum over points of (full degree)^2
+    bool stats_ready = false; // pair_hist and sum_sq_deg computed (graph_stats)
     uint64_t device_bytes = 0;
     int n_windows = 1;
     // host-tiled graphs (n_windows > 1): the forward CSR lives in pinned host
@@ -212,6 +213,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
 void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_t *neg,
                 uint64_t *ncl, const gs_anchor_range *anchors);
 void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w);
+void graph_stats(Graph &g);
 void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJob &job);
 uint64_t build_footprint(const Graph &g, const BuildJob &job);
 void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok);

@@ -57,6 +57,8 @@ struct C3Args {
     const uint8_t *mark;    // anchored: hubs that can own an anchored triangle (nullable)
     int nb, nconf, log2h;
     int trunc;              // cut spoke rows at the hub row's largest label
+    int packed;             // hash entries hold (label << 8 | bin): labels < 2^24 - 1
+    int lut;                // configuration index from an LDS table of nb^3 entries
     uint32_t maxdeg;
     uint32_t anchor_lo, anchor_hi;
     double wmul;            // 2^wscale
@@ -67,13 +69,21 @@ struct C3Args {
     unsigned long long *ntri;   // 1
 };
 
+constexpr int kUnroll3 = 4;     // candidates per lane per pass
+constexpr int kLutMaxBins = 16; // nb^3 u16 table up to 8 KB
+
+struct TrueT { static constexpr bool value = true; };
+struct FalseT { static constexpr bool value = false; };
+
 // LDS layout of one work group (byte offsets).
 struct Layout3 {
-    uint32_t hkey, hbin, hslot, mstart, mpref, mbin, mw, mperm, hist, wlo, whi, tab, wtot, misc, total;
+    uint32_t hkey, hbin, hslot, mstart, mpref, mbin, mw, mperm, hist, wlo, whi, tab, wtot, misc, lut,
+        total;
 };
 
 __host__ __device__ inline Layout3 layout3(int block, uint32_t H, uint32_t maxdeg, int nconf, int nb,
-                                           bool weighted, bool anchored, bool lds_hist) {
+                                           bool weighted, bool anchored, bool lds_hist, bool packed,
+                                           bool lut) {
     if (!lds_hist) nconf = 0;
     Layout3 L{};
     uint32_t o = 0;
@@ -89,7 +99,8 @@ __host__ __device__ inline Layout3 layout3(int block, uint32_t H, uint32_t maxde
     L.wtot = o;   o = lds_align(o + 4 * (block / 64 + 1), 16);
     L.misc = o;   o = lds_align(o + 16, 16);
     L.hslot = o;  o = lds_align(o + 2 * (maxdeg + 1), 16);
-    L.hbin = o;   o = lds_align(o + H, 16);
+    L.lut = o;    if (lut) o = lds_align(o + 2 * nb * nb * nb, 16);
+    L.hbin = o;   if (!packed) o = lds_align(o + H, 16);
     L.mbin = o;   o = lds_align(o + block, 16);
     L.total = o;
     return L;
@@ -156,7 +167,8 @@ template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const uint32_t H = 1u << a.log2h, mask = H - 1;
-    const Layout3 L = layout3(BLOCK, H, a.maxdeg, a.nconf, a.nb, WEIGHTED, ANCHORED, LDS_HIST);
+    const Layout3 L = layout3(BLOCK, H, a.maxdeg, a.nconf, a.nb, WEIGHTED, ANCHORED, LDS_HIST, a.packed, a.lut);
+    uint16_t *lut = (uint16_t *)(sm + L.lut);
     uint32_t *hkey = (uint32_t *)(sm + L.hkey);
     uint8_t *hbin = (uint8_t *)(sm + L.hbin);
     uint16_t *hslot = (uint16_t *)(sm + L.hslot);
@@ -185,6 +197,12 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
         ta[b] = rank_a(a.nb, b);
         tb[b] = rank_b(a.nb, b);
     }
+    if (a.lut)
+        for (int t = tid; t < a.nb * a.nb * a.nb; t += BLOCK) {
+            const int x = t / (a.nb * a.nb), y = (t / a.nb) % a.nb, z = t % a.nb;
+            const int lo = min(x, min(y, z)), hi = max(x, max(y, z)), mid = x + y + z - lo - hi;
+            lut[t] = (uint16_t)(rank_a(a.nb, lo) + rank_b(a.nb, mid) + hi);
+        }
     if (tid == 0) *s_cnt = 0;
     __syncthreads();
 
@@ -255,12 +273,14 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
         if (WEIGHTED) wi = a.w[i];
         if (ANCHORED) pi = a.perm[i];
 
-        // stage N+(i): label -> bin of (i, k)
+        // stage N+(i): label -> bin of (i, k); packed as (label << 8 | bin)
+        // when labels fit 24 bits, else label and bin in separate arrays
         for (uint32_t e = tid; e < d; e += BLOCK) {
             const uint32_t k = hcol[beg + e];
+            const uint32_t v = a.packed ? ((k << 8) | hbinp[beg + e]) : k;
             uint32_t s = label_hash(k, a.log2h);
-            while (atomicCAS(&hkey[s], kEmptyKey, k) != kEmptyKey) s = (s + 1) & mask;
-            hbin[s] = hbinp[beg + e];
+            while (atomicCAS(&hkey[s], kEmptyKey, v) != kEmptyKey) s = (s + 1) & mask;
+            if (!a.packed) hbin[s] = hbinp[beg + e];
             hslot[e] = (uint16_t)s;
         }
         __syncthreads();
@@ -303,48 +323,93 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             acc += total;
             __syncthreads();
 
-            uint32_t sp = 0;
-            for (uint32_t e0 = 0; e0 < total; e0 += BLOCK) {
-                const uint32_t e = e0 + tid;
-                if (e < total) {
-                    while (mpref[sp + 1] <= e) ++sp;
-                    const uint64_t pos = mstart[sp] + (e - mpref[sp]);
-                    const uint32_t k = scol[pos];
-                    uint32_t h = label_hash(k, a.log2h);
-                    uint32_t key;
-                    while ((key = hkey[h]) != k && key != kEmptyKey) h = (h + 1) & mask;
-                    if (key == k) {
-                        bool take = true;
-                        if (ANCHORED) {
-                            uint32_t m = min(pi, min(mperm[sp], a.perm[k]));
-                            take = m >= a.anchor_lo && m < a.anchor_hi;
+            // U candidates per lane per pass, their loads issued back to back
+            auto probe_flat = [&](auto pack_tag, auto lut_tag) {
+                constexpr bool PACK = decltype(pack_tag)::value;
+                constexpr bool LUT = decltype(lut_tag)::value;
+                constexpr int U = kUnroll3;
+                uint32_t sp = 0;
+                for (uint32_t e0 = 0; e0 < total; e0 += U * BLOCK) {
+                    uint32_t kk[U], spk[U], key[U], hh[U];
+                    uint8_t bz[U];
+                    bool ok[U];
+                    uint64_t posk[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        uint32_t e = e0 + u * BLOCK + tid;
+                        ok[u] = e < total;
+                        if (!ok[u]) e = total - 1;  // in-bounds stand-in, result dropped
+                        while (mpref[sp + 1] <= e) ++sp;
+                        spk[u] = sp;
+                        posk[u] = mstart[sp] + (e - mpref[sp]);
+                        kk[u] = scol[posk[u]];
+                        bz[u] = sbinp[posk[u]];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        hh[u] = label_hash(kk[u], a.log2h);
+                        key[u] = hkey[hh[u]];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        bool hit;
+                        if (PACK) {
+                            while (key[u] != kEmptyKey && (key[u] >> 8) != kk[u]) {
+                                hh[u] = (hh[u] + 1) & mask;
+                                key[u] = hkey[hh[u]];
+                            }
+                            hit = key[u] != kEmptyKey;
+                        } else {
+                            while (key[u] != kk[u] && key[u] != kEmptyKey) {
+                                hh[u] = (hh[u] + 1) & mask;
+                                key[u] = hkey[hh[u]];
+                            }
+                            hit = key[u] == kk[u];
                         }
-                        if (take) {
-                            const int x = mbin[sp], y = hbin[h], z = sbinp[pos];
+                        if (!(hit && ok[u])) continue;
+                        const uint32_t k = kk[u];
+                        const int sidx2 = spk[u];
+                        if (ANCHORED) {
+                            const uint32_t m = min(pi, min(mperm[sidx2], a.perm[k]));
+                            if (m < a.anchor_lo || m >= a.anchor_hi) continue;
+                        }
+                        const int x = mbin[sidx2];
+                        const int y = PACK ? (int)(key[u] & 0xFFu) : (int)hbin[hh[u]];
+                        const int z = bz[u];
+                        int idx;
+                        if (LUT) {
+                            idx = lut[(x * a.nb + y) * a.nb + z];
+                        } else {
                             const int lo = min(x, min(y, z)), hi = max(x, max(y, z));
                             const int mid = x + y + z - lo - hi;
-                            const int idx = ta[lo] + tb[mid] + hi;
-                            if (LDS_HIST) atomicAdd(&hist[idx], 1u);
-                            else atomicAdd(&hout[idx], 1ull);
-                            ++mytri;
-                            if (WEIGHTED) {
-                                double p = wi, q = mw[sp], r = a.w[k], t;
-                                if (p > q) { t = p; p = q; q = t; }
-                                if (q > r) { t = q; q = r; r = t; }
-                                if (p > q) { t = p; p = q; q = t; }
-                                const double prod = __dmul_rn(__dmul_rn(p, q), r);
-                                const unsigned long long ti =
-                                    (unsigned long long)__dmul_rn(prod, a.wmul);
-                                if (LDS_HIST) {
-                                    atomicAdd(&wlo[idx], ti & 0xFFFFFFFFull);
-                                    atomicAdd(&whi[idx], ti >> 32);
-                                } else {
-                                    add128(&a.wsum[2 * idx], (unsigned __int128)ti);
-                                }
+                            idx = ta[lo] + tb[mid] + hi;
+                        }
+                        if (LDS_HIST) atomicAdd(&hist[idx], 1u);
+                        else atomicAdd(&hout[idx], 1ull);
+                        ++mytri;
+                        if (WEIGHTED) {
+                            double p = wi, q = mw[sidx2], r = a.w[k], t;
+                            if (p > q) { t = p; p = q; q = t; }
+                            if (q > r) { t = q; q = r; r = t; }
+                            if (p > q) { t = p; p = q; q = t; }
+                            const double prod = __dmul_rn(__dmul_rn(p, q), r);
+                            const unsigned long long ti = (unsigned long long)__dmul_rn(prod, a.wmul);
+                            if (LDS_HIST) {
+                                atomicAdd(&wlo[idx], ti & 0xFFFFFFFFull);
+                                atomicAdd(&whi[idx], ti >> 32);
+                            } else {
+                                add128(&a.wsum[2 * idx], (unsigned __int128)ti);
                             }
                         }
                     }
                 }
+            };
+            if (a.packed) {
+                if (a.lut) probe_flat(TrueT{}, TrueT{});
+                else probe_flat(TrueT{}, FalseT{});
+            } else {
+                if (a.lut) probe_flat(FalseT{}, TrueT{});
+                else probe_flat(FalseT{}, FalseT{});
             }
             __syncthreads();
         }
@@ -397,6 +462,8 @@ void launch3_b(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds, bool w, b
 struct Plan3 {
     int block = 256;
     int trunc = 0;
+    bool packed = true;
+    bool lut = true;
     int log2h = 6;
     bool lds_hist = true;
     uint32_t lds = 0;
@@ -409,8 +476,10 @@ void launch3_any(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P, bool 
 
 // Work-group size and LDS plan: hash table at load factor <= 0.7, 512
 // threads per hub for long rows (more waves per CU when LDS limits groups).
-Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchored) {
+Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchored, uint64_t max_n) {
     Plan3 p;
+    p.packed = max_n < (1ull << 24) - 1;
+    p.lut = nb <= kLutMaxBins;
     const int nconf = (int)n_configs(nb);
     if (maxdeg > 16384) fail(GS_EUNSUPPORTED, "forward degree above 16384");
     if (const char *eb = getenv("GS_BLOCK3")) p.block = atoi(eb) == 512 ? 512 : 256;
@@ -422,10 +491,10 @@ Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchore
     while ((uint64_t)H * 7 < (uint64_t)maxdeg * 10) { H <<= 1; ++p.log2h; }
     // per-work-group LDS histograms while they fit; global atomics beyond
     p.lds_hist = nconf <= 8192;
-    Layout3 L = layout3(p.block, H, maxdeg, nconf, nb, weighted, anchored, p.lds_hist);
+    Layout3 L = layout3(p.block, H, maxdeg, nconf, nb, weighted, anchored, p.lds_hist, p.packed, p.lut);
     if ((int)L.total > ctx.max_lds && p.lds_hist) {
         p.lds_hist = false;
-        L = layout3(p.block, H, maxdeg, nconf, nb, weighted, anchored, false);
+        L = layout3(p.block, H, maxdeg, nconf, nb, weighted, anchored, false, p.packed, p.lut);
     }
     if ((int)L.total > ctx.max_lds) fail(GS_EUNSUPPORTED, "LDS footprint too large for this degree");
     p.lds = L.total;
@@ -482,7 +551,9 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     }
     if (nvirt >= 0xFFFFFFFFull) fail(GS_EUNSUPPORTED, "batch holds 2^32 or more points");
     const int nconf = (int)n_configs(nb);
-    const Plan3 P = plan3(ctx, maxdeg, nb, false, false);
+    uint64_t max_n = 0;
+    for (int g = 0; g < ng; ++g) max_n = std::max<uint64_t>(max_n, (uint64_t)gs[g]->n);
+    const Plan3 P = plan3(ctx, maxdeg, nb, false, false, max_n);
     b.ng = ng;
     b.nconf = nconf;
     const size_t per = (size_t)nconf + 1;
@@ -514,6 +585,8 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     a.nconf = nconf;
     a.log2h = P.log2h;
     a.trunc = P.trunc;
+    a.packed = P.packed;
+    a.lut = P.lut;
     a.maxdeg = maxdeg;
     a.flush_limit = flush_limit_for(maxdeg, P.block);
     a.queue = (uint32_t *)(dv + (size_t)ng * per);
@@ -535,7 +608,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     const bool anchored = anchors != nullptr;
     if (anchored && (anchors->lo > anchors->hi)) fail(GS_EINVAL, "anchor range lo > hi");
     const uint32_t maxdeg = g.max_deg;
-    const Plan3 P = plan3(ctx, maxdeg, nb, weighted, anchored);
+    const Plan3 P = plan3(ctx, maxdeg, nb, weighted, anchored, (uint64_t)g.n);
     const int W = g.n_windows;
     const int ntiles = W * (W + 1) / 2;
 
@@ -551,6 +624,8 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.nconf = nconf;
     a.log2h = P.log2h;
     a.trunc = P.trunc;
+    a.packed = P.packed;
+    a.lut = P.lut;
     a.maxdeg = maxdeg;
     a.anchor_lo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
     a.anchor_hi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;
@@ -683,7 +758,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     ctx.t.kernel_launches = g.n > 0 ? (uint64_t)ntiles : 0;
     // merge-walk bytes: each hub-spoke step reads both forward half-lists,
     // 5 bytes per entry: 2.5 B x sum_i m_i^2 over full degrees m_i
-    ctx.t.alg_bytes = (uint64_t)(2.5 * (double)g.sum_sq_deg);
+    ctx.t.alg_bytes = g.stats_ready ? (uint64_t)(2.5 * (double)g.sum_sq_deg) : 0;
 }
 
 }  // namespace gsn

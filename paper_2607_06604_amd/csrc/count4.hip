@@ -437,7 +437,7 @@ void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_
     ctx.t.count_ms = ms;
     ctx.t.kernel_ms = kms;
     ctx.t.kernel_launches = g.n > 0 ? 1 : 0;
-    ctx.t.alg_bytes = (uint64_t)(2.5 * (double)g.sum_sq_deg);
+    ctx.t.alg_bytes = g.stats_ready ? (uint64_t)(2.5 * (double)g.sum_sq_deg) : 0;
 }
 
 }  // namespace gsn

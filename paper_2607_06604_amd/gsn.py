@@ -55,7 +55,8 @@ class AnchorRange(ctypes.Structure):
 class GraphStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_edges", ctypes.c_uint64), ("max_deg", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_uint64), ("n_windows", ctypes.c_int32),
-                ("nbins", ctypes.c_int32), ("pair_hist", ctypes.c_uint64 * 255)]
+                ("nbins", ctypes.c_int32), ("pair_hist", ctypes.c_uint64 * 255),
+                ("sum_sq_degree", ctypes.c_uint64)]
 
 
 class Timings(ctypes.Structure):

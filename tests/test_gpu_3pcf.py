@@ -103,6 +103,7 @@ def test_graph_edges_and_bins_match_oracle(ctx, case):
     assert info.n_edges == len(ko)
     assert list(info.pair_hist[:nb]) == np.bincount(bo, minlength=nb).tolist()
     assert info.max_deg == int(np.diff(rp.astype(np.int64)).max(initial=0))
+    assert info.sum_sq_degree == int((np.diff(orp).astype(np.int64) ** 2).sum())
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
