@@ -22,6 +22,7 @@
 // XCD's L2, and moves on to the other queues once its own is empty.
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 
 #include "kern_util.h"
 
@@ -58,6 +59,7 @@ struct C3Args {
     int nb, nconf, log2h;
     int trunc;              // cut spoke rows at the hub row's largest label
     int packed;             // hash entries hold (label << 8 | bin): labels < 2^24 - 1
+    int glog;               // > 0: spoke rows walked by groups of 2^glog lanes
     int lut;                // configuration index from an LDS table of nb^3 entries
     uint32_t maxdeg;
     uint32_t anchor_lo, anchor_hi;
@@ -77,8 +79,8 @@ struct FalseT { static constexpr bool value = false; };
 
 // LDS layout of one work group (byte offsets).
 struct Layout3 {
-    uint32_t hkey, hbin, hslot, mstart, mpref, mbin, mw, mperm, hist, wlo, whi, tab, wtot, misc, lut,
-        total;
+    uint32_t hkey, hbin, hslot, mstart, mpref, mbin, mw, mperm, hist, wlo, whi, tab, wtot, wflag, misc,
+        lut, total;
 };
 
 __host__ __device__ inline Layout3 layout3(int block, uint32_t H, uint32_t maxdeg, int nconf, int nb,
@@ -96,7 +98,8 @@ __host__ __device__ inline Layout3 layout3(int block, uint32_t H, uint32_t maxde
     L.mperm = o;  if (anchored) o = lds_align(o + 4 * block, 16);
     L.hist = o;   o = lds_align(o + 4 * nconf, 16);
     L.tab = o;    o = lds_align(o + 8 * (nb + 1), 16);
-    L.wtot = o;   o = lds_align(o + 4 * (block / 64 + 1), 16);
+    L.wtot = o;   o = lds_align(o + 8 * (block / 64 + 1), 16);
+    L.wflag = o;  o = lds_align(o + 4 * block, 16);
     L.misc = o;   o = lds_align(o + 16, 16);
     L.hslot = o;  o = lds_align(o + 2 * (maxdeg + 1), 16);
     L.lut = o;    if (lut) o = lds_align(o + 2 * nb * nb * nb, 16);
@@ -163,6 +166,259 @@ __device__ __forceinline__ int graph_of(const GDesc *gd, int ng, uint32_t v) {
     return lo;
 }
 
+// Everything the candidate walk of one spoke chunk reads or updates.
+struct Probe {
+    const uint32_t *mpref;        // flat start of each compact spoke, [ncomp] = total
+    const unsigned long long *mstart;  // row offset of each compact spoke in scol / sbin
+    const uint8_t *mbin;          // bin of edge (hub, spoke)
+    const double *mw;             // spoke weights
+    const uint32_t *mperm;        // spoke original indices
+    uint32_t *wflag;              // this wave's 64 LDS tags
+    const uint32_t *hkey;         // hub hash
+    const uint8_t *hbin;          // hub bins (unpacked hash)
+    const uint16_t *lut;          // nb^3 configuration table
+    const int *ta, *tb;           // rank tables
+    uint32_t *hist;               // LDS counters (LDS_HIST)
+    unsigned long long *hout;     // global counters (otherwise)
+    unsigned long long *wlo, *whi, *wsum;
+    const uint32_t *scol;
+    const uint8_t *sbin;
+    uint32_t mask, ncomp;
+    int log2h, nb;
+    double wi, wmul;
+    const double *w;
+    uint32_t pi;
+    const uint32_t *perm;
+    uint32_t anchor_lo, anchor_hi;
+    int glog;                     // lanes per spoke group = 1 << glog (group walk)
+};
+
+// One candidate: probe the hub hash, bin and count a hit.
+template <bool PACK, bool LUT, bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
+__device__ __forceinline__ void probe_one(const Probe &c, uint32_t k, uint32_t key, uint32_t hh, int s2,
+                                          int z, unsigned long long &mytri) {
+    const bool more = PACK ? (key != kEmptyKey && (key >> 8) != k) : (key != k && key != kEmptyKey);
+    if (more) {
+        do {
+            hh = (hh + 1) & c.mask;
+            key = c.hkey[hh];
+        } while (PACK ? (key != kEmptyKey && (key >> 8) != k) : (key != k && key != kEmptyKey));
+    }
+    const bool hit = PACK ? key != kEmptyKey : key == k;
+    if (!hit) return;
+    if (ANCHORED) {
+        const uint32_t mm = min(c.pi, min(c.mperm[s2], c.perm[k]));
+        if (mm < c.anchor_lo || mm >= c.anchor_hi) return;
+    }
+    const int x = c.mbin[s2];
+    const int y = PACK ? (int)(key & 0xFFu) : (int)c.hbin[hh];
+    int idx;
+    if (LUT) {
+        idx = c.lut[(x * c.nb + y) * c.nb + z];
+    } else {
+        const int lo = min(x, min(y, z)), hi = max(x, max(y, z));
+        const int mid = x + y + z - lo - hi;
+        idx = c.ta[lo] + c.tb[mid] + hi;
+    }
+    if (LDS_HIST) atomicAdd(&c.hist[idx], 1u);
+    else atomicAdd(&c.hout[idx], 1ull);
+    ++mytri;
+    if (WEIGHTED) {
+        double p = c.wi, q = c.mw[s2], r = c.w[k], t;
+        if (p > q) { t = p; p = q; q = t; }
+        if (q > r) { t = q; q = r; r = t; }
+        if (p > q) { t = p; p = q; q = t; }
+        const double prod = __dmul_rn(__dmul_rn(p, q), r);
+        const unsigned long long ti = (unsigned long long)__dmul_rn(prod, c.wmul);
+        if (LDS_HIST) {
+            atomicAdd(&c.wlo[idx], ti & 0xFFFFFFFFull);
+            atomicAdd(&c.whi[idx], ti >> 32);
+        } else {
+            add128(&c.wsum[2 * idx], (unsigned __int128)ti);
+        }
+    }
+}
+
+// Spokes sfirst, sfirst + sstep, ... of a chunk, walked by groups of
+// 2^glog lanes: group g of the wave takes every G-th of those spokes and
+// reads its row 2^glog candidates at a time, U steps per pass with the loads
+// of a pass issued back to back. Rows are padded to whole steps.
+template <bool PACK, bool LUT, bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
+__device__ __forceinline__ void probe_groups(const Probe &c, uint32_t sfirst, uint32_t sstep,
+                                             unsigned long long &mytri) {
+    constexpr int U = kUnroll3;
+    const uint32_t lane = threadIdx.x & 63;
+    const int glog = c.glog;
+    const uint32_t S = 1u << glog, G = 64u >> glog;
+    const uint32_t sub = lane & (S - 1), gi = lane >> glog;
+    const uint32_t ncomp = c.ncomp;
+    uint32_t s = sfirst + gi * sstep;         // this group's spoke
+    const uint32_t gstep = G * sstep;
+    uint32_t off = 0, len = 0;
+    uint64_t base = 0;
+    if (s < ncomp) {
+        len = c.mpref[s + 1] - c.mpref[s];
+        base = c.mstart[s];
+    }
+    while (true) {
+        uint32_t kk[U], key[U], hh[U], sp[U];
+        uint8_t bz[U];
+        bool ok[U];
+        bool any = false;  // this lane has a candidate in this pass
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (off >= len && s < ncomp) {  // next spoke of this group
+                s += gstep;
+                off = 0;
+                len = 0;
+                if (s < ncomp) {
+                    len = c.mpref[s + 1] - c.mpref[s];
+                    base = c.mstart[s];
+                }
+            }
+            const uint32_t e = off + sub;
+            ok[u] = s < ncomp && e < len;
+            sp[u] = ok[u] ? s : 0;
+            const uint64_t pos = ok[u] ? base + e : c.mstart[0];  // in-bounds stand-in
+            kk[u] = c.scol[pos];
+            bz[u] = c.sbin[pos];
+            off += S;
+            any |= ok[u];
+        }
+        if (!__any(any)) break;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            hh[u] = label_hash(kk[u], c.log2h);
+            key[u] = c.hkey[hh[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (ok[u]) probe_one<PACK, LUT, WEIGHTED, ANCHORED, LDS_HIST>(c, kk[u], key[u], hh[u], sp[u], bz[u], mytri);
+    }
+}
+
+template <bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
+__device__ __forceinline__ void probe_groups_any(bool packed, bool lut, const Probe &c, uint32_t sfirst,
+                                                 uint32_t sstep, unsigned long long &mytri) {
+    if (packed) {
+        if (lut) probe_groups<true, true, WEIGHTED, ANCHORED, LDS_HIST>(c, sfirst, sstep, mytri);
+        else probe_groups<true, false, WEIGHTED, ANCHORED, LDS_HIST>(c, sfirst, sstep, mytri);
+    } else {
+        if (lut) probe_groups<false, true, WEIGHTED, ANCHORED, LDS_HIST>(c, sfirst, sstep, mytri);
+        else probe_groups<false, false, WEIGHTED, ANCHORED, LDS_HIST>(c, sfirst, sstep, mytri);
+    }
+}
+
+// Candidates [r0, r1) of the flat range of a spoke chunk, walked by one
+// wavefront in windows of 64, U windows per pass with their loads issued back
+// to back. The spokes starting inside a window tag their start positions in
+// the wave's LDS flags; a ballot of the tags and a count of the tagged lanes
+// below give every lane its spoke without a search.
+template <bool PACK, bool LUT, bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
+__device__ __forceinline__ void probe_range(const Probe &c, uint32_t r0, uint32_t r1,
+                                            unsigned long long &mytri) {
+    constexpr int U = kUnroll3;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t ncomp = c.ncomp;
+    c.wflag[lane] = 0;  // tags of earlier chunks must not match this one's
+    wave_lds_sync();
+    uint32_t base = upper_index(c.mpref, ncomp, r0);  // spoke holding r0
+    for (uint32_t w0 = r0; w0 < r1; w0 += U * 64) {
+        uint32_t kk[U], spk[U], key[U], hh[U];
+        uint8_t bz[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t e0 = w0 + u * 64;
+            const uint32_t cs = base + 1 + lane;
+            const uint32_t p = cs < ncomp ? c.mpref[cs] - e0 : 0xFFFFFFFFu;
+            if (p < 64) c.wflag[p] = e0 + 1;
+            wave_lds_sync();
+            const bool f = lane > 0 && c.wflag[lane] == e0 + 1;
+            const uint64_t m = __ballot(f);
+            const uint64_t at64 = __ballot(p == 64);
+            const uint32_t sp = base + lanes_below(m) + (f ? 1u : 0u);
+            base += (uint32_t)__popcll(m) + (at64 ? 1u : 0u);
+            uint32_t e = e0 + lane;
+            ok[u] = e < r1;
+            const uint32_t sps = min(ok[u] ? sp : base, ncomp - 1);
+            if (!ok[u]) e = c.mpref[sps];  // in-bounds stand-in, result dropped
+            spk[u] = sps;
+            const uint64_t pos = c.mstart[sps] + (e - c.mpref[sps]);
+            kk[u] = c.scol[pos];
+            bz[u] = c.sbin[pos];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            hh[u] = label_hash(kk[u], c.log2h);
+            key[u] = c.hkey[hh[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            // the first probe resolves almost always; chains are rare
+            const bool more = PACK ? (key[u] != kEmptyKey && (key[u] >> 8) != kk[u])
+                                   : (key[u] != kk[u] && key[u] != kEmptyKey);
+            if (more) {
+                uint32_t h = hh[u], kv;
+                do {
+                    h = (h + 1) & c.mask;
+                    kv = c.hkey[h];
+                } while (PACK ? (kv != kEmptyKey && (kv >> 8) != kk[u]) : (kv != kk[u] && kv != kEmptyKey));
+                hh[u] = h;
+                key[u] = kv;
+            }
+            const bool hit = PACK ? key[u] != kEmptyKey : key[u] == kk[u];
+            if (!(hit && ok[u])) continue;
+            const uint32_t k = kk[u];
+            const int s2 = spk[u];
+            if (ANCHORED) {
+                const uint32_t mm = min(c.pi, min(c.mperm[s2], c.perm[k]));
+                if (mm < c.anchor_lo || mm >= c.anchor_hi) continue;
+            }
+            const int x = c.mbin[s2];
+            const int y = PACK ? (int)(key[u] & 0xFFu) : (int)c.hbin[hh[u]];
+            const int z = bz[u];
+            int idx;
+            if (LUT) {
+                idx = c.lut[(x * c.nb + y) * c.nb + z];
+            } else {
+                const int lo = min(x, min(y, z)), hi = max(x, max(y, z));
+                const int mid = x + y + z - lo - hi;
+                idx = c.ta[lo] + c.tb[mid] + hi;
+            }
+            if (LDS_HIST) atomicAdd(&c.hist[idx], 1u);
+            else atomicAdd(&c.hout[idx], 1ull);
+            ++mytri;
+            if (WEIGHTED) {
+                double p = c.wi, q = c.mw[s2], r = c.w[k], t;
+                if (p > q) { t = p; p = q; q = t; }
+                if (q > r) { t = q; q = r; r = t; }
+                if (p > q) { t = p; p = q; q = t; }
+                const double prod = __dmul_rn(__dmul_rn(p, q), r);
+                const unsigned long long ti = (unsigned long long)__dmul_rn(prod, c.wmul);
+                if (LDS_HIST) {
+                    atomicAdd(&c.wlo[idx], ti & 0xFFFFFFFFull);
+                    atomicAdd(&c.whi[idx], ti >> 32);
+                } else {
+                    add128(&c.wsum[2 * idx], (unsigned __int128)ti);
+                }
+            }
+        }
+    }
+}
+
+template <bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
+__device__ __forceinline__ void probe_any(bool packed, bool lut, const Probe &c, uint32_t r0,
+                                          uint32_t r1, unsigned long long &mytri) {
+    if (packed) {
+        if (lut) probe_range<true, true, WEIGHTED, ANCHORED, LDS_HIST>(c, r0, r1, mytri);
+        else probe_range<true, false, WEIGHTED, ANCHORED, LDS_HIST>(c, r0, r1, mytri);
+    } else {
+        if (lut) probe_range<false, true, WEIGHTED, ANCHORED, LDS_HIST>(c, r0, r1, mytri);
+        else probe_range<false, false, WEIGHTED, ANCHORED, LDS_HIST>(c, r0, r1, mytri);
+    }
+}
+
 template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     extern __shared__ __align__(16) unsigned char sm[];
@@ -183,6 +439,8 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     int *ta = (int *)(sm + L.tab);
     int *tb = ta + (a.nb + 1);
     uint32_t *wtot = (uint32_t *)(sm + L.wtot);
+    uint64_t *wtot64 = (uint64_t *)(sm + L.wtot);
+    uint32_t *wflag = (uint32_t *)(sm + L.wflag) + (threadIdx.x & ~63u);  // this wave's 64 tags
     uint32_t *s_hub = (uint32_t *)(sm + L.misc);
     unsigned long long *s_cnt = (unsigned long long *)(sm + L.misc + 8);
     const int tid = threadIdx.x;
@@ -291,6 +549,9 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             const uint32_t sidx = c0 + tid;
             uint32_t len = 0;
             uint64_t st = 0;
+            uint8_t sb = 0;
+            double sw = 0.0;
+            uint32_t spm = 0;
             if (sidx + 1 < d) {
                 const uint32_t j = hcol[beg + sidx];
                 if (j >= s0 && j < s1) {
@@ -306,16 +567,25 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
                         }
                         len = lo;
                     }
-                    mbin[tid] = hbinp[beg + sidx];
-                    if (WEIGHTED) mw[tid] = a.w[j];
-                    if (ANCHORED) mperm[tid] = a.perm[j];
+                    sb = hbinp[beg + sidx];
+                    if (WEIGHTED) sw = a.w[j];
+                    if (ANCHORED) spm = a.perm[j];
                 }
             }
-            uint32_t total;
-            const uint32_t pre = wg_excl_scan<BLOCK>(len, wtot, total);
-            mstart[tid] = st;
-            mpref[tid] = pre;
-            if (tid == 0) mpref[BLOCK] = total;
+            // one scan gives each non-empty spoke its compact index (high
+            // word) and the flat start of its row (low word)
+            uint64_t tot64;
+            const uint64_t pre64 = wg_excl_scan64<BLOCK>(((uint64_t)(len > 0) << 32) | len, wtot64, tot64);
+            const uint32_t total = (uint32_t)tot64, ncomp = (uint32_t)(tot64 >> 32);
+            if (len > 0) {
+                const uint32_t c = (uint32_t)(pre64 >> 32);
+                mstart[c] = st;
+                mpref[c] = (uint32_t)pre64;
+                mbin[c] = sb;
+                if (WEIGHTED) mw[c] = sw;
+                if (ANCHORED) mperm[c] = spm;
+            }
+            if (tid == 0) mpref[ncomp] = total;
             if (acc + total >= a.flush_limit) {
                 flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout);
                 acc = 0;
@@ -323,93 +593,23 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             acc += total;
             __syncthreads();
 
-            // U candidates per lane per pass, their loads issued back to back
-            auto probe_flat = [&](auto pack_tag, auto lut_tag) {
-                constexpr bool PACK = decltype(pack_tag)::value;
-                constexpr bool LUT = decltype(lut_tag)::value;
-                constexpr int U = kUnroll3;
-                uint32_t sp = 0;
-                for (uint32_t e0 = 0; e0 < total; e0 += U * BLOCK) {
-                    uint32_t kk[U], spk[U], key[U], hh[U];
-                    uint8_t bz[U];
-                    bool ok[U];
-                    uint64_t posk[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        uint32_t e = e0 + u * BLOCK + tid;
-                        ok[u] = e < total;
-                        if (!ok[u]) e = total - 1;  // in-bounds stand-in, result dropped
-                        while (mpref[sp + 1] <= e) ++sp;
-                        spk[u] = sp;
-                        posk[u] = mstart[sp] + (e - mpref[sp]);
-                        kk[u] = scol[posk[u]];
-                        bz[u] = sbinp[posk[u]];
-                    }
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        hh[u] = label_hash(kk[u], a.log2h);
-                        key[u] = hkey[hh[u]];
-                    }
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        bool hit;
-                        if (PACK) {
-                            while (key[u] != kEmptyKey && (key[u] >> 8) != kk[u]) {
-                                hh[u] = (hh[u] + 1) & mask;
-                                key[u] = hkey[hh[u]];
-                            }
-                            hit = key[u] != kEmptyKey;
-                        } else {
-                            while (key[u] != kk[u] && key[u] != kEmptyKey) {
-                                hh[u] = (hh[u] + 1) & mask;
-                                key[u] = hkey[hh[u]];
-                            }
-                            hit = key[u] == kk[u];
-                        }
-                        if (!(hit && ok[u])) continue;
-                        const uint32_t k = kk[u];
-                        const int sidx2 = spk[u];
-                        if (ANCHORED) {
-                            const uint32_t m = min(pi, min(mperm[sidx2], a.perm[k]));
-                            if (m < a.anchor_lo || m >= a.anchor_hi) continue;
-                        }
-                        const int x = mbin[sidx2];
-                        const int y = PACK ? (int)(key[u] & 0xFFu) : (int)hbin[hh[u]];
-                        const int z = bz[u];
-                        int idx;
-                        if (LUT) {
-                            idx = lut[(x * a.nb + y) * a.nb + z];
-                        } else {
-                            const int lo = min(x, min(y, z)), hi = max(x, max(y, z));
-                            const int mid = x + y + z - lo - hi;
-                            idx = ta[lo] + tb[mid] + hi;
-                        }
-                        if (LDS_HIST) atomicAdd(&hist[idx], 1u);
-                        else atomicAdd(&hout[idx], 1ull);
-                        ++mytri;
-                        if (WEIGHTED) {
-                            double p = wi, q = mw[sidx2], r = a.w[k], t;
-                            if (p > q) { t = p; p = q; q = t; }
-                            if (q > r) { t = q; q = r; r = t; }
-                            if (p > q) { t = p; p = q; q = t; }
-                            const double prod = __dmul_rn(__dmul_rn(p, q), r);
-                            const unsigned long long ti = (unsigned long long)__dmul_rn(prod, a.wmul);
-                            if (LDS_HIST) {
-                                atomicAdd(&wlo[idx], ti & 0xFFFFFFFFull);
-                                atomicAdd(&whi[idx], ti >> 32);
-                            } else {
-                                add128(&a.wsum[2 * idx], (unsigned __int128)ti);
-                            }
-                        }
-                    }
-                }
-            };
-            if (a.packed) {
-                if (a.lut) probe_flat(TrueT{}, TrueT{});
-                else probe_flat(TrueT{}, FalseT{});
-            } else {
-                if (a.lut) probe_flat(FalseT{}, TrueT{});
-                else probe_flat(FalseT{}, FalseT{});
+            // each wave walks one contiguous quarter of the flat range
+            if (total > 0) {
+                constexpr int NW = BLOCK / 64;
+                const uint32_t wid = tid >> 6;
+                const uint32_t r0 = (uint32_t)((uint64_t)total * wid / NW);
+                const uint32_t r1 = (uint32_t)((uint64_t)total * (wid + 1) / NW);
+                Probe c;
+                c.mpref = mpref; c.mstart = mstart; c.mbin = mbin; c.mw = mw; c.mperm = mperm;
+                c.wflag = wflag; c.hkey = hkey; c.hbin = hbin; c.lut = lut; c.ta = ta; c.tb = tb;
+                c.hist = hist; c.hout = hout; c.wlo = wlo; c.whi = whi; c.wsum = a.wsum;
+                c.scol = scol; c.sbin = sbinp; c.mask = mask; c.ncomp = ncomp; c.log2h = a.log2h;
+                c.nb = a.nb; c.wi = wi; c.wmul = a.wmul; c.w = a.w; c.pi = pi; c.perm = a.perm;
+                c.anchor_lo = a.anchor_lo; c.anchor_hi = a.anchor_hi; c.glog = a.glog;
+                if (a.glog > 0)
+                    probe_groups_any<WEIGHTED, ANCHORED, LDS_HIST>(a.packed, a.lut, c, wid, NW, mytri);
+                else if (r0 < r1)
+                    probe_any<WEIGHTED, ANCHORED, LDS_HIST>(a.packed, a.lut, c, r0, r1, mytri);
             }
             __syncthreads();
         }
@@ -422,6 +622,295 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     if (mytri) atomicAdd(s_cnt, mytri);
     __syncthreads();
     if (tid == 0 && *s_cnt && tout) atomicAdd(tout, *s_cnt);
+}
+
+// ---------------------------------------------------------------------------
+// Wave-per-hub variant for small degrees: every wavefront of a work group
+// runs its own hub with its own LDS hash and spoke tables, so no work-group
+// barrier is ever needed; the configuration table is shared. Unbatched, the
+// work group's waves share one histogram that any wave may hand to global
+// memory at any time by atomically exchanging each counter with zero (no
+// increment is lost or counted twice); batched, each wave keeps its own
+// histogram because neighbouring waves may be counting other catalogues.
+
+struct Layout3w {
+    uint32_t wlo, whi, acc, hist, tab, lut, shared_end;                  // work group
+    uint32_t mstart, mw, hkey, mpref, mperm, wflag, whist, hslot, hbin, mbin, per_wave;  // per wave
+    uint32_t total;
+};
+
+__host__ __device__ inline Layout3w layout3w(int nw, uint32_t H, uint32_t maxdeg, int nconf, int nb,
+                                             bool weighted, bool anchored, bool lds_hist, bool packed,
+                                             bool lut, bool batch) {
+    const int nsh = (lds_hist && !batch) ? nconf : 0;  // shared counters
+    const int nwv = (lds_hist && batch) ? nconf : 0;   // per-wave counters
+    Layout3w L{};
+    uint32_t o = 0;
+    L.wlo = o;   if (weighted) o = lds_align(o + 8 * nsh, 16);
+    L.whi = o;   if (weighted) o = lds_align(o + 8 * nsh, 16);
+    L.acc = o;   o = lds_align(o + 16, 16);
+    L.hist = o;  o = lds_align(o + 4 * nsh, 16);
+    L.tab = o;   o = lds_align(o + 8 * (nb + 1), 16);
+    L.lut = o;   if (lut) o = lds_align(o + 2 * nb * nb * nb, 16);
+    L.shared_end = o;
+    uint32_t q = 0;
+    L.mstart = q; q = lds_align(q + 8 * 64, 16);
+    L.mw = q;     if (weighted) q = lds_align(q + 8 * 64, 16);
+    L.hkey = q;   q = lds_align(q + 4 * H, 16);
+    L.mpref = q;  q = lds_align(q + 4 * 65, 16);
+    L.mperm = q;  if (anchored) q = lds_align(q + 4 * 64, 16);
+    L.wflag = q;  q = lds_align(q + 4 * 64, 16);
+    L.whist = q;  q = lds_align(q + 4 * nwv, 16);
+    L.hslot = q;  q = lds_align(q + 2 * (maxdeg + 1), 16);
+    L.hbin = q;   if (!packed) q = lds_align(q + H, 16);
+    L.mbin = q;   q = lds_align(q + 64, 16);
+    L.per_wave = q;
+    L.total = o + (uint32_t)nw * q;
+    return L;
+}
+
+__device__ __forceinline__ uint64_t wave_excl_scan64(uint64_t v, uint64_t &total) {
+    const int lane = threadIdx.x & 63;
+    uint64_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int NW, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool BATCH>
+__global__ __launch_bounds__(NW * 64) void k_count3w(C3Args a) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    const uint32_t H = 1u << a.log2h, mask = H - 1;
+    const Layout3w L = layout3w(NW, H, a.maxdeg, a.nconf, a.nb, WEIGHTED, ANCHORED, LDS_HIST, a.packed, a.lut, BATCH);
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    uint16_t *lut = (uint16_t *)(sm + L.lut);
+    int *ta = (int *)(sm + L.tab);
+    int *tb = ta + (a.nb + 1);
+    unsigned long long *s_acc = (unsigned long long *)(sm + L.acc);
+    unsigned long long *wlo = (unsigned long long *)(sm + L.wlo);
+    unsigned long long *whi = (unsigned long long *)(sm + L.whi);
+    unsigned char *wb = sm + L.shared_end + wid * L.per_wave;
+    uint32_t *hist = BATCH ? (uint32_t *)(wb + L.whist) : (uint32_t *)(sm + L.hist);
+    uint32_t *hkey = (uint32_t *)(wb + L.hkey);
+    uint8_t *hbin = (uint8_t *)(wb + L.hbin);
+    uint16_t *hslot = (uint16_t *)(wb + L.hslot);
+    unsigned long long *mstart = (unsigned long long *)(wb + L.mstart);
+    uint32_t *mpref = (uint32_t *)(wb + L.mpref);
+    uint8_t *mbin = (uint8_t *)(wb + L.mbin);
+    double *mw = (double *)(wb + L.mw);
+    uint32_t *mperm = (uint32_t *)(wb + L.mperm);
+    uint32_t *wflag = (uint32_t *)(wb + L.wflag);
+
+    for (uint32_t q = lane; q < H; q += 64) hkey[q] = kEmptyKey;
+    if (LDS_HIST) {
+        if (BATCH) {
+            for (int b = lane; b < a.nconf; b += 64) hist[b] = 0;
+        } else {
+            for (int b = tid; b < a.nconf; b += NW * 64) {
+                hist[b] = 0;
+                if (WEIGHTED) { wlo[b] = 0; whi[b] = 0; }
+            }
+        }
+    }
+    for (int b = tid; b < a.nb; b += NW * 64) {
+        ta[b] = rank_a(a.nb, b);
+        tb[b] = rank_b(a.nb, b);
+    }
+    if (a.lut)
+        for (int t = tid; t < a.nb * a.nb * a.nb; t += NW * 64) {
+            const int x = t / (a.nb * a.nb), y = (t / a.nb) % a.nb, z = t % a.nb;
+            const int lo = min(x, min(y, z)), hi = max(x, max(y, z)), mid = x + y + z - lo - hi;
+            lut[t] = (uint16_t)(rank_a(a.nb, lo) + rank_b(a.nb, mid) + hi);
+        }
+    if (tid == 0) *s_acc = 0;
+    __syncthreads();
+
+    unsigned long long mytri = 0;
+    uint64_t acc = 0;   // batched: increments since this wave's last flush
+    int qv = 0;
+    int cur = -1;
+    const uint64_t *rp = a.rp;
+    const uint32_t *hcol = a.hcol, *scol = a.scol;
+    const uint8_t *hbinp = a.hbin, *sbinp = a.sbin;
+    uint64_t hbase = a.hbase, sbase = a.sbase;
+    uint32_t s0 = a.s0, s1 = a.s1;
+    unsigned long long *hout = a.hist, *tout = a.ntri;
+
+    // batched: hand this wave's counts to its catalogue
+    auto flush_wave = [&]() {
+        if (LDS_HIST)
+            for (int b = lane; b < a.nconf; b += 64) {
+                const uint32_t v = hist[b];
+                if (v) {
+                    atomicAdd(&hout[b], (unsigned long long)v);
+                    hist[b] = 0;
+                }
+            }
+        const unsigned long long t = wave_sum64(mytri);
+        if (lane == 0 && t) atomicAdd(tout, t);
+        mytri = 0;
+    };
+    // unbatched: any wave may move the shared counters to global memory
+    auto flush_shared_exchange = [&]() {
+        for (int b = lane; b < a.nconf; b += 64) {
+            const uint32_t v = atomicExch(&hist[b], 0u);
+            if (v) atomicAdd(&a.hist[b], (unsigned long long)v);
+            if (WEIGHTED) {
+                const unsigned long long lo = atomicExch(&wlo[b], 0ull);
+                const unsigned long long hi = atomicExch(&whi[b], 0ull);
+                if (lo | hi) add128(&a.wsum[2 * b], ((unsigned __int128)hi << 32) + (unsigned __int128)lo);
+            }
+        }
+    };
+
+    while (true) {
+        uint32_t v = kEmptyKey;
+        int g = 0;
+        if (lane == 0) {
+            if (BATCH) {
+                v = next_hub_in(a.queue, 0, a.nvirt, &qv);
+                if (v != kEmptyKey) {
+                    g = graph_of(a.gd, a.ngraph, v);
+                    v = (uint32_t)(v - a.gd[g].v0);
+                }
+            } else {
+                v = next_hub_in(a.queue, a.h0, a.h1, &qv);
+            }
+        }
+        const uint32_t i = __builtin_amdgcn_readfirstlane(v);
+        if (i == kEmptyKey) break;
+        if (BATCH) {
+            g = __builtin_amdgcn_readfirstlane(g);
+            if (g != cur) {
+                if (cur >= 0) flush_wave();
+                acc = 0;
+                cur = g;
+                const GDesc &G = a.gd[g];
+                rp = G.rp;
+                hcol = scol = G.col;
+                hbinp = sbinp = G.bin;
+                hbase = sbase = 0;
+                s0 = 0;
+                s1 = G.n;
+                hout = G.hist;
+                tout = G.ntri;
+            }
+        }
+        const uint64_t beg = rp[i] - hbase;
+        const uint32_t d = (uint32_t)(rp[i + 1] - rp[i]);
+        if (d < 2 || (ANCHORED && a.mark && !a.mark[i])) continue;
+        const uint32_t kmax = hcol[beg + d - 1];
+        const double wi = WEIGHTED ? a.w[i] : 0.0;
+        const uint32_t pi = ANCHORED ? a.perm[i] : 0;
+
+        for (uint32_t e = lane; e < d; e += 64) {
+            const uint32_t k = hcol[beg + e];
+            const uint32_t val = a.packed ? ((k << 8) | hbinp[beg + e]) : k;
+            uint32_t q = label_hash(k, a.log2h);
+            while (atomicCAS(&hkey[q], kEmptyKey, val) != kEmptyKey) q = (q + 1) & mask;
+            if (!a.packed) hbin[q] = hbinp[beg + e];
+            hslot[e] = (uint16_t)q;
+        }
+        wave_lds_sync();
+
+        for (uint32_t c0 = 0; c0 + 1 < d; c0 += 64) {
+            const uint32_t sidx = c0 + lane;
+            uint32_t len = 0;
+            uint64_t st = 0;
+            uint8_t sb = 0;
+            double sw = 0.0;
+            uint32_t spm = 0;
+            if (sidx + 1 < d) {
+                const uint32_t j = hcol[beg + sidx];
+                if (j >= s0 && j < s1) {
+                    st = rp[j] - sbase;
+                    len = (uint32_t)(rp[j + 1] - rp[j]);
+                    if (a.trunc && len > 16 && scol[st + len - 1] > kmax) {
+                        uint32_t lo = 0, hi = len;
+                        while (lo < hi) {
+                            const uint32_t mid = (lo + hi) >> 1;
+                            if (scol[st + mid] <= kmax) lo = mid + 1;
+                            else hi = mid;
+                        }
+                        len = lo;
+                    }
+                    sb = hbinp[beg + sidx];
+                    if (WEIGHTED) sw = a.w[j];
+                    if (ANCHORED) spm = a.perm[j];
+                }
+            }
+            uint64_t tot64;
+            const uint64_t pre64 = wave_excl_scan64(((uint64_t)(len > 0) << 32) | len, tot64);
+            const uint32_t total = (uint32_t)tot64, ncomp = (uint32_t)(tot64 >> 32);
+            if (total == 0) continue;
+            if (len > 0) {
+                const uint32_t c = (uint32_t)(pre64 >> 32);
+                mstart[c] = st;
+                mpref[c] = (uint32_t)pre64;
+                mbin[c] = sb;
+                if (WEIGHTED) mw[c] = sw;
+                if (ANCHORED) mperm[c] = spm;
+            }
+            if (lane == 0) mpref[ncomp] = total;
+            wave_lds_sync();
+            if (LDS_HIST) {
+                if (BATCH) {
+                    if (acc + total >= a.flush_limit) {
+                        flush_wave();
+                        acc = 0;
+                    }
+                    acc += total;
+                } else {
+                    // the group's increments since the start; the wave that
+                    // crosses a multiple of 2^30 moves the shared counters out
+                    unsigned long long old = 0;
+                    if (lane == 0) old = atomicAdd(s_acc, (unsigned long long)total);
+                    old = __shfl(old, 0, 64);
+                    const unsigned long long lim = a.flush_limit >> 2;
+                    if (old / lim != (old + total) / lim) flush_shared_exchange();
+                }
+            }
+            Probe c;
+            c.mpref = mpref; c.mstart = mstart; c.mbin = mbin; c.mw = mw; c.mperm = mperm;
+            c.wflag = wflag; c.hkey = hkey; c.hbin = hbin; c.lut = lut; c.ta = ta; c.tb = tb;
+            c.hist = hist; c.hout = BATCH ? hout : a.hist; c.wlo = wlo; c.whi = whi; c.wsum = a.wsum;
+            c.scol = scol; c.sbin = sbinp; c.mask = mask; c.ncomp = ncomp; c.log2h = a.log2h;
+            c.nb = a.nb; c.wi = wi; c.wmul = a.wmul; c.w = a.w; c.pi = pi; c.perm = a.perm;
+            c.anchor_lo = a.anchor_lo; c.anchor_hi = a.anchor_hi; c.glog = a.glog;
+            if (a.glog > 0) probe_groups_any<WEIGHTED, ANCHORED, LDS_HIST>(a.packed, a.lut, c, 0, 1, mytri);
+            else probe_any<WEIGHTED, ANCHORED, LDS_HIST>(a.packed, a.lut, c, 0, total, mytri);
+            wave_lds_sync();
+        }
+        for (uint32_t e = lane; e < d; e += 64) hkey[hslot[e]] = kEmptyKey;
+        wave_lds_sync();
+    }
+
+    if (BATCH) {
+        if (cur >= 0) flush_wave();
+    } else {
+        const unsigned long long t = wave_sum64(mytri);
+        if (lane == 0 && t) atomicAdd(a.ntri, t);
+        __syncthreads();
+        if (LDS_HIST)
+            for (int b = tid; b < a.nconf; b += NW * 64) {
+                const uint32_t v = hist[b];
+                if (v) atomicAdd(&a.hist[b], (unsigned long long)v);
+                if (WEIGHTED) {
+                    const unsigned long long lo = wlo[b], hi = whi[b];
+                    if (lo | hi) add128(&a.wsum[2 * b], ((unsigned __int128)hi << 32) + (unsigned __int128)lo);
+                }
+            }
+    }
 }
 
 __global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
@@ -459,7 +948,56 @@ void launch3_b(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds, bool w, b
     }
 }
 
+constexpr uint32_t kWaveMaxDeg = 512;  // wave-per-hub kernel up to this forward degree
+
+template <int NW, bool W, bool A, bool LH, bool BATCH>
+void launch3w(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds) {
+    const void *kern = reinterpret_cast<const void *>(&k_count3w<NW, W, A, LH, BATCH>);
+    if (lds > 65536)
+        GS_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count3w<NW, W, A, LH, BATCH>, NW * 64, lds));
+    if (per_cu < 1) fail(GS_EUNSUPPORTED, "count kernel does not fit a compute unit");
+    uint32_t grid = (uint32_t)ctx.n_cu * (uint32_t)per_cu;
+    grid = (grid + kNumQueues - 1) / kNumQueues * kNumQueues;
+    k_count3w<NW, W, A, LH, BATCH><<<dim3(grid), dim3(NW * 64), lds, s>>>(a);
+    GS_HIP(hipGetLastError());
+}
+
+template <int NW, bool BATCH>
+void launch3w_n(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds, bool w, bool an, bool lh) {
+    if (BATCH) {
+        if (lh) launch3w<NW, false, false, true, true>(ctx, s, a, lds);
+        else launch3w<NW, false, false, false, true>(ctx, s, a, lds);
+        return;
+    }
+    if (lh) {
+        if (!w && !an) launch3w<NW, false, false, true, false>(ctx, s, a, lds);
+        else if (w && !an) launch3w<NW, true, false, true, false>(ctx, s, a, lds);
+        else if (!w && an) launch3w<NW, false, true, true, false>(ctx, s, a, lds);
+        else launch3w<NW, true, true, true, false>(ctx, s, a, lds);
+    } else {
+        if (!w && !an) launch3w<NW, false, false, false, false>(ctx, s, a, lds);
+        else if (w && !an) launch3w<NW, true, false, false, false>(ctx, s, a, lds);
+        else if (!w && an) launch3w<NW, false, true, false, false>(ctx, s, a, lds);
+        else launch3w<NW, true, true, false, false>(ctx, s, a, lds);
+    }
+}
+
+// Lanes per spoke group from the mean forward row length (GS_GLOG / GS_MAP3
+// override): short rows in small groups, long rows across the wavefront.
+int group_log(double mean_row) {
+    if (const char *em = getenv("GS_MAP3"))
+        if (strcmp(em, "flat") == 0) return 0;
+    if (const char *eg = getenv("GS_GLOG")) return std::max(0, std::min(6, atoi(eg)));
+    if (mean_row < 24) return 3;
+    if (mean_row < 64) return 4;
+    if (mean_row < 160) return 5;
+    return 6;
+}
+
 struct Plan3 {
+    int nw = 0;           // > 0: wave-per-hub kernel with nw waves per group
     int block = 256;
     int trunc = 0;
     bool packed = true;
@@ -470,18 +1008,46 @@ struct Plan3 {
 };
 
 void launch3_any(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P, bool w, bool an) {
-    if (P.block == 512) launch3_b<512>(ctx, s, a, P.lds, w, an, P.lds_hist);
+    if (P.nw == 8) launch3w_n<8, false>(ctx, s, a, P.lds, w, an, P.lds_hist);
+    else if (P.nw == 4) launch3w_n<4, false>(ctx, s, a, P.lds, w, an, P.lds_hist);
+    else if (P.nw == 2) launch3w_n<2, false>(ctx, s, a, P.lds, w, an, P.lds_hist);
+    else if (P.block == 512) launch3_b<512>(ctx, s, a, P.lds, w, an, P.lds_hist);
     else launch3_b<256>(ctx, s, a, P.lds, w, an, P.lds_hist);
 }
 
 // Work-group size and LDS plan: hash table at load factor <= 0.7, 512
 // threads per hub for long rows (more waves per CU when LDS limits groups).
-Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchored, uint64_t max_n) {
+Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchored, uint64_t max_n,
+            bool batch = false) {
     Plan3 p;
     p.packed = max_n < (1ull << 24) - 1;
     p.lut = nb <= kLutMaxBins;
     const int nconf = (int)n_configs(nb);
     if (maxdeg > 16384) fail(GS_EUNSUPPORTED, "forward degree above 16384");
+    // small degrees: one wavefront per hub (GS_KERNEL3=team|wave overrides)
+    const char *ek = getenv("GS_KERNEL3");
+    const bool wave = ek ? strcmp(ek, "wave") == 0 : maxdeg <= kWaveMaxDeg;
+    if (wave) {
+        p.nw = 4;
+        if (const char *ew = getenv("GS_WAVES3")) p.nw = atoi(ew) == 8 ? 8 : (atoi(ew) == 2 ? 2 : 4);
+        p.trunc = 0;
+        if (const char *et = getenv("GS_TRUNC")) p.trunc = atoi(et) != 0;
+        uint32_t H = 64;
+        while ((uint64_t)H * 7 < (uint64_t)maxdeg * 10) { H <<= 1; ++p.log2h; }
+        p.lds_hist = nconf <= 8192;
+        Layout3w L = layout3w(p.nw, H, maxdeg, nconf, nb, weighted, anchored, p.lds_hist, p.packed, p.lut, batch);
+        if ((int)L.total > ctx.max_lds && p.lds_hist) {
+            p.lds_hist = false;
+            L = layout3w(p.nw, H, maxdeg, nconf, nb, weighted, anchored, false, p.packed, p.lut, batch);
+        }
+        if ((int)L.total <= ctx.max_lds) {
+            p.lds = L.total;
+            p.block = 64 * p.nw;
+            return p;
+        }
+        p.nw = 0;  // does not fit: team kernel
+        p.log2h = 6;
+    }
     if (const char *eb = getenv("GS_BLOCK3")) p.block = atoi(eb) == 512 ? 512 : 256;
     else p.block = maxdeg >= 1024 ? 512 : 256;
     // the per-spoke binary search pays off on long rows only
@@ -553,7 +1119,10 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     const int nconf = (int)n_configs(nb);
     uint64_t max_n = 0;
     for (int g = 0; g < ng; ++g) max_n = std::max<uint64_t>(max_n, (uint64_t)gs[g]->n);
-    const Plan3 P = plan3(ctx, maxdeg, nb, false, false, max_n);
+    const Plan3 P = plan3(ctx, maxdeg, nb, false, false, max_n, true);
+    uint64_t sum_e = 0;
+    for (int g = 0; g < ng; ++g) sum_e += gs[g]->n_edges;
+    const int glog_sel = group_log(nvirt ? (double)sum_e / (double)nvirt : 0.0);
     b.ng = ng;
     b.nconf = nconf;
     const size_t per = (size_t)nconf + 1;
@@ -587,11 +1156,15 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     a.trunc = P.trunc;
     a.packed = P.packed;
     a.lut = P.lut;
+    a.glog = glog_sel;
     a.maxdeg = maxdeg;
     a.flush_limit = flush_limit_for(maxdeg, P.block);
     a.queue = (uint32_t *)(dv + (size_t)ng * per);
     if (nvirt > 0) {
-        if (P.block == 512) launch3_batch<512>(ctx, s, a, P);
+        if (P.nw == 8) launch3w_n<8, true>(ctx, s, a, P.lds, false, false, P.lds_hist);
+        else if (P.nw == 4) launch3w_n<4, true>(ctx, s, a, P.lds, false, false, P.lds_hist);
+        else if (P.nw == 2) launch3w_n<2, true>(ctx, s, a, P.lds, false, false, P.lds_hist);
+        else if (P.block == 512) launch3_batch<512>(ctx, s, a, P);
         else launch3_batch<256>(ctx, s, a, P);
     }
     b.out.alloc(sizeof(unsigned long long) * (size_t)ng * per);
@@ -609,6 +1182,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     if (anchored && (anchors->lo > anchors->hi)) fail(GS_EINVAL, "anchor range lo > hi");
     const uint32_t maxdeg = g.max_deg;
     const Plan3 P = plan3(ctx, maxdeg, nb, weighted, anchored, (uint64_t)g.n);
+    const int glog_sel = group_log(g.n ? (double)g.n_edges / (double)g.n : 0.0);
     const int W = g.n_windows;
     const int ntiles = W * (W + 1) / 2;
 
@@ -626,6 +1200,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.trunc = P.trunc;
     a.packed = P.packed;
     a.lut = P.lut;
+    a.glog = glog_sel;
     a.maxdeg = maxdeg;
     a.anchor_lo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
     a.anchor_hi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;

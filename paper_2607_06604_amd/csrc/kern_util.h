@@ -40,6 +40,41 @@ __device__ __forceinline__ uint32_t wg_excl_scan(uint32_t v, uint32_t *wtot, uin
     return off + x - v;
 }
 
+// Exclusive scan of one u64 per thread over the work group; ends with a barrier.
+template <int BLOCK>
+__device__ __forceinline__ uint64_t wg_excl_scan64(uint64_t v, uint64_t *wtot, uint64_t &total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint64_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wtot[wid] = x;
+    __syncthreads();
+    uint64_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < BLOCK / 64; ++k) {
+        uint64_t t = wtot[k];
+        off += (k < wid) ? t : 0ull;
+        tot += t;
+    }
+    total = tot;
+    __syncthreads();
+    return off + x - v;
+}
+
+// Lanes below this one with their bit set in the 64-bit wave mask.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Order LDS accesses of one wavefront (program order within the wave).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Position of the r-th set bit (r < popcount(w)).
 __device__ __forceinline__ int select_bit(uint32_t w, int r) {
     int pos = 0, c;

@@ -256,3 +256,48 @@ def test_invalid_inputs_rejected(ctx, gsn):
         ctx.count_4pcf_parity(g)
     assert e.value.code == gsn.GS_ENOCOORDS
     g.free()
+
+
+@pytest.mark.parametrize("kernel,mapping", [("team", "flat"), ("team", "3"), ("team", "6"),
+                                            ("wave", "flat"), ("wave", "4"), ("wave", "5")])
+def test_both_count_kernels_match_oracle(ctx, monkeypatch, kernel, mapping):
+    """The work-group-per-hub and the wavefront-per-hub kernels, each with the
+    flat candidate walk and with spoke groups of 2^k lanes, on plain,
+    weighted, anchored, tiled and batched counts."""
+    monkeypatch.setenv("GS_KERNEL3", kernel)
+    if mapping == "flat":
+        monkeypatch.setenv("GS_MAP3", "flat")
+    else:
+        monkeypatch.setenv("GS_GLOG", mapping)
+    x = synth.neyman_scott(12_000, 40, 1.5, 60.0, 301)
+    w = synth.uniform_values(len(x), 0.5, 1.0, 302)
+    L, rmax, nb = 60.0, 3.5, 9
+    say("kernel", kernel)
+    ref = oracle.count_3pcf(x, L, 0.0, rmax, nb, weights=w)
+    g = ctx.build_graph(x, L, 0.0, rmax, nb, weights=w)
+    got = ctx.count_3pcf(g, weighted=True)
+    assert np.array_equal(got.hist, ref.hist) and got.wsum_int() == ref.wsum_int()
+    part = ctx.count_3pcf(g, anchors=(2000, 7000))
+    refp = oracle.count_3pcf(x, L, 0.0, rmax, nb, anchors=(2000, 7000))
+    assert np.array_equal(part.hist, refp.hist) and part.n_triangles == refp.n_triangles
+    g.free()
+    monkeypatch.setenv("GS_WINDOWS", "3")
+    gt = ctx.build_graph(x, L, 0.0, rmax, nb, weights=w)
+    tiled = ctx.count_3pcf(gt, weighted=True)
+    gt.free()
+    monkeypatch.delenv("GS_WINDOWS")
+    assert np.array_equal(tiled.hist, ref.hist) and tiled.wsum_int() == ref.wsum_int()
+    y = synth.uniform(9_000, L, 303)
+    gs = [ctx.build_graph(c, L, 0.0, rmax, nb) for c in (x, y, x[:5000])]
+    bat = ctx.count_3pcf_batch(gs)
+    for gg in gs:
+        gg.free()
+    assert np.array_equal(bat[0].hist, ref.hist)
+    assert np.array_equal(bat[1].hist, oracle.count_3pcf(y, L, 0.0, rmax, nb).hist)
+    assert np.array_equal(bat[2].hist, oracle.count_3pcf(x[:5000], L, 0.0, rmax, nb).hist)
+    # forced flushes of the shared / per-wave counters
+    monkeypatch.setenv("GS_FLUSH_LIMIT", str(64 * 512 * 4))
+    g = ctx.build_graph(x, L, 0.0, rmax, nb, weights=w)
+    again = ctx.count_3pcf(g, weighted=True)
+    g.free()
+    assert np.array_equal(again.hist, ref.hist) and again.wsum_int() == ref.wsum_int()
