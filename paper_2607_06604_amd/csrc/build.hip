@@ -461,7 +461,7 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
 
 // CSR bytes the graph will hold once build_end runs resident.
 uint64_t build_footprint(const Graph &g, const BuildJob &job) {
-    return g.row_ptr.bytes + g.perm.bytes + g.coords.bytes + g.weights.bytes + 5 * job.E + 8;
+    return g.row_ptr.bytes + g.perm.bytes + g.coords.bytes + g.weights.bytes + 5 * (job.E + kRowSlack);
 }
 
 // Phase 2: the CSR itself, resident or in host-pinned windows (tile_ok).
@@ -471,8 +471,8 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok) {
     const uint64_t E = job.E;
     GS_HIP(hipEventRecord(ctx.ev[0], s));
     if (job.empty) {
-        g.col.alloc(4);
-        g.bin.alloc(1);
+        g.col.alloc(sizeof(uint32_t) * kRowSlack);
+        g.bin.alloc(kRowSlack);
         g.device_bytes = g.row_ptr.bytes + g.perm.bytes + g.col.bytes + g.bin.bytes;
         ctx.t.build_ms = job.begin_ms;
         return;
@@ -494,8 +494,8 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok) {
 
     ea.rp = g.row_ptr.as<uint64_t>();
     if (W == 1) {
-        g.col.alloc(sizeof(uint32_t) * (E ? E : 1));
-        g.bin.alloc(E ? E : 1);
+        g.col.alloc(sizeof(uint32_t) * (E + kRowSlack));
+        g.bin.alloc(E + kRowSlack);
         ea.col = g.col.as<uint32_t>();
         ea.bin = g.bin.as<uint8_t>();
         k_edges<true><<<grid_for(n), kBlock, 0, s>>>(ea);

@@ -287,6 +287,7 @@ int gs_count_3pcf_batch(gs_ctx *ctx, const gs_graph *const *graphs, int ng, uint
         GS_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
         GS_HIP(hipEventSynchronize(b.done));
         GS_HIP(hipStreamSynchronize(ctx->stream));
+        if (b.error()) fail(GS_EUNSUPPORTED, "batched count failed on the device (LDS addressing)");
         const unsigned long long *o = b.out.as<unsigned long long>();
         const size_t per = (size_t)b.nconf + 1;
         for (int g = 0; g < ng; ++g) {

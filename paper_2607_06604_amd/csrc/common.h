@@ -126,6 +126,11 @@ struct Bins {
     double t[256];
 };
 
+// Entries of readable slack after every device edge array (col, bin and
+// their window buffers): the count kernel's lanes past the end of a row may
+// load them (the values are never used), so it needs no per-lane clamp.
+constexpr uint64_t kRowSlack = 64;
+
 struct Graph {
     int device = 0;
     int64_t n = 0;
@@ -220,7 +225,8 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok);
 
 // Batched triangle counts over resident graphs with equal bin counts: one
 // persistent launch. Results land in host memory `out` (ng x (nconf+1) u64:
-// each graph's histogram then its triangle count) once `done` has fired.
+// each graph's histogram then its triangle count; then one error word, 0
+// when the counts are valid) once `done` has fired.
 struct Batch3 {
     DevBuf dv;          // device results + queues
     DevBuf gd;          // descriptors
@@ -228,6 +234,7 @@ struct Batch3 {
     HostBuf out;        // pinned results
     hipEvent_t done = nullptr;
     int ng = 0, nconf = 0;
+    unsigned long long error() const { return out.as<unsigned long long>()[(size_t)ng * (nconf + 1)]; }
     ~Batch3();
 };
 void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int ng, Batch3 &b);

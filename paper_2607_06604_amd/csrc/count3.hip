@@ -4,22 +4,24 @@
 //
 // Every triangle {i < j < k} (labels) is found exactly once: at hub i, spoke
 // j in N+(i), third vertex k in N+(i) and N+(j). The work group of a hub
-// stages N+(i) in an LDS hash table (label -> bin of edge (i,k)), then
-// streams the forward rows of its spokes as one flat, coalesced sequence;
-// each lane probes one candidate k. A hit has its three bins (ij from the
-// spoke, ik from the table, jk from the row), which are sorted and ranked
-// into an LDS histogram of 32-bit counters, flushed into the 64-bit result
-// before any counter could wrap. Weighted counts add the exact integer
-// t * 2^s of each triangle into 64-bit LDS halves, merged into 128-bit sums.
+// stages N+(i) in an LDS hash table (label -> bin of edge (i,k)) and cuts the
+// forward rows of its spokes into steps of S = 2^glog consecutive entries,
+// listed in an LDS step table; a group of S lanes takes one step and each of
+// its lanes probes one candidate k. A hit has its three bins (ij from the
+// step's spoke, ik from the table, jk from the row), which a configuration
+// table turns into the LDS address of a 32-bit counter; the counters are
+// flushed into the 64-bit result before any of them could wrap, and the
+// triangle total is the sum of what was flushed. Weighted counts add the
+// exact integer t * 2^s of each triangle into 64-bit LDS halves, merged into
+// 128-bit sums.
 //
 // A launch covers one tile: hubs in [h0, h1) and spokes in [s0, s1). A
 // resident graph is a single tile; a host-tiled graph runs every (hub
 // window, spoke window >= hub window) pair, so each spoke (i, j) -- and with
 // it every triangle -- belongs to exactly one tile.
 //
-// Hubs are pulled from eight queues, one per slice of the tile's hub range;
-// a work group starts on the queue of its own XCD so nearby hubs share that
-// XCD's L2, and moves on to the other queues once its own is empty.
+// Hubs are pulled from eight queues, one per slice of the tile's hub range,
+// in runs of consecutive hubs (next_hub_in).
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -58,55 +60,79 @@ struct C3Args {
     const uint8_t *mark;    // anchored: hubs that can own an anchored triangle (nullable)
     int nb, nconf, log2h;
     int trunc;              // cut spoke rows at the hub row's largest label
-    int packed;             // hash entries hold (label << 8 | bin): labels < 2^24 - 1
-    int glog;               // > 0: spoke rows walked by groups of 2^glog lanes
-    int lut;                // configuration index from an LDS table of nb^3 entries
+    int packed;             // hash entries hold (bin << 24 | label): labels < 2^24 - 1
+    int glog;               // entries per step = 2^glog
+    int mode;               // hit counter addressing: kRank, kLut or kCube
     uint32_t maxdeg;
+    uint32_t tmax;          // steps per table fill
+    uint32_t tcap;          // table entries: tmax + padding of one pass
     uint32_t anchor_lo, anchor_hi;
     double wmul;            // 2^wscale
     uint64_t flush_limit;   // flush LDS counters before this many increments
-    uint32_t *queue;        // kNumQueues counters
+    uint32_t *queue;        // kQueueWords words
     unsigned long long *hist;   // nconf
     unsigned long long *wsum;   // 2*nconf (lo, hi)
     unsigned long long *ntri;   // 1
+    uint32_t *err;          // bit 0: a hub's spoke rows span too many entries; bit 1: LDS addressing
 };
 
-constexpr int kUnroll3 = 4;     // candidates per lane per pass
-constexpr int kLutMaxBins = 16; // nb^3 u16 table up to 8 KB
+constexpr int kUnroll3 = 4;              // steps per lane per pass
+constexpr int kLutMaxBins = 24;          // nb^3 u16 table up to 27 KB
+constexpr int kCubeMaxBins = 16;         // nb^3 u32 counters up to 16 KB
 
-struct TrueT { static constexpr bool value = true; };
-struct FalseT { static constexpr bool value = false; };
+// How a hit finds its counter: the configuration index from the rank tables
+// (kRank), an nb^3 table of counter addresses (kLut), or no index at all --
+// one LDS counter per ordered bin triple (x, y, z), folded into
+// configurations when the counters are flushed (kCube, unweighted only).
+enum { kRank = 0, kLut = 1, kCube = 2 };
+// Spoke rows of one hub are addressed by 32-bit offsets from the hub's
+// first spoke row: byte offsets (loads with a scalar base) below 2^30
+// entries, entry offsets with 64-bit addresses (WIDE launches) below 2^32.
+constexpr uint64_t kNarrowSpan = 1ull << 30;
+constexpr uint64_t kWideSpan = 1ull << 32;
 
-// LDS layout of one work group (byte offsets).
+// LDS layout of one work group (byte offsets). The configuration table and
+// the counters come first so that their byte addresses fit 16 bits.
 struct Layout3 {
-    uint32_t hkey, hbin, hslot, mstart, mpref, mbin, mw, mperm, hist, wlo, whi, tab, wtot, wflag, misc,
-        lut, total;
+    uint32_t cube, lut, hist, wlo, whi, hkey, hrow, hxb, hslot, tab, mw, mperm, rtab, wtot, misc, hbin, total;
 };
 
-__host__ __device__ inline Layout3 layout3(int block, uint32_t H, uint32_t maxdeg, int nconf, int nb,
-                                           bool weighted, bool anchored, bool lds_hist, bool packed,
-                                           bool lut) {
+__host__ __device__ inline Layout3 layout3(int block, uint32_t H, uint32_t maxdeg, uint32_t tcap, int nconf,
+                                           int nb, bool weighted, bool anchored, bool lds_hist, bool packed,
+                                           int mode) {
     if (!lds_hist) nconf = 0;
     Layout3 L{};
     uint32_t o = 0;
-    L.mstart = o; o = lds_align(o + 8 * block, 16);
-    L.mw = o;     if (weighted) o = lds_align(o + 8 * block, 16);
+    L.cube = o;   if (mode == kCube) o = lds_align(o + 4 * nb * nb * nb, 16);
+    L.lut = o;    if (mode == kLut) o = lds_align(o + 2 * nb * nb * nb, 16);
+    L.hist = o;   o = lds_align(o + 4 * nconf, 16);
     L.wlo = o;    if (weighted) o = lds_align(o + 8 * nconf, 16);
     L.whi = o;    if (weighted) o = lds_align(o + 8 * nconf, 16);
     L.hkey = o;   o = lds_align(o + 4 * H, 16);
-    L.mpref = o;  o = lds_align(o + 4 * (block + 1), 16);
+    L.hrow = o;   o = lds_align(o + 4 * maxdeg, 16);
+    L.tab = o;    o = lds_align(o + 8 * tcap, 16);
+    L.mw = o;     if (weighted) o = lds_align(o + 8 * block, 16);
     L.mperm = o;  if (anchored) o = lds_align(o + 4 * block, 16);
-    L.hist = o;   o = lds_align(o + 4 * nconf, 16);
-    L.tab = o;    o = lds_align(o + 8 * (nb + 1), 16);
+    L.rtab = o;   o = lds_align(o + 8 * (nb + 1), 16);
     L.wtot = o;   o = lds_align(o + 8 * (block / 64 + 1), 16);
-    L.wflag = o;  o = lds_align(o + 4 * block, 16);
-    L.misc = o;   o = lds_align(o + 16, 16);
-    L.hslot = o;  o = lds_align(o + 2 * (maxdeg + 1), 16);
-    L.lut = o;    if (lut) o = lds_align(o + 2 * nb * nb * nb, 16);
+    L.misc = o;   o = lds_align(o + 32, 16);
+    L.hslot = o;  o = lds_align(o + 2 * maxdeg, 16);
+    L.hxb = o;    o = lds_align(o + maxdeg, 16);
     L.hbin = o;   if (!packed) o = lds_align(o + H, 16);
-    L.mbin = o;   o = lds_align(o + block, 16);
     L.total = o;
     return L;
+}
+
+// Fibonacci hash of a label below 2^24 in 24-bit arithmetic: the top log2h
+// bits of k * A mod 2^24 with A = 2^24 / golden ratio (odd). Both factors fit
+// 24 bits, so the multiply is the full-rate 24-bit one.
+__device__ __forceinline__ uint32_t label_hash24(uint32_t k, int log2h) {
+    return (((k & 0xFFFFFFu) * 0x9E3779u) & 0xFFFFFFu) >> (24 - log2h);
+}
+
+template <bool PACK>
+__device__ __forceinline__ uint32_t hub_hash(uint32_t k, int log2h) {
+    return PACK ? label_hash24(k, log2h) : label_hash(k, log2h);
 }
 
 // 128-bit add into a (lo, hi) pair of global words.
@@ -117,42 +143,56 @@ __device__ __forceinline__ void add128(unsigned long long *dst, unsigned __int12
     if (hi) atomicAdd(&dst[1], hi);
 }
 
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Move the LDS counters into the 64-bit results (and their sum into the
+// triangle total); the caller brackets it with barriers.
 template <int BLOCK, bool WEIGHTED, bool LDS_HIST>
-__device__ void flush3(const C3Args &a, const Layout3 &L, unsigned char *sm,
-                       unsigned long long *hout) {
+__device__ void flush3(const C3Args &a, const Layout3 &L, unsigned char *sm, unsigned long long *hout,
+                       unsigned long long *tout) {
     if (!LDS_HIST) return;
     uint32_t *hist = (uint32_t *)(sm + L.hist);
+    if (!WEIGHTED && a.mode == kCube) {
+        // fold the ordered bin triples into their configurations
+        uint32_t *cube = (uint32_t *)(sm + L.cube);
+        const int *ta = (const int *)(sm + L.rtab), *tb = ta + (a.nb + 1);
+        const int nb = a.nb;
+        for (int t = threadIdx.x; t < nb * nb * nb; t += BLOCK) {
+            const uint32_t v = cube[t];
+            if (v) {
+                cube[t] = 0;
+                const int x = t / (nb * nb), y = (t / nb) % nb, z = t % nb;
+                const int lo = min(x, min(y, z)), hi = max(x, max(y, z)), mid = x + y + z - lo - hi;
+                atomicAdd(&hist[ta[lo] + tb[mid] + hi], v);
+            }
+        }
+        __syncthreads();
+    }
+    unsigned long long sum = 0;
     for (int b = threadIdx.x; b < a.nconf; b += BLOCK) {
-        uint32_t v = hist[b];
+        const uint32_t v = hist[b];
         if (v) {
             atomicAdd(&hout[b], (unsigned long long)v);
             hist[b] = 0;
+            sum += v;
         }
         if (WEIGHTED) {
             unsigned long long *wlo = (unsigned long long *)(sm + L.wlo);
             unsigned long long *whi = (unsigned long long *)(sm + L.whi);
-            unsigned long long lo = wlo[b], hi = whi[b];
+            const unsigned long long lo = wlo[b], hi = whi[b];
             if (lo | hi) {
-                unsigned __int128 V = ((unsigned __int128)hi << 32) + (unsigned __int128)lo;
-                add128(&a.wsum[2 * b], V);
+                add128(&a.wsum[2 * b], ((unsigned __int128)hi << 32) + (unsigned __int128)lo);
                 wlo[b] = 0;
                 whi[b] = 0;
             }
         }
     }
-}
-
-__device__ __forceinline__ uint32_t next_hub_in(uint32_t *queue, uint32_t h0, uint32_t h1, int *qv) {
-    const int q0 = blockIdx.x % kNumQueues;
-    const uint64_t n = (uint64_t)(h1 - h0);
-    while (*qv < kNumQueues) {
-        const int q = (q0 + *qv) % kNumQueues;
-        const uint64_t lo = h0 + n * q / kNumQueues, hi = h0 + n * (q + 1) / kNumQueues;
-        const uint32_t v = atomicAdd(&queue[q], 1u);
-        if (lo + v < hi) return (uint32_t)(lo + v);
-        ++*qv;
-    }
-    return kEmptyKey;
+    sum = wave_sum64(sum);
+    if ((threadIdx.x & 63) == 0 && sum && tout) atomicAdd(tout, sum);
 }
 
 // Catalogue of virtual hub v: the last descriptor with v0 <= v.
@@ -166,65 +206,66 @@ __device__ __forceinline__ int graph_of(const GDesc *gd, int ng, uint32_t v) {
     return lo;
 }
 
-// Everything the candidate walk of one spoke chunk reads or updates.
-struct Probe {
-    const uint32_t *mpref;        // flat start of each compact spoke, [ncomp] = total
-    const unsigned long long *mstart;  // row offset of each compact spoke in scol / sbin
-    const uint8_t *mbin;          // bin of edge (hub, spoke)
-    const double *mw;             // spoke weights
-    const uint32_t *mperm;        // spoke original indices
-    uint32_t *wflag;              // this wave's 64 LDS tags
+// What the walk over one step table reads or updates.
+struct Walk {
+    const uint2 *tab;             // steps: (row offset, entries | slot << 7 | x term << 16)
     const uint32_t *hkey;         // hub hash
-    const uint8_t *hbin;          // hub bins (unpacked hash)
-    const uint16_t *lut;          // nb^3 configuration table
+    const uint8_t *hbin;          // hub bins per slot (unpacked hash)
     const int *ta, *tb;           // rank tables
-    uint32_t *hist;               // LDS counters (LDS_HIST)
-    unsigned long long *hout;     // global counters (otherwise)
+    const double *mw;             // spoke weights (by spoke slot)
+    const uint32_t *mperm;        // spoke original indices (by spoke slot)
+    unsigned char *sm;            // LDS base
+    unsigned long long *hout;     // global counters (!LDS_HIST)
     unsigned long long *wlo, *whi, *wsum;
-    const uint32_t *scol;
-    const uint8_t *sbin;
-    uint32_t mask, ncomp;
-    int log2h, nb;
-    double wi, wmul;
+    gbl_u32 *srow;                // spoke rows of this hub (32-bit offsets)
+    gbl_u8 *sbrow;
     const double *w;
-    uint32_t pi;
     const uint32_t *perm;
-    uint32_t anchor_lo, anchor_hi;
-    int glog;                     // lanes per spoke group = 1 << glog (group walk)
+    uint32_t mask, hist_addr;     // LDS byte address of counter 0
+    int log2h, nb, glog;
+    double wi, wmul;
+    uint32_t pi, anchor_lo, anchor_hi;
 };
 
-// One candidate: probe the hub hash, bin and count a hit.
-template <bool PACK, bool LUT, bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
-__device__ __forceinline__ void probe_one(const Probe &c, uint32_t k, uint32_t key, uint32_t hh, int s2,
-                                          int z, unsigned long long &mytri) {
-    const bool more = PACK ? (key != kEmptyKey && (key >> 8) != k) : (key != k && key != kEmptyKey);
-    if (more) {
-        do {
-            hh = (hh + 1) & c.mask;
-            key = c.hkey[hh];
-        } while (PACK ? (key != kEmptyKey && (key >> 8) != k) : (key != k && key != kEmptyKey));
-    }
-    const bool hit = PACK ? key != kEmptyKey : key == k;
-    if (!hit) return;
+// One hit: bins x (spoke, in the step's x term), y (hub table), z (row).
+// The x term is the LDS byte address of plane x of the ordered-triple
+// counters (kCube) or of row x of the configuration table (kLut), whose
+// entries are counter addresses (or indices); with kRank it is x itself.
+template <int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
+__device__ __forceinline__ void count_hit(const Walk &c, uint32_t k, uint32_t meta, uint32_t y, uint32_t z,
+                                          unsigned long long &mytri) {
+    const uint32_t slot = (meta >> 7) & 511u;
     if (ANCHORED) {
-        const uint32_t mm = min(c.pi, min(c.mperm[s2], c.perm[k]));
+        const uint32_t mm = min(c.pi, min(c.mperm[slot], c.perm[k]));
         if (mm < c.anchor_lo || mm >= c.anchor_hi) return;
     }
-    const int x = c.mbin[s2];
-    const int y = PACK ? (int)(key & 0xFFu) : (int)c.hbin[hh];
-    int idx;
-    if (LUT) {
-        idx = c.lut[(x * c.nb + y) * c.nb + z];
-    } else {
-        const int lo = min(x, min(y, z)), hi = max(x, max(y, z));
-        const int mid = x + y + z - lo - hi;
-        idx = c.ta[lo] + c.tb[mid] + hi;
+    if (MODE == kCube) {
+        // y, z < 256 and nb <= 16: 24-bit multiply
+        const uint32_t addr = (meta >> 16) + 4 * ((y & 0xFFu) * ((uint32_t)c.nb & 0xFFu) + z);
+        __hip_atomic_fetch_add((lds_u32 *)(size_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return;
     }
-    if (LDS_HIST) atomicAdd(&c.hist[idx], 1u);
-    else atomicAdd(&c.hout[idx], 1ull);
-    ++mytri;
+    uint32_t addr, idx;
+    if (MODE == kLut) {
+        // y, z < 256 and nb <= 24: 24-bit multiply
+        const uint32_t v = *(lds_u16 *)(size_t)((meta >> 16) + 2 * ((y & 0xFFu) * ((uint32_t)c.nb & 0xFFu) + z));
+        addr = v;
+        idx = LDS_HIST ? (v - c.hist_addr) >> 2 : v;
+    } else {
+        const int x = (int)(meta >> 16);
+        const int lo = min(x, min((int)y, (int)z)), hi = max(x, max((int)y, (int)z));
+        const int mid = x + (int)y + (int)z - lo - hi;
+        idx = (uint32_t)(c.ta[lo] + c.tb[mid] + hi);
+        addr = c.hist_addr + 4 * idx;
+    }
+    if (LDS_HIST) {
+        __hip_atomic_fetch_add((lds_u32 *)(size_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+        atomicAdd(&c.hout[idx], 1ull);
+        ++mytri;
+    }
     if (WEIGHTED) {
-        double p = c.wi, q = c.mw[s2], r = c.w[k], t;
+        double p = c.wi, q = c.mw[slot], r = c.w[k], t;
         if (p > q) { t = p; p = q; q = t; }
         if (q > r) { t = q; q = r; r = t; }
         if (p > q) { t = p; p = q; q = t; }
@@ -239,211 +280,121 @@ __device__ __forceinline__ void probe_one(const Probe &c, uint32_t k, uint32_t k
     }
 }
 
-// Spokes sfirst, sfirst + sstep, ... of a chunk, walked by groups of
-// 2^glog lanes: group g of the wave takes every G-th of those spokes and
-// reads its row 2^glog candidates at a time, U steps per pass with the loads
-// of a pass issued back to back. Rows are padded to whole steps.
-template <bool PACK, bool LUT, bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
-__device__ __forceinline__ void probe_groups(const Probe &c, uint32_t sfirst, uint32_t sstep,
-                                             unsigned long long &mytri) {
+// Steps [0, nsteps) of the table: lane group g (2^glog lanes) of the work
+// group takes steps g, g + G, ... (G groups), U of them per pass with their
+// row loads issued back to back; lane s of a group probes entry s of its
+// step. The table is padded with empty steps past nsteps, and lanes past
+// the end of a step load (and ignore) the row slack, so the loads need no
+// branch.
+template <int BLOCK, bool PACK, int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WIDE>
+__device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned long long &mytri) {
     constexpr int U = kUnroll3;
-    const uint32_t lane = threadIdx.x & 63;
-    const int glog = c.glog;
-    const uint32_t S = 1u << glog, G = 64u >> glog;
-    const uint32_t sub = lane & (S - 1), gi = lane >> glog;
-    const uint32_t ncomp = c.ncomp;
-    uint32_t s = sfirst + gi * sstep;         // this group's spoke
-    const uint32_t gstep = G * sstep;
-    uint32_t off = 0, len = 0;
-    uint64_t base = 0;
-    if (s < ncomp) {
-        len = c.mpref[s + 1] - c.mpref[s];
-        base = c.mstart[s];
-    }
-    while (true) {
-        uint32_t kk[U], key[U], hh[U], sp[U];
-        uint8_t bz[U];
+    const uint32_t glog = (uint32_t)c.glog;
+    const uint32_t sub = threadIdx.x & ((1u << glog) - 1u);
+    const uint32_t per = (uint32_t)BLOCK >> glog;
+    const uint2 *tp = c.tab + (threadIdx.x >> glog);
+    for (uint32_t base = 0; base < nsteps; base += U * per) {
+        uint32_t kk[U], zz[U], meta[U], hh[U], key[U];
         bool ok[U];
-        bool any = false;  // this lane has a candidate in this pass
+        // 1. row loads of all U steps (a slot past the table's end is skipped
+        //    by the whole work group)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (off >= len && s < ncomp) {  // next spoke of this group
-                s += gstep;
-                off = 0;
-                len = 0;
-                if (s < ncomp) {
-                    len = c.mpref[s + 1] - c.mpref[s];
-                    base = c.mstart[s];
+            ok[u] = false;
+            kk[u] = zz[u] = meta[u] = 0;
+            if (base + u * per < nsteps) {
+                const uint2 e = tp[base + u * per];
+                const uint32_t pos = e.x + sub;
+                ok[u] = sub < (e.y & 127u);
+                meta[u] = e.y;
+                if (WIDE) {
+                    kk[u] = c.srow[pos];
+                } else {
+                    kk[u] = *(gbl_u32 *)((gbl_u8 *)c.srow + (pos << 2));
                 }
+                zz[u] = c.sbrow[pos];
             }
-            const uint32_t e = off + sub;
-            ok[u] = s < ncomp && e < len;
-            sp[u] = ok[u] ? s : 0;
-            const uint64_t pos = ok[u] ? base + e : c.mstart[0];  // in-bounds stand-in
-            kk[u] = c.scol[pos];
-            bz[u] = c.sbin[pos];
-            off += S;
-            any |= ok[u];
         }
-        if (!__any(any)) break;
+        // 2. first probes of all U candidates
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            hh[u] = label_hash(kk[u], c.log2h);
+            hh[u] = hub_hash<PACK>(kk[u], c.log2h);
             key[u] = c.hkey[hh[u]];
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (ok[u]) probe_one<PACK, LUT, WEIGHTED, ANCHORED, LDS_HIST>(c, kk[u], key[u], hh[u], sp[u], bz[u], mytri);
-    }
-}
-
-template <bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
-__device__ __forceinline__ void probe_groups_any(bool packed, bool lut, const Probe &c, uint32_t sfirst,
-                                                 uint32_t sstep, unsigned long long &mytri) {
-    if (packed) {
-        if (lut) probe_groups<true, true, WEIGHTED, ANCHORED, LDS_HIST>(c, sfirst, sstep, mytri);
-        else probe_groups<true, false, WEIGHTED, ANCHORED, LDS_HIST>(c, sfirst, sstep, mytri);
-    } else {
-        if (lut) probe_groups<false, true, WEIGHTED, ANCHORED, LDS_HIST>(c, sfirst, sstep, mytri);
-        else probe_groups<false, false, WEIGHTED, ANCHORED, LDS_HIST>(c, sfirst, sstep, mytri);
-    }
-}
-
-// Candidates [r0, r1) of the flat range of a spoke chunk, walked by one
-// wavefront in windows of 64, U windows per pass with their loads issued back
-// to back. The spokes starting inside a window tag their start positions in
-// the wave's LDS flags; a ballot of the tags and a count of the tagged lanes
-// below give every lane its spoke without a search.
-template <bool PACK, bool LUT, bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
-__device__ __forceinline__ void probe_range(const Probe &c, uint32_t r0, uint32_t r1,
-                                            unsigned long long &mytri) {
-    constexpr int U = kUnroll3;
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t ncomp = c.ncomp;
-    c.wflag[lane] = 0;  // tags of earlier chunks must not match this one's
-    wave_lds_sync();
-    uint32_t base = upper_index(c.mpref, ncomp, r0);  // spoke holding r0
-    for (uint32_t w0 = r0; w0 < r1; w0 += U * 64) {
-        uint32_t kk[U], spk[U], key[U], hh[U];
-        uint8_t bz[U];
-        bool ok[U];
+        // 3. probe sequences to their ends, and the hits
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t e0 = w0 + u * 64;
-            const uint32_t cs = base + 1 + lane;
-            const uint32_t p = cs < ncomp ? c.mpref[cs] - e0 : 0xFFFFFFFFu;
-            if (p < 64) c.wflag[p] = e0 + 1;
-            wave_lds_sync();
-            const bool f = lane > 0 && c.wflag[lane] == e0 + 1;
-            const uint64_t m = __ballot(f);
-            const uint64_t at64 = __ballot(p == 64);
-            const uint32_t sp = base + lanes_below(m) + (f ? 1u : 0u);
-            base += (uint32_t)__popcll(m) + (at64 ? 1u : 0u);
-            uint32_t e = e0 + lane;
-            ok[u] = e < r1;
-            const uint32_t sps = min(ok[u] ? sp : base, ncomp - 1);
-            if (!ok[u]) e = c.mpref[sps];  // in-bounds stand-in, result dropped
-            spk[u] = sps;
-            const uint64_t pos = c.mstart[sps] + (e - c.mpref[sps]);
-            kk[u] = c.scol[pos];
-            bz[u] = c.sbin[pos];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            hh[u] = label_hash(kk[u], c.log2h);
-            key[u] = c.hkey[hh[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            // the first probe resolves almost always; chains are rare
-            const bool more = PACK ? (key[u] != kEmptyKey && (key[u] >> 8) != kk[u])
-                                   : (key[u] != kk[u] && key[u] != kEmptyKey);
-            if (more) {
-                uint32_t h = hh[u], kv;
-                do {
+            if (!ok[u]) continue;
+            const uint32_t k = kk[u];
+            uint32_t h = hh[u], kv = key[u];
+            if (PACK) {
+                while (((kv ^ k) & 0xFFFFFFu) != 0 && kv != kEmptyKey) {
                     h = (h + 1) & c.mask;
                     kv = c.hkey[h];
-                } while (PACK ? (kv != kEmptyKey && (kv >> 8) != kk[u]) : (kv != kk[u] && kv != kEmptyKey));
-                hh[u] = h;
-                key[u] = kv;
-            }
-            const bool hit = PACK ? key[u] != kEmptyKey : key[u] == kk[u];
-            if (!(hit && ok[u])) continue;
-            const uint32_t k = kk[u];
-            const int s2 = spk[u];
-            if (ANCHORED) {
-                const uint32_t mm = min(c.pi, min(c.mperm[s2], c.perm[k]));
-                if (mm < c.anchor_lo || mm >= c.anchor_hi) continue;
-            }
-            const int x = c.mbin[s2];
-            const int y = PACK ? (int)(key[u] & 0xFFu) : (int)c.hbin[hh[u]];
-            const int z = bz[u];
-            int idx;
-            if (LUT) {
-                idx = c.lut[(x * c.nb + y) * c.nb + z];
-            } else {
-                const int lo = min(x, min(y, z)), hi = max(x, max(y, z));
-                const int mid = x + y + z - lo - hi;
-                idx = c.ta[lo] + c.tb[mid] + hi;
-            }
-            if (LDS_HIST) atomicAdd(&c.hist[idx], 1u);
-            else atomicAdd(&c.hout[idx], 1ull);
-            ++mytri;
-            if (WEIGHTED) {
-                double p = c.wi, q = c.mw[s2], r = c.w[k], t;
-                if (p > q) { t = p; p = q; q = t; }
-                if (q > r) { t = q; q = r; r = t; }
-                if (p > q) { t = p; p = q; q = t; }
-                const double prod = __dmul_rn(__dmul_rn(p, q), r);
-                const unsigned long long ti = (unsigned long long)__dmul_rn(prod, c.wmul);
-                if (LDS_HIST) {
-                    atomicAdd(&c.wlo[idx], ti & 0xFFFFFFFFull);
-                    atomicAdd(&c.whi[idx], ti >> 32);
-                } else {
-                    add128(&c.wsum[2 * idx], (unsigned __int128)ti);
                 }
+                if (kv != kEmptyKey)
+                    count_hit<MODE, WEIGHTED, ANCHORED, LDS_HIST>(c, k, meta[u], kv >> 24, zz[u], mytri);
+            } else {
+                while (kv != k && kv != kEmptyKey) {
+                    h = (h + 1) & c.mask;
+                    kv = c.hkey[h];
+                }
+                if (kv == k) count_hit<MODE, WEIGHTED, ANCHORED, LDS_HIST>(c, k, meta[u], c.hbin[h], zz[u], mytri);
             }
         }
     }
 }
 
-template <bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
-__device__ __forceinline__ void probe_any(bool packed, bool lut, const Probe &c, uint32_t r0,
-                                          uint32_t r1, unsigned long long &mytri) {
+template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WIDE>
+__device__ __forceinline__ void walk3_any(bool packed, int mode, const Walk &c, uint32_t nsteps,
+                                          unsigned long long &mytri) {
+    // kCube only for unweighted counts into LDS (never selected otherwise)
+    constexpr int CUBE = (!WEIGHTED && LDS_HIST) ? kCube : kLut;
     if (packed) {
-        if (lut) probe_range<true, true, WEIGHTED, ANCHORED, LDS_HIST>(c, r0, r1, mytri);
-        else probe_range<true, false, WEIGHTED, ANCHORED, LDS_HIST>(c, r0, r1, mytri);
+        if (mode == kCube) walk3<BLOCK, true, CUBE, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(c, nsteps, mytri);
+        else if (mode == kLut) walk3<BLOCK, true, kLut, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(c, nsteps, mytri);
+        else walk3<BLOCK, true, kRank, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(c, nsteps, mytri);
     } else {
-        if (lut) probe_range<false, true, WEIGHTED, ANCHORED, LDS_HIST>(c, r0, r1, mytri);
-        else probe_range<false, false, WEIGHTED, ANCHORED, LDS_HIST>(c, r0, r1, mytri);
+        if (mode == kCube) walk3<BLOCK, false, CUBE, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(c, nsteps, mytri);
+        else if (mode == kLut) walk3<BLOCK, false, kLut, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(c, nsteps, mytri);
+        else walk3<BLOCK, false, kRank, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(c, nsteps, mytri);
     }
 }
 
-template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool BATCH>
+template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool BATCH, bool WIDE>
 __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const uint32_t H = 1u << a.log2h, mask = H - 1;
-    const Layout3 L = layout3(BLOCK, H, a.maxdeg, a.nconf, a.nb, WEIGHTED, ANCHORED, LDS_HIST, a.packed, a.lut);
+    const Layout3 L = layout3(BLOCK, H, a.maxdeg, a.tcap, a.nconf, a.nb, WEIGHTED, ANCHORED, LDS_HIST,
+                              a.packed, a.mode);
     uint16_t *lut = (uint16_t *)(sm + L.lut);
+    uint32_t *cube = (uint32_t *)(sm + L.cube);
     uint32_t *hkey = (uint32_t *)(sm + L.hkey);
+    uint32_t *hrow = (uint32_t *)(sm + L.hrow);
+    uint8_t *hxb = (uint8_t *)(sm + L.hxb);
     uint8_t *hbin = (uint8_t *)(sm + L.hbin);
     uint16_t *hslot = (uint16_t *)(sm + L.hslot);
-    unsigned long long *mstart = (unsigned long long *)(sm + L.mstart);
-    uint32_t *mpref = (uint32_t *)(sm + L.mpref);
-    uint8_t *mbin = (uint8_t *)(sm + L.mbin);
+    uint2 *tab = (uint2 *)(sm + L.tab);
     double *mw = (double *)(sm + L.mw);
     uint32_t *mperm = (uint32_t *)(sm + L.mperm);
     uint32_t *hist = (uint32_t *)(sm + L.hist);
     unsigned long long *wlo = (unsigned long long *)(sm + L.wlo);
     unsigned long long *whi = (unsigned long long *)(sm + L.whi);
-    int *ta = (int *)(sm + L.tab);
+    int *ta = (int *)(sm + L.rtab);
     int *tb = ta + (a.nb + 1);
-    uint32_t *wtot = (uint32_t *)(sm + L.wtot);
     uint64_t *wtot64 = (uint64_t *)(sm + L.wtot);
-    uint32_t *wflag = (uint32_t *)(sm + L.wflag) + (threadIdx.x & ~63u);  // this wave's 64 tags
-    uint32_t *s_hub = (uint32_t *)(sm + L.misc);
-    unsigned long long *s_cnt = (unsigned long long *)(sm + L.misc + 8);
+    uint32_t *s_hub = (uint32_t *)(sm + L.misc);      // hub, largest label of its row
+    int *s_g = (int *)(sm + L.misc + 8);              // its catalogue (batched)
+    uint64_t *s_r = (uint64_t *)(sm + L.misc + 16);   // its row bounds
     const int tid = threadIdx.x;
+    const uint32_t glog = (uint32_t)a.glog, S = 1u << glog;
+    // the configuration table holds 16-bit LDS addresses
+    const uint32_t smb = lds_addr(sm);
+    if ((a.mode == kLut && smb + L.hist + 4 * (uint32_t)a.nconf > 0xFFFFu) ||
+        (a.mode == kCube && smb + L.cube + 4 * (uint32_t)(a.nb * a.nb * a.nb) > 0xFFFFu)) {
+        if (tid == 0) atomicOr(a.err, 2u);
+        return;
+    }
 
     for (uint32_t s = tid; s < H; s += BLOCK) hkey[s] = kEmptyKey;
     if (LDS_HIST)
@@ -451,24 +402,27 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             hist[b] = 0;
             if (WEIGHTED) { wlo[b] = 0; whi[b] = 0; }
         }
+    if (a.mode == kCube)
+        for (int t = tid; t < a.nb * a.nb * a.nb; t += BLOCK) cube[t] = 0;
     for (int b = tid; b < a.nb; b += BLOCK) {
         ta[b] = rank_a(a.nb, b);
         tb[b] = rank_b(a.nb, b);
     }
-    if (a.lut)
+    // table entry (x, y, z) at x*nb*nb + y*nb + z: the counter's absolute
+    // LDS byte address, or its index when the counters are global
+    if (a.mode == kLut)
         for (int t = tid; t < a.nb * a.nb * a.nb; t += BLOCK) {
             const int x = t / (a.nb * a.nb), y = (t / a.nb) % a.nb, z = t % a.nb;
             const int lo = min(x, min(y, z)), hi = max(x, max(y, z)), mid = x + y + z - lo - hi;
-            lut[t] = (uint16_t)(rank_a(a.nb, lo) + rank_b(a.nb, mid) + hi);
+            const int idx = rank_a(a.nb, lo) + rank_b(a.nb, mid) + hi;
+            lut[t] = (uint16_t)(LDS_HIST ? smb + L.hist + 4 * idx : idx);
         }
-    if (tid == 0) *s_cnt = 0;
     __syncthreads();
 
-    unsigned long long mytri = 0;
+    unsigned long long mytri = 0;  // global counters: this thread's hits
     uint64_t acc = 0;   // upper bound on increments since the last flush (uniform)
-    int qv = 0;         // queues found empty (thread 0)
+    HubCursor cursor;   // thread 0's claimed run of hubs
     int cur = -1;       // batched launch: catalogue whose counts the LDS holds
-    int *s_g = (int *)(sm + L.misc + 4);
     // the CSR view of the current hub: the launch's tile, or one catalogue
     const uint64_t *rp = a.rp;
     const uint32_t *hcol = a.hcol, *scol = a.scol;
@@ -477,38 +431,57 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     uint32_t s0 = a.s0, s1 = a.s1;
     unsigned long long *hout = a.hist, *tout = a.ntri;
 
-    while (true) {
-        if (tid == 0) {
-            if (BATCH) {
-                const uint32_t v = next_hub_in(a.queue, 0, a.nvirt, &qv);
-                if (v != kEmptyKey) {
-                    const int g = graph_of(a.gd, a.ngraph, v);
-                    *s_g = g;
-                    *s_hub = (uint32_t)(v - a.gd[g].v0);
-                } else {
-                    *s_hub = kEmptyKey;
-                }
-            } else {
-                *s_hub = next_hub_in(a.queue, a.h0, a.h1, &qv);
+    Walk c;
+    c.tab = tab; c.hkey = hkey; c.hbin = hbin; c.ta = ta; c.tb = tb; c.mw = mw;
+    c.mperm = mperm; c.sm = sm; c.wlo = wlo; c.whi = whi; c.wsum = a.wsum; c.w = a.w; c.perm = a.perm;
+    c.mask = mask; c.hist_addr = smb + L.hist; c.log2h = a.log2h; c.nb = a.nb; c.glog = a.glog; c.wmul = a.wmul;
+    c.anchor_lo = a.anchor_lo; c.anchor_hi = a.anchor_hi;
+
+    // thread 0 claims hubs one ahead and loads their row bounds, so a hub's
+    // bounds are in LDS when the work group starts on it
+    uint32_t nx_i = kEmptyKey;
+    int nx_g = 0;
+    uint64_t nx_r0 = 0, nx_r1 = 0;
+    auto claim = [&]() {
+        if (BATCH) {
+            const uint32_t v = next_hub_in(a.queue, 0, a.nvirt, gridDim.x, cursor);
+            nx_i = kEmptyKey;
+            if (v != kEmptyKey) {
+                nx_g = graph_of(a.gd, a.ngraph, v);
+                nx_i = (uint32_t)(v - a.gd[nx_g].v0);
+                const uint64_t *r = a.gd[nx_g].rp;
+                nx_r0 = r[nx_i];
+                nx_r1 = r[nx_i + 1];
+            }
+        } else {
+            nx_i = next_hub_in(a.queue, a.h0, a.h1, gridDim.x, cursor);
+            if (nx_i != kEmptyKey) {
+                nx_r0 = a.rp[nx_i];
+                nx_r1 = a.rp[nx_i + 1];
             }
         }
+    };
+    if (tid == 0) claim();
+
+    while (true) {
+        if (tid == 0) {
+            s_hub[0] = nx_i;
+            *s_g = nx_g;
+            s_r[0] = nx_r0;
+            s_r[1] = nx_r1;
+            if (nx_i != kEmptyKey) claim();
+        }
         __syncthreads();
-        const uint32_t i = *s_hub;
+        const uint32_t i = __builtin_amdgcn_readfirstlane(s_hub[0]);
         if (i == kEmptyKey) break;
         if (BATCH) {
-            const int g = *s_g;
+            const int g = __builtin_amdgcn_readfirstlane(*s_g);
             if (g != cur) {
                 // a new catalogue: hand the previous one its counts first
                 if (cur >= 0) {
-                    flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout);
-                    if (mytri) atomicAdd(s_cnt, mytri);
-                    mytri = 0;
+                    flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout, tout);
                     acc = 0;
                     __syncthreads();
-                    if (tid == 0 && *s_cnt) {
-                        atomicAdd(tout, *s_cnt);
-                        *s_cnt = 0;
-                    }
                 }
                 cur = g;
                 const GDesc &G = a.gd[g];
@@ -522,394 +495,132 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
                 tout = G.ntri;
             }
         }
-        const uint64_t beg = rp[i] - hbase;
-        const uint32_t d = (uint32_t)(rp[i + 1] - rp[i]);
-        if (d < 2 || (ANCHORED && a.mark && !a.mark[i])) { __syncthreads(); continue; }
-        const uint32_t kmax = hcol[beg + d - 1];  // largest label of N+(i)
-        double wi = 0.0;
-        uint32_t pi = 0;
-        if (WEIGHTED) wi = a.w[i];
-        if (ANCHORED) pi = a.perm[i];
+        const uint64_t r0 = uniform64(s_r[0]), r1 = uniform64(s_r[1]);
+        const uint64_t beg = r0 - hbase;
+        const uint32_t d = (uint32_t)(r1 - r0);
+        // spokes of this tile have labels >= jlo; their rows are addressed
+        // from rb = rp[jlo]
+        const uint32_t jlo = max(i + 1, s0);
+        if (d < 2 || jlo >= s1 || (ANCHORED && a.mark && !a.mark[i])) { __syncthreads(); continue; }
+        const uint64_t rb = uniform64(jlo == i + 1 ? r1 : rp[jlo]);
+        if (WIDE) {
+            // a launch with 2^32 or more spoke entries could exceed the
+            // 32-bit entry offsets of one hub
+            const uint32_t jhi = min(hcol[beg + d - 1], s1 - 1);
+            if (jlo <= jhi && rp[jhi + 1] - rb >= kWideSpan) {
+                if (tid == 0) atomicOr(a.err, 1u);
+                __syncthreads();
+                continue;
+            }
+        }
+        // uniform: the row loads take these as their scalar base
+        c.srow = (gbl_u32 *)uniform64((uint64_t)(scol + (rb - sbase)));
+        c.sbrow = (gbl_u8 *)uniform64((uint64_t)(sbinp + (rb - sbase)));
+        if (WEIGHTED) c.wi = a.w[i];
+        if (ANCHORED) c.pi = a.perm[i];
+        c.hout = hout;
 
-        // stage N+(i): label -> bin of (i, k); packed as (label << 8 | bin)
-        // when labels fit 24 bits, else label and bin in separate arrays
+        // stage N+(i): labels and bins in order, and label -> bin in the
+        // hash; the first spoke chunk's row bounds load alongside
+        uint32_t st0 = 0, len0 = 0;
         for (uint32_t e = tid; e < d; e += BLOCK) {
             const uint32_t k = hcol[beg + e];
-            const uint32_t v = a.packed ? ((k << 8) | hbinp[beg + e]) : k;
-            uint32_t s = label_hash(k, a.log2h);
+            const uint32_t y = hbinp[beg + e];
+            if (e == (uint32_t)tid && e + 1 < d && k >= s0 && k < s1) {
+                const uint64_t rk = rp[k];
+                st0 = (uint32_t)(rk - rb);
+                len0 = (uint32_t)(rp[k + 1] - rk);
+            }
+            if (e + 1 == d) s_hub[1] = k;   // largest label of N+(i)
+            hrow[e] = k;
+            hxb[e] = (uint8_t)y;
+            uint32_t s, v;
+            if (a.packed) {
+                s = label_hash24(k, a.log2h);
+                v = (y << 24) | k;
+            } else {
+                s = label_hash(k, a.log2h);
+                v = k;
+            }
             while (atomicCAS(&hkey[s], kEmptyKey, v) != kEmptyKey) s = (s + 1) & mask;
-            if (!a.packed) hbin[s] = hbinp[beg + e];
+            if (!a.packed) hbin[s] = (uint8_t)y;
             hslot[e] = (uint16_t)s;
         }
         __syncthreads();
+        const uint32_t kmax = s_hub[1];
 
-        // spokes in chunks of BLOCK; the last spoke cannot close a triangle;
-        // spokes outside this tile's spoke range contribute nothing here
+        // spokes in chunks of BLOCK, one per thread; the last spoke cannot
+        // close a triangle; spokes outside the tile contribute nothing here
         for (uint32_t c0 = 0; c0 + 1 < d; c0 += BLOCK) {
             const uint32_t sidx = c0 + tid;
-            uint32_t len = 0;
-            uint64_t st = 0;
-            uint8_t sb = 0;
-            double sw = 0.0;
-            uint32_t spm = 0;
+            uint32_t len = 0, st = 0, xv = 0;
             if (sidx + 1 < d) {
-                const uint32_t j = hcol[beg + sidx];
+                const uint32_t j = hrow[sidx];
                 if (j >= s0 && j < s1) {
-                    st = rp[j] - sbase;
-                    len = (uint32_t)(rp[j + 1] - rp[j]);
+                    if (c0 == 0) {
+                        st = st0;
+                        len = len0;
+                    } else {
+                        const uint64_t rj = rp[j];
+                        st = (uint32_t)(rj - rb);
+                        len = (uint32_t)(rp[j + 1] - rj);
+                    }
                     // entries of N+(j) above the largest label of N+(i) cannot match
-                    if (a.trunc && len > 16 && scol[st + len - 1] > kmax) {
+                    if (a.trunc && len > 16 && c.srow[st + len - 1] > kmax) {
                         uint32_t lo = 0, hi = len;  // first entry > kmax
                         while (lo < hi) {
                             const uint32_t mid = (lo + hi) >> 1;
-                            if (scol[st + mid] <= kmax) lo = mid + 1;
+                            if (c.srow[st + mid] <= kmax) lo = mid + 1;
                             else hi = mid;
                         }
                         len = lo;
                     }
-                    sb = hbinp[beg + sidx];
-                    if (WEIGHTED) sw = a.w[j];
-                    if (ANCHORED) spm = a.perm[j];
+                    const uint32_t x = hxb[sidx];
+                    xv = a.mode == kCube ? smb + L.cube + 4 * x * (uint32_t)(a.nb * a.nb)
+                         : a.mode == kLut ? smb + L.lut + 2 * x * (uint32_t)(a.nb * a.nb)
+                                          : x;
+                    if (WEIGHTED) mw[tid] = a.w[j];
+                    if (ANCHORED) mperm[tid] = a.perm[j];
                 }
             }
-            // one scan gives each non-empty spoke its compact index (high
-            // word) and the flat start of its row (low word)
+            const uint32_t ns = (len + S - 1) >> glog;
+            // one scan: steps before this spoke (low word), candidates (high);
+            // wtot is next written after the fill barrier below
             uint64_t tot64;
-            const uint64_t pre64 = wg_excl_scan64<BLOCK>(((uint64_t)(len > 0) << 32) | len, wtot64, tot64);
-            const uint32_t total = (uint32_t)tot64, ncomp = (uint32_t)(tot64 >> 32);
-            if (len > 0) {
-                const uint32_t c = (uint32_t)(pre64 >> 32);
-                mstart[c] = st;
-                mpref[c] = (uint32_t)pre64;
-                mbin[c] = sb;
-                if (WEIGHTED) mw[c] = sw;
-                if (ANCHORED) mperm[c] = spm;
-            }
-            if (tid == 0) mpref[ncomp] = total;
-            if (acc + total >= a.flush_limit) {
-                flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout);
+            const uint64_t pre = wg_excl_scan64<BLOCK, false>(((uint64_t)len << 32) | ns, wtot64, tot64);
+            const uint32_t t0 = (uint32_t)pre, T = (uint32_t)tot64;
+            const uint64_t cand = tot64 >> 32;
+            if (acc + cand >= a.flush_limit) {
+                flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout, tout);
                 acc = 0;
             }
-            acc += total;
-            __syncthreads();
-
-            // each wave walks one contiguous quarter of the flat range
-            if (total > 0) {
-                constexpr int NW = BLOCK / 64;
-                const uint32_t wid = tid >> 6;
-                const uint32_t r0 = (uint32_t)((uint64_t)total * wid / NW);
-                const uint32_t r1 = (uint32_t)((uint64_t)total * (wid + 1) / NW);
-                Probe c;
-                c.mpref = mpref; c.mstart = mstart; c.mbin = mbin; c.mw = mw; c.mperm = mperm;
-                c.wflag = wflag; c.hkey = hkey; c.hbin = hbin; c.lut = lut; c.ta = ta; c.tb = tb;
-                c.hist = hist; c.hout = hout; c.wlo = wlo; c.whi = whi; c.wsum = a.wsum;
-                c.scol = scol; c.sbin = sbinp; c.mask = mask; c.ncomp = ncomp; c.log2h = a.log2h;
-                c.nb = a.nb; c.wi = wi; c.wmul = a.wmul; c.w = a.w; c.pi = pi; c.perm = a.perm;
-                c.anchor_lo = a.anchor_lo; c.anchor_hi = a.anchor_hi; c.glog = a.glog;
-                if (a.glog > 0)
-                    probe_groups_any<WEIGHTED, ANCHORED, LDS_HIST>(a.packed, a.lut, c, wid, NW, mytri);
-                else if (r0 < r1)
-                    probe_any<WEIGHTED, ANCHORED, LDS_HIST>(a.packed, a.lut, c, r0, r1, mytri);
+            acc += cand;
+            if (T == 0) __syncthreads();   // (the fill barrier guards wtot otherwise)
+            // the table holds tmax steps: fill and walk it as often as needed
+            for (uint32_t w0 = 0; w0 < T; w0 += a.tmax) {
+                const uint32_t lo = max(t0, w0), hi = min(t0 + ns, w0 + a.tmax);
+                const uint32_t nfill = min(a.tmax, T - w0);
+                for (uint32_t s = lo; s < hi; ++s) {
+                    const uint32_t r = (s - t0) << glog;
+                    const uint32_t cnt = min(S, len - r);
+                    tab[s - w0] = make_uint2(st + r, cnt | ((uint32_t)tid << 7) | (xv << 16));
+                }
+                for (uint32_t s = tid; s < kUnroll3 * (BLOCK >> glog); s += BLOCK) tab[nfill + s] = make_uint2(0u, 0u);
+                __syncthreads();
+                walk3_any<BLOCK, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(a.packed, a.mode, c, nfill, mytri);
+                __syncthreads();
             }
-            __syncthreads();
         }
+        // the barrier at the top of the loop orders this before the next
+        // hub's staging
         for (uint32_t e = tid; e < d; e += BLOCK) hkey[hslot[e]] = kEmptyKey;
-        __syncthreads();
     }
 
     __syncthreads();
-    flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout);
-    if (mytri) atomicAdd(s_cnt, mytri);
-    __syncthreads();
-    if (tid == 0 && *s_cnt && tout) atomicAdd(tout, *s_cnt);
-}
-
-// ---------------------------------------------------------------------------
-// Wave-per-hub variant for small degrees: every wavefront of a work group
-// runs its own hub with its own LDS hash and spoke tables, so no work-group
-// barrier is ever needed; the configuration table is shared. Unbatched, the
-// work group's waves share one histogram that any wave may hand to global
-// memory at any time by atomically exchanging each counter with zero (no
-// increment is lost or counted twice); batched, each wave keeps its own
-// histogram because neighbouring waves may be counting other catalogues.
-
-struct Layout3w {
-    uint32_t wlo, whi, acc, hist, tab, lut, shared_end;                  // work group
-    uint32_t mstart, mw, hkey, mpref, mperm, wflag, whist, hslot, hbin, mbin, per_wave;  // per wave
-    uint32_t total;
-};
-
-__host__ __device__ inline Layout3w layout3w(int nw, uint32_t H, uint32_t maxdeg, int nconf, int nb,
-                                             bool weighted, bool anchored, bool lds_hist, bool packed,
-                                             bool lut, bool batch) {
-    const int nsh = (lds_hist && !batch) ? nconf : 0;  // shared counters
-    const int nwv = (lds_hist && batch) ? nconf : 0;   // per-wave counters
-    Layout3w L{};
-    uint32_t o = 0;
-    L.wlo = o;   if (weighted) o = lds_align(o + 8 * nsh, 16);
-    L.whi = o;   if (weighted) o = lds_align(o + 8 * nsh, 16);
-    L.acc = o;   o = lds_align(o + 16, 16);
-    L.hist = o;  o = lds_align(o + 4 * nsh, 16);
-    L.tab = o;   o = lds_align(o + 8 * (nb + 1), 16);
-    L.lut = o;   if (lut) o = lds_align(o + 2 * nb * nb * nb, 16);
-    L.shared_end = o;
-    uint32_t q = 0;
-    L.mstart = q; q = lds_align(q + 8 * 64, 16);
-    L.mw = q;     if (weighted) q = lds_align(q + 8 * 64, 16);
-    L.hkey = q;   q = lds_align(q + 4 * H, 16);
-    L.mpref = q;  q = lds_align(q + 4 * 65, 16);
-    L.mperm = q;  if (anchored) q = lds_align(q + 4 * 64, 16);
-    L.wflag = q;  q = lds_align(q + 4 * 64, 16);
-    L.whist = q;  q = lds_align(q + 4 * nwv, 16);
-    L.hslot = q;  q = lds_align(q + 2 * (maxdeg + 1), 16);
-    L.hbin = q;   if (!packed) q = lds_align(q + H, 16);
-    L.mbin = q;   q = lds_align(q + 64, 16);
-    L.per_wave = q;
-    L.total = o + (uint32_t)nw * q;
-    return L;
-}
-
-__device__ __forceinline__ uint64_t wave_excl_scan64(uint64_t v, uint64_t &total) {
-    const int lane = threadIdx.x & 63;
-    uint64_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint64_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    total = __shfl(x, 63, 64);
-    return x - v;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-template <int NW, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool BATCH>
-__global__ __launch_bounds__(NW * 64) void k_count3w(C3Args a) {
-    extern __shared__ __align__(16) unsigned char sm[];
-    const uint32_t H = 1u << a.log2h, mask = H - 1;
-    const Layout3w L = layout3w(NW, H, a.maxdeg, a.nconf, a.nb, WEIGHTED, ANCHORED, LDS_HIST, a.packed, a.lut, BATCH);
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    uint16_t *lut = (uint16_t *)(sm + L.lut);
-    int *ta = (int *)(sm + L.tab);
-    int *tb = ta + (a.nb + 1);
-    unsigned long long *s_acc = (unsigned long long *)(sm + L.acc);
-    unsigned long long *wlo = (unsigned long long *)(sm + L.wlo);
-    unsigned long long *whi = (unsigned long long *)(sm + L.whi);
-    unsigned char *wb = sm + L.shared_end + wid * L.per_wave;
-    uint32_t *hist = BATCH ? (uint32_t *)(wb + L.whist) : (uint32_t *)(sm + L.hist);
-    uint32_t *hkey = (uint32_t *)(wb + L.hkey);
-    uint8_t *hbin = (uint8_t *)(wb + L.hbin);
-    uint16_t *hslot = (uint16_t *)(wb + L.hslot);
-    unsigned long long *mstart = (unsigned long long *)(wb + L.mstart);
-    uint32_t *mpref = (uint32_t *)(wb + L.mpref);
-    uint8_t *mbin = (uint8_t *)(wb + L.mbin);
-    double *mw = (double *)(wb + L.mw);
-    uint32_t *mperm = (uint32_t *)(wb + L.mperm);
-    uint32_t *wflag = (uint32_t *)(wb + L.wflag);
-
-    for (uint32_t q = lane; q < H; q += 64) hkey[q] = kEmptyKey;
-    if (LDS_HIST) {
-        if (BATCH) {
-            for (int b = lane; b < a.nconf; b += 64) hist[b] = 0;
-        } else {
-            for (int b = tid; b < a.nconf; b += NW * 64) {
-                hist[b] = 0;
-                if (WEIGHTED) { wlo[b] = 0; whi[b] = 0; }
-            }
-        }
-    }
-    for (int b = tid; b < a.nb; b += NW * 64) {
-        ta[b] = rank_a(a.nb, b);
-        tb[b] = rank_b(a.nb, b);
-    }
-    if (a.lut)
-        for (int t = tid; t < a.nb * a.nb * a.nb; t += NW * 64) {
-            const int x = t / (a.nb * a.nb), y = (t / a.nb) % a.nb, z = t % a.nb;
-            const int lo = min(x, min(y, z)), hi = max(x, max(y, z)), mid = x + y + z - lo - hi;
-            lut[t] = (uint16_t)(rank_a(a.nb, lo) + rank_b(a.nb, mid) + hi);
-        }
-    if (tid == 0) *s_acc = 0;
-    __syncthreads();
-
-    unsigned long long mytri = 0;
-    uint64_t acc = 0;   // batched: increments since this wave's last flush
-    int qv = 0;
-    int cur = -1;
-    const uint64_t *rp = a.rp;
-    const uint32_t *hcol = a.hcol, *scol = a.scol;
-    const uint8_t *hbinp = a.hbin, *sbinp = a.sbin;
-    uint64_t hbase = a.hbase, sbase = a.sbase;
-    uint32_t s0 = a.s0, s1 = a.s1;
-    unsigned long long *hout = a.hist, *tout = a.ntri;
-
-    // batched: hand this wave's counts to its catalogue
-    auto flush_wave = [&]() {
-        if (LDS_HIST)
-            for (int b = lane; b < a.nconf; b += 64) {
-                const uint32_t v = hist[b];
-                if (v) {
-                    atomicAdd(&hout[b], (unsigned long long)v);
-                    hist[b] = 0;
-                }
-            }
-        const unsigned long long t = wave_sum64(mytri);
-        if (lane == 0 && t) atomicAdd(tout, t);
-        mytri = 0;
-    };
-    // unbatched: any wave may move the shared counters to global memory
-    auto flush_shared_exchange = [&]() {
-        for (int b = lane; b < a.nconf; b += 64) {
-            const uint32_t v = atomicExch(&hist[b], 0u);
-            if (v) atomicAdd(&a.hist[b], (unsigned long long)v);
-            if (WEIGHTED) {
-                const unsigned long long lo = atomicExch(&wlo[b], 0ull);
-                const unsigned long long hi = atomicExch(&whi[b], 0ull);
-                if (lo | hi) add128(&a.wsum[2 * b], ((unsigned __int128)hi << 32) + (unsigned __int128)lo);
-            }
-        }
-    };
-
-    while (true) {
-        uint32_t v = kEmptyKey;
-        int g = 0;
-        if (lane == 0) {
-            if (BATCH) {
-                v = next_hub_in(a.queue, 0, a.nvirt, &qv);
-                if (v != kEmptyKey) {
-                    g = graph_of(a.gd, a.ngraph, v);
-                    v = (uint32_t)(v - a.gd[g].v0);
-                }
-            } else {
-                v = next_hub_in(a.queue, a.h0, a.h1, &qv);
-            }
-        }
-        const uint32_t i = __builtin_amdgcn_readfirstlane(v);
-        if (i == kEmptyKey) break;
-        if (BATCH) {
-            g = __builtin_amdgcn_readfirstlane(g);
-            if (g != cur) {
-                if (cur >= 0) flush_wave();
-                acc = 0;
-                cur = g;
-                const GDesc &G = a.gd[g];
-                rp = G.rp;
-                hcol = scol = G.col;
-                hbinp = sbinp = G.bin;
-                hbase = sbase = 0;
-                s0 = 0;
-                s1 = G.n;
-                hout = G.hist;
-                tout = G.ntri;
-            }
-        }
-        const uint64_t beg = rp[i] - hbase;
-        const uint32_t d = (uint32_t)(rp[i + 1] - rp[i]);
-        if (d < 2 || (ANCHORED && a.mark && !a.mark[i])) continue;
-        const uint32_t kmax = hcol[beg + d - 1];
-        const double wi = WEIGHTED ? a.w[i] : 0.0;
-        const uint32_t pi = ANCHORED ? a.perm[i] : 0;
-
-        for (uint32_t e = lane; e < d; e += 64) {
-            const uint32_t k = hcol[beg + e];
-            const uint32_t val = a.packed ? ((k << 8) | hbinp[beg + e]) : k;
-            uint32_t q = label_hash(k, a.log2h);
-            while (atomicCAS(&hkey[q], kEmptyKey, val) != kEmptyKey) q = (q + 1) & mask;
-            if (!a.packed) hbin[q] = hbinp[beg + e];
-            hslot[e] = (uint16_t)q;
-        }
-        wave_lds_sync();
-
-        for (uint32_t c0 = 0; c0 + 1 < d; c0 += 64) {
-            const uint32_t sidx = c0 + lane;
-            uint32_t len = 0;
-            uint64_t st = 0;
-            uint8_t sb = 0;
-            double sw = 0.0;
-            uint32_t spm = 0;
-            if (sidx + 1 < d) {
-                const uint32_t j = hcol[beg + sidx];
-                if (j >= s0 && j < s1) {
-                    st = rp[j] - sbase;
-                    len = (uint32_t)(rp[j + 1] - rp[j]);
-                    if (a.trunc && len > 16 && scol[st + len - 1] > kmax) {
-                        uint32_t lo = 0, hi = len;
-                        while (lo < hi) {
-                            const uint32_t mid = (lo + hi) >> 1;
-                            if (scol[st + mid] <= kmax) lo = mid + 1;
-                            else hi = mid;
-                        }
-                        len = lo;
-                    }
-                    sb = hbinp[beg + sidx];
-                    if (WEIGHTED) sw = a.w[j];
-                    if (ANCHORED) spm = a.perm[j];
-                }
-            }
-            uint64_t tot64;
-            const uint64_t pre64 = wave_excl_scan64(((uint64_t)(len > 0) << 32) | len, tot64);
-            const uint32_t total = (uint32_t)tot64, ncomp = (uint32_t)(tot64 >> 32);
-            if (total == 0) continue;
-            if (len > 0) {
-                const uint32_t c = (uint32_t)(pre64 >> 32);
-                mstart[c] = st;
-                mpref[c] = (uint32_t)pre64;
-                mbin[c] = sb;
-                if (WEIGHTED) mw[c] = sw;
-                if (ANCHORED) mperm[c] = spm;
-            }
-            if (lane == 0) mpref[ncomp] = total;
-            wave_lds_sync();
-            if (LDS_HIST) {
-                if (BATCH) {
-                    if (acc + total >= a.flush_limit) {
-                        flush_wave();
-                        acc = 0;
-                    }
-                    acc += total;
-                } else {
-                    // the group's increments since the start; the wave that
-                    // crosses a multiple of 2^30 moves the shared counters out
-                    unsigned long long old = 0;
-                    if (lane == 0) old = atomicAdd(s_acc, (unsigned long long)total);
-                    old = __shfl(old, 0, 64);
-                    const unsigned long long lim = a.flush_limit >> 2;
-                    if (old / lim != (old + total) / lim) flush_shared_exchange();
-                }
-            }
-            Probe c;
-            c.mpref = mpref; c.mstart = mstart; c.mbin = mbin; c.mw = mw; c.mperm = mperm;
-            c.wflag = wflag; c.hkey = hkey; c.hbin = hbin; c.lut = lut; c.ta = ta; c.tb = tb;
-            c.hist = hist; c.hout = BATCH ? hout : a.hist; c.wlo = wlo; c.whi = whi; c.wsum = a.wsum;
-            c.scol = scol; c.sbin = sbinp; c.mask = mask; c.ncomp = ncomp; c.log2h = a.log2h;
-            c.nb = a.nb; c.wi = wi; c.wmul = a.wmul; c.w = a.w; c.pi = pi; c.perm = a.perm;
-            c.anchor_lo = a.anchor_lo; c.anchor_hi = a.anchor_hi; c.glog = a.glog;
-            if (a.glog > 0) probe_groups_any<WEIGHTED, ANCHORED, LDS_HIST>(a.packed, a.lut, c, 0, 1, mytri);
-            else probe_any<WEIGHTED, ANCHORED, LDS_HIST>(a.packed, a.lut, c, 0, total, mytri);
-            wave_lds_sync();
-        }
-        for (uint32_t e = lane; e < d; e += 64) hkey[hslot[e]] = kEmptyKey;
-        wave_lds_sync();
-    }
-
-    if (BATCH) {
-        if (cur >= 0) flush_wave();
-    } else {
-        const unsigned long long t = wave_sum64(mytri);
-        if (lane == 0 && t) atomicAdd(a.ntri, t);
-        __syncthreads();
-        if (LDS_HIST)
-            for (int b = tid; b < a.nconf; b += NW * 64) {
-                const uint32_t v = hist[b];
-                if (v) atomicAdd(&a.hist[b], (unsigned long long)v);
-                if (WEIGHTED) {
-                    const unsigned long long lo = wlo[b], hi = whi[b];
-                    if (lo | hi) add128(&a.wsum[2 * b], ((unsigned __int128)hi << 32) + (unsigned __int128)lo);
-                }
-            }
+    flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout, tout);
+    if (!LDS_HIST) {
+        mytri = wave_sum64(mytri);
+        if ((tid & 63) == 0 && mytri && tout) atomicAdd(tout, mytri);
     }
 }
 
@@ -919,151 +630,124 @@ __global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
         p[i] = 0;
 }
 
-template <int B, bool W, bool A, bool LH, bool BATCH = false>
+template <int B, bool W, bool A, bool LH, bool BATCH = false, bool WIDE = false>
 void launch3(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds) {
-    const void *kern = reinterpret_cast<const void *>(&k_count3<B, W, A, LH, BATCH>);
+    const void *kern = reinterpret_cast<const void *>(&k_count3<B, W, A, LH, BATCH, WIDE>);
     if (lds > 65536)
         GS_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
-    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count3<B, W, A, LH, BATCH>, B, lds));
+    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count3<B, W, A, LH, BATCH, WIDE>, B, lds));
     if (per_cu < 1) fail(GS_EUNSUPPORTED, "count kernel does not fit a compute unit");
     uint32_t grid = (uint32_t)ctx.n_cu * (uint32_t)per_cu;
     grid = (grid + kNumQueues - 1) / kNumQueues * kNumQueues;
-    k_count3<B, W, A, LH, BATCH><<<dim3(grid), dim3(B), lds, s>>>(a);
+    if (getenv("GS_PLAN_LOG")) fprintf(stderr, "count3 launch: %d groups per CU, grid %u\n", per_cu, grid);
+    k_count3<B, W, A, LH, BATCH, WIDE><<<dim3(grid), dim3(B), lds, s>>>(a);
     GS_HIP(hipGetLastError());
 }
 
-template <int B>
-void launch3_b(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds, bool w, bool an, bool lh) {
+template <int B, bool WIDE>
+void launch3_bw(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds, bool w, bool an, bool lh) {
     if (lh) {
-        if (!w && !an) launch3<B, false, false, true>(ctx, s, a, lds);
-        else if (w && !an) launch3<B, true, false, true>(ctx, s, a, lds);
-        else if (!w && an) launch3<B, false, true, true>(ctx, s, a, lds);
-        else launch3<B, true, true, true>(ctx, s, a, lds);
+        if (!w && !an) launch3<B, false, false, true, false, WIDE>(ctx, s, a, lds);
+        else if (w && !an) launch3<B, true, false, true, false, WIDE>(ctx, s, a, lds);
+        else if (!w && an) launch3<B, false, true, true, false, WIDE>(ctx, s, a, lds);
+        else launch3<B, true, true, true, false, WIDE>(ctx, s, a, lds);
     } else {
-        if (!w && !an) launch3<B, false, false, false>(ctx, s, a, lds);
-        else if (w && !an) launch3<B, true, false, false>(ctx, s, a, lds);
-        else if (!w && an) launch3<B, false, true, false>(ctx, s, a, lds);
-        else launch3<B, true, true, false>(ctx, s, a, lds);
+        if (!w && !an) launch3<B, false, false, false, false, WIDE>(ctx, s, a, lds);
+        else if (w && !an) launch3<B, true, false, false, false, WIDE>(ctx, s, a, lds);
+        else if (!w && an) launch3<B, false, true, false, false, WIDE>(ctx, s, a, lds);
+        else launch3<B, true, true, false, false, WIDE>(ctx, s, a, lds);
     }
 }
 
-constexpr uint32_t kWaveMaxDeg = 512;  // wave-per-hub kernel up to this forward degree
-
-template <int NW, bool W, bool A, bool LH, bool BATCH>
-void launch3w(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds) {
-    const void *kern = reinterpret_cast<const void *>(&k_count3w<NW, W, A, LH, BATCH>);
-    if (lds > 65536)
-        GS_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    int per_cu = 0;
-    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count3w<NW, W, A, LH, BATCH>, NW * 64, lds));
-    if (per_cu < 1) fail(GS_EUNSUPPORTED, "count kernel does not fit a compute unit");
-    uint32_t grid = (uint32_t)ctx.n_cu * (uint32_t)per_cu;
-    grid = (grid + kNumQueues - 1) / kNumQueues * kNumQueues;
-    k_count3w<NW, W, A, LH, BATCH><<<dim3(grid), dim3(NW * 64), lds, s>>>(a);
-    GS_HIP(hipGetLastError());
-}
-
-template <int NW, bool BATCH>
-void launch3w_n(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds, bool w, bool an, bool lh) {
-    if (BATCH) {
-        if (lh) launch3w<NW, false, false, true, true>(ctx, s, a, lds);
-        else launch3w<NW, false, false, false, true>(ctx, s, a, lds);
-        return;
-    }
-    if (lh) {
-        if (!w && !an) launch3w<NW, false, false, true, false>(ctx, s, a, lds);
-        else if (w && !an) launch3w<NW, true, false, true, false>(ctx, s, a, lds);
-        else if (!w && an) launch3w<NW, false, true, true, false>(ctx, s, a, lds);
-        else launch3w<NW, true, true, true, false>(ctx, s, a, lds);
-    } else {
-        if (!w && !an) launch3w<NW, false, false, false, false>(ctx, s, a, lds);
-        else if (w && !an) launch3w<NW, true, false, false, false>(ctx, s, a, lds);
-        else if (!w && an) launch3w<NW, false, true, false, false>(ctx, s, a, lds);
-        else launch3w<NW, true, true, false, false>(ctx, s, a, lds);
-    }
-}
-
-// Lanes per spoke group from the mean forward row length (GS_GLOG / GS_MAP3
-// override): short rows in small groups, long rows across the wavefront.
+// Entries per step from the mean forward row length (GS_GLOG overrides):
+// about a tenth of a row, so that padding the last step of a row costs
+// little and most rows still take several steps.
 int group_log(double mean_row) {
-    if (const char *em = getenv("GS_MAP3"))
-        if (strcmp(em, "flat") == 0) return 0;
     if (const char *eg = getenv("GS_GLOG")) return std::max(0, std::min(6, atoi(eg)));
-    if (mean_row < 24) return 3;
-    if (mean_row < 64) return 4;
-    if (mean_row < 160) return 5;
-    return 6;
+    int g = 0;
+    while (g < 6 && (double)(2u << g) * 10.0 <= mean_row) ++g;
+    return g;
 }
 
 struct Plan3 {
-    int nw = 0;           // > 0: wave-per-hub kernel with nw waves per group
     int block = 256;
+    int glog = 0;
     int trunc = 0;
     bool packed = true;
-    bool lut = true;
+    int mode = kLut;
     int log2h = 6;
     bool lds_hist = true;
+    uint32_t tmax = 1024, tcap = 0;
     uint32_t lds = 0;
 };
 
-void launch3_any(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P, bool w, bool an) {
-    if (P.nw == 8) launch3w_n<8, false>(ctx, s, a, P.lds, w, an, P.lds_hist);
-    else if (P.nw == 4) launch3w_n<4, false>(ctx, s, a, P.lds, w, an, P.lds_hist);
-    else if (P.nw == 2) launch3w_n<2, false>(ctx, s, a, P.lds, w, an, P.lds_hist);
-    else if (P.block == 512) launch3_b<512>(ctx, s, a, P.lds, w, an, P.lds_hist);
-    else launch3_b<256>(ctx, s, a, P.lds, w, an, P.lds_hist);
+// wide: the launch's spoke rows hold 2^30 entries or more (GS_WIDE=1 forces
+// the wide addressing, for tests)
+void launch3_any(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P, bool w, bool an, bool wide) {
+    if (const char *ew = getenv("GS_WIDE")) wide = wide || atoi(ew) != 0;
+    if (wide) {
+        if (P.block == 512) launch3_bw<512, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
+        else if (P.block == 128) launch3_bw<128, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
+        else launch3_bw<256, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
+    } else {
+        if (P.block == 512) launch3_bw<512, false>(ctx, s, a, P.lds, w, an, P.lds_hist);
+        else if (P.block == 128) launch3_bw<128, false>(ctx, s, a, P.lds, w, an, P.lds_hist);
+        else launch3_bw<256, false>(ctx, s, a, P.lds, w, an, P.lds_hist);
+    }
 }
 
-// Work-group size and LDS plan: hash table at load factor <= 0.7, 512
-// threads per hub for long rows (more waves per CU when LDS limits groups).
+// Work-group size and LDS plan: hash table at load factor <= 1/2 where it
+// fits (<= 0.7 otherwise), 512 threads per hub for long rows.
 Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchored, uint64_t max_n,
-            bool batch = false) {
+            double mean_row) {
     Plan3 p;
+    p.glog = group_log(mean_row);
+    // GS_PACK=0 / GS_MODE3=rank|lut|cube / GS_TMAX force other paths (tests)
     p.packed = max_n < (1ull << 24) - 1;
-    p.lut = nb <= kLutMaxBins;
+    if (const char *ep = getenv("GS_PACK")) p.packed = p.packed && atoi(ep) != 0;
     const int nconf = (int)n_configs(nb);
     if (maxdeg > 16384) fail(GS_EUNSUPPORTED, "forward degree above 16384");
-    // small degrees: one wavefront per hub (GS_KERNEL3=team|wave overrides)
-    const char *ek = getenv("GS_KERNEL3");
-    const bool wave = ek ? strcmp(ek, "wave") == 0 : maxdeg <= kWaveMaxDeg;
-    if (wave) {
-        p.nw = 4;
-        if (const char *ew = getenv("GS_WAVES3")) p.nw = atoi(ew) == 8 ? 8 : (atoi(ew) == 2 ? 2 : 4);
-        p.trunc = 0;
-        if (const char *et = getenv("GS_TRUNC")) p.trunc = atoi(et) != 0;
-        uint32_t H = 64;
-        while ((uint64_t)H * 7 < (uint64_t)maxdeg * 10) { H <<= 1; ++p.log2h; }
-        p.lds_hist = nconf <= 8192;
-        Layout3w L = layout3w(p.nw, H, maxdeg, nconf, nb, weighted, anchored, p.lds_hist, p.packed, p.lut, batch);
-        if ((int)L.total > ctx.max_lds && p.lds_hist) {
-            p.lds_hist = false;
-            L = layout3w(p.nw, H, maxdeg, nconf, nb, weighted, anchored, false, p.packed, p.lut, batch);
-        }
-        if ((int)L.total <= ctx.max_lds) {
-            p.lds = L.total;
-            p.block = 64 * p.nw;
-            return p;
-        }
-        p.nw = 0;  // does not fit: team kernel
-        p.log2h = 6;
-    }
-    if (const char *eb = getenv("GS_BLOCK3")) p.block = atoi(eb) == 512 ? 512 : 256;
+    if (const char *eb = getenv("GS_BLOCK3")) p.block = atoi(eb) == 512 ? 512 : atoi(eb) == 128 ? 128 : 256;
     else p.block = maxdeg >= 1024 ? 512 : 256;
+    p.tmax = 4 * (uint32_t)p.block;
+    if (const char *em = getenv("GS_TMAX")) p.tmax = std::max(64, std::min(1 << 16, atoi(em)));
+    p.tcap = p.tmax + kUnroll3 * ((uint32_t)p.block >> p.glog);
     // the per-spoke binary search pays off on long rows only
     if (const char *et = getenv("GS_TRUNC")) p.trunc = atoi(et) != 0;
     else p.trunc = maxdeg >= 1024;
-    uint32_t H = 64;
-    while ((uint64_t)H * 7 < (uint64_t)maxdeg * 10) { H <<= 1; ++p.log2h; }
-    // per-work-group LDS histograms while they fit; global atomics beyond
+    // per-work-group LDS counters while they fit; global atomics beyond
     p.lds_hist = nconf <= 8192;
-    Layout3 L = layout3(p.block, H, maxdeg, nconf, nb, weighted, anchored, p.lds_hist, p.packed, p.lut);
-    if ((int)L.total > ctx.max_lds && p.lds_hist) {
-        p.lds_hist = false;
-        L = layout3(p.block, H, maxdeg, nconf, nb, weighted, anchored, false, p.packed, p.lut);
+    int want = nb <= kCubeMaxBins && !weighted ? kCube : nb <= kLutMaxBins ? kLut : kRank;
+    if (const char *e = getenv("GS_MODE3")) {
+        if (strcmp(e, "rank") == 0) want = kRank;
+        else if (strcmp(e, "lut") == 0 && nb <= kLutMaxBins) want = kLut;
+        else if (strcmp(e, "cube") == 0 && nb <= kCubeMaxBins && !weighted) want = kCube;
     }
-    if ((int)L.total > ctx.max_lds) fail(GS_EUNSUPPORTED, "LDS footprint too large for this degree");
-    p.lds = L.total;
+    for (int half = 1; half >= 0; --half) {
+        uint32_t H = 64;
+        p.log2h = 6;
+        while (half ? H < 2 * maxdeg : (uint64_t)H * 7 < (uint64_t)maxdeg * 10) { H <<= 1; ++p.log2h; }
+        for (int lh = p.lds_hist; lh >= 0; --lh) {
+            // the cube lives in LDS; table entries hold 16-bit counter addresses
+            int mode = want;
+            if (mode == kCube && !lh) mode = nb <= kLutMaxBins ? kLut : kRank;
+            if (mode == kLut && lh && 4 * (uint64_t)nconf + 2 * (uint64_t)nb * nb * nb >= 65536) mode = kRank;
+            const Layout3 L = layout3(p.block, H, maxdeg, p.tcap, nconf, nb, weighted, anchored, lh, p.packed, mode);
+            if ((int)L.total <= ctx.max_lds) {
+                p.lds_hist = lh;
+                p.mode = mode;
+                p.lds = L.total;
+                if (getenv("GS_PLAN_LOG"))
+                    fprintf(stderr, "count3 plan: maxdeg %u mean_row %.1f block %d glog %d mode %d packed %d H %u "
+                                    "tmax %u tcap %u lds_hist %d trunc %d lds %u\n",
+                            maxdeg, mean_row, p.block, p.glog, p.mode, (int)p.packed, H, p.tmax, p.tcap,
+                            (int)p.lds_hist, p.trunc, p.lds);
+                return p;
+            }
+        }
+    }
+    fail(GS_EUNSUPPORTED, "LDS footprint too large for this degree");
     return p;
 }
 
@@ -1092,8 +776,8 @@ uint64_t flush_limit_for(uint32_t maxdeg, uint64_t per_chunk_factor) {
 
 template <int B>
 void launch3_batch(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P) {
-    if (P.lds_hist) launch3<B, false, false, true, true>(ctx, s, a, P.lds);
-    else launch3<B, false, false, false, true>(ctx, s, a, P.lds);
+    if (P.lds_hist) launch3<B, false, false, true, true, false>(ctx, s, a, P.lds);
+    else launch3<B, false, false, false, true, false>(ctx, s, a, P.lds);
 }
 
 }  // namespace
@@ -1119,14 +803,18 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     const int nconf = (int)n_configs(nb);
     uint64_t max_n = 0;
     for (int g = 0; g < ng; ++g) max_n = std::max<uint64_t>(max_n, (uint64_t)gs[g]->n);
-    const Plan3 P = plan3(ctx, maxdeg, nb, false, false, max_n, true);
     uint64_t sum_e = 0;
-    for (int g = 0; g < ng; ++g) sum_e += gs[g]->n_edges;
-    const int glog_sel = group_log(nvirt ? (double)sum_e / (double)nvirt : 0.0);
+    for (int g = 0; g < ng; ++g) {
+        sum_e += gs[g]->n_edges;
+        if (gs[g]->n_edges >= kNarrowSpan) fail(GS_EUNSUPPORTED, "batched catalogue with 2^30 or more edges");
+    }
+    const Plan3 P = plan3(ctx, maxdeg, nb, false, false, max_n, nvirt ? (double)sum_e / (double)nvirt : 0.0);
     b.ng = ng;
     b.nconf = nconf;
     const size_t per = (size_t)nconf + 1;
-    const size_t words = (size_t)ng * per + kNumQueues / 2 + 1;
+    // device staging: counts per catalogue | error word | queues (256-byte aligned)
+    const size_t qoff = ((size_t)ng * per + 1 + 31) / 32 * 32;
+    const size_t words = qoff + kQueueWords / 2;
     b.dv.alloc(words * 8);
     unsigned long long *dv = b.dv.as<unsigned long long>();
     b.hostdesc.alloc(sizeof(GDesc) * ng);
@@ -1155,20 +843,21 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     a.log2h = P.log2h;
     a.trunc = P.trunc;
     a.packed = P.packed;
-    a.lut = P.lut;
-    a.glog = glog_sel;
+    a.mode = P.mode;
+    a.glog = P.glog;
     a.maxdeg = maxdeg;
+    a.tmax = P.tmax;
+    a.tcap = P.tcap;
     a.flush_limit = flush_limit_for(maxdeg, P.block);
-    a.queue = (uint32_t *)(dv + (size_t)ng * per);
+    a.queue = (uint32_t *)(dv + qoff);
+    a.err = (uint32_t *)(dv + (size_t)ng * per);
     if (nvirt > 0) {
-        if (P.nw == 8) launch3w_n<8, true>(ctx, s, a, P.lds, false, false, P.lds_hist);
-        else if (P.nw == 4) launch3w_n<4, true>(ctx, s, a, P.lds, false, false, P.lds_hist);
-        else if (P.nw == 2) launch3w_n<2, true>(ctx, s, a, P.lds, false, false, P.lds_hist);
-        else if (P.block == 512) launch3_batch<512>(ctx, s, a, P);
+        if (P.block == 512) launch3_batch<512>(ctx, s, a, P);
+        else if (P.block == 128) launch3_batch<128>(ctx, s, a, P);
         else launch3_batch<256>(ctx, s, a, P);
     }
-    b.out.alloc(sizeof(unsigned long long) * (size_t)ng * per);
-    GS_HIP(hipMemcpyAsync(b.out.p, dv, sizeof(unsigned long long) * (size_t)ng * per, hipMemcpyDeviceToHost, s));
+    b.out.alloc(sizeof(unsigned long long) * ((size_t)ng * per + 1));
+    GS_HIP(hipMemcpyAsync(b.out.p, dv, sizeof(unsigned long long) * ((size_t)ng * per + 1), hipMemcpyDeviceToHost, s));
     if (!b.done) GS_HIP(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
     GS_HIP(hipEventRecord(b.done, s));
 }
@@ -1181,14 +870,15 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     const bool anchored = anchors != nullptr;
     if (anchored && (anchors->lo > anchors->hi)) fail(GS_EINVAL, "anchor range lo > hi");
     const uint32_t maxdeg = g.max_deg;
-    const Plan3 P = plan3(ctx, maxdeg, nb, weighted, anchored, (uint64_t)g.n);
-    const int glog_sel = group_log(g.n ? (double)g.n_edges / (double)g.n : 0.0);
+    const Plan3 P = plan3(ctx, maxdeg, nb, weighted, anchored, (uint64_t)g.n,
+                          g.n ? (double)g.n_edges / (double)g.n : 0.0);
     const int W = g.n_windows;
     const int ntiles = W * (W + 1) / 2;
 
-    // device staging: hist | wsum | ntri | queues (8 per tile)
-    const size_t qwords = (size_t)ntiles * kNumQueues / 2 + 1;
-    const size_t words = 3 * (size_t)nconf + 1 + qwords;
+    // device staging: hist | wsum | ntri | error word | queue sets, one per
+    // tile (256-byte aligned)
+    const size_t qoff = (3 * (size_t)nconf + 2 + 31) / 32 * 32;
+    const size_t words = qoff + (size_t)ntiles * kQueueWords / 2;
     unsigned long long *dv = (unsigned long long *)ctx.scratch_get(words * 8);
     C3Args a{};
     a.rp = g.row_ptr.as<uint64_t>();
@@ -1199,9 +889,11 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.log2h = P.log2h;
     a.trunc = P.trunc;
     a.packed = P.packed;
-    a.lut = P.lut;
-    a.glog = glog_sel;
+    a.mode = P.mode;
+    a.glog = P.glog;
     a.maxdeg = maxdeg;
+    a.tmax = P.tmax;
+    a.tcap = P.tcap;
     a.anchor_lo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
     a.anchor_hi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;
     a.wmul = std::ldexp(1.0, g.wscale);
@@ -1209,7 +901,8 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.hist = dv;
     a.wsum = dv + nconf;
     a.ntri = dv + 3 * (size_t)nconf;
-    uint32_t *queues = (uint32_t *)(dv + 3 * (size_t)nconf + 1);
+    a.err = (uint32_t *)(dv + 3 * (size_t)nconf + 1);
+    uint32_t *queues = (uint32_t *)(dv + qoff);
 
     hipStream_t s = ctx.stream;
     GS_HIP(hipEventRecord(ctx.ev[0], s));
@@ -1231,7 +924,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
         a.h0 = a.s0 = 0;
         a.h1 = a.s1 = (uint32_t)g.n;
         a.queue = queues;
-        launch3_any(ctx, s, a, P, weighted, anchored);
+        launch3_any(ctx, s, a, P, weighted, anchored, g.n_edges >= kNarrowSpan);
     } else if (g.n > 0) {
         // host-tiled graph: spoke window S resident, hub windows H <= S
         // streamed through; copies of the next tile's windows overlap the
@@ -1240,10 +933,10 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
         for (int w = 0; w < W; ++w) maxE = std::max<uint64_t>(maxE, g.win_edge[w + 1] - g.win_edge[w]);
         DevBuf scol[2], sbin[2], hcol[2], hbin[2];
         for (int k = 0; k < 2; ++k) {
-            scol[k].alloc(maxE * 4);
-            sbin[k].alloc(maxE);
-            hcol[k].alloc(maxE * 4);
-            hbin[k].alloc(maxE);
+            scol[k].alloc((maxE + kRowSlack) * 4);
+            sbin[k].alloc(maxE + kRowSlack);
+            hcol[k].alloc((maxE + kRowSlack) * 4);
+            hbin[k].alloc(maxE + kRowSlack);
         }
         struct Tile { int S, H, hslot; bool first_of_S, last_of_S; };
         std::vector<Tile> tiles;
@@ -1302,8 +995,8 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
             b.hbase = g.win_edge[t.H];
             b.h0 = (uint32_t)g.win[t.H];
             b.h1 = (uint32_t)g.win[t.H + 1];
-            b.queue = queues + ti * kNumQueues;
-            launch3_any(ctx, s, b, P, weighted, anchored);
+            b.queue = queues + ti * kQueueWords;
+            launch3_any(ctx, s, b, P, weighted, anchored, maxE >= kNarrowSpan);
             if (t.hslot >= 0) GS_HIP(hipEventRecord(ev_hfree[t.hslot], s));
             if (t.last_of_S) GS_HIP(hipEventRecord(ev_sfree[sk], s));
         }
@@ -1317,10 +1010,13 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
         }
     }
     GS_HIP(hipEventRecord(ctx.ev[3], s));
-    std::vector<unsigned long long> h(3 * (size_t)nconf + 1);
+    std::vector<unsigned long long> h(3 * (size_t)nconf + 2);
     GS_HIP(hipMemcpyAsync(h.data(), dv, h.size() * 8, hipMemcpyDeviceToHost, s));
     GS_HIP(hipEventRecord(ctx.ev[1], s));
     GS_HIP(hipStreamSynchronize(s));
+    if (h[3 * (size_t)nconf + 1] & 1)
+        fail(GS_EUNSUPPORTED, "the spoke rows of a hub span 2^32 or more entries");
+    if (h[3 * (size_t)nconf + 1] & 2) fail(GS_EUNSUPPORTED, "configuration table beyond 16-bit LDS addresses");
     for (int c = 0; c < nconf; ++c) hist[c] = h[c];
     if (weighted)
         for (int c = 0; c < 2 * nconf; ++c) wsum[c] = h[nconf + c];

@@ -166,11 +166,11 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
 
     unsigned long long mycl = 0;
     uint64_t acc = 0;
-    int qv = 0;
+    HubCursor cursor;   // thread 0's claimed run of hubs
     const double Lb = a.L, half = a.half;
 
     while (true) {
-        if (tid == 0) *s_hub = next_hub(a.queue, a.n, &qv);
+        if (tid == 0) *s_hub = next_hub_in(a.queue, 0, a.n, gridDim.x, cursor);
         __syncthreads();
         const uint32_t i = *s_hub;
         if (i == kEmptyKey) break;
@@ -380,7 +380,8 @@ void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_
         fail(GS_EUNSUPPORTED, "parity kernel LDS footprint too large (forward degree " +
                                   std::to_string(maxdeg) + ", " + std::to_string(L.total) + " bytes)");
 
-    const size_t words = 3 * (size_t)nconf + 1 + kNumQueues + 2;
+    const size_t qoff = (3 * (size_t)nconf + 1 + 31) / 32 * 32;   // queues 256-byte aligned
+    const size_t words = qoff + kQueueWords / 2;
     unsigned long long *dv = (unsigned long long *)ctx.scratch_get(words * 8 + 256 * 8);
     double *dthr = (double *)(dv + words);
     C4Args a{};
@@ -409,7 +410,7 @@ void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_
         a.flush_limit = 0xFFFFFFFFull;
     a.hist = dv;
     a.ncl = dv + 3 * (size_t)nconf;
-    a.queue = (uint32_t *)(dv + 3 * (size_t)nconf + 1);
+    a.queue = (uint32_t *)(dv + qoff);
 
     hipStream_t s = ctx.stream;
     GS_HIP(hipEventRecord(ctx.ev[0], s));

@@ -10,6 +10,27 @@ constexpr int kNumQueues = 8;
 
 __host__ __device__ inline uint32_t lds_align(uint32_t x, uint32_t a) { return (x + a - 1) / a * a; }
 
+// Pointers with their address space spelled out: global rows whose loads
+// take a scalar base and a 32-bit lane offset, and LDS words addressed by
+// absolute byte address (no per-access base add).
+typedef __attribute__((address_space(1))) const uint32_t gbl_u32;
+typedef __attribute__((address_space(1))) const uint8_t gbl_u8;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) const uint16_t lds_u16;
+
+// Byte address of an LDS location.
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return (uint32_t)(size_t)(__attribute__((address_space(3))) const void *)p;
+}
+
+// A value the whole wavefront holds alike, moved to scalar registers (so a
+// pointer built from it can serve as the scalar base of vector loads).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Fibonacci hash of a label into a table of 2^log2h slots.
 __device__ __forceinline__ uint32_t label_hash(uint32_t k, int log2h) {
     return (k * 2654435769u) >> (32 - log2h);
@@ -40,8 +61,10 @@ __device__ __forceinline__ uint32_t wg_excl_scan(uint32_t v, uint32_t *wtot, uin
     return off + x - v;
 }
 
-// Exclusive scan of one u64 per thread over the work group; ends with a barrier.
-template <int BLOCK>
+// Exclusive scan of one u64 per thread over the work group. With TRAIL it
+// ends with a barrier so that wtot can be reused at once; without, the
+// caller puts a barrier between this call and the next write of wtot.
+template <int BLOCK, bool TRAIL = true>
 __device__ __forceinline__ uint64_t wg_excl_scan64(uint64_t v, uint64_t *wtot, uint64_t &total) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint64_t x = v;
@@ -60,7 +83,7 @@ __device__ __forceinline__ uint64_t wg_excl_scan64(uint64_t v, uint64_t *wtot, u
         tot += t;
     }
     total = tot;
-    __syncthreads();
+    if (TRAIL) __syncthreads();
     return off + x - v;
 }
 
@@ -97,17 +120,50 @@ __device__ __forceinline__ uint32_t upper_index(const uint32_t *pref, uint32_t n
     return lo;
 }
 
-// Next hub from eight label-range queues, starting at this work group's XCD
-// (work groups are placed on the eight XCDs round-robin by block index).
-// Called by one thread; *qv counts queues found empty. kEmptyKey when done.
-__device__ __forceinline__ uint32_t next_hub(uint32_t *queue, uint32_t n, int *qv) {
+// Hubs are handed out from eight label-range queues, one per slice of the
+// hub range; a team (a work group, or one wavefront) starts on the queue of
+// its own XCD (work groups are placed on the eight XCDs round-robin by block
+// index) so nearby hubs share that XCD's L2, and moves on to the other queues
+// once its own is empty. Each counter sits in a 256-byte line of its own so
+// that the eight never contend for one line, and a team claims a run of
+// consecutive hubs per atomic: the run is an eighth of the queue's remaining
+// share per team, at most kMaxRun (guided self-scheduling), so the number of
+// atomics grows with the log of the hub count rather than with the count,
+// while the last hubs still go out one at a time.
+constexpr int kQueueStride = 64;                       // u32 words between counters
+constexpr int kQueueWords = kNumQueues * kQueueStride;  // words per queue set
+constexpr uint32_t kMaxRun = 32;
+
+struct HubCursor {
+    uint32_t cur = 0, end = 0;  // unclaimed part of the current run
+    uint32_t run = 0;           // length of the next claim (0: from the queue's full share)
+    int qv = 0;                 // queues found empty
+};
+
+// Next hub of [h0, h1) for the calling thread (one per team), or kEmptyKey.
+// teams: how many teams draw from these queues.
+__device__ __forceinline__ uint32_t next_hub_in(uint32_t *queue, uint32_t h0, uint32_t h1, uint32_t teams,
+                                                HubCursor &c) {
+    if (c.cur < c.end) return c.cur++;
     const int q0 = blockIdx.x % kNumQueues;
-    while (*qv < kNumQueues) {
-        const int q = (q0 + *qv) % kNumQueues;
-        const uint64_t lo = (uint64_t)n * q / kNumQueues, hi = (uint64_t)n * (q + 1) / kNumQueues;
-        const uint32_t v = atomicAdd(&queue[q], 1u);
-        if (lo + v < hi) return (uint32_t)(lo + v);
-        ++*qv;
+    const uint64_t n = (uint64_t)(h1 - h0);
+    const uint64_t per_queue = (teams + kNumQueues - 1) / kNumQueues;
+    while (c.qv < kNumQueues) {
+        const int q = (q0 + c.qv) % kNumQueues;
+        const uint64_t lo = h0 + n * q / kNumQueues, hi = h0 + n * (q + 1) / kNumQueues;
+        if (c.run == 0)
+            c.run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kMaxRun, (hi - lo) / (8 * per_queue)));
+        const uint32_t v = atomicAdd(&queue[q * kQueueStride], c.run);
+        if (lo + v < hi) {
+            const uint64_t first = lo + v, last = std::min<uint64_t>(first + c.run, hi);
+            c.cur = (uint32_t)first + 1;
+            c.end = (uint32_t)last;
+            const uint64_t left = hi - last;
+            c.run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kMaxRun, left / (8 * per_queue)));
+            return (uint32_t)first;
+        }
+        ++c.qv;
+        c.run = 1;
     }
     return kEmptyKey;
 }

@@ -91,12 +91,16 @@ void run(Server *Sp) {
         if (inflight && hipEventQuery(inflight->done) == hipSuccess) {
             const unsigned long long *o = inflight->out.as<unsigned long long>();
             const size_t per = (size_t)inflight->nconf + 1;
+            const bool bad = inflight->error() != 0;
             std::lock_guard<std::mutex> lk(S.mu);
             const Clock::time_point now = Clock::now();
             for (size_t k = 0; k < step.size(); ++k) {
                 Request *r = step[k];
                 if (r->cancel) {
                     r->state = kCancelled;
+                } else if (bad) {
+                    r->state = kFailed;
+                    r->error = GS_EUNSUPPORTED;
                 } else {
                     r->hist.assign(o + k * per, o + k * per + inflight->nconf);
                     r->ntri = o[k * per + inflight->nconf];

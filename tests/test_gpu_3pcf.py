@@ -258,21 +258,32 @@ def test_invalid_inputs_rejected(ctx, gsn):
     g.free()
 
 
-@pytest.mark.parametrize("kernel,mapping", [("team", "flat"), ("team", "3"), ("team", "6"),
-                                            ("wave", "flat"), ("wave", "4"), ("wave", "5")])
-def test_both_count_kernels_match_oracle(ctx, monkeypatch, kernel, mapping):
-    """The work-group-per-hub and the wavefront-per-hub kernels, each with the
-    flat candidate walk and with spoke groups of 2^k lanes, on plain,
-    weighted, anchored, tiled and batched counts."""
-    monkeypatch.setenv("GS_KERNEL3", kernel)
-    if mapping == "flat":
-        monkeypatch.setenv("GS_MAP3", "flat")
-    else:
-        monkeypatch.setenv("GS_GLOG", mapping)
+KERNEL_PLANS = [
+    {"GS_BLOCK3": "256", "GS_GLOG": "0"},
+    {"GS_BLOCK3": "256", "GS_GLOG": "2", "GS_TRUNC": "1"},
+    {"GS_BLOCK3": "256", "GS_GLOG": "4", "GS_TMAX": "64", "GS_MODE3": "lut"},
+    {"GS_BLOCK3": "512", "GS_GLOG": "3", "GS_PACK": "0"},
+    {"GS_BLOCK3": "512", "GS_GLOG": "6", "GS_MODE3": "rank", "GS_TMAX": "100"},
+    {"GS_BLOCK3": "256", "GS_GLOG": "1", "GS_PACK": "0", "GS_MODE3": "rank", "GS_TRUNC": "1"},
+    {"GS_BLOCK3": "256", "GS_GLOG": "3", "GS_PACK": "0", "GS_MODE3": "lut"},
+    {"GS_BLOCK3": "256", "GS_GLOG": "3", "GS_WIDE": "1"},
+    {"GS_BLOCK3": "512", "GS_GLOG": "5", "GS_WIDE": "1", "GS_PACK": "0", "GS_TRUNC": "1"},
+]
+
+
+@pytest.mark.parametrize("plan", KERNEL_PLANS, ids=lambda p: "-".join(f"{k[3:].lower()}{v}" for k, v in p.items()))
+def test_count_kernel_plans_match_oracle(ctx, monkeypatch, plan):
+    """Every kernel plan -- work-group size, entries per step, row
+    truncation, step table capacity (several fills per spoke chunk), packed or
+    separate hash bins, configuration table or rank arithmetic, 32-bit or
+    64-bit row addressing -- on plain, weighted, anchored, tiled and batched
+    counts."""
+    for k, v in plan.items():
+        monkeypatch.setenv(k, v)
     x = synth.neyman_scott(12_000, 40, 1.5, 60.0, 301)
     w = synth.uniform_values(len(x), 0.5, 1.0, 302)
     L, rmax, nb = 60.0, 3.5, 9
-    say("kernel", kernel)
+    say("plan", plan)
     ref = oracle.count_3pcf(x, L, 0.0, rmax, nb, weights=w)
     g = ctx.build_graph(x, L, 0.0, rmax, nb, weights=w)
     got = ctx.count_3pcf(g, weighted=True)
