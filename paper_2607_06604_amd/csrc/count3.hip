@@ -63,6 +63,9 @@ struct C3Args {
     int packed;             // hash entries hold (bin << 24 | label): labels < 2^24 - 1
     int glog;               // entries per step = 2^glog
     int mode;               // hit counter addressing: kRank, kLut or kCube
+    int kmax;               // hubs per group (1..kMaxGroup)
+    int yshift;             // packed hash entries: bin << yshift | hub << 24 | label
+    uint64_t group_cap;     // rows of a group (beyond the first hub) fit this many entries
     uint32_t maxdeg;
     uint32_t tmax;          // steps per table fill
     uint32_t tcap;          // table entries: tmax + padding of one pass
@@ -79,6 +82,7 @@ struct C3Args {
 constexpr int kUnroll3 = 4;              // steps per lane per pass
 constexpr int kLutMaxBins = 24;          // nb^3 u16 table up to 27 KB
 constexpr int kCubeMaxBins = 16;         // nb^3 u32 counters up to 16 KB
+constexpr int kMaxGroup = 4;             // hubs per group: two bits in a step entry
 
 // How a hit finds its counter: the configuration index from the rank tables
 // (kRank), an nb^3 table of counter addresses (kLut), or no index at all --
@@ -115,7 +119,7 @@ __host__ __device__ inline Layout3 layout3(int block, uint32_t H, uint32_t maxde
     L.mperm = o;  if (anchored) o = lds_align(o + 4 * block, 16);
     L.rtab = o;   o = lds_align(o + 8 * (nb + 1), 16);
     L.wtot = o;   o = lds_align(o + 8 * (block / 64 + 1), 16);
-    L.misc = o;   o = lds_align(o + 32, 16);
+    L.misc = o;   o = lds_align(o + 128, 16);
     L.hslot = o;  o = lds_align(o + 2 * maxdeg, 16);
     L.hxb = o;    o = lds_align(o + maxdeg, 16);
     L.hbin = o;   if (!packed) o = lds_align(o + H, 16);
@@ -221,10 +225,13 @@ struct Walk {
     gbl_u8 *sbrow;
     const double *w;
     const uint32_t *perm;
+    const double *hw;             // weights of the group's hubs
+    const uint32_t *hp;           // original indices of the group's hubs
     uint32_t mask, hist_addr;     // LDS byte address of counter 0
+    uint32_t ys, qmask;           // packed keys: bin at bit ys, key bits below
     int log2h, nb, glog;
-    double wi, wmul;
-    uint32_t pi, anchor_lo, anchor_hi;
+    double wmul;
+    uint32_t anchor_lo, anchor_hi;
 };
 
 // One hit: bins x (spoke, in the step's x term), y (hub table), z (row).
@@ -233,10 +240,10 @@ struct Walk {
 // entries are counter addresses (or indices); with kRank it is x itself.
 template <int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
 __device__ __forceinline__ void count_hit(const Walk &c, uint32_t k, uint32_t meta, uint32_t y, uint32_t z,
-                                          unsigned long long &mytri) {
+                                          uint32_t hub, unsigned long long &mytri) {
     const uint32_t slot = (meta >> 7) & 511u;
     if (ANCHORED) {
-        const uint32_t mm = min(c.pi, min(c.mperm[slot], c.perm[k]));
+        const uint32_t mm = min(c.hp[hub], min(c.mperm[slot], c.perm[k]));
         if (mm < c.anchor_lo || mm >= c.anchor_hi) return;
     }
     if (MODE == kCube) {
@@ -265,7 +272,7 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t k, uint32_t me
         ++mytri;
     }
     if (WEIGHTED) {
-        double p = c.wi, q = c.mw[slot], r = c.w[k], t;
+        double p = c.hw[hub], q = c.mw[slot], r = c.w[k], t;
         if (p > q) { t = p; p = q; q = t; }
         if (q > r) { t = q; q = r; r = t; }
         if (p > q) { t = p; p = q; q = t; }
@@ -294,52 +301,63 @@ __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned l
     const uint32_t per = (uint32_t)BLOCK >> glog;
     const uint2 *tp = c.tab + (threadIdx.x >> glog);
     for (uint32_t base = 0; base < nsteps; base += U * per) {
-        uint32_t kk[U], zz[U], meta[U], hh[U], key[U];
+        uint32_t kk[U], zz[U], meta[U], hub[U], hh[U], key[U];
         bool ok[U];
         // 1. row loads of all U steps (a slot past the table's end is skipped
         //    by the whole work group)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             ok[u] = false;
-            kk[u] = zz[u] = meta[u] = 0;
+            kk[u] = zz[u] = meta[u] = hub[u] = 0;
             if (base + u * per < nsteps) {
                 const uint2 e = tp[base + u * per];
-                const uint32_t pos = e.x + sub;
                 ok[u] = sub < (e.y & 127u);
                 meta[u] = e.y;
                 if (WIDE) {
+                    const uint32_t pos = e.x + sub;
                     kk[u] = c.srow[pos];
+                    zz[u] = c.sbrow[pos];
                 } else {
+                    // hub of the group in the top two bits
+                    const uint32_t pos = (e.x & 0x3FFFFFFFu) + sub;
+                    hub[u] = e.x >> 30;
                     kk[u] = *(gbl_u32 *)((gbl_u8 *)c.srow + (pos << 2));
+                    zz[u] = c.sbrow[pos];
                 }
-                zz[u] = c.sbrow[pos];
             }
         }
         // 2. first probes of all U candidates
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            hh[u] = hub_hash<PACK>(kk[u], c.log2h);
+            if (PACK) {
+                hh[u] = label_hash24(kk[u] ^ (hub[u] << 22), c.log2h);
+                kk[u] = (hub[u] << 24) | (kk[u] & 0xFFFFFFu);   // the key bits
+            } else {
+                hh[u] = label_hash(kk[u], c.log2h);
+            }
             key[u] = c.hkey[hh[u]];
         }
         // 3. probe sequences to their ends, and the hits
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (!ok[u]) continue;
-            const uint32_t k = kk[u];
+            const uint32_t q = kk[u];
             uint32_t h = hh[u], kv = key[u];
             if (PACK) {
-                while (((kv ^ k) & 0xFFFFFFu) != 0 && kv != kEmptyKey) {
+                while (((kv ^ q) & c.qmask) != 0 && kv != kEmptyKey) {
                     h = (h + 1) & c.mask;
                     kv = c.hkey[h];
                 }
                 if (kv != kEmptyKey)
-                    count_hit<MODE, WEIGHTED, ANCHORED, LDS_HIST>(c, k, meta[u], kv >> 24, zz[u], mytri);
+                    count_hit<MODE, WEIGHTED, ANCHORED, LDS_HIST>(c, q & 0xFFFFFFu, meta[u], kv >> c.ys, zz[u],
+                                                                  hub[u], mytri);
             } else {
-                while (kv != k && kv != kEmptyKey) {
+                while (kv != q && kv != kEmptyKey) {
                     h = (h + 1) & c.mask;
                     kv = c.hkey[h];
                 }
-                if (kv == k) count_hit<MODE, WEIGHTED, ANCHORED, LDS_HIST>(c, k, meta[u], c.hbin[h], zz[u], mytri);
+                if (kv == q)
+                    count_hit<MODE, WEIGHTED, ANCHORED, LDS_HIST>(c, q, meta[u], c.hbin[h], zz[u], 0u, mytri);
             }
         }
     }
@@ -383,9 +401,15 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     int *ta = (int *)(sm + L.rtab);
     int *tb = ta + (a.nb + 1);
     uint64_t *wtot64 = (uint64_t *)(sm + L.wtot);
-    uint32_t *s_hub = (uint32_t *)(sm + L.misc);      // hub, largest label of its row
-    int *s_g = (int *)(sm + L.misc + 8);              // its catalogue (batched)
-    uint64_t *s_r = (uint64_t *)(sm + L.misc + 16);   // its row bounds
+    // the current hub group: first hub and hub count, catalogue, row
+    // bounds, largest label per row, hub weights, indices and marks
+    uint32_t *s_hub = (uint32_t *)(sm + L.misc);
+    int *s_g = (int *)(sm + L.misc + 8);
+    uint64_t *s_rb = (uint64_t *)(sm + L.misc + 16);          // kMaxGroup + 1
+    uint32_t *s_kmax = (uint32_t *)(sm + L.misc + 56);        // kMaxGroup
+    double *s_hw = (double *)(sm + L.misc + 72);              // kMaxGroup
+    uint32_t *s_hp = (uint32_t *)(sm + L.misc + 104);         // kMaxGroup
+    uint8_t *s_mk = (uint8_t *)(sm + L.misc + 120);           // kMaxGroup
     const int tid = threadIdx.x;
     const uint32_t glog = (uint32_t)a.glog, S = 1u << glog;
     // the configuration table holds 16-bit LDS addresses
@@ -435,45 +459,63 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     c.tab = tab; c.hkey = hkey; c.hbin = hbin; c.ta = ta; c.tb = tb; c.mw = mw;
     c.mperm = mperm; c.sm = sm; c.wlo = wlo; c.whi = whi; c.wsum = a.wsum; c.w = a.w; c.perm = a.perm;
     c.mask = mask; c.hist_addr = smb + L.hist; c.log2h = a.log2h; c.nb = a.nb; c.glog = a.glog; c.wmul = a.wmul;
-    c.anchor_lo = a.anchor_lo; c.anchor_hi = a.anchor_hi;
+    c.anchor_lo = a.anchor_lo; c.anchor_hi = a.anchor_hi; c.hw = s_hw; c.hp = s_hp;
+    c.ys = (uint32_t)a.yshift;
+    c.qmask = (1u << a.yshift) - 1u;
 
-    // thread 0 claims hubs one ahead and loads their row bounds, so a hub's
-    // bounds are in LDS when the work group starts on it
-    uint32_t nx_i = kEmptyKey;
-    int nx_g = 0;
-    uint64_t nx_r0 = 0, nx_r1 = 0;
-    auto claim = [&]() {
-        if (BATCH) {
-            const uint32_t v = next_hub_in(a.queue, 0, a.nvirt, gridDim.x, cursor);
-            nx_i = kEmptyKey;
-            if (v != kEmptyKey) {
-                nx_g = graph_of(a.gd, a.ngraph, v);
-                nx_i = (uint32_t)(v - a.gd[nx_g].v0);
-                const uint64_t *r = a.gd[nx_g].rp;
-                nx_r0 = r[nx_i];
-                nx_r1 = r[nx_i + 1];
-            }
-        } else {
-            nx_i = next_hub_in(a.queue, a.h0, a.h1, gridDim.x, cursor);
-            if (nx_i != kEmptyKey) {
-                nx_r0 = a.rp[nx_i];
-                nx_r1 = a.rp[nx_i + 1];
-            }
-        }
-    };
-    if (tid == 0) claim();
-
+    // hub groups: up to a.kmax consecutive hubs whose rows (contiguous in
+    // the CSR) fit the table together; their spokes share one step table
+    const uint32_t kmaxg = (uint32_t)a.kmax;
     while (true) {
-        if (tid == 0) {
-            s_hub[0] = nx_i;
-            *s_g = nx_g;
-            s_r[0] = nx_r0;
-            s_r[1] = nx_r1;
-            if (nx_i != kEmptyKey) claim();
+        if (tid < 64) {
+            // wavefront 0 forms the group: lane 0 owns the run of claimed
+            // hubs, lanes 0..kmax load the row bounds of its next hubs
+            uint32_t v0 = kEmptyKey, avail = 0;
+            if (tid == 0 && (BATCH ? next_hub_run(a.queue, 0, a.nvirt, gridDim.x, cursor)
+                                   : next_hub_run(a.queue, a.h0, a.h1, gridDim.x, cursor))) {
+                v0 = cursor.cur;
+                avail = cursor.end - cursor.cur;
+            }
+            v0 = __shfl(v0, 0, 64);
+            avail = __shfl(avail, 0, 64);
+            if (v0 != kEmptyKey) {
+                const uint64_t *grp = a.rp;
+                uint32_t i0 = v0;
+                int g = 0;
+                if (BATCH) {
+                    // a group stays inside one catalogue
+                    g = graph_of(a.gd, a.ngraph, v0);
+                    i0 = (uint32_t)(v0 - a.gd[g].v0);
+                    grp = a.gd[g].rp;
+                    avail = min(avail, a.gd[g].n - i0);
+                }
+                const uint32_t na = min(avail, kmaxg);
+                const uint64_t r = tid <= na ? grp[i0 + tid] : 0;
+                const uint64_t rn = __shfl_down(r, 1, 64);
+                // rows of the first l + 1 hubs, and how many hubs fit
+                const uint64_t span = __shfl(r, 0, 64);
+                const bool fits = tid < na && (tid == 0 || rn - span <= a.group_cap);
+                const uint32_t K = max(1u, (uint32_t)__popcll(__ballot(fits)));
+                if (tid <= K) s_rb[tid] = r;
+                if (tid < K) {
+                    if (ANCHORED) s_hp[tid] = a.perm[i0 + tid];
+                    if (ANCHORED) s_mk[tid] = a.mark ? a.mark[i0 + tid] : 1;
+                    if (WEIGHTED) s_hw[tid] = a.w[i0 + tid];
+                }
+                if (tid == 0) {
+                    s_hub[0] = i0;
+                    s_hub[1] = K;
+                    *s_g = g;
+                    cursor.cur += K;
+                }
+            } else if (tid == 0) {
+                s_hub[0] = kEmptyKey;
+            }
         }
         __syncthreads();
-        const uint32_t i = __builtin_amdgcn_readfirstlane(s_hub[0]);
-        if (i == kEmptyKey) break;
+        const uint32_t i0 = __builtin_amdgcn_readfirstlane(s_hub[0]);
+        if (i0 == kEmptyKey) break;
+        const uint32_t K = __builtin_amdgcn_readfirstlane(s_hub[1]);
         if (BATCH) {
             const int g = __builtin_amdgcn_readfirstlane(*s_g);
             if (g != cur) {
@@ -495,18 +537,24 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
                 tout = G.ntri;
             }
         }
-        const uint64_t r0 = uniform64(s_r[0]), r1 = uniform64(s_r[1]);
-        const uint64_t beg = r0 - hbase;
-        const uint32_t d = (uint32_t)(r1 - r0);
+        // rows of the group: [rb0, rb0 + D) in the hub rows; hub k's row
+        // starts at offset ofs(k) (ofs(k) = D for k >= K)
+        const uint64_t rb0 = uniform64(s_rb[0]);
+        const uint32_t D = (uint32_t)(uniform64(s_rb[K]) - rb0);
+        uint32_t ofs1 = D, ofs2 = D, ofs3 = D;
+        if (K > 1) ofs1 = (uint32_t)(uniform64(s_rb[1]) - rb0);
+        if (K > 2) ofs2 = (uint32_t)(uniform64(s_rb[2]) - rb0);
+        if (K > 3) ofs3 = (uint32_t)(uniform64(s_rb[3]) - rb0);
+        const uint64_t beg = rb0 - hbase;
         // spokes of this tile have labels >= jlo; their rows are addressed
         // from rb = rp[jlo]
-        const uint32_t jlo = max(i + 1, s0);
-        if (d < 2 || jlo >= s1 || (ANCHORED && a.mark && !a.mark[i])) { __syncthreads(); continue; }
-        const uint64_t rb = uniform64(jlo == i + 1 ? r1 : rp[jlo]);
+        const uint32_t jlo = max(i0 + 1, s0);
+        if (D < 2 || jlo >= s1) { __syncthreads(); continue; }
+        const uint64_t rb = uniform64(jlo == i0 + 1 ? s_rb[1] : rp[jlo]);
         if (WIDE) {
             // a launch with 2^32 or more spoke entries could exceed the
-            // 32-bit entry offsets of one hub
-            const uint32_t jhi = min(hcol[beg + d - 1], s1 - 1);
+            // 32-bit entry offsets of one hub (groups are single hubs here)
+            const uint32_t jhi = min(hcol[beg + D - 1], s1 - 1);
             if (jlo <= jhi && rp[jhi + 1] - rb >= kWideSpan) {
                 if (tid == 0) atomicOr(a.err, 1u);
                 __syncthreads();
@@ -516,28 +564,30 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
         // uniform: the row loads take these as their scalar base
         c.srow = (gbl_u32 *)uniform64((uint64_t)(scol + (rb - sbase)));
         c.sbrow = (gbl_u8 *)uniform64((uint64_t)(sbinp + (rb - sbase)));
-        if (WEIGHTED) c.wi = a.w[i];
-        if (ANCHORED) c.pi = a.perm[i];
         c.hout = hout;
 
-        // stage N+(i): labels and bins in order, and label -> bin in the
-        // hash; the first spoke chunk's row bounds load alongside
+        // stage the group's rows: labels and bins in order, and (hub, label)
+        // -> bin in the hash; the first spoke chunk's row bounds load along
         uint32_t st0 = 0, len0 = 0;
-        for (uint32_t e = tid; e < d; e += BLOCK) {
+        for (uint32_t e = tid; e < D; e += BLOCK) {
             const uint32_t k = hcol[beg + e];
             const uint32_t y = hbinp[beg + e];
-            if (e == (uint32_t)tid && e + 1 < d && k >= s0 && k < s1) {
+            const uint32_t hk = (e >= ofs1) + (e >= ofs2) + (e >= ofs3);
+            const uint32_t next = hk == 0 ? ofs1 : hk == 1 ? ofs2 : hk == 2 ? ofs3 : D;
+            // the last entry of a hub's row is no spoke; it carries the row's
+            // largest label
+            if (e + 1 == next) s_kmax[hk] = k;
+            else if (e == (uint32_t)tid && k >= s0 && k < s1) {
                 const uint64_t rk = rp[k];
                 st0 = (uint32_t)(rk - rb);
                 len0 = (uint32_t)(rp[k + 1] - rk);
             }
-            if (e + 1 == d) s_hub[1] = k;   // largest label of N+(i)
             hrow[e] = k;
             hxb[e] = (uint8_t)y;
             uint32_t s, v;
             if (a.packed) {
-                s = label_hash24(k, a.log2h);
-                v = (y << 24) | k;
+                s = label_hash24(k ^ (hk << 22), a.log2h);
+                v = (y << c.ys) | (hk << 24) | k;
             } else {
                 s = label_hash(k, a.log2h);
                 v = k;
@@ -547,16 +597,17 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             hslot[e] = (uint16_t)s;
         }
         __syncthreads();
-        const uint32_t kmax = s_hub[1];
 
-        // spokes in chunks of BLOCK, one per thread; the last spoke cannot
-        // close a triangle; spokes outside the tile contribute nothing here
-        for (uint32_t c0 = 0; c0 + 1 < d; c0 += BLOCK) {
+        // spokes in chunks of BLOCK entries, one per thread; spokes outside
+        // the tile (or of hubs that own no anchored triangle) add nothing
+        for (uint32_t c0 = 0; c0 < D; c0 += BLOCK) {
             const uint32_t sidx = c0 + tid;
-            uint32_t len = 0, st = 0, xv = 0;
-            if (sidx + 1 < d) {
+            uint32_t len = 0, st = 0, xv = 0, hk = 0;
+            if (sidx < D) {
+                hk = (sidx >= ofs1) + (sidx >= ofs2) + (sidx >= ofs3);
+                const uint32_t next = hk == 0 ? ofs1 : hk == 1 ? ofs2 : hk == 2 ? ofs3 : D;
                 const uint32_t j = hrow[sidx];
-                if (j >= s0 && j < s1) {
+                if (sidx + 1 < next && j >= s0 && j < s1 && (!ANCHORED || s_mk[hk])) {
                     if (c0 == 0) {
                         st = st0;
                         len = len0;
@@ -565,7 +616,9 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
                         st = (uint32_t)(rj - rb);
                         len = (uint32_t)(rp[j + 1] - rj);
                     }
-                    // entries of N+(j) above the largest label of N+(i) cannot match
+                    // entries of N+(j) above the largest label of the hub's
+                    // row cannot match
+                    const uint32_t kmax = s_kmax[hk];
                     if (a.trunc && len > 16 && c.srow[st + len - 1] > kmax) {
                         uint32_t lo = 0, hi = len;  // first entry > kmax
                         while (lo < hi) {
@@ -585,7 +638,7 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             }
             const uint32_t ns = (len + S - 1) >> glog;
             // one scan: steps before this spoke (low word), candidates (high);
-            // wtot is next written after the fill barrier below
+            // wtot is next written after a barrier below
             uint64_t tot64;
             const uint64_t pre = wg_excl_scan64<BLOCK, false>(((uint64_t)len << 32) | ns, wtot64, tot64);
             const uint32_t t0 = (uint32_t)pre, T = (uint32_t)tot64;
@@ -597,13 +650,14 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             acc += cand;
             if (T == 0) __syncthreads();   // (the fill barrier guards wtot otherwise)
             // the table holds tmax steps: fill and walk it as often as needed
+            const uint32_t xhub = WIDE ? 0u : hk << 30;
             for (uint32_t w0 = 0; w0 < T; w0 += a.tmax) {
                 const uint32_t lo = max(t0, w0), hi = min(t0 + ns, w0 + a.tmax);
                 const uint32_t nfill = min(a.tmax, T - w0);
                 for (uint32_t s = lo; s < hi; ++s) {
                     const uint32_t r = (s - t0) << glog;
                     const uint32_t cnt = min(S, len - r);
-                    tab[s - w0] = make_uint2(st + r, cnt | ((uint32_t)tid << 7) | (xv << 16));
+                    tab[s - w0] = make_uint2((st + r) | xhub, cnt | ((uint32_t)tid << 7) | (xv << 16));
                 }
                 for (uint32_t s = tid; s < kUnroll3 * (BLOCK >> glog); s += BLOCK) tab[nfill + s] = make_uint2(0u, 0u);
                 __syncthreads();
@@ -612,8 +666,8 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             }
         }
         // the barrier at the top of the loop orders this before the next
-        // hub's staging
-        for (uint32_t e = tid; e < d; e += BLOCK) hkey[hslot[e]] = kEmptyKey;
+        // group's staging
+        for (uint32_t e = tid; e < D; e += BLOCK) hkey[hslot[e]] = kEmptyKey;
     }
 
     __syncthreads();
@@ -682,10 +736,25 @@ struct Plan3 {
     uint32_t lds = 0;
 };
 
-// wide: the launch's spoke rows hold 2^30 entries or more (GS_WIDE=1 forces
-// the wide addressing, for tests)
+// Rows of 2^30 or more spoke entries take 64-bit addresses (GS_WIDE=1
+// forces them, for tests).
+bool wide_rows(uint64_t entries) {
+    if (const char *ew = getenv("GS_WIDE"))
+        if (atoi(ew) != 0) return true;
+    return entries >= kNarrowSpan;
+}
+
+// Hubs per group and the packed key layout: groups need packed keys with
+// room for the hub index (bins below 64) and 32-bit row offsets with two
+// spare bits (GS_GROUP caps the group size, for tests).
+void set_groups(C3Args &a, const Plan3 &P, int nb, bool wide) {
+    a.yshift = P.packed && nb <= 64 ? 26 : 24;
+    a.kmax = P.packed && nb <= 64 && !wide ? kMaxGroup : 1;
+    if (const char *eg = getenv("GS_GROUP")) a.kmax = std::max(1, std::min(a.kmax, atoi(eg)));
+    a.group_cap = std::min<uint64_t>(a.maxdeg, (uint64_t)P.block);
+}
+
 void launch3_any(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P, bool w, bool an, bool wide) {
-    if (const char *ew = getenv("GS_WIDE")) wide = wide || atoi(ew) != 0;
     if (wide) {
         if (P.block == 512) launch3_bw<512, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
         else if (P.block == 128) launch3_bw<128, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
@@ -851,6 +920,7 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     a.flush_limit = flush_limit_for(maxdeg, P.block);
     a.queue = (uint32_t *)(dv + qoff);
     a.err = (uint32_t *)(dv + (size_t)ng * per);
+    set_groups(a, P, nb, false);
     if (nvirt > 0) {
         if (P.block == 512) launch3_batch<512>(ctx, s, a, P);
         else if (P.block == 128) launch3_batch<128>(ctx, s, a, P);
@@ -924,7 +994,9 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
         a.h0 = a.s0 = 0;
         a.h1 = a.s1 = (uint32_t)g.n;
         a.queue = queues;
-        launch3_any(ctx, s, a, P, weighted, anchored, g.n_edges >= kNarrowSpan);
+        const bool wide = wide_rows(g.n_edges);
+        set_groups(a, P, nb, wide);
+        launch3_any(ctx, s, a, P, weighted, anchored, wide);
     } else if (g.n > 0) {
         // host-tiled graph: spoke window S resident, hub windows H <= S
         // streamed through; copies of the next tile's windows overlap the
@@ -996,7 +1068,9 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
             b.h0 = (uint32_t)g.win[t.H];
             b.h1 = (uint32_t)g.win[t.H + 1];
             b.queue = queues + ti * kQueueWords;
-            launch3_any(ctx, s, b, P, weighted, anchored, maxE >= kNarrowSpan);
+            const bool wide = wide_rows(maxE);
+            set_groups(b, P, nb, wide);
+            launch3_any(ctx, s, b, P, weighted, anchored, wide);
             if (t.hslot >= 0) GS_HIP(hipEventRecord(ev_hfree[t.hslot], s));
             if (t.last_of_S) GS_HIP(hipEventRecord(ev_sfree[sk], s));
         }

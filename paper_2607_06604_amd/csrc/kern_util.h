@@ -168,4 +168,16 @@ __device__ __forceinline__ uint32_t next_hub_in(uint32_t *queue, uint32_t h0, ui
     return kEmptyKey;
 }
 
+// Make sure the cursor holds unclaimed hubs: false once every queue is
+// empty, else the caller owns hubs [c.cur, c.end) (consecutive labels) and
+// takes some of them by advancing c.cur.
+__device__ __forceinline__ bool next_hub_run(uint32_t *queue, uint32_t h0, uint32_t h1, uint32_t teams,
+                                             HubCursor &c) {
+    if (c.cur < c.end) return true;
+    const uint32_t v = next_hub_in(queue, h0, h1, teams, c);
+    if (v == kEmptyKey) return false;
+    c.cur = v;  // hand the first hub of the new run back
+    return true;
+}
+
 }  // namespace gsn
