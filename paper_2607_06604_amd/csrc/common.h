@@ -231,6 +231,7 @@ struct Batch3 {
     DevBuf dv;          // device results + queues
     DevBuf gd;          // descriptors
     HostBuf hostdesc;   // staging of descriptors
+    HostBuf hostcfg;    // staging of the configuration table
     HostBuf out;        // pinned results
     hipEvent_t done = nullptr;
     int ng = 0, nconf = 0;

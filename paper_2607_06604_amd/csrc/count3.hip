@@ -77,6 +77,7 @@ struct C3Args {
     unsigned long long *wsum;   // 2*nconf (lo, hi)
     unsigned long long *ntri;   // 1
     uint32_t *err;          // bit 0: a hub's spoke rows span too many entries; bit 1: LDS addressing
+    const uint16_t *cfg3;   // kLut / kCube: configuration index of ordered triple (x*nb + y)*nb + z
 };
 
 constexpr int kUnroll3 = 4;              // steps per lane per pass
@@ -98,7 +99,7 @@ constexpr uint64_t kWideSpan = 1ull << 32;
 // LDS layout of one work group (byte offsets). The configuration table and
 // the counters come first so that their byte addresses fit 16 bits.
 struct Layout3 {
-    uint32_t cube, lut, hist, wlo, whi, hkey, hrow, hxb, hslot, tab, mw, mperm, rtab, wtot, misc, hbin, total;
+    uint32_t cube, lut, hist, wlo, whi, hkey, hxb, tab, mw, mperm, rtab, wtot, misc, hbin, total;
 };
 
 __host__ __device__ inline Layout3 layout3(int block, uint32_t H, uint32_t maxdeg, uint32_t tcap, int nconf,
@@ -107,20 +108,22 @@ __host__ __device__ inline Layout3 layout3(int block, uint32_t H, uint32_t maxde
     if (!lds_hist) nconf = 0;
     Layout3 L{};
     uint32_t o = 0;
+    // with the cube the configuration counters are only written while the
+    // step table is idle (flushes), so they share its space
+    const bool alias = mode == kCube && lds_hist;
     L.cube = o;   if (mode == kCube) o = lds_align(o + 4 * nb * nb * nb, 16);
     L.lut = o;    if (mode == kLut) o = lds_align(o + 2 * nb * nb * nb, 16);
-    L.hist = o;   o = lds_align(o + 4 * nconf, 16);
+    L.hist = o;   if (!alias) o = lds_align(o + 4 * nconf, 16);
     L.wlo = o;    if (weighted) o = lds_align(o + 8 * nconf, 16);
     L.whi = o;    if (weighted) o = lds_align(o + 8 * nconf, 16);
     L.hkey = o;   o = lds_align(o + 4 * H, 16);
-    L.hrow = o;   o = lds_align(o + 4 * maxdeg, 16);
-    L.tab = o;    o = lds_align(o + 8 * tcap, 16);
+    L.tab = o;    o = lds_align(o + std::max(8 * tcap, alias ? 4u * nconf : 0u), 16);
+    if (alias) L.hist = L.tab;
     L.mw = o;     if (weighted) o = lds_align(o + 8 * block, 16);
     L.mperm = o;  if (anchored) o = lds_align(o + 4 * block, 16);
     L.rtab = o;   o = lds_align(o + 8 * (nb + 1), 16);
     L.wtot = o;   o = lds_align(o + 8 * (block / 64 + 1), 16);
     L.misc = o;   o = lds_align(o + 128, 16);
-    L.hslot = o;  o = lds_align(o + 2 * maxdeg, 16);
     L.hxb = o;    o = lds_align(o + maxdeg, 16);
     L.hbin = o;   if (!packed) o = lds_align(o + H, 16);
     L.total = o;
@@ -161,17 +164,17 @@ __device__ void flush3(const C3Args &a, const Layout3 &L, unsigned char *sm, uns
     if (!LDS_HIST) return;
     uint32_t *hist = (uint32_t *)(sm + L.hist);
     if (!WEIGHTED && a.mode == kCube) {
-        // fold the ordered bin triples into their configurations
+        // fold the ordered bin triples into their configurations (the
+        // configuration counters share the idle step table: clear them first)
+        for (int b = threadIdx.x; b < a.nconf; b += BLOCK) hist[b] = 0;
+        __syncthreads();
         uint32_t *cube = (uint32_t *)(sm + L.cube);
-        const int *ta = (const int *)(sm + L.rtab), *tb = ta + (a.nb + 1);
-        const int nb = a.nb;
-        for (int t = threadIdx.x; t < nb * nb * nb; t += BLOCK) {
+        const int n3 = a.nb * a.nb * a.nb;
+        for (int t = threadIdx.x; t < n3; t += BLOCK) {
             const uint32_t v = cube[t];
             if (v) {
                 cube[t] = 0;
-                const int x = t / (nb * nb), y = (t / nb) % nb, z = t % nb;
-                const int lo = min(x, min(y, z)), hi = max(x, max(y, z)), mid = x + y + z - lo - hi;
-                atomicAdd(&hist[ta[lo] + tb[mid] + hi], v);
+                atomicAdd(&hist[a.cfg3[t]], v);
             }
         }
         __syncthreads();
@@ -388,10 +391,8 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     uint16_t *lut = (uint16_t *)(sm + L.lut);
     uint32_t *cube = (uint32_t *)(sm + L.cube);
     uint32_t *hkey = (uint32_t *)(sm + L.hkey);
-    uint32_t *hrow = (uint32_t *)(sm + L.hrow);
     uint8_t *hxb = (uint8_t *)(sm + L.hxb);
     uint8_t *hbin = (uint8_t *)(sm + L.hbin);
-    uint16_t *hslot = (uint16_t *)(sm + L.hslot);
     uint2 *tab = (uint2 *)(sm + L.tab);
     double *mw = (double *)(sm + L.mw);
     uint32_t *mperm = (uint32_t *)(sm + L.mperm);
@@ -436,15 +437,13 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     // LDS byte address, or its index when the counters are global
     if (a.mode == kLut)
         for (int t = tid; t < a.nb * a.nb * a.nb; t += BLOCK) {
-            const int x = t / (a.nb * a.nb), y = (t / a.nb) % a.nb, z = t % a.nb;
-            const int lo = min(x, min(y, z)), hi = max(x, max(y, z)), mid = x + y + z - lo - hi;
-            const int idx = rank_a(a.nb, lo) + rank_b(a.nb, mid) + hi;
+            const uint32_t idx = a.cfg3[t];
             lut[t] = (uint16_t)(LDS_HIST ? smb + L.hist + 4 * idx : idx);
         }
     __syncthreads();
 
     unsigned long long mytri = 0;  // global counters: this thread's hits
-    uint64_t acc = 0;   // upper bound on increments since the last flush (uniform)
+    uint64_t acc = 0;   // candidates probed since the last flush: bounds the increments (uniform)
     HubCursor cursor;   // thread 0's claimed run of hubs
     int cur = -1;       // batched launch: catalogue whose counts the LDS holds
     // the CSR view of the current hub: the launch's tile, or one catalogue
@@ -568,7 +567,7 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
 
         // stage the group's rows: labels and bins in order, and (hub, label)
         // -> bin in the hash; the first spoke chunk's row bounds load along
-        uint32_t st0 = 0, len0 = 0;
+        uint32_t st0 = 0, len0 = 0, j0 = 0;
         for (uint32_t e = tid; e < D; e += BLOCK) {
             const uint32_t k = hcol[beg + e];
             const uint32_t y = hbinp[beg + e];
@@ -576,13 +575,13 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             const uint32_t next = hk == 0 ? ofs1 : hk == 1 ? ofs2 : hk == 2 ? ofs3 : D;
             // the last entry of a hub's row is no spoke; it carries the row's
             // largest label
+            if (e == (uint32_t)tid) j0 = k;
             if (e + 1 == next) s_kmax[hk] = k;
             else if (e == (uint32_t)tid && k >= s0 && k < s1) {
                 const uint64_t rk = rp[k];
                 st0 = (uint32_t)(rk - rb);
                 len0 = (uint32_t)(rp[k + 1] - rk);
             }
-            hrow[e] = k;
             hxb[e] = (uint8_t)y;
             uint32_t s, v;
             if (a.packed) {
@@ -594,7 +593,6 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             }
             while (atomicCAS(&hkey[s], kEmptyKey, v) != kEmptyKey) s = (s + 1) & mask;
             if (!a.packed) hbin[s] = (uint8_t)y;
-            hslot[e] = (uint16_t)s;
         }
         __syncthreads();
 
@@ -606,7 +604,7 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             if (sidx < D) {
                 hk = (sidx >= ofs1) + (sidx >= ofs2) + (sidx >= ofs3);
                 const uint32_t next = hk == 0 ? ofs1 : hk == 1 ? ofs2 : hk == 2 ? ofs3 : D;
-                const uint32_t j = hrow[sidx];
+                const uint32_t j = c0 == 0 ? j0 : hcol[beg + sidx];
                 if (sidx + 1 < next && j >= s0 && j < s1 && (!ANCHORED || s_mk[hk])) {
                     if (c0 == 0) {
                         st = st0;
@@ -642,12 +640,7 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             uint64_t tot64;
             const uint64_t pre = wg_excl_scan64<BLOCK, false>(((uint64_t)len << 32) | ns, wtot64, tot64);
             const uint32_t t0 = (uint32_t)pre, T = (uint32_t)tot64;
-            const uint64_t cand = tot64 >> 32;
-            if (acc + cand >= a.flush_limit) {
-                flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout, tout);
-                acc = 0;
-            }
-            acc += cand;
+            acc += tot64 >> 32;
             if (T == 0) __syncthreads();   // (the fill barrier guards wtot otherwise)
             // the table holds tmax steps: fill and walk it as often as needed
             const uint32_t xhub = WIDE ? 0u : hk << 30;
@@ -667,7 +660,14 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
         }
         // the barrier at the top of the loop orders this before the next
         // group's staging
-        for (uint32_t e = tid; e < D; e += BLOCK) hkey[hslot[e]] = kEmptyKey;
+        for (uint32_t q = tid; q < H; q += BLOCK) hkey[q] = kEmptyKey;
+        // a group adds at most maxdeg^2 increments (rows of at most maxdeg
+        // entries, at most maxdeg spokes): flush while the next one cannot
+        // pass the limit (the walk's last barrier ordered every increment)
+        if (acc + (uint64_t)a.maxdeg * a.maxdeg >= a.flush_limit) {
+            flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout, tout);
+            acc = 0;
+        }
     }
 
     __syncthreads();
@@ -715,12 +715,12 @@ void launch3_bw(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds, bool w, 
 }
 
 // Entries per step from the mean forward row length (GS_GLOG overrides):
-// about a tenth of a row, so that padding the last step of a row costs
-// little and most rows still take several steps.
+// the largest power of two up to a fifth of a row, so that padding the last
+// step of a row costs little and a row still takes several steps.
 int group_log(double mean_row) {
     if (const char *eg = getenv("GS_GLOG")) return std::max(0, std::min(6, atoi(eg)));
     int g = 0;
-    while (g < 6 && (double)(2u << g) * 10.0 <= mean_row) ++g;
+    while (g < 6 && (double)(2u << g) * 5.0 <= mean_row) ++g;
     return g;
 }
 
@@ -735,6 +735,22 @@ struct Plan3 {
     uint32_t tmax = 1024, tcap = 0;
     uint32_t lds = 0;
 };
+
+// Configuration index of every ordered bin triple (x, y, z) at
+// (x*nb + y)*nb + z: the counter table and the cube fold read it.
+std::vector<uint16_t> config_table(int nb) {
+    std::vector<uint16_t> t;
+    if (nb > kLutMaxBins) return t;
+    t.resize((size_t)nb * nb * nb);
+    for (int x = 0; x < nb; ++x)
+        for (int y = 0; y < nb; ++y)
+            for (int z = 0; z < nb; ++z) {
+                const int lo = std::min(x, std::min(y, z)), hi = std::max(x, std::max(y, z));
+                const int mid = x + y + z - lo - hi;
+                t[((size_t)x * nb + y) * nb + z] = (uint16_t)(rank_a(nb, lo) + rank_b(nb, mid) + hi);
+            }
+    return t;
+}
 
 // Rows of 2^30 or more spoke entries take 64-bit addresses (GS_WIDE=1
 // forces them, for tests).
@@ -779,7 +795,7 @@ Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchore
     if (maxdeg > 16384) fail(GS_EUNSUPPORTED, "forward degree above 16384");
     if (const char *eb = getenv("GS_BLOCK3")) p.block = atoi(eb) == 512 ? 512 : atoi(eb) == 128 ? 128 : 256;
     else p.block = maxdeg >= 1024 ? 512 : 256;
-    p.tmax = 4 * (uint32_t)p.block;
+    p.tmax = 2 * (uint32_t)p.block;
     if (const char *em = getenv("GS_TMAX")) p.tmax = std::max(64, std::min(1 << 16, atoi(em)));
     p.tcap = p.tmax + kUnroll3 * ((uint32_t)p.block >> p.glog);
     // the per-spoke binary search pays off on long rows only
@@ -881,9 +897,12 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     b.ng = ng;
     b.nconf = nconf;
     const size_t per = (size_t)nconf + 1;
-    // device staging: counts per catalogue | error word | queues (256-byte aligned)
+    // device staging: counts per catalogue | error word | queues (256-byte
+    // aligned) | configuration table
     const size_t qoff = ((size_t)ng * per + 1 + 31) / 32 * 32;
-    const size_t words = qoff + kQueueWords / 2;
+    const std::vector<uint16_t> cfg = config_table(nb);
+    const size_t coff = qoff + kQueueWords / 2;
+    const size_t words = coff + (cfg.size() + 3) / 4;
     b.dv.alloc(words * 8);
     unsigned long long *dv = b.dv.as<unsigned long long>();
     b.hostdesc.alloc(sizeof(GDesc) * ng);
@@ -903,6 +922,12 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     b.gd.alloc(sizeof(GDesc) * ng);
     GS_HIP(hipMemcpyAsync(b.gd.p, hd, sizeof(GDesc) * ng, hipMemcpyHostToDevice, s));
     k_zero_u64<<<64, 256, 0, s>>>(dv, words);
+    if (!cfg.empty()) {
+        // pinned staging that lives as long as the batch (the copy is async)
+        b.hostcfg.alloc(cfg.size() * 2);
+        memcpy(b.hostcfg.p, cfg.data(), cfg.size() * 2);
+        GS_HIP(hipMemcpyAsync(dv + coff, b.hostcfg.p, cfg.size() * 2, hipMemcpyHostToDevice, s));
+    }
     C3Args a{};
     a.gd = b.gd.as<GDesc>();
     a.ngraph = ng;
@@ -920,6 +945,7 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     a.flush_limit = flush_limit_for(maxdeg, P.block);
     a.queue = (uint32_t *)(dv + qoff);
     a.err = (uint32_t *)(dv + (size_t)ng * per);
+    a.cfg3 = (const uint16_t *)(dv + coff);
     set_groups(a, P, nb, false);
     if (nvirt > 0) {
         if (P.block == 512) launch3_batch<512>(ctx, s, a, P);
@@ -948,7 +974,9 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     // device staging: hist | wsum | ntri | error word | queue sets, one per
     // tile (256-byte aligned)
     const size_t qoff = (3 * (size_t)nconf + 2 + 31) / 32 * 32;
-    const size_t words = qoff + (size_t)ntiles * kQueueWords / 2;
+    const std::vector<uint16_t> cfg = config_table(nb);   // | configuration table
+    const size_t coff = qoff + (size_t)ntiles * kQueueWords / 2;
+    const size_t words = coff + (cfg.size() + 3) / 4;
     unsigned long long *dv = (unsigned long long *)ctx.scratch_get(words * 8);
     C3Args a{};
     a.rp = g.row_ptr.as<uint64_t>();
@@ -972,11 +1000,14 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.wsum = dv + nconf;
     a.ntri = dv + 3 * (size_t)nconf;
     a.err = (uint32_t *)(dv + 3 * (size_t)nconf + 1);
+    a.cfg3 = (const uint16_t *)(dv + coff);
     uint32_t *queues = (uint32_t *)(dv + qoff);
 
     hipStream_t s = ctx.stream;
     GS_HIP(hipEventRecord(ctx.ev[0], s));
     k_zero_u64<<<64, 256, 0, s>>>(dv, words);
+    if (!cfg.empty())
+        GS_HIP(hipMemcpyAsync(dv + coff, cfg.data(), cfg.size() * 2, hipMemcpyHostToDevice, s));
     GS_HIP(hipEventRecord(ctx.ev[2], s));
     DevBuf mark;
     if (anchored && W == 1 && g.n > 0) {

@@ -170,7 +170,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     const double Lb = a.L, half = a.half;
 
     while (true) {
-        if (tid == 0) *s_hub = next_hub_in(a.queue, 0, a.n, gridDim.x, cursor);
+        if (tid == 0) *s_hub = next_hub_in(a.queue, 0, a.n, gridDim.x, cursor, 1);
         __syncthreads();
         const uint32_t i = *s_hub;
         if (i == kEmptyKey) break;

@@ -141,9 +141,10 @@ struct HubCursor {
 };
 
 // Next hub of [h0, h1) for the calling thread (one per team), or kEmptyKey.
-// teams: how many teams draw from these queues.
+// teams: how many teams draw from these queues; max_run caps a claim (1 for
+// hubs whose costs vary too much to hand out in runs).
 __device__ __forceinline__ uint32_t next_hub_in(uint32_t *queue, uint32_t h0, uint32_t h1, uint32_t teams,
-                                                HubCursor &c) {
+                                                HubCursor &c, uint32_t max_run = kMaxRun) {
     if (c.cur < c.end) return c.cur++;
     const int q0 = blockIdx.x % kNumQueues;
     const uint64_t n = (uint64_t)(h1 - h0);
@@ -152,14 +153,14 @@ __device__ __forceinline__ uint32_t next_hub_in(uint32_t *queue, uint32_t h0, ui
         const int q = (q0 + c.qv) % kNumQueues;
         const uint64_t lo = h0 + n * q / kNumQueues, hi = h0 + n * (q + 1) / kNumQueues;
         if (c.run == 0)
-            c.run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kMaxRun, (hi - lo) / (8 * per_queue)));
+            c.run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(max_run, (hi - lo) / (8 * per_queue)));
         const uint32_t v = atomicAdd(&queue[q * kQueueStride], c.run);
         if (lo + v < hi) {
             const uint64_t first = lo + v, last = std::min<uint64_t>(first + c.run, hi);
             c.cur = (uint32_t)first + 1;
             c.end = (uint32_t)last;
             const uint64_t left = hi - last;
-            c.run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kMaxRun, left / (8 * per_queue)));
+            c.run = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(max_run, left / (8 * per_queue)));
             return (uint32_t)first;
         }
         ++c.qv;
