@@ -87,8 +87,18 @@ def run_stream(args):
     print("generated %d catalogues, %d points" % (len(cats), int(sizes.sum())), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
+    # the schedule is tuned once on the largest catalogue's shape (setup)
+    big = int(np.argmax(sizes))
+
+    def tune(c):
+        g = c.build_graph(cats[big], L, 0.0, rmax, nb)
+        c.tune_3pcf(g)
+        g.free()
+
     # plain path: one catalogue at a time, host input, build + count
     with gsn.Context(0) as c:
+        if not args.no_tune:
+            tune(c)
         for x in cats[:2]:
             g = c.build_graph(x, L, 0.0, rmax, nb)
             c.count_3pcf(g)
@@ -108,6 +118,8 @@ def run_stream(args):
 
     def serve(arrivals):
         with gsn.Context(0) as s:
+            if not args.no_tune:
+                tune(s)
             # warm the server (thread, streams, kernels) on a small request
             t = s.submit(cats[1][:1000], L, 0.0, rmax, nb)
             while s.poll(t, nb) is None:
@@ -176,6 +188,8 @@ def main():
                     help="fraction of anchor points for the oracle baseline (0 = default per workload)")
     ap.add_argument("--windows", type=int, default=0,
                     help="force a host-tiled graph with this many windows (out-of-core path)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the schedule autotuner (built-in schedule)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -216,6 +230,16 @@ def main():
     ctx = gsn.Context(0, stream=stream)
     keep = spec["kind"] == "4pcf"
     wd = torch.from_numpy(w.weights).to(dev) if spec["kind"] == "w3pcf" else None
+
+    # schedule autotuning on this catalogue's graph (setup, outside the timed steps)
+    schedule = None
+    if spec["kind"] in ("3pcf", "w3pcf") and not args.no_tune and not args.windows:
+        g = ctx.build_graph(xd, w.box, w.rmin, w.rmax, w.nbins, weights=wd)
+        tt = time.perf_counter()
+        schedule = ctx.tune_3pcf(g, weighted=spec["kind"] == "w3pcf")
+        schedule["tune_s"] = round(time.perf_counter() - tt, 3)
+        g.free()
+        print("tuned schedule: %s" % json.dumps(schedule), file=sys.stderr, flush=True)
 
     def step():
         g = ctx.build_graph(xd, w.box, w.rmin, w.rmax, w.nbins, keep_coords=keep, weights=wd)
@@ -300,6 +324,7 @@ def main():
                        "build_ms": round(build_ms / args.steps, 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "schedule": schedule,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -160,6 +160,37 @@ int gs_count_4pcf_parity(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_
 int gs_count_3pcf_batch(gs_ctx *ctx, const gs_graph *const *graphs, int ng, uint64_t *hists,
                         uint64_t *n_triangles);
 
+/* ---- autotuning of the triangle-count schedule ----
+ * The count's schedule: threads per work group, candidates per step (the
+ * lanes that walk one spoke row together, Sec. 3.5.2), hubs per group (hubs
+ * counted together, their rows contiguous in the CSR of Sec. 3.5.1), step
+ * table entries, and how a hit finds its counter. gs_tune_3pcf times
+ * candidate schedules on a sample of g's hubs (counts discarded), starting
+ * from the built-in choice and changing one parameter at a time while that
+ * helps; the fastest is kept in the context for graphs of g's shape (bin
+ * count, weighting, label width, and the scale of the largest and the mean
+ * forward degree), and every later count of such a graph in this context
+ * (gs_count_3pcf, gs_count_3pcf_batch, and requests served after the
+ * context's first gs_submit, which takes the schedules tuned before it) uses
+ * it. Not thread-safe against concurrent counts on the same context.
+ *  g: a device-resident graph (GS_EUNSUPPORTED for host-tiled graphs);
+ *  flags: GS_WEIGHTED tunes weighted counts (g must be weighted);
+ *  out: nullable, host: the chosen schedule. Results never depend on it. */
+typedef struct {
+    int32_t block;       /* threads per work group (256 or 512)                 */
+    int32_t step_log2;   /* candidates per step = 2^step_log2 (0..6)            */
+    int32_t group;       /* hubs per group (1..4)                                */
+    int32_t table;       /* step table entries per fill                          */
+    int32_t counters;    /* 0: rank arithmetic, 1: table of counter addresses,   */
+                         /* 2: per-(x,y,z) counters folded at flush              */
+    int32_t trials;      /* schedules timed                                      */
+    double sample_ms;    /* chosen schedule on the sample (kernel time)          */
+    double default_ms;   /* built-in schedule on the same sample                 */
+    double sample_frac;  /* fraction of hubs in the sample                       */
+} gs_plan3;
+
+int gs_tune_3pcf(gs_ctx *ctx, const gs_graph *g, uint32_t flags, gs_plan3 *out);
+
 /* ---- serving: continuous batching of triangle-count requests ----
  * gs_submit copies the catalogue and returns a ticket at once. A scheduler
  * thread of the context admits queued requests while device memory (the

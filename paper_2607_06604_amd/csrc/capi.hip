@@ -274,6 +274,16 @@ int gs_count_4pcf_parity(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_
     });
 }
 
+int gs_tune_3pcf(gs_ctx *ctx, const gs_graph *g, uint32_t flags, gs_plan3 *out) {
+    return guarded([&] {
+        if (!ctx || !g) fail(GS_EINVAL, "null argument");
+        if (flags & ~GS_WEIGHTED) fail(GS_EINVAL, "unknown flags");
+        if (g->device != ctx->device) fail(GS_EINVAL, "graph and context on different devices");
+        ctx->use();
+        tune3(*ctx, *g, (flags & GS_WEIGHTED) != 0, out);
+    });
+}
+
 int gs_count_3pcf_batch(gs_ctx *ctx, const gs_graph *const *graphs, int ng, uint64_t *hists,
                         uint64_t *n_triangles) {
     return guarded([&] {

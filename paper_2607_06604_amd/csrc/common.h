@@ -101,6 +101,12 @@ struct Timings {
 struct Server;
 
 // Result staging shared by the count entry points of one context.
+// A triangle-count schedule (-1: the built-in choice): work-group size,
+// entries per step (log2), hubs per group, step table entries, counter mode.
+struct Tune3 {
+    int block = -1, glog = -1, group = -1, tmax = -1, mode = -1;
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -115,6 +121,7 @@ struct Ctx {
     void *pinned = nullptr;     // small pinned host staging
     size_t pinned_bytes = 0;
     Server *server = nullptr;   // continuous-batching scheduler (gs_submit)
+    std::vector<std::pair<uint64_t, Tune3>> tuned;  // autotuned schedules by graph shape
     void *scratch_get(size_t bytes);
     void *pinned_get(size_t bytes);
     void use() const;
@@ -213,8 +220,14 @@ __host__ __device__ inline int rank_b(int nb, int b2) { return (int)(-c2(nb - b2
 
 // ---------------------------------------------------------- launches ------
 
+// sample_hi > sample_lo: count only hubs [sample_lo, sample_hi) of a resident
+// graph (timing samples); force: a schedule to use instead of the tuned or
+// built-in one.
 void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64_t *ntri,
-                const gs_anchor_range *anchors);
+                const gs_anchor_range *anchors, const Tune3 *force = nullptr, uint32_t sample_lo = 0,
+                uint32_t sample_hi = 0);
+// Time schedules on a sample of g's hubs and keep the fastest for g's shape.
+void tune3(Ctx &ctx, const Graph &g, bool weighted, gs_plan3 *out);
 void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_t *neg,
                 uint64_t *ncl, const gs_anchor_range *anchors);
 void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w);

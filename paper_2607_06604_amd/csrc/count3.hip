@@ -78,6 +78,8 @@ struct C3Args {
     unsigned long long *ntri;   // 1
     uint32_t *err;          // bit 0: a hub's spoke rows span too many entries; bit 1: LDS addressing
     const uint16_t *cfg3;   // kLut / kCube: configuration index of ordered triple (x*nb + y)*nb + z
+    const uint32_t *tiles;  // hub tiles of about equal cost: tile t = [tiles[t], tiles[t+1]) (or null)
+    uint32_t ntiles;
 };
 
 constexpr int kUnroll3 = 4;              // steps per lane per pass
@@ -123,7 +125,7 @@ __host__ __device__ inline Layout3 layout3(int block, uint32_t H, uint32_t maxde
     L.mperm = o;  if (anchored) o = lds_align(o + 4 * block, 16);
     L.rtab = o;   o = lds_align(o + 8 * (nb + 1), 16);
     L.wtot = o;   o = lds_align(o + 8 * (block / 64 + 1), 16);
-    L.misc = o;   o = lds_align(o + 128, 16);
+    L.misc = o;   o = lds_align(o + 160, 16);
     L.hxb = o;    o = lds_align(o + maxdeg, 16);
     L.hbin = o;   if (!packed) o = lds_align(o + H, 16);
     L.total = o;
@@ -382,8 +384,9 @@ __device__ __forceinline__ void walk3_any(bool packed, int mode, const Walk &c, 
     }
 }
 
+// Plain unbatched counts fit 64 VGPRs: eight wavefronts per SIMD.
 template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool BATCH, bool WIDE>
-__global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
+__global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED || BATCH) ? 1 : 8) void k_count3(C3Args a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const uint32_t H = 1u << a.log2h, mask = H - 1;
     const Layout3 L = layout3(BLOCK, H, a.maxdeg, a.tcap, a.nconf, a.nb, WEIGHTED, ANCHORED, LDS_HIST,
@@ -444,7 +447,14 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
 
     unsigned long long mytri = 0;  // global counters: this thread's hits
     uint64_t acc = 0;   // candidates probed since the last flush: bounds the increments (uniform)
-    HubCursor cursor;   // thread 0's claimed run of hubs
+    // thread 0's claimed hubs and tile claims live in LDS (no registers held
+    // across the loop)
+    HubCursor &cursor = *(HubCursor *)(sm + L.misc + 128);
+    HubCursor &tcursor = *(HubCursor *)(sm + L.misc + 144);
+    if (tid == 0) {
+        cursor = HubCursor();
+        tcursor = HubCursor();
+    }
     int cur = -1;       // batched launch: catalogue whose counts the LDS holds
     // the CSR view of the current hub: the launch's tile, or one catalogue
     const uint64_t *rp = a.rp;
@@ -470,8 +480,24 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
             // wavefront 0 forms the group: lane 0 owns the run of claimed
             // hubs, lanes 0..kmax load the row bounds of its next hubs
             uint32_t v0 = kEmptyKey, avail = 0;
-            if (tid == 0 && (BATCH ? next_hub_run(a.queue, 0, a.nvirt, gridDim.x, cursor)
-                                   : next_hub_run(a.queue, a.h0, a.h1, gridDim.x, cursor))) {
+            bool have = false;
+            if (tid == 0) {
+                if (a.tiles) {
+                    // the queues hand out tiles; a tile's hubs go in order
+                    have = cursor.cur < cursor.end;
+                    while (!have) {
+                        const uint32_t t = next_hub_in(a.queue, 0, a.ntiles, gridDim.x, tcursor, 1);
+                        if (t == kEmptyKey) break;
+                        cursor.cur = a.tiles[t];
+                        cursor.end = a.tiles[t + 1];
+                        have = cursor.cur < cursor.end;
+                    }
+                } else {
+                    have = BATCH ? next_hub_run(a.queue, 0, a.nvirt, gridDim.x, cursor)
+                                 : next_hub_run(a.queue, a.h0, a.h1, gridDim.x, cursor);
+                }
+            }
+            if (have) {
                 v0 = cursor.cur;
                 avail = cursor.end - cursor.cur;
             }
@@ -678,6 +704,72 @@ __global__ __launch_bounds__(BLOCK) void k_count3(C3Args a) {
     }
 }
 
+// Hub tiles balanced by the sum of squared forward degrees. Blocks of q
+// consecutive hubs get their cost; one work group scans the block costs and
+// cuts [h0, h1) at the blocks where the running cost crosses t/T of the
+// total. Batched launches number hubs across catalogues (virtual hubs).
+__global__ void k_block_cost(const uint64_t *__restrict__ rp, const GDesc *__restrict__ gd, int ng, uint32_t h0,
+                             uint32_t h1, uint32_t q, unsigned long long *__restrict__ cost, uint32_t nblk) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblk) return;
+    unsigned long long c = 0;
+    const uint32_t lo = h0 + b * q, hi = min(h1, lo + q);
+    for (uint32_t v = lo; v < hi; ++v) {
+        uint64_t d;
+        if (gd) {
+            const int g = graph_of(gd, ng, v);
+            const uint32_t i = (uint32_t)(v - gd[g].v0);
+            d = gd[g].rp[i + 1] - gd[g].rp[i];
+        } else {
+            d = rp[v + 1] - rp[v];
+        }
+        c += (unsigned long long)(d * d);
+    }
+    cost[b] = c;
+}
+
+constexpr int kTileScanBlock = 1024;
+
+__global__ __launch_bounds__(kTileScanBlock) void k_tile_bounds(unsigned long long *__restrict__ cost,
+                                                                 uint32_t nblk, uint32_t q, uint32_t h0,
+                                                                 uint32_t h1, uint32_t T,
+                                                                 uint32_t *__restrict__ tiles) {
+    __shared__ uint64_t wtot[kTileScanBlock / 64 + 1];
+    const uint32_t tid = threadIdx.x;
+    // each thread scans a contiguous share of the blocks (inclusive)
+    const uint32_t per = (nblk + kTileScanBlock - 1) / kTileScanBlock;
+    const uint32_t b0 = min(nblk, tid * per), b1 = min(nblk, b0 + per);
+    uint64_t run = 0;
+    for (uint32_t b = b0; b < b1; ++b) run += cost[b];
+    uint64_t total;
+    const uint64_t off = wg_excl_scan64<kTileScanBlock>(run, wtot, total);
+    run = off;
+    for (uint32_t b = b0; b < b1; ++b) {
+        run += cost[b];
+        cost[b] = run;
+    }
+    __syncthreads();
+    for (uint32_t t = tid; t <= T; t += kTileScanBlock) {
+        uint32_t at;
+        if (t == 0) {
+            at = h0;
+        } else if (t == T || total == 0) {
+            at = t == T ? h1 : (uint32_t)min<uint64_t>(h1, h0 + (uint64_t)(h1 - h0) * t / T);
+        } else {
+            // first block whose running cost passes t/T of the total
+            const uint64_t target = (uint64_t)((unsigned __int128)total * t / T);
+            uint32_t lo = 0, hi = nblk;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (cost[mid] <= target) lo = mid + 1;
+                else hi = mid;
+            }
+            at = (uint32_t)min<uint64_t>(h1, h0 + (uint64_t)lo * q);
+        }
+        tiles[t] = at;
+    }
+}
+
 __global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -724,6 +816,32 @@ int group_log(double mean_row) {
     return g;
 }
 
+// Graphs of one shape share a tuned schedule: bin count, weighting, label
+// width, and the scale (half powers of two) of the largest and the mean
+// forward degree.
+uint64_t tune_key(int nb, bool weighted, bool packed, uint32_t maxdeg, double mean_row) {
+    const uint64_t lmax = (uint64_t)std::lround(2.0 * std::log2(std::max(1.0, (double)maxdeg)));
+    const uint64_t lmean = (uint64_t)std::lround(2.0 * std::log2(std::max(1.0, mean_row)));
+    return (uint64_t)nb | (uint64_t)weighted << 8 | (uint64_t)packed << 9 | lmax << 10 | lmean << 20;
+}
+
+// The tuned schedule of the nearest shape with the same bin count, weighting
+// and label width, if its degree scales are within a factor two of key's.
+Tune3 tuned_for(const Ctx &ctx, uint64_t key) {
+    Tune3 best;
+    long bestd = 5;
+    for (const auto &kv : ctx.tuned) {
+        if ((kv.first & 0x3FF) != (key & 0x3FF)) continue;
+        const long dmax = std::labs((long)((kv.first >> 10) & 0x3FF) - (long)((key >> 10) & 0x3FF));
+        const long dmean = std::labs((long)(kv.first >> 20) - (long)(key >> 20));
+        if (dmax <= 2 && dmean <= 2 && dmax + dmean < bestd) {
+            bestd = dmax + dmean;
+            best = kv.second;
+        }
+    }
+    return best;
+}
+
 struct Plan3 {
     int block = 256;
     int glog = 0;
@@ -752,6 +870,34 @@ std::vector<uint16_t> config_table(int nb) {
     return t;
 }
 
+// Hub tiles for [h0, h1): at most T of about equal sum of squared forward
+// degree, cut at multiples of q hubs (q keeps the block count <= 2^16).
+// GS_TILES=0 turns them off (hubs then go out in guided runs).
+struct TilePlan {
+    uint32_t q = 16, nblk = 1, T = 1;
+};
+
+bool tiles_enabled() {
+    const char *e = getenv("GS_TILES");
+    return !e || atoi(e) != 0;
+}
+
+TilePlan tile_plan(const Ctx &ctx, uint64_t nhubs) {
+    TilePlan t;
+    while ((nhubs + t.q - 1) / t.q > 65536) t.q <<= 1;
+    t.nblk = (uint32_t)std::max<uint64_t>(1, (nhubs + t.q - 1) / t.q);
+    t.T = std::max<uint32_t>(1, std::min<uint32_t>(t.nblk, (uint32_t)ctx.n_cu * 64));
+    return t;
+}
+
+void enqueue_tiles(hipStream_t s, const TilePlan &tp, const uint64_t *rp, const GDesc *gd, int ng, uint32_t h0,
+                   uint32_t h1, unsigned long long *cost, uint32_t *tiles) {
+    k_block_cost<<<(tp.nblk + 255) / 256, 256, 0, s>>>(rp, gd, ng, h0, h1, tp.q, cost, tp.nblk);
+    GS_HIP(hipGetLastError());
+    k_tile_bounds<<<1, kTileScanBlock, 0, s>>>(cost, tp.nblk, tp.q, h0, h1, tp.T, tiles);
+    GS_HIP(hipGetLastError());
+}
+
 // Rows of 2^30 or more spoke entries take 64-bit addresses (GS_WIDE=1
 // forces them, for tests).
 bool wide_rows(uint64_t entries) {
@@ -763,9 +909,10 @@ bool wide_rows(uint64_t entries) {
 // Hubs per group and the packed key layout: groups need packed keys with
 // room for the hub index (bins below 64) and 32-bit row offsets with two
 // spare bits (GS_GROUP caps the group size, for tests).
-void set_groups(C3Args &a, const Plan3 &P, int nb, bool wide) {
+void set_groups(C3Args &a, const Plan3 &P, int nb, bool wide, const Tune3 &tune) {
     a.yshift = P.packed && nb <= 64 ? 26 : 24;
     a.kmax = P.packed && nb <= 64 && !wide ? kMaxGroup : 1;
+    if (tune.group > 0) a.kmax = std::min(a.kmax, tune.group);
     if (const char *eg = getenv("GS_GROUP")) a.kmax = std::max(1, std::min(a.kmax, atoi(eg)));
     a.group_cap = std::min<uint64_t>(a.maxdeg, (uint64_t)P.block);
 }
@@ -785,25 +932,29 @@ void launch3_any(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P, bool 
 // Work-group size and LDS plan: hash table at load factor <= 1/2 where it
 // fits (<= 0.7 otherwise), 512 threads per hub for long rows.
 Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchored, uint64_t max_n,
-            double mean_row) {
+            double mean_row, const Tune3 &tune) {
     Plan3 p;
-    p.glog = group_log(mean_row);
+    p.glog = tune.glog >= 0 ? std::min(6, tune.glog) : group_log(mean_row);
     // GS_PACK=0 / GS_MODE3=rank|lut|cube / GS_TMAX force other paths (tests)
     p.packed = max_n < (1ull << 24) - 1;
     if (const char *ep = getenv("GS_PACK")) p.packed = p.packed && atoi(ep) != 0;
     const int nconf = (int)n_configs(nb);
     if (maxdeg > 16384) fail(GS_EUNSUPPORTED, "forward degree above 16384");
     if (const char *eb = getenv("GS_BLOCK3")) p.block = atoi(eb) == 512 ? 512 : atoi(eb) == 128 ? 128 : 256;
+    else if (tune.block > 0) p.block = tune.block == 512 ? 512 : 256;
     else p.block = maxdeg >= 1024 ? 512 : 256;
-    p.tmax = 2 * (uint32_t)p.block;
-    if (const char *em = getenv("GS_TMAX")) p.tmax = std::max(64, std::min(1 << 16, atoi(em)));
+    p.tmax = tune.tmax > 0 ? (uint32_t)tune.tmax : 2 * (uint32_t)p.block;
+    if (const char *em = getenv("GS_TMAX")) p.tmax = atoi(em);
+    p.tmax = std::max<uint32_t>(64, std::min<uint32_t>(1 << 16, p.tmax));
     p.tcap = p.tmax + kUnroll3 * ((uint32_t)p.block >> p.glog);
     // the per-spoke binary search pays off on long rows only
     if (const char *et = getenv("GS_TRUNC")) p.trunc = atoi(et) != 0;
     else p.trunc = maxdeg >= 1024;
     // per-work-group LDS counters while they fit; global atomics beyond
     p.lds_hist = nconf <= 8192;
-    int want = nb <= kCubeMaxBins && !weighted ? kCube : nb <= kLutMaxBins ? kLut : kRank;
+    int want = nb <= kLutMaxBins ? kLut : kRank;
+    if (tune.mode == kRank) want = kRank;
+    if (tune.mode == kCube && nb <= kCubeMaxBins && !weighted) want = kCube;
     if (const char *e = getenv("GS_MODE3")) {
         if (strcmp(e, "rank") == 0) want = kRank;
         else if (strcmp(e, "lut") == 0 && nb <= kLutMaxBins) want = kLut;
@@ -893,7 +1044,10 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
         sum_e += gs[g]->n_edges;
         if (gs[g]->n_edges >= kNarrowSpan) fail(GS_EUNSUPPORTED, "batched catalogue with 2^30 or more edges");
     }
-    const Plan3 P = plan3(ctx, maxdeg, nb, false, false, max_n, nvirt ? (double)sum_e / (double)nvirt : 0.0);
+    const double mean_row = nvirt ? (double)sum_e / (double)nvirt : 0.0;
+    const bool packed = max_n < (1ull << 24) - 1;
+    const Tune3 tune = tuned_for(ctx, tune_key(nb, false, packed, maxdeg, mean_row));
+    const Plan3 P = plan3(ctx, maxdeg, nb, false, false, max_n, mean_row, tune);
     b.ng = ng;
     b.nconf = nconf;
     const size_t per = (size_t)nconf + 1;
@@ -902,7 +1056,12 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     const size_t qoff = ((size_t)ng * per + 1 + 31) / 32 * 32;
     const std::vector<uint16_t> cfg = config_table(nb);
     const size_t coff = qoff + kQueueWords / 2;
-    const size_t words = coff + (cfg.size() + 3) / 4;
+    // | hub tile bounds | block costs
+    const bool use_tiles = tiles_enabled();
+    const TilePlan tp = tile_plan(ctx, nvirt);
+    const size_t toff = coff + (cfg.size() + 3) / 4;
+    const size_t boff = toff + (tp.T + 2) / 2;
+    const size_t words = use_tiles ? boff + tp.nblk : toff;
     b.dv.alloc(words * 8);
     unsigned long long *dv = b.dv.as<unsigned long long>();
     b.hostdesc.alloc(sizeof(GDesc) * ng);
@@ -946,7 +1105,12 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     a.queue = (uint32_t *)(dv + qoff);
     a.err = (uint32_t *)(dv + (size_t)ng * per);
     a.cfg3 = (const uint16_t *)(dv + coff);
-    set_groups(a, P, nb, false);
+    set_groups(a, P, nb, false, tune);
+    if (nvirt > 0 && use_tiles) {
+        enqueue_tiles(s, tp, nullptr, a.gd, ng, 0, (uint32_t)nvirt, dv + boff, (uint32_t *)(dv + toff));
+        a.tiles = (uint32_t *)(dv + toff);
+        a.ntiles = tp.T;
+    }
     if (nvirt > 0) {
         if (P.block == 512) launch3_batch<512>(ctx, s, a, P);
         else if (P.block == 128) launch3_batch<128>(ctx, s, a, P);
@@ -959,15 +1123,17 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
 }
 
 void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64_t *ntri,
-                const gs_anchor_range *anchors) {
+                const gs_anchor_range *anchors, const Tune3 *force, uint32_t sample_lo, uint32_t sample_hi) {
     const int nb = g.nbins;
     const int nconf = (int)n_configs(nb);
     const bool weighted = wsum != nullptr;
     const bool anchored = anchors != nullptr;
     if (anchored && (anchors->lo > anchors->hi)) fail(GS_EINVAL, "anchor range lo > hi");
     const uint32_t maxdeg = g.max_deg;
-    const Plan3 P = plan3(ctx, maxdeg, nb, weighted, anchored, (uint64_t)g.n,
-                          g.n ? (double)g.n_edges / (double)g.n : 0.0);
+    const double mean_row = g.n ? (double)g.n_edges / (double)g.n : 0.0;
+    const bool packed = (uint64_t)g.n < (1ull << 24) - 1;
+    const Tune3 tune = force ? *force : tuned_for(ctx, tune_key(nb, weighted, packed, maxdeg, mean_row));
+    const Plan3 P = plan3(ctx, maxdeg, nb, weighted, anchored, (uint64_t)g.n, mean_row, tune);
     const int W = g.n_windows;
     const int ntiles = W * (W + 1) / 2;
 
@@ -976,7 +1142,14 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     const size_t qoff = (3 * (size_t)nconf + 2 + 31) / 32 * 32;
     const std::vector<uint16_t> cfg = config_table(nb);   // | configuration table
     const size_t coff = qoff + (size_t)ntiles * kQueueWords / 2;
-    const size_t words = coff + (cfg.size() + 3) / 4;
+    // | hub tile bounds | block costs
+    const bool use_tiles = tiles_enabled();
+    uint64_t max_hubs = 1;
+    for (int w = 0; w < W; ++w) max_hubs = std::max<uint64_t>(max_hubs, W == 1 ? g.n : g.win[w + 1] - g.win[w]);
+    const TilePlan tp = tile_plan(ctx, max_hubs);
+    const size_t toff = coff + (cfg.size() + 3) / 4;
+    const size_t boff = toff + (tp.T + 2) / 2;
+    const size_t words = use_tiles ? boff + tp.nblk : toff;
     unsigned long long *dv = (unsigned long long *)ctx.scratch_get(words * 8);
     C3Args a{};
     a.rp = g.row_ptr.as<uint64_t>();
@@ -1002,6 +1175,8 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.err = (uint32_t *)(dv + 3 * (size_t)nconf + 1);
     a.cfg3 = (const uint16_t *)(dv + coff);
     uint32_t *queues = (uint32_t *)(dv + qoff);
+    uint32_t *tbounds = (uint32_t *)(dv + toff);
+    unsigned long long *bcost = dv + boff;
 
     hipStream_t s = ctx.stream;
     GS_HIP(hipEventRecord(ctx.ev[0], s));
@@ -1024,9 +1199,19 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
         a.hbase = a.sbase = 0;
         a.h0 = a.s0 = 0;
         a.h1 = a.s1 = (uint32_t)g.n;
+        if (sample_hi > sample_lo) {
+            a.h0 = std::min<uint32_t>(sample_lo, (uint32_t)g.n);
+            a.h1 = std::min<uint32_t>(sample_hi, (uint32_t)g.n);
+        }
         a.queue = queues;
+        if (use_tiles) {
+            const TilePlan t1 = tile_plan(ctx, a.h1 - a.h0);
+            enqueue_tiles(s, t1, a.rp, nullptr, 0, a.h0, a.h1, bcost, tbounds);
+            a.tiles = tbounds;
+            a.ntiles = t1.T;
+        }
         const bool wide = wide_rows(g.n_edges);
-        set_groups(a, P, nb, wide);
+        set_groups(a, P, nb, wide, tune);
         launch3_any(ctx, s, a, P, weighted, anchored, wide);
     } else if (g.n > 0) {
         // host-tiled graph: spoke window S resident, hub windows H <= S
@@ -1099,8 +1284,14 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
             b.h0 = (uint32_t)g.win[t.H];
             b.h1 = (uint32_t)g.win[t.H + 1];
             b.queue = queues + ti * kQueueWords;
+            if (use_tiles) {
+                const TilePlan tt = tile_plan(ctx, b.h1 - b.h0);
+                enqueue_tiles(s, tt, a.rp, nullptr, 0, b.h0, b.h1, bcost, tbounds);
+                b.tiles = tbounds;
+                b.ntiles = tt.T;
+            }
             const bool wide = wide_rows(maxE);
-            set_groups(b, P, nb, wide);
+            set_groups(b, P, nb, wide, tune);
             launch3_any(ctx, s, b, P, weighted, anchored, wide);
             if (t.hslot >= 0) GS_HIP(hipEventRecord(ev_hfree[t.hslot], s));
             if (t.last_of_S) GS_HIP(hipEventRecord(ev_sfree[sk], s));
@@ -1135,6 +1326,134 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     // merge-walk bytes: each hub-spoke step reads both forward half-lists,
     // 5 bytes per entry: 2.5 B x sum_i m_i^2 over full degrees m_i
     ctx.t.alg_bytes = g.stats_ready ? (uint64_t)(2.5 * (double)g.sum_sq_deg) : 0;
+}
+
+}  // namespace gsn
+
+namespace gsn {
+
+// Coordinate descent over the schedule on a centred run of hubs that takes a
+// few milliseconds: each parameter in turn takes the value that times
+// fastest (by more than 2%), the others held at their current best.
+void tune3(Ctx &ctx, const Graph &g, bool weighted, gs_plan3 *out) {
+    if (g.n_windows != 1) fail(GS_EUNSUPPORTED, "schedules are tuned on device-resident graphs");
+    if (weighted && !(g.flags & GS_WEIGHTED)) fail(GS_EINVAL, "graph has no weights");
+    const int nb = g.nbins;
+    const size_t nconf = (size_t)n_configs(nb);
+    const uint32_t n = (uint32_t)g.n;
+    const double mean_row = g.n ? (double)g.n_edges / (double)g.n : 0.0;
+    const bool packed = (uint64_t)g.n < (1ull << 24) - 1;
+    const bool wide = wide_rows(g.n_edges);
+    std::vector<uint64_t> hist(nconf), ws(weighted ? 2 * nconf : 0);
+    uint64_t ntri = 0;
+    int trials = 0;
+    auto trial = [&](const Tune3 &t, uint32_t lo, uint32_t hi) {
+        double best = 1e300;
+        for (int r = 0; r < 2; ++r) {
+            count3_run(ctx, g, hist.data(), weighted ? ws.data() : nullptr, &ntri, nullptr, &t, lo, hi);
+            best = std::min(best, (double)ctx.t.kernel_ms);
+            if (best > 100.0) break;   // long samples time steadily: once is enough
+        }
+        ++trials;
+        return best;
+    };
+
+    // the built-in schedule, spelled out
+    const Plan3 P0 = plan3(ctx, g.max_deg, nb, weighted, false, (uint64_t)g.n, mean_row, Tune3());
+    Tune3 cur;
+    cur.block = P0.block;
+    cur.glog = P0.glog;
+    cur.tmax = (int)P0.tmax;
+    cur.mode = P0.mode;
+    cur.group = packed && nb <= 64 && !wide ? kMaxGroup : 1;
+
+    // the sample: every hub when a full count takes under ~30 ms, else a
+    // centred hub run grown (or shrunk) to 10..40 ms but never below 64 hubs
+    // per compute unit (short runs mistime the schedules: the launch tail and
+    // the sample's own skew weigh too much)
+    const uint64_t min_len = std::min<uint64_t>(n, (uint64_t)ctx.n_cu * 64);
+    uint64_t len = std::max<uint64_t>(min_len, n / 16);
+    uint32_t lo = 0, hi = n;
+    double t0 = 0;
+    for (int it = 0; it < 8 && n > 0; ++it) {
+        lo = (uint32_t)((n - len) / 2);
+        hi = (uint32_t)(lo + len);
+        t0 = trial(cur, lo, hi);
+        if (len >= n) break;
+        const double full = t0 * (double)n / (double)len;
+        if (full <= 30.0) {
+            len = n;
+            continue;
+        }
+        if (t0 >= 10.0 && t0 <= 40.0) break;
+        const double f = std::max(0.25, std::min(8.0, 20.0 / std::max(t0, 1e-3)));
+        const uint64_t next = std::max<uint64_t>(min_len, std::min<uint64_t>(n, (uint64_t)((double)len * f)));
+        if (next == len) break;
+        len = next;
+    }
+    double best = t0;
+    auto consider = [&](Tune3 t) {
+        const double ms = trial(t, lo, hi);
+        if (ms < 0.98 * best) {
+            best = ms;
+            cur = t;
+        }
+    };
+    if (n > 0) {
+        // counter addressing
+        for (int m : {kLut, kCube, kRank}) {
+            if (m == cur.mode) continue;
+            if (m == kLut && nb > kLutMaxBins) continue;
+            if (m == kCube && (nb > kCubeMaxBins || weighted)) continue;
+            Tune3 t = cur;
+            t.mode = m;
+            consider(t);
+        }
+        // candidates per step
+        const int g0 = cur.glog;
+        for (int d : {-1, 1, -2, 2}) {
+            const int gl = g0 + d;
+            if (gl < 0 || gl > 6) continue;
+            Tune3 t = cur;
+            t.glog = gl;
+            consider(t);
+        }
+        // hubs per group
+        if (cur.group > 1)
+            for (int k : {1, 2}) {
+                Tune3 t = cur;
+                t.group = k;
+                consider(t);
+            }
+        // step table and work-group size
+        for (int f : {2, 4}) {
+            Tune3 t = cur;
+            t.tmax = f == 2 ? cur.tmax / 2 : cur.tmax * 2;
+            if (t.tmax >= 128 && t.tmax <= 8192) consider(t);
+        }
+        Tune3 t = cur;
+        t.block = cur.block == 512 ? 256 : 512;
+        consider(t);
+    }
+    const uint64_t key = tune_key(nb, weighted, packed, g.max_deg, mean_row);
+    bool found = false;
+    for (auto &kv : ctx.tuned)
+        if (kv.first == key) {
+            kv.second = cur;
+            found = true;
+        }
+    if (!found) ctx.tuned.emplace_back(key, cur);
+    if (out) {
+        out->block = cur.block;
+        out->step_log2 = cur.glog;
+        out->group = cur.group;
+        out->table = cur.tmax;
+        out->counters = cur.mode;
+        out->trials = trials;
+        out->sample_ms = best;
+        out->default_ms = t0;
+        out->sample_frac = n ? (double)(hi - lo) / (double)n : 0.0;
+    }
 }
 
 }  // namespace gsn

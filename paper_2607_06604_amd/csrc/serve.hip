@@ -230,6 +230,7 @@ Server &server_of(Ctx &ctx) {
         b.n_cu = ctx.n_cu;
         b.max_lds = ctx.max_lds;
         b.budget = ~0ull;  // serving admits by footprint itself; graphs stay resident
+        b.tuned = ctx.tuned;  // schedules tuned in the context before its first request
         GS_HIP(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));
         b.own_stream = true;
         GS_HIP(hipStreamCreateWithFlags(&b.copy_stream, hipStreamNonBlocking));

@@ -39,7 +39,7 @@ GS_CANCELLED = 3
 # every symbol include/gsn.h declares
 EXPORTS = ["gs_create", "gs_destroy", "gs_build_graph", "gs_graph_info", "gs_graph_export",
            "gs_graph_free", "gs_count_3pcf", "gs_count_4pcf_parity", "gs_count_3pcf_batch",
-           "gs_submit", "gs_poll", "gs_cancel", "gs_get_timings", "gs_strerror",
+           "gs_tune_3pcf", "gs_submit", "gs_poll", "gs_cancel", "gs_get_timings", "gs_strerror",
            "gs_last_error_detail"]
 
 
@@ -63,6 +63,13 @@ class Timings(ctypes.Structure):
     _fields_ = [("build_ms", ctypes.c_double), ("count_ms", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_uint64),
                 ("alg_bytes", ctypes.c_uint64)]
+
+
+class Plan3(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("step_log2", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("table", ctypes.c_int32), ("counters", ctypes.c_int32), ("trials", ctypes.c_int32),
+                ("sample_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("sample_frac", ctypes.c_double)]
 
 
 class Request(ctypes.Structure):
@@ -110,6 +117,7 @@ def load(path: str = LIB_PATH):
         "gs_count_3pcf": ([P, P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_count_4pcf_parity": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_count_3pcf_batch": ([P, P, i32, P, P], i32),
+        "gs_tune_3pcf": ([P, P, ctypes.c_uint32, ctypes.POINTER(Plan3)], i32),
         "gs_submit": ([P, ctypes.POINTER(Request), ctypes.POINTER(u64)], i32),
         "gs_poll": ([P, u64, ctypes.POINTER(Result)], i32),
         "gs_cancel": ([P, u64], i32),
@@ -232,6 +240,14 @@ class Context:
         _check(load().gs_count_4pcf_parity(self._h, g.handle, _ptr(e), _ptr(p), _ptr(m), _ptr(nk), ar),
                "gs_count_4pcf_parity")
         return Count4(e, p, m, int(nk[0]))
+
+    def tune_3pcf(self, g: "Graph", weighted=False) -> dict:
+        """Autotune the triangle-count schedule on g's shape (kept in this
+        context); returns the chosen schedule and its sample timings."""
+        out = Plan3()
+        _check(load().gs_tune_3pcf(self._h, g.handle, GS_WEIGHTED if weighted else 0, ctypes.byref(out)),
+               "gs_tune_3pcf")
+        return {k: getattr(out, k) for k, _ in Plan3._fields_}
 
     def count_3pcf_batch(self, graphs):
         """One persistent launch over several resident graphs (same nbins)."""

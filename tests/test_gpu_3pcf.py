@@ -312,3 +312,35 @@ def test_count_kernel_plans_match_oracle(ctx, monkeypatch, plan):
     again = ctx.count_3pcf(g, weighted=True)
     g.free()
     assert np.array_equal(again.hist, ref.hist) and again.wsum_int() == ref.wsum_int()
+
+
+def test_autotuned_schedule_counts_identical(gsn):
+    """The tuner times schedules on a hub sample and keeps the fastest for the
+    graph's shape; counts with the tuned schedule (plain, weighted, batched)
+    equal the oracle's, and the schedule it reports is a valid one."""
+    x = synth.neyman_scott(40_000, 40, 1.5, 80.0, 311)
+    w = synth.uniform_values(len(x), 0.5, 1.0, 312)
+    L, rmax, nb = 80.0, 3.5, 12
+    ref = oracle.count_3pcf(x, L, 0.0, rmax, nb, weights=w)
+    with gsn.Context(0) as c:
+        g = c.build_graph(x, L, 0.0, rmax, nb)
+        plan = c.tune_3pcf(g)
+        say("plan", plan)
+        assert plan["block"] in (256, 512) and 0 <= plan["step_log2"] <= 6
+        assert 1 <= plan["group"] <= 4 and plan["counters"] in (0, 1, 2) and plan["table"] >= 64
+        assert plan["trials"] >= 2 and 0 < plan["sample_ms"] <= plan["default_ms"] * 1.0001
+        assert 0 < plan["sample_frac"] <= 1
+        got = c.count_3pcf(g)
+        assert np.array_equal(got.hist, ref.hist) and got.n_triangles == ref.n_triangles
+        bat = c.count_3pcf_batch([g, g])
+        assert np.array_equal(bat[0].hist, ref.hist) and np.array_equal(bat[1].hist, ref.hist)
+        g.free()
+        gw = c.build_graph(x, L, 0.0, rmax, nb, weights=w)
+        pw = c.tune_3pcf(gw, weighted=True)
+        assert pw["counters"] != 2   # no per-triple counters for weighted sums
+        gotw = c.count_3pcf(gw, weighted=True)
+        assert np.array_equal(gotw.hist, ref.hist) and gotw.wsum_int() == ref.wsum_int()
+        with pytest.raises(gsn.GsError) as e:
+            c.tune_3pcf(c.build_graph(x, L, 0.0, rmax, nb), weighted=True)
+        assert e.value.code == gsn.GS_EINVAL
+        gw.free()
