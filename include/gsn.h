@@ -164,7 +164,8 @@ int gs_count_3pcf_batch(gs_ctx *ctx, const gs_graph *const *graphs, int ng, uint
  * The count's schedule: threads per work group, candidates per step (the
  * lanes that walk one spoke row together, Sec. 3.5.2), hubs per group (hubs
  * counted together, their rows contiguous in the CSR of Sec. 3.5.1), step
- * table entries, and how a hit finds its counter. gs_tune_3pcf times
+ * table entries, how a hit finds its counter, and the hub hash table's load
+ * bound. gs_tune_3pcf times
  * candidate schedules on a sample of g's hubs (counts discarded), starting
  * from the built-in choice and changing one parameter at a time while that
  * helps; the fastest is kept in the context for graphs of g's shape (bin
@@ -183,6 +184,7 @@ typedef struct {
     int32_t table;       /* step table entries per fill                          */
     int32_t counters;    /* 0: rank arithmetic, 1: table of counter addresses,   */
                          /* 2: per-(x,y,z) counters folded at flush              */
+    int32_t hash_load;   /* hub hash table load bound: 5 (1/2) or 7 (0.7)         */
     int32_t trials;      /* schedules timed                                      */
     double sample_ms;    /* chosen schedule on the sample (kernel time)          */
     double default_ms;   /* built-in schedule on the same sample                 */

@@ -244,11 +244,12 @@ struct Walk {
 // counters (kCube) or of row x of the configuration table (kLut), whose
 // entries are counter addresses (or indices); with kRank it is x itself.
 template <int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
-__device__ __forceinline__ void count_hit(const Walk &c, uint32_t k, uint32_t meta, uint32_t y, uint32_t z,
-                                          uint32_t hub, unsigned long long &mytri) {
+__device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk, uint32_t meta, uint32_t y,
+                                          uint32_t z, uint32_t hub, unsigned long long &mytri) {
+    // pk, wk: original index and weight of the third vertex (anchored / weighted)
     const uint32_t slot = (meta >> 7) & 511u;
     if (ANCHORED) {
-        const uint32_t mm = min(c.hp[hub], min(c.mperm[slot], c.perm[k]));
+        const uint32_t mm = min(c.hp[hub], min(c.mperm[slot], pk));
         if (mm < c.anchor_lo || mm >= c.anchor_hi) return;
     }
     if (MODE == kCube) {
@@ -277,7 +278,7 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t k, uint32_t me
         ++mytri;
     }
     if (WEIGHTED) {
-        double p = c.hw[hub], q = c.mw[slot], r = c.w[k], t;
+        double p = c.hw[hub], q = c.mw[slot], r = wk, t;
         if (p > q) { t = p; p = q; q = t; }
         if (q > r) { t = q; q = r; r = t; }
         if (p > q) { t = p; p = q; q = t; }
@@ -342,9 +343,13 @@ __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned l
             }
             key[u] = c.hkey[hh[u]];
         }
-        // 3. probe sequences to their ends, and the hits
+        // 3. probe sequences to their ends: hit flag and the bin of (hub, k)
+        bool hit[U];
+        uint32_t yy[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            hit[u] = false;
+            yy[u] = 0;
             if (!ok[u]) continue;
             const uint32_t q = kk[u];
             uint32_t h = hh[u], kv = key[u];
@@ -353,18 +358,34 @@ __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned l
                     h = (h + 1) & c.mask;
                     kv = c.hkey[h];
                 }
-                if (kv != kEmptyKey)
-                    count_hit<MODE, WEIGHTED, ANCHORED, LDS_HIST>(c, q & 0xFFFFFFu, meta[u], kv >> c.ys, zz[u],
-                                                                  hub[u], mytri);
+                hit[u] = kv != kEmptyKey;
+                yy[u] = kv >> c.ys;
+                kk[u] = q & 0xFFFFFFu;
             } else {
                 while (kv != q && kv != kEmptyKey) {
                     h = (h + 1) & c.mask;
                     kv = c.hkey[h];
                 }
-                if (kv == q)
-                    count_hit<MODE, WEIGHTED, ANCHORED, LDS_HIST>(c, q, meta[u], c.hbin[h], zz[u], 0u, mytri);
+                hit[u] = kv == q;
+                if (hit[u]) yy[u] = c.hbin[h];
             }
         }
+        // 4. the third vertex's weight / original index, loaded for all hits
+        //    at once, then the hits
+        double wk[U];
+        uint32_t pk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            wk[u] = 0.0;
+            pk[u] = 0;
+            if (WEIGHTED && hit[u]) wk[u] = c.w[kk[u]];
+            if (ANCHORED && hit[u]) pk[u] = c.perm[kk[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (hit[u])
+                count_hit<MODE, WEIGHTED, ANCHORED, LDS_HIST>(c, pk[u], wk[u], meta[u], yy[u], zz[u],
+                                                              WIDE ? 0u : hub[u], mytri);
     }
 }
 
@@ -704,17 +725,25 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED || BATCH) ? 1 : 8) voi
     }
 }
 
-// Hub tiles balanced by the sum of squared forward degrees. Blocks of q
-// consecutive hubs get their cost; one work group scans the block costs and
-// cuts [h0, h1) at the blocks where the running cost crosses t/T of the
-// total. Batched launches number hubs across catalogues (virtual hubs).
-__global__ void k_block_cost(const uint64_t *__restrict__ rp, const GDesc *__restrict__ gd, int ng, uint32_t h0,
-                             uint32_t h1, uint32_t q, unsigned long long *__restrict__ cost, uint32_t nblk) {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nblk) return;
-    unsigned long long c = 0;
-    const uint32_t lo = h0 + b * q, hi = min(h1, lo + q);
-    for (uint32_t v = lo; v < hi; ++v) {
+// Hub tiles balanced by the sum of squared forward degrees, handed out in
+// guided order. The cost prefix runs over hubs (per 256-hub chunk, then over
+// chunks); the hub range is cut into eight slices of equal cost (one per hub
+// queue, so an XCD keeps to one slice of labels), and each slice into tiles
+// whose cost shrinks geometrically: tile u of a slice ends at the cost
+// fraction 1 - (1 - 1/(k P))^(u+1) (P teams per slice, k = 4) until 1/64 of
+// the slice is left, which goes in k P equal tiles. Batched launches number
+// hubs across catalogues (virtual hubs).
+constexpr int kTileChunk = 256;
+constexpr int kTileScanBlock = 1024;
+
+__global__ __launch_bounds__(kTileChunk) void k_hub_cost(const uint64_t *__restrict__ rp,
+                                                         const GDesc *__restrict__ gd, int ng, uint32_t h0,
+                                                         uint32_t h1, unsigned long long *__restrict__ pre,
+                                                         unsigned long long *__restrict__ chunk_tot) {
+    __shared__ uint64_t wtot[kTileChunk / 64 + 1];
+    const uint32_t v = h0 + blockIdx.x * kTileChunk + threadIdx.x;
+    uint64_t c = 0;
+    if (v < h1) {
         uint64_t d;
         if (gd) {
             const int g = graph_of(gd, ng, v);
@@ -723,48 +752,75 @@ __global__ void k_block_cost(const uint64_t *__restrict__ rp, const GDesc *__res
         } else {
             d = rp[v + 1] - rp[v];
         }
-        c += (unsigned long long)(d * d);
+        c = d * d;
     }
-    cost[b] = c;
+    uint64_t tot;
+    const uint64_t ex = wg_excl_scan64<kTileChunk>(c, wtot, tot);
+    if (v < h1) pre[v - h0] = ex + c;
+    if (threadIdx.x == 0) chunk_tot[blockIdx.x] = tot;
 }
 
-constexpr int kTileScanBlock = 1024;
+// Cost fraction at the end of tile u of a slice with Tq tiles (see above).
+__device__ __forceinline__ double tile_frac(uint32_t u, uint32_t tq, uint32_t kp, uint32_t tstar, double lq) {
+    if (u + 1 >= tq) return 1.0;
+    if (u + 1 <= tstar) return 1.0 - exp(lq * (double)(u + 1));
+    const double r = exp(lq * (double)tstar);
+    return 1.0 - r + r * (double)(u + 1 - tstar) / (double)kp;
+}
 
-__global__ __launch_bounds__(kTileScanBlock) void k_tile_bounds(unsigned long long *__restrict__ cost,
-                                                                 uint32_t nblk, uint32_t q, uint32_t h0,
-                                                                 uint32_t h1, uint32_t T,
-                                                                 uint32_t *__restrict__ tiles) {
+__global__ __launch_bounds__(kTileScanBlock) void k_tile_bounds(const unsigned long long *__restrict__ pre,
+                                                                 unsigned long long *__restrict__ chunk_tot,
+                                                                 uint32_t nchunk, uint32_t h0, uint32_t h1,
+                                                                 uint32_t tq, uint32_t kp, uint32_t tstar,
+                                                                 double lq, uint32_t *__restrict__ tiles) {
     __shared__ uint64_t wtot[kTileScanBlock / 64 + 1];
     const uint32_t tid = threadIdx.x;
-    // each thread scans a contiguous share of the blocks (inclusive)
-    const uint32_t per = (nblk + kTileScanBlock - 1) / kTileScanBlock;
-    const uint32_t b0 = min(nblk, tid * per), b1 = min(nblk, b0 + per);
+    // inclusive scan of the chunk totals, a contiguous share per thread
+    const uint32_t per = (nchunk + kTileScanBlock - 1) / kTileScanBlock;
+    const uint32_t b0 = min(nchunk, tid * per), b1 = min(nchunk, b0 + per);
     uint64_t run = 0;
-    for (uint32_t b = b0; b < b1; ++b) run += cost[b];
+    for (uint32_t b = b0; b < b1; ++b) run += chunk_tot[b];
     uint64_t total;
-    const uint64_t off = wg_excl_scan64<kTileScanBlock>(run, wtot, total);
-    run = off;
+    run = wg_excl_scan64<kTileScanBlock>(run, wtot, total);
     for (uint32_t b = b0; b < b1; ++b) {
-        run += cost[b];
-        cost[b] = run;
+        run += chunk_tot[b];
+        chunk_tot[b] = run;
     }
     __syncthreads();
+    const uint32_t T = 8 * tq;
     for (uint32_t t = tid; t <= T; t += kTileScanBlock) {
         uint32_t at;
         if (t == 0) {
             at = h0;
-        } else if (t == T || total == 0) {
-            at = t == T ? h1 : (uint32_t)min<uint64_t>(h1, h0 + (uint64_t)(h1 - h0) * t / T);
+        } else if (t == T) {
+            at = h1;
+        } else if (total == 0) {
+            at = (uint32_t)min<uint64_t>(h1, h0 + (uint64_t)(h1 - h0) * t / T);
         } else {
-            // first block whose running cost passes t/T of the total
-            const uint64_t target = (uint64_t)((unsigned __int128)total * t / T);
-            uint32_t lo = 0, hi = nblk;
+            // tile t - 1 ends at cost fraction (slice + its fraction) / 8
+            const uint32_t sl = (t - 1) / tq, u = (t - 1) % tq;
+            const double f = ((double)sl + tile_frac(u, tq, kp, tstar, lq)) / 8.0;
+            const uint64_t target = (uint64_t)min((double)total, f * (double)total);
+            // first hub whose inclusive cost exceeds the target
+            uint32_t lo = 0, hi = nchunk;
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
-                if (cost[mid] <= target) lo = mid + 1;
+                if (chunk_tot[mid] <= target) lo = mid + 1;
                 else hi = mid;
             }
-            at = (uint32_t)min<uint64_t>(h1, h0 + (uint64_t)lo * q);
+            if (lo >= nchunk) {
+                at = h1;
+            } else {
+                const uint64_t base = lo ? chunk_tot[lo - 1] : 0;
+                const uint32_t c0 = lo * kTileChunk, c1 = min(h1 - h0, c0 + kTileChunk);
+                uint32_t a = c0, b = c1;
+                while (a < b) {
+                    const uint32_t mid = (a + b) >> 1;
+                    if (base + pre[mid] <= target) a = mid + 1;
+                    else b = mid;
+                }
+                at = h0 + a;
+            }
         }
         tiles[t] = at;
     }
@@ -845,6 +901,7 @@ Tune3 tuned_for(const Ctx &ctx, uint64_t key) {
 struct Plan3 {
     int block = 256;
     int glog = 0;
+    int hload = 5;
     int trunc = 0;
     bool packed = true;
     int mode = kLut;
@@ -870,11 +927,13 @@ std::vector<uint16_t> config_table(int nb) {
     return t;
 }
 
-// Hub tiles for [h0, h1): at most T of about equal sum of squared forward
-// degree, cut at multiples of q hubs (q keeps the block count <= 2^16).
-// GS_TILES=0 turns them off (hubs then go out in guided runs).
+// Guided cost tiles for up to nhubs hubs (see k_tile_bounds): Tq tiles per
+// slice for P = teams / 8 teams per slice. GS_TILES=0 turns them off (hubs
+// then go out in runs of guided length by count).
 struct TilePlan {
-    uint32_t q = 16, nblk = 1, T = 1;
+    uint32_t nchunk = 1, tq = 1, kp = 1, tstar = 0;
+    double lq = 0;
+    uint32_t T() const { return 8 * tq; }
 };
 
 bool tiles_enabled() {
@@ -884,17 +943,24 @@ bool tiles_enabled() {
 
 TilePlan tile_plan(const Ctx &ctx, uint64_t nhubs) {
     TilePlan t;
-    while ((nhubs + t.q - 1) / t.q > 65536) t.q <<= 1;
-    t.nblk = (uint32_t)std::max<uint64_t>(1, (nhubs + t.q - 1) / t.q);
-    t.T = std::max<uint32_t>(1, std::min<uint32_t>(t.nblk, (uint32_t)ctx.n_cu * 64));
+    t.nchunk = (uint32_t)std::max<uint64_t>(1, (nhubs + kTileChunk - 1) / kTileChunk);
+    // teams per slice (8 per CU over 8 slices), fewer for small graphs so
+    // that tiles average at least ~8 hubs (a slice holds about 20 P tiles)
+    const uint32_t P = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ctx.n_cu, nhubs / 1320));
+    t.kp = 4 * P;
+    t.lq = std::log1p(-1.0 / (double)t.kp);
+    t.tstar = (uint32_t)std::ceil(std::log(64.0) / -t.lq);
+    t.tq = t.tstar + t.kp;
     return t;
 }
 
 void enqueue_tiles(hipStream_t s, const TilePlan &tp, const uint64_t *rp, const GDesc *gd, int ng, uint32_t h0,
-                   uint32_t h1, unsigned long long *cost, uint32_t *tiles) {
-    k_block_cost<<<(tp.nblk + 255) / 256, 256, 0, s>>>(rp, gd, ng, h0, h1, tp.q, cost, tp.nblk);
+                   uint32_t h1, unsigned long long *pre, unsigned long long *chunk_tot, uint32_t *tiles) {
+    const uint32_t nchunk = std::max<uint32_t>(1, (h1 - h0 + kTileChunk - 1) / kTileChunk);
+    k_hub_cost<<<nchunk, kTileChunk, 0, s>>>(rp, gd, ng, h0, h1, pre, chunk_tot);
     GS_HIP(hipGetLastError());
-    k_tile_bounds<<<1, kTileScanBlock, 0, s>>>(cost, tp.nblk, tp.q, h0, h1, tp.T, tiles);
+    k_tile_bounds<<<1, kTileScanBlock, 0, s>>>(pre, chunk_tot, nchunk, h0, h1, tp.tq, tp.kp, tp.tstar, tp.lq,
+                                                tiles);
     GS_HIP(hipGetLastError());
 }
 
@@ -931,6 +997,10 @@ void launch3_any(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P, bool 
 
 // Work-group size and LDS plan: hash table at load factor <= 1/2 where it
 // fits (<= 0.7 otherwise), 512 threads per hub for long rows.
+// The schedule's LDS layout: among hash loads 1/2 and 0.7, the counter mode
+// (or rank arithmetic) and a full or halved step table, the choice that
+// fits the most wavefronts per CU, earlier choices first on ties. Tuned
+// values and GS_* test overrides pin their parameter.
 Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchored, uint64_t max_n,
             double mean_row, const Tune3 &tune) {
     Plan3 p;
@@ -943,47 +1013,70 @@ Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchore
     if (const char *eb = getenv("GS_BLOCK3")) p.block = atoi(eb) == 512 ? 512 : atoi(eb) == 128 ? 128 : 256;
     else if (tune.block > 0) p.block = tune.block == 512 ? 512 : 256;
     else p.block = maxdeg >= 1024 ? 512 : 256;
-    p.tmax = tune.tmax > 0 ? (uint32_t)tune.tmax : 2 * (uint32_t)p.block;
-    if (const char *em = getenv("GS_TMAX")) p.tmax = atoi(em);
-    p.tmax = std::max<uint32_t>(64, std::min<uint32_t>(1 << 16, p.tmax));
-    p.tcap = p.tmax + kUnroll3 * ((uint32_t)p.block >> p.glog);
+    int tmax_pin = tune.tmax > 0 ? tune.tmax : 0;
+    if (const char *em = getenv("GS_TMAX")) tmax_pin = atoi(em);
     // the per-spoke binary search pays off on long rows only
     if (const char *et = getenv("GS_TRUNC")) p.trunc = atoi(et) != 0;
     else p.trunc = maxdeg >= 1024;
     // per-work-group LDS counters while they fit; global atomics beyond
-    p.lds_hist = nconf <= 8192;
+    const bool lds_hist_ok = nconf <= 8192;
     int want = nb <= kLutMaxBins ? kLut : kRank;
-    if (tune.mode == kRank) want = kRank;
-    if (tune.mode == kCube && nb <= kCubeMaxBins && !weighted) want = kCube;
+    bool mode_pin = false;
+    if (tune.mode == kRank) want = kRank, mode_pin = true;
+    if (tune.mode == kLut && nb <= kLutMaxBins) want = kLut, mode_pin = true;
+    if (tune.mode == kCube && nb <= kCubeMaxBins && !weighted) want = kCube, mode_pin = true;
     if (const char *e = getenv("GS_MODE3")) {
+        mode_pin = true;
         if (strcmp(e, "rank") == 0) want = kRank;
         else if (strcmp(e, "lut") == 0 && nb <= kLutMaxBins) want = kLut;
         else if (strcmp(e, "cube") == 0 && nb <= kCubeMaxBins && !weighted) want = kCube;
     }
-    for (int half = 1; half >= 0; --half) {
+    const int hload_pin = tune.hload;   // 5: load <= 1/2, 7: load <= 0.7
+    int best_waves = -1;
+    for (int hl : {5, 7}) {
+        if (hload_pin && hl != hload_pin) continue;
         uint32_t H = 64;
-        p.log2h = 6;
-        while (half ? H < 2 * maxdeg : (uint64_t)H * 7 < (uint64_t)maxdeg * 10) { H <<= 1; ++p.log2h; }
-        for (int lh = p.lds_hist; lh >= 0; --lh) {
-            // the cube lives in LDS; table entries hold 16-bit counter addresses
-            int mode = want;
-            if (mode == kCube && !lh) mode = nb <= kLutMaxBins ? kLut : kRank;
-            if (mode == kLut && lh && 4 * (uint64_t)nconf + 2 * (uint64_t)nb * nb * nb >= 65536) mode = kRank;
-            const Layout3 L = layout3(p.block, H, maxdeg, p.tcap, nconf, nb, weighted, anchored, lh, p.packed, mode);
-            if ((int)L.total <= ctx.max_lds) {
-                p.lds_hist = lh;
-                p.mode = mode;
-                p.lds = L.total;
-                if (getenv("GS_PLAN_LOG"))
-                    fprintf(stderr, "count3 plan: maxdeg %u mean_row %.1f block %d glog %d mode %d packed %d H %u "
-                                    "tmax %u tcap %u lds_hist %d trunc %d lds %u\n",
-                            maxdeg, mean_row, p.block, p.glog, p.mode, (int)p.packed, H, p.tmax, p.tcap,
-                            (int)p.lds_hist, p.trunc, p.lds);
-                return p;
+        int log2h = 6;
+        while (hl == 5 ? H < 2 * maxdeg : (uint64_t)H * 7 < (uint64_t)maxdeg * 10) { H <<= 1; ++log2h; }
+        for (int mi = 0; mi < 2; ++mi) {
+            int mode0 = mi == 0 ? want : kRank;
+            if (mi == 1 && (mode_pin || want == kRank)) continue;
+            for (int tf = 0; tf < 2; ++tf) {
+                if (tmax_pin && tf) continue;
+                const uint32_t tmax = std::max<uint32_t>(
+                    64, std::min<uint32_t>(1 << 16, tmax_pin ? (uint32_t)tmax_pin : (tf ? 1u : 2u) * p.block));
+                const uint32_t tcap = tmax + kUnroll3 * ((uint32_t)p.block >> p.glog);
+                for (int lh = lds_hist_ok; lh >= 0; --lh) {
+                    // the cube lives in LDS; table entries hold 16-bit counter addresses
+                    int mode = mode0;
+                    if (mode == kCube && !lh) mode = nb <= kLutMaxBins ? kLut : kRank;
+                    if (mode == kLut && lh && 4 * (uint64_t)nconf + 2 * (uint64_t)nb * nb * nb >= 65536) mode = kRank;
+                    const Layout3 L = layout3(p.block, H, maxdeg, tcap, nconf, nb, weighted, anchored, lh, p.packed,
+                                              mode);
+                    if ((int)L.total > ctx.max_lds) continue;
+                    const int groups = std::max(1, ctx.max_lds / (int)L.total);
+                    const int waves = std::min(32, groups * p.block / 64);
+                    if (waves > best_waves) {
+                        best_waves = waves;
+                        p.lds_hist = lh;
+                        p.mode = mode;
+                        p.lds = L.total;
+                        p.log2h = log2h;
+                        p.tmax = tmax;
+                        p.tcap = tcap;
+                        p.hload = hl;
+                    }
+                    break;   // LDS counters preferred when they fit
+                }
             }
         }
     }
-    fail(GS_EUNSUPPORTED, "LDS footprint too large for this degree");
+    if (best_waves < 0) fail(GS_EUNSUPPORTED, "LDS footprint too large for this degree");
+    if (getenv("GS_PLAN_LOG"))
+        fprintf(stderr, "count3 plan: maxdeg %u mean_row %.1f block %d glog %d mode %d packed %d H %u "
+                        "tmax %u tcap %u lds_hist %d trunc %d lds %u waves/CU %d\n",
+                maxdeg, mean_row, p.block, p.glog, p.mode, (int)p.packed, 1u << p.log2h, p.tmax, p.tcap,
+                (int)p.lds_hist, p.trunc, p.lds, best_waves);
     return p;
 }
 
@@ -1060,8 +1153,9 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     const bool use_tiles = tiles_enabled();
     const TilePlan tp = tile_plan(ctx, nvirt);
     const size_t toff = coff + (cfg.size() + 3) / 4;
-    const size_t boff = toff + (tp.T + 2) / 2;
-    const size_t words = use_tiles ? boff + tp.nblk : toff;
+    const size_t poff = toff + (tp.T() + 2) / 2;    // | hub cost prefix | chunk costs
+    const size_t koff = poff + nvirt;
+    const size_t words = use_tiles ? koff + tp.nchunk : toff;
     b.dv.alloc(words * 8);
     unsigned long long *dv = b.dv.as<unsigned long long>();
     b.hostdesc.alloc(sizeof(GDesc) * ng);
@@ -1107,9 +1201,9 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     a.cfg3 = (const uint16_t *)(dv + coff);
     set_groups(a, P, nb, false, tune);
     if (nvirt > 0 && use_tiles) {
-        enqueue_tiles(s, tp, nullptr, a.gd, ng, 0, (uint32_t)nvirt, dv + boff, (uint32_t *)(dv + toff));
+        enqueue_tiles(s, tp, nullptr, a.gd, ng, 0, (uint32_t)nvirt, dv + poff, dv + koff, (uint32_t *)(dv + toff));
         a.tiles = (uint32_t *)(dv + toff);
-        a.ntiles = tp.T;
+        a.ntiles = tp.T();
     }
     if (nvirt > 0) {
         if (P.block == 512) launch3_batch<512>(ctx, s, a, P);
@@ -1148,8 +1242,9 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     for (int w = 0; w < W; ++w) max_hubs = std::max<uint64_t>(max_hubs, W == 1 ? g.n : g.win[w + 1] - g.win[w]);
     const TilePlan tp = tile_plan(ctx, max_hubs);
     const size_t toff = coff + (cfg.size() + 3) / 4;
-    const size_t boff = toff + (tp.T + 2) / 2;
-    const size_t words = use_tiles ? boff + tp.nblk : toff;
+    const size_t poff = toff + (tp.T() + 2) / 2;    // | hub cost prefix | chunk costs
+    const size_t koff = poff + max_hubs;
+    const size_t words = use_tiles ? koff + tp.nchunk : toff;
     unsigned long long *dv = (unsigned long long *)ctx.scratch_get(words * 8);
     C3Args a{};
     a.rp = g.row_ptr.as<uint64_t>();
@@ -1176,7 +1271,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.cfg3 = (const uint16_t *)(dv + coff);
     uint32_t *queues = (uint32_t *)(dv + qoff);
     uint32_t *tbounds = (uint32_t *)(dv + toff);
-    unsigned long long *bcost = dv + boff;
+    unsigned long long *hpre = dv + poff, *ctot = dv + koff;
 
     hipStream_t s = ctx.stream;
     GS_HIP(hipEventRecord(ctx.ev[0], s));
@@ -1206,9 +1301,9 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
         a.queue = queues;
         if (use_tiles) {
             const TilePlan t1 = tile_plan(ctx, a.h1 - a.h0);
-            enqueue_tiles(s, t1, a.rp, nullptr, 0, a.h0, a.h1, bcost, tbounds);
+            enqueue_tiles(s, t1, a.rp, nullptr, 0, a.h0, a.h1, hpre, ctot, tbounds);
             a.tiles = tbounds;
-            a.ntiles = t1.T;
+            a.ntiles = t1.T();
         }
         const bool wide = wide_rows(g.n_edges);
         set_groups(a, P, nb, wide, tune);
@@ -1286,9 +1381,9 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
             b.queue = queues + ti * kQueueWords;
             if (use_tiles) {
                 const TilePlan tt = tile_plan(ctx, b.h1 - b.h0);
-                enqueue_tiles(s, tt, a.rp, nullptr, 0, b.h0, b.h1, bcost, tbounds);
+                enqueue_tiles(s, tt, a.rp, nullptr, 0, b.h0, b.h1, hpre, ctot, tbounds);
                 b.tiles = tbounds;
-                b.ntiles = tt.T;
+                b.ntiles = tt.T();
             }
             const bool wide = wide_rows(maxE);
             set_groups(b, P, nb, wide, tune);
@@ -1365,6 +1460,7 @@ void tune3(Ctx &ctx, const Graph &g, bool weighted, gs_plan3 *out) {
     cur.glog = P0.glog;
     cur.tmax = (int)P0.tmax;
     cur.mode = P0.mode;
+    cur.hload = P0.hload;
     cur.group = packed && nb <= 64 && !wide ? kMaxGroup : 1;
 
     // the sample: every hub when a full count takes under ~30 ms, else a
@@ -1425,6 +1521,12 @@ void tune3(Ctx &ctx, const Graph &g, bool weighted, gs_plan3 *out) {
                 t.group = k;
                 consider(t);
             }
+        // hash table load
+        {
+            Tune3 t = cur;
+            t.hload = cur.hload == 5 ? 7 : 5;
+            consider(t);
+        }
         // step table and work-group size
         for (int f : {2, 4}) {
             Tune3 t = cur;
@@ -1449,6 +1551,7 @@ void tune3(Ctx &ctx, const Graph &g, bool weighted, gs_plan3 *out) {
         out->group = cur.group;
         out->table = cur.tmax;
         out->counters = cur.mode;
+        out->hash_load = cur.hload;
         out->trials = trials;
         out->sample_ms = best;
         out->default_ms = t0;

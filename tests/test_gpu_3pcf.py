@@ -328,6 +328,7 @@ def test_autotuned_schedule_counts_identical(gsn):
         say("plan", plan)
         assert plan["block"] in (256, 512) and 0 <= plan["step_log2"] <= 6
         assert 1 <= plan["group"] <= 4 and plan["counters"] in (0, 1, 2) and plan["table"] >= 64
+        assert plan["hash_load"] in (5, 7)
         assert plan["trials"] >= 2 and 0 < plan["sample_ms"] <= plan["default_ms"] * 1.0001
         assert 0 < plan["sample_frac"] <= 1
         got = c.count_3pcf(g)
