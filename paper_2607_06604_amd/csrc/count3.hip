@@ -730,9 +730,9 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED || BATCH) ? 1 : 8) voi
 // chunks); the hub range is cut into eight slices of equal cost (one per hub
 // queue, so an XCD keeps to one slice of labels), and each slice into tiles
 // whose cost shrinks geometrically: tile u of a slice ends at the cost
-// fraction 1 - (1 - 1/(k P))^(u+1) (P teams per slice, k = 4) until 1/64 of
-// the slice is left, which goes in k P equal tiles. Batched launches number
-// hubs across catalogues (virtual hubs).
+// fraction 1 - (1 - 1/(k P))^(u+1) (P teams per slice, k >= 4) until 1/64
+// of the slice is left, which goes in k P equal tiles. Batched launches
+// number hubs across catalogues (virtual hubs).
 constexpr int kTileChunk = 256;
 constexpr int kTileScanBlock = 1024;
 
@@ -768,14 +768,12 @@ __device__ __forceinline__ double tile_frac(uint32_t u, uint32_t tq, uint32_t kp
     return 1.0 - r + r * (double)(u + 1 - tstar) / (double)kp;
 }
 
-__global__ __launch_bounds__(kTileScanBlock) void k_tile_bounds(const unsigned long long *__restrict__ pre,
-                                                                 unsigned long long *__restrict__ chunk_tot,
-                                                                 uint32_t nchunk, uint32_t h0, uint32_t h1,
-                                                                 uint32_t tq, uint32_t kp, uint32_t tstar,
-                                                                 double lq, uint32_t *__restrict__ tiles) {
+// In-place inclusive scan of the chunk costs (one work group, a contiguous
+// share per thread).
+__global__ __launch_bounds__(kTileScanBlock) void k_chunk_scan(unsigned long long *__restrict__ chunk_tot,
+                                                                uint32_t nchunk) {
     __shared__ uint64_t wtot[kTileScanBlock / 64 + 1];
     const uint32_t tid = threadIdx.x;
-    // inclusive scan of the chunk totals, a contiguous share per thread
     const uint32_t per = (nchunk + kTileScanBlock - 1) / kTileScanBlock;
     const uint32_t b0 = min(nchunk, tid * per), b1 = min(nchunk, b0 + per);
     uint64_t run = 0;
@@ -786,44 +784,51 @@ __global__ __launch_bounds__(kTileScanBlock) void k_tile_bounds(const unsigned l
         run += chunk_tot[b];
         chunk_tot[b] = run;
     }
-    __syncthreads();
+}
+
+// Tile bounds, one thread per bound: the first hub whose inclusive cost
+// exceeds the bound's cost target.
+__global__ void k_tile_bounds(const unsigned long long *__restrict__ pre,
+                              const unsigned long long *__restrict__ chunk_tot, uint32_t nchunk, uint32_t h0,
+                              uint32_t h1, uint32_t tq, uint32_t kp, uint32_t tstar, double lq,
+                              uint32_t *__restrict__ tiles) {
     const uint32_t T = 8 * tq;
-    for (uint32_t t = tid; t <= T; t += kTileScanBlock) {
-        uint32_t at;
-        if (t == 0) {
-            at = h0;
-        } else if (t == T) {
-            at = h1;
-        } else if (total == 0) {
-            at = (uint32_t)min<uint64_t>(h1, h0 + (uint64_t)(h1 - h0) * t / T);
-        } else {
-            // tile t - 1 ends at cost fraction (slice + its fraction) / 8
-            const uint32_t sl = (t - 1) / tq, u = (t - 1) % tq;
-            const double f = ((double)sl + tile_frac(u, tq, kp, tstar, lq)) / 8.0;
-            const uint64_t target = (uint64_t)min((double)total, f * (double)total);
-            // first hub whose inclusive cost exceeds the target
-            uint32_t lo = 0, hi = nchunk;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (chunk_tot[mid] <= target) lo = mid + 1;
-                else hi = mid;
-            }
-            if (lo >= nchunk) {
-                at = h1;
-            } else {
-                const uint64_t base = lo ? chunk_tot[lo - 1] : 0;
-                const uint32_t c0 = lo * kTileChunk, c1 = min(h1 - h0, c0 + kTileChunk);
-                uint32_t a = c0, b = c1;
-                while (a < b) {
-                    const uint32_t mid = (a + b) >> 1;
-                    if (base + pre[mid] <= target) a = mid + 1;
-                    else b = mid;
-                }
-                at = h0 + a;
-            }
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > T) return;
+    const uint64_t total = chunk_tot[nchunk - 1];
+    uint32_t at;
+    if (t == 0) {
+        at = h0;
+    } else if (t == T) {
+        at = h1;
+    } else if (total == 0) {
+        at = (uint32_t)min<uint64_t>(h1, h0 + (uint64_t)(h1 - h0) * t / T);
+    } else {
+        // tile t - 1 ends at cost fraction (slice + its fraction) / 8
+        const uint32_t sl = (t - 1) / tq, u = (t - 1) % tq;
+        const double f = ((double)sl + tile_frac(u, tq, kp, tstar, lq)) / 8.0;
+        const uint64_t target = (uint64_t)min((double)total, f * (double)total);
+        uint32_t lo = 0, hi = nchunk;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (chunk_tot[mid] <= target) lo = mid + 1;
+            else hi = mid;
         }
-        tiles[t] = at;
+        if (lo >= nchunk) {
+            at = h1;
+        } else {
+            const uint64_t base = lo ? chunk_tot[lo - 1] : 0;
+            const uint32_t c0 = lo * kTileChunk, c1 = min(h1 - h0, c0 + kTileChunk);
+            uint32_t a = c0, b = c1;
+            while (a < b) {
+                const uint32_t mid = (a + b) >> 1;
+                if (base + pre[mid] <= target) a = mid + 1;
+                else b = mid;
+            }
+            at = h0 + a;
+        }
     }
+    tiles[t] = at;
 }
 
 __global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
@@ -945,9 +950,13 @@ TilePlan tile_plan(const Ctx &ctx, uint64_t nhubs) {
     TilePlan t;
     t.nchunk = (uint32_t)std::max<uint64_t>(1, (nhubs + kTileChunk - 1) / kTileChunk);
     // teams per slice (8 per CU over 8 slices), fewer for small graphs so
-    // that tiles average at least ~8 hubs (a slice holds about 20 P tiles)
+    // that tiles average at least ~8 hubs (a slice holds about 5.2 k P
+    // tiles); k so that the first tiles hold about 32 hubs: the hubs that
+    // an XCD's work groups count at once then span few enough labels for
+    // their spoke rows to share that XCD's L2
     const uint32_t P = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ctx.n_cu, nhubs / 1320));
-    t.kp = 4 * P;
+    const uint64_t k = std::max<uint64_t>(4, std::min<uint64_t>(64, nhubs / (8ull * P * 32)));
+    t.kp = (uint32_t)(k * P);
     t.lq = std::log1p(-1.0 / (double)t.kp);
     t.tstar = (uint32_t)std::ceil(std::log(64.0) / -t.lq);
     t.tq = t.tstar + t.kp;
@@ -959,8 +968,10 @@ void enqueue_tiles(hipStream_t s, const TilePlan &tp, const uint64_t *rp, const 
     const uint32_t nchunk = std::max<uint32_t>(1, (h1 - h0 + kTileChunk - 1) / kTileChunk);
     k_hub_cost<<<nchunk, kTileChunk, 0, s>>>(rp, gd, ng, h0, h1, pre, chunk_tot);
     GS_HIP(hipGetLastError());
-    k_tile_bounds<<<1, kTileScanBlock, 0, s>>>(pre, chunk_tot, nchunk, h0, h1, tp.tq, tp.kp, tp.tstar, tp.lq,
-                                                tiles);
+    k_chunk_scan<<<1, kTileScanBlock, 0, s>>>(chunk_tot, nchunk);
+    GS_HIP(hipGetLastError());
+    k_tile_bounds<<<(tp.T() + 256) / 256, 256, 0, s>>>(pre, chunk_tot, nchunk, h0, h1, tp.tq, tp.kp, tp.tstar,
+                                                        tp.lq, tiles);
     GS_HIP(hipGetLastError());
 }
 
