@@ -8,9 +8,10 @@ count binned triangles (3pCF) -- or, for the parity workload, binned
     python bench.py [--steps K] [--warmup W] [--workload ns_3pcf|ns_4pcf_parity]
 
 value = tuples counted per second of step time (build + count);
-roofline = the counting kernel's algorithmic bytes per launch over its
-average launch duration (HIP events recorded by the library on the stream
-it launches on), against the 8 TB/s HBM peak; cpu_baseline = the CPU
+roofline = the counting kernel's algorithmic bytes per count over its
+kernel time (HIP events recorded by the library on the stream it launches
+on), against the 8 TB/s HBM peak -- for the parity workload its float64
+operations per count against the non-fused float64 rate; cpu_baseline = the CPU
 oracle on a bounded sample of the same catalogue (anchor range), on the
 host's cores.
 """
@@ -28,6 +29,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "binned triangles/s and 4-cliques/s on 1 GPU; batched catalogues/hour + p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+FP64_NONFUSED_TFLOPS = 256 * 64 * 2.4e9 / 1e12   # 39.3: one float64 op per lane per cycle
+FP64_OPS_PER_CLIQUE = 105
 PROFILES = os.path.join(ROOT, "profiles")
 
 WORKLOADS = {
@@ -284,12 +287,28 @@ def main():
     alg_bytes = int(2.5 * g.info().sum_sq_degree)
     g.free()
     avg_launch_ms = kern_ms / max(launches, 1)
-    achieved = alg_bytes / (avg_launch_ms / 1e3) / 1e9 if avg_launch_ms > 0 else 0.0
+    # the algorithmic bytes are those of one whole count: a host-tiled graph
+    # spreads them over its tile launches, so divide by the count's kernel time
+    count_kernel_ms = kern_ms / args.steps
+    achieved = alg_bytes / (count_kernel_ms / 1e3) / 1e9 if count_kernel_ms > 0 else 0.0
     traffic = stored_traffic(args.workload, spec["kind"])
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_count4" if spec["kind"] == "4pcf" else "k_count3",
-                "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_launch_ms, 4)}
+    if spec["kind"] == "4pcf":
+        # float64 arithmetic per clique (separations, squared lengths, four hub
+        # volumes and thresholds; no fused multiply-add) against the non-fused
+        # float64 vector rate: 256 CU x 64 lanes x 2.4 GHz
+        ops = FP64_OPS_PER_CLIQUE * tuples
+        tflops = ops / (count_kernel_ms / 1e3) / 1e12 if count_kernel_ms > 0 else 0.0
+        roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP64_NONFUSED_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tflops / FP64_NONFUSED_TFLOPS, 4), "traffic": traffic, "kernel": "k_count4",
+                    "fp64_ops_per_clique": FP64_OPS_PER_CLIQUE, "avg_launch_ms": round(avg_launch_ms, 4),
+                    "alg_bytes_per_count": alg_bytes,
+                    "alg_bytes_frac_of_hbm": round(achieved / HBM_PEAK_GBS, 4)}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_count3",
+                    "alg_bytes_per_launch": alg_bytes if launches == args.steps else None,
+                    "alg_bytes_per_count": alg_bytes, "avg_launch_ms": round(avg_launch_ms, 4),
+                    "launches_per_count": launches // max(args.steps, 1)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -1,16 +1,16 @@
 // serve.hip - continuous batching of triangle-count requests (gs_submit,
 // gs_poll, gs_cancel).
 //
-// One scheduler thread per context. A submitted catalogue waits in a FIFO
-// queue; the scheduler runs the first build phase of the queue head (cells,
-// relabelling, degree pass: O(n) memory, after which the exact CSR size is
-// known), admits it when that footprint fits the context budget next to the
-// graphs already held and a batch slot is free, and finishes its build. Built
-// graphs wait for the next count step: one batched launch over every built
-// graph. Builds run on the build stream while a step runs on the count
-// stream, so requests arriving during a step are built in the meantime and
-// join the next one. A finished step hands each request its histogram and
-// frees its graph.
+// Per context, a pool of builder threads and one count thread. A submitted
+// catalogue waits in a FIFO queue. A free builder (each has its own stream
+// and scratch, so builds run concurrently) takes the queue head while a
+// batch slot is free, runs the first build phase (cells, relabelling, degree
+// pass: O(n) memory, after which the exact CSR size is known), waits until
+// that footprint fits the context budget next to the graphs already held
+// (or nothing else is held), and finishes the build. The count thread
+// launches one batched count over every graph built so far, waits for it,
+// hands each request its histogram, frees its graph, and starts the next
+// step over whatever was built meanwhile.
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -29,7 +29,7 @@ using Clock = std::chrono::steady_clock;
 
 namespace {
 
-enum ReqState { kQueued, kBuilt, kCounting, kDone, kFailed, kCancelled };
+enum ReqState { kQueued, kBuilding, kBuilt, kCounting, kDone, kFailed, kCancelled };
 
 struct Request {
     uint64_t ticket = 0;
@@ -55,14 +55,18 @@ double secs(Clock::time_point a, Clock::time_point b) {
 }  // namespace
 
 struct Server {
-    Ctx bctx;                  // build context: own stream, scratch and events
+    std::vector<std::unique_ptr<Ctx>> bctx;   // one per builder: own stream, scratch and events
+    Ctx cctx;                                  // count step planning (tuned schedules)
     hipStream_t cstream = nullptr;
-    std::thread th;
+    std::vector<std::thread> builders;
+    std::thread counter;
     std::mutex mu;
     std::condition_variable cv;
     bool stop = false;
     uint64_t next_ticket = 1;
-    std::deque<Request *> queue;                        // submitted, not yet built
+    std::deque<Request *> queue;                        // submitted, not yet taken by a builder
+    std::vector<Request *> ready;                       // built, waiting for a count step
+    int building = 0, counting = 0;                     // requests in those states
     std::map<uint64_t, std::unique_ptr<Request>> all;   // live tickets
     uint64_t budget = 0, used = 0;
     int max_slots = 64;
@@ -80,165 +84,200 @@ void fail_request(Server &S, Request *r, int code) {
     r->job.reset();
 }
 
-void run(Server *Sp) {
+void builder(Server *Sp, int k) {
     Server &S = *Sp;
-    (void)hipSetDevice(S.bctx.device);
-    std::vector<Request *> ready, step;
-    std::unique_ptr<Batch3> inflight;
+    Ctx &B = *S.bctx[k];
+    (void)hipSetDevice(B.device);
     while (true) {
-        bool progress = false;
-        // 1. a finished step hands out its results
-        if (inflight && hipEventQuery(inflight->done) == hipSuccess) {
-            const unsigned long long *o = inflight->out.as<unsigned long long>();
-            const size_t per = (size_t)inflight->nconf + 1;
-            const bool bad = inflight->error() != 0;
+        Request *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(S.mu);
+            S.cv.wait(lk, [&] {
+                return S.stop || (!S.queue.empty() &&
+                                  (int)S.ready.size() + S.building + S.counting < S.max_slots);
+            });
+            if (S.stop) return;
+            r = S.queue.front();
+            S.queue.pop_front();
+            if (r->cancel) {
+                r->state = kCancelled;
+                r->t_done = Clock::now();
+                continue;
+            }
+            r->state = kBuilding;
+            r->t_build0 = Clock::now();
+            ++S.building;
+        }
+        bool reserved = false;
+        try {
+            r->g.reset(new gs_graph());
+            Graph &g = *r->g;
+            g.device = B.device;
+            g.n = r->n;
+            g.box = r->p.box;
+            g.rmin = r->p.rmin;
+            g.rmax = r->p.rmax;
+            g.nbins = r->p.nbins;
+            g.flags = 0;
+            g.bins = make_bins(r->p.rmin, r->p.rmax, r->p.nbins);
+            r->job.reset(new BuildJob());
+            build_begin(B, g, r->xyz.data(), nullptr, *r->job);
+            const uint64_t fp = build_footprint(g, *r->job);
+            {
+                // admission: the exact footprint fits next to the held graphs,
+                // or nothing else is held
+                std::unique_lock<std::mutex> lk(S.mu);
+                S.cv.wait(lk, [&] { return S.stop || S.used + fp <= S.budget || S.used == 0; });
+                if (S.stop) {
+                    --S.building;
+                    return;
+                }
+                S.used += fp;
+                r->footprint = fp;
+                reserved = true;
+            }
+            build_end(B, g, *r->job, false);
+            r->job.reset();
+            {
+                std::lock_guard<std::mutex> lk(S.mu);
+                --S.building;
+                r->t_build1 = Clock::now();
+                r->xyz.clear();
+                r->xyz.shrink_to_fit();
+                if (r->cancel) {
+                    r->state = kCancelled;
+                    r->t_done = r->t_build1;
+                    S.used -= r->footprint;
+                    r->g.reset();
+                } else {
+                    r->state = kBuilt;
+                    S.ready.push_back(r);
+                }
+            }
+        } catch (const Error &e) {
+            {
+                std::lock_guard<std::mutex> lk(S.mu);
+                --S.building;
+                if (reserved) S.used -= r->footprint;
+            }
+            fail_request(S, r, e.code);
+        } catch (...) {
+            {
+                std::lock_guard<std::mutex> lk(S.mu);
+                --S.building;
+                if (reserved) S.used -= r->footprint;
+            }
+            fail_request(S, r, GS_ENOMEM);
+        }
+        S.cv.notify_all();
+    }
+}
+
+void count_loop(Server *Sp) {
+    Server &S = *Sp;
+    (void)hipSetDevice(S.cctx.device);
+    while (true) {
+        std::vector<Request *> step;
+        {
+            std::unique_lock<std::mutex> lk(S.mu);
+            S.cv.wait(lk, [&] { return S.stop || !S.ready.empty(); });
+            if (S.stop) return;
+            // one step counts the built graphs that share the first one's bin
+            // count (one histogram layout per launch); the rest wait
+            const int nb = S.ready.front()->p.nbins;
+            std::vector<Request *> rest;
+            for (Request *q : S.ready) (q->p.nbins == nb ? step : rest).push_back(q);
+            S.ready.swap(rest);
+            S.counting = (int)step.size();
+            const Clock::time_point now = Clock::now();
+            for (Request *q : step) {
+                q->state = kCounting;
+                q->t_count0 = now;
+                q->step_size = (uint32_t)step.size();
+            }
+        }
+        std::vector<const Graph *> gs;
+        for (Request *q : step) gs.push_back(q->g.get());
+        std::unique_ptr<Batch3> b(new Batch3());
+        int err = GS_OK;
+        try {
+            count3_batch_enqueue(S.cctx, S.cstream, gs.data(), (int)gs.size(), *b);
+            GS_HIP(hipEventSynchronize(b->done));
+            if (b->error()) err = GS_EUNSUPPORTED;
+        } catch (const Error &e) {
+            (void)hipStreamSynchronize(S.cstream);
+            err = e.code;
+        }
+        {
             std::lock_guard<std::mutex> lk(S.mu);
+            const unsigned long long *o = err == GS_OK ? b->out.as<unsigned long long>() : nullptr;
+            const size_t per = (size_t)b->nconf + 1;
             const Clock::time_point now = Clock::now();
             for (size_t k = 0; k < step.size(); ++k) {
                 Request *r = step[k];
                 if (r->cancel) {
                     r->state = kCancelled;
-                } else if (bad) {
+                } else if (err != GS_OK) {
                     r->state = kFailed;
-                    r->error = GS_EUNSUPPORTED;
+                    r->error = err;
                 } else {
-                    r->hist.assign(o + k * per, o + k * per + inflight->nconf);
-                    r->ntri = o[k * per + inflight->nconf];
+                    r->hist.assign(o + k * per, o + k * per + b->nconf);
+                    r->ntri = o[k * per + b->nconf];
                     r->state = kDone;
                 }
                 r->t_done = now;
                 S.used -= r->footprint;
                 r->g.reset();
             }
-            step.clear();
-            inflight.reset();
-            progress = true;
+            S.counting = 0;
         }
-        // 2. build the queue head if a slot is free and its graph fits
-        Request *r = nullptr;
-        {
-            std::lock_guard<std::mutex> lk(S.mu);
-            if (S.stop) break;
-            while (!S.queue.empty() && S.queue.front()->cancel) {
-                S.queue.front()->state = kCancelled;
-                S.queue.front()->t_done = Clock::now();
-                S.queue.front()->job.reset();
-                S.queue.pop_front();
-            }
-            if (!S.queue.empty() && (int)(ready.size() + step.size()) < S.max_slots) r = S.queue.front();
-        }
-        if (r) {
-            bool admitted = false;
-            try {
-                if (!r->job) {
-                    r->t_build0 = Clock::now();
-                    r->g.reset(new gs_graph());
-                    Graph &g = *r->g;
-                    g.device = S.bctx.device;
-                    g.n = r->n;
-                    g.box = r->p.box;
-                    g.rmin = r->p.rmin;
-                    g.rmax = r->p.rmax;
-                    g.nbins = r->p.nbins;
-                    g.flags = 0;
-                    g.bins = make_bins(r->p.rmin, r->p.rmax, r->p.nbins);
-                    r->job.reset(new BuildJob());
-                    build_begin(S.bctx, g, r->xyz.data(), nullptr, *r->job);
-                    r->footprint = build_footprint(g, *r->job);
-                }
-                const bool idle = ready.empty() && step.empty();
-                if (S.used + r->footprint <= S.budget || idle) {
-                    build_end(S.bctx, *r->g, *r->job, false);
-                    r->job.reset();
-                    r->t_build1 = Clock::now();
-                    admitted = true;
-                }
-            } catch (const Error &e) {
-                {
-                    std::lock_guard<std::mutex> lk(S.mu);
-                    S.queue.pop_front();
-                }
-                fail_request(S, r, e.code);
-                progress = true;
-                r = nullptr;
-            } catch (...) {
-                {
-                    std::lock_guard<std::mutex> lk(S.mu);
-                    S.queue.pop_front();
-                }
-                fail_request(S, r, GS_ENOMEM);
-                progress = true;
-                r = nullptr;
-            }
-            if (r && admitted) {
-                std::lock_guard<std::mutex> lk(S.mu);
-                S.queue.pop_front();
-                r->state = kBuilt;
-                r->xyz.clear();
-                r->xyz.shrink_to_fit();
-                S.used += r->footprint;
-                ready.push_back(r);
-                progress = true;
-            }
-        }
-        // 3. no step in flight: count everything built, in one launch
-        if (!inflight && !ready.empty()) {
-            step.swap(ready);
-            std::vector<const Graph *> gs;
-            for (Request *q : step) gs.push_back(q->g.get());
-            const Clock::time_point now = Clock::now();
-            try {
-                inflight.reset(new Batch3());
-                count3_batch_enqueue(S.bctx, S.cstream, gs.data(), (int)gs.size(), *inflight);
-                std::lock_guard<std::mutex> lk(S.mu);
-                for (Request *q : step) {
-                    q->state = kCounting;
-                    q->t_count0 = now;
-                    q->step_size = (uint32_t)step.size();
-                }
-            } catch (const Error &e) {
-                (void)hipStreamSynchronize(S.cstream);
-                std::lock_guard<std::mutex> lk(S.mu);
-                for (Request *q : step) {
-                    q->state = kFailed;
-                    q->error = e.code;
-                    q->t_done = Clock::now();
-                    S.used -= q->footprint;
-                    q->g.reset();
-                }
-                step.clear();
-                inflight.reset();
-            }
-            progress = true;
-        }
-        if (!progress) {
-            std::unique_lock<std::mutex> lk(S.mu);
-            S.cv.wait_for(lk, std::chrono::microseconds(inflight ? 100 : 2000),
-                          [&] { return S.stop || (!S.queue.empty() && !inflight); });
-        }
+        S.cv.notify_all();
     }
-    if (inflight) (void)hipEventSynchronize(inflight->done);
-    (void)hipStreamSynchronize(S.cstream);
-    (void)hipStreamSynchronize(S.bctx.stream);
+}
+
+// A builder's context: device properties and tuned schedules of the parent,
+// its own streams and events.
+Ctx *builder_ctx(const Ctx &ctx) {
+    std::unique_ptr<Ctx> b(new Ctx());
+    b->device = ctx.device;
+    b->n_cu = ctx.n_cu;
+    b->max_lds = ctx.max_lds;
+    b->budget = ~0ull;  // serving admits by footprint itself; graphs stay resident
+    b->tuned = ctx.tuned;
+    GS_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    b->own_stream = true;
+    GS_HIP(hipStreamCreateWithFlags(&b->copy_stream, hipStreamNonBlocking));
+    for (auto &e : b->ev) GS_HIP(hipEventCreate(&e));
+    return b.release();
+}
+
+void release_ctx(Ctx &b) {
+    if (b.stream) (void)hipStreamSynchronize(b.stream);
+    for (auto &e : b.ev)
+        if (e) (void)hipEventDestroy(e);
+    if (b.copy_stream) (void)hipStreamDestroy(b.copy_stream);
+    if (b.own_stream && b.stream) (void)hipStreamDestroy(b.stream);
+    if (b.pinned) (void)hipHostFree(b.pinned);
+    b.pinned = nullptr;
 }
 
 Server &server_of(Ctx &ctx) {
     if (!ctx.server) {
         std::unique_ptr<Server> S(new Server());
-        Ctx &b = S->bctx;
-        b.device = ctx.device;
-        b.n_cu = ctx.n_cu;
-        b.max_lds = ctx.max_lds;
-        b.budget = ~0ull;  // serving admits by footprint itself; graphs stay resident
-        b.tuned = ctx.tuned;  // schedules tuned in the context before its first request
-        GS_HIP(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));
-        b.own_stream = true;
-        GS_HIP(hipStreamCreateWithFlags(&b.copy_stream, hipStreamNonBlocking));
-        for (auto &e : b.ev) GS_HIP(hipEventCreate(&e));
+        int nb = 4;
+        if (const char *eb = getenv("GS_BUILDERS")) nb = std::max(1, std::min(16, atoi(eb)));
+        for (int k = 0; k < nb; ++k) S->bctx.emplace_back(builder_ctx(ctx));
+        Ctx &c = S->cctx;
+        c.device = ctx.device;
+        c.n_cu = ctx.n_cu;
+        c.max_lds = ctx.max_lds;
+        c.budget = ~0ull;
+        c.tuned = ctx.tuned;  // schedules tuned in the context before its first request
         GS_HIP(hipStreamCreateWithFlags(&S->cstream, hipStreamNonBlocking));
         S->budget = ctx.budget;
         if (const char *ms = getenv("GS_MAX_SLOTS")) S->max_slots = std::max(1, atoi(ms));
-        S->th = std::thread(run, S.get());
+        for (int k = 0; k < nb; ++k) S->builders.emplace_back(builder, S.get(), k);
+        S->counter = std::thread(count_loop, S.get());
         ctx.server = S.release();
     }
     return *ctx.server;
@@ -254,13 +293,13 @@ void server_stop(Ctx &ctx) {
         S->stop = true;
     }
     S->cv.notify_all();
-    if (S->th.joinable()) S->th.join();
+    for (auto &t : S->builders)
+        if (t.joinable()) t.join();
+    if (S->counter.joinable()) S->counter.join();
     S->all.clear();
+    (void)hipStreamSynchronize(S->cstream);
     (void)hipStreamDestroy(S->cstream);
-    for (auto &e : S->bctx.ev)
-        if (e) (void)hipEventDestroy(e);
-    (void)hipStreamDestroy(S->bctx.copy_stream);
-    (void)hipStreamDestroy(S->bctx.stream);
+    for (auto &b : S->bctx) release_ctx(*b);
     delete S;
     ctx.server = nullptr;
 }
@@ -310,7 +349,7 @@ int gs_poll(gs_ctx *ctx, uint64_t ticket, gs_result *out) {
         auto it = S.all.find(ticket);
         if (it == S.all.end()) fail(GS_ENOTFOUND, "no such ticket");
         Request &r = *it->second;
-        if (r.state == kQueued || r.state == kBuilt || r.state == kCounting) {
+        if (r.state == kQueued || r.state == kBuilding || r.state == kBuilt || r.state == kCounting) {
             out->status = GS_PENDING;
             return;
         }

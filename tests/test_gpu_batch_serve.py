@@ -172,3 +172,30 @@ def test_serving_small_budget_admits_one_at_a_time(gsn):
     for t, a in zip(ts, want):
         assert res[t]["status"] == gsn.GS_DONE and np.array_equal(res[t]["hist"], a.hist)
         assert res[t]["step_size"] <= 2
+
+
+def test_serving_mixed_bin_counts(gsn):
+    """Requests with different bin counts are counted in separate steps, each
+    with the histogram layout of its own bin count."""
+    cats = catalogues(10, 13, lo=3_000, hi=12_000)
+    nbs = [NB if k % 2 == 0 else NB + 3 for k in range(len(cats))]
+    with gsn.Context(0) as c:
+        want = []
+        for x, nb in zip(cats, nbs):
+            g = c.build_graph(x, L, 0.0, RMAX, nb)
+            want.append(c.count_3pcf(g).hist)
+            g.free()
+    with gsn.Context(0) as s:
+        ts = [s.submit(x, L, 0.0, RMAX, nb) for x, nb in zip(cats, nbs)]
+        res = {}
+        t0 = time.time()
+        while len(res) < len(ts):
+            assert time.time() - t0 < 120.0, "serving did not finish"
+            for t, nb in zip(ts, nbs):
+                if t not in res:
+                    r = s.poll(t, nb)
+                    if r is not None:
+                        res[t] = r
+            time.sleep(0.002)
+    for t, w in zip(ts, want):
+        assert res[t]["status"] == gsn.GS_DONE and np.array_equal(res[t]["hist"], w)
