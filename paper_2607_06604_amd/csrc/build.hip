@@ -12,7 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 
-#include "common.h"
+#include "kern_util.h"
 
 namespace gsn {
 namespace {
@@ -126,17 +126,26 @@ struct EdgeArgs {
 
 // One thread per label: scan the label's own cell after it, then the forward
 // adjacent cells in ascending cell id.
+// Graph edges, one work group per cell: its wavefronts take the cell's
+// points in turn, and for a point i the 64 lanes sweep its candidates -- the
+// rest of its own cell (labels above i), then the forward cells in ascending
+// cell id, hence ascending labels -- one candidate per lane, so loads are
+// coalesced, no lane waits on another cell's list, and a ballot compacts
+// each window's edges in label order. The count pass writes degrees; the
+// fill pass writes col / bin at the offsets the count pass produced.
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
     __shared__ double t[256];
+    __shared__ uint64_t rs[27];   // first label of forward cell range r
+    __shared__ uint32_t rq[28];   // running length before range r
+    __shared__ int s_nr;
+    const uint32_t c = blockIdx.x;
+    const uint64_t cs = a.cstart[c], ce = a.cstart[c + 1];
+    const uint64_t i0 = cs > a.l0 ? cs : (uint64_t)a.l0, i1 = ce < a.l1 ? ce : (uint64_t)a.l1;
+    if (i0 >= i1) return;   // no point of this launch in the cell (uniform)
     for (int k = threadIdx.x; k <= a.nb; k += blockDim.x) t[k] = a.thr[k];
-    __syncthreads();
-    uint32_t l = a.l0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (l < a.l1) {
+    if (threadIdx.x == 0) {
         const int nc = a.nc;
-        const uint32_t c = a.cellL[l];
-        const double xi = a.X[l], yi = a.Y[l], zi = a.Z[l];
-        const double t0 = t[0], tn = t[a.nb];
         int ax[3], ay[3], az[3], na = 1;
         const int cx = (int)(c / (uint32_t)(nc * nc)), cy = (int)((c / nc) % nc), cz = (int)(c % nc);
         if (nc >= 3) {
@@ -154,40 +163,70 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
         } else {
             ax[0] = ay[0] = az[0] = 0;
         }
-        uint32_t cnt = 0;
-        const uint64_t out = FILL ? a.rp[l] - a.obase : 0;
-        const uint64_t cap = FILL ? a.rp[l + 1] - a.rp[l] : 0;  // the count pass's result
-        auto visit = [&](uint64_t j0, uint64_t j1) {
-            for (uint64_t j = j0; j < j1; ++j) {
-                double dx = min_image(xi, a.X[j], a.L, a.half);
-                double dy = min_image(yi, a.Y[j], a.L, a.half);
-                double dz = min_image(zi, a.Z[j], a.L, a.half);
-                double q = sq_len(dx, dy, dz);
-                if (q >= t0 && q < tn) {
-                    if (FILL && cnt < cap) {
-                        a.col[out + cnt] = (uint32_t)j;
-                        a.bin[out + cnt] = (uint8_t)bin_of(t, a.nb, q);
-                    }
-                    ++cnt;
-                }
-            }
-        };
-        visit((uint64_t)l + 1, a.cstart[c + 1]);
+        int nr = 0;
+        uint32_t run = 0;
         for (int u = 0; u < na; ++u)
             for (int v = 0; v < na; ++v)
                 for (int w = 0; w < na; ++w) {
-                    uint32_t id = ((uint32_t)ax[u] * nc + ay[v]) * nc + az[w];
+                    const uint32_t id = ((uint32_t)ax[u] * nc + ay[v]) * nc + az[w];
                     if (id <= c) continue;
-                    visit(a.cstart[id], a.cstart[id + 1]);
+                    const uint64_t b0 = a.cstart[id], b1 = a.cstart[id + 1];
+                    if (b1 == b0) continue;
+                    rs[nr] = b0;
+                    rq[nr] = run;
+                    run += (uint32_t)(b1 - b0);
+                    ++nr;
                 }
-        if (!FILL) a.deg[l] = cnt;
+        rq[nr] = run;
+        s_nr = nr;
     }
-    if (!FILL) {
-        // one atomic per wave for the largest forward degree
-        uint32_t m = (l < a.l1) ? a.deg[l] : 0u;
-        for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
-        if ((threadIdx.x & 63) == 0) atomicMax(a.maxdeg, m);
+    __syncthreads();
+    const int nr = s_nr;
+    const uint32_t Mf = rq[nr];
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const double t0 = t[0], tn = t[a.nb];
+    uint32_t mymax = 0;
+    for (uint64_t i = i0 + wid; i < i1; i += kBlock / 64) {
+        const double xi = a.X[i], yi = a.Y[i], zi = a.Z[i];
+        const uint32_t own = (uint32_t)(ce - i - 1);   // own-cell labels above i
+        const uint32_t M = own + Mf;
+        const uint64_t out = FILL ? a.rp[i] - a.obase : 0;
+        const uint32_t cap = FILL ? (uint32_t)(a.rp[i + 1] - a.rp[i]) : 0;  // the count pass's result
+        uint32_t cnt = 0;
+        for (uint32_t f0 = 0; f0 < M; f0 += 64) {
+            const uint32_t f = f0 + lane;
+            bool in = false;
+            uint64_t j = 0;
+            double q = 0.0;
+            if (f < M) {
+                if (f < own) {
+                    j = i + 1 + f;
+                } else {
+                    const uint32_t g = f - own;
+                    const uint32_t r = upper_index(rq, (uint32_t)nr, g);
+                    j = rs[r] + (g - rq[r]);
+                }
+                const double dx = min_image(xi, a.X[j], a.L, a.half);
+                const double dy = min_image(yi, a.Y[j], a.L, a.half);
+                const double dz = min_image(zi, a.Z[j], a.L, a.half);
+                q = sq_len(dx, dy, dz);
+                in = q >= t0 && q < tn;
+            }
+            const uint64_t mask = __ballot(in);
+            if (FILL && in) {
+                const uint32_t k = cnt + lanes_below(mask);
+                if (k < cap) {
+                    a.col[out + k] = (uint32_t)j;
+                    a.bin[out + k] = (uint8_t)bin_of(t, a.nb, q);
+                }
+            }
+            cnt += (uint32_t)__popcll(mask);
+        }
+        if (!FILL && lane == 0) a.deg[i] = cnt;
+        mymax = cnt > mymax ? cnt : mymax;
     }
+    // one atomic per wave for the largest forward degree
+    if (!FILL && lane == 0 && mymax) atomicMax(a.maxdeg, mymax);
 }
 
 // Graph statistics outside the build: in-degrees (for the full degrees) and
@@ -422,7 +461,7 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
     EdgeArgs ea = edge_args(g, job);
     ea.deg = deg.as<uint32_t>();
     ea.maxdeg = fl + 1;
-    k_edges<false><<<grid_for(n), kBlock, 0, s>>>(ea);
+    k_edges<false><<<(unsigned)((uint64_t)job.nc * job.nc * job.nc), kBlock, 0, s>>>(ea);
     GS_HIP(hipGetLastError());
     scan<uint32_t>(deg.as<uint32_t>(), n, g.row_ptr.as<uint64_t>(), s);
 
@@ -498,7 +537,7 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok) {
         g.bin.alloc(E + kRowSlack);
         ea.col = g.col.as<uint32_t>();
         ea.bin = g.bin.as<uint8_t>();
-        k_edges<true><<<grid_for(n), kBlock, 0, s>>>(ea);
+        k_edges<true><<<(unsigned)((uint64_t)job.nc * job.nc * job.nc), kBlock, 0, s>>>(ea);
     } else {
         // row-aligned windows of about E/W entries each
         std::vector<uint64_t> hrp((size_t)n + 1);
@@ -529,7 +568,7 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok) {
             ea.l1 = (uint32_t)g.win[w + 1];
             ea.obase = g.win_edge[w];
             const uint64_t ne = g.win_edge[w + 1] - g.win_edge[w];
-            k_edges<true><<<grid_for(ea.l1 - ea.l0), kBlock, 0, s>>>(ea);
+            k_edges<true><<<(unsigned)((uint64_t)job.nc * job.nc * job.nc), kBlock, 0, s>>>(ea);
             GS_HIP(hipGetLastError());
             GS_HIP(hipMemcpyAsync(g.hcol.as<uint32_t>() + g.win_edge[w], stc.p, ne * 4, hipMemcpyDeviceToHost, s));
             GS_HIP(hipMemcpyAsync(g.hbin.as<uint8_t>() + g.win_edge[w], stb.p, ne, hipMemcpyDeviceToHost, s));
