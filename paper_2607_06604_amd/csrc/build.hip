@@ -318,25 +318,27 @@ __global__ void k_set_total(uint64_t *out, uint64_t n, const uint64_t *tile_off,
 inline unsigned grid_for(uint64_t n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
 
 // Exclusive scan of n values into out[0..n]; out[n] = total.
+// Temporaries come from the building context's cache (reused only by later
+// work on the same stream) or, without one, are freed after a synchronize.
 template <class TI>
-void scan(const TI *in, uint64_t n, uint64_t *out, hipStream_t s) {
+void scan(const TI *in, uint64_t n, uint64_t *out, hipStream_t s, const std::shared_ptr<DevPool> &pool) {
     if (n == 0) {
         k_fill_u64<<<1, 1, 0, s>>>(out, 1, 0);
         return;
     }
     uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
-    DevBuf sums(sizeof(uint64_t) * ntiles), offs(sizeof(uint64_t) * (ntiles + 1));
+    DevBuf sums(sizeof(uint64_t) * ntiles, pool), offs(sizeof(uint64_t) * (ntiles + 1), pool);
     k_scan_tiles<TI><<<(unsigned)ntiles, kBlock, 0, s>>>(in, n, out, sums.as<uint64_t>());
     GS_HIP(hipGetLastError());
     if (ntiles > 1) {
-        scan<uint64_t>(sums.as<uint64_t>(), ntiles, offs.as<uint64_t>(), s);
+        scan<uint64_t>(sums.as<uint64_t>(), ntiles, offs.as<uint64_t>(), s, pool);
         k_scan_add<<<grid_for(n), kBlock, 0, s>>>(out, n, offs.as<uint64_t>());
     } else {
         k_fill_u64<<<1, 1, 0, s>>>(offs.as<uint64_t>(), 1, 0);
     }
     k_set_total<<<1, 1, 0, s>>>(out, n, offs.as<uint64_t>(), ntiles, sums.as<uint64_t>());
     GS_HIP(hipGetLastError());
-    GS_HIP(hipStreamSynchronize(s));  // sums/offs are freed on return
+    if (!pool) GS_HIP(hipStreamSynchronize(s));  // sums/offs are freed on return
 }
 
 // sum of (out-degree + in-degree)^2 over labels
@@ -385,14 +387,14 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
     const bool weighted = (g.flags & GS_WEIGHTED) != 0;
     const bool keep = (g.flags & GS_KEEP_COORDS) != 0;
 
-    g.row_ptr.alloc(sizeof(uint64_t) * ((size_t)n + 1));
-    g.perm.alloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    g.row_ptr.alloc(sizeof(uint64_t) * ((size_t)n + 1), ctx.pool);
+    g.perm.alloc(sizeof(uint32_t) * (size_t)(n ? n : 1), ctx.pool);
     job.E = 0;
     job.empty = n == 0;
     if (n == 0) {
         k_fill_u64<<<1, 1, 0, s>>>(g.row_ptr.as<uint64_t>(), 1, 0);
-        if (keep) g.coords.alloc(8);
-        if (weighted) g.weights.alloc(8);
+        if (keep) g.coords.alloc(8, ctx.pool);
+        if (weighted) g.weights.alloc(8, ctx.pool);
         GS_HIP(hipStreamSynchronize(s));
         return;
     }
@@ -400,11 +402,11 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
     DevBuf in_xyz, in_w;
     const double *dxyz = xyz, *dw = w;
     if (!on_dev) {
-        in_xyz.alloc(sizeof(double) * 3 * (size_t)n);
+        in_xyz.alloc(sizeof(double) * 3 * (size_t)n, ctx.pool);
         GS_HIP(hipMemcpyAsync(in_xyz.p, xyz, sizeof(double) * 3 * (size_t)n, hipMemcpyHostToDevice, s));
         dxyz = in_xyz.as<double>();
         if (weighted) {
-            in_w.alloc(sizeof(double) * (size_t)n);
+            in_w.alloc(sizeof(double) * (size_t)n, ctx.pool);
             GS_HIP(hipMemcpyAsync(in_w.p, w, sizeof(double) * (size_t)n, hipMemcpyHostToDevice, s));
             dw = in_w.as<double>();
         }
@@ -417,10 +419,11 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
     int nc = ncd < 3 ? 1 : (int)ncd;
     uint64_t ncell = (uint64_t)nc * nc * nc;
 
-    DevBuf cell_of(sizeof(uint32_t) * n), count(sizeof(uint32_t) * ncell), order(sizeof(uint32_t) * n),
-        flags(64), deg(sizeof(uint32_t) * n);
-    job.cstart.alloc(sizeof(uint64_t) * (ncell + 1));
-    job.cellL.alloc(sizeof(uint32_t) * n);
+    const std::shared_ptr<DevPool> &pool = ctx.pool;
+    DevBuf cell_of(sizeof(uint32_t) * n, pool), count(sizeof(uint32_t) * ncell, pool),
+        order(sizeof(uint32_t) * n, pool), flags(64, pool), deg(sizeof(uint32_t) * n, pool);
+    job.cstart.alloc(sizeof(uint64_t) * (ncell + 1), ctx.pool);
+    job.cellL.alloc(sizeof(uint32_t) * n, ctx.pool);
     DevBuf &cstart = job.cstart, &cellL = job.cellL;
     job.nc = nc;
     uint32_t *fl = flags.as<uint32_t>();
@@ -433,7 +436,7 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
     if (weighted)
         k_weights<<<grid_for(n), kBlock, 0, s>>>(dw, n, fl, (unsigned long long *)(flags.as<uint64_t>() + 4));
     GS_HIP(hipGetLastError());
-    scan<uint32_t>(count.as<uint32_t>(), ncell, cstart.as<uint64_t>(), s);
+    scan<uint32_t>(count.as<uint32_t>(), ncell, cstart.as<uint64_t>(), s, ctx.pool);
     k_fill_u32<<<grid_for(ncell), kBlock, 0, s>>>(count.as<uint32_t>(), ncell, 0);
     k_scatter<<<grid_for(n), kBlock, 0, s>>>(cell_of.as<uint32_t>(), n, cstart.as<uint64_t>(),
                                              count.as<uint32_t>(), order.as<uint32_t>());
@@ -441,21 +444,21 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
                                           cstart.as<uint64_t>(), n, g.perm.as<uint32_t>());
     double *C;
     if (keep) {
-        g.coords.alloc(sizeof(double) * 3 * (size_t)n);
+        g.coords.alloc(sizeof(double) * 3 * (size_t)n, ctx.pool);
         C = g.coords.as<double>();
     } else {
-        job.tmp_coords.alloc(sizeof(double) * 3 * (size_t)n);
+        job.tmp_coords.alloc(sizeof(double) * 3 * (size_t)n, ctx.pool);
         C = job.tmp_coords.as<double>();
     }
     job.C = C;
-    if (weighted) g.weights.alloc(sizeof(double) * n);
+    if (weighted) g.weights.alloc(sizeof(double) * n, ctx.pool);
     k_gather<<<grid_for(n), kBlock, 0, s>>>(g.perm.as<uint32_t>(), dxyz, dw, cell_of.as<uint32_t>(), n,
                                             C, C + n, C + 2 * (size_t)n,
                                             weighted ? g.weights.as<double>() : nullptr,
                                             cellL.as<uint32_t>());
     GS_HIP(hipGetLastError());
 
-    job.thr.alloc(sizeof(double) * 256);
+    job.thr.alloc(sizeof(double) * 256, ctx.pool);
     GS_HIP(hipMemcpyAsync(job.thr.p, g.bins.t, sizeof(double) * 256, hipMemcpyHostToDevice, s));
 
     EdgeArgs ea = edge_args(g, job);
@@ -463,7 +466,7 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
     ea.maxdeg = fl + 1;
     k_edges<false><<<(unsigned)((uint64_t)job.nc * job.nc * job.nc), kBlock, 0, s>>>(ea);
     GS_HIP(hipGetLastError());
-    scan<uint32_t>(deg.as<uint32_t>(), n, g.row_ptr.as<uint64_t>(), s);
+    scan<uint32_t>(deg.as<uint32_t>(), n, g.row_ptr.as<uint64_t>(), s, ctx.pool);
 
     struct {
         uint32_t f[8];
@@ -510,8 +513,8 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok) {
     const uint64_t E = job.E;
     GS_HIP(hipEventRecord(ctx.ev[0], s));
     if (job.empty) {
-        g.col.alloc(sizeof(uint32_t) * kRowSlack);
-        g.bin.alloc(kRowSlack);
+        g.col.alloc(sizeof(uint32_t) * kRowSlack, ctx.pool);
+        g.bin.alloc(kRowSlack, ctx.pool);
         g.device_bytes = g.row_ptr.bytes + g.perm.bytes + g.col.bytes + g.bin.bytes;
         ctx.t.build_ms = job.begin_ms;
         return;
@@ -533,8 +536,8 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok) {
 
     ea.rp = g.row_ptr.as<uint64_t>();
     if (W == 1) {
-        g.col.alloc(sizeof(uint32_t) * (E + kRowSlack));
-        g.bin.alloc(E + kRowSlack);
+        g.col.alloc(sizeof(uint32_t) * (E + kRowSlack), ctx.pool);
+        g.bin.alloc(E + kRowSlack, ctx.pool);
         ea.col = g.col.as<uint32_t>();
         ea.bin = g.bin.as<uint8_t>();
         k_edges<true><<<(unsigned)((uint64_t)job.nc * job.nc * job.nc), kBlock, 0, s>>>(ea);
@@ -558,9 +561,9 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok) {
         for (int w = 0; w < W; ++w) maxE = std::max<uint64_t>(maxE, g.win_edge[w + 1] - g.win_edge[w]);
         g.hcol.alloc(sizeof(uint32_t) * (E ? E : 1));
         g.hbin.alloc(E ? E : 1);
-        g.col.alloc(4);
-        g.bin.alloc(1);
-        DevBuf stc(sizeof(uint32_t) * maxE), stb(maxE);
+        g.col.alloc(4, ctx.pool);
+        g.bin.alloc(1, ctx.pool);
+        DevBuf stc(sizeof(uint32_t) * maxE, ctx.pool), stb(maxE, ctx.pool);
         ea.col = stc.as<uint32_t>();
         ea.bin = stb.as<uint8_t>();
         for (int w = 0; w < W; ++w) {

@@ -22,8 +22,90 @@ void DevBuf::alloc(size_t n) {
         (void)hipGetLastError();
         fail(GS_EDEVMEM, "hipMalloc(" + std::to_string(n) + " bytes): " + hipGetErrorString(e));
     }
-    bytes = n;
+    bytes = cap = n;
 }
+
+void DevBuf::alloc(size_t n, const std::shared_ptr<DevPool> &from) {
+    if (!from) {
+        alloc(n);
+        return;
+    }
+    reset();
+    if (n == 0) n = 1;
+    size_t got = 0;
+    p = from->take(n, got);
+    bytes = n;
+    cap = got;
+    pool = from;
+}
+
+size_t DevPool::round_size(size_t n) {
+    if (n <= 256) return 256;
+    size_t b = 1;
+    while (b < n) b <<= 1;  // next power of two
+    if (b <= (1u << 20)) return b;
+    const size_t step = b >> 4;  // eighth of the power of two below
+    return (n + step - 1) / step * step;
+}
+
+void *DevPool::take(size_t n, size_t &got) {
+    const size_t r = round_size(n);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = blocks.lower_bound(r);
+        if (it != blocks.end() && it->first <= r + r / 4) {
+            void *p = it->second;
+            got = it->first;
+            held -= got;
+            blocks.erase(it);
+            return p;
+        }
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, r);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        trim();  // cached blocks may be what the device is short of
+        e = hipMalloc(&p, r);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(GS_EDEVMEM, "hipMalloc(" + std::to_string(r) + " bytes): " + hipGetErrorString(e));
+        }
+    }
+    got = r;
+    return p;
+}
+
+void DevPool::give(void *p, size_t got) {
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (held + got <= cap) {
+            blocks.emplace(got, p);
+            held += got;
+            return;
+        }
+    }
+    (void)hipDeviceSynchronize();  // the block may still be in use on the builder's stream
+    (void)hipFree(p);
+}
+
+void DevPool::trim() {
+    std::multimap<size_t, void *> drop;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        drop.swap(blocks);
+        held = 0;
+    }
+    if (drop.empty()) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
+    for (auto &b : drop) (void)hipFree(b.second);
+    (void)hipSetDevice(cur);
+}
+
+DevPool::~DevPool() { trim(); }
 
 void HostBuf::alloc(size_t n) {
     reset();
@@ -123,6 +205,9 @@ int gs_create(gs_ctx **out, int device, uint64_t hbm_budget_bytes, void *hip_str
         size_t fr = 0, tot = 0;
         GS_HIP(hipMemGetInfo(&fr, &tot));
         c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
+        c->pool = std::make_shared<DevPool>();
+        c->pool->device = device;
+        c->pool->cap = c->budget / 8;
     });
     if (rc != GS_OK) {
         if (c) gs_destroy(c);

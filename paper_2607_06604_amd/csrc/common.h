@@ -6,6 +6,9 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -51,25 +54,61 @@ int guarded(F &&body) {
 
 // ------------------------------------------------------- device buffers ---
 
-// Owning device allocation.
+// A context's cache of device blocks. Graph buffers and build temporaries
+// come from it and go back to it when released, so that a build does not
+// pay for hipMalloc and a graph release does not pay for hipFree (which
+// waits for the whole device). Sizes are rounded up to classes (powers of two
+// up to 1 MiB, then steps of an eighth of the power of two below), so a
+// block serves later requests of nearly the same size. A block is handed
+// back only once no kernel on another stream can still use it: graph blocks
+// after the device has drained, build temporaries only to the building
+// context, whose later takes are ordered after them on its one stream.
+struct DevPool {
+    int device = 0;
+    uint64_t cap = 0;   // bytes the cache may hold
+    std::mutex mu;
+    std::multimap<size_t, void *> blocks;  // by block size
+    uint64_t held = 0;
+    static size_t round_size(size_t n);
+    void *take(size_t n, size_t &got);
+    void give(void *p, size_t got);
+    void trim();        // free every cached block (waits for the device)
+    ~DevPool();
+};
+
+// Owning device allocation, from hipMalloc or from a DevPool.
 struct DevBuf {
     void *p = nullptr;
-    size_t bytes = 0;
+    size_t bytes = 0;   // size asked for
+    size_t cap = 0;     // size of the block held
+    std::shared_ptr<DevPool> pool;
     DevBuf() = default;
     explicit DevBuf(size_t n) { alloc(n); }
+    DevBuf(size_t n, const std::shared_ptr<DevPool> &from) { alloc(n, from); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), cap(o.cap), pool(std::move(o.pool)) {
+        o.p = nullptr; o.bytes = o.cap = 0;
+    }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { reset(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        if (this != &o) {
+            reset();
+            p = o.p; bytes = o.bytes; cap = o.cap; pool = std::move(o.pool);
+            o.p = nullptr; o.bytes = o.cap = 0;
+        }
         return *this;
     }
     ~DevBuf() { reset(); }
     void alloc(size_t n);
+    void alloc(size_t n, const std::shared_ptr<DevPool> &from);
     void reset() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (pool) pool->give(p, cap);
+            else (void)hipFree(p);
+        }
         p = nullptr;
-        bytes = 0;
+        bytes = cap = 0;
+        pool.reset();
     }
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
@@ -120,6 +159,7 @@ struct Ctx {
     Timings t;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     DevBuf scratch;             // grown on demand, reused across calls
+    std::shared_ptr<DevPool> pool;  // graph buffers and build temporaries
     void *pinned = nullptr;     // small pinned host staging
     size_t pinned_bytes = 0;
     Server *server = nullptr;   // continuous-batching scheduler (gs_submit)
@@ -241,7 +281,9 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok);
 // Batched triangle counts over resident graphs with equal bin counts: one
 // persistent launch. Results land in host memory `out` (ng x (nconf+1) u64:
 // each graph's histogram then its triangle count; then one error word, 0
-// when the counts are valid) once `done` has fired.
+// when the counts are valid) once `done` has fired. One object may serve a
+// launch after another once the previous one has completed; its buffers are
+// kept while large enough.
 struct Batch3 {
     DevBuf dv;          // device results + queues
     DevBuf gd;          // descriptors

@@ -1126,6 +1126,18 @@ Batch3::~Batch3() {
     if (done) (void)hipEventDestroy(done);
 }
 
+namespace {
+// Keep a batch buffer when it is large enough (a batch object serves one
+// launch after another once the previous one has completed).
+void grow(DevBuf &d, size_t n) {
+    if (!d.p || d.cap < n) d.alloc(n);
+    else d.bytes = n;
+}
+void grow(HostBuf &h, size_t n) {
+    if (!h.p || h.bytes < n) h.alloc(n);
+}
+}  // namespace
+
 void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int ng, Batch3 &b) {
     if (ng < 1) fail(GS_EINVAL, "empty batch");
     const int nb = gs[0]->nbins;
@@ -1167,9 +1179,9 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
     const size_t poff = toff + (tp.T() + 2) / 2;    // | hub cost prefix | chunk costs
     const size_t koff = poff + nvirt;
     const size_t words = use_tiles ? koff + tp.nchunk : toff;
-    b.dv.alloc(words * 8);
+    grow(b.dv, words * 8);
     unsigned long long *dv = b.dv.as<unsigned long long>();
-    b.hostdesc.alloc(sizeof(GDesc) * ng);
+    grow(b.hostdesc, sizeof(GDesc) * ng);
     GDesc *hd = b.hostdesc.as<GDesc>();
     uint64_t v0 = 0;
     for (int g = 0; g < ng; ++g) {
@@ -1183,12 +1195,12 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
         hd[g].ntri = dv + (size_t)g * per + nconf;
         v0 += (uint64_t)gs[g]->n;
     }
-    b.gd.alloc(sizeof(GDesc) * ng);
+    grow(b.gd, sizeof(GDesc) * ng);
     GS_HIP(hipMemcpyAsync(b.gd.p, hd, sizeof(GDesc) * ng, hipMemcpyHostToDevice, s));
     k_zero_u64<<<64, 256, 0, s>>>(dv, words);
     if (!cfg.empty()) {
         // pinned staging that lives as long as the batch (the copy is async)
-        b.hostcfg.alloc(cfg.size() * 2);
+        grow(b.hostcfg, cfg.size() * 2);
         memcpy(b.hostcfg.p, cfg.data(), cfg.size() * 2);
         GS_HIP(hipMemcpyAsync(dv + coff, b.hostcfg.p, cfg.size() * 2, hipMemcpyHostToDevice, s));
     }
@@ -1221,7 +1233,7 @@ void count3_batch_enqueue(Ctx &ctx, hipStream_t s, const Graph *const *gs, int n
         else if (P.block == 128) launch3_batch<128>(ctx, s, a, P);
         else launch3_batch<256>(ctx, s, a, P);
     }
-    b.out.alloc(sizeof(unsigned long long) * ((size_t)ng * per + 1));
+    grow(b.out, sizeof(unsigned long long) * ((size_t)ng * per + 1));
     GS_HIP(hipMemcpyAsync(b.out.p, dv, sizeof(unsigned long long) * ((size_t)ng * per + 1), hipMemcpyDeviceToHost, s));
     if (!b.done) GS_HIP(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
     GS_HIP(hipEventRecord(b.done, s));

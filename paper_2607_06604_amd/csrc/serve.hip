@@ -176,6 +176,10 @@ void builder(Server *Sp, int k) {
 void count_loop(Server *Sp) {
     Server &S = *Sp;
     (void)hipSetDevice(S.cctx.device);
+    // one batch object for every step: its device and pinned buffers are
+    // reused (a step starts after the previous one has completed), so no
+    // step pays for a free that would wait for the builders' kernels
+    std::unique_ptr<Batch3> b(new Batch3());
     while (true) {
         std::vector<Request *> step;
         {
@@ -198,7 +202,6 @@ void count_loop(Server *Sp) {
         }
         std::vector<const Graph *> gs;
         for (Request *q : step) gs.push_back(q->g.get());
-        std::unique_ptr<Batch3> b(new Batch3());
         int err = GS_OK;
         try {
             count3_batch_enqueue(S.cctx, S.cstream, gs.data(), (int)gs.size(), *b);
@@ -237,13 +240,18 @@ void count_loop(Server *Sp) {
 
 // A builder's context: device properties and tuned schedules of the parent,
 // its own streams and events.
-Ctx *builder_ctx(const Ctx &ctx) {
+Ctx *builder_ctx(const Ctx &ctx, int n_builders) {
     std::unique_ptr<Ctx> b(new Ctx());
     b->device = ctx.device;
     b->n_cu = ctx.n_cu;
     b->max_lds = ctx.max_lds;
     b->budget = ~0ull;  // serving admits by footprint itself; graphs stay resident
     b->tuned = ctx.tuned;
+    // a cache of its own: its build temporaries are handed back before its
+    // stream has finished with them, so no other stream may take them
+    b->pool = std::make_shared<DevPool>();
+    b->pool->device = ctx.device;
+    b->pool->cap = (ctx.pool ? ctx.pool->cap : 0) / std::max(1, n_builders);
     GS_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     b->own_stream = true;
     GS_HIP(hipStreamCreateWithFlags(&b->copy_stream, hipStreamNonBlocking));
@@ -266,7 +274,7 @@ Server &server_of(Ctx &ctx) {
         std::unique_ptr<Server> S(new Server());
         int nb = 4;
         if (const char *eb = getenv("GS_BUILDERS")) nb = std::max(1, std::min(16, atoi(eb)));
-        for (int k = 0; k < nb; ++k) S->bctx.emplace_back(builder_ctx(ctx));
+        for (int k = 0; k < nb; ++k) S->bctx.emplace_back(builder_ctx(ctx, nb));
         Ctx &c = S->cctx;
         c.device = ctx.device;
         c.n_cu = ctx.n_cu;
