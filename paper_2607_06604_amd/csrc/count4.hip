@@ -38,6 +38,7 @@ struct C4Args {
     int nb, nconf, log2h, W;
     uint32_t maxdeg;
     double L, half;
+    double in_lo, in_hi;   // hubs with every coordinate in [in_lo, in_hi] see no wrapped pair
     uint32_t anchor_lo, anchor_hi;
     uint64_t flush_limit;
     uint32_t *queue;
@@ -46,7 +47,7 @@ struct C4Args {
 };
 
 struct Layout4 {
-    uint32_t hkey, hloc, hslot, px, py, pz, pq, pb, pperm, R, rowpref, eA, eB, epref, ecw, mstart,
+    uint32_t hkey, hloc, hslot, px, py, pz, sx, sy, sz, pq, pb, pperm, R, rowpref, eA, eB, epref, ecw, mstart,
         mpref, mloc, hist, tab, thr, wtot, misc, total;
 };
 
@@ -57,6 +58,9 @@ __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxde
     L.px = o;      o = lds_align(o + 8 * d, 16);
     L.py = o;      o = lds_align(o + 8 * d, 16);
     L.pz = o;      o = lds_align(o + 8 * d, 16);
+    L.sx = o;      o = lds_align(o + 8 * d, 16);
+    L.sy = o;      o = lds_align(o + 8 * d, 16);
+    L.sz = o;      o = lds_align(o + 8 * d, 16);
     L.pq = o;      o = lds_align(o + 8 * d, 16);
     L.thr = o;     o = lds_align(o + 8 * (nb + 1), 16);
     L.mstart = o;  o = lds_align(o + 8 * block, 16);
@@ -81,37 +85,107 @@ __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxde
     return L;
 }
 
-struct Spoke {
-    double x, y, z, q;
-    int b;
+struct P3 {
+    double x, y, z;
 };
 
-__device__ __forceinline__ void cswap(Spoke &a, Spoke &b) {
-    if (b.q < a.q) {
-        Spoke t = a;
-        a = b;
-        b = t;
-    }
+__device__ __forceinline__ P3 neg(const P3 &v) { return P3{-v.x, -v.y, -v.z}; }
+
+// Separation xb - xa under the minimum image. WRAP false: the caller knows
+// no wrap applies (|xb - xa| <= L/2), so the plain difference is the same
+// value. Branch-free: subtracting -L is adding L, and subtracting 0 leaves
+// the value unchanged, so this is bitwise the definition's result.
+template <bool WRAP>
+__device__ __forceinline__ double sep(double xa, double xb, double L, double half) {
+    const double d = __dsub_rn(xb, xa);
+    if (!WRAP) return d;
+    const double off = d > half ? L : (d < -half ? -L : 0.0);
+    return __dsub_rn(d, off);
 }
 
-// Channel (0 pos, 1 neg, 2 degenerate) and configuration of one hub.
-__device__ __forceinline__ int hub_channel(Spoke s0, Spoke s1, Spoke s2, const int *ta, const int *tb,
+// (u x v) . w, the cross product then the dot product in the definition's
+// operation order.
+__device__ __forceinline__ double triple(const P3 &u, const P3 &v, const P3 &w) {
+    const double cx = __dsub_rn(__dmul_rn(u.y, v.z), __dmul_rn(u.z, v.y));
+    const double cy = __dsub_rn(__dmul_rn(u.z, v.x), __dmul_rn(u.x, v.z));
+    const double cz = __dsub_rn(__dmul_rn(u.x, v.y), __dmul_rn(u.y, v.x));
+    return __dadd_rn(__dadd_rn(__dmul_rn(cx, w.x), __dmul_rn(cy, w.y)), __dmul_rn(cz, w.z));
+}
+
+// Channel (0 pos, 1 neg, 2 degenerate) and configuration of one hub with
+// spokes P, Q, R (squared lengths qP, qQ, qR, bins bP, bQ, bR).
+// The definition sorts the spokes by length, s0 <= s1 <= s2, and takes the
+// sign of (s0 x s1) . s2. Without moving vectors: the bins are monotone in
+// the length, so the sorted bins are the min, median and max of the three;
+// the sorted lengths likewise. With w the longest spoke and (u, v) the other
+// two in cyclic order, (s0 x s1) . s2 is (u x v) . w when u is the shorter of
+// the two and its exact negation otherwise (swapping the factors of each
+// product leaves it unchanged, and a rounded difference changes only its
+// sign when its operands swap), so the three candidates (one per choice of
+// w) are formed and one is selected. Ties in length are degenerate whatever
+// the order taken among the tied spokes.
+__device__ __forceinline__ int hub_channel(const P3 &P, const P3 &Q, const P3 &R, double qP, double qQ,
+                                           double qR, int bP, int bQ, int bR, const int *ta, const int *tb,
                                            int *idx) {
-    cswap(s0, s1);
-    cswap(s1, s2);
-    cswap(s0, s1);
-    *idx = ta[s0.b] + tb[s1.b] + s2.b;
-    const double cx = __dsub_rn(__dmul_rn(s0.y, s1.z), __dmul_rn(s0.z, s1.y));
-    const double cy = __dsub_rn(__dmul_rn(s0.z, s1.x), __dmul_rn(s0.x, s1.z));
-    const double cz = __dsub_rn(__dmul_rn(s0.x, s1.y), __dmul_rn(s0.y, s1.x));
-    const double V = __dadd_rn(__dadd_rn(__dmul_rn(cx, s2.x), __dmul_rn(cy, s2.y)), __dmul_rn(cz, s2.z));
-    if (s0.q == s1.q || s1.q == s2.q) return 2;
-    const double lim = __dmul_rn(1e-18, __dmul_rn(__dmul_rn(s0.q, s1.q), s2.q));
-    if (__dmul_rn(V, V) <= lim) return 2;
-    return V > 0.0 ? 0 : 1;
+    const int b0 = min(min(bP, bQ), bR), b2 = max(max(bP, bQ), bR);
+    const int b1 = bP + bQ + bR - b0 - b2;
+    *idx = ta[b0] + tb[b1] + b2;
+    const bool pq = qP < qQ;
+    const double lo = pq ? qP : qQ, hi = pq ? qQ : qP;
+    const double q0 = lo < qR ? lo : qR, q2 = hi > qR ? hi : qR;
+    const double mh = hi < qR ? hi : qR;
+    const double q1 = lo > mh ? lo : mh;
+    const bool selP = qP > qQ && qP > qR;
+    const bool selQ = !selP && qQ > qR;
+    const double vR = triple(P, Q, R), vP = triple(Q, R, P), vQ = triple(R, P, Q);
+    const double V = selP ? vP : (selQ ? vQ : vR);
+    const bool up = selP ? (qQ <= qR) : (selQ ? (qR <= qP) : (qP <= qQ));
+    const double lim = __dmul_rn(1e-18, __dmul_rn(__dmul_rn(q0, q1), q2));
+    const bool degen = (q0 == q1) | (q1 == q2) | (__dmul_rn(V, V) <= lim);
+    return degen ? 2 : ((V > 0.0) == up ? 0 : 1);
 }
 
-__device__ __forceinline__ Spoke neg(const Spoke &s) { return Spoke{-s.x, -s.y, -s.z, s.q, s.b}; }
+// Per-hub LDS state the clique evaluation reads.
+struct Stage4 {
+    const double *px, *py, *pz;   // absolute coordinates of N+(i)
+    const double *sx, *sy, *sz;   // spokes from the hub (minimum image)
+    const double *pq;             // squared spoke lengths
+    const uint8_t *pb;            // spoke bins
+    const double *thr;            // t_0 .. t_nb
+    const int *ta, *tb;           // configuration rank tables
+    uint32_t *hist;               // pos | neg | degenerate counters
+    int nb, nconf;
+    double L, half;
+};
+
+// The four hubs of the clique {i, va, vb, vc}: each hub's spokes are the
+// separations to the other three (the hub's own spokes negated where the
+// clique's edge points towards it).
+template <bool WRAP>
+__device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t va, uint32_t vb, uint32_t vc) {
+    const P3 A{S.px[va], S.py[va], S.pz[va]};
+    const P3 B{S.px[vb], S.py[vb], S.pz[vb]};
+    const P3 C{S.px[vc], S.py[vc], S.pz[vc]};
+    const P3 ia{S.sx[va], S.sy[va], S.sz[va]};
+    const P3 ib{S.sx[vb], S.sy[vb], S.sz[vb]};
+    const P3 ic{S.sx[vc], S.sy[vc], S.sz[vc]};
+    const double qa = S.pq[va], qb = S.pq[vb], qc = S.pq[vc];
+    const int ba = S.pb[va], bb = S.pb[vb], bc = S.pb[vc];
+    const P3 ab{sep<WRAP>(A.x, B.x, S.L, S.half), sep<WRAP>(A.y, B.y, S.L, S.half), sep<WRAP>(A.z, B.z, S.L, S.half)};
+    const P3 ac{sep<WRAP>(A.x, C.x, S.L, S.half), sep<WRAP>(A.y, C.y, S.L, S.half), sep<WRAP>(A.z, C.z, S.L, S.half)};
+    const P3 bcv{sep<WRAP>(B.x, C.x, S.L, S.half), sep<WRAP>(B.y, C.y, S.L, S.half), sep<WRAP>(B.z, C.z, S.L, S.half)};
+    const double qab = sq_len(ab.x, ab.y, ab.z), qac = sq_len(ac.x, ac.y, ac.z), qbc = sq_len(bcv.x, bcv.y, bcv.z);
+    const int bab = bin_of(S.thr, S.nb, qab), bac = bin_of(S.thr, S.nb, qac), bbc = bin_of(S.thr, S.nb, qbc);
+    int idx, ch;
+    ch = hub_channel(ia, ib, ic, qa, qb, qc, ba, bb, bc, S.ta, S.tb, &idx);
+    atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
+    ch = hub_channel(neg(ia), ab, ac, qa, qab, qac, ba, bab, bac, S.ta, S.tb, &idx);
+    atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
+    ch = hub_channel(neg(ib), neg(ab), bcv, qb, qab, qbc, bb, bab, bbc, S.ta, S.tb, &idx);
+    atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
+    ch = hub_channel(neg(ic), neg(ac), neg(bcv), qc, qac, qbc, bc, bac, bbc, S.ta, S.tb, &idx);
+    atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
+}
 
 template <int BLOCK>
 __device__ void flush4(const C4Args &a, uint32_t *hist) {
@@ -134,6 +208,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint16_t *hloc = (uint16_t *)(sm + L.hloc);
     uint16_t *hslot = (uint16_t *)(sm + L.hslot);
     double *px = (double *)(sm + L.px), *py = (double *)(sm + L.py), *pz = (double *)(sm + L.pz);
+    double *sx = (double *)(sm + L.sx), *sy = (double *)(sm + L.sy), *sz = (double *)(sm + L.sz);
     double *pq = (double *)(sm + L.pq);
     uint8_t *pb = (uint8_t *)(sm + L.pb);
     uint32_t *pperm = (uint32_t *)(sm + L.pperm);
@@ -168,6 +243,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint64_t acc = 0;
     HubCursor cursor;   // thread 0's claimed run of hubs
     const double Lb = a.L, half = a.half;
+    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, hist, a.nb, a.nconf, a.L, a.half};
 
     while (true) {
         if (tid == 0) *s_hub = next_hub_in(a.queue, 0, a.n, gridDim.x, cursor, 1);
@@ -179,6 +255,10 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
         if (d < 3) { __syncthreads(); continue; }
         const double xi = a.X[i], yi = a.Y[i], zi = a.Z[i];
         const uint32_t pi = ANCHORED ? a.perm[i] : 0;
+        // every vertex of this hub's cliques lies within rmax of the hub and
+        // so, away from the faces, no separation among them wraps
+        const bool inner = xi >= a.in_lo && xi <= a.in_hi && yi >= a.in_lo && yi <= a.in_hi &&
+                           zi >= a.in_lo && zi <= a.in_hi;
 
         // 1. stage the hub's forward row
         for (uint32_t e = tid; e < d; e += BLOCK) {
@@ -191,7 +271,12 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
             px[e] = x;
             py[e] = y;
             pz[e] = z;
-            pq[e] = sq_len(min_image(xi, x, Lb, half), min_image(yi, y, Lb, half), min_image(zi, z, Lb, half));
+            const double dx = min_image(xi, x, Lb, half), dy = min_image(yi, y, Lb, half),
+                         dz = min_image(zi, z, Lb, half);
+            sx[e] = dx;
+            sy[e] = dy;
+            sz[e] = dz;
+            pq[e] = sq_len(dx, dy, dz);
             pb[e] = a.bin[beg + e];
             if (ANCHORED) pperm[e] = a.perm[k];
         }
@@ -298,33 +383,8 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
                     if (mn < a.anchor_lo || mn >= a.anchor_hi) continue;
                 }
                 ++mycl;
-                const double ax = px[va], ay = py[va], az = pz[va];
-                const double bx = px[vb], by = py[vb], bz = pz[vb];
-                const double cx = px[vc], cy = py[vc], cz = pz[vc];
-                const Spoke ia{min_image(xi, ax, Lb, half), min_image(yi, ay, Lb, half),
-                               min_image(zi, az, Lb, half), pq[va], pb[va]};
-                const Spoke ib{min_image(xi, bx, Lb, half), min_image(yi, by, Lb, half),
-                               min_image(zi, bz, Lb, half), pq[vb], pb[vb]};
-                const Spoke ic{min_image(xi, cx, Lb, half), min_image(yi, cy, Lb, half),
-                               min_image(zi, cz, Lb, half), pq[vc], pb[vc]};
-                Spoke ab{min_image(ax, bx, Lb, half), min_image(ay, by, Lb, half), min_image(az, bz, Lb, half), 0, 0};
-                ab.q = sq_len(ab.x, ab.y, ab.z);
-                ab.b = bin_of(thr, a.nb, ab.q);
-                Spoke ac{min_image(ax, cx, Lb, half), min_image(ay, cy, Lb, half), min_image(az, cz, Lb, half), 0, 0};
-                ac.q = sq_len(ac.x, ac.y, ac.z);
-                ac.b = bin_of(thr, a.nb, ac.q);
-                Spoke bc{min_image(bx, cx, Lb, half), min_image(by, cy, Lb, half), min_image(bz, cz, Lb, half), 0, 0};
-                bc.q = sq_len(bc.x, bc.y, bc.z);
-                bc.b = bin_of(thr, a.nb, bc.q);
-                int idx, ch;
-                ch = hub_channel(ia, ib, ic, ta, tb, &idx);
-                atomicAdd(&hist[ch * a.nconf + idx], 1u);
-                ch = hub_channel(neg(ia), ab, ac, ta, tb, &idx);
-                atomicAdd(&hist[ch * a.nconf + idx], 1u);
-                ch = hub_channel(neg(ib), neg(ab), bc, ta, tb, &idx);
-                atomicAdd(&hist[ch * a.nconf + idx], 1u);
-                ch = hub_channel(neg(ic), neg(ac), neg(bc), ta, tb, &idx);
-                atomicAdd(&hist[ch * a.nconf + idx], 1u);
+                if (inner) eval_clique<false>(S, va, vb, vc);
+                else eval_clique<true>(S, va, vb, vc);
             }
             __syncthreads();
         }
@@ -402,6 +462,15 @@ void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_
     a.maxdeg = maxdeg;
     a.L = g.box;
     a.half = 0.5 * g.box;
+    // Hubs at least 2 rmax (with margin) from every face: their clique
+    // vertices lie within rmax of the hub, hence unwrapped, and any two of
+    // them within 2 rmax < L/2 of each other, so no separation among them
+    // wraps. The window is empty unless 4 rmax is below L.
+    {
+        const double m = 2.0 * g.rmax * (1.0 + 1e-9);
+        a.in_lo = m;
+        a.in_hi = m < 0.5 * g.box ? g.box - m : -1.0;
+    }
     a.anchor_lo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
     a.anchor_hi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;
     const char *fl = getenv("GS_FLUSH_LIMIT");
