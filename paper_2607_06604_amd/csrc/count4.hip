@@ -39,6 +39,7 @@ struct C4Args {
     uint32_t maxdeg;
     double L, half;
     double in_lo, in_hi;   // hubs with every coordinate in [in_lo, in_hi] see no wrapped pair
+    double eb;             // margin on a shared triple product (interior hubs)
     uint32_t anchor_lo, anchor_hi;
     uint64_t flush_limit;
     uint32_t *queue;
@@ -47,9 +48,11 @@ struct C4Args {
 };
 
 struct Layout4 {
-    uint32_t hkey, hloc, hslot, px, py, pz, sx, sy, sz, pq, pb, pperm, R, rowpref, eA, eB, epref, ecw, mstart,
-        mpref, mloc, hist, tab, thr, wtot, misc, total;
+    uint32_t hkey, hloc, hslot, px, py, pz, sx, sy, sz, pq, pb, pperm, R, rbnd, queue, mstart, mpref, mloc,
+        hist, tab, thr, wtot, misc, total;
 };
+
+constexpr int kQueue4 = 128;   // clique ring entries per wavefront
 
 __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxdeg, int W, int nconf,
                                            int nb, bool anchored) {
@@ -64,21 +67,18 @@ __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxde
     L.pq = o;      o = lds_align(o + 8 * d, 16);
     L.thr = o;     o = lds_align(o + 8 * (nb + 1), 16);
     L.mstart = o;  o = lds_align(o + 8 * block, 16);
+    L.rbnd = o;    o = lds_align(o + 8 * (d + 1), 16);
+    L.queue = o;   o = lds_align(o + 8 * kQueue4 * (block / 64), 16);
+    L.wtot = o;    o = lds_align(o + 8 * (block / 64 + 1), 16);
+    L.misc = o;    o = lds_align(o + 32, 16);
     L.hkey = o;    o = lds_align(o + 4 * H, 16);
     L.R = o;       o = lds_align(o + 4 * d * W, 16);
-    L.ecw = o;     o = lds_align(o + 4 * block * W, 16);
-    L.rowpref = o; o = lds_align(o + 4 * (d + 1), 16);
-    L.epref = o;   o = lds_align(o + 4 * (block + 1), 16);
     L.mpref = o;   o = lds_align(o + 4 * (block + 1), 16);
     L.pperm = o;   if (anchored) o = lds_align(o + 4 * d, 16);
     L.hist = o;    o = lds_align(o + 4 * 3 * nconf, 16);
     L.tab = o;     o = lds_align(o + 8 * (nb + 1), 16);
-    L.wtot = o;    o = lds_align(o + 4 * (block / 64 + 1), 16);
-    L.misc = o;    o = lds_align(o + 16, 16);
     L.hloc = o;    o = lds_align(o + 2 * H, 16);
     L.hslot = o;   o = lds_align(o + 2 * d, 16);
-    L.eA = o;      o = lds_align(o + 2 * block, 16);
-    L.eB = o;      o = lds_align(o + 2 * block, 16);
     L.mloc = o;    o = lds_align(o + 2 * block, 16);
     L.pb = o;      o = lds_align(o + d, 16);
     L.total = o;
@@ -145,6 +145,49 @@ __device__ __forceinline__ int hub_channel(const P3 &P, const P3 &Q, const P3 &R
     return degen ? 2 : ((V > 0.0) == up ? 0 : 1);
 }
 
+// One hub of a clique whose separations none wrap, decided from Vc, the
+// triple product (ia x ib) . ic of hub i's spokes in label order, where that
+// is safe. In exact arithmetic every hub's sorted triple product is +-T (T
+// the signed volume times 6): the hub's spokes P, Q, R are differences of the
+// same four points, so (P x Q) . R is T for hubs i and b and -T for hubs a
+// and c (sign0), and sorting the spokes multiplies it by the parity of the
+// sorting permutation. Every spoke is the exact difference rounded once
+// (no wrap), and evaluating a triple product rounds each of its few terms
+// once; both the definition's value for this hub and Vc are therefore
+// within a small multiple of the unit roundoff times the product of the
+// spoke lengths (at most rmax^3) of +-T. eb bounds twice the sum of the two
+// errors, so when |Vc| - eb already squares above the hub's limit the
+// definition's value does too and carries the predicted sign, and when
+// |Vc| + eb squares below it the hub is degenerate. Otherwise (a clique
+// within rounding of coplanar, or of the threshold) the hub is evaluated
+// exactly as the definition says. Ties in length are decided exactly.
+__device__ __forceinline__ int hub_channel_shared(const P3 &P, const P3 &Q, const P3 &R, double qP, double qQ,
+                                                  double qR, int bP, int bQ, int bR, const int *ta,
+                                                  const int *tb, int *idx, double Vc, bool sign0,
+                                                  double eb) {
+    const int b0 = min(min(bP, bQ), bR), b2 = max(max(bP, bQ), bR);
+    const int b1 = bP + bQ + bR - b0 - b2;
+    *idx = ta[b0] + tb[b1] + b2;
+    const bool pq = qP < qQ;
+    const double lo = pq ? qP : qQ, hi = pq ? qQ : qP;
+    const double q0 = lo < qR ? lo : qR, q2 = hi > qR ? hi : qR;
+    const double mh = hi < qR ? hi : qR;
+    const double q1 = lo > mh ? lo : mh;
+    if (q0 == q1 || q1 == q2) return 2;
+    const double lim = __dmul_rn(1e-18, __dmul_rn(__dmul_rn(q0, q1), q2));
+    const double A = fabs(Vc);
+    const double x = __dsub_rn(A, eb), y = __dadd_rn(A, eb);
+    if (x > 0.0 && __dmul_rn(x, x) > lim) {
+        // parity of the sort: inversions among (qP, qQ, qR), no ties here
+        const bool odd = ((qP > qQ) ^ (qP > qR) ^ (qQ > qR));
+        const bool pos = (Vc > 0.0) ^ odd ^ !sign0;
+        return pos ? 0 : 1;
+    }
+    if (__dmul_rn(y, y) <= lim) return 2;
+    int idx2;
+    return hub_channel(P, Q, R, qP, qQ, qR, bP, bQ, bR, ta, tb, &idx2);
+}
+
 // Per-hub LDS state the clique evaluation reads.
 struct Stage4 {
     const double *px, *py, *pz;   // absolute coordinates of N+(i)
@@ -156,6 +199,7 @@ struct Stage4 {
     uint32_t *hist;               // pos | neg | degenerate counters
     int nb, nconf;
     double L, half;
+    double eb;                    // shared triple product margin
 };
 
 // The four hubs of the clique {i, va, vb, vc}: each hub's spokes are the
@@ -177,6 +221,20 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t va, uint32
     const double qab = sq_len(ab.x, ab.y, ab.z), qac = sq_len(ac.x, ac.y, ac.z), qbc = sq_len(bcv.x, bcv.y, bcv.z);
     const int bab = bin_of(S.thr, S.nb, qab), bac = bin_of(S.thr, S.nb, qac), bbc = bin_of(S.thr, S.nb, qbc);
     int idx, ch;
+    if (!WRAP) {
+        const double Vc = triple(ia, ib, ic);
+        ch = hub_channel_shared(ia, ib, ic, qa, qb, qc, ba, bb, bc, S.ta, S.tb, &idx, Vc, true, S.eb);
+        atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
+        ch = hub_channel_shared(neg(ia), ab, ac, qa, qab, qac, ba, bab, bac, S.ta, S.tb, &idx, Vc, false, S.eb);
+        atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
+        ch = hub_channel_shared(neg(ib), neg(ab), bcv, qb, qab, qbc, bb, bab, bbc, S.ta, S.tb, &idx, Vc, true,
+                                S.eb);
+        atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
+        ch = hub_channel_shared(neg(ic), neg(ac), neg(bcv), qc, qac, qbc, bc, bac, bbc, S.ta, S.tb, &idx, Vc,
+                                false, S.eb);
+        atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
+        return;
+    }
     ch = hub_channel(ia, ib, ic, qa, qb, qc, ba, bb, bc, S.ta, S.tb, &idx);
     atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
     ch = hub_channel(neg(ia), ab, ac, qa, qab, qac, ba, bab, bac, S.ta, S.tb, &idx);
@@ -213,10 +271,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint8_t *pb = (uint8_t *)(sm + L.pb);
     uint32_t *pperm = (uint32_t *)(sm + L.pperm);
     uint32_t *R = (uint32_t *)(sm + L.R);
-    uint32_t *rowpref = (uint32_t *)(sm + L.rowpref);
-    uint16_t *eA = (uint16_t *)(sm + L.eA), *eB = (uint16_t *)(sm + L.eB);
-    uint32_t *epref = (uint32_t *)(sm + L.epref);
-    uint32_t *ecw = (uint32_t *)(sm + L.ecw);
+    unsigned long long *rbnd = (unsigned long long *)(sm + L.rbnd);
     unsigned long long *mstart = (unsigned long long *)(sm + L.mstart);
     uint32_t *mpref = (uint32_t *)(sm + L.mpref);
     uint16_t *mloc = (uint16_t *)(sm + L.mloc);
@@ -225,9 +280,13 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     int *tb = ta + (a.nb + 1);
     double *thr = (double *)(sm + L.thr);
     uint32_t *wtot = (uint32_t *)(sm + L.wtot);
+    uint64_t *wtot64 = (uint64_t *)(sm + L.wtot);
     uint32_t *s_hub = (uint32_t *)(sm + L.misc);
+    uint32_t *s_row = (uint32_t *)(sm + L.misc + 4);
     unsigned long long *s_cnt = (unsigned long long *)(sm + L.misc + 8);
-    const int tid = threadIdx.x;
+    unsigned long long *s_round = (unsigned long long *)(sm + L.misc + 16);
+    const int tid = threadIdx.x, lane = tid & 63;
+    unsigned long long *ring = (unsigned long long *)(sm + L.queue) + (tid >> 6) * kQueue4;
 
     for (uint32_t s = tid; s < H; s += BLOCK) hkey[s] = kEmptyKey;
     for (int b = tid; b < 3 * a.nconf; b += BLOCK) hist[b] = 0;
@@ -243,7 +302,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint64_t acc = 0;
     HubCursor cursor;   // thread 0's claimed run of hubs
     const double Lb = a.L, half = a.half;
-    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, hist, a.nb, a.nconf, a.L, a.half};
+    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, hist, a.nb, a.nconf, a.L, a.half, a.eb};
 
     while (true) {
         if (tid == 0) *s_hub = next_hub_in(a.queue, 0, a.n, gridDim.x, cursor, 1);
@@ -317,76 +376,122 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
             __syncthreads();
         }
 
-        // 3a. local edges per row, prefix over rows
-        uint32_t base = 0;
-        for (uint32_t r0 = 0; r0 < d; r0 += BLOCK) {
-            const uint32_t r = r0 + tid;
-            uint32_t cnt = 0;
-            if (r < d)
-                for (int w = 0; w < W; ++w) cnt += __popc(R[r * W + w]);
-            uint32_t total;
-            const uint32_t pre = wg_excl_scan<BLOCK>(cnt, wtot, total);
-            if (r < d) rowpref[r] = base + pre;
-            base += total;
-        }
-        if (tid == 0) rowpref[d] = base;
-        __syncthreads();
-        const uint32_t nloc = base;
-
-        // 3b. chunks of BLOCK local edges; all their cliques as one flat range
-        for (uint32_t cb = 0; cb < nloc; cb += BLOCK) {
-            const uint32_t x = cb + tid;
-            uint32_t m = 0;
-            if (x < nloc) {
-                const uint32_t ra = upper_index(rowpref, d, x);
-                int r = (int)(x - rowpref[ra]);
-                uint32_t rb = 0;
-                for (int w = 0; w < W; ++w) {
-                    const uint32_t word = R[ra * W + w];
-                    const int pc = __popc(word);
-                    if (r < pc) { rb = (uint32_t)(w * 32 + select_bit(word, r)); break; }
-                    r -= pc;
+        // 3a. a bound on the counter increments of the cliques each row
+        //     starts, 4 C(popcount, 2) (one increment per hub), prefix over rows
+        {
+            uint64_t base = 0;
+            for (uint32_t r0 = 0; r0 < d; r0 += BLOCK) {
+                const uint32_t r = r0 + tid;
+                uint64_t bnd = 0;
+                if (r < d) {
+                    uint32_t cnt = 0;
+                    for (int w = 0; w < W; ++w) cnt += __popc(R[r * W + w]);
+                    bnd = cnt ? 2ull * cnt * (cnt - 1) : 0ull;
                 }
-                for (int w = 0; w < W; ++w) {
-                    const uint32_t cw = R[ra * W + w] & R[rb * W + w];
-                    ecw[tid * W + w] = cw;
-                    m += __popc(cw);
-                }
-                eA[tid] = (uint16_t)ra;
-                eB[tid] = (uint16_t)rb;
+                uint64_t total;
+                const uint64_t pre = wg_excl_scan64<BLOCK>(bnd, wtot64, total);
+                if (r < d) rbnd[r] = base + pre;
+                base += total;
             }
-            uint32_t total;
-            const uint32_t pre = wg_excl_scan<BLOCK>(m, wtot, total);
-            epref[tid] = pre;
-            if (tid == 0) epref[BLOCK] = total;
-            if (acc + 4ull * total >= a.flush_limit) {
+            if (tid == 0) rbnd[d] = base;
+            __syncthreads();
+        }
+
+        // 3b. rounds of rows whose bound fits under the counters' flush limit
+        //     (normally the whole hub). In a round the wavefronts claim rows
+        //     a; for every local edge (a, b) of a row they scan the common
+        //     forward neighbours c (bits of row a AND row b) 64 at a time,
+        //     one lane per candidate bit, and compact the cliques {i, a, b, c}
+        //     into a per-wavefront ring; every 64 queued cliques are
+        //     evaluated, one per lane.
+        for (uint32_t r0 = 0; r0 < d;) {
+            const uint64_t rest = rbnd[d] - rbnd[r0];
+            if (acc > 0 && acc + rest >= a.flush_limit) {
                 flush4<BLOCK>(a, hist);
                 acc = 0;
+                __syncthreads();
             }
-            acc += 4ull * total;
+            const uint64_t room = a.flush_limit - 1 - acc;
+            uint32_t r1 = d;
+            if (rest > room) {
+                uint32_t lo = r0 + 1, hi = d;  // one row always fits an empty set of counters
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (rbnd[mid] - rbnd[r0] <= room) lo = mid;
+                    else hi = mid;
+                }
+                r1 = lo;
+            }
+            if (tid == 0) {
+                *s_row = r0;
+                *s_round = 0;
+            }
             __syncthreads();
-            for (uint32_t e0 = 0; e0 < total; e0 += BLOCK) {
-                const uint32_t e = e0 + tid;
-                if (e >= total) continue;
-                const uint32_t k = upper_index(epref, BLOCK, e);
-                int r = (int)(e - epref[k]);
-                uint32_t vc = 0;
-                for (int w = 0; w < W; ++w) {
-                    const uint32_t word = ecw[k * W + w];
-                    const int pc = __popc(word);
-                    if (r < pc) { vc = (uint32_t)(w * 32 + select_bit(word, r)); break; }
-                    r -= pc;
+
+            uint32_t qhead = 0, qtail = 0;   // ring positions (wavefront-uniform)
+            unsigned long long mine_n = 0;   // cliques this lane evaluated in the round
+            while (true) {
+                uint32_t ra = 0;
+                if (lane == 0) ra = atomicAdd(s_row, 1u);
+                ra = __builtin_amdgcn_readfirstlane(ra);
+                if (ra >= r1) break;
+                const uint32_t *Ra = R + ra * W;
+                const uint32_t pa = ANCHORED ? min(pi, pperm[ra]) : 0u;
+                for (int wa = 0; wa < W; ++wa) {
+                    uint32_t bits = __builtin_amdgcn_readfirstlane(Ra[wa]);
+                    while (bits) {
+                        const uint32_t rb = (uint32_t)(wa * 32 + __builtin_ctz(bits));
+                        bits &= bits - 1;
+                        const uint32_t *Rb = R + rb * W;
+                        const uint32_t pab = ANCHORED ? min(pa, pperm[rb]) : 0u;
+                        for (int w = (int)((rb + 1) >> 5); w < W; w += 2) {
+                            const uint32_t lo = __builtin_amdgcn_readfirstlane(Ra[w] & Rb[w]);
+                            const uint32_t hi =
+                                w + 1 < W ? __builtin_amdgcn_readfirstlane(Ra[w + 1] & Rb[w + 1]) : 0u;
+                            if ((lo | hi) == 0u) continue;
+                            const uint32_t word = lane < 32 ? lo : hi;
+                            const uint32_t rc = (uint32_t)(w * 32 + lane);
+                            bool take = ((word >> (lane & 31)) & 1u) != 0u;
+                            if (ANCHORED && take) {
+                                const uint32_t mn = min(pab, pperm[rc]);
+                                take = mn >= a.anchor_lo && mn < a.anchor_hi;
+                            }
+                            const uint64_t bal = __ballot(take);
+                            if (take)
+                                ring[(qtail + lanes_below(bal)) & (kQueue4 - 1)] =
+                                    (unsigned long long)ra | ((unsigned long long)rb << 16) |
+                                    ((unsigned long long)rc << 32);
+                            qtail += (uint32_t)__popcll(bal);
+                            if (qtail - qhead >= 64) {
+                                wave_lds_sync();
+                                const unsigned long long t = ring[(qhead + lane) & (kQueue4 - 1)];
+                                qhead += 64;
+                                ++mine_n;
+                                const uint32_t va = (uint32_t)t & 0xFFFFu, vb = (uint32_t)(t >> 16) & 0xFFFFu,
+                                               vc = (uint32_t)(t >> 32);
+                                if (inner) eval_clique<false>(S, va, vb, vc);
+                                else eval_clique<true>(S, va, vb, vc);
+                                wave_lds_sync();
+                            }
+                        }
+                    }
                 }
-                const uint32_t va = eA[k], vb = eB[k];
-                if (ANCHORED) {
-                    const uint32_t mn = min(min(pi, pperm[va]), min(pperm[vb], pperm[vc]));
-                    if (mn < a.anchor_lo || mn >= a.anchor_hi) continue;
-                }
-                ++mycl;
+            }
+            wave_lds_sync();
+            if ((uint32_t)lane < qtail - qhead) {
+                const unsigned long long t = ring[(qhead + lane) & (kQueue4 - 1)];
+                ++mine_n;
+                const uint32_t va = (uint32_t)t & 0xFFFFu, vb = (uint32_t)(t >> 16) & 0xFFFFu,
+                               vc = (uint32_t)(t >> 32);
                 if (inner) eval_clique<false>(S, va, vb, vc);
                 else eval_clique<true>(S, va, vb, vc);
             }
+            mycl += mine_n;
+            if (mine_n) atomicAdd(s_round, mine_n);
             __syncthreads();
+            acc += 4ull * *s_round;
+            r0 = r1;
+            __syncthreads();  // s_round is read before it is cleared
         }
 
         for (uint32_t e = tid; e < d; e += BLOCK) hkey[hslot[e]] = kEmptyKey;
@@ -462,21 +567,26 @@ void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_
     a.maxdeg = maxdeg;
     a.L = g.box;
     a.half = 0.5 * g.box;
-    // Hubs at least 2 rmax (with margin) from every face: their clique
+    // Hubs at least rmax (with margin) from every face: their clique
     // vertices lie within rmax of the hub, hence unwrapped, and any two of
     // them within 2 rmax < L/2 of each other, so no separation among them
     // wraps. The window is empty unless 4 rmax is below L.
     {
-        const double m = 2.0 * g.rmax * (1.0 + 1e-9);
+        const double m = g.rmax * (1.0 + 1e-9);
         a.in_lo = m;
-        a.in_hi = m < 0.5 * g.box ? g.box - m : -1.0;
+        a.in_hi = 4.0 * m < g.box ? g.box - m : -1.0;
+        // twice the summed error bounds of two triple products of spokes no
+        // longer than rmax (each below 70 unit roundoffs times rmax^3)
+        a.eb = 1e-13 * m * m * m;
     }
     a.anchor_lo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
     a.anchor_hi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;
     const char *fl = getenv("GS_FLUSH_LIMIT");
     a.flush_limit = fl ? strtoull(fl, nullptr, 10) : 0xFFFFFFFFull;
-    if (a.flush_limit < 4 * (uint64_t)BLOCK * (maxdeg + 1) || a.flush_limit > 0xFFFFFFFFull)
-        a.flush_limit = 0xFFFFFFFFull;
+    // the smallest limit a round can live with: one row's bound, 4 C(d, 2)
+    const uint64_t min_limit = std::max<uint64_t>(4 * (uint64_t)BLOCK * (maxdeg + 1),
+                                                  2ull * (maxdeg + 1) * (maxdeg + 1) + 4);
+    if (a.flush_limit < min_limit || a.flush_limit > 0xFFFFFFFFull) a.flush_limit = 0xFFFFFFFFull;
     a.hist = dv;
     a.ncl = dv + 3 * (size_t)nconf;
     a.queue = (uint32_t *)(dv + qoff);
