@@ -519,6 +519,8 @@ void launch4(Ctx &ctx, const C4Args &a, uint32_t lds) {
     int per_cu = 0;
     GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count4<BLOCK, A>, BLOCK, lds));
     if (per_cu < 1) fail(GS_EUNSUPPORTED, "parity kernel does not fit a compute unit");
+    if (getenv("GS_PLAN_LOG"))
+        fprintf(stderr, "[gsn] count4 block %d lds %u blocks/CU %d maxdeg %u\n", BLOCK, lds, per_cu, a.maxdeg);
     uint32_t grid = (uint32_t)ctx.n_cu * (uint32_t)per_cu;
     grid = (grid + kNumQueues - 1) / kNumQueues * kNumQueues;
     k_count4<BLOCK, A><<<dim3(grid), dim3(BLOCK), lds, ctx.stream>>>(a);
@@ -539,7 +541,11 @@ void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_
     int log2h = 6;
     while (H < 2 * maxdeg) { H <<= 1; ++log2h; }
     const int W = (int)((maxdeg + 31) / 32 > 0 ? (maxdeg + 31) / 32 : 1);
-    constexpr int BLOCK = 256;
+    // 512 lanes: the footprint above (set by the largest forward degree)
+    // usually leaves room for two work groups per compute unit, so the
+    // wider group doubles the wavefronts that hide LDS and float64 latency
+    int BLOCK = 512;
+    if (const char *eb = getenv("GS_BLOCK4")) BLOCK = atoi(eb) == 256 ? 256 : 512;
     Layout4 L = layout4(BLOCK, H, maxdeg, W, nconf, nb, anchored);
     if ((int)L.total > ctx.max_lds)
         fail(GS_EUNSUPPORTED, "parity kernel LDS footprint too large (forward degree " +
@@ -597,8 +603,13 @@ void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_
     GS_HIP(hipMemcpyAsync(dthr, g.bins.t, sizeof(double) * 256, hipMemcpyHostToDevice, s));
     GS_HIP(hipEventRecord(ctx.ev[2], s));
     if (g.n > 0) {
-        if (anchored) launch4<BLOCK, true>(ctx, a, L.total);
-        else launch4<BLOCK, false>(ctx, a, L.total);
+        if (BLOCK == 512) {
+            if (anchored) launch4<512, true>(ctx, a, L.total);
+            else launch4<512, false>(ctx, a, L.total);
+        } else {
+            if (anchored) launch4<256, true>(ctx, a, L.total);
+            else launch4<256, false>(ctx, a, L.total);
+        }
     }
     GS_HIP(hipEventRecord(ctx.ev[3], s));
     std::vector<unsigned long long> h(3 * (size_t)nconf + 1);

@@ -140,6 +140,15 @@ def test_count4_forced_flushes_identical(ctx, monkeypatch):
     same(got, ref)
 
 
+def test_count4_block256_identical(ctx, monkeypatch):
+    x = synth.neyman_scott(8000, 50, 1.2, 60.0, 41)
+    ref = gpu4(ctx, x, 60.0, 0.0, 3.0, 8)
+    monkeypatch.setenv("GS_BLOCK4", "256")
+    got = gpu4(ctx, x, 60.0, 0.0, 3.0, 8)
+    same(got, ref)
+    same(got, oracle.count_4pcf_parity(x, 60.0, 0.0, 3.0, 8))
+
+
 def test_lattice_closed_forms_gpu(ctx):
     g = _golden("lattice_sc.json")
     m = g["sites_per_axis"]
