@@ -18,6 +18,7 @@ namespace gsn {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr uint32_t kChunk = 64;   // labels per build work group (at most)
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -107,6 +108,9 @@ struct EdgeArgs {
     const double *X, *Y, *Z;
     const uint32_t *cellL;
     const uint64_t *cstart;
+    const uint64_t *chpref;  // chunks before each cell; [ncell] = all chunks
+    const uint32_t *gcell;   // cell of each chunk
+    uint32_t ncell, chunk;   // cells; labels per chunk
     const double *thr;     // t_0 .. t_nb
     uint32_t n;
     uint32_t l0, l1;    // labels handled by this launch
@@ -139,10 +143,16 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
     __shared__ uint64_t rs[27];   // first label of forward cell range r
     __shared__ uint32_t rq[28];   // running length before range r
     __shared__ int s_nr;
-    const uint32_t c = blockIdx.x;
+    // one work group per chunk of at most `chunk` labels of a cell, so that
+    // a crowded cell is spread over many groups instead of forming a tail
+    const uint32_t b = blockIdx.x;
+    if (b >= a.chpref[a.ncell]) return;   // the grid is an upper bound
+    const uint32_t c = a.gcell[b];
     const uint64_t cs = a.cstart[c], ce = a.cstart[c + 1];
-    const uint64_t i0 = cs > a.l0 ? cs : (uint64_t)a.l0, i1 = ce < a.l1 ? ce : (uint64_t)a.l1;
-    if (i0 >= i1) return;   // no point of this launch in the cell (uniform)
+    const uint64_t p0 = cs + (uint64_t)(b - a.chpref[c]) * a.chunk;
+    const uint64_t p1 = p0 + a.chunk < ce ? p0 + a.chunk : ce;
+    const uint64_t i0 = p0 > a.l0 ? p0 : (uint64_t)a.l0, i1 = p1 < a.l1 ? p1 : (uint64_t)a.l1;
+    if (i0 >= i1) return;   // no point of this launch in the chunk (uniform)
     for (int k = threadIdx.x; k <= a.nb; k += blockDim.x) t[k] = a.thr[k];
     if (threadIdx.x == 0) {
         const int nc = a.nc;
@@ -341,6 +351,20 @@ void scan(const TI *in, uint64_t n, uint64_t *out, hipStream_t s, const std::sha
     if (!pool) GS_HIP(hipStreamSynchronize(s));  // sums/offs are freed on return
 }
 
+// Chunks of at most `chunk` labels per cell.
+__global__ void k_chunk_count(const uint64_t *__restrict__ cstart, uint32_t ncell, uint32_t chunk,
+                              uint32_t *__restrict__ nch) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncell) nch[c] = (uint32_t)((cstart[c + 1] - cstart[c] + chunk - 1) / chunk);
+}
+
+// The cell of every chunk.
+__global__ void k_chunk_cells(const uint64_t *__restrict__ chpref, uint32_t ncell, uint32_t *__restrict__ gcell) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncell)
+        for (uint64_t k = chpref[c]; k < chpref[c + 1]; ++k) gcell[k] = c;
+}
+
 // sum of (out-degree + in-degree)^2 over labels
 __global__ void k_sum_sq_deg(const uint64_t *__restrict__ rp, const uint32_t *__restrict__ indeg,
                              uint32_t n, unsigned long long *__restrict__ acc) {
@@ -363,6 +387,10 @@ EdgeArgs edge_args(const Graph &g, const BuildJob &job) {
     ea.Z = job.C + 2 * (size_t)n;
     ea.cellL = job.cellL.as<uint32_t>();
     ea.cstart = job.cstart.as<uint64_t>();
+    ea.chpref = job.chpref.as<uint64_t>();
+    ea.gcell = job.gcell.as<uint32_t>();
+    ea.ncell = (uint32_t)((uint64_t)job.nc * job.nc * job.nc);
+    ea.chunk = kChunk;
     ea.thr = job.thr.as<double>();
     ea.n = n;
     ea.l0 = 0;
@@ -437,6 +465,18 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
         k_weights<<<grid_for(n), kBlock, 0, s>>>(dw, n, fl, (unsigned long long *)(flags.as<uint64_t>() + 4));
     GS_HIP(hipGetLastError());
     scan<uint32_t>(count.as<uint32_t>(), ncell, cstart.as<uint64_t>(), s, ctx.pool);
+    {
+        DevBuf nch(sizeof(uint32_t) * ncell, pool);
+        job.chpref.alloc(sizeof(uint64_t) * (ncell + 1), ctx.pool);
+        job.grid = (uint64_t)n / kChunk + ncell;   // at most one partial chunk per cell
+        job.gcell.alloc(sizeof(uint32_t) * job.grid, ctx.pool);
+        k_chunk_count<<<grid_for(ncell), kBlock, 0, s>>>(cstart.as<uint64_t>(), (uint32_t)ncell, kChunk,
+                                                          nch.as<uint32_t>());
+        scan<uint32_t>(nch.as<uint32_t>(), ncell, job.chpref.as<uint64_t>(), s, ctx.pool);
+        k_chunk_cells<<<grid_for(ncell), kBlock, 0, s>>>(job.chpref.as<uint64_t>(), (uint32_t)ncell,
+                                                          job.gcell.as<uint32_t>());
+        GS_HIP(hipGetLastError());
+    }
     k_fill_u32<<<grid_for(ncell), kBlock, 0, s>>>(count.as<uint32_t>(), ncell, 0);
     k_scatter<<<grid_for(n), kBlock, 0, s>>>(cell_of.as<uint32_t>(), n, cstart.as<uint64_t>(),
                                              count.as<uint32_t>(), order.as<uint32_t>());
@@ -464,7 +504,7 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
     EdgeArgs ea = edge_args(g, job);
     ea.deg = deg.as<uint32_t>();
     ea.maxdeg = fl + 1;
-    k_edges<false><<<(unsigned)((uint64_t)job.nc * job.nc * job.nc), kBlock, 0, s>>>(ea);
+    k_edges<false><<<(unsigned)job.grid, kBlock, 0, s>>>(ea);
     GS_HIP(hipGetLastError());
     scan<uint32_t>(deg.as<uint32_t>(), n, g.row_ptr.as<uint64_t>(), s, ctx.pool);
 
@@ -540,7 +580,7 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok) {
         g.bin.alloc(E + kRowSlack, ctx.pool);
         ea.col = g.col.as<uint32_t>();
         ea.bin = g.bin.as<uint8_t>();
-        k_edges<true><<<(unsigned)((uint64_t)job.nc * job.nc * job.nc), kBlock, 0, s>>>(ea);
+        k_edges<true><<<(unsigned)job.grid, kBlock, 0, s>>>(ea);
     } else {
         // row-aligned windows of about E/W entries each
         std::vector<uint64_t> hrp((size_t)n + 1);
@@ -571,7 +611,7 @@ void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok) {
             ea.l1 = (uint32_t)g.win[w + 1];
             ea.obase = g.win_edge[w];
             const uint64_t ne = g.win_edge[w + 1] - g.win_edge[w];
-            k_edges<true><<<(unsigned)((uint64_t)job.nc * job.nc * job.nc), kBlock, 0, s>>>(ea);
+            k_edges<true><<<(unsigned)job.grid, kBlock, 0, s>>>(ea);
             GS_HIP(hipGetLastError());
             GS_HIP(hipMemcpyAsync(g.hcol.as<uint32_t>() + g.win_edge[w], stc.p, ne * 4, hipMemcpyDeviceToHost, s));
             GS_HIP(hipMemcpyAsync(g.hbin.as<uint8_t>() + g.win_edge[w], stb.p, ne, hipMemcpyDeviceToHost, s));
