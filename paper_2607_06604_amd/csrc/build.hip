@@ -128,6 +128,66 @@ struct EdgeArgs {
     uint32_t *indeg;                // full-degree bookkeeping
 };
 
+// The rows of labels [i0, i1) of one cell (ce: the cell's end): a wavefront
+// per label, its lanes over the label's candidates 64 at a time (the own cell
+// after the label, then the forward cells' ranges rs / rq). WRAP false: the
+// caller knows no candidate separation needs a minimum-image correction.
+template <bool FILL, bool WRAP>
+__device__ __forceinline__ uint32_t edge_rows(const EdgeArgs &a, const double *t, const uint64_t *rs,
+                                              const uint32_t *rq, int nr, uint32_t Mf, uint64_t i0, uint64_t i1,
+                                              uint64_t ce) {
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const double t0 = t[0], tn = t[a.nb];
+    uint32_t mymax = 0;
+    for (uint64_t i = i0 + wid; i < i1; i += kBlock / 64) {
+        const double xi = a.X[i], yi = a.Y[i], zi = a.Z[i];
+        const uint32_t own = (uint32_t)(ce - i - 1);   // own-cell labels above i
+        const uint32_t M = own + Mf;
+        const uint64_t out = FILL ? a.rp[i] - a.obase : 0;
+        const uint32_t cap = FILL ? (uint32_t)(a.rp[i + 1] - a.rp[i]) : 0;  // the count pass's result
+        uint32_t cnt = 0;
+        for (uint32_t f0 = 0; f0 < M; f0 += 64) {
+            const uint32_t f = f0 + lane;
+            bool in = false;
+            uint64_t j = 0;
+            double q = 0.0;
+            if (f < M) {
+                if (f < own) {
+                    j = i + 1 + f;
+                } else {
+                    const uint32_t g = f - own;
+                    const uint32_t r = upper_index(rq, (uint32_t)nr, g);
+                    j = rs[r] + (g - rq[r]);
+                }
+                double dx, dy, dz;
+                if (WRAP) {
+                    dx = min_image(xi, a.X[j], a.L, a.half);
+                    dy = min_image(yi, a.Y[j], a.L, a.half);
+                    dz = min_image(zi, a.Z[j], a.L, a.half);
+                } else {  // no correction can apply: the plain difference is the same double
+                    dx = __dsub_rn(a.X[j], xi);
+                    dy = __dsub_rn(a.Y[j], yi);
+                    dz = __dsub_rn(a.Z[j], zi);
+                }
+                q = sq_len(dx, dy, dz);
+                in = q >= t0 && q < tn;
+            }
+            const uint64_t mask = __ballot(in);
+            if (FILL && in) {
+                const uint32_t k = cnt + lanes_below(mask);
+                if (k < cap) {
+                    a.col[out + k] = (uint32_t)j;
+                    a.bin[out + k] = (uint8_t)bin_of(t, a.nb, q);
+                }
+            }
+            cnt += (uint32_t)__popcll(mask);
+        }
+        if (!FILL && lane == 0) a.deg[i] = cnt;
+        mymax = cnt > mymax ? cnt : mymax;
+    }
+    return mymax;
+}
+
 // One thread per label: scan the label's own cell after it, then the forward
 // adjacent cells in ascending cell id.
 // Graph edges, one work group per cell: its wavefronts take the cell's
@@ -143,6 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
     __shared__ uint64_t rs[27];   // first label of forward cell range r
     __shared__ uint32_t rq[28];   // running length before range r
     __shared__ int s_nr;
+    __shared__ int s_wf;
     // one work group per chunk of at most `chunk` labels of a cell, so that
     // a crowded cell is spread over many groups instead of forming a tail
     const uint32_t b = blockIdx.x;
@@ -158,6 +219,10 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
         const int nc = a.nc;
         int ax[3], ay[3], az[3], na = 1;
         const int cx = (int)(c / (uint32_t)(nc * nc)), cy = (int)((c / nc) % nc), cz = (int)(c % nc);
+        // a cell off the boundary layer with at least 5 cells per axis: its
+        // candidates lie in truly adjacent cells, within 2 L / nc <= 0.4 L of
+        // the label, so no minimum-image correction can apply
+        s_wf = nc >= 5 && cx >= 1 && cx <= nc - 2 && cy >= 1 && cy <= nc - 2 && cz >= 1 && cz <= nc - 2;
         if (nc >= 3) {
             na = 3;
             auto sorted3 = [nc](int v, int *o) {
@@ -193,50 +258,11 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
     __syncthreads();
     const int nr = s_nr;
     const uint32_t Mf = rq[nr];
-    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const double t0 = t[0], tn = t[a.nb];
-    uint32_t mymax = 0;
-    for (uint64_t i = i0 + wid; i < i1; i += kBlock / 64) {
-        const double xi = a.X[i], yi = a.Y[i], zi = a.Z[i];
-        const uint32_t own = (uint32_t)(ce - i - 1);   // own-cell labels above i
-        const uint32_t M = own + Mf;
-        const uint64_t out = FILL ? a.rp[i] - a.obase : 0;
-        const uint32_t cap = FILL ? (uint32_t)(a.rp[i + 1] - a.rp[i]) : 0;  // the count pass's result
-        uint32_t cnt = 0;
-        for (uint32_t f0 = 0; f0 < M; f0 += 64) {
-            const uint32_t f = f0 + lane;
-            bool in = false;
-            uint64_t j = 0;
-            double q = 0.0;
-            if (f < M) {
-                if (f < own) {
-                    j = i + 1 + f;
-                } else {
-                    const uint32_t g = f - own;
-                    const uint32_t r = upper_index(rq, (uint32_t)nr, g);
-                    j = rs[r] + (g - rq[r]);
-                }
-                const double dx = min_image(xi, a.X[j], a.L, a.half);
-                const double dy = min_image(yi, a.Y[j], a.L, a.half);
-                const double dz = min_image(zi, a.Z[j], a.L, a.half);
-                q = sq_len(dx, dy, dz);
-                in = q >= t0 && q < tn;
-            }
-            const uint64_t mask = __ballot(in);
-            if (FILL && in) {
-                const uint32_t k = cnt + lanes_below(mask);
-                if (k < cap) {
-                    a.col[out + k] = (uint32_t)j;
-                    a.bin[out + k] = (uint8_t)bin_of(t, a.nb, q);
-                }
-            }
-            cnt += (uint32_t)__popcll(mask);
-        }
-        if (!FILL && lane == 0) a.deg[i] = cnt;
-        mymax = cnt > mymax ? cnt : mymax;
-    }
+    const bool wrapfree = __builtin_amdgcn_readfirstlane((int)s_wf) != 0;
+    const uint32_t mymax = wrapfree ? edge_rows<FILL, false>(a, t, rs, rq, nr, Mf, i0, i1, ce)
+                                    : edge_rows<FILL, true>(a, t, rs, rq, nr, Mf, i0, i1, ce);
     // one atomic per wave for the largest forward degree
-    if (!FILL && lane == 0 && mymax) atomicMax(a.maxdeg, mymax);
+    if (!FILL && (threadIdx.x & 63) == 0 && mymax) atomicMax(a.maxdeg, mymax);
 }
 
 // Graph statistics outside the build: in-degrees (for the full degrees) and
