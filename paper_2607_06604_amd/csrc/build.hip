@@ -416,7 +416,7 @@ EdgeArgs edge_args(const Graph &g, const BuildJob &job) {
     ea.chpref = job.chpref.as<uint64_t>();
     ea.gcell = job.gcell.as<uint32_t>();
     ea.ncell = (uint32_t)((uint64_t)job.nc * job.nc * job.nc);
-    ea.chunk = kChunk;
+    ea.chunk = job.chunk;
     ea.thr = job.thr.as<double>();
     ea.n = n;
     ea.l0 = 0;
@@ -494,9 +494,11 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
     {
         DevBuf nch(sizeof(uint32_t) * ncell, pool);
         job.chpref.alloc(sizeof(uint64_t) * (ncell + 1), ctx.pool);
-        job.grid = (uint64_t)n / kChunk + ncell;   // at most one partial chunk per cell
+        job.chunk = kChunk;
+        if (const char *ec = getenv("GS_BUILD_CHUNK")) job.chunk = (uint32_t)std::min(1024, std::max(8, atoi(ec)));
+        job.grid = (uint64_t)n / job.chunk + ncell;   // at most one partial chunk per cell
         job.gcell.alloc(sizeof(uint32_t) * job.grid, ctx.pool);
-        k_chunk_count<<<grid_for(ncell), kBlock, 0, s>>>(cstart.as<uint64_t>(), (uint32_t)ncell, kChunk,
+        k_chunk_count<<<grid_for(ncell), kBlock, 0, s>>>(cstart.as<uint64_t>(), (uint32_t)ncell, job.chunk,
                                                           nch.as<uint32_t>());
         scan<uint32_t>(nch.as<uint32_t>(), ncell, job.chpref.as<uint64_t>(), s, ctx.pool);
         k_chunk_cells<<<grid_for(ncell), kBlock, 0, s>>>(job.chpref.as<uint64_t>(), (uint32_t)ncell,

@@ -216,6 +216,7 @@ struct BuildJob {
     DevBuf chpref;       // u64[ncell+1]: chunks (build work groups) before each cell
     DevBuf gcell;        // u32[grid]: cell of each chunk
     uint64_t grid = 0;   // build work groups (an upper bound on the chunks)
+    uint32_t chunk = 64; // labels per build work group (at most)
     DevBuf cellL;        // u32[n]: cell of each label
     DevBuf thr;          // f64[256] squared thresholds
     DevBuf tmp_coords;   // f64[3n] when the graph does not keep coordinates
