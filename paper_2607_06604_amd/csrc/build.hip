@@ -19,6 +19,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr uint32_t kChunk = 64;   // labels per build work group (at most)
+constexpr uint32_t kStage = 1024; // candidates whose coordinates a work group stages in LDS
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -132,10 +133,11 @@ struct EdgeArgs {
 // per label, its lanes over the label's candidates 64 at a time (the own cell
 // after the label, then the forward cells' ranges rs / rq). WRAP false: the
 // caller knows no candidate separation needs a minimum-image correction.
-template <bool FILL, bool WRAP>
+template <bool FILL, bool WRAP, bool STAGED>
 __device__ __forceinline__ uint32_t edge_rows(const EdgeArgs &a, const double *t, const uint64_t *rs,
                                               const uint32_t *rq, int nr, uint32_t Mf, uint64_t i0, uint64_t i1,
-                                              uint64_t ce) {
+                                              uint64_t cs, uint64_t ce, const double *lx, const double *ly,
+                                              const double *lz) {
     const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const double t0 = t[0], tn = t[a.nb];
     uint32_t mymax = 0;
@@ -152,22 +154,35 @@ __device__ __forceinline__ uint32_t edge_rows(const EdgeArgs &a, const double *t
             uint64_t j = 0;
             double q = 0.0;
             if (f < M) {
-                if (f < own) {
-                    j = i + 1 + f;
+                double xj, yj, zj;
+                if (STAGED) {
+                    // the candidate's coordinates from the group's LDS copy:
+                    // the own cell first, then the forward ranges in order
+                    const uint32_t s = f < own ? (uint32_t)(i - cs) + 1 + f : (uint32_t)(ce - cs) + (f - own);
+                    xj = lx[s];
+                    yj = ly[s];
+                    zj = lz[s];
                 } else {
-                    const uint32_t g = f - own;
-                    const uint32_t r = upper_index(rq, (uint32_t)nr, g);
-                    j = rs[r] + (g - rq[r]);
+                    if (f < own) {
+                        j = i + 1 + f;
+                    } else {
+                        const uint32_t g = f - own;
+                        const uint32_t r = upper_index(rq, (uint32_t)nr, g);
+                        j = rs[r] + (g - rq[r]);
+                    }
+                    xj = a.X[j];
+                    yj = a.Y[j];
+                    zj = a.Z[j];
                 }
                 double dx, dy, dz;
                 if (WRAP) {
-                    dx = min_image(xi, a.X[j], a.L, a.half);
-                    dy = min_image(yi, a.Y[j], a.L, a.half);
-                    dz = min_image(zi, a.Z[j], a.L, a.half);
+                    dx = min_image(xi, xj, a.L, a.half);
+                    dy = min_image(yi, yj, a.L, a.half);
+                    dz = min_image(zi, zj, a.L, a.half);
                 } else {  // no correction can apply: the plain difference is the same double
-                    dx = __dsub_rn(a.X[j], xi);
-                    dy = __dsub_rn(a.Y[j], yi);
-                    dz = __dsub_rn(a.Z[j], zi);
+                    dx = __dsub_rn(xj, xi);
+                    dy = __dsub_rn(yj, yi);
+                    dz = __dsub_rn(zj, zi);
                 }
                 q = sq_len(dx, dy, dz);
                 in = q >= t0 && q < tn;
@@ -175,6 +190,15 @@ __device__ __forceinline__ uint32_t edge_rows(const EdgeArgs &a, const double *t
             const uint64_t mask = __ballot(in);
             if (FILL && in) {
                 const uint32_t k = cnt + lanes_below(mask);
+                if (STAGED) {  // the label of a hit (only the fill pass needs it)
+                    if (f < own) {
+                        j = i + 1 + f;
+                    } else {
+                        const uint32_t g = f - own;
+                        const uint32_t r = upper_index(rq, (uint32_t)nr, g);
+                        j = rs[r] + (g - rq[r]);
+                    }
+                }
                 if (k < cap) {
                     a.col[out + k] = (uint32_t)j;
                     a.bin[out + k] = (uint8_t)bin_of(t, a.nb, q);
@@ -204,6 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
     __shared__ uint32_t rq[28];   // running length before range r
     __shared__ int s_nr;
     __shared__ int s_wf;
+    __shared__ double lx[kStage], ly[kStage], lz[kStage];
     // one work group per chunk of at most `chunk` labels of a cell, so that
     // a crowded cell is spread over many groups instead of forming a tail
     const uint32_t b = blockIdx.x;
@@ -259,8 +284,33 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
     const int nr = s_nr;
     const uint32_t Mf = rq[nr];
     const bool wrapfree = __builtin_amdgcn_readfirstlane((int)s_wf) != 0;
-    const uint32_t mymax = wrapfree ? edge_rows<FILL, false>(a, t, rs, rq, nr, Mf, i0, i1, ce)
-                                    : edge_rows<FILL, true>(a, t, rs, rq, nr, Mf, i0, i1, ce);
+    // stage the candidates' coordinates (own cell, then the forward ranges)
+    // in LDS when they fit: every label of the group sweeps the same set
+    const uint32_t P = (uint32_t)(ce - cs);
+    const bool staged = P + Mf <= kStage;
+    if (staged) {
+        for (uint32_t k = threadIdx.x; k < P + Mf; k += kBlock) {
+            uint64_t l;
+            if (k < P) {
+                l = cs + k;
+            } else {
+                const uint32_t g = k - P;
+                const uint32_t r = upper_index(rq, (uint32_t)nr, g);
+                l = rs[r] + (g - rq[r]);
+            }
+            lx[k] = a.X[l];
+            ly[k] = a.Y[l];
+            lz[k] = a.Z[l];
+        }
+        __syncthreads();
+    }
+    uint32_t mymax;
+    if (staged)
+        mymax = wrapfree ? edge_rows<FILL, false, true>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz)
+                         : edge_rows<FILL, true, true>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz);
+    else
+        mymax = wrapfree ? edge_rows<FILL, false, false>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz)
+                         : edge_rows<FILL, true, false>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz);
     // one atomic per wave for the largest forward degree
     if (!FILL && (threadIdx.x & 63) == 0 && mymax) atomicMax(a.maxdeg, mymax);
 }
