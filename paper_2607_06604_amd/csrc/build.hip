@@ -19,7 +19,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr uint32_t kChunk = 64;   // labels per build work group (at most)
-constexpr uint32_t kStage = 1024; // candidates whose coordinates a work group stages in LDS
+constexpr uint32_t kStage = 512;  // candidates whose coordinates a work group stages in LDS
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
