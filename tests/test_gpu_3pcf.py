@@ -68,6 +68,10 @@ CASES = [
     ("two_cells_per_axis", lambda: synth.uniform(700, 10.0, 26), 10.0, 0.0, 4.2, 7, None),
     ("many_bins", lambda: synth.uniform(2000, 16.0, 25), 16.0, 0.0, 2.2, 21, None),
     ("dyadic_ties", lambda: synth.dyadic_uniform(3000, 16.0, 27, bits=6), 16.0, 0.0, 1.5, 6, None),
+    # crowded cells: a work group's candidates exceed its LDS stage (3 and 6
+    # cells per axis: every cell wrapping, and interior cells without wraps)
+    ("dense_wrap", lambda: synth.uniform(4000, 12.0, 28), 12.0, 0.0, 3.9, 5, None),
+    ("dense_interior", lambda: synth.uniform(12000, 25.0, 29), 25.0, 0.0, 3.9, 5, None),
     ("uniform_c1", None, None, None, None, None, ("uniform_3pcf", 1.0)),
     ("ns_c2_eighth", None, None, None, None, None, ("ns_3pcf", 0.125)),
     ("ns_c3_full", None, None, None, None, None, ("ns_4pcf_parity", 1.0)),
@@ -82,7 +86,7 @@ def _case(c):
     return mk(), L, rmin, rmax, nb
 
 
-@pytest.mark.parametrize("case", CASES[:8], ids=[c[0] for c in CASES[:8]])
+@pytest.mark.parametrize("case", CASES[:10], ids=[c[0] for c in CASES[:10]])
 def test_graph_edges_and_bins_match_oracle(ctx, case):
     x, L, rmin, rmax, nb = _case(case)
     say("graph", case[0], len(x))
