@@ -311,8 +311,17 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
     else
         mymax = wrapfree ? edge_rows<FILL, false, false>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz)
                          : edge_rows<FILL, true, false>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz);
-    // one atomic per wave for the largest forward degree
-    if (!FILL && (threadIdx.x & 63) == 0 && mymax) atomicMax(a.maxdeg, mymax);
+    // the largest forward degree: one value per group, and a device atomic
+    // only when it could raise the running maximum (one address shared by
+    // every group would otherwise serialise tens of thousands of atomics)
+    if (!FILL) {
+        __shared__ uint32_t s_max;
+        if (threadIdx.x == 0) s_max = 0;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0 && mymax) atomicMax(&s_max, mymax);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_max > __atomic_load_n(a.maxdeg, __ATOMIC_RELAXED)) atomicMax(a.maxdeg, s_max);
+    }
 }
 
 // Graph statistics outside the build: in-degrees (for the full degrees) and
