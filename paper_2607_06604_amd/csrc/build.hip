@@ -55,16 +55,26 @@ __global__ void k_cells(const double *__restrict__ xyz, uint32_t n, double L, in
 // Positive finite weights; min and max as ordered bit patterns.
 __global__ void k_weights(const double *__restrict__ w, uint32_t n, uint32_t *__restrict__ flags,
                           unsigned long long *__restrict__ mm) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double v = w[i];
-    if (!(v > 0.0) || !(v <= 1.79769313486231570e308)) {
-        atomicOr(&flags[0], 2u);
-        return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long lo = ~0ull, hi = 0;
+    if (i < n) {
+        const double v = w[i];
+        if (!(v > 0.0) || !(v <= 1.79769313486231570e308)) {
+            atomicOr(&flags[0], 2u);
+        } else {
+            lo = hi = (unsigned long long)__double_as_longlong(v);
+        }
     }
-    unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    atomicMin(&mm[0], b);
-    atomicMax(&mm[1], b);
+    // wavefront min / max first: one pair of device atomics per wavefront
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long l2 = __shfl_xor(lo, o, 64), h2 = __shfl_xor(hi, o, 64);
+        lo = l2 < lo ? l2 : lo;
+        hi = h2 > hi ? h2 : hi;
+    }
+    if ((threadIdx.x & 63) == 0 && hi) {
+        atomicMin(&mm[0], lo);
+        atomicMax(&mm[1], hi);
+    }
 }
 
 __global__ void k_scatter(const uint32_t *__restrict__ cell_of, uint32_t n,
