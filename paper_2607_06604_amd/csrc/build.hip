@@ -147,7 +147,7 @@ template <bool FILL, bool WRAP, bool STAGED>
 __device__ __forceinline__ uint32_t edge_rows(const EdgeArgs &a, const double *t, const uint64_t *rs,
                                               const uint32_t *rq, int nr, uint32_t Mf, uint64_t i0, uint64_t i1,
                                               uint64_t cs, uint64_t ce, const double *lx, const double *ly,
-                                              const double *lz) {
+                                              const double *lz, const uint32_t *lj) {
     const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const double t0 = t[0], tn = t[a.nb];
     uint32_t mymax = 0;
@@ -200,15 +200,8 @@ __device__ __forceinline__ uint32_t edge_rows(const EdgeArgs &a, const double *t
             const uint64_t mask = __ballot(in);
             if (FILL && in) {
                 const uint32_t k = cnt + lanes_below(mask);
-                if (STAGED) {  // the label of a hit (only the fill pass needs it)
-                    if (f < own) {
-                        j = i + 1 + f;
-                    } else {
-                        const uint32_t g = f - own;
-                        const uint32_t r = upper_index(rq, (uint32_t)nr, g);
-                        j = rs[r] + (g - rq[r]);
-                    }
-                }
+                if (STAGED)  // the label of a hit (only the fill pass needs it)
+                    j = f < own ? i + 1 + f : (uint64_t)lj[f - own];
                 if (k < cap) {
                     a.col[out + k] = (uint32_t)j;
                     a.bin[out + k] = (uint8_t)bin_of(t, a.nb, q);
@@ -239,6 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
     __shared__ int s_nr;
     __shared__ int s_wf;
     __shared__ double lx[kStage], ly[kStage], lz[kStage];
+    __shared__ uint32_t lj[FILL ? kStage : 1];   // labels of the forward candidates (fill pass)
     // one work group per chunk of at most `chunk` labels of a cell, so that
     // a crowded cell is spread over many groups instead of forming a tail
     const uint32_t b = blockIdx.x;
@@ -311,16 +305,17 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
             lx[k] = a.X[l];
             ly[k] = a.Y[l];
             lz[k] = a.Z[l];
+            if (FILL && k >= P) lj[k - P] = (uint32_t)l;
         }
         __syncthreads();
     }
     uint32_t mymax;
     if (staged)
-        mymax = wrapfree ? edge_rows<FILL, false, true>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz)
-                         : edge_rows<FILL, true, true>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz);
+        mymax = wrapfree ? edge_rows<FILL, false, true>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz, lj)
+                         : edge_rows<FILL, true, true>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz, lj);
     else
-        mymax = wrapfree ? edge_rows<FILL, false, false>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz)
-                         : edge_rows<FILL, true, false>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz);
+        mymax = wrapfree ? edge_rows<FILL, false, false>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz, lj)
+                         : edge_rows<FILL, true, false>(a, t, rs, rq, nr, Mf, i0, i1, cs, ce, lx, ly, lz, lj);
     // the largest forward degree: one value per group, and a device atomic
     // only when it could raise the running maximum (one address shared by
     // every group would otherwise serialise tens of thousands of atomics)
