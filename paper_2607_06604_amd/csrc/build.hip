@@ -215,15 +215,15 @@ __device__ __forceinline__ uint32_t edge_rows(const EdgeArgs &a, const double *t
     return mymax;
 }
 
-// One thread per label: scan the label's own cell after it, then the forward
-// adjacent cells in ascending cell id.
-// Graph edges, one work group per cell: its wavefronts take the cell's
-// points in turn, and for a point i the 64 lanes sweep its candidates -- the
-// rest of its own cell (labels above i), then the forward cells in ascending
-// cell id, hence ascending labels -- one candidate per lane, so loads are
-// coalesced, no lane waits on another cell's list, and a ballot compacts
-// each window's edges in label order. The count pass writes degrees; the
-// fill pass writes col / bin at the offsets the count pass produced.
+// Graph edges, one work group per chunk of at most 64 labels of a cell: its
+// wavefronts take the chunk's labels in turn, and for a label i the 64 lanes
+// sweep its candidates -- the rest of its own cell (labels above i), then
+// the forward cells in ascending cell id, hence ascending labels -- one
+// candidate per lane, and a ballot compacts each window's edges in label
+// order. The candidates' coordinates (and, for the fill pass, labels) are
+// staged in LDS when they fit. The count pass writes degrees and the largest
+// degree; the fill pass writes col / bin at the offsets the count pass
+// produced.
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
     __shared__ double t[256];
