@@ -185,6 +185,7 @@ typedef struct {
     int32_t counters;    /* 0: rank arithmetic, 1: table of counter addresses,   */
                          /* 2: per-(x,y,z) counters folded at flush              */
     int32_t hash_load;   /* hub hash table load bound: 5 (1/2) or 7 (0.7)         */
+    int32_t truncate;    /* 1: spoke rows cut at the hub row's largest label     */
     int32_t trials;      /* schedules timed                                      */
     double sample_ms;    /* chosen schedule on the sample (kernel time)          */
     double default_ms;   /* built-in schedule on the same sample                 */

@@ -142,10 +142,11 @@ struct Server;
 // Result staging shared by the count entry points of one context.
 // A triangle-count schedule (-1: the built-in choice): work-group size,
 // entries per step (log2), hubs per group, step table entries, counter mode,
-// hash table load bound.
+// hash table load bound, spoke-row truncation.
 struct Tune3 {
     int block = -1, glog = -1, group = -1, tmax = -1, mode = -1;
     int hload = 0;   // hash table load bound: 5 (1/2), 7 (0.7), 0 built-in
+    int trunc = -1;  // spoke rows cut at the hub row's largest label: 0, 1, -1 built-in
 };
 
 struct Ctx {

@@ -1027,8 +1027,12 @@ Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchore
     int tmax_pin = tune.tmax > 0 ? tune.tmax : 0;
     if (const char *em = getenv("GS_TMAX")) tmax_pin = atoi(em);
     // the per-spoke binary search pays off on long rows only
+    // cutting spoke rows at the hub row's largest label skips probes that
+    // cannot match (in cell order a spoke's row runs past the hub's reach);
+    // a binary search per spoke, so not for short rows
     if (const char *et = getenv("GS_TRUNC")) p.trunc = atoi(et) != 0;
-    else p.trunc = maxdeg >= 1024;
+    else if (tune.trunc >= 0) p.trunc = tune.trunc != 0;
+    else p.trunc = maxdeg >= 32;
     // per-work-group LDS counters while they fit; global atomics beyond
     const bool lds_hist_ok = nconf <= 8192;
     int want = nb <= kLutMaxBins ? kLut : kRank;
@@ -1484,6 +1488,7 @@ void tune3(Ctx &ctx, const Graph &g, bool weighted, gs_plan3 *out) {
     cur.tmax = (int)P0.tmax;
     cur.mode = P0.mode;
     cur.hload = P0.hload;
+    cur.trunc = P0.trunc;
     cur.group = packed && nb <= 64 && !wide ? kMaxGroup : 1;
 
     // the sample: every hub when a full count takes under ~30 ms, else a
@@ -1550,6 +1555,12 @@ void tune3(Ctx &ctx, const Graph &g, bool weighted, gs_plan3 *out) {
             t.hload = cur.hload == 5 ? 7 : 5;
             consider(t);
         }
+        // spoke-row truncation
+        {
+            Tune3 t = cur;
+            t.trunc = cur.trunc ? 0 : 1;
+            consider(t);
+        }
         // step table and work-group size
         for (int f : {2, 4}) {
             Tune3 t = cur;
@@ -1575,6 +1586,7 @@ void tune3(Ctx &ctx, const Graph &g, bool weighted, gs_plan3 *out) {
         out->table = cur.tmax;
         out->counters = cur.mode;
         out->hash_load = cur.hload;
+        out->truncate = cur.trunc;
         out->trials = trials;
         out->sample_ms = best;
         out->default_ms = t0;

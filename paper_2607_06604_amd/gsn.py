@@ -68,7 +68,7 @@ class Timings(ctypes.Structure):
 class Plan3(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("step_log2", ctypes.c_int32), ("group", ctypes.c_int32),
                 ("table", ctypes.c_int32), ("counters", ctypes.c_int32), ("hash_load", ctypes.c_int32),
-                ("trials", ctypes.c_int32),
+                ("truncate", ctypes.c_int32), ("trials", ctypes.c_int32),
                 ("sample_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
                 ("sample_frac", ctypes.c_double)]
 

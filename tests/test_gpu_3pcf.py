@@ -263,13 +263,13 @@ def test_invalid_inputs_rejected(ctx, gsn):
 
 
 KERNEL_PLANS = [
-    {"GS_BLOCK3": "256", "GS_GLOG": "0"},
+    {"GS_BLOCK3": "256", "GS_GLOG": "0", "GS_TRUNC": "0"},
     {"GS_BLOCK3": "256", "GS_GLOG": "2", "GS_TRUNC": "1"},
     {"GS_BLOCK3": "256", "GS_GLOG": "4", "GS_TMAX": "64", "GS_MODE3": "lut"},
     {"GS_BLOCK3": "512", "GS_GLOG": "3", "GS_PACK": "0"},
     {"GS_BLOCK3": "512", "GS_GLOG": "6", "GS_MODE3": "rank", "GS_TMAX": "100"},
     {"GS_BLOCK3": "256", "GS_GLOG": "1", "GS_PACK": "0", "GS_MODE3": "rank", "GS_TRUNC": "1"},
-    {"GS_BLOCK3": "256", "GS_GLOG": "3", "GS_PACK": "0", "GS_MODE3": "lut"},
+    {"GS_BLOCK3": "256", "GS_GLOG": "3", "GS_PACK": "0", "GS_MODE3": "lut", "GS_TRUNC": "0"},
     {"GS_BLOCK3": "256", "GS_GLOG": "3", "GS_WIDE": "1"},
     {"GS_BLOCK3": "512", "GS_GLOG": "5", "GS_WIDE": "1", "GS_PACK": "0", "GS_TRUNC": "1"},
 ]
@@ -332,7 +332,7 @@ def test_autotuned_schedule_counts_identical(gsn):
         say("plan", plan)
         assert plan["block"] in (256, 512) and 0 <= plan["step_log2"] <= 6
         assert 1 <= plan["group"] <= 4 and plan["counters"] in (0, 1, 2) and plan["table"] >= 64
-        assert plan["hash_load"] in (5, 7)
+        assert plan["hash_load"] in (5, 7) and plan["truncate"] in (0, 1)
         assert plan["trials"] >= 2 and 0 < plan["sample_ms"] <= plan["default_ms"] * 1.0001
         assert 0 < plan["sample_frac"] <= 1
         got = c.count_3pcf(g)
