@@ -407,7 +407,7 @@ __device__ __forceinline__ void walk3_any(bool packed, int mode, const Walk &c, 
 
 // Plain unbatched counts fit 64 VGPRs: eight wavefronts per SIMD.
 template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool BATCH, bool WIDE>
-__global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED || BATCH) ? 1 : 8) void k_count3(C3Args a) {
+__global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count3(C3Args a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const uint32_t H = 1u << a.log2h, mask = H - 1;
     const Layout3 L = layout3(BLOCK, H, a.maxdeg, a.tcap, a.nconf, a.nb, WEIGHTED, ANCHORED, LDS_HIST,
