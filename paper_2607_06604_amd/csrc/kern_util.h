@@ -98,17 +98,6 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Position of the r-th set bit (r < popcount(w)).
-__device__ __forceinline__ int select_bit(uint32_t w, int r) {
-    int pos = 0, c;
-    c = __popc(w & 0xFFFFu); if (r >= c) { r -= c; w >>= 16; pos += 16; }
-    c = __popc(w & 0xFFu);   if (r >= c) { r -= c; w >>= 8;  pos += 8; }
-    c = __popc(w & 0xFu);    if (r >= c) { r -= c; w >>= 4;  pos += 4; }
-    c = __popc(w & 0x3u);    if (r >= c) { r -= c; w >>= 2;  pos += 2; }
-    c = __popc(w & 0x1u);    if (r >= c) { pos += 1; }
-    return pos;
-}
-
 // Largest k in [0, n) with pref[k] <= x, given pref[n] > x and pref non-decreasing.
 __device__ __forceinline__ uint32_t upper_index(const uint32_t *pref, uint32_t n, uint32_t x) {
     uint32_t lo = 0, hi = n;
