@@ -40,6 +40,7 @@ struct C4Args {
     double L, half;
     double in_lo, in_hi;   // hubs with every coordinate in [in_lo, in_hi] see no wrapped pair
     double eb;             // margin on a shared triple product (interior hubs)
+    double tk[16];         // t_1 .. t_15 (bins of up to 16 counted against them directly)
     uint32_t anchor_lo, anchor_hi;
     uint64_t flush_limit;
     uint32_t *queue;
@@ -200,6 +201,7 @@ struct Stage4 {
     int nb, nconf;
     double L, half;
     double eb;                    // shared triple product margin
+    const double *tk;             // t_1 .. t_15 in the kernel arguments (nb <= 16)
 };
 
 // The four hubs of the clique {i, va, vb, vc}: each hub's spokes are the
@@ -219,7 +221,23 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t va, uint32
     const P3 ac{sep<WRAP>(A.x, C.x, S.L, S.half), sep<WRAP>(A.y, C.y, S.L, S.half), sep<WRAP>(A.z, C.z, S.L, S.half)};
     const P3 bcv{sep<WRAP>(B.x, C.x, S.L, S.half), sep<WRAP>(B.y, C.y, S.L, S.half), sep<WRAP>(B.z, C.z, S.L, S.half)};
     const double qab = sq_len(ab.x, ab.y, ab.z), qac = sq_len(ac.x, ac.y, ac.z), qbc = sq_len(bcv.x, bcv.y, bcv.z);
-    const int bab = bin_of(S.thr, S.nb, qab), bac = bin_of(S.thr, S.nb, qac), bbc = bin_of(S.thr, S.nb, qbc);
+    int bab, bac, bbc;
+    if (S.nb <= 16) {
+        // the bin is the number of thresholds t_1..t_{nb-1} at most q
+        bab = bac = bbc = 0;
+#pragma unroll
+        for (int k = 0; k < 15; ++k)
+            if (k + 1 < S.nb) {
+                const double t = S.tk[k];
+                bab += qab >= t;
+                bac += qac >= t;
+                bbc += qbc >= t;
+            }
+    } else {
+        bab = bin_of(S.thr, S.nb, qab);
+        bac = bin_of(S.thr, S.nb, qac);
+        bbc = bin_of(S.thr, S.nb, qbc);
+    }
     int idx, ch;
     if (!WRAP) {
         const double Vc = triple(ia, ib, ic);
@@ -302,7 +320,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint64_t acc = 0;
     HubCursor cursor;   // thread 0's claimed run of hubs
     const double Lb = a.L, half = a.half;
-    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, hist, a.nb, a.nconf, a.L, a.half, a.eb};
+    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, hist, a.nb, a.nconf, a.L, a.half, a.eb, a.tk};
 
     while (true) {
         if (tid == 0) *s_hub = next_hub_in(a.queue, 0, a.n, gridDim.x, cursor, 1);
@@ -573,6 +591,7 @@ void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_
     a.maxdeg = maxdeg;
     a.L = g.box;
     a.half = 0.5 * g.box;
+    for (int k = 0; k < 16; ++k) a.tk[k] = g.bins.t[std::min(k + 1, nb)];
     // Hubs at least rmax (with margin) from every face: their clique
     // vertices lie within rmax of the hub, hence unwrapped, and any two of
     // them within 2 rmax < L/2 of each other, so no separation among them
