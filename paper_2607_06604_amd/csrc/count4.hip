@@ -39,7 +39,7 @@ struct C4Args {
     uint32_t maxdeg;
     double L, half;
     double in_lo, in_hi;   // hubs with every coordinate in [in_lo, in_hi] see no wrapped pair
-    double eb;             // margin on a shared triple product (interior hubs)
+    double eb_in, eb_wrap; // margins on the shared triple product (interior hubs, the others)
     double tk[16];         // t_1 .. t_15 (bins of up to 16 counted against them directly)
     uint32_t anchor_lo, anchor_hi;
     uint64_t flush_limit;
@@ -92,18 +92,6 @@ struct P3 {
 
 __device__ __forceinline__ P3 neg(const P3 &v) { return P3{-v.x, -v.y, -v.z}; }
 
-// Separation xb - xa under the minimum image. WRAP false: the caller knows
-// no wrap applies (|xb - xa| <= L/2), so the plain difference is the same
-// value. Branch-free: subtracting -L is adding L, and subtracting 0 leaves
-// the value unchanged, so this is bitwise the definition's result.
-template <bool WRAP>
-__device__ __forceinline__ double sep(double xa, double xb, double L, double half) {
-    const double d = __dsub_rn(xb, xa);
-    if (!WRAP) return d;
-    const double off = d > half ? L : (d < -half ? -L : 0.0);
-    return __dsub_rn(d, off);
-}
-
 // (u x v) . w, the cross product then the dot product in the definition's
 // operation order.
 __device__ __forceinline__ double triple(const P3 &u, const P3 &v, const P3 &w) {
@@ -146,22 +134,24 @@ __device__ __forceinline__ int hub_channel(const P3 &P, const P3 &Q, const P3 &R
     return degen ? 2 : ((V > 0.0) == up ? 0 : 1);
 }
 
-// One hub of a clique whose separations none wrap, decided from Vc, the
-// triple product (ia x ib) . ic of hub i's spokes in label order, where that
-// is safe. In exact arithmetic every hub's sorted triple product is +-T (T
-// the signed volume times 6): the hub's spokes P, Q, R are differences of the
-// same four points, so (P x Q) . R is T for hubs i and b and -T for hubs a
-// and c (sign0), and sorting the spokes multiplies it by the parity of the
-// sorting permutation. Every spoke is the exact difference rounded once
-// (no wrap), and evaluating a triple product rounds each of its few terms
-// once; both the definition's value for this hub and Vc are therefore
-// within a small multiple of the unit roundoff times the product of the
-// spoke lengths (at most rmax^3) of +-T. eb bounds twice the sum of the two
-// errors, so when |Vc| - eb already squares above the hub's limit the
-// definition's value does too and carries the predicted sign, and when
-// |Vc| + eb squares below it the hub is degenerate. Otherwise (a clique
-// within rounding of coplanar, or of the threshold) the hub is evaluated
-// exactly as the definition says. Ties in length are decided exactly.
+// One hub of a clique decided from Vc, the triple product (ia x ib) . ic of
+// hub i's spokes in label order, where that is safe. In exact arithmetic
+// every hub's sorted triple product is +-T (T the signed volume times 6):
+// with 4 rmax below the box size all separations are differences of the same
+// four points, so (P x Q) . R of the hub's spokes in the order given is T for
+// hubs i and b and -T for hubs a and c (sign0), and sorting the spokes
+// multiplies it by the parity of the sorting permutation. Every spoke
+// component is the exact difference rounded once (error at most u, the unit
+// roundoff, times the component; where it wraps, at most u times the box
+// size, the correction by L being exact), and evaluating a triple product
+// rounds each of its few terms once: the definition's value for this hub and
+// Vc both lie within a small multiple of u rmax^3 (plus u L rmax^2 near the
+// faces) of +-T. eb is at least twice the sum of the two bounds, so when
+// |Vc| - eb already squares above the hub's limit the definition's value
+// does too and carries the predicted sign, and when |Vc| + eb squares below
+// it the hub is degenerate. Otherwise (a clique within rounding of coplanar,
+// or of the threshold, or eb infinite) the hub is evaluated exactly as the
+// definition says. Ties in length are decided exactly.
 __device__ __forceinline__ int hub_channel_shared(const P3 &P, const P3 &Q, const P3 &R, double qP, double qQ,
                                                   double qR, int bP, int bQ, int bR, const int *ta,
                                                   const int *tb, int *idx, double Vc, bool sign0,
@@ -200,15 +190,23 @@ struct Stage4 {
     uint32_t *hist;               // pos | neg | degenerate counters
     int nb, nconf;
     double L, half;
-    double eb;                    // shared triple product margin
     const double *tk;             // t_1 .. t_15 in the kernel arguments (nb <= 16)
 };
 
+// The minimum-image correction of a plain difference d.
+__device__ __forceinline__ double wrap1(double d, double L, double half) {
+    return d > half ? __dsub_rn(d, L) : (d < -half ? __dadd_rn(d, L) : d);
+}
+
 // The four hubs of the clique {i, va, vb, vc}: each hub's spokes are the
 // separations to the other three (the hub's own spokes negated where the
-// clique's edge points towards it).
-template <bool WRAP>
-__device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t va, uint32_t vb, uint32_t vc) {
+// clique's edge points towards it), decided from one shared triple product
+// with margin eb where it allows. wrap: the hub is near a face, so a
+// separation may need its minimum-image correction (applied after the plain
+// difference, as the definition does; elsewhere none can apply and the plain
+// difference is the value).
+__device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t va, uint32_t vb, uint32_t vc, double eb,
+                                            bool wrap) {
     const P3 A{S.px[va], S.py[va], S.pz[va]};
     const P3 B{S.px[vb], S.py[vb], S.pz[vb]};
     const P3 C{S.px[vc], S.py[vc], S.pz[vc]};
@@ -217,9 +215,15 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t va, uint32
     const P3 ic{S.sx[vc], S.sy[vc], S.sz[vc]};
     const double qa = S.pq[va], qb = S.pq[vb], qc = S.pq[vc];
     const int ba = S.pb[va], bb = S.pb[vb], bc = S.pb[vc];
-    const P3 ab{sep<WRAP>(A.x, B.x, S.L, S.half), sep<WRAP>(A.y, B.y, S.L, S.half), sep<WRAP>(A.z, B.z, S.L, S.half)};
-    const P3 ac{sep<WRAP>(A.x, C.x, S.L, S.half), sep<WRAP>(A.y, C.y, S.L, S.half), sep<WRAP>(A.z, C.z, S.L, S.half)};
-    const P3 bcv{sep<WRAP>(B.x, C.x, S.L, S.half), sep<WRAP>(B.y, C.y, S.L, S.half), sep<WRAP>(B.z, C.z, S.L, S.half)};
+    P3 ab{__dsub_rn(B.x, A.x), __dsub_rn(B.y, A.y), __dsub_rn(B.z, A.z)};
+    P3 ac{__dsub_rn(C.x, A.x), __dsub_rn(C.y, A.y), __dsub_rn(C.z, A.z)};
+    P3 bcv{__dsub_rn(C.x, B.x), __dsub_rn(C.y, B.y), __dsub_rn(C.z, B.z)};
+    if (wrap) {
+        const double L = S.L, h = S.half;
+        ab = P3{wrap1(ab.x, L, h), wrap1(ab.y, L, h), wrap1(ab.z, L, h)};
+        ac = P3{wrap1(ac.x, L, h), wrap1(ac.y, L, h), wrap1(ac.z, L, h)};
+        bcv = P3{wrap1(bcv.x, L, h), wrap1(bcv.y, L, h), wrap1(bcv.z, L, h)};
+    }
     const double qab = sq_len(ab.x, ab.y, ab.z), qac = sq_len(ac.x, ac.y, ac.z), qbc = sq_len(bcv.x, bcv.y, bcv.z);
     int bab, bac, bbc;
     if (S.nb <= 16) {
@@ -239,27 +243,14 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t va, uint32
         bbc = bin_of(S.thr, S.nb, qbc);
     }
     int idx, ch;
-    if (!WRAP) {
-        const double Vc = triple(ia, ib, ic);
-        ch = hub_channel_shared(ia, ib, ic, qa, qb, qc, ba, bb, bc, S.ta, S.tb, &idx, Vc, true, S.eb);
-        atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
-        ch = hub_channel_shared(neg(ia), ab, ac, qa, qab, qac, ba, bab, bac, S.ta, S.tb, &idx, Vc, false, S.eb);
-        atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
-        ch = hub_channel_shared(neg(ib), neg(ab), bcv, qb, qab, qbc, bb, bab, bbc, S.ta, S.tb, &idx, Vc, true,
-                                S.eb);
-        atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
-        ch = hub_channel_shared(neg(ic), neg(ac), neg(bcv), qc, qac, qbc, bc, bac, bbc, S.ta, S.tb, &idx, Vc,
-                                false, S.eb);
-        atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
-        return;
-    }
-    ch = hub_channel(ia, ib, ic, qa, qb, qc, ba, bb, bc, S.ta, S.tb, &idx);
+    const double Vc = triple(ia, ib, ic);
+    ch = hub_channel_shared(ia, ib, ic, qa, qb, qc, ba, bb, bc, S.ta, S.tb, &idx, Vc, true, eb);
     atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
-    ch = hub_channel(neg(ia), ab, ac, qa, qab, qac, ba, bab, bac, S.ta, S.tb, &idx);
+    ch = hub_channel_shared(neg(ia), ab, ac, qa, qab, qac, ba, bab, bac, S.ta, S.tb, &idx, Vc, false, eb);
     atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
-    ch = hub_channel(neg(ib), neg(ab), bcv, qb, qab, qbc, bb, bab, bbc, S.ta, S.tb, &idx);
+    ch = hub_channel_shared(neg(ib), neg(ab), bcv, qb, qab, qbc, bb, bab, bbc, S.ta, S.tb, &idx, Vc, true, eb);
     atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
-    ch = hub_channel(neg(ic), neg(ac), neg(bcv), qc, qac, qbc, bc, bac, bbc, S.ta, S.tb, &idx);
+    ch = hub_channel_shared(neg(ic), neg(ac), neg(bcv), qc, qac, qbc, bc, bac, bbc, S.ta, S.tb, &idx, Vc, false, eb);
     atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
 }
 
@@ -320,7 +311,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint64_t acc = 0;
     HubCursor cursor;   // thread 0's claimed run of hubs
     const double Lb = a.L, half = a.half;
-    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, hist, a.nb, a.nconf, a.L, a.half, a.eb, a.tk};
+    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, hist, a.nb, a.nconf, a.L, a.half, a.tk};
 
     while (true) {
         if (tid == 0) *s_hub = next_hub_in(a.queue, 0, a.n, gridDim.x, cursor, 1);
@@ -334,8 +325,8 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
         const uint32_t pi = ANCHORED ? a.perm[i] : 0;
         // every vertex of this hub's cliques lies within rmax of the hub and
         // so, away from the faces, no separation among them wraps
-        const bool inner = xi >= a.in_lo && xi <= a.in_hi && yi >= a.in_lo && yi <= a.in_hi &&
-                           zi >= a.in_lo && zi <= a.in_hi;
+        const bool inner = __builtin_amdgcn_readfirstlane((int)(xi >= a.in_lo && xi <= a.in_hi && yi >= a.in_lo &&
+                                                                 yi <= a.in_hi && zi >= a.in_lo && zi <= a.in_hi)) != 0;
 
         // 1. stage the hub's forward row
         for (uint32_t e = tid; e < d; e += BLOCK) {
@@ -487,8 +478,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
                                 ++mine_n;
                                 const uint32_t va = (uint32_t)t & 0xFFFFu, vb = (uint32_t)(t >> 16) & 0xFFFFu,
                                                vc = (uint32_t)(t >> 32);
-                                if (inner) eval_clique<false>(S, va, vb, vc);
-                                else eval_clique<true>(S, va, vb, vc);
+                                eval_clique(S, va, vb, vc, inner ? a.eb_in : a.eb_wrap, !inner);
                                 wave_lds_sync();
                             }
                         }
@@ -501,8 +491,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
                 ++mine_n;
                 const uint32_t va = (uint32_t)t & 0xFFFFu, vb = (uint32_t)(t >> 16) & 0xFFFFu,
                                vc = (uint32_t)(t >> 32);
-                if (inner) eval_clique<false>(S, va, vb, vc);
-                else eval_clique<true>(S, va, vb, vc);
+                eval_clique(S, va, vb, vc, inner ? a.eb_in : a.eb_wrap, !inner);
             }
             mycl += mine_n;
             if (mine_n) atomicAdd(s_round, mine_n);
@@ -600,9 +589,13 @@ void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_
         const double m = g.rmax * (1.0 + 1e-9);
         a.in_lo = m;
         a.in_hi = 4.0 * m < g.box ? g.box - m : -1.0;
-        // twice the summed error bounds of two triple products of spokes no
-        // longer than rmax (each below 70 unit roundoffs times rmax^3)
-        a.eb = 1e-13 * m * m * m;
+        // margins: at least twice the summed error bounds of two triple
+        // products of spokes no longer than rmax, each under 70 u rmax^3,
+        // plus 6 u L rmax^2 where components wrap (u = 2^-53); infinite
+        // (every hub evaluated exactly) unless 4 rmax is below the box size
+        const bool shared = 4.0 * m < g.box;
+        a.eb_in = shared ? 1e-13 * m * m * m : HUGE_VAL;
+        a.eb_wrap = shared ? 1e-13 * m * m * m + 1e-14 * g.box * m * m : HUGE_VAL;
     }
     a.anchor_lo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
     a.anchor_hi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;
