@@ -291,7 +291,9 @@ def main():
     # spreads them over its tile launches, so divide by the count's kernel time
     count_kernel_ms = kern_ms / args.steps
     achieved = alg_bytes / (count_kernel_ms / 1e3) / 1e9 if count_kernel_ms > 0 else 0.0
-    traffic = stored_traffic(args.workload, spec["kind"])
+    # the stored counters were taken on the resident count (one launch); a
+    # host-tiled count spreads the work over per-tile launches
+    traffic = stored_traffic(args.workload, spec["kind"]) if args.windows <= 1 else None
     if spec["kind"] == "4pcf":
         # float64 arithmetic per clique (separations, squared lengths, four hub
         # volumes and thresholds; no fused multiply-add) against the non-fused
