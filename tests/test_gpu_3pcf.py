@@ -349,3 +349,30 @@ def test_autotuned_schedule_counts_identical(gsn):
             c.tune_3pcf(c.build_graph(x, L, 0.0, rmax, nb), weighted=True)
         assert e.value.code == gsn.GS_EINVAL
         gw.free()
+
+
+def test_reused_device_blocks_give_exact_graphs(gsn):
+    """A context hands a released graph's device blocks to later builds
+    (stale contents included): a smaller catalogue built into a larger one's
+    blocks, two graphs alive at once, and a graph released after its context
+    all count exactly."""
+    L, rmax, nb = 30.0, 2.4, 6
+    big = synth.neyman_scott(12_000, 25, 0.8, L, 401)
+    small = synth.uniform(5_000, L, 402)
+    other = synth.uniform(7_000, L, 403)
+    ref_small = oracle.count_3pcf(small, L, 0.0, rmax, nb)
+    ref_other = oracle.count_3pcf(other, L, 0.0, rmax, nb)
+    with gsn.Context(0) as c:
+        for _ in range(2):
+            g = c.build_graph(big, L, 0.0, rmax, nb)
+            g.free()
+            g = c.build_graph(small, L, 0.0, rmax, nb)
+            h = c.build_graph(other, L, 0.0, rmax, nb)
+            got_s, got_o = c.count_3pcf(g), c.count_3pcf(h)
+            assert np.array_equal(got_s.hist, ref_small.hist) and got_s.n_triangles == ref_small.n_triangles
+            assert np.array_equal(got_o.hist, ref_other.hist) and got_o.n_triangles == ref_other.n_triangles
+            g.free()
+            h.free()
+        late = c.build_graph(small, L, 0.0, rmax, nb)
+        assert np.array_equal(c.count_3pcf(late).hist, ref_small.hist)
+    late.free()   # after the context: its blocks are released with the graph
