@@ -7,8 +7,8 @@
  * baseline do. It shares no code, header or table with the GPU library.
  *
  * It is deliberately plain and slow: full symmetric neighbour rows from a
- * cell list, then for every hub the v1-style membership test by binary
- * search (paper Sec. 2.2: "a binary search on N(j), costing O(log m)"), not
+ * cell list, then for every hub the original membership test of Sec. 2.2 (a
+ * binary search in the spoke's sorted row, logarithmic per candidate), not
  * the merge-walk the paper introduces in Sec. 3.1. The counts it produces are
  * the plain definitions below; the merge-walk reaches the same sets faster.
  *

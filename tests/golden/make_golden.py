@@ -65,7 +65,25 @@ def lognormal_w3pcf_sampled():
                 samples=out, oracle_seconds=round(time.time() - t, 1))
 
 
-TARGETS = {"ns_3pcf_full": ns_3pcf_full, "ns_4pcf_parity_sampled": ns_4pcf_parity_sampled,
+def stream_served():
+    """Serving-stream catalogues (periodic 600 Mpc/h boxes, rmax 40, 10 bins;
+    even index clustered, odd index uniform), a spread of sizes from 5e4 to
+    2.5e5 points, each counted in full."""
+    L, rmax, nb = 600.0, 40.0, 10
+    sizes = synth.stream_sizes(256, seed=5)
+    picks = [1, 16, 18, 31, 80, 88, 121, 161, 162, 165, 197, 201, 212, 240]
+    out = []
+    t = time.time()
+    for k in picks:
+        x = synth.stream_catalogue(k, int(sizes[k]), L=L, seed=5)
+        r = oracle.count_3pcf(x, L, 0.0, rmax, nb)
+        out.append(dict(index=k, n=int(sizes[k]), xyz_sha256=digest(x), n_triangles=r.n_triangles,
+                        hist=[int(v) for v in r.hist]))
+    return dict(workload="stream_3pcf", box=L, rmin=0.0, rmax=rmax, nbins=nb, seed=5,
+                catalogues=out, oracle_seconds=round(time.time() - t, 1))
+
+
+TARGETS = {"ns_3pcf_full": ns_3pcf_full, "stream_served": stream_served, "ns_4pcf_parity_sampled": ns_4pcf_parity_sampled,
            "lognormal_w3pcf_sampled": lognormal_w3pcf_sampled}
 
 if __name__ == "__main__":

@@ -214,3 +214,45 @@ def test_count3_forced_flushes_identical(ctx, monkeypatch):
     got = ctx.count_3pcf(g, weighted=True)
     g.free()
     assert np.array_equal(got.hist, ref.hist) and got.wsum_int() == ref.wsum_int()
+
+
+# hand-derived degenerate-rule units (tests/golden/degenerate_units.json)
+from tests import units as _units  # noqa: E402
+
+
+@pytest.mark.parametrize("k_exp", [None, -30, 30, -29, 29, -28, 28])
+def test_degenerate_rule_units_gpu(ctx, k_exp):
+    g = _golden("degenerate_units.json")
+    L, rmin, rmax, nb = g["box"], g["rmin"], g["rmax"], g["nbins"]
+    lifted = g["lifted"]
+    names = ["O", "A", "B", "C"]
+    if k_exp is None:
+        off, signs = _units.offsets(g["coplanar"], names), {}
+    else:
+        eps = float(np.sign(k_exp)) * 2.0 ** (-abs(k_exp))
+        off = _units.offsets(g["coplanar"], names, lift=lifted["lift_vertex"], eps=eps)
+        signs = {h: int(np.sign(k_exp)) * lifted["signs_eps_positive"][h]
+                 for h in lifted["signed_hubs"][str(-abs(k_exp))]}
+    n_units = 300      # interior units and units near the box faces
+    x = _units.place([off] * n_units, L)
+    say("degenerate units", k_exp, len(x))
+    got = gpu4(ctx, x, L, rmin, rmax, nb)
+    even, odd = _units.expected_parity(nb, oracle.config_index, g["coplanar"]["hub_configs"], signs)
+    assert got.n_cliques == n_units
+    assert np.array_equal(got.even.astype(np.int64), n_units * even)
+    assert np.array_equal(got.odd, n_units * odd)
+    assert int(got.pos.sum() + got.neg.sum()) == n_units * int(np.abs(odd).sum())
+    same(got, oracle.count_4pcf_parity(x, L, rmin, rmax, nb))
+
+
+def test_degenerate_rule_zero_length_spoke_gpu(ctx):
+    g = _golden("degenerate_units.json")
+    L, rmin, rmax, nb = g["box"], g["rmin"], g["rmax"], g["nbins"]
+    c = g["coincident"]
+    x = _units.place([_units.offsets(c, ["P", "Q", "X", "Y"])] * 200, L)
+    got = gpu4(ctx, x, L, rmin, rmax, nb)
+    even, _ = _units.expected_parity(nb, oracle.config_index, c["hub_configs"], {})
+    assert got.n_cliques == 200
+    assert np.array_equal(got.even.astype(np.int64), 200 * even)
+    assert got.pos.sum() == 0 and got.neg.sum() == 0
+    same(got, oracle.count_4pcf_parity(x, L, rmin, rmax, nb))

@@ -49,6 +49,11 @@ def catalogues(count, seed, lo=2_000, hi=30_000):
     return out
 
 
+def ref3(x, nb=NB):
+    """The oracle's histogram of catalogue x."""
+    return oracle.count_3pcf(x, L, 0.0, RMAX, nb).hist
+
+
 def alone(ctx, x):
     g = ctx.build_graph(x, L, 0.0, RMAX, NB)
     r = ctx.count_3pcf(g)
@@ -66,9 +71,7 @@ def test_batch_matches_individual_and_oracle(ctx):
     for k, x in enumerate(cats):
         a = alone(ctx, x)
         assert got[k].n_triangles == a.n_triangles and np.array_equal(got[k].hist, a.hist)
-        if k < 4:
-            ref = oracle.count_3pcf(x, L, 0.0, RMAX, NB)
-            assert np.array_equal(got[k].hist, ref.hist)
+        assert np.array_equal(got[k].hist, ref3(x))
 
 
 def test_batch_of_one_and_with_empty_catalogue(ctx):
@@ -127,6 +130,7 @@ def test_serving_alone_vs_mix(gsn):
         assert r["status"] == gsn.GS_DONE
         assert r["n_triangles"] == a.n_triangles
         assert np.array_equal(r["hist"], a.hist)
+        assert np.array_equal(r["hist"], ref3(x))
         assert r["t_total_s"] >= r["t_count_s"] >= 0
         steps.append(r["step_size"])
     assert max(steps) > 1, "no request was batched with another"
@@ -157,6 +161,7 @@ def test_serving_failures_cancel_and_unknown(gsn):
         for t, x in zip(ts + tc[:-1], cats[:2] + cats[3:-1]):
             assert res[t]["status"] == gsn.GS_DONE
             assert np.array_equal(res[t]["hist"], alone(c, x).hist)
+            assert np.array_equal(res[t]["hist"], ref3(x))
 
 
 def test_serving_small_budget_admits_one_at_a_time(gsn):
@@ -169,8 +174,9 @@ def test_serving_small_budget_admits_one_at_a_time(gsn):
     with gsn.Context(0, budget_bytes=int(fp * 1.3)) as s:
         ts = [s.submit(x, L, 0.0, RMAX, NB) for x in cats]
         res = drain(s, ts)
-    for t, a in zip(ts, want):
+    for t, a, x in zip(ts, want, cats):
         assert res[t]["status"] == gsn.GS_DONE and np.array_equal(res[t]["hist"], a.hist)
+        assert np.array_equal(res[t]["hist"], ref3(x))
         assert res[t]["step_size"] <= 2
 
 
@@ -197,5 +203,45 @@ def test_serving_mixed_bin_counts(gsn):
                     if r is not None:
                         res[t] = r
             time.sleep(0.002)
-    for t, w in zip(ts, want):
+    for t, w, x, nb in zip(ts, want, cats, nbs):
         assert res[t]["status"] == gsn.GS_DONE and np.array_equal(res[t]["hist"], w)
+        assert np.array_equal(res[t]["hist"], ref3(x, nb))
+
+
+def test_serving_stream_catalogues_against_stored_oracle(gsn):
+    """Catalogues of the serving stream (periodic 600 Mpc/h boxes, 5e4 to
+    2.5e5 points, clustered and uniform, rmax 40, 10 bins), served together
+    with arrivals spread over several steps: every histogram equals the
+    stored oracle count."""
+    import hashlib
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "stream_served.json")))
+    Ls, rmax, nb = gold["box"], gold["rmax"], gold["nbins"]
+    cats = []
+    for c in gold["catalogues"]:
+        x = synth.stream_catalogue(c["index"], c["n"], L=Ls, seed=gold["seed"])
+        assert hashlib.sha256(np.ascontiguousarray(x).tobytes()).hexdigest() == c["xyz_sha256"]
+        cats.append(x)
+    with gsn.Context(0) as s:
+        say("serving stream catalogues", len(cats))
+        ts = []
+        for k, x in enumerate(cats):
+            ts.append(s.submit(x, Ls, 0.0, rmax, nb))
+            if k % 4 == 3:
+                time.sleep(0.01)
+        res = {}
+        t0 = time.time()
+        while len(res) < len(ts):
+            assert time.time() - t0 < 120.0, "serving did not finish"
+            for t in ts:
+                if t not in res:
+                    r = s.poll(t, nb)
+                    if r is not None:
+                        res[t] = r
+            time.sleep(0.002)
+    for t, c in zip(ts, gold["catalogues"]):
+        assert res[t]["status"] == gsn.GS_DONE
+        assert res[t]["n_triangles"] == c["n_triangles"]
+        assert res[t]["hist"].tolist() == c["hist"]

@@ -426,3 +426,61 @@ def test_sum_over_bins_invariants():
     # parity-symmetric field: odd channel consistent with zero
     tot = float(r4.pos.sum() + r4.neg.sum())
     assert abs(float(r4.pos.sum()) - float(r4.neg.sum())) < 4 * math.sqrt(max(tot, 1.0)) * 2
+
+
+# ------------------------------------------------- degenerate-volume rule ----
+# Hand-derived units (tests/golden/degenerate_units.json): a scalene coplanar
+# unit (V = 0 exactly, no length ties), the same unit lifted off its plane by
+# dyadic eps on both sides of each hub's 1e-9 normalised-volume limit, and a
+# coincident pair (a zero-length spoke, decided by the rule's '<=').
+
+from tests import units as _units  # noqa: E402
+
+_COPLANAR = ["O", "A", "B", "C"]
+
+
+def _degenerate_case(golden_dir, k_exp, n_units=5):
+    g = _golden(golden_dir, "degenerate_units.json")
+    L, rmin, rmax, nb = g["box"], g["rmin"], g["rmax"], g["nbins"]
+    lifted = g["lifted"]
+    if k_exp is None:
+        off, signs = _units.offsets(g["coplanar"], _COPLANAR), {}
+    else:
+        eps = float(np.sign(k_exp)) * 2.0 ** (-abs(k_exp))
+        off = _units.offsets(g["coplanar"], _COPLANAR, lift=lifted["lift_vertex"], eps=eps)
+        signed = lifted["signed_hubs"][str(-abs(k_exp))]
+        signs = {h: int(np.sign(k_exp)) * lifted["signs_eps_positive"][h] for h in signed}
+    x = _units.place([off] * n_units, L)
+    even, odd = _units.expected_parity(nb, oracle.config_index, g["coplanar"]["hub_configs"], signs)
+    tri = _units.expected_triangles(nb, oracle.config_index, g["coplanar"]["triangle_configs"])
+    return x, (L, rmin, rmax, nb), n_units * even, n_units * odd, n_units * tri
+
+
+@pytest.mark.parametrize("k_exp", [None, -30, 30, -29, 29, -28, 28],
+                         ids=["coplanar", "eps-2^-30", "eps+2^-30", "eps-2^-29", "eps+2^-29",
+                              "eps-2^-28", "eps+2^-28"])
+def test_degenerate_rule_coplanar_and_lifted_units(golden_dir, k_exp):
+    x, (L, rmin, rmax, nb), even, odd, tri = _degenerate_case(golden_dir, k_exp)
+    r = oracle.count_4pcf_parity(x, L, rmin, rmax, nb)
+    assert r.n_cliques == 5
+    assert np.array_equal(r.even.astype(np.int64), even)
+    assert np.array_equal(r.odd, odd)
+    # every non-zero odd entry is a single signed hub, never both channels
+    assert int(r.pos.sum() + r.neg.sum()) == int(np.abs(odd).sum())
+    r3 = oracle.count_3pcf(x, L, rmin, rmax, nb)
+    assert np.array_equal(r3.hist.astype(np.int64), tri)
+
+
+def test_degenerate_rule_zero_length_spoke(golden_dir):
+    g = _golden(golden_dir, "degenerate_units.json")
+    L, rmin, rmax, nb = g["box"], g["rmin"], g["rmax"], g["nbins"]
+    c = g["coincident"]
+    x = _units.place([_units.offsets(c, ["P", "Q", "X", "Y"])] * 4, L)
+    even, odd = _units.expected_parity(nb, oracle.config_index, c["hub_configs"], {})
+    r = oracle.count_4pcf_parity(x, L, rmin, rmax, nb)
+    assert r.n_cliques == 4
+    assert np.array_equal(r.even.astype(np.int64), 4 * even)
+    assert r.pos.sum() == 0 and r.neg.sum() == 0
+    r3 = oracle.count_3pcf(x, L, rmin, rmax, nb)
+    assert np.array_equal(r3.hist.astype(np.int64),
+                          4 * _units.expected_triangles(nb, oracle.config_index, c["triangle_configs"]))
