@@ -93,6 +93,9 @@ typedef struct {
     uint64_t alg_bytes;      /* 2.5 B x sum_sq_degree of the counted graph(s), the
                                 bytes a merge walk reads; 0 until gs_graph_info
                                 has computed the degree statistics               */
+    uint64_t probes;         /* last triangle count: candidates its hash probes
+                                tested (spoke-row entries up to the hub row's
+                                largest label)                                    */
 } gs_timings;
 
 /* Create a context on HIP device `device`. hbm_budget_bytes = 0 means 90% of
@@ -194,37 +197,59 @@ typedef struct {
 
 int gs_tune_3pcf(gs_ctx *ctx, const gs_graph *g, uint32_t flags, gs_plan3 *out);
 
-/* ---- serving: continuous batching of triangle-count requests ----
- * gs_submit copies the catalogue and returns a ticket at once. A scheduler
- * thread of the context admits queued requests while device memory (the
- * context budget, checked against each graph's exact footprint once its edge
- * count is known) and batch slots allow, builds their graphs while the
- * previous count step runs, and counts all built graphs in one batched
- * launch per step; requests arriving meanwhile join the next step. Results
- * are identical to a lone gs_build_graph + gs_count_3pcf.
+/* ---- serving: continuous batching of count requests ----
+ * gs_submit copies the catalogue (and its weights) and returns a ticket at
+ * once. A scheduler thread of the context admits queued requests while
+ * device memory (the context budget, checked against each graph's exact
+ * footprint once its edge count is known) and batch slots allow, builds
+ * their graphs while the previous count step runs, and counts every graph
+ * built so far in the next step: plain triangle counts of one bin count in
+ * one batched launch, each weighted triangle count and each parity count as
+ * a count of its own on the same stream; requests arriving meanwhile join
+ * the next step. Results are identical to a lone gs_build_graph followed by
+ * gs_count_3pcf (GS_3PCF) or gs_count_4pcf_parity (GS_4PCF_PARITY).
  * submit / poll / cancel are thread-safe. */
 #define GS_PENDING 1      /* queued, building or counting                       */
 #define GS_DONE 0         /* result available (returned once, then forgotten)   */
 #define GS_FAILED 2       /* request failed: error holds the status code        */
 #define GS_CANCELLED 3
 
+/* request kinds (gs_request.kind) */
+#define GS_3PCF 0          /* binned triangles (Sec. 2.2), optionally weighted   */
+#define GS_4PCF_PARITY 1   /* parity-decomposed 4-cliques (Sec. 3.2)             */
+
 typedef struct {
     const double *xyz;      /* host n x 3 float64, copied by gs_submit          */
     int64_t n;
-    gs_graph_params p;      /* flags must be 0 (host input, unweighted)          */
+    const double *weights;  /* host n float64 > 0, copied; non-NULL iff
+                               p.flags has GS_WEIGHTED (GS_3PCF only)            */
+    gs_graph_params p;      /* flags: 0 or GS_WEIGHTED (host input; parity
+                               requests keep coordinates by themselves)         */
+    int32_t kind;           /* GS_3PCF or GS_4PCF_PARITY                         */
+    int32_t reserved;
 } gs_request;
 
+/* Outputs of a finished request; the caller sets the array pointers (any may
+ * be NULL to skip) before gs_poll, which fills them on GS_DONE:
+ *  hist: u64[C(nbins+2,3)]: triangle counts (GS_3PCF) or the even channel,
+ *    every hub contribution (GS_4PCF_PARITY);
+ *  pos, neg: u64[C(nbins+2,3)] each (GS_4PCF_PARITY), as gs_count_4pcf_parity;
+ *  wsum128: u64[2*C(nbins+2,3)], whist: double[C(nbins+2,3)] and wscale
+ *    (weighted GS_3PCF), as gs_count_3pcf. */
 typedef struct {
     int32_t status;         /* GS_PENDING / GS_DONE / GS_FAILED / GS_CANCELLED   */
     int32_t error;          /* status code when GS_FAILED                        */
-    uint64_t n_triangles;
-    uint64_t *hist;         /* caller-provided u64[C(nbins+2,3)], filled on DONE */
+    uint64_t n_tuples;      /* triangles (GS_3PCF) or 4-cliques (GS_4PCF_PARITY) */
+    uint64_t *hist;
+    uint64_t *pos, *neg;
+    uint64_t *wsum128;
+    double *whist;
+    int32_t wscale;
+    uint32_t step_size;     /* requests counted in the step that held this one   */
     double t_queue_s;       /* submit -> graph build started                     */
     double t_build_s;       /* graph build                                       */
-    double t_count_s;       /* the batched count step that held this request     */
+    double t_count_s;       /* the count step that held this request             */
     double t_total_s;       /* submit -> result ready                            */
-    uint32_t step_size;     /* catalogues counted in that step                   */
-    uint32_t reserved;
 } gs_result;
 
 /* Errors: GS_EINVAL (bad request), GS_EAGAIN (queue full), GS_EUNSUPPORTED. */
@@ -235,6 +260,27 @@ int gs_poll(gs_ctx *ctx, uint64_t ticket, gs_result *out);
 /* Cancel a request not yet finished: it is dropped if still queued, its
  * result discarded if already building or counting. GS_ENOTFOUND if unknown. */
 int gs_cancel(gs_ctx *ctx, uint64_t ticket);
+
+/* ---- attainable ceilings (measurement only; no counting) ----
+ * Rates the device sustains for the work the counting kernels are made of,
+ * timed with HIP events on the context's stream, so that each kernel can be
+ * reported against the ceiling that binds it.
+ * gs_ceiling_copy: a device-to-device copy of `bytes` (>= 1 MiB; the call
+ *   allocates 2 x bytes of device memory for it): *gbs = read + written
+ *   bytes per second / 1e9, best of five.
+ * gs_ceiling_probe: the per-candidate work of the triangle count -- a
+ *   coalesced 4-byte label and 1-byte bin load from an L2-resident array,
+ *   the 24-bit hash, a linear-probe chain in an LDS table of 2^table_log2
+ *   slots holding keys_in_table labels (<= 0.7 of the slots), and for the
+ *   hit_rate fraction of candidates that hit, the counter address from the
+ *   nbins^3 configuration table and one LDS atomic (plus, weighted != 0,
+ *   the weight gather, the exact triangle integer and two u64 LDS atomics).
+ *   probe == 0 skips the hash (every candidate a hit): the LDS-atomic
+ *   histogram ceiling at this bin count. block: 256 or 512 threads.
+ *   *per_s = candidates per second. nbins 1..24. */
+int gs_ceiling_copy(gs_ctx *ctx, uint64_t bytes, double *gbs);
+int gs_ceiling_probe(gs_ctx *ctx, int32_t nbins, uint32_t table_log2, uint32_t keys_in_table,
+                     double hit_rate, int32_t weighted, int32_t probe, int32_t block, double *per_s);
 
 /* Device timings of the context's last build / count call. */
 int gs_get_timings(const gs_ctx *ctx, gs_timings *out);

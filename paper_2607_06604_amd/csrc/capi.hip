@@ -411,6 +411,7 @@ int gs_get_timings(const gs_ctx *ctx, gs_timings *out) {
     out->kernel_ms = ctx->t.kernel_ms;
     out->kernel_launches = ctx->t.kernel_launches;
     out->alg_bytes = ctx->t.alg_bytes;
+    out->probes = ctx->t.probes;
     return GS_OK;
 }
 

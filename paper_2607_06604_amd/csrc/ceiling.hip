@@ -1,0 +1,270 @@
+// ceiling.hip - attainable-ceiling microbenchmarks for the counting kernels:
+// the rates the hardware sustains for the work each kernel is made of, so
+// that a kernel is reported against the ceiling that binds it.
+//
+//  copy:  a device-to-device stream copy (16-byte loads and stores, grid
+//         stride): attainable HBM bandwidth, read + written bytes per second.
+//  hist:  one LDS atomic increment per tuple into C(nb+2,3) u32 counters
+//         through the ordered-triple configuration table (two more u64 LDS
+//         atomics per tuple when weighted): attainable binned tuples/s.
+//  probe: the per-candidate work of the triangle count's intersection
+//         (Sec. 3.1 done as hash probes): a coalesced 5-byte candidate load
+//         from an L2-resident array, the 24-bit hash, a linear-probe chain in
+//         an LDS table loaded like a hub group's, and on a hit the counter
+//         address from the configuration table and its LDS atomic (plus the
+//         weighted triangle's exact integer and its two u64 atomics):
+//         attainable candidates/s with perfect balance and no scheduling.
+// None of these counts anything; each keeps its result live through a sink.
+#include <cstdio>
+#include <cstdlib>
+
+#include "kern_util.h"
+
+namespace gsn {
+namespace {
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void k_ceil_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+__global__ void k_ceil_fill(uint32_t *__restrict__ keys, uint8_t *__restrict__ bins, double *__restrict__ w,
+                            uint32_t n, uint32_t universe, uint32_t nw, int nb) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        keys[i] = mix32(i * 2u + 1u) % universe;
+        bins[i] = (uint8_t)(mix32(i ^ 0x5bd1e995u) % (uint32_t)nb);
+    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += gridDim.x * blockDim.x)
+        w[i] = 0.5 + (double)mix32(i + 12345u) * 0x1.0p-32;
+}
+
+struct CeilArgs {
+    const uint32_t *keys;   // candidate labels (L2-resident, length mask + 1)
+    const uint8_t *bins;    // candidate row bins
+    const double *w;        // weights by label
+    uint32_t mask;          // array length - 1 (power of two)
+    uint64_t per_group;     // candidates per work group
+    int log2h;              // LDS table of 2^log2h slots
+    uint32_t K;             // keys held in the table (labels 0 .. K-1)
+    int nb, nconf;
+    double wmul;
+    unsigned long long *sink;
+};
+
+constexpr int kCeilU = 4;
+
+// LDS: configuration-table counter addresses (u16, nb^3) | counters (u32,
+// nconf) | u64 halves (weighted) | hash table (u32, packed bin << 26 | key).
+template <int BLOCK, bool PROBE, bool WEIGHTED>
+__global__ __launch_bounds__(BLOCK) void k_ceil_probe(CeilArgs a) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    const int nb = a.nb, n3 = nb * nb * nb;
+    const uint32_t H = 1u << a.log2h, hmask = H - 1;
+    uint16_t *lut = (uint16_t *)sm;
+    const uint32_t o_hist = lds_align(2 * n3, 16);
+    uint32_t *hist = (uint32_t *)(sm + o_hist);
+    const uint32_t o_wlo = lds_align(o_hist + 4 * a.nconf, 16);
+    unsigned long long *wlo = (unsigned long long *)(sm + o_wlo);
+    const uint32_t o_whi = o_wlo + (WEIGHTED ? 8 * a.nconf : 0);
+    unsigned long long *whi = (unsigned long long *)(sm + o_whi);
+    const uint32_t o_tab = lds_align(o_whi + (WEIGHTED ? 8 * a.nconf : 0), 16);
+    uint32_t *tab = (uint32_t *)(sm + o_tab);
+    const uint32_t smb = lds_addr(sm);
+    const int tid = threadIdx.x;
+
+    for (int t = tid; t < n3; t += BLOCK) {
+        const int x = t / (nb * nb), y = (t / nb) % nb, z = t % nb;
+        const int lo = min(x, min(y, z)), hi = max(x, max(y, z)), mid = x + y + z - lo - hi;
+        lut[t] = (uint16_t)(smb + o_hist + 4 * (rank_a(nb, lo) + rank_b(nb, mid) + hi));
+    }
+    for (int b = tid; b < a.nconf; b += BLOCK) {
+        hist[b] = 0;
+        if (WEIGHTED) { wlo[b] = 0; whi[b] = 0; }
+    }
+    for (uint32_t s = tid; s < H; s += BLOCK) tab[s] = kEmptyKey;
+    __syncthreads();
+    if (PROBE)
+        for (uint32_t k = tid; k < a.K; k += BLOCK) {
+            uint32_t s = (((k & 0xFFFFFFu) * 0x9E3779u) & 0xFFFFFFu) >> (24 - a.log2h);
+            const uint32_t v = ((k % (uint32_t)nb) << 26) | k;
+            while (atomicCAS(&tab[s], kEmptyKey, v) != kEmptyKey) s = (s + 1) & hmask;
+        }
+    __syncthreads();
+
+    const uint64_t base = (uint64_t)blockIdx.x * 7919ull * BLOCK;
+    const double hw = a.w[blockIdx.x & 1023];
+    for (uint64_t i0 = 0; i0 < a.per_group; i0 += (uint64_t)kCeilU * BLOCK) {
+        uint32_t kk[kCeilU], zz[kCeilU], xx[kCeilU], hh[kCeilU], kv[kCeilU];
+        // the spoke's bin: one per pass of the work group (uniform)
+        const uint32_t xs = (uint32_t)((i0 >> 10) % (uint64_t)nb);
+#pragma unroll
+        for (int u = 0; u < kCeilU; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * BLOCK + tid;
+            const uint32_t idx = (uint32_t)(base + i) & a.mask;
+            kk[u] = a.keys[idx];
+            zz[u] = a.bins[idx];
+            xx[u] = xs;
+        }
+        bool hit[kCeilU];
+        uint32_t yy[kCeilU];
+#pragma unroll
+        for (int u = 0; u < kCeilU; ++u) {
+            if (PROBE) {
+                hh[u] = (((kk[u] & 0xFFFFFFu) * 0x9E3779u) & 0xFFFFFFu) >> (24 - a.log2h);
+                kv[u] = tab[hh[u]];
+            } else {
+                hit[u] = true;
+                yy[u] = kk[u] % (uint32_t)nb;
+            }
+        }
+        if (PROBE) {
+#pragma unroll
+            for (int u = 0; u < kCeilU; ++u) {
+                uint32_t h = hh[u], v = kv[u];
+                while (((v ^ kk[u]) & 0x3FFFFFFu) != 0 && v != kEmptyKey) {
+                    h = (h + 1) & hmask;
+                    v = tab[h];
+                }
+                hit[u] = v != kEmptyKey;
+                yy[u] = v >> 26;
+            }
+        }
+        double wk[kCeilU];
+#pragma unroll
+        for (int u = 0; u < kCeilU; ++u) wk[u] = (WEIGHTED && hit[u]) ? a.w[kk[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kCeilU; ++u) {
+            if (!hit[u]) continue;
+            const uint32_t addr = lut[(xx[u] * (uint32_t)nb + yy[u]) * (uint32_t)nb + zz[u]];
+            __hip_atomic_fetch_add((lds_u32 *)(size_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (WEIGHTED) {
+                double p = hw, q = a.w[xx[u]], r = wk[u], t;
+                if (p > q) { t = p; p = q; q = t; }
+                if (q > r) { t = q; q = r; r = t; }
+                if (p > q) { t = p; p = q; q = t; }
+                const unsigned long long ti = (unsigned long long)__dmul_rn(__dmul_rn(__dmul_rn(p, q), r), a.wmul);
+                const uint32_t idx = (addr - (smb + o_hist)) >> 2;
+                atomicAdd(&wlo[idx], ti & 0xFFFFFFFFull);
+                atomicAdd(&whi[idx], ti >> 32);
+            }
+        }
+    }
+    __syncthreads();
+    unsigned long long s = 0;
+    for (int b = tid; b < a.nconf; b += BLOCK) s += hist[b] + (WEIGHTED ? (wlo[b] ^ whi[b]) : 0ull);
+    if (s) atomicAdd(a.sink, s);
+}
+
+template <int BLOCK, bool PROBE, bool WEIGHTED>
+double run_probe(Ctx &ctx, const CeilArgs &a, uint32_t lds) {
+    const void *kern = reinterpret_cast<const void *>(&k_ceil_probe<BLOCK, PROBE, WEIGHTED>);
+    if (lds > 65536) GS_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ceil_probe<BLOCK, PROBE, WEIGHTED>, BLOCK, lds));
+    if (per_cu < 1) fail(GS_EUNSUPPORTED, "ceiling kernel does not fit a compute unit");
+    const uint32_t grid = (uint32_t)ctx.n_cu * (uint32_t)per_cu;
+    hipStream_t s = ctx.stream;
+    // warm-up, then the timed launch
+    CeilArgs w = a;
+    w.per_group = std::max<uint64_t>(kCeilU * BLOCK, a.per_group / 16);
+    k_ceil_probe<BLOCK, PROBE, WEIGHTED><<<grid, BLOCK, lds, s>>>(w);
+    GS_HIP(hipGetLastError());
+    GS_HIP(hipEventRecord(ctx.ev[0], s));
+    k_ceil_probe<BLOCK, PROBE, WEIGHTED><<<grid, BLOCK, lds, s>>>(a);
+    GS_HIP(hipGetLastError());
+    GS_HIP(hipEventRecord(ctx.ev[1], s));
+    GS_HIP(hipEventSynchronize(ctx.ev[1]));
+    float ms = 0;
+    GS_HIP(hipEventElapsedTime(&ms, ctx.ev[0], ctx.ev[1]));
+    return (double)a.per_group * (double)grid / (ms * 1e-3);
+}
+
+}  // namespace
+}  // namespace gsn
+
+using namespace gsn;
+
+extern "C" {
+
+int gs_ceiling_copy(gs_ctx *ctx, uint64_t bytes, double *gbs) {
+    return guarded([&] {
+        if (!ctx || !gbs || bytes < (1u << 20)) fail(GS_EINVAL, "bad argument");
+        ctx->use();
+        const uint64_t n = bytes / 16;
+        DevBuf src(n * 16), dst(n * 16);
+        hipStream_t s = ctx->stream;
+        const uint32_t grid = (uint32_t)ctx->n_cu * 8;
+        k_ceil_fill<<<grid, 256, 0, s>>>(src.as<uint32_t>(), dst.as<uint8_t>(), nullptr, (uint32_t)std::min<uint64_t>(n * 4, 0xFFFFFFFFu), 1u << 30, 0, 1);
+        k_ceil_copy<<<grid, 256, 0, s>>>(src.as<uint4>(), dst.as<uint4>(), n);   // warm-up
+        GS_HIP(hipGetLastError());
+        float best = 1e30f;
+        for (int r = 0; r < 5; ++r) {
+            GS_HIP(hipEventRecord(ctx->ev[0], s));
+            k_ceil_copy<<<grid, 256, 0, s>>>(src.as<uint4>(), dst.as<uint4>(), n);
+            GS_HIP(hipEventRecord(ctx->ev[1], s));
+            GS_HIP(hipEventSynchronize(ctx->ev[1]));
+            float ms = 0;
+            GS_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+            best = std::min(best, ms);
+        }
+        GS_HIP(hipStreamSynchronize(s));
+        *gbs = 2.0 * (double)(n * 16) / (best * 1e-3) / 1e9;
+    });
+}
+
+int gs_ceiling_probe(gs_ctx *ctx, int32_t nbins, uint32_t table_log2, uint32_t keys_in_table,
+                     double hit_rate, int32_t weighted, int32_t probe, int32_t block, double *per_s) {
+    return guarded([&] {
+        if (!ctx || !per_s || nbins < 1 || nbins > 24 || table_log2 < 6 || table_log2 > 15 ||
+            keys_in_table > (1u << table_log2) * 7 / 10 || !(hit_rate > 0.0 && hit_rate <= 1.0) ||
+            (block != 256 && block != 512))
+            fail(GS_EINVAL, "bad argument");
+        ctx->use();
+        const int nconf = (int)n_configs(nbins);
+        const uint32_t K = std::max<uint32_t>(1, keys_in_table);
+        const uint32_t universe = std::max<uint32_t>(K, (uint32_t)((double)K / hit_rate));
+        const uint32_t len = 1u << 18;   // 1 MiB of labels + 256 KiB of bins: L2-resident
+        DevBuf keys(4ull * len), bins(len), w(8ull * std::max<uint32_t>(universe, 1024)), sink(8);
+        hipStream_t s = ctx->stream;
+        k_ceil_fill<<<256, 256, 0, s>>>(keys.as<uint32_t>(), bins.as<uint8_t>(), w.as<double>(), len, universe,
+                                        std::max<uint32_t>(universe, 1024), nbins);
+        GS_HIP(hipGetLastError());
+        CeilArgs a{};
+        a.keys = keys.as<uint32_t>();
+        a.bins = bins.as<uint8_t>();
+        a.w = w.as<double>();
+        a.mask = len - 1;
+        a.log2h = (int)table_log2;
+        a.K = K;
+        a.nb = nbins;
+        a.nconf = nconf;
+        a.wmul = 0x1.0p55;
+        a.sink = (unsigned long long *)sink.p;
+        a.per_group = 1ull << 22;
+        const uint32_t o_hist = lds_align(2 * nbins * nbins * nbins, 16);
+        uint32_t lds = lds_align(o_hist + 4 * nconf, 16) + (weighted ? 16 * nconf : 0);
+        lds = lds_align(lds, 16) + 4 * (1u << table_log2);
+        double r = 0;
+        const bool W = weighted != 0, Pr = probe != 0;
+        if (block == 512) {
+            if (Pr) r = W ? run_probe<512, true, true>(*ctx, a, lds) : run_probe<512, true, false>(*ctx, a, lds);
+            else r = W ? run_probe<512, false, true>(*ctx, a, lds) : run_probe<512, false, false>(*ctx, a, lds);
+        } else {
+            if (Pr) r = W ? run_probe<256, true, true>(*ctx, a, lds) : run_probe<256, true, false>(*ctx, a, lds);
+            else r = W ? run_probe<256, false, true>(*ctx, a, lds) : run_probe<256, false, false>(*ctx, a, lds);
+        }
+        GS_HIP(hipStreamSynchronize(s));
+        *per_s = r;
+    });
+}
+
+}  // extern "C"

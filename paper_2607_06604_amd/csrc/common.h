@@ -134,7 +134,7 @@ struct HostBuf {
 
 struct Timings {
     double build_ms = 0, count_ms = 0, kernel_ms = 0;
-    uint64_t kernel_launches = 0, alg_bytes = 0;
+    uint64_t kernel_launches = 0, alg_bytes = 0, probes = 0;
 };
 
 struct Server;

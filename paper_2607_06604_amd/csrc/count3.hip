@@ -76,6 +76,7 @@ struct C3Args {
     unsigned long long *hist;   // nconf
     unsigned long long *wsum;   // 2*nconf (lo, hi)
     unsigned long long *ntri;   // 1
+    unsigned long long *probes; // candidates probed (nullable)
     uint32_t *err;          // bit 0: a hub's spoke rows span too many entries; bit 1: LDS addressing
     const uint16_t *cfg3;   // kLut / kCube: configuration index of ordered triple (x*nb + y)*nb + z
     const uint32_t *tiles;  // hub tiles of about equal cost: tile t = [tiles[t], tiles[t+1]) (or null)
@@ -468,6 +469,7 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
 
     unsigned long long mytri = 0;  // global counters: this thread's hits
     uint64_t acc = 0;   // candidates probed since the last flush: bounds the increments (uniform)
+    uint64_t probed = 0;  // candidates probed in all (uniform)
     // thread 0's claimed hubs and tile claims live in LDS (no registers held
     // across the loop)
     HubCursor &cursor = *(HubCursor *)(sm + L.misc + 128);
@@ -688,6 +690,7 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
             const uint64_t pre = wg_excl_scan64<BLOCK, false>(((uint64_t)len << 32) | ns, wtot64, tot64);
             const uint32_t t0 = (uint32_t)pre, T = (uint32_t)tot64;
             acc += tot64 >> 32;
+            probed += tot64 >> 32;
             if (T == 0) __syncthreads();   // (the fill barrier guards wtot otherwise)
             // the table holds tmax steps: fill and walk it as often as needed
             const uint32_t xhub = WIDE ? 0u : hk << 30;
@@ -719,6 +722,7 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
 
     __syncthreads();
     flush3<BLOCK, WEIGHTED, LDS_HIST>(a, L, sm, hout, tout);
+    if (tid == 0 && a.probes && probed) atomicAdd(a.probes, (unsigned long long)probed);
     if (!LDS_HIST) {
         mytri = wave_sum64(mytri);
         if ((tid & 63) == 0 && mytri && tout) atomicAdd(tout, mytri);
@@ -1258,9 +1262,9 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     const int W = g.n_windows;
     const int ntiles = W * (W + 1) / 2;
 
-    // device staging: hist | wsum | ntri | error word | queue sets, one per
-    // tile (256-byte aligned)
-    const size_t qoff = (3 * (size_t)nconf + 2 + 31) / 32 * 32;
+    // device staging: hist | wsum | ntri | error word | probes | queue sets,
+    // one per tile (256-byte aligned)
+    const size_t qoff = (3 * (size_t)nconf + 3 + 31) / 32 * 32;
     const std::vector<uint16_t> cfg = config_table(nb);   // | configuration table
     const size_t coff = qoff + (size_t)ntiles * kQueueWords / 2;
     // | hub tile bounds | block costs
@@ -1295,6 +1299,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.wsum = dv + nconf;
     a.ntri = dv + 3 * (size_t)nconf;
     a.err = (uint32_t *)(dv + 3 * (size_t)nconf + 1);
+    a.probes = dv + 3 * (size_t)nconf + 2;
     a.cfg3 = (const uint16_t *)(dv + coff);
     uint32_t *queues = (uint32_t *)(dv + qoff);
     uint32_t *tbounds = (uint32_t *)(dv + toff);
@@ -1428,7 +1433,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
         }
     }
     GS_HIP(hipEventRecord(ctx.ev[3], s));
-    std::vector<unsigned long long> h(3 * (size_t)nconf + 2);
+    std::vector<unsigned long long> h(3 * (size_t)nconf + 3);
     GS_HIP(hipMemcpyAsync(h.data(), dv, h.size() * 8, hipMemcpyDeviceToHost, s));
     GS_HIP(hipEventRecord(ctx.ev[1], s));
     GS_HIP(hipStreamSynchronize(s));
@@ -1445,6 +1450,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     ctx.t.count_ms = ms;
     ctx.t.kernel_ms = kms;
     ctx.t.kernel_launches = g.n > 0 ? (uint64_t)ntiles : 0;
+    ctx.t.probes = h[3 * (size_t)nconf + 2];
     // merge-walk bytes: each hub-spoke step reads both forward half-lists,
     // 5 bytes per entry: 2.5 B x sum_i m_i^2 over full degrees m_i
     ctx.t.alg_bytes = g.stats_ready ? (uint64_t)(2.5 * (double)g.sum_sq_deg) : 0;

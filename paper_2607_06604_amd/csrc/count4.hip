@@ -50,8 +50,10 @@ struct C4Args {
 
 struct Layout4 {
     uint32_t hkey, hloc, hslot, px, py, pz, sx, sy, sz, pq, pb, pperm, R, rbnd, queue, mstart, mpref, mloc,
-        hist, tab, thr, wtot, misc, total;
+        hist, tab, lut, thr, wtot, misc, total;
 };
+
+constexpr int kLut4MaxBins = 16;   // nb^3 u16 counter addresses up to 8 KB
 
 constexpr int kQueue4 = 128;   // clique ring entries per wavefront
 
@@ -78,6 +80,7 @@ __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxde
     L.pperm = o;   if (anchored) o = lds_align(o + 4 * d, 16);
     L.hist = o;    o = lds_align(o + 4 * 3 * nconf, 16);
     L.tab = o;     o = lds_align(o + 8 * (nb + 1), 16);
+    L.lut = o;     if (nb <= kLut4MaxBins) o = lds_align(o + 2 * nb * nb * nb, 16);
     L.hloc = o;    o = lds_align(o + 2 * H, 16);
     L.hslot = o;   o = lds_align(o + 2 * d, 16);
     L.mloc = o;    o = lds_align(o + 2 * block, 16);
@@ -134,49 +137,47 @@ __device__ __forceinline__ int hub_channel(const P3 &P, const P3 &Q, const P3 &R
     return degen ? 2 : ((V > 0.0) == up ? 0 : 1);
 }
 
-// One hub of a clique decided from Vc, the triple product (ia x ib) . ic of
-// hub i's spokes in label order, where that is safe. In exact arithmetic
-// every hub's sorted triple product is +-T (T the signed volume times 6):
-// with 4 rmax below the box size all separations are differences of the same
-// four points, so (P x Q) . R of the hub's spokes in the order given is T for
-// hubs i and b and -T for hubs a and c (sign0), and sorting the spokes
-// multiplies it by the parity of the sorting permutation. Every spoke
-// component is the exact difference rounded once (error at most u, the unit
-// roundoff, times the component; where it wraps, at most u times the box
-// size, the correction by L being exact), and evaluating a triple product
-// rounds each of its few terms once: the definition's value for this hub and
-// Vc both lie within a small multiple of u rmax^3 (plus u L rmax^2 near the
-// faces) of +-T. eb is at least twice the sum of the two bounds, so when
-// |Vc| - eb already squares above the hub's limit the definition's value
-// does too and carries the predicted sign, and when |Vc| + eb squares below
-// it the hub is degenerate. Otherwise (a clique within rounding of coplanar,
-// or of the threshold, or eb infinite) the hub is evaluated exactly as the
-// definition says. Ties in length are decided exactly.
-__device__ __forceinline__ int hub_channel_shared(const P3 &P, const P3 &Q, const P3 &R, double qP, double qQ,
-                                                  double qR, int bP, int bQ, int bR, const int *ta,
-                                                  const int *tb, int *idx, double Vc, bool sign0,
-                                                  double eb) {
-    const int b0 = min(min(bP, bQ), bR), b2 = max(max(bP, bQ), bR);
-    const int b1 = bP + bQ + bR - b0 - b2;
-    *idx = ta[b0] + tb[b1] + b2;
-    const bool pq = qP < qQ;
-    const double lo = pq ? qP : qQ, hi = pq ? qQ : qP;
-    const double q0 = lo < qR ? lo : qR, q2 = hi > qR ? hi : qR;
-    const double mh = hi < qR ? hi : qR;
-    const double q1 = lo > mh ? lo : mh;
-    if (q0 == q1 || q1 == q2) return 2;
+// The part of the shared decision common to a clique's four hubs: Vc, the
+// triple product (ia x ib) . ic of hub i's spokes in label order, and the
+// squares of |Vc| -+ eb.
+struct Shared4 {
+    double Vc, x2, y2;
+    bool xpos;
+};
+
+// One hub of a clique decided from Vc where that is safe. In exact
+// arithmetic every hub's sorted triple product is +-T (T the signed volume
+// times 6): with 4 rmax below the box size all separations are differences
+// of the same four points, so (P x Q) . R of the hub's spokes in the order
+// given is T for hubs i and b and -T for hubs a and c (sign0), and sorting
+// the spokes multiplies it by the parity of the sorting permutation. Every
+// spoke component is the exact difference rounded once (error at most u,
+// the unit roundoff, times the component; where it wraps, at most u times
+// the box size, the correction by L being exact), and evaluating a triple
+// product rounds each of its few terms once: the definition's value for
+// this hub and Vc both lie within a small multiple of u rmax^3 (plus
+// u L rmax^2 near the faces) of +-T. eb is at least twice the sum of the two
+// bounds, so when |Vc| - eb already squares above the hub's limit the
+// definition's value does too and carries the predicted sign, and when
+// |Vc| + eb squares below it the hub is degenerate. Otherwise (a clique
+// within rounding of coplanar, or of the threshold, or eb infinite) *exact
+// is set and the caller evaluates the hub as the definition says. Ties in
+// length are decided exactly, and without a sort: the sorted lengths tie
+// iff two of the three are equal, and the sorting permutation's parity is
+// the parity of the inversions among (qP, qQ, qR). Returns 0 pos, 1 neg,
+// 2 degenerate.
+__device__ __forceinline__ int hub_fast(double qP, double qQ, double qR, const Shared4 &sh, bool sign0,
+                                        bool &exact) {
+    const bool tie = (qP == qQ) | (qP == qR) | (qQ == qR);
+    const double lo = fmin(qP, qQ), hi = fmax(qP, qQ);
+    const double q0 = fmin(lo, qR), q2 = fmax(hi, qR), q1 = fmax(lo, fmin(hi, qR));
     const double lim = __dmul_rn(1e-18, __dmul_rn(__dmul_rn(q0, q1), q2));
-    const double A = fabs(Vc);
-    const double x = __dsub_rn(A, eb), y = __dadd_rn(A, eb);
-    if (x > 0.0 && __dmul_rn(x, x) > lim) {
-        // parity of the sort: inversions among (qP, qQ, qR), no ties here
-        const bool odd = ((qP > qQ) ^ (qP > qR) ^ (qQ > qR));
-        const bool pos = (Vc > 0.0) ^ odd ^ !sign0;
-        return pos ? 0 : 1;
-    }
-    if (__dmul_rn(y, y) <= lim) return 2;
-    int idx2;
-    return hub_channel(P, Q, R, qP, qQ, qR, bP, bQ, bR, ta, tb, &idx2);
+    const bool odd = (qP > qQ) ^ (qP > qR) ^ (qQ > qR);
+    const bool sgn = !tie && sh.xpos && sh.x2 > lim;
+    const bool deg = tie || (!sgn && sh.y2 <= lim);
+    exact = !sgn && !deg;
+    const bool pos = (sh.Vc > 0.0) ^ odd ^ !sign0;
+    return deg ? 2 : (pos ? 0 : 1);
 }
 
 // Per-hub LDS state the clique evaluation reads.
@@ -187,6 +188,7 @@ struct Stage4 {
     const uint8_t *pb;            // spoke bins
     const double *thr;            // t_0 .. t_nb
     const int *ta, *tb;           // configuration rank tables
+    const uint16_t *lut;          // nb <= 16: configuration of ordered bin triple (x*nb + y)*nb + z
     uint32_t *hist;               // pos | neg | degenerate counters
     int nb, nconf;
     double L, half;
@@ -198,33 +200,77 @@ __device__ __forceinline__ double wrap1(double d, double L, double half) {
     return d > half ? __dsub_rn(d, L) : (d < -half ? __dadd_rn(d, L) : d);
 }
 
-// The four hubs of the clique {i, va, vb, vc}: each hub's spokes are the
-// separations to the other three (the hub's own spokes negated where the
-// clique's edge points towards it), decided from one shared triple product
-// with margin eb where it allows. wrap: the hub is near a face, so a
-// separation may need its minimum-image correction (applied after the plain
-// difference, as the definition does; elsewhere none can apply and the plain
-// difference is the value).
-__device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t va, uint32_t vb, uint32_t vc, double eb,
-                                            bool wrap) {
+// Separations among the clique's non-hub vertices a, b, c: plain differences,
+// corrected by +-L near a face (wrap) as the definition does.
+__device__ __forceinline__ void local_seps(const Stage4 &S, uint32_t va, uint32_t vb, uint32_t vc, bool wrap,
+                                          P3 &ab, P3 &ac, P3 &bcv) {
     const P3 A{S.px[va], S.py[va], S.pz[va]};
     const P3 B{S.px[vb], S.py[vb], S.pz[vb]};
     const P3 C{S.px[vc], S.py[vc], S.pz[vc]};
-    const P3 ia{S.sx[va], S.sy[va], S.sz[va]};
-    const P3 ib{S.sx[vb], S.sy[vb], S.sz[vb]};
-    const P3 ic{S.sx[vc], S.sy[vc], S.sz[vc]};
-    const double qa = S.pq[va], qb = S.pq[vb], qc = S.pq[vc];
-    const int ba = S.pb[va], bb = S.pb[vb], bc = S.pb[vc];
-    P3 ab{__dsub_rn(B.x, A.x), __dsub_rn(B.y, A.y), __dsub_rn(B.z, A.z)};
-    P3 ac{__dsub_rn(C.x, A.x), __dsub_rn(C.y, A.y), __dsub_rn(C.z, A.z)};
-    P3 bcv{__dsub_rn(C.x, B.x), __dsub_rn(C.y, B.y), __dsub_rn(C.z, B.z)};
+    ab = P3{__dsub_rn(B.x, A.x), __dsub_rn(B.y, A.y), __dsub_rn(B.z, A.z)};
+    ac = P3{__dsub_rn(C.x, A.x), __dsub_rn(C.y, A.y), __dsub_rn(C.z, A.z)};
+    bcv = P3{__dsub_rn(C.x, B.x), __dsub_rn(C.y, B.y), __dsub_rn(C.z, B.z)};
     if (wrap) {
         const double L = S.L, h = S.half;
         ab = P3{wrap1(ab.x, L, h), wrap1(ab.y, L, h), wrap1(ab.z, L, h)};
         ac = P3{wrap1(ac.x, L, h), wrap1(ac.y, L, h), wrap1(ac.z, L, h)};
         bcv = P3{wrap1(bcv.x, L, h), wrap1(bcv.y, L, h), wrap1(bcv.z, L, h)};
     }
+}
+
+// Hubs of the clique that the shared product left undecided (bit h of
+// mask: 0 hub i, 1 a, 2 b, 3 c), evaluated as the definition says. The
+// separations are recomputed from the staged coordinates (the same
+// operations, hence the same values) so the common path holds no vectors.
+__device__ __forceinline__ void exact_hubs(const Stage4 &S, uint32_t va, uint32_t vb, uint32_t vc, bool wrap,
+                                        uint32_t mask, int *ch) {
+    const P3 ia{S.sx[va], S.sy[va], S.sz[va]};
+    const P3 ib{S.sx[vb], S.sy[vb], S.sz[vb]};
+    const P3 ic{S.sx[vc], S.sy[vc], S.sz[vc]};
+    const double qa = S.pq[va], qb = S.pq[vb], qc = S.pq[vc];
+    P3 ab, ac, bcv;
+    local_seps(S, va, vb, vc, wrap, ab, ac, bcv);
     const double qab = sq_len(ab.x, ab.y, ab.z), qac = sq_len(ac.x, ac.y, ac.z), qbc = sq_len(bcv.x, bcv.y, bcv.z);
+    int idx;
+    if (mask & 1u) ch[0] = hub_channel(ia, ib, ic, qa, qb, qc, 0, 0, 0, S.ta, S.tb, &idx);
+    if (mask & 2u) ch[1] = hub_channel(neg(ia), ab, ac, qa, qab, qac, 0, 0, 0, S.ta, S.tb, &idx);
+    if (mask & 4u) ch[2] = hub_channel(neg(ib), neg(ab), bcv, qb, qab, qbc, 0, 0, 0, S.ta, S.tb, &idx);
+    if (mask & 8u) ch[3] = hub_channel(neg(ic), neg(ac), neg(bcv), qc, qac, qbc, 0, 0, 0, S.ta, S.tb, &idx);
+}
+
+// Counter address (LDS bytes) of the configuration of bins x, y, z in the
+// pos block; the neg and degenerate blocks follow at 4 nconf bytes each.
+template <bool LUT>
+__device__ __forceinline__ uint32_t conf_addr(const Stage4 &S, uint32_t hist_addr, int x, int y, int z) {
+    if (LUT) return hist_addr + 4u * (uint32_t)S.lut[((uint32_t)x * (uint32_t)S.nb + (uint32_t)y) * (uint32_t)S.nb + (uint32_t)z];
+    const int b0 = min(min(x, y), z), b2 = max(max(x, y), z);
+    const int b1 = x + y + z - b0 - b2;
+    return hist_addr + 4u * (uint32_t)(S.ta[b0] + S.tb[b1] + b2);
+}
+
+// The four hubs of the clique {i, va, vb, vc}: each hub's spokes are the
+// separations to the other three; the squared lengths and bins of the
+// three new separations are computed here, the hub's spokes were staged.
+// wrap: the hub is near a face, so a separation may need its minimum-image
+// correction (elsewhere none can apply and the plain difference is the
+// value).
+template <bool LUT>
+__device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr, uint32_t va, uint32_t vb,
+                                            uint32_t vc, double eb, bool wrap) {
+    const double qa = S.pq[va], qb = S.pq[vb], qc = S.pq[vc];
+    const int ba = S.pb[va], bb = S.pb[vb], bc = S.pb[vc];
+    double qab, qac, qbc, Vc;
+    {
+        P3 ab, ac, bcv;
+        local_seps(S, va, vb, vc, wrap, ab, ac, bcv);
+        qab = sq_len(ab.x, ab.y, ab.z);
+        qac = sq_len(ac.x, ac.y, ac.z);
+        qbc = sq_len(bcv.x, bcv.y, bcv.z);
+        const P3 ia{S.sx[va], S.sy[va], S.sz[va]};
+        const P3 ib{S.sx[vb], S.sy[vb], S.sz[vb]};
+        const P3 ic{S.sx[vc], S.sy[vc], S.sz[vc]};
+        Vc = triple(ia, ib, ic);
+    }
     int bab, bac, bbc;
     if (S.nb <= 16) {
         // the bin is the number of thresholds t_1..t_{nb-1} at most q
@@ -242,16 +288,30 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t va, uint32
         bac = bin_of(S.thr, S.nb, qac);
         bbc = bin_of(S.thr, S.nb, qbc);
     }
-    int idx, ch;
-    const double Vc = triple(ia, ib, ic);
-    ch = hub_channel_shared(ia, ib, ic, qa, qb, qc, ba, bb, bc, S.ta, S.tb, &idx, Vc, true, eb);
-    atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
-    ch = hub_channel_shared(neg(ia), ab, ac, qa, qab, qac, ba, bab, bac, S.ta, S.tb, &idx, Vc, false, eb);
-    atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
-    ch = hub_channel_shared(neg(ib), neg(ab), bcv, qb, qab, qbc, bb, bab, bbc, S.ta, S.tb, &idx, Vc, true, eb);
-    atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
-    ch = hub_channel_shared(neg(ic), neg(ac), neg(bcv), qc, qac, qbc, bc, bac, bbc, S.ta, S.tb, &idx, Vc, false, eb);
-    atomicAdd(&S.hist[ch * S.nconf + idx], 1u);
+    Shared4 sh;
+    sh.Vc = Vc;
+    const double A = fabs(Vc);
+    const double x = __dsub_rn(A, eb), y = __dadd_rn(A, eb);
+    sh.xpos = x > 0.0;
+    sh.x2 = __dmul_rn(x, x);
+    sh.y2 = __dmul_rn(y, y);
+    int ch[4];
+    bool e0, e1, e2, e3;
+    ch[0] = hub_fast(qa, qb, qc, sh, true, e0);
+    ch[1] = hub_fast(qa, qab, qac, sh, false, e1);
+    ch[2] = hub_fast(qb, qab, qbc, sh, true, e2);
+    ch[3] = hub_fast(qc, qac, qbc, sh, false, e3);
+    const uint32_t mask = (uint32_t)e0 | ((uint32_t)e1 << 1) | ((uint32_t)e2 << 2) | ((uint32_t)e3 << 3);
+    if (mask) exact_hubs(S, va, vb, vc, wrap, mask, ch);
+    const uint32_t blk = 4u * (uint32_t)S.nconf;
+    const uint32_t a0 = conf_addr<LUT>(S, hist_addr, ba, bb, bc) + blk * (uint32_t)ch[0];
+    const uint32_t a1 = conf_addr<LUT>(S, hist_addr, ba, bab, bac) + blk * (uint32_t)ch[1];
+    const uint32_t a2 = conf_addr<LUT>(S, hist_addr, bb, bab, bbc) + blk * (uint32_t)ch[2];
+    const uint32_t a3 = conf_addr<LUT>(S, hist_addr, bc, bac, bbc) + blk * (uint32_t)ch[3];
+    __hip_atomic_fetch_add((lds_u32 *)(size_t)a0, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add((lds_u32 *)(size_t)a1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add((lds_u32 *)(size_t)a2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add((lds_u32 *)(size_t)a3, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <int BLOCK>
@@ -265,7 +325,7 @@ __device__ void flush4(const C4Args &a, uint32_t *hist) {
     }
 }
 
-template <int BLOCK, bool ANCHORED>
+template <int BLOCK, bool ANCHORED, bool LUT>
 __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const uint32_t H = 1u << a.log2h, mask = H - 1;
@@ -286,6 +346,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint16_t *mloc = (uint16_t *)(sm + L.mloc);
     uint32_t *hist = (uint32_t *)(sm + L.hist);
     int *ta = (int *)(sm + L.tab);
+    uint16_t *lut = (uint16_t *)(sm + L.lut);
     int *tb = ta + (a.nb + 1);
     double *thr = (double *)(sm + L.thr);
     uint32_t *wtot = (uint32_t *)(sm + L.wtot);
@@ -303,6 +364,12 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
         ta[b] = rank_a(a.nb, b);
         tb[b] = rank_b(a.nb, b);
     }
+    if (LUT)
+        for (int t = tid; t < a.nb * a.nb * a.nb; t += BLOCK) {
+            const int x = t / (a.nb * a.nb), y = (t / a.nb) % a.nb, z = t % a.nb;
+            const int b0 = min(min(x, y), z), b2 = max(max(x, y), z), b1 = x + y + z - b0 - b2;
+            lut[t] = (uint16_t)(rank_a(a.nb, b0) + rank_b(a.nb, b1) + b2);
+        }
     for (int b = tid; b <= a.nb; b += BLOCK) thr[b] = a.thr[b];
     if (tid == 0) *s_cnt = 0;
     __syncthreads();
@@ -311,7 +378,8 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint64_t acc = 0;
     HubCursor cursor;   // thread 0's claimed run of hubs
     const double Lb = a.L, half = a.half;
-    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, hist, a.nb, a.nconf, a.L, a.half, a.tk};
+    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, lut, hist, a.nb, a.nconf, a.L, a.half, a.tk};
+    const uint32_t hist_addr = lds_addr(hist);
 
     while (true) {
         if (tid == 0) *s_hub = next_hub_in(a.queue, 0, a.n, gridDim.x, cursor, 1);
@@ -478,7 +546,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
                                 ++mine_n;
                                 const uint32_t va = (uint32_t)t & 0xFFFFu, vb = (uint32_t)(t >> 16) & 0xFFFFu,
                                                vc = (uint32_t)(t >> 32);
-                                eval_clique(S, va, vb, vc, inner ? a.eb_in : a.eb_wrap, !inner);
+                                eval_clique<LUT>(S, hist_addr, va, vb, vc, inner ? a.eb_in : a.eb_wrap, !inner);
                                 wave_lds_sync();
                             }
                         }
@@ -491,7 +559,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
                 ++mine_n;
                 const uint32_t va = (uint32_t)t & 0xFFFFu, vb = (uint32_t)(t >> 16) & 0xFFFFu,
                                vc = (uint32_t)(t >> 32);
-                eval_clique(S, va, vb, vc, inner ? a.eb_in : a.eb_wrap, !inner);
+                eval_clique<LUT>(S, hist_addr, va, vb, vc, inner ? a.eb_in : a.eb_wrap, !inner);
             }
             mycl += mine_n;
             if (mine_n) atomicAdd(s_round, mine_n);
@@ -518,19 +586,19 @@ __global__ void k_zero4(unsigned long long *p, uint64_t n) {
         p[i] = 0;
 }
 
-template <int BLOCK, bool A>
+template <int BLOCK, bool A, bool LUT>
 void launch4(Ctx &ctx, const C4Args &a, uint32_t lds) {
-    const void *kern = reinterpret_cast<const void *>(&k_count4<BLOCK, A>);
+    const void *kern = reinterpret_cast<const void *>(&k_count4<BLOCK, A, LUT>);
     if (lds > 65536)
         GS_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
-    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count4<BLOCK, A>, BLOCK, lds));
+    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count4<BLOCK, A, LUT>, BLOCK, lds));
     if (per_cu < 1) fail(GS_EUNSUPPORTED, "parity kernel does not fit a compute unit");
     if (getenv("GS_PLAN_LOG"))
         fprintf(stderr, "[gsn] count4 block %d lds %u blocks/CU %d maxdeg %u\n", BLOCK, lds, per_cu, a.maxdeg);
     uint32_t grid = (uint32_t)ctx.n_cu * (uint32_t)per_cu;
     grid = (grid + kNumQueues - 1) / kNumQueues * kNumQueues;
-    k_count4<BLOCK, A><<<dim3(grid), dim3(BLOCK), lds, ctx.stream>>>(a);
+    k_count4<BLOCK, A, LUT><<<dim3(grid), dim3(BLOCK), lds, ctx.stream>>>(a);
     GS_HIP(hipGetLastError());
 }
 
@@ -615,12 +683,13 @@ void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_
     GS_HIP(hipMemcpyAsync(dthr, g.bins.t, sizeof(double) * 256, hipMemcpyHostToDevice, s));
     GS_HIP(hipEventRecord(ctx.ev[2], s));
     if (g.n > 0) {
+        const bool lut = nb <= kLut4MaxBins;
         if (BLOCK == 512) {
-            if (anchored) launch4<512, true>(ctx, a, L.total);
-            else launch4<512, false>(ctx, a, L.total);
+            if (anchored) lut ? launch4<512, true, true>(ctx, a, L.total) : launch4<512, true, false>(ctx, a, L.total);
+            else lut ? launch4<512, false, true>(ctx, a, L.total) : launch4<512, false, false>(ctx, a, L.total);
         } else {
-            if (anchored) launch4<256, true>(ctx, a, L.total);
-            else launch4<256, false>(ctx, a, L.total);
+            if (anchored) lut ? launch4<256, true, true>(ctx, a, L.total) : launch4<256, true, false>(ctx, a, L.total);
+            else lut ? launch4<256, false, true>(ctx, a, L.total) : launch4<256, false, false>(ctx, a, L.total);
         }
     }
     GS_HIP(hipEventRecord(ctx.ev[3], s));

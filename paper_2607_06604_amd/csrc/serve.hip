@@ -1,5 +1,6 @@
-// serve.hip - continuous batching of triangle-count requests (gs_submit,
-// gs_poll, gs_cancel).
+// serve.hip - continuous batching of count requests (gs_submit, gs_poll,
+// gs_cancel): triangle counts, exact weighted triangle sums and
+// parity-decomposed 4-clique counts.
 //
 // Per context, a pool of builder threads and one count thread. A submitted
 // catalogue waits in a FIFO queue. A free builder (each has its own stream
@@ -7,10 +8,12 @@
 // batch slot is free, runs the first build phase (cells, relabelling, degree
 // pass: O(n) memory, after which the exact CSR size is known), waits until
 // that footprint fits the context budget next to the graphs already held
-// (or nothing else is held), and finishes the build. The count thread
-// launches one batched count over every graph built so far, waits for it,
-// hands each request its histogram, frees its graph, and starts the next
-// step over whatever was built meanwhile.
+// (or nothing else is held), and finishes the build. The count thread takes
+// every graph built so far: the plain triangle counts of one bin count go
+// into one batched launch, and each weighted triangle count and each parity
+// count runs as a count of its own (one such count already fills the
+// device); it hands each request its results, frees its graph, and starts
+// the next step over whatever was built meanwhile.
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -34,13 +37,17 @@ enum ReqState { kQueued, kBuilding, kBuilt, kCounting, kDone, kFailed, kCancelle
 struct Request {
     uint64_t ticket = 0;
     std::vector<double> xyz;
+    std::vector<double> w;        // weights (weighted triangle counts)
     int64_t n = 0;
     gs_graph_params p{};
+    int kind = GS_3PCF;
     ReqState state = kQueued;
     bool cancel = false;
     int error = 0;
-    std::vector<uint64_t> hist;
-    uint64_t ntri = 0;
+    std::vector<uint64_t> hist;   // triangle counts, or the even channel
+    std::vector<uint64_t> pos, neg, wsum;
+    int wscale = 0;
+    uint64_t ntri = 0;            // triangles or 4-cliques
     uint32_t step_size = 0;
     Clock::time_point t_submit, t_build0, t_build1, t_count0, t_done;
     std::unique_ptr<gs_graph> g;
@@ -118,10 +125,10 @@ void builder(Server *Sp, int k) {
             g.rmin = r->p.rmin;
             g.rmax = r->p.rmax;
             g.nbins = r->p.nbins;
-            g.flags = 0;
+            g.flags = (r->w.empty() ? 0u : GS_WEIGHTED) | (r->kind == GS_4PCF_PARITY ? GS_KEEP_COORDS : 0u);
             g.bins = make_bins(r->p.rmin, r->p.rmax, r->p.nbins);
             r->job.reset(new BuildJob());
-            build_begin(B, g, r->xyz.data(), nullptr, *r->job);
+            build_begin(B, g, r->xyz.data(), r->w.empty() ? nullptr : r->w.data(), *r->job);
             const uint64_t fp = build_footprint(g, *r->job);
             {
                 // admission: the exact footprint fits next to the held graphs,
@@ -144,6 +151,8 @@ void builder(Server *Sp, int k) {
                 r->t_build1 = Clock::now();
                 r->xyz.clear();
                 r->xyz.shrink_to_fit();
+                r->w.clear();
+                r->w.shrink_to_fit();
                 if (r->cancel) {
                     r->state = kCancelled;
                     r->t_done = r->t_build1;
@@ -173,6 +182,9 @@ void builder(Server *Sp, int k) {
     }
 }
 
+// A plain (unweighted) triangle count: the kind that batched launches take.
+bool batchable(const Request *q) { return q->kind == GS_3PCF && !(q->g->flags & GS_WEIGHTED); }
+
 void count_loop(Server *Sp) {
     Server &S = *Sp;
     (void)hipSetDevice(S.cctx.device);
@@ -186,11 +198,14 @@ void count_loop(Server *Sp) {
             std::unique_lock<std::mutex> lk(S.mu);
             S.cv.wait(lk, [&] { return S.stop || !S.ready.empty(); });
             if (S.stop) return;
-            // one step counts the built graphs that share the first one's bin
-            // count (one histogram layout per launch); the rest wait
-            const int nb = S.ready.front()->p.nbins;
+            // one step takes the plain triangle counts that share the first
+            // one's bin count (one histogram layout per launch) and every
+            // weighted or parity count; other plain counts wait
+            int nb = -1;
+            for (Request *q : S.ready)
+                if (batchable(q)) { nb = q->p.nbins; break; }
             std::vector<Request *> rest;
-            for (Request *q : S.ready) (q->p.nbins == nb ? step : rest).push_back(q);
+            for (Request *q : S.ready) (!batchable(q) || q->p.nbins == nb ? step : rest).push_back(q);
             S.ready.swap(rest);
             S.counting = (int)step.size();
             const Clock::time_point now = Clock::now();
@@ -200,34 +215,70 @@ void count_loop(Server *Sp) {
                 q->step_size = (uint32_t)step.size();
             }
         }
+        std::vector<Request *> plain;
         std::vector<const Graph *> gs;
-        for (Request *q : step) gs.push_back(q->g.get());
+        for (Request *q : step)
+            if (batchable(q)) {
+                plain.push_back(q);
+                gs.push_back(q->g.get());
+            }
         int err = GS_OK;
-        try {
-            count3_batch_enqueue(S.cctx, S.cstream, gs.data(), (int)gs.size(), *b);
-            GS_HIP(hipEventSynchronize(b->done));
-            if (b->error()) err = GS_EUNSUPPORTED;
-        } catch (const Error &e) {
-            (void)hipStreamSynchronize(S.cstream);
-            err = e.code;
+        if (!plain.empty()) {
+            try {
+                count3_batch_enqueue(S.cctx, S.cstream, gs.data(), (int)gs.size(), *b);
+                GS_HIP(hipEventSynchronize(b->done));
+                if (b->error()) err = GS_EUNSUPPORTED;
+            } catch (const Error &e) {
+                (void)hipStreamSynchronize(S.cstream);
+                err = e.code;
+            }
+        }
+        // weighted and parity counts, one at a time, results into the request
+        std::vector<int> own_err(step.size(), GS_OK);
+        for (size_t k = 0; k < step.size(); ++k) {
+            Request *r = step[k];
+            if (batchable(r) || r->cancel) continue;
+            try {
+                const int64_t nconf = n_configs(r->p.nbins);
+                const Graph &g = *r->g;
+                r->hist.assign(nconf, 0);
+                if (r->kind == GS_4PCF_PARITY) {
+                    r->pos.assign(nconf, 0);
+                    r->neg.assign(nconf, 0);
+                    count4_run(S.cctx, g, r->hist.data(), r->pos.data(), r->neg.data(), &r->ntri, nullptr);
+                } else {
+                    r->wsum.assign(2 * nconf, 0);
+                    count3_run(S.cctx, g, r->hist.data(), r->wsum.data(), &r->ntri, nullptr);
+                    r->wscale = g.wscale;
+                }
+            } catch (const Error &e) {
+                (void)hipStreamSynchronize(S.cstream);
+                own_err[k] = e.code;
+            }
         }
         {
             std::lock_guard<std::mutex> lk(S.mu);
-            const unsigned long long *o = err == GS_OK ? b->out.as<unsigned long long>() : nullptr;
+            const unsigned long long *o = err == GS_OK && !plain.empty() ? b->out.as<unsigned long long>() : nullptr;
             const size_t per = (size_t)b->nconf + 1;
             const Clock::time_point now = Clock::now();
+            size_t slot = 0;
             for (size_t k = 0; k < step.size(); ++k) {
                 Request *r = step[k];
+                const bool in_batch = batchable(r);
+                const int e = in_batch ? err : own_err[k];
                 if (r->cancel) {
                     r->state = kCancelled;
-                } else if (err != GS_OK) {
+                } else if (e != GS_OK) {
                     r->state = kFailed;
-                    r->error = err;
+                    r->error = e;
                 } else {
-                    r->hist.assign(o + k * per, o + k * per + b->nconf);
-                    r->ntri = o[k * per + b->nconf];
+                    if (in_batch) {
+                        r->hist.assign(o + slot * per, o + slot * per + b->nconf);
+                        r->ntri = o[slot * per + b->nconf];
+                    }
                     r->state = kDone;
                 }
+                if (in_batch) ++slot;
                 r->t_done = now;
                 S.used -= r->footprint;
                 r->g.reset();
@@ -282,6 +333,10 @@ Server &server_of(Ctx &ctx) {
         c.budget = ~0ull;
         c.tuned = ctx.tuned;  // schedules tuned in the context before its first request
         GS_HIP(hipStreamCreateWithFlags(&S->cstream, hipStreamNonBlocking));
+        // weighted and parity counts run through the lone-count paths on
+        // the count stream, with the count context's events and scratch
+        c.stream = S->cstream;
+        for (auto &e : c.ev) GS_HIP(hipEventCreate(&e));
         S->budget = ctx.budget;
         if (const char *ms = getenv("GS_MAX_SLOTS")) S->max_slots = std::max(1, atoi(ms));
         for (int k = 0; k < nb; ++k) S->builders.emplace_back(builder, S.get(), k);
@@ -306,6 +361,10 @@ void server_stop(Ctx &ctx) {
     if (S->counter.joinable()) S->counter.join();
     S->all.clear();
     (void)hipStreamSynchronize(S->cstream);
+    for (auto &e : S->cctx.ev)
+        if (e) (void)hipEventDestroy(e);
+    S->cctx.stream = nullptr;
+    S->cctx.scratch.reset();
     (void)hipStreamDestroy(S->cstream);
     for (auto &b : S->bctx) release_ctx(*b);
     delete S;
@@ -324,7 +383,12 @@ int gs_submit(gs_ctx *ctx, const gs_request *req, uint64_t *ticket) {
         const gs_graph_params &p = req->p;
         if (req->n < 0 || (req->n > 0 && !req->xyz)) fail(GS_EINVAL, "bad catalogue");
         if (req->n >= 0xFFFFFFFFll) fail(GS_EOVERFLOW, "n must be below 2^32 - 1");
-        if (p.flags != 0) fail(GS_EUNSUPPORTED, "served requests take host, unweighted input");
+        if (req->kind != GS_3PCF && req->kind != GS_4PCF_PARITY) fail(GS_EINVAL, "unknown request kind");
+        if (p.flags & GS_INPUT_ON_DEVICE) fail(GS_EUNSUPPORTED, "served requests take host input");
+        if (p.flags & ~(GS_WEIGHTED | GS_KEEP_COORDS)) fail(GS_EINVAL, "unknown flags");
+        const bool weighted = (p.flags & GS_WEIGHTED) != 0;
+        if (weighted != (req->weights != nullptr)) fail(GS_EINVAL, "weights given iff GS_WEIGHTED");
+        if (weighted && req->kind != GS_3PCF) fail(GS_EINVAL, "weights apply to triangle counts only");
         if (!(p.box > 0) || !std::isfinite(p.box)) fail(GS_EINVAL, "box must be finite and > 0");
         if (p.nbins < 1 || p.nbins > 255) fail(GS_EINVAL, "nbins must be in 1..255");
         if (!(p.rmin >= 0) || !(p.rmin < p.rmax) || !(p.rmax < 0.5 * p.box))
@@ -333,8 +397,10 @@ int gs_submit(gs_ctx *ctx, const gs_request *req, uint64_t *ticket) {
         Server &S = server_of(*ctx);
         std::unique_ptr<Request> r(new Request());
         r->xyz.assign(req->xyz, req->xyz + 3 * req->n);
+        if (weighted) r->w.assign(req->weights, req->weights + req->n);
         r->n = req->n;
         r->p = p;
+        r->kind = req->kind;
         r->t_submit = Clock::now();
         {
             std::lock_guard<std::mutex> lk(S.mu);
@@ -363,8 +429,20 @@ int gs_poll(gs_ctx *ctx, uint64_t ticket, gs_result *out) {
         }
         out->status = r.state == kDone ? GS_DONE : (r.state == kFailed ? GS_FAILED : GS_CANCELLED);
         out->error = r.error;
-        out->n_triangles = r.ntri;
-        if (r.state == kDone && out->hist) memcpy(out->hist, r.hist.data(), sizeof(uint64_t) * r.hist.size());
+        out->n_tuples = r.ntri;
+        out->wscale = r.wscale;
+        if (r.state == kDone) {
+            if (out->hist) memcpy(out->hist, r.hist.data(), sizeof(uint64_t) * r.hist.size());
+            if (out->pos && !r.pos.empty()) memcpy(out->pos, r.pos.data(), sizeof(uint64_t) * r.pos.size());
+            if (out->neg && !r.neg.empty()) memcpy(out->neg, r.neg.data(), sizeof(uint64_t) * r.neg.size());
+            if (out->wsum128 && !r.wsum.empty())
+                memcpy(out->wsum128, r.wsum.data(), sizeof(uint64_t) * r.wsum.size());
+            if (out->whist && !r.wsum.empty())
+                for (size_t c = 0; c < r.wsum.size() / 2; ++c) {
+                    const unsigned __int128 v = ((unsigned __int128)r.wsum[2 * c + 1] << 64) | r.wsum[2 * c];
+                    out->whist[c] = std::ldexp((double)v, -r.wscale);
+                }
+        }
         const bool built = r.t_build1 != Clock::time_point{};
         out->t_queue_s = r.t_build0 != Clock::time_point{} ? secs(r.t_submit, r.t_build0) : secs(r.t_submit, r.t_done);
         out->t_build_s = built ? secs(r.t_build0, r.t_build1) : 0.0;

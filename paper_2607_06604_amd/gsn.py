@@ -36,11 +36,14 @@ GS_PENDING = 1
 GS_FAILED = 2
 GS_CANCELLED = 3
 
+GS_3PCF = 0
+GS_4PCF_PARITY = 1
+
 # every symbol include/gsn.h declares
 EXPORTS = ["gs_create", "gs_destroy", "gs_build_graph", "gs_graph_info", "gs_graph_export",
            "gs_graph_free", "gs_count_3pcf", "gs_count_4pcf_parity", "gs_count_3pcf_batch",
            "gs_tune_3pcf", "gs_submit", "gs_poll", "gs_cancel", "gs_get_timings", "gs_strerror",
-           "gs_last_error_detail"]
+           "gs_last_error_detail", "gs_ceiling_copy", "gs_ceiling_probe"]
 
 
 class GraphParams(ctypes.Structure):
@@ -62,7 +65,7 @@ class GraphStats(ctypes.Structure):
 class Timings(ctypes.Structure):
     _fields_ = [("build_ms", ctypes.c_double), ("count_ms", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_uint64),
-                ("alg_bytes", ctypes.c_uint64)]
+                ("alg_bytes", ctypes.c_uint64), ("probes", ctypes.c_uint64)]
 
 
 class Plan3(ctypes.Structure):
@@ -74,14 +77,16 @@ class Plan3(ctypes.Structure):
 
 
 class Request(ctypes.Structure):
-    _fields_ = [("xyz", ctypes.c_void_p), ("n", ctypes.c_int64), ("p", GraphParams)]
+    _fields_ = [("xyz", ctypes.c_void_p), ("n", ctypes.c_int64), ("weights", ctypes.c_void_p),
+                ("p", GraphParams), ("kind", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
-    _fields_ = [("status", ctypes.c_int32), ("error", ctypes.c_int32), ("n_triangles", ctypes.c_uint64),
-                ("hist", ctypes.c_void_p), ("t_queue_s", ctypes.c_double), ("t_build_s", ctypes.c_double),
-                ("t_count_s", ctypes.c_double), ("t_total_s", ctypes.c_double),
-                ("step_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+    _fields_ = [("status", ctypes.c_int32), ("error", ctypes.c_int32), ("n_tuples", ctypes.c_uint64),
+                ("hist", ctypes.c_void_p), ("pos", ctypes.c_void_p), ("neg", ctypes.c_void_p),
+                ("wsum128", ctypes.c_void_p), ("whist", ctypes.c_void_p), ("wscale", ctypes.c_int32),
+                ("step_size", ctypes.c_uint32), ("t_queue_s", ctypes.c_double),
+                ("t_build_s", ctypes.c_double), ("t_count_s", ctypes.c_double), ("t_total_s", ctypes.c_double)]
 
 
 class GsError(RuntimeError):
@@ -117,6 +122,9 @@ def load(path: str = LIB_PATH):
         "gs_graph_free": ([P], i32),
         "gs_count_3pcf": ([P, P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_count_4pcf_parity": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
+        "gs_ceiling_copy": ([P, u64, ctypes.POINTER(ctypes.c_double)], i32),
+        "gs_ceiling_probe": ([P, i32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, i32, i32, i32,
+                              ctypes.POINTER(ctypes.c_double)], i32),
         "gs_count_3pcf_batch": ([P, P, i32, P, P], i32),
         "gs_tune_3pcf": ([P, P, ctypes.c_uint32, ctypes.POINTER(Plan3)], i32),
         "gs_submit": ([P, ctypes.POINTER(Request), ctypes.POINTER(u64)], i32),
@@ -262,33 +270,67 @@ class Context:
                "gs_count_3pcf_batch")
         return [Count3(hs[k], int(nt[k]), None, None, None) for k in range(ng)]
 
-    def submit(self, xyz, box, rmin, rmax, nbins) -> int:
-        """Queue a triangle count of host catalogue xyz; returns a ticket."""
+    def submit(self, xyz, box, rmin, rmax, nbins, weights=None, kind=GS_3PCF) -> int:
+        """Queue a count of host catalogue xyz (triangles, weighted triangles
+        with `weights`, or parity 4-cliques with kind=GS_4PCF_PARITY);
+        returns a ticket."""
         x = _host(xyz, np.float64)
         if x.ndim != 2 or x.shape[1] != 3:
             raise ValueError("xyz must be (N,3)")
+        w = None if weights is None else _host(weights, np.float64)
+        if w is not None and w.shape != (x.shape[0],):
+            raise ValueError("weights must be (N,)")
         req = Request(ctypes.c_void_p(x.ctypes.data), x.shape[0],
-                      GraphParams(float(box), float(rmin), float(rmax), int(nbins), 0))
+                      None if w is None else ctypes.c_void_p(w.ctypes.data),
+                      GraphParams(float(box), float(rmin), float(rmax), int(nbins),
+                                  GS_WEIGHTED if w is not None else 0), int(kind), 0)
         t = ctypes.c_uint64()
         _check(load().gs_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "gs_submit")
         return int(t.value)
 
     def poll(self, ticket: int, nbins: int):
-        """None while pending; else a dict with status, histogram and timings
-        (the ticket is retired)."""
-        hist = np.zeros(n_configs(nbins), dtype=np.uint64)
+        """None while pending; else a dict with status, counts and timings
+        (the ticket is retired). hist is the triangle histogram or the parity
+        even channel; pos / neg (parity) and wsum / whist / wscale (weighted
+        triangles) are filled for those kinds."""
+        nc = n_configs(nbins)
+        hist, pos, neg = (np.zeros(nc, dtype=np.uint64) for _ in range(3))
+        wsum = np.zeros((nc, 2), dtype=np.uint64)
+        whist = np.zeros(nc, dtype=np.float64)
         r = Result()
         r.hist = hist.ctypes.data
+        r.pos = pos.ctypes.data
+        r.neg = neg.ctypes.data
+        r.wsum128 = wsum.ctypes.data
+        r.whist = whist.ctypes.data
         _check(load().gs_poll(self._h, ticket, ctypes.byref(r)), "gs_poll")
         if r.status == GS_PENDING:
             return None
-        return dict(status=int(r.status), error=int(r.error), n_triangles=int(r.n_triangles),
-                    hist=hist if r.status == GS_DONE else None, t_queue_s=r.t_queue_s,
-                    t_build_s=r.t_build_s, t_count_s=r.t_count_s, t_total_s=r.t_total_s,
-                    step_size=int(r.step_size))
+        done = r.status == GS_DONE
+        return dict(status=int(r.status), error=int(r.error), n_tuples=int(r.n_tuples),
+                    n_triangles=int(r.n_tuples), hist=hist if done else None, pos=pos if done else None,
+                    neg=neg if done else None, wsum=wsum if done else None, whist=whist if done else None,
+                    wscale=int(r.wscale), t_queue_s=r.t_queue_s, t_build_s=r.t_build_s,
+                    t_count_s=r.t_count_s, t_total_s=r.t_total_s, step_size=int(r.step_size))
 
     def cancel(self, ticket: int):
         _check(load().gs_cancel(self._h, ticket), "gs_cancel")
+
+    def ceiling_copy(self, nbytes: int) -> float:
+        """Attainable device copy bandwidth, GB/s (read + written)."""
+        v = ctypes.c_double()
+        _check(load().gs_ceiling_copy(self._h, int(nbytes), ctypes.byref(v)), "gs_ceiling_copy")
+        return v.value
+
+    def ceiling_probe(self, nbins, table_log2, keys_in_table, hit_rate, weighted=False, probe=True,
+                      block=256) -> float:
+        """Attainable candidates/s of the triangle count's probe work (or of
+        its LDS histogram alone with probe=False)."""
+        v = ctypes.c_double()
+        _check(load().gs_ceiling_probe(self._h, int(nbins), int(table_log2), int(keys_in_table),
+                                       float(hit_rate), int(bool(weighted)), int(bool(probe)), int(block),
+                                       ctypes.byref(v)), "gs_ceiling_probe")
+        return v.value
 
     def timings(self) -> Timings:
         t = Timings()

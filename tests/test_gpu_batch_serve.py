@@ -245,3 +245,56 @@ def test_serving_stream_catalogues_against_stored_oracle(gsn):
         assert res[t]["status"] == gsn.GS_DONE
         assert res[t]["n_triangles"] == c["n_triangles"]
         assert res[t]["hist"].tolist() == c["hist"]
+
+
+def test_serving_mixed_kinds_against_oracle(gsn):
+    """A stream mixing plain triangle counts, exact weighted triangle sums and
+    parity-decomposed 4-clique counts, arriving over several steps: every
+    result equals the oracle's (bit for bit, 128-bit weighted sums too)."""
+    cats = catalogues(12, 17, lo=2_000, hi=12_000)
+    kinds = []
+    reqs = []
+    for k, x in enumerate(cats):
+        kind = ("3pcf", "w3pcf", "4pcf")[k % 3]
+        w = synth.uniform_values(len(x), 0.5, 1.0, 1700 + k) if kind == "w3pcf" else None
+        kinds.append(kind)
+        reqs.append((x, w))
+    rmax4 = 6.0
+    with gsn.Context(0) as s:
+        say("serving mixed kinds", len(cats))
+        ts = []
+        for k, ((x, w), kind) in enumerate(zip(reqs, kinds)):
+            if kind == "4pcf":
+                ts.append(s.submit(x, L, 0.0, rmax4, NB, kind=gsn.GS_4PCF_PARITY))
+            else:
+                ts.append(s.submit(x, L, 0.0, RMAX, NB, weights=w))
+            if k % 4 == 3:
+                time.sleep(0.005)
+        res = drain(s, ts)
+    for t, (x, w), kind in zip(ts, reqs, kinds):
+        r = res[t]
+        assert r["status"] == gsn.GS_DONE, (kind, r)
+        if kind == "4pcf":
+            ref = oracle.count_4pcf_parity(x, L, 0.0, rmax4, NB)
+            assert r["n_tuples"] == ref.n_cliques
+            assert np.array_equal(r["hist"], ref.even)
+            assert np.array_equal(r["pos"], ref.pos) and np.array_equal(r["neg"], ref.neg)
+        else:
+            ref = oracle.count_3pcf(x, L, 0.0, RMAX, NB, weights=w)
+            assert r["n_tuples"] == ref.n_triangles
+            assert np.array_equal(r["hist"], ref.hist)
+            if kind == "w3pcf":
+                assert r["wscale"] == ref.wscale
+                assert np.array_equal(r["wsum"], ref.wsum)
+                assert np.array_equal(r["whist"], ref.whist())
+
+
+def test_serving_rejects_bad_kinds(gsn):
+    x = synth.uniform(1000, L, 19)
+    with gsn.Context(0) as s:
+        with pytest.raises(gsn.GsError) as e:
+            s.submit(x, L, 0.0, RMAX, NB, kind=7)
+        assert e.value.code == gsn.GS_EINVAL
+        with pytest.raises(gsn.GsError) as e:
+            s.submit(x, L, 0.0, RMAX, NB, weights=np.ones(len(x)), kind=gsn.GS_4PCF_PARITY)
+        assert e.value.code == gsn.GS_EINVAL
