@@ -56,6 +56,12 @@ def _load():
         lib.oracle_count_3pcf.restype = i32
         lib.oracle_count_4pcf_parity.argtypes = [P, i64, d, d, d, i32, i64, i64, i32, P, P, P, P, P]
         lib.oracle_count_4pcf_parity.restype = i32
+        lib.oracle_n_configs6.argtypes = [i32]
+        lib.oracle_n_configs6.restype = i64
+        lib.oracle_config6.argtypes = [i32, i64, P]
+        lib.oracle_config6.restype = i32
+        lib.oracle_count_4pcf_full.argtypes = [P, i64, d, d, d, i32, i64, i64, i32, P, P, P]
+        lib.oracle_count_4pcf_full.restype = i32
         _lib = lib
     return _lib
 
@@ -192,3 +198,45 @@ def count_4pcf_parity(xyz, box, rmin, rmax, nbins, anchors=None, threads=0) -> R
     if rc:
         raise OracleError(rc)
     return Result4(e, p, m, int(nk[0]), int(used[0]))
+
+
+def n_configs6(nbins: int) -> int:
+    """Number of 6-edge 4-clique configurations (edge-bin tuples up to
+    relabelling of the four vertices) over nbins bins (nbins <= 12)."""
+    r = int(_load().oracle_n_configs6(nbins))
+    if r < 0:
+        raise OracleError(r if r == -3 else -1)
+    return r
+
+
+def config6(nbins: int, index: int):
+    """The smallest edge-bin tuple (b01, b02, b03, b12, b13, b23) of
+    configuration `index`."""
+    out = np.zeros(6, dtype=np.int32)
+    rc = _load().oracle_config6(nbins, index, _p(out))
+    if rc:
+        raise OracleError(rc)
+    return tuple(int(v) for v in out)
+
+
+@dataclass
+class Result6:
+    hist: np.ndarray   # uint64[n_configs6]
+    n_cliques: int
+    threads: int
+
+
+def count_4pcf_full(xyz, box, rmin, rmax, nbins, anchors=None, threads=0) -> Result6:
+    """Every 4-clique once, binned by the configuration of its six edge bins."""
+    x = _xyz(xyz)
+    n = x.shape[0]
+    lo, hi = (0, n) if anchors is None else anchors
+    nc = n_configs6(nbins) if 1 <= nbins <= 12 else 1
+    h = np.zeros(nc, dtype=np.uint64)
+    nk = np.zeros(1, dtype=np.uint64)
+    used = np.zeros(1, dtype=np.int32)
+    rc = _load().oracle_count_4pcf_full(_p(x), n, box, rmin, rmax, nbins, lo, hi, threads, _p(h), _p(nk),
+                                        _p(used))
+    if rc:
+        raise OracleError(rc)
+    return Result6(h, int(nk[0]), int(used[0]))

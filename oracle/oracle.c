@@ -38,6 +38,15 @@
  *    qa == qb or qb == qc or V*V <= 1e-18*((qa*qb)*qc) (the paper's |V| < 1e-9
  *    taken on the normalised volume); otherwise V > 0 -> pos, V < 0 -> neg.
  *
+ * D8 6-edge 4pCF (the full four-point configurations of Sec. 3.3 and Sec.
+ *    5.3): every 4-clique counts once into the configuration of its six
+ *    edge bins. A vertex ordering (p0,p1,p2,p3) of the clique gives the tuple
+ *    of the bins of edges (p0p1, p0p2, p0p3, p1p2, p1p3, p2p3); the
+ *    configuration is the lexicographically smallest tuple over the 24
+ *    orderings (its class under relabelling of the four vertices), and
+ *    configurations are indexed by their rank in lexicographic order among
+ *    all such smallest tuples.
+ *
  * Anchors: only tuples whose smallest original point index lies in
  * [anchor_lo, anchor_hi) are counted.
  */
@@ -467,6 +476,155 @@ static void hub_parity(const params_t *p, const double *xyz, int64_t h, const in
     if (V * V <= 1e-18 * ((qa * qb) * qc)) return;
     if (V > 0) P[idx] += 1;
     else N[idx] += 1;
+}
+
+/* ------------------------------------------------ 6-edge configurations -- */
+
+#define OR_MAX_BINS6 12
+
+static const int k_edge[4][4] = {{-1, 0, 1, 2}, {0, -1, 3, 4}, {1, 3, -1, 5}, {2, 4, 5, -1}};
+
+/* the smallest edge-bin tuple over the 24 orderings of the four vertices */
+static void canon6(const int t[6], int out[6]) {
+    int first = 1;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+            for (int c = 0; c < 4; ++c)
+                for (int d = 0; d < 4; ++d) {
+                    if (a == b || a == c || a == d || b == c || b == d || c == d) continue;
+                    const int p[4] = {a, b, c, d};
+                    int u[6], e = 0;
+                    for (int x = 0; x < 4; ++x)
+                        for (int y = x + 1; y < 4; ++y) u[e++] = t[k_edge[p[x]][p[y]]];
+                    int less = first;
+                    for (int k = 0; k < 6 && !first; ++k)
+                        if (u[k] != out[k]) { less = u[k] < out[k]; break; }
+                    if (less) memcpy(out, u, sizeof u);
+                    first = 0;
+                }
+}
+
+static int64_t tuple_code(int nb, const int t[6]) {
+    int64_t c = 0;
+    for (int k = 0; k < 6; ++k) c = c * nb + t[k];
+    return c;
+}
+
+/* rank of every tuple's configuration (index nb^6 by tuple code); the
+ * number of configurations in *n6 */
+static int32_t *config6_table(int nb, int64_t *n6) {
+    const int64_t n = (int64_t)nb * nb * nb * nb * nb * nb;
+    int32_t *rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!rank) return NULL;
+    int64_t r = 0;
+    /* codes in increasing order are tuples in lexicographic order */
+    for (int64_t code = 0; code < n; ++code) {
+        int t[6], u[6];
+        int64_t v = code;
+        for (int k = 5; k >= 0; --k) { t[k] = (int)(v % nb); v /= nb; }
+        canon6(t, u);
+        rank[code] = (tuple_code(nb, u) == code) ? (int32_t)r++ : -1;
+    }
+    for (int64_t code = 0; code < n; ++code) {
+        if (rank[code] >= 0) continue;
+        int t[6], u[6];
+        int64_t v = code;
+        for (int k = 5; k >= 0; --k) { t[k] = (int)(v % nb); v /= nb; }
+        canon6(t, u);
+        rank[code] = rank[tuple_code(nb, u)];
+    }
+    *n6 = r;
+    return rank;
+}
+
+int64_t oracle_n_configs6(int nbins) {
+    if (nbins < 1 || nbins > OR_MAX_BINS6) return -1;
+    int64_t n6 = 0;
+    int32_t *t = config6_table(nbins, &n6);
+    if (!t) return -3;
+    free(t);
+    return n6;
+}
+
+/* the smallest tuple of configuration `index` */
+int oracle_config6(int nbins, int64_t index, int *out) {
+    if (nbins < 1 || nbins > OR_MAX_BINS6) return OR_EINVAL;
+    const int64_t n = (int64_t)nbins * nbins * nbins * nbins * nbins * nbins;
+    int64_t r = 0;
+    for (int64_t code = 0; code < n; ++code) {
+        int t[6], u[6];
+        int64_t v = code;
+        for (int k = 5; k >= 0; --k) { t[k] = (int)(v % nbins); v /= nbins; }
+        canon6(t, u);
+        if (tuple_code(nbins, u) != code) continue;
+        if (r++ == index) {
+            memcpy(out, t, sizeof t);
+            return OR_OK;
+        }
+    }
+    return OR_EINVAL;
+}
+
+int oracle_count_4pcf_full(const double *xyz, int64_t n, double box, double rmin, double rmax, int nbins,
+                           int64_t anchor_lo, int64_t anchor_hi, int nthreads, uint64_t *hist6,
+                           uint64_t *n_cliques, int *threads_used) {
+    params_t p;
+    int rc = make_params(&p, box, rmin, rmax, nbins);
+    if (rc == OR_OK) rc = check_points(xyz, n, box);
+    if (rc != OR_OK) return rc;
+    if (n >= ((int64_t)1 << 31) || !hist6 || !n_cliques || nbins > OR_MAX_BINS6) return OR_EINVAL;
+    if (anchor_lo < 0) anchor_lo = 0;
+    if (anchor_hi > n) anchor_hi = n;
+    int64_t n6 = 0;
+    int32_t *rank = config6_table(nbins, &n6);
+    if (!rank) return OR_ENOMEM;
+    int nt = resolve_threads(nthreads);
+    if (threads_used) *threads_used = nt;
+    rows_t g;
+    rc = rows_for_anchors(&p, xyz, n, nt, anchor_lo, anchor_hi, &g);
+    if (rc != OR_OK) { free(rank); return rc; }
+    uint64_t *tH = (uint64_t *)calloc((size_t)(nt * n6), sizeof(uint64_t));
+    uint64_t *tn = (uint64_t *)calloc((size_t)nt, sizeof(uint64_t));
+    if (!tH || !tn) { free(tH); free(tn); free(rank); rows_free(&g); return OR_ENOMEM; }
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = omp_get_thread_num();
+        uint64_t *H = tH + (int64_t)tid * n6;
+        uint64_t cnt = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = anchor_lo; i < anchor_hi; ++i) {
+            for (int64_t a = g.ptr[i]; a < g.ptr[i + 1]; ++a) {
+                int32_t j = g.col[a];
+                if (j <= i) continue;
+                for (int64_t b = a + 1; b < g.ptr[i + 1]; ++b) {
+                    int32_t k = g.col[b];
+                    int64_t fjk = find(&g, j, k);
+                    if (fjk < 0) continue;
+                    for (int64_t c = b + 1; c < g.ptr[i + 1]; ++c) {
+                        int32_t l = g.col[c];
+                        int64_t fjl = find(&g, j, l), fkl = find(&g, k, l);
+                        if (fjl < 0 || fkl < 0) continue;
+                        ++cnt;
+                        /* vertices (i, j, k, l): edges ij, ik, il, jk, jl, kl */
+                        const int t[6] = {g.bin[a], g.bin[b], g.bin[c], g.bin[fjk], g.bin[fjl], g.bin[fkl]};
+                        H[rank[tuple_code(nbins, t)]] += 1;
+                    }
+                }
+            }
+        }
+        tn[tid] = cnt;
+    }
+    memset(hist6, 0, sizeof(uint64_t) * (size_t)n6);
+    *n_cliques = 0;
+    for (int t = 0; t < nt; ++t) {
+        *n_cliques += tn[t];
+        for (int64_t c = 0; c < n6; ++c) hist6[c] += tH[(int64_t)t * n6 + c];
+    }
+    free(tH);
+    free(tn);
+    free(rank);
+    rows_free(&g);
+    return OR_OK;
 }
 
 int oracle_count_4pcf_parity(const double *xyz, int64_t n, double box, double rmin, double rmax,

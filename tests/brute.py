@@ -119,3 +119,47 @@ def cliques4(xyz, L, rmin, rmax, nb, anchors=None):
                         else:
                             N[r] += 1
     return E, P, N, count
+
+
+_EDGES6 = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+
+
+def canonical6(t):
+    """Smallest edge-bin tuple over the 24 vertex orderings (itertools)."""
+    import itertools
+    pos = {e: k for k, e in enumerate(_EDGES6)}
+    best = None
+    for p in itertools.permutations(range(4)):
+        u = tuple(t[pos[tuple(sorted((p[a], p[b])))]] for a, b in _EDGES6)
+        if best is None or u < best:
+            best = u
+    return best
+
+
+def configs6(nb):
+    """All 6-edge configurations in lexicographic order -> {tuple: rank}."""
+    import itertools
+    c = sorted({canonical6(t) for t in itertools.product(range(nb), repeat=6)})
+    return {t: k for k, t in enumerate(c)}
+
+
+def cliques4_six(xyz, L, rmin, rmax, nb, anchors=None):
+    """Histogram of 4-cliques by their 6-edge configuration, and the count."""
+    n = len(xyz)
+    _, _, adj, b = pair_matrix(xyz, L, rmin, rmax, nb)
+    rank = configs6(nb)
+    H = np.zeros(len(rank), dtype=np.int64)
+    lo, hi = (0, n) if anchors is None else anchors
+    count = 0
+    for i in range(lo, hi):
+        for j in range(i + 1, n):
+            if not adj[i, j]:
+                continue
+            common = adj[i] & adj[j]
+            for k in [k for k in np.nonzero(common)[0] if k > j]:
+                for l in [l for l in np.nonzero(common & adj[k])[0] if l > k]:
+                    v = (i, j, int(k), int(l))
+                    t = tuple(int(b[v[x], v[y]]) for x, y in _EDGES6)
+                    H[rank[canonical6(t)]] += 1
+                    count += 1
+    return H, count

@@ -484,3 +484,88 @@ def test_degenerate_rule_zero_length_spoke(golden_dir):
     r3 = oracle.count_3pcf(x, L, rmin, rmax, nb)
     assert np.array_equal(r3.hist.astype(np.int64),
                           4 * _units.expected_triangles(nb, oracle.config_index, c["triangle_configs"]))
+
+
+# ------------------------------------------------------ 6-edge 4pCF (D8) -----
+
+@pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 6, 8])
+def test_six_edge_configuration_count_is_burnside(nb):
+    # edge colourings of K4 up to relabelling: (k^6 + 9 k^4 + 14 k^2) / 24
+    assert oracle.n_configs6(nb) == (nb ** 6 + 9 * nb ** 4 + 14 * nb ** 2) // 24
+
+
+@pytest.mark.parametrize("nb", [1, 2, 3, 4])
+def test_six_edge_configuration_rank_is_lexicographic(nb):
+    rank = brute.configs6(nb)
+    assert len(rank) == oracle.n_configs6(nb)
+    for t, r in rank.items():
+        assert oracle.config6(nb, r) == t
+
+
+def test_six_edge_counts_printed_in_paper(golden_dir):
+    g = _golden(golden_dir, "paper_config_counts.json")["six_edge"]
+    nb = g["nbins"]
+    assert oracle.n_configs6(nb) == g["configurations"]
+    w = (g["rmax"] - g["rmin"]) / nb
+    cen = [g["rmin"] + (k + 0.5) * w for k in range(nb)]
+    edges = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    realizable = 0
+    for idx in range(g["configurations"]):
+        t = oracle.config6(nb, idx)
+        m = np.ones((5, 5))
+        m[0, 0] = 0.0
+        d = np.zeros((4, 4))
+        for (a, b), k in zip(edges, t):
+            d[a, b] = d[b, a] = cen[k] ** 2
+        m[1:, 1:] = d
+        realizable += np.linalg.det(m) > 0      # 288 V^2 > 0
+    assert realizable == g["realizable"]
+
+
+@pytest.mark.parametrize("case", TINY4, ids=[c[0] for c in TINY4])
+def test_oracle_4pcf_full_matches_brute_force(case):
+    _, mk, L, rmin, rmax, nb = case
+    x = mk()
+    H, cnt = brute.cliques4_six(x, L, rmin, rmax, nb)
+    r = oracle.count_4pcf_full(x, L, rmin, rmax, nb, threads=3)
+    assert cnt > 20 and r.n_cliques == cnt
+    assert np.array_equal(r.hist.astype(np.int64), H)
+    assert r.n_cliques == oracle.count_4pcf_parity(x, L, rmin, rmax, nb).n_cliques
+
+
+def test_oracle_4pcf_full_anchor_split():
+    x = synth.neyman_scott(110, 22, 0.7, 10.0, 32)
+    full = oracle.count_4pcf_full(x, 10.0, 0.0, 2.0, 5)
+    acc = np.zeros_like(full.hist)
+    for lo, hi in [(0, 30), (30, 31), (31, 110)]:
+        r = oracle.count_4pcf_full(x, 10.0, 0.0, 2.0, 5, anchors=(lo, hi))
+        H, cnt = brute.cliques4_six(x, 10.0, 0.0, 2.0, 5, anchors=(lo, hi))
+        assert r.n_cliques == cnt and np.array_equal(r.hist.astype(np.int64), H)
+        acc += r.hist
+    assert np.array_equal(acc, full.hist)
+
+
+@pytest.mark.parametrize("shift", [(0.0, 0.0, 0.0), (0.25, 0.5, 0.125)])
+def test_lattice_six_edge_closed_form(golden_dir, shift):
+    g = _golden(golden_dir, "lattice_sc.json")
+    x = _lattice(g, shift)
+    nb = g["nbins"]
+    r = oracle.count_4pcf_full(x, g["box"], g["rmin"], g["rmax"], nb)
+    rank = brute.configs6(nb)
+    exp = np.zeros(oracle.n_configs6(nb), dtype=np.int64)
+    for key, v in g["six_edge_configs_per_site"].items():
+        exp[rank[tuple(map(int, key.split(",")))]] = v * len(x)
+    assert r.n_cliques == g["cliques_per_site"] * len(x)
+    assert np.array_equal(r.hist.astype(np.int64), exp)
+
+
+def test_six_edge_invariant_under_relabelling_and_reflection():
+    L = 16.0
+    x = synth.dyadic_uniform(700, L, 41)
+    p = synth.permutation(len(x), 46)
+    y = x.copy()
+    y[:, 0] = np.mod(L - y[:, 0], L)
+    a = oracle.count_4pcf_full(x, L, 0.0, 2.2, 4)
+    assert a.n_cliques > 100
+    assert np.array_equal(a.hist, oracle.count_4pcf_full(x[p], L, 0.0, 2.2, 4).hist)
+    assert np.array_equal(a.hist, oracle.count_4pcf_full(y, L, 0.0, 2.2, 4).hist)
