@@ -54,13 +54,15 @@ def _load():
         lib.oracle_graph.restype = i32
         lib.oracle_count_3pcf.argtypes = [P, i64, P, d, d, d, i32, i64, i64, i32, P, P, P, P, P]
         lib.oracle_count_3pcf.restype = i32
-        lib.oracle_count_4pcf_parity.argtypes = [P, i64, d, d, d, i32, i64, i64, i32, P, P, P, P, P]
+        lib.oracle_count_4pcf_parity.argtypes = [P, i64, P, d, d, d, i32, i64, i64, i32, P, P, P, P, P, P, P]
         lib.oracle_count_4pcf_parity.restype = i32
         lib.oracle_n_configs6.argtypes = [i32]
         lib.oracle_n_configs6.restype = i64
         lib.oracle_config6.argtypes = [i32, i64, P]
         lib.oracle_config6.restype = i32
-        lib.oracle_count_4pcf_full.argtypes = [P, i64, d, d, d, i32, i64, i64, i32, P, P, P]
+        lib.oracle_count_4pcf_full.argtypes = [P, i64, P, d, d, d, i32, i64, i64, i32, P, P, P, P, P]
+        lib.oracle_pair_sums.argtypes = [P, i64, P, d, d, d, i32, i64, i64, P, P, P]
+        lib.oracle_pair_sums.restype = i32
         lib.oracle_count_4pcf_full.restype = i32
         _lib = lib
     return _lib
@@ -131,6 +133,46 @@ def graph(xyz, box, rmin, rmax, nbins):
     return rp, col[:E], b[:E]
 
 
+def signed128(words) -> list:
+    """(lo, hi) word pairs of two's-complement 128-bit sums -> Python ints."""
+    out = []
+    for lo, hi in np.asarray(words, dtype=np.uint64).reshape(-1, 2):
+        v = int(lo) + (int(hi) << 64)
+        out.append(v - (1 << 128) if v >> 127 else v)
+    return out
+
+
+def rounded(values, scale) -> np.ndarray:
+    """Exact integers in units of 2^-scale, each rounded once to float64."""
+    import math
+    return np.array([math.ldexp(float(v), -scale) for v in values])
+
+
+@dataclass
+class Result2:
+    pairs: np.ndarray           # uint64[nbins]
+    wsum: np.ndarray | None     # uint64[nbins, 2]
+    wscale: int | None
+
+    def wsum_int(self):
+        return signed128(self.wsum)
+
+
+def pair_sums(xyz, box, rmin, rmax, nbins, weights=None, anchors=None) -> Result2:
+    """Edges per bin and, with weights, the exact per-bin sums of w_i*w_j."""
+    x = _xyz(xyz)
+    n = x.shape[0]
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    lo, hi = (0, n) if anchors is None else anchors
+    pairs = np.zeros(max(nbins, 1), dtype=np.uint64)
+    wsum = np.zeros((max(nbins, 1), 2), dtype=np.uint64) if w is not None else None
+    ws = np.zeros(1, dtype=np.int32)
+    rc = _load().oracle_pair_sums(_p(x), n, _p(w), box, rmin, rmax, nbins, lo, hi, _p(pairs), _p(wsum), _p(ws))
+    if rc:
+        raise OracleError(rc)
+    return Result2(pairs, wsum, int(ws[0]) if w is not None else None)
+
+
 @dataclass
 class Result3:
     hist: np.ndarray            # uint64[n_configs]
@@ -141,13 +183,11 @@ class Result3:
 
     def wsum_int(self):
         """Exact weighted sums as Python ints (units of 2^-wscale)."""
-        return [int(lo) + (int(hi) << 64) for lo, hi in self.wsum]
+        return signed128(self.wsum)
 
     def whist(self) -> np.ndarray:
         """Weighted sums rounded once to float64."""
-        import math
-        return np.array([math.ldexp(float(v), -self.wscale) if v < (1 << 1023) else float("inf")
-                         for v in self.wsum_int()])
+        return rounded(self.wsum_int(), self.wscale)
 
 
 def count_3pcf(xyz, box, rmin, rmax, nbins, weights=None, anchors=None, threads=0) -> Result3:
@@ -177,27 +217,36 @@ class Result4:
     neg: np.ndarray    # uint64[n_configs]: V < 0, non-degenerate
     n_cliques: int
     threads: int
+    wsum: np.ndarray | None = None   # uint64[3, n_configs, 2]: even | pos | neg weighted sums
+    wscale: int | None = None
 
     @property
     def odd(self) -> np.ndarray:
         return self.pos.astype(np.int64) - self.neg.astype(np.int64)
 
+    def wsum_int(self, channel: int):
+        """Exact weighted sums of one channel (0 even, 1 pos, 2 neg)."""
+        return signed128(self.wsum[channel])
 
-def count_4pcf_parity(xyz, box, rmin, rmax, nbins, anchors=None, threads=0) -> Result4:
+
+def count_4pcf_parity(xyz, box, rmin, rmax, nbins, anchors=None, threads=0, weights=None) -> Result4:
     x = _xyz(xyz)
     n = x.shape[0]
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
     lo, hi = (0, n) if anchors is None else anchors
     nc = n_configs(nbins) if 1 <= nbins <= 255 else 1
     e = np.zeros(nc, dtype=np.uint64)
     p = np.zeros(nc, dtype=np.uint64)
     m = np.zeros(nc, dtype=np.uint64)
+    ws = np.zeros((3, nc, 2), dtype=np.uint64) if w is not None else None
+    sc = np.zeros(1, dtype=np.int32)
     nk = np.zeros(1, dtype=np.uint64)
     used = np.zeros(1, dtype=np.int32)
-    rc = _load().oracle_count_4pcf_parity(_p(x), n, box, rmin, rmax, nbins, lo, hi, threads,
-                                          _p(e), _p(p), _p(m), _p(nk), _p(used))
+    rc = _load().oracle_count_4pcf_parity(_p(x), n, _p(w), box, rmin, rmax, nbins, lo, hi, threads,
+                                          _p(e), _p(p), _p(m), _p(ws), _p(sc), _p(nk), _p(used))
     if rc:
         raise OracleError(rc)
-    return Result4(e, p, m, int(nk[0]), int(used[0]))
+    return Result4(e, p, m, int(nk[0]), int(used[0]), ws, int(sc[0]) if w is not None else None)
 
 
 def n_configs6(nbins: int) -> int:
@@ -224,19 +273,28 @@ class Result6:
     hist: np.ndarray   # uint64[n_configs6]
     n_cliques: int
     threads: int
+    wsum: np.ndarray | None = None   # uint64[n_configs6, 2]
+    wscale: int | None = None
+
+    def wsum_int(self):
+        return signed128(self.wsum)
 
 
-def count_4pcf_full(xyz, box, rmin, rmax, nbins, anchors=None, threads=0) -> Result6:
-    """Every 4-clique once, binned by the configuration of its six edge bins."""
+def count_4pcf_full(xyz, box, rmin, rmax, nbins, anchors=None, threads=0, weights=None) -> Result6:
+    """Every 4-clique once, binned by the configuration of its six edge bins
+    (with weights: the exact sums of ((w1*w2)*w3)*w4, ascending values)."""
     x = _xyz(xyz)
     n = x.shape[0]
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
     lo, hi = (0, n) if anchors is None else anchors
     nc = n_configs6(nbins) if 1 <= nbins <= 12 else 1
     h = np.zeros(nc, dtype=np.uint64)
+    ws = np.zeros((nc, 2), dtype=np.uint64) if w is not None else None
+    sc = np.zeros(1, dtype=np.int32)
     nk = np.zeros(1, dtype=np.uint64)
     used = np.zeros(1, dtype=np.int32)
-    rc = _load().oracle_count_4pcf_full(_p(x), n, box, rmin, rmax, nbins, lo, hi, threads, _p(h), _p(nk),
-                                        _p(used))
+    rc = _load().oracle_count_4pcf_full(_p(x), n, _p(w), box, rmin, rmax, nbins, lo, hi, threads, _p(h),
+                                        _p(ws), _p(sc), _p(nk), _p(used))
     if rc:
         raise OracleError(rc)
-    return Result6(h, int(nk[0]), int(used[0]))
+    return Result6(h, int(nk[0]), int(used[0]), ws, int(sc[0]) if w is not None else None)

@@ -28,9 +28,15 @@
  * D5 3pCF: every unordered triangle (all three pairs edges) counts once into
  *    the bin of its sorted side bins b1 <= b2 <= b3, indexed lexicographically
  *    (the sorted-side configurations r1 <= r2 <= r3 of Sec. 5; C(nb+2,3) of
- *    them). Weighted: t = (w1*w2)*w3 with the three weights in ascending
- *    order; per bin the exact sum of t as a 128-bit integer multiple of
- *    2^-s, where s = 52 - floor(log2(((wmin*wmin)*wmin))).
+ *    them). Weighted: t = +-(a1*a2)*a3 with a1 <= a2 <= a3 the three weight
+ *    magnitudes in ascending order and the sign the product of the weights'
+ *    signs; per bin the exact sum of t as a signed 128-bit integer multiple
+ *    of 2^-s, where s = 52 - floor(log2(((m*m)*m))) and m is the smallest
+ *    weight magnitude. Weights are finite and nonzero, of either sign: the
+ *    signed, normalised data-minus-random weights of Sec. 2.1. (For
+ *    positive weights: the product of the weights in ascending order.)
+ * D4w weighted pairs (the internal 2pCF of Sec. 3.3): per bin the exact sum
+ *    over edges of w_i*w_j, in units of 2^-s2, s2 = 52 - floor(log2(m*m)).
  * D6 4pCF parity (Sec. 3.2, Eq. 2 and the degenerate rule): every 4-clique
  *    contributes once per hub h (each of its four vertices): spokes r = sep(h,.)
  *    ordered by q (qa <= qb <= qc); even[idx(bins)] += 1; c = ra x rb,
@@ -61,6 +67,7 @@
 #define OR_ENOMEM (-3)
 
 typedef unsigned __int128 u128;
+typedef __int128 i128;
 
 typedef struct {
     double L, half, rmin, rmax;
@@ -345,21 +352,94 @@ int oracle_graph(const double *xyz, int64_t n, double box, double rmin, double r
     return OR_OK;
 }
 
-/* scale s of the exact weighted sums: every product t >= t_lo is an integer
- * multiple of 2^-s. Rejects weights whose products would not fit 64 bits. */
-static int weight_scale(const double *w, int64_t n, int *s_out) {
+/* scale s of the exact weighted sums of products of k weights: every product
+ * of magnitude at least (((m*m)*m)...) (k factors of the smallest weight
+ * magnitude m) is an integer multiple of 2^-s. Rejects zero or non-finite
+ * weights and ranges whose scaled products would not leave room for 2^40
+ * terms in a signed 128-bit sum. */
+static int weight_scale_k(const double *w, int64_t n, int k, int *s_out) {
     double wmin = INFINITY, wmax = 0.0;
     for (int64_t i = 0; i < n; ++i) {
-        if (!(w[i] > 0.0) || !isfinite(w[i])) return OR_EINVAL;
-        if (w[i] < wmin) wmin = w[i];
-        if (w[i] > wmax) wmax = w[i];
+        const double a = fabs(w[i]);
+        if (!(a > 0.0) || !isfinite(a)) return OR_EINVAL;
+        if (a < wmin) wmin = a;
+        if (a > wmax) wmax = a;
     }
     if (n == 0) { *s_out = 0; return OR_OK; }
-    double tlo = (wmin * wmin) * wmin, thi = (wmax * wmax) * wmax;
+    double tlo = wmin, thi = wmax;
+    for (int j = 1; j < k; ++j) { tlo = tlo * wmin; thi = thi * wmax; }
     if (!(tlo >= 0x1.0p-1022) || !isfinite(thi)) return OR_EINVAL;
     int s = 52 - ilogb(tlo);
-    if (ilogb(thi) + s >= 64) return OR_EINVAL;
+    if (ilogb(thi) + s > 86) return OR_EINVAL;
     *s_out = s;
+    return OR_OK;
+}
+
+static int weight_scale(const double *w, int64_t n, int *s_out) { return weight_scale_k(w, n, 3, s_out); }
+
+/* +-((a1*a2)*...)*ak: the magnitudes of v[0..k) multiplied in ascending
+ * order, signed by the product of their signs */
+static double signed_product(const double *v, int k) {
+    double a[4];
+    int neg = 0;
+    for (int j = 0; j < k; ++j) {
+        a[j] = fabs(v[j]);
+        neg ^= v[j] < 0;
+    }
+    for (int x = 1; x < k; ++x)
+        for (int y = x; y > 0 && a[y - 1] > a[y]; --y) {
+            double t = a[y];
+            a[y] = a[y - 1];
+            a[y - 1] = t;
+        }
+    double p = a[0];
+    for (int j = 1; j < k; ++j) p = p * a[j];
+    return neg ? -p : p;
+}
+
+static void put128(uint64_t *dst, i128 v) {
+    dst[0] = (uint64_t)(u128)v;
+    dst[1] = (uint64_t)((u128)v >> 64);
+}
+
+/* D4 / D4w: pairs (edges) per bin, and with weights the exact per-bin sums
+ * of w_i*w_j (units of 2^-s2). Anchors: pairs whose smaller original index
+ * lies in [anchor_lo, anchor_hi). */
+int oracle_pair_sums(const double *xyz, int64_t n, const double *w, double box, double rmin, double rmax,
+                     int nbins, int64_t anchor_lo, int64_t anchor_hi, uint64_t *pairs, uint64_t *wsum,
+                     int *wscale) {
+    params_t p;
+    int rc = make_params(&p, box, rmin, rmax, nbins);
+    if (rc == OR_OK) rc = check_points(xyz, n, box);
+    if (rc != OR_OK) return rc;
+    if (n >= ((int64_t)1 << 31) || !pairs) return OR_EINVAL;
+    int s = 0;
+    if (w) {
+        if (!wsum) return OR_EINVAL;
+        rc = weight_scale_k(w, n, 2, &s);
+        if (rc != OR_OK) return rc;
+        if (wscale) *wscale = s;
+    }
+    if (anchor_lo < 0) anchor_lo = 0;
+    if (anchor_hi > n) anchor_hi = n;
+    rows_t g;
+    rc = rows_for_anchors(&p, xyz, n, resolve_threads(0), anchor_lo, anchor_hi, &g);
+    if (rc != OR_OK) return rc;
+    i128 *acc = (i128 *)calloc((size_t)nbins, sizeof(i128));
+    if (!acc) { rows_free(&g); return OR_ENOMEM; }
+    memset(pairs, 0, sizeof(uint64_t) * (size_t)nbins);
+    const double scale = ldexp(1.0, s);
+    for (int64_t i = anchor_lo; i < anchor_hi; ++i)
+        for (int64_t e = g.ptr[i]; e < g.ptr[i + 1]; ++e) {
+            const int32_t j = g.col[e];
+            if (j <= i) continue;
+            pairs[g.bin[e]] += 1;
+            if (w) acc[g.bin[e]] += (i128)((w[i] * w[j]) * scale);
+        }
+    if (w)
+        for (int b = 0; b < nbins; ++b) put128(&wsum[2 * b], acc[b]);
+    free(acc);
+    rows_free(&g);
     return OR_OK;
 }
 
@@ -388,7 +468,7 @@ int oracle_count_3pcf(const double *xyz, int64_t n, const double *w, double box,
     if (rc != OR_OK) return rc;
     int64_t nconf = binom3(nbins + 2);
     uint64_t *th = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));
-    u128 *tw = w ? (u128 *)calloc((size_t)(nt * nconf), sizeof(u128)) : NULL;
+    i128 *tw = w ? (i128 *)calloc((size_t)(nt * nconf), sizeof(i128)) : NULL;
     uint64_t *tn = (uint64_t *)calloc((size_t)nt, sizeof(uint64_t));
     if (!th || !tn || (w && !tw)) { free(th); free(tw); free(tn); rows_free(&g); return OR_ENOMEM; }
     double scale = ldexp(1.0, s);
@@ -397,7 +477,7 @@ int oracle_count_3pcf(const double *xyz, int64_t n, const double *w, double box,
     {
         int tid = omp_get_thread_num();
         uint64_t *H = th + (int64_t)tid * nconf;
-        u128 *Wt = w ? tw + (int64_t)tid * nconf : NULL;
+        i128 *Wt = w ? tw + (int64_t)tid * nconf : NULL;
         uint64_t cnt = 0;
 #pragma omp for schedule(dynamic, 64)
         for (int64_t i = anchor_lo; i < anchor_hi; ++i) {
@@ -414,12 +494,8 @@ int oracle_count_3pcf(const double *xyz, int64_t n, const double *w, double box,
                     H[idx] += 1;
                     ++cnt;
                     if (Wt) {
-                        double x = w[i], y = w[j], z = w[k], t;
-                        if (x > y) { t = x; x = y; y = t; }
-                        if (y > z) { t = y; y = z; z = t; }
-                        if (x > y) { t = x; x = y; y = t; }
-                        double prod = (x * y) * z;
-                        Wt[idx] += (u128)(prod * scale);
+                        const double v[3] = {w[i], w[j], w[k]};
+                        Wt[idx] += (i128)(signed_product(v, 3) * scale);
                     }
                 }
             }
@@ -434,10 +510,9 @@ int oracle_count_3pcf(const double *xyz, int64_t n, const double *w, double box,
     }
     if (w) {
         for (int64_t c = 0; c < nconf; ++c) {
-            u128 acc = 0;
+            i128 acc = 0;
             for (int t = 0; t < nt; ++t) acc += tw[(int64_t)t * nconf + c];
-            wsum[2 * c] = (uint64_t)acc;
-            wsum[2 * c + 1] = (uint64_t)(acc >> 64);
+            put128(&wsum[2 * c], acc);
         }
     }
     free(th);
@@ -447,9 +522,9 @@ int oracle_count_3pcf(const double *xyz, int64_t n, const double *w, double box,
     return OR_OK;
 }
 
-/* one hub's contribution to the parity histograms (D6) */
-static void hub_parity(const params_t *p, const double *xyz, int64_t h, const int64_t s[3],
-                       uint64_t *E, uint64_t *P, uint64_t *N) {
+/* one hub's contribution to the parity histograms (D6): its configuration
+ * in *idx; returns 0 (pos), 1 (neg) or 2 (degenerate) */
+static int hub_parity(const params_t *p, const double *xyz, int64_t h, const int64_t s[3], int64_t *idx_out) {
     double r[3][3], q[3];
     int ord[3] = {0, 1, 2};
     for (int u = 0; u < 3; ++u) {
@@ -466,16 +541,21 @@ static void hub_parity(const params_t *p, const double *xyz, int64_t h, const in
     const double *ra = r[ord[0]], *rb = r[ord[1]], *rc = r[ord[2]];
     double qa = q[ord[0]], qb = q[ord[1]], qc = q[ord[2]];
     int b1 = edge_bin(p, qa), b2 = edge_bin(p, qb), b3 = edge_bin(p, qc);
-    int64_t idx = config_index(p->nb, b1, b2, b3);
-    E[idx] += 1;
+    *idx_out = config_index(p->nb, b1, b2, b3);
     double cx = ra[1] * rb[2] - ra[2] * rb[1];
     double cy = ra[2] * rb[0] - ra[0] * rb[2];
     double cz = ra[0] * rb[1] - ra[1] * rb[0];
     double V = (cx * rc[0] + cy * rc[1]) + cz * rc[2];
-    if (qa == qb || qb == qc) return;
-    if (V * V <= 1e-18 * ((qa * qb) * qc)) return;
-    if (V > 0) P[idx] += 1;
-    else N[idx] += 1;
+    if (qa == qb || qb == qc) return 2;
+    if (V * V <= 1e-18 * ((qa * qb) * qc)) return 2;
+    return V > 0 ? 0 : 1;
+}
+
+/* t = +-((a1*a2)*a3)*a4 of a 4-clique's weights (magnitudes ascending, the
+ * sign their product's), as an integer multiple of 2^-s (scale = 2^s) */
+static i128 clique_weight(const double *w, const int64_t v[4], double scale) {
+    const double x[4] = {w[v[0]], w[v[1]], w[v[2]], w[v[3]]};
+    return (i128)(signed_product(x, 4) * scale);
 }
 
 /* ------------------------------------------------ 6-edge configurations -- */
@@ -565,14 +645,22 @@ int oracle_config6(int nbins, int64_t index, int *out) {
     return OR_EINVAL;
 }
 
-int oracle_count_4pcf_full(const double *xyz, int64_t n, double box, double rmin, double rmax, int nbins,
-                           int64_t anchor_lo, int64_t anchor_hi, int nthreads, uint64_t *hist6,
-                           uint64_t *n_cliques, int *threads_used) {
+int oracle_count_4pcf_full(const double *xyz, int64_t n, const double *w, double box, double rmin, double rmax,
+                           int nbins, int64_t anchor_lo, int64_t anchor_hi, int nthreads, uint64_t *hist6,
+                           uint64_t *wsum6, int *wscale, uint64_t *n_cliques, int *threads_used) {
     params_t p;
     int rc = make_params(&p, box, rmin, rmax, nbins);
     if (rc == OR_OK) rc = check_points(xyz, n, box);
     if (rc != OR_OK) return rc;
     if (n >= ((int64_t)1 << 31) || !hist6 || !n_cliques || nbins > OR_MAX_BINS6) return OR_EINVAL;
+    int s = 0;
+    if (w) {
+        if (!wsum6) return OR_EINVAL;
+        rc = weight_scale_k(w, n, 4, &s);
+        if (rc != OR_OK) return rc;
+        if (wscale) *wscale = s;
+    }
+    const double scale = ldexp(1.0, s);
     if (anchor_lo < 0) anchor_lo = 0;
     if (anchor_hi > n) anchor_hi = n;
     int64_t n6 = 0;
@@ -584,12 +672,14 @@ int oracle_count_4pcf_full(const double *xyz, int64_t n, double box, double rmin
     rc = rows_for_anchors(&p, xyz, n, nt, anchor_lo, anchor_hi, &g);
     if (rc != OR_OK) { free(rank); return rc; }
     uint64_t *tH = (uint64_t *)calloc((size_t)(nt * n6), sizeof(uint64_t));
+    i128 *tW = w ? (i128 *)calloc((size_t)(nt * n6), sizeof(i128)) : NULL;
     uint64_t *tn = (uint64_t *)calloc((size_t)nt, sizeof(uint64_t));
-    if (!tH || !tn) { free(tH); free(tn); free(rank); rows_free(&g); return OR_ENOMEM; }
+    if (!tH || !tn || (w && !tW)) { free(tH); free(tW); free(tn); free(rank); rows_free(&g); return OR_ENOMEM; }
 #pragma omp parallel num_threads(nt)
     {
         int tid = omp_get_thread_num();
         uint64_t *H = tH + (int64_t)tid * n6;
+        i128 *Wt = w ? tW + (int64_t)tid * n6 : NULL;
         uint64_t cnt = 0;
 #pragma omp for schedule(dynamic, 16)
         for (int64_t i = anchor_lo; i < anchor_hi; ++i) {
@@ -607,7 +697,12 @@ int oracle_count_4pcf_full(const double *xyz, int64_t n, double box, double rmin
                         ++cnt;
                         /* vertices (i, j, k, l): edges ij, ik, il, jk, jl, kl */
                         const int t[6] = {g.bin[a], g.bin[b], g.bin[c], g.bin[fjk], g.bin[fjl], g.bin[fkl]};
-                        H[rank[tuple_code(nbins, t)]] += 1;
+                        const int32_t cfg = rank[tuple_code(nbins, t)];
+                        H[cfg] += 1;
+                        if (Wt) {
+                            const int64_t v[4] = {i, j, k, l};
+                            Wt[cfg] += clique_weight(w, v, scale);
+                        }
                     }
                 }
             }
@@ -620,6 +715,13 @@ int oracle_count_4pcf_full(const double *xyz, int64_t n, double box, double rmin
         *n_cliques += tn[t];
         for (int64_t c = 0; c < n6; ++c) hist6[c] += tH[(int64_t)t * n6 + c];
     }
+    if (w)
+        for (int64_t c = 0; c < n6; ++c) {
+            i128 acc = 0;
+            for (int t = 0; t < nt; ++t) acc += tW[(int64_t)t * n6 + c];
+            put128(&wsum6[2 * c], acc);
+        }
+    free(tW);
     free(tH);
     free(tn);
     free(rank);
@@ -627,15 +729,27 @@ int oracle_count_4pcf_full(const double *xyz, int64_t n, double box, double rmin
     return OR_OK;
 }
 
-int oracle_count_4pcf_parity(const double *xyz, int64_t n, double box, double rmin, double rmax,
-                             int nbins, int64_t anchor_lo, int64_t anchor_hi, int nthreads,
-                             uint64_t *even, uint64_t *pos, uint64_t *neg, uint64_t *n_cliques,
-                             int *threads_used) {
+/* With weights, wsum3 (3 x 2 nconf words: even | pos | neg) receives per
+ * configuration the exact sums of each hub contribution's clique weight
+ * t = +-((a1*a2)*a3)*a4 (magnitudes ascending, the sign the product of the
+ * weights' signs), in units of 2^-wscale. */
+int oracle_count_4pcf_parity(const double *xyz, int64_t n, const double *w, double box, double rmin,
+                             double rmax, int nbins, int64_t anchor_lo, int64_t anchor_hi, int nthreads,
+                             uint64_t *even, uint64_t *pos, uint64_t *neg, uint64_t *wsum3, int *wscale,
+                             uint64_t *n_cliques, int *threads_used) {
     params_t p;
     int rc = make_params(&p, box, rmin, rmax, nbins);
     if (rc == OR_OK) rc = check_points(xyz, n, box);
     if (rc != OR_OK) return rc;
     if (n >= ((int64_t)1 << 31) || !even || !pos || !neg || !n_cliques) return OR_EINVAL;
+    int s = 0;
+    if (w) {
+        if (!wsum3) return OR_EINVAL;
+        rc = weight_scale_k(w, n, 4, &s);
+        if (rc != OR_OK) return rc;
+        if (wscale) *wscale = s;
+    }
+    const double scale = ldexp(1.0, s);
     if (anchor_lo < 0) anchor_lo = 0;
     if (anchor_hi > n) anchor_hi = n;
     int nt = resolve_threads(nthreads);
@@ -647,9 +761,10 @@ int oracle_count_4pcf_parity(const double *xyz, int64_t n, double box, double rm
     uint64_t *tE = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));
     uint64_t *tP = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));
     uint64_t *tN = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));
+    i128 *tW = w ? (i128 *)calloc((size_t)(3 * nt * nconf), sizeof(i128)) : NULL;
     uint64_t *tn = (uint64_t *)calloc((size_t)nt, sizeof(uint64_t));
-    if (!tE || !tP || !tN || !tn) {
-        free(tE); free(tP); free(tN); free(tn); rows_free(&g);
+    if (!tE || !tP || !tN || !tn || (w && !tW)) {
+        free(tE); free(tP); free(tN); free(tW); free(tn); rows_free(&g);
         return OR_ENOMEM;
     }
 #pragma omp parallel num_threads(nt)
@@ -657,6 +772,7 @@ int oracle_count_4pcf_parity(const double *xyz, int64_t n, double box, double rm
         int tid = omp_get_thread_num();
         uint64_t *E = tE + (int64_t)tid * nconf, *P = tP + (int64_t)tid * nconf,
                  *N = tN + (int64_t)tid * nconf;
+        i128 *Wt = w ? tW + 3 * (int64_t)tid * nconf : NULL;   /* even | pos | neg */
         uint64_t cnt = 0;
 #pragma omp for schedule(dynamic, 16)
         for (int64_t i = anchor_lo; i < anchor_hi; ++i) {
@@ -671,12 +787,20 @@ int oracle_count_4pcf_parity(const double *xyz, int64_t n, double box, double rm
                         if (find(&g, j, l) < 0 || find(&g, k, l) < 0) continue;
                         ++cnt;
                         int64_t v[4] = {i, j, k, l};
+                        const i128 t = Wt ? clique_weight(w, v, scale) : 0;
                         for (int h = 0; h < 4; ++h) {
-                            int64_t sp[3];
+                            int64_t sp[3], idx;
                             int u = 0;
                             for (int o = 0; o < 4; ++o)
                                 if (o != h) sp[u++] = v[o];
-                            hub_parity(&p, xyz, v[h], sp, E, P, N);
+                            const int ch = hub_parity(&p, xyz, v[h], sp, &idx);
+                            E[idx] += 1;
+                            if (ch == 0) P[idx] += 1;
+                            if (ch == 1) N[idx] += 1;
+                            if (Wt) {
+                                Wt[idx] += t;
+                                if (ch < 2) Wt[(1 + ch) * nconf + idx] += t;
+                            }
                         }
                     }
                 }
@@ -696,6 +820,13 @@ int oracle_count_4pcf_parity(const double *xyz, int64_t n, double box, double rm
             neg[c] += tN[(int64_t)t * nconf + c];
         }
     }
+    if (w)
+        for (int64_t c = 0; c < 3 * nconf; ++c) {
+            i128 acc = 0;
+            for (int t = 0; t < nt; ++t) acc += tW[3 * (int64_t)t * nconf + c];
+            put128(&wsum3[2 * c], acc);
+        }
+    free(tW);
     free(tE);
     free(tP);
     free(tN);

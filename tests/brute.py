@@ -53,7 +53,7 @@ def triangles(xyz, L, rmin, rmax, nb, weights=None, anchors=None):
     s = None
     if weights is not None:
         w = [float(v) for v in weights]
-        wmin = min(w)
+        wmin = min(abs(v) for v in w)
         s = 52 - math.frexp((wmin * wmin) * wmin)[1] + 1
     lo, hi = (0, n) if anchors is None else anchors
     count = 0
@@ -67,9 +67,7 @@ def triangles(xyz, L, rmin, rmax, nb, weights=None, anchors=None):
                 hist[rank[key]] += 1
                 count += 1
                 if weights is not None:
-                    a3 = sorted((w[i], w[j], w[int(k)]))
-                    t = (a3[0] * a3[1]) * a3[2]
-                    wsum[rank[key]] += int(t * 2.0 ** s)
+                    wsum[rank[key]] += int(signed_product((w[i], w[j], w[int(k)])) * 2.0 ** s)
     return hist, count, wsum, s
 
 
@@ -163,3 +161,73 @@ def cliques4_six(xyz, L, rmin, rmax, nb, anchors=None):
                     H[rank[canonical6(t)]] += 1
                     count += 1
     return H, count
+
+
+def _scale(weights, k):
+    m = min(abs(float(v)) for v in weights)
+    t = m
+    for _ in range(k - 1):
+        t = t * m
+    return 52 - math.frexp(t)[1] + 1
+
+
+def pairs_weighted(xyz, L, rmin, rmax, nb, weights):
+    """Edges per bin and exact sums of w_i*w_j (Python ints, units 2^-s)."""
+    _, _, adj, b = pair_matrix(xyz, L, rmin, rmax, nb)
+    s = _scale(weights, 2)
+    cnt = np.zeros(nb, dtype=np.int64)
+    ws = [0] * nb
+    ii, jj = np.nonzero(np.triu(adj, 1))
+    for i, j in zip(ii, jj):
+        cnt[b[i, j]] += 1
+        ws[b[i, j]] += int((float(weights[i]) * float(weights[j])) * 2.0 ** s)
+    return cnt, ws, s
+
+
+def signed_product(values):
+    """Magnitudes multiplied in ascending order, signed by the product of
+    the signs."""
+    mags = sorted(abs(float(v)) for v in values)
+    p = mags[0]
+    for m in mags[1:]:
+        p = p * m
+    neg = sum(1 for v in values if float(v) < 0) % 2
+    return -p if neg else p
+
+
+def _clique_t(weights, v, s):
+    return int(signed_product([weights[u] for u in v]) * 2.0 ** s)
+
+
+def cliques4_weighted(xyz, L, rmin, rmax, nb, weights):
+    """Exact clique-weight sums: by 6-edge configuration, and per hub
+    contribution for the parity channels (even, pos, neg)."""
+    n = len(xyz)
+    d, q, adj, b = pair_matrix(xyz, L, rmin, rmax, nb)
+    s = _scale(weights, 4)
+    rank6 = configs6(nb)
+    rank3 = lex_configs(nb)
+    W6 = [0] * len(rank6)
+    WE, WP, WN = ([0] * len(rank3) for _ in range(3))
+    for i in range(n):
+        for j in range(i + 1, n):
+            if not adj[i, j]:
+                continue
+            common = adj[i] & adj[j]
+            for k in [k for k in np.nonzero(common)[0] if k > j]:
+                for l in [l for l in np.nonzero(common & adj[k])[0] if l > k]:
+                    v = (i, j, int(k), int(l))
+                    t = _clique_t(weights, v, s)
+                    W6[rank6[canonical6(tuple(int(b[v[x], v[y]]) for x, y in _EDGES6))]] += t
+                    for h in v:
+                        sp = sorted([u for u in v if u != h], key=lambda u: q[h, u])
+                        qa, qb, qc = (float(q[h, u]) for u in sp)
+                        r = rank3[tuple(int(b[h, u]) for u in sp)]
+                        WE[r] += t
+                        if qa == qb or qb == qc:
+                            continue
+                        V = hub_volume(*(tuple(float(c) for c in d[h, u]) for u in sp))
+                        if V * V <= 1e-18 * ((qa * qb) * qc):
+                            continue
+                        (WP if V > 0 else WN)[r] += t
+    return W6, WE, WP, WN, s

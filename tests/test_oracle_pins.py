@@ -569,3 +569,77 @@ def test_six_edge_invariant_under_relabelling_and_reflection():
     assert a.n_cliques > 100
     assert np.array_equal(a.hist, oracle.count_4pcf_full(x[p], L, 0.0, 2.2, 4).hist)
     assert np.array_equal(a.hist, oracle.count_4pcf_full(y, L, 0.0, 2.2, 4).hist)
+
+
+# --------------------------------------------- signed weights (Sec. 2.1) -----
+
+def _signed_weights(n, seed, frac_neg=0.5):
+    """Data weights U(0.5,1.5) and random weights -U(0.5,1.5)/2 (the signed
+    data-minus-random weights of the estimator, before normalisation)."""
+    w = synth.uniform_values(n, 0.5, 1.0, seed)
+    neg = synth.uniform_values(n, 0.0, 1.0, seed + 1) < frac_neg
+    return np.where(neg, -0.5 * w, w)
+
+
+@pytest.mark.parametrize("case", TINY[:3], ids=[c[0] for c in TINY[:3]])
+def test_oracle_signed_weighted_3pcf_matches_brute_force(case):
+    _, mk, L, rmin, rmax, nb = case
+    x = mk()
+    w = _signed_weights(len(x), 201)
+    bh, bcount, bw, bs = brute.triangles(x, L, rmin, rmax, nb, weights=w)
+    r = oracle.count_3pcf(x, L, rmin, rmax, nb, weights=w, threads=3)
+    assert r.n_triangles == bcount and r.wscale == bs
+    assert r.wsum_int() == bw
+    assert min(bw) < 0 < max(bw)
+
+
+@pytest.mark.parametrize("case", TINY[:3], ids=[c[0] for c in TINY[:3]])
+def test_oracle_weighted_pairs_match_brute_force(case):
+    _, mk, L, rmin, rmax, nb = case
+    x = mk()
+    w = _signed_weights(len(x), 202)
+    cnt, ws, s = brute.pairs_weighted(x, L, rmin, rmax, nb, w)
+    r = oracle.pair_sums(x, L, rmin, rmax, nb, weights=w)
+    assert np.array_equal(r.pairs.astype(np.int64), cnt)
+    assert r.wscale == s and r.wsum_int() == ws
+    rp, col, b = oracle.graph(x, L, rmin, rmax, nb)
+    assert np.array_equal(np.bincount(b, minlength=nb), 2 * cnt)
+
+
+@pytest.mark.parametrize("case", TINY4[:2], ids=[c[0] for c in TINY4[:2]])
+def test_oracle_weighted_4cliques_match_brute_force(case):
+    _, mk, L, rmin, rmax, nb = case
+    x = mk()
+    w = _signed_weights(len(x), 203)
+    W6, WE, WP, WN, s = brute.cliques4_weighted(x, L, rmin, rmax, nb, w)
+    r6 = oracle.count_4pcf_full(x, L, rmin, rmax, nb, weights=w)
+    assert r6.wscale == s and r6.wsum_int() == W6
+    r4 = oracle.count_4pcf_parity(x, L, rmin, rmax, nb, weights=w)
+    assert r4.wscale == s
+    assert r4.wsum_int(0) == WE and r4.wsum_int(1) == WP and r4.wsum_int(2) == WN
+    assert np.array_equal(r6.hist, oracle.count_4pcf_full(x, L, rmin, rmax, nb).hist)
+
+
+def test_signed_weight_identities():
+    """Weights all -1: products of k weights are (-1)^k, so every sum is
+    (-1)^k times the count in units of 2^52; flipping every sign negates the
+    triangle sums and leaves pair and 4-clique sums unchanged."""
+    L = 10.0
+    x = synth.uniform(300, L, 61)
+    n = len(x)
+    m1 = -np.ones(n)
+    r3 = oracle.count_3pcf(x, L, 0.0, 2.4, 5, weights=m1)
+    assert r3.wsum_int() == [-(int(h) << 52) for h in r3.hist]
+    r2 = oracle.pair_sums(x, L, 0.0, 2.4, 5, weights=m1)
+    assert r2.wsum_int() == [int(c) << 52 for c in r2.pairs]
+    r6 = oracle.count_4pcf_full(x, L, 0.0, 2.4, 4, weights=m1)
+    assert r6.wsum_int() == [int(c) << 52 for c in r6.hist]
+    w = _signed_weights(n, 62)
+    a3 = oracle.count_3pcf(x, L, 0.0, 2.4, 5, weights=w)
+    b3 = oracle.count_3pcf(x, L, 0.0, 2.4, 5, weights=-w)
+    assert b3.wsum_int() == [-v for v in a3.wsum_int()]
+    a6 = oracle.count_4pcf_full(x, L, 0.0, 2.4, 4, weights=w)
+    b6 = oracle.count_4pcf_full(x, L, 0.0, 2.4, 4, weights=-w)
+    assert a6.wsum_int() == b6.wsum_int()
+    a4 = oracle.count_4pcf_parity(x, L, 0.0, 2.4, 4, weights=w)
+    assert sum(a4.wsum_int(0)) == 4 * sum(a6.wsum_int())
