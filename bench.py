@@ -129,7 +129,7 @@ def cpu_baseline(w, kind):
     return {"value": round(cnt / dt, 1), "unit": WORKLOADS_UNIT[kind], "cores": threads, "kind": "oracle",
             "sample": "tuples whose smallest original index lies in %d ranges of %d anchors spread evenly "
                       "over the %d points (%d anchors, %.2e of the catalogue; rows built for the anchors and "
-                      "their neighbours), %d tuples in %.1f s" % (nr, per, w.n, nr * per, nr * per / w.n, w.n,
+                      "their neighbours), %d tuples in %.1f s" % (nr, per, w.n, nr * per, nr * per / w.n,
                                                                   cnt, dt)}
 
 

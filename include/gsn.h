@@ -107,11 +107,13 @@ int gs_destroy(gs_ctx *ctx);
 
 /* Build the r < rmax graph of n points (Sec. 2.1; CSR of Sec. 3.5.1):
  *  xyz: n x 3 float64, AoS (x0,y0,z0,x1,...), host or device (flag);
- *  weights: nullable, n float64 > 0 (required iff GS_WEIGHTED);
+ *  weights: nullable, n float64, finite and nonzero, of either sign (the
+ *    signed, normalised data-minus-random weights of Sec. 2.1; required iff
+ *    GS_WEIGHTED);
  *  Points are relabelled in cell order; only forward edges (label j > i) are
  *  stored: row_ptr u64[n+1], col u32[E], bin u8[E], rows strictly increasing.
  *  Errors: GS_EINVAL (NaN, coordinate outside [0, box), bad params, weights
- *  missing / non-positive / of too wide a range for exact sums),
+ *  missing / zero / not finite),
  *  GS_EOVERFLOW, GS_EDEVMEM, GS_EHIP. On error *out is NULL. */
 int gs_build_graph(gs_ctx *ctx, const double *xyz, int64_t n, const double *weights,
                    const gs_graph_params *p, gs_graph **out);
@@ -131,10 +133,15 @@ int gs_graph_free(gs_graph *g);
  * sorted side bins.
  *  hist: host u64[C(nbins+2,3)];
  *  wsum128: nullable, host u64[2*C(nbins+2,3)], (lo, hi) words of the exact
- *    sum per configuration of t = (w1*w2)*w3 (weights of the triangle in
- *    ascending order), in units of 2^-wscale (graph must be weighted);
+ *    signed 128-bit (two's complement) sum per configuration of
+ *    t = +-(a1*a2)*a3, the triangle's weight magnitudes in ascending order
+ *    signed by the product of the weights' signs, in units of 2^-wscale
+ *    (graph must be weighted);
  *  whist: nullable, host double[C(nbins+2,3)]: those sums rounded once;
- *  wscale: nullable, out: s = 52 - floor(log2((wmin*wmin)*wmin));
+ *  wscale: nullable, out: s = 52 - floor(log2((m*m)*m)), m the smallest
+ *    weight magnitude. Every term t*2^s is an integer; GS_EINVAL if the
+ *    largest would reach 2^87 or the products leave the normal float64
+ *    range;
  *  n_triangles: host out, counted separately from the bins;
  *  anchors: nullable (see gs_anchor_range). */
 int gs_count_3pcf(gs_ctx *ctx, const gs_graph *g, uint64_t *hist, uint64_t *wsum128,
@@ -150,6 +157,53 @@ int gs_count_3pcf(gs_ctx *ctx, const gs_graph *g, uint64_t *hist, uint64_t *wsum
  * Needs a graph built with GS_KEEP_COORDS (else GS_ENOCOORDS). */
 int gs_count_4pcf_parity(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos,
                          uint64_t *neg, uint64_t *n_cliques, const gs_anchor_range *anchors);
+
+/* Weighted parity counts (Sec. 3.2 with the signed weights of Sec. 2.1):
+ * the counts of gs_count_4pcf_parity, and per configuration the exact sums
+ * of each hub contribution's clique weight t = +-((a1*a2)*a3)*a4 (the four
+ * weight magnitudes in ascending order, signed by the product of the signs):
+ *  wsum128: host u64[3*2*C(nbins+2,3)]: blocks even | pos | neg, each
+ *    configuration's signed 128-bit sum as (lo, hi) words, units 2^-wscale;
+ *  wscale: nullable, out: s = 52 - floor(log2(((m*m)*m)*m)), m the smallest
+ *    weight magnitude (GS_EINVAL if a term would reach 2^87).
+ * Needs a weighted graph built with GS_KEEP_COORDS. */
+int gs_count_4pcf_parity_weighted(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos,
+                                  uint64_t *neg, uint64_t *wsum128, int32_t *wscale, uint64_t *n_cliques,
+                                  const gs_anchor_range *anchors);
+
+/* Full 6-edge 4-clique counts (Sec. 3.3 and Sec. 5.3, the four-point
+ * configurations): every 4-clique counts once into the configuration of its
+ * six edge bins up to relabelling of its four vertices. A vertex order
+ * (p0,p1,p2,p3) gives the bin tuple of edges (p0p1, p0p2, p0p3, p1p2, p1p3,
+ * p2p3); the configuration is the class of tuples the 24 orders give,
+ * represented by its lexicographically smallest tuple, and configurations
+ * are numbered in the lexicographic order of those tuples (276 at 4 bins).
+ *  hist6: host u64[n6] (gs_n_configs6);
+ *  wsum128: nullable, host u64[2*n6]: exact signed 128-bit sums of the clique
+ *    weights t = +-((a1*a2)*a3)*a4 (as gs_count_4pcf_parity_weighted);
+ *  wscale: nullable, out (as gs_count_4pcf_parity_weighted);
+ *  n_cliques: host out; anchors: nullable.
+ * nbins 1..12 (GS_EUNSUPPORTED above). Needs GS_KEEP_COORDS (the three
+ * separations among a hub's spokes are recomputed from the coordinates with
+ * the bin rule of the graph, which gives the graph's own bins). */
+int gs_count_4pcf_full(gs_ctx *ctx, const gs_graph *g, uint64_t *hist6, uint64_t *wsum128, int32_t *wscale,
+                       uint64_t *n_cliques, const gs_anchor_range *anchors);
+/* Number of 6-edge configurations at nbins (1..12): (k^6 + 9k^4 + 14k^2)/24. */
+int gs_n_configs6(int32_t nbins, uint32_t *n6);
+/* The configuration of every 6-edge bin tuple: rank: host u32[nbins^6],
+ * indexed by the tuple's code sum_e bin_e * nbins^(5-e) (edges in the order
+ * above). */
+int gs_config6_table(int32_t nbins, uint32_t *rank);
+
+/* Pair counts per bin and exact weighted pair sums (the internal 2pCF that
+ * the connected 4pCF of Sec. 3.3 subtracts): every edge once.
+ *  pairs: host u64[nbins];
+ *  wsum128: nullable, host u64[2*nbins]: exact signed 128-bit sums of
+ *    w_i*w_j, units 2^-wscale, s = 52 - floor(log2(m*m));
+ *  anchors: nullable: pairs whose smaller original index lies in [lo, hi).
+ * Works on resident and host-tiled graphs. */
+int gs_pair_sums(gs_ctx *ctx, const gs_graph *g, uint64_t *pairs, uint64_t *wsum128, int32_t *wscale,
+                 const gs_anchor_range *anchors);
 
 /* Binned triangle counts of several resident graphs (same nbins) in ONE
  * persistent launch: hubs of all graphs form one queue, so small and large
@@ -221,7 +275,7 @@ int gs_tune_3pcf(gs_ctx *ctx, const gs_graph *g, uint32_t flags, gs_plan3 *out);
 typedef struct {
     const double *xyz;      /* host n x 3 float64, copied by gs_submit          */
     int64_t n;
-    const double *weights;  /* host n float64 > 0, copied; non-NULL iff
+    const double *weights;  /* host n float64, finite, nonzero; copied; non-NULL iff
                                p.flags has GS_WEIGHTED (GS_3PCF only)            */
     gs_graph_params p;      /* flags: 0 or GS_WEIGHTED (host input; parity
                                requests keep coordinates by themselves)         */

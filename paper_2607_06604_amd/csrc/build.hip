@@ -52,13 +52,14 @@ __global__ void k_cells(const double *__restrict__ xyz, uint32_t n, double L, in
     atomicAdd(&count[c], 1u);
 }
 
-// Positive finite weights; min and max as ordered bit patterns.
+// Finite nonzero weights of either sign (signed data-minus-random weights,
+// Sec. 2.1); the smallest and largest magnitude as ordered bit patterns.
 __global__ void k_weights(const double *__restrict__ w, uint32_t n, uint32_t *__restrict__ flags,
                           unsigned long long *__restrict__ mm) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long lo = ~0ull, hi = 0;
     if (i < n) {
-        const double v = w[i];
+        const double v = fabs(w[i]);
         if (!(v > 0.0) || !(v <= 1.79769313486231570e308)) {
             atomicOr(&flags[0], 2u);
         } else {
@@ -358,6 +359,70 @@ __global__ __launch_bounds__(kBlock) void k_stats(const uint64_t *__restrict__ r
     }
 }
 
+// Pair counts and exact weighted pair sums per bin (the internal 2pCF of
+// Sec. 3.3): a wavefront per row, its lanes over the row's entries; counts
+// and the weighted terms' low 32 bits / arithmetic high parts summed in LDS,
+// then added to the 64-bit counts and 128-bit sums. Anchored: only pairs
+// whose smaller original index lies in [alo, ahi).
+struct PairArgs {
+    const uint64_t *rp;
+    const uint32_t *col;
+    const uint8_t *bin;
+    const uint32_t *perm;
+    const double *w;
+    double wmul;
+    uint32_t l0, l1;
+    uint64_t obase;
+    int nb;
+    uint32_t alo, ahi;
+    unsigned long long *cnt, *wsum;
+};
+
+template <bool WEIGHTED, bool ANCHORED>
+__global__ __launch_bounds__(kBlock) void k_pairs(PairArgs a) {
+    __shared__ unsigned long long sc[256], slo[256], shi[256];
+    for (int k = threadIdx.x; k < 256; k += kBlock) {
+        sc[k] = 0;
+        if (WEIGHTED) {
+            slo[k] = 0;
+            shi[k] = 0;
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (kBlock / 64);
+    for (uint32_t l = a.l0 + blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); l < a.l1; l += waves) {
+        const uint64_t b0 = a.rp[l] - a.obase, b1 = a.rp[l + 1] - a.obase;
+        const double wi = WEIGHTED ? a.w[l] : 0.0;
+        const uint32_t pi = ANCHORED ? a.perm[l] : 0u;
+        for (uint64_t e = b0 + lane; e < b1; e += 64) {
+            const uint32_t j = a.col[e];
+            if (ANCHORED) {
+                const uint32_t m = min(pi, a.perm[j]);
+                if (m < a.alo || m >= a.ahi) continue;
+            }
+            const uint32_t b = a.bin[e];
+            atomicAdd(&sc[b], 1ull);
+            if (WEIGHTED) {
+                const double wj = a.w[j];
+                const double x = __dmul_rn(__dmul_rn(fabs(wi), fabs(wj)), a.wmul);
+                const bool ng = (wi < 0.0) ^ (wj < 0.0);
+                if (narrow_term(x)) {
+                    const long long m = (long long)x;
+                    lds_term(&slo[b], &shi[b], ng ? -m : m);
+                } else {
+                    add128_words(&a.wsum[2 * b], wide_term(x, ng));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < a.nb; k += kBlock) {
+        if (sc[k]) atomicAdd(&a.cnt[k], sc[k]);
+        if (WEIGHTED && (slo[k] | shi[k])) add128_words(&a.wsum[2 * k], lds_sum128(slo[k], shi[k]));
+    }
+}
+
 // ---- exclusive scan u32 -> u64 (out has n+1 entries, out[n] = total) ----
 
 constexpr int kScanItems = 8;
@@ -610,22 +675,14 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
     GS_HIP(hipMemcpyAsync(&E, g.row_ptr.as<uint64_t>() + n, sizeof E, hipMemcpyDeviceToHost, s));
     GS_HIP(hipStreamSynchronize(s));
     if (hf.f[0] & 1u) fail(GS_EINVAL, "coordinate outside [0, box) or NaN");
-    if (hf.f[0] & 2u) fail(GS_EINVAL, "weights must be finite and > 0");
+    if (hf.f[0] & 2u) fail(GS_EINVAL, "weights must be finite and nonzero");
     g.n_edges = E;
     g.max_deg = hf.f[1];
     if (weighted) {
-        double wmin, wmax;
-        memcpy(&wmin, &hf.wmin, 8);
-        memcpy(&wmax, &hf.wmax, 8);
-        volatile double tlo = wmin * wmin;
-        tlo = tlo * wmin;
-        volatile double thi = wmax * wmax;
-        thi = thi * wmax;
-        if (!(tlo >= 0x1.0p-1022) || !std::isfinite((double)thi))
-            fail(GS_EINVAL, "weights out of range for exact sums");
-        g.wscale = 52 - std::ilogb((double)tlo);
-        if (std::ilogb((double)thi) + g.wscale >= 64)
-            fail(GS_EINVAL, "weight range too wide for exact 128-bit sums");
+        memcpy(&g.wmin, &hf.wmin, 8);
+        memcpy(&g.wmax, &hf.wmax, 8);
+        int s3 = 0;
+        g.wscale = weight_scale_ok(g, 3, &s3) ? s3 : kNoScale;
     }
     job.E = E;
     float ms = 0;
@@ -769,6 +826,67 @@ void graph_stats(Graph &g) {
     GS_HIP(hipStreamSynchronize(s));
     for (int k = 0; k < 255; ++k) g.pair_hist[k] = k < g.nbins ? hph[k] : 0;
     g.stats_ready = true;
+}
+
+// Pair counts per bin and (with weights) their exact weighted sums.
+void pair_sums_run(Ctx &ctx, const Graph &g, uint64_t *pairs, uint64_t *wsum, int *wscale,
+                   const gs_anchor_range *anchors) {
+    const int nb = g.nbins;
+    const bool weighted = wsum != nullptr;
+    const bool anchored = anchors != nullptr;
+    if (anchored && anchors->lo > anchors->hi) fail(GS_EINVAL, "anchor range lo > hi");
+    const int s2 = weighted ? weight_scale(g, 2) : 0;
+    hipStream_t s = ctx.stream;
+    unsigned long long *dv = (unsigned long long *)ctx.scratch_get(8 * 3 * 256);
+    k_fill_u64<<<3, 256, 0, s>>>((uint64_t *)dv, 3 * 256, 0);
+    PairArgs a{};
+    a.rp = g.row_ptr.as<uint64_t>();
+    a.perm = g.perm.as<uint32_t>();
+    a.w = weighted ? g.weights.as<double>() : nullptr;
+    a.wmul = std::ldexp(1.0, s2);
+    a.nb = nb;
+    a.alo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
+    a.ahi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;
+    a.cnt = dv;
+    a.wsum = dv + 256;
+    auto go = [&](uint32_t l0, uint32_t l1) {
+        if (l1 <= l0) return;
+        a.l0 = l0;
+        a.l1 = l1;
+        const uint64_t waves = (uint64_t)(l1 - l0);
+        const unsigned grid = (unsigned)std::min<uint64_t>((waves + 3) / 4, (uint64_t)ctx.n_cu * 16);
+        if (weighted) anchored ? k_pairs<true, true><<<grid, kBlock, 0, s>>>(a) : k_pairs<true, false><<<grid, kBlock, 0, s>>>(a);
+        else anchored ? k_pairs<false, true><<<grid, kBlock, 0, s>>>(a) : k_pairs<false, false><<<grid, kBlock, 0, s>>>(a);
+        GS_HIP(hipGetLastError());
+    };
+    if (g.n_windows == 1) {
+        a.col = g.col.as<uint32_t>();
+        a.bin = g.bin.as<uint8_t>();
+        a.obase = 0;
+        go(0, (uint32_t)g.n);
+    } else {
+        uint64_t maxE = 1;
+        for (int w = 0; w < g.n_windows; ++w) maxE = std::max<uint64_t>(maxE, g.win_edge[w + 1] - g.win_edge[w]);
+        DevBuf wc(maxE * 4), wb(maxE);
+        for (int w = 0; w < g.n_windows; ++w) {
+            const uint64_t e0 = g.win_edge[w], ne = g.win_edge[w + 1] - e0;
+            GS_HIP(hipMemcpyAsync(wc.p, g.hcol.as<uint32_t>() + e0, ne * 4, hipMemcpyHostToDevice, s));
+            GS_HIP(hipMemcpyAsync(wb.p, g.hbin.as<uint8_t>() + e0, ne, hipMemcpyHostToDevice, s));
+            a.col = wc.as<uint32_t>();
+            a.bin = wb.as<uint8_t>();
+            a.obase = e0;
+            go((uint32_t)g.win[w], (uint32_t)g.win[w + 1]);
+            GS_HIP(hipStreamSynchronize(s));
+        }
+    }
+    uint64_t h[3 * 256];
+    GS_HIP(hipMemcpyAsync(h, dv, sizeof h, hipMemcpyDeviceToHost, s));
+    GS_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < nb; ++k) pairs[k] = h[k];
+    if (weighted) {
+        for (int k = 0; k < 2 * nb; ++k) wsum[k] = h[256 + k];
+        if (wscale) *wscale = s2;
+    }
 }
 
 void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w) {

@@ -155,6 +155,42 @@ Bins make_bins(double rmin, double rmax, int nb) {
     return b;
 }
 
+bool weight_scale_ok(const Graph &g, int k, int *s, int *why) {
+    if (g.n == 0) {
+        *s = 0;
+        return true;
+    }
+    volatile double tlo = g.wmin, thi = g.wmax;
+    for (int j = 1; j < k; ++j) {
+        tlo = tlo * g.wmin;
+        thi = thi * g.wmax;
+    }
+    if (!(tlo >= 0x1.0p-1022) || !std::isfinite((double)thi)) {
+        if (why) *why = GS_EINVAL;
+        return false;
+    }
+    const int sc = 52 - std::ilogb((double)tlo);
+    if (std::ilogb((double)thi) + sc > 86) {   // every term below 2^87
+        if (why) *why = GS_EINVAL;
+        return false;
+    }
+    *s = sc;
+    return true;
+}
+
+double sum128_to_double(const uint64_t *w, int scale) {
+    const __int128 v = (__int128)(((unsigned __int128)w[1] << 64) | w[0]);
+    return std::ldexp((double)v, -scale);
+}
+
+int weight_scale(const Graph &g, int k) {
+    int s = 0, why = GS_EINVAL;
+    if (!(g.flags & GS_WEIGHTED)) fail(GS_EINVAL, "graph has no weights");
+    if (!weight_scale_ok(g, k, &s, &why))
+        fail(why, "weight products leave the normal float64 range or span more than 2^34 (exact sums)");
+    return s;
+}
+
 }  // namespace gsn
 
 using namespace gsn;
@@ -336,13 +372,11 @@ int gs_count_3pcf(gs_ctx *ctx, const gs_graph *g, uint64_t *hist, uint64_t *wsum
         }
         count3_run(*ctx, *g, hist, wdst, n_triangles, anchors);
         if (g->flags & GS_WEIGHTED) {
+            const int sc = weight_scale(*g, 3);
             if (wsum128) memcpy(wsum128, ws.data(), sizeof(uint64_t) * 2 * nc);
             if (whist)
-                for (int64_t c = 0; c < nc; ++c) {
-                    unsigned __int128 v = ((unsigned __int128)ws[2 * c + 1] << 64) | ws[2 * c];
-                    whist[c] = std::ldexp((double)v, -g->wscale);
-                }
-            if (wscale) *wscale = g->wscale;
+                for (int64_t c = 0; c < nc; ++c) whist[c] = sum128_to_double(&ws[2 * c], sc);
+            if (wscale) *wscale = sc;
         }
     });
 }
@@ -355,7 +389,111 @@ int gs_count_4pcf_parity(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_
         if (g->n_windows > 1) fail(GS_EUNSUPPORTED, "parity counts need a device-resident graph");
         if (g->device != ctx->device) fail(GS_EINVAL, "graph and context on different devices");
         ctx->use();
-        count4_run(*ctx, *g, even, pos, neg, n_cliques, anchors);
+        const int64_t nc = n_configs(g->nbins);
+        Count4Out o;
+        o.kind = kParity4;
+        o.cnt[0] = pos;
+        o.cnt[1] = neg;
+        o.cnt[2] = even;   // the degenerate block, then even = pos + neg + degenerate
+        o.ncl = n_cliques;
+        count4_run(*ctx, *g, o, anchors);
+        for (int64_t c = 0; c < nc; ++c) even[c] += pos[c] + neg[c];
+    });
+}
+
+// 128-bit two's complement words a + b into out (lo, hi).
+static void add128w(const uint64_t *a, const uint64_t *b, uint64_t *out) {
+    const unsigned __int128 x = ((unsigned __int128)a[1] << 64) | a[0], y = ((unsigned __int128)b[1] << 64) | b[0];
+    const unsigned __int128 z = x + y;
+    out[0] = (uint64_t)z;
+    out[1] = (uint64_t)(z >> 64);
+}
+
+static void check4(gs_ctx *ctx, const gs_graph *g) {
+    if (!(g->flags & GS_KEEP_COORDS)) fail(GS_ENOCOORDS, "4-clique counts need GS_KEEP_COORDS");
+    if (g->n_windows > 1) fail(GS_EUNSUPPORTED, "4-clique counts need a device-resident graph");
+    if (g->device != ctx->device) fail(GS_EINVAL, "graph and context on different devices");
+}
+
+int gs_count_4pcf_parity_weighted(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos, uint64_t *neg,
+                                  uint64_t *wsum128, int32_t *wscale, uint64_t *n_cliques,
+                                  const gs_anchor_range *anchors) {
+    return guarded([&] {
+        if (!ctx || !g || !even || !pos || !neg || !wsum128 || !n_cliques) fail(GS_EINVAL, "null argument");
+        if (!(g->flags & GS_WEIGHTED)) fail(GS_EINVAL, "graph has no weights");
+        check4(ctx, g);
+        ctx->use();
+        const int64_t nc = n_configs(g->nbins);
+        std::vector<uint64_t> deg(nc), wdeg(2 * nc);
+        uint64_t *we = wsum128, *wp = wsum128 + 2 * nc, *wn = wsum128 + 4 * nc;
+        Count4Out o;
+        o.kind = kParity4;
+        o.cnt[0] = pos;
+        o.cnt[1] = neg;
+        o.cnt[2] = deg.data();
+        o.wsum[0] = wp;
+        o.wsum[1] = wn;
+        o.wsum[2] = wdeg.data();
+        int sc = 0;
+        o.wscale = &sc;
+        o.ncl = n_cliques;
+        count4_run(*ctx, *g, o, anchors);
+        for (int64_t c = 0; c < nc; ++c) {
+            even[c] = pos[c] + neg[c] + deg[c];
+            uint64_t t[2];
+            add128w(&wp[2 * c], &wn[2 * c], t);
+            add128w(t, &wdeg[2 * c], &we[2 * c]);
+        }
+        if (wscale) *wscale = sc;
+    });
+}
+
+int gs_count_4pcf_full(gs_ctx *ctx, const gs_graph *g, uint64_t *hist6, uint64_t *wsum128, int32_t *wscale,
+                       uint64_t *n_cliques, const gs_anchor_range *anchors) {
+    return guarded([&] {
+        if (!ctx || !g || !hist6 || !n_cliques) fail(GS_EINVAL, "null argument");
+        if ((wsum128 || wscale) && !(g->flags & GS_WEIGHTED)) fail(GS_EINVAL, "graph has no weights");
+        if (g->nbins > kMaxBins6) fail(GS_EUNSUPPORTED, "6-edge counts take at most 12 bins");
+        check4(ctx, g);
+        ctx->use();
+        Count4Out o;
+        o.kind = kSix4;
+        o.cnt[0] = hist6;
+        o.wsum[0] = wsum128;
+        int sc = 0;
+        o.wscale = &sc;
+        o.ncl = n_cliques;
+        count4_run(*ctx, *g, o, anchors);
+        if (wscale) *wscale = sc;
+    });
+}
+
+int gs_n_configs6(int32_t nbins, uint32_t *n6) {
+    return guarded([&] {
+        if (!n6 || nbins < 1 || nbins > kMaxBins6) fail(GS_EINVAL, "nbins must be 1..12");
+        (void)config6_table(nbins, n6);
+    });
+}
+
+int gs_config6_table(int32_t nbins, uint32_t *rank) {
+    return guarded([&] {
+        if (!rank || nbins < 1 || nbins > kMaxBins6) fail(GS_EINVAL, "nbins must be 1..12");
+        uint32_t n6 = 0;
+        const std::vector<uint32_t> &t = config6_table(nbins, &n6);
+        memcpy(rank, t.data(), sizeof(uint32_t) * t.size());
+    });
+}
+
+int gs_pair_sums(gs_ctx *ctx, const gs_graph *g, uint64_t *pairs, uint64_t *wsum128, int32_t *wscale,
+                 const gs_anchor_range *anchors) {
+    return guarded([&] {
+        if (!ctx || !g || !pairs) fail(GS_EINVAL, "null argument");
+        if ((wsum128 || wscale) && !(g->flags & GS_WEIGHTED)) fail(GS_EINVAL, "graph has no weights");
+        if (g->device != ctx->device) fail(GS_EINVAL, "graph and context on different devices");
+        ctx->use();
+        int sc = 0;
+        pair_sums_run(*ctx, *g, pairs, wsum128, &sc, anchors);
+        if (wscale) *wscale = wsum128 ? sc : 0;
     });
 }
 

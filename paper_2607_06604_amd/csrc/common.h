@@ -165,6 +165,7 @@ struct Ctx {
     size_t pinned_bytes = 0;
     Server *server = nullptr;   // continuous-batching scheduler (gs_submit)
     std::vector<std::pair<uint64_t, Tune3>> tuned;  // autotuned schedules by graph shape
+    std::map<int, DevBuf> cfg6;  // 6-edge configuration tables by bin count
     void *scratch_get(size_t bytes);
     void *pinned_get(size_t bytes);
     void use() const;
@@ -189,7 +190,8 @@ struct Graph {
     double box = 0, rmin = 0, rmax = 0;
     int nbins = 0;
     uint32_t flags = 0;
-    int wscale = 0;
+    int wscale = 0;           // exact-sum scale of weighted triangles (kNoScale: none)
+    double wmin = 0, wmax = 0;  // smallest and largest weight magnitude
     Bins bins;
     uint64_t pair_hist[255] = {};
     uint64_t sum_sq_deg = 0;  // sum over points of (full degree)^2
@@ -229,6 +231,20 @@ struct BuildJob {
 };
 
 Bins make_bins(double rmin, double rmax, int nb);
+
+// Exact sums of products of k weights (Sec. 2.1 signed weights): every
+// product +-((a1*a2)*...)*ak of magnitudes in ascending order, times 2^s, is
+// an integer when s = 52 - floor(log2(wmin^k)) (the smallest possible product
+// lies in [2^52, 2^53) units of 2^-s). weight_scale_ok gives s when the
+// largest product then stays below 2^87 (terms below 2^63 are summed in LDS,
+// wider ones straight into the 128-bit sums); weight_scale throws GS_EINVAL
+// otherwise (or when the products leave the normal float64 range).
+constexpr int kNoScale = -100000;
+bool weight_scale_ok(const Graph &g, int k, int *s, int *why = nullptr);
+int weight_scale(const Graph &g, int k);
+// An exact signed 128-bit sum (lo, hi words, two's complement) in units of
+// 2^-scale, rounded once to float64.
+double sum128_to_double(const uint64_t *w, int scale);
 inline int64_t n_configs(int nb) { return (int64_t)(nb + 2) * (nb + 1) * nb / 6; }
 
 // ------------------------------------------------------- device helpers ---
@@ -275,10 +291,33 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
                 uint32_t sample_hi = 0);
 // Time schedules on a sample of g's hubs and keep the fastest for g's shape.
 void tune3(Ctx &ctx, const Graph &g, bool weighted, gs_plan3 *out);
-void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_t *neg,
-                uint64_t *ncl, const gs_anchor_range *anchors);
+// 4-clique counts. kind kParity4: counters in three blocks of C(nb+2,3),
+// pos | neg | degenerate (even = their sum); kSix4: one block of 6-edge
+// configurations. Each block is copied to host cnt[b]; with wsum[0] set,
+// wsum[b] receives the block's exact signed 128-bit weighted sums (2 words
+// per counter, units 2^-wscale). scratch: device memory of scratch_bytes to
+// use instead of the context's (nothing is allocated then).
+enum { kParity4 = 0, kSix4 = 1 };
+constexpr int kMaxBins6 = 12;
+struct Count4Out {
+    int kind = kParity4;
+    uint64_t *cnt[3] = {nullptr, nullptr, nullptr};
+    uint64_t *wsum[3] = {nullptr, nullptr, nullptr};
+    int *wscale = nullptr;
+    uint64_t *ncl = nullptr;
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+};
+void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_range *anchors);
+// Configuration rank of every 6-edge bin-tuple code, and the number of
+// configurations (host table, cached per bin count).
+const std::vector<uint32_t> &config6_table(int nb, uint32_t *n6);
 void build_run(Ctx &ctx, Graph &g, const double *xyz, const double *w);
 void graph_stats(Graph &g);
+// Pairs (edges) per bin and, with wsum (2 words per bin), the exact signed
+// 128-bit sums of w_i*w_j in units of 2^-wscale (the internal 2pCF).
+void pair_sums_run(Ctx &ctx, const Graph &g, uint64_t *pairs, uint64_t *wsum, int *wscale,
+                   const gs_anchor_range *anchors);
 void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJob &job);
 uint64_t build_footprint(const Graph &g, const BuildJob &job);
 void build_end(Ctx &ctx, Graph &g, BuildJob &job, bool tile_ok);

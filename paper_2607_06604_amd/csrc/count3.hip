@@ -145,13 +145,6 @@ __device__ __forceinline__ uint32_t hub_hash(uint32_t k, int log2h) {
     return PACK ? label_hash24(k, log2h) : label_hash(k, log2h);
 }
 
-// 128-bit add into a (lo, hi) pair of global words.
-__device__ __forceinline__ void add128(unsigned long long *dst, unsigned __int128 v) {
-    unsigned long long lo = (unsigned long long)v, hi = (unsigned long long)(v >> 64);
-    unsigned long long old = atomicAdd(&dst[0], lo);
-    if (old + lo < old) hi += 1;
-    if (hi) atomicAdd(&dst[1], hi);
-}
 
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
 #pragma unroll
@@ -195,7 +188,7 @@ __device__ void flush3(const C3Args &a, const Layout3 &L, unsigned char *sm, uns
             unsigned long long *whi = (unsigned long long *)(sm + L.whi);
             const unsigned long long lo = wlo[b], hi = whi[b];
             if (lo | hi) {
-                add128(&a.wsum[2 * b], ((unsigned __int128)hi << 32) + (unsigned __int128)lo);
+                add128_words(&a.wsum[2 * b], lds_sum128(lo, hi));
                 wlo[b] = 0;
                 whi[b] = 0;
             }
@@ -279,17 +272,20 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk,
         ++mytri;
     }
     if (WEIGHTED) {
-        double p = c.hw[hub], q = c.mw[slot], r = wk, t;
+        // magnitudes in ascending order, multiplied left to right; the sign
+        // is the product of the three signs
+        const double w0 = c.hw[hub], w1 = c.mw[slot];
+        const bool ng = (w0 < 0.0) ^ (w1 < 0.0) ^ (wk < 0.0);
+        double p = fabs(w0), q = fabs(w1), r = fabs(wk), t;
         if (p > q) { t = p; p = q; q = t; }
         if (q > r) { t = q; q = r; r = t; }
         if (p > q) { t = p; p = q; q = t; }
-        const double prod = __dmul_rn(__dmul_rn(p, q), r);
-        const unsigned long long ti = (unsigned long long)__dmul_rn(prod, c.wmul);
-        if (LDS_HIST) {
-            atomicAdd(&c.wlo[idx], ti & 0xFFFFFFFFull);
-            atomicAdd(&c.whi[idx], ti >> 32);
+        const double x = __dmul_rn(__dmul_rn(__dmul_rn(p, q), r), c.wmul);
+        if (LDS_HIST && narrow_term(x)) {
+            const long long m = (long long)x;
+            lds_term(&c.wlo[idx], &c.whi[idx], ng ? -m : m);
         } else {
-            add128(&c.wsum[2 * idx], (unsigned __int128)ti);
+            add128_words(&c.wsum[2 * idx], wide_term(x, ng));
         }
     }
 }
@@ -1293,7 +1289,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.tcap = P.tcap;
     a.anchor_lo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
     a.anchor_hi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;
-    a.wmul = std::ldexp(1.0, g.wscale);
+    a.wmul = weighted ? std::ldexp(1.0, weight_scale(g, 3)) : 1.0;
     a.flush_limit = flush_limit_for(maxdeg, P.block);
     a.hist = dv;
     a.wsum = dv + nconf;

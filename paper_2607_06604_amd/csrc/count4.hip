@@ -19,6 +19,13 @@
 // of the float64 triple product the channel: positive, negative or
 // degenerate (tied lengths or |V| at most 1e-9 of the spoke-length product).
 // even = pos + neg + degenerate is formed on the host.
+//
+// The same enumeration serves the full 6-edge 4pCF (Sec. 3.3, Sec. 5.3):
+// each clique counts once into the configuration of its six edge bins up to
+// relabelling of its four vertices (a table from the tuple of bins to the
+// configuration's rank), and both counts optionally sum each clique's exact
+// weight product (signed weights of Sec. 2.1) per counter.
+#include <array>
 #include <cstdio>
 #include <cstdlib>
 
@@ -44,30 +51,48 @@ struct C4Args {
     uint32_t anchor_lo, anchor_hi;
     uint64_t flush_limit;
     uint32_t *queue;
-    unsigned long long *hist;   // 3*nconf: pos | neg | degenerate
+    unsigned long long *hist;   // parity: 3*nconf (pos | neg | degenerate); 6-edge: n6
     unsigned long long *ncl;
+    const double *w;            // label-ordered weights (weighted counts)
+    double wmul;                // 2^s, s the exact-sum scale of 4-weight products
+    unsigned long long *wsum;   // weighted: 2 words per counter (two's complement 128-bit)
+    const uint32_t *cfg6;       // 6-edge: configuration of every edge-bin tuple code
+    int n6;                     // 6-edge configurations
+    int lds_cnt;                // counters held in LDS (0: 6-edge counts go to global memory)
 };
+
 
 struct Layout4 {
     uint32_t hkey, hloc, hslot, px, py, pz, sx, sy, sz, pq, pb, pperm, R, rbnd, queue, mstart, mpref, mloc,
-        hist, tab, lut, thr, wtot, misc, total;
+        hist, tab, lut, thr, wtot, misc, pw, wlo, whi, tab6, total;
 };
 
 constexpr int kLut4MaxBins = 16;   // nb^3 u16 counter addresses up to 8 KB
 
 constexpr int kQueue4 = 128;   // clique ring entries per wavefront
 
-__host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxdeg, int W, int nconf,
-                                           int nb, bool anchored) {
+// 6-edge tuple tables of at most this many codes live in LDS (u16 ranks).
+constexpr int kTab6Lds = 4096;
+// 6-edge counters in LDS up to this many configurations.
+constexpr int kCnt6Lds = 6144;
+
+// kind: kParity4 or kSix4; ncnt: counters held in LDS; tab6: codes of the
+// 6-edge table staged in LDS (0: none).
+__host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxdeg, int W, int ncnt,
+                                           int nb, bool anchored, int kind, bool weighted, int tab6) {
     Layout4 L{};
     uint32_t o = 0, d = maxdeg + 1;
+    const bool spokes = kind == kParity4;   // hub spokes and lengths: parity only
     L.px = o;      o = lds_align(o + 8 * d, 16);
     L.py = o;      o = lds_align(o + 8 * d, 16);
     L.pz = o;      o = lds_align(o + 8 * d, 16);
-    L.sx = o;      o = lds_align(o + 8 * d, 16);
-    L.sy = o;      o = lds_align(o + 8 * d, 16);
-    L.sz = o;      o = lds_align(o + 8 * d, 16);
-    L.pq = o;      o = lds_align(o + 8 * d, 16);
+    L.sx = o;      if (spokes) o = lds_align(o + 8 * d, 16);
+    L.sy = o;      if (spokes) o = lds_align(o + 8 * d, 16);
+    L.sz = o;      if (spokes) o = lds_align(o + 8 * d, 16);
+    L.pq = o;      if (spokes) o = lds_align(o + 8 * d, 16);
+    L.pw = o;      if (weighted) o = lds_align(o + 8 * d, 16);
+    L.wlo = o;     if (weighted) o = lds_align(o + 8 * ncnt, 16);
+    L.whi = o;     if (weighted) o = lds_align(o + 8 * ncnt, 16);
     L.thr = o;     o = lds_align(o + 8 * (nb + 1), 16);
     L.mstart = o;  o = lds_align(o + 8 * block, 16);
     L.rbnd = o;    o = lds_align(o + 8 * (d + 1), 16);
@@ -78,9 +103,10 @@ __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxde
     L.R = o;       o = lds_align(o + 4 * d * W, 16);
     L.mpref = o;   o = lds_align(o + 4 * (block + 1), 16);
     L.pperm = o;   if (anchored) o = lds_align(o + 4 * d, 16);
-    L.hist = o;    o = lds_align(o + 4 * 3 * nconf, 16);
+    L.hist = o;    o = lds_align(o + 4 * ncnt, 16);
     L.tab = o;     o = lds_align(o + 8 * (nb + 1), 16);
-    L.lut = o;     if (nb <= kLut4MaxBins) o = lds_align(o + 2 * nb * nb * nb, 16);
+    L.lut = o;     if (spokes && nb <= kLut4MaxBins) o = lds_align(o + 2 * nb * nb * nb, 16);
+    L.tab6 = o;    o = lds_align(o + 2 * tab6, 16);
     L.hloc = o;    o = lds_align(o + 2 * H, 16);
     L.hslot = o;   o = lds_align(o + 2 * d, 16);
     L.mloc = o;    o = lds_align(o + 2 * block, 16);
@@ -189,11 +215,43 @@ struct Stage4 {
     const double *thr;            // t_0 .. t_nb
     const int *ta, *tb;           // configuration rank tables
     const uint16_t *lut;          // nb <= 16: configuration of ordered bin triple (x*nb + y)*nb + z
-    uint32_t *hist;               // pos | neg | degenerate counters
+    uint32_t *hist;               // pos | neg | degenerate counters (parity), 6-edge counters
     int nb, nconf;
     double L, half;
     const double *tk;             // t_1 .. t_15 in the kernel arguments (nb <= 16)
+    const double *pw;             // weights of N+(i) (weighted)
+    double wmul;
+    unsigned long long *wlo, *whi;  // LDS sums of the terms' low 32 bits / high parts
+    unsigned long long *ghist, *gwsum;  // global counters and sums (6-edge beyond LDS)
+    const uint32_t *cfg6;         // 6-edge configuration of a tuple code (global)
+    const uint16_t *tab6;         // the same table in LDS (small bin counts)
 };
+
+// A clique's weight term in units of 2^-s: the four magnitudes in ascending
+// order multiplied left to right, times 2^s (an integer); neg: the product
+// of the four signs is negative.
+__device__ __forceinline__ double clique_term(double w0, double w1, double w2, double w3, double wmul, bool &neg) {
+    neg = (w0 < 0.0) ^ (w1 < 0.0) ^ (w2 < 0.0) ^ (w3 < 0.0);
+    double a = fabs(w0), b = fabs(w1), c = fabs(w2), d = fabs(w3), t;
+    if (a > b) { t = a; a = b; b = t; }
+    if (c > d) { t = c; c = d; d = t; }
+    if (a > c) { t = a; a = c; c = t; }
+    if (b > d) { t = b; b = d; d = t; }
+    if (b > c) { t = b; b = c; c = t; }
+    return __dmul_rn(__dmul_rn(__dmul_rn(__dmul_rn(a, b), c), d), wmul);
+}
+
+// A term into sums k: narrow terms into the LDS sums (when LDS holds them),
+// wide ones into the global 128-bit sums.
+template <bool LDS_CNT>
+__device__ __forceinline__ void add_term(const Stage4 &S, uint32_t k, double x, bool neg) {
+    if (LDS_CNT && narrow_term(x)) {
+        const long long m = (long long)x;
+        lds_term(&S.wlo[k], &S.whi[k], neg ? -m : m);
+    } else {
+        add128_words(&S.gwsum[2 * k], wide_term(x, neg));
+    }
+}
 
 // The minimum-image correction of a plain difference d.
 __device__ __forceinline__ double wrap1(double d, double L, double half) {
@@ -254,9 +312,9 @@ __device__ __forceinline__ uint32_t conf_addr(const Stage4 &S, uint32_t hist_add
 // wrap: the hub is near a face, so a separation may need its minimum-image
 // correction (elsewhere none can apply and the plain difference is the
 // value).
-template <bool LUT>
+template <bool LUT, bool WEIGHTED>
 __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr, uint32_t va, uint32_t vb,
-                                            uint32_t vc, double eb, bool wrap) {
+                                            uint32_t vc, double eb, bool wrap, double wi) {
     const double qa = S.pq[va], qb = S.pq[vb], qc = S.pq[vc];
     const int ba = S.pb[va], bb = S.pb[vb], bc = S.pb[vc];
     double qab, qac, qbc, Vc;
@@ -312,25 +370,102 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr,
     __hip_atomic_fetch_add((lds_u32 *)(size_t)a1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_add((lds_u32 *)(size_t)a2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_add((lds_u32 *)(size_t)a3, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (WEIGHTED) {
+        // every hub contribution carries the clique's weight product
+        bool ng;
+        const double x = clique_term(wi, S.pw[va], S.pw[vb], S.pw[vc], S.wmul, ng);
+        add_term<true>(S, (a0 - hist_addr) >> 2, x, ng);
+        add_term<true>(S, (a1 - hist_addr) >> 2, x, ng);
+        add_term<true>(S, (a2 - hist_addr) >> 2, x, ng);
+        add_term<true>(S, (a3 - hist_addr) >> 2, x, ng);
+    }
 }
 
-template <int BLOCK>
-__device__ void flush4(const C4Args &a, uint32_t *hist) {
-    for (int b = threadIdx.x; b < 3 * a.nconf; b += BLOCK) {
+// The bins of the three separations among a clique's non-hub vertices
+// (the hub's spoke bins are staged): squared lengths from the staged
+// coordinates, counted against the thresholds.
+__device__ __forceinline__ void local_bins(const Stage4 &S, uint32_t va, uint32_t vb, uint32_t vc, bool wrap,
+                                           int &bab, int &bac, int &bbc) {
+    P3 ab, ac, bcv;
+    local_seps(S, va, vb, vc, wrap, ab, ac, bcv);
+    const double qab = sq_len(ab.x, ab.y, ab.z), qac = sq_len(ac.x, ac.y, ac.z), qbc = sq_len(bcv.x, bcv.y, bcv.z);
+    if (S.nb <= 16) {
+        bab = bac = bbc = 0;
+#pragma unroll
+        for (int k = 0; k < 15; ++k)
+            if (k + 1 < S.nb) {
+                const double t = S.tk[k];
+                bab += qab >= t;
+                bac += qac >= t;
+                bbc += qbc >= t;
+            }
+    } else {
+        bab = bin_of(S.thr, S.nb, qab);
+        bac = bin_of(S.thr, S.nb, qac);
+        bbc = bin_of(S.thr, S.nb, qbc);
+    }
+}
+
+// 6-edge configuration of the clique {i, a, b, c}: the code of its edge-bin
+// tuple (ia, ib, ic, ab, ac, bc) looked up in the configuration table (the
+// table is invariant under relabelling, so the order taken does not matter).
+// LDS_CNT: counters in LDS, else 64-bit global counters.
+template <bool TAB6_LDS, bool LDS_CNT, bool WEIGHTED>
+__device__ __forceinline__ void eval_six(const Stage4 &S, uint32_t hist_addr, uint32_t va, uint32_t vb,
+                                         uint32_t vc, bool wrap, double wi) {
+    int bab, bac, bbc;
+    local_bins(S, va, vb, vc, wrap, bab, bac, bbc);
+    const uint32_t nb = (uint32_t)S.nb;
+    const uint32_t code =
+        ((((((uint32_t)S.pb[va] * nb + S.pb[vb]) * nb + S.pb[vc]) * nb + (uint32_t)bab) * nb + (uint32_t)bac) * nb) +
+        (uint32_t)bbc;
+    const uint32_t cfg = TAB6_LDS ? (uint32_t)S.tab6[code] : S.cfg6[code];
+    if (LDS_CNT)
+        __hip_atomic_fetch_add((lds_u32 *)(size_t)(hist_addr + 4 * cfg), 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+        atomicAdd(&S.ghist[cfg], 1ull);
+    if (WEIGHTED) {
+        bool ng;
+        const double x = clique_term(wi, S.pw[va], S.pw[vb], S.pw[vc], S.wmul, ng);
+        add_term<LDS_CNT>(S, cfg, x, ng);
+    }
+}
+
+// LDS counters (and weighted sums) into the 64-bit (128-bit) results.
+template <int BLOCK, bool WEIGHTED>
+__device__ void flush4(const C4Args &a, const Stage4 &S, uint32_t *hist) {
+    for (int b = threadIdx.x; b < a.lds_cnt; b += BLOCK) {
         uint32_t v = hist[b];
         if (v) {
             atomicAdd(&a.hist[b], (unsigned long long)v);
             hist[b] = 0;
         }
+        if (WEIGHTED) {
+            const unsigned long long lo = S.wlo[b], hi = S.whi[b];
+            if (lo | hi) {
+                add128_words(&a.wsum[2 * b], lds_sum128(lo, hi));
+                S.wlo[b] = 0;
+                S.whi[b] = 0;
+            }
+        }
     }
 }
 
-template <int BLOCK, bool ANCHORED, bool LUT>
+// KIND kParity4: VAR 1 = configuration of an ordered bin triple from an LDS
+// table (nb <= 16), 0 = rank arithmetic. KIND kSix4: VAR 0 = tuple table and
+// counters in LDS, 1 = table in global memory and counters in LDS, 2 = both
+// in global memory.
+template <int BLOCK, int KIND, bool ANCHORED, int VAR, bool WEIGHTED>
 __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const uint32_t H = 1u << a.log2h, mask = H - 1;
     const int W = a.W;
-    const Layout4 L = layout4(BLOCK, H, a.maxdeg, W, a.nconf, a.nb, ANCHORED);
+    constexpr bool LUT = KIND == kParity4 && VAR == 1;
+    constexpr bool TAB6 = KIND == kSix4 && VAR == 0;
+    constexpr bool CNT_LDS = KIND == kParity4 || VAR < 2;
+    const Layout4 L = layout4(BLOCK, H, a.maxdeg, W, a.lds_cnt, a.nb, ANCHORED, KIND, WEIGHTED,
+                              TAB6 ? a.nb * a.nb * a.nb * a.nb * a.nb * a.nb : 0);
     uint32_t *hkey = (uint32_t *)(sm + L.hkey);
     uint16_t *hloc = (uint16_t *)(sm + L.hloc);
     uint16_t *hslot = (uint16_t *)(sm + L.hslot);
@@ -358,8 +493,22 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     const int tid = threadIdx.x, lane = tid & 63;
     unsigned long long *ring = (unsigned long long *)(sm + L.queue) + (tid >> 6) * kQueue4;
 
+    double *pw = (double *)(sm + L.pw);
+    unsigned long long *wlo = (unsigned long long *)(sm + L.wlo), *whi = (unsigned long long *)(sm + L.whi);
+    uint16_t *tab6 = (uint16_t *)(sm + L.tab6);
+
     for (uint32_t s = tid; s < H; s += BLOCK) hkey[s] = kEmptyKey;
-    for (int b = tid; b < 3 * a.nconf; b += BLOCK) hist[b] = 0;
+    for (int b = tid; b < a.lds_cnt; b += BLOCK) {
+        hist[b] = 0;
+        if (WEIGHTED) {
+            wlo[b] = 0;
+            whi[b] = 0;
+        }
+    }
+    if (TAB6) {
+        const int n6c = a.nb * a.nb * a.nb * a.nb * a.nb * a.nb;
+        for (int t = tid; t < n6c; t += BLOCK) tab6[t] = (uint16_t)a.cfg6[t];
+    }
     for (int b = tid; b < a.nb; b += BLOCK) {
         ta[b] = rank_a(a.nb, b);
         tb[b] = rank_b(a.nb, b);
@@ -378,7 +527,8 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint64_t acc = 0;
     HubCursor cursor;   // thread 0's claimed run of hubs
     const double Lb = a.L, half = a.half;
-    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, lut, hist, a.nb, a.nconf, a.L, a.half, a.tk};
+    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, lut, hist, a.nb, a.nconf, a.L, a.half, a.tk,
+                   pw, a.wmul, wlo, whi, a.hist, a.wsum, a.cfg6, tab6};
     const uint32_t hist_addr = lds_addr(hist);
 
     while (true) {
@@ -407,15 +557,19 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
             px[e] = x;
             py[e] = y;
             pz[e] = z;
-            const double dx = min_image(xi, x, Lb, half), dy = min_image(yi, y, Lb, half),
-                         dz = min_image(zi, z, Lb, half);
-            sx[e] = dx;
-            sy[e] = dy;
-            sz[e] = dz;
-            pq[e] = sq_len(dx, dy, dz);
+            if (KIND == kParity4) {
+                const double dx = min_image(xi, x, Lb, half), dy = min_image(yi, y, Lb, half),
+                             dz = min_image(zi, z, Lb, half);
+                sx[e] = dx;
+                sy[e] = dy;
+                sz[e] = dz;
+                pq[e] = sq_len(dx, dy, dz);
+            }
             pb[e] = a.bin[beg + e];
             if (ANCHORED) pperm[e] = a.perm[k];
+            if (WEIGHTED) pw[e] = a.w[k];
         }
+        const double wi = WEIGHTED ? a.w[i] : 0.0;
         for (uint32_t w = tid; w < d * W; w += BLOCK) R[w] = 0;
         __syncthreads();
 
@@ -484,7 +638,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
         for (uint32_t r0 = 0; r0 < d;) {
             const uint64_t rest = rbnd[d] - rbnd[r0];
             if (acc > 0 && acc + rest >= a.flush_limit) {
-                flush4<BLOCK>(a, hist);
+                flush4<BLOCK, WEIGHTED>(a, S, hist);
                 acc = 0;
                 __syncthreads();
             }
@@ -546,7 +700,11 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
                                 ++mine_n;
                                 const uint32_t va = (uint32_t)t & 0xFFFFu, vb = (uint32_t)(t >> 16) & 0xFFFFu,
                                                vc = (uint32_t)(t >> 32);
-                                eval_clique<LUT>(S, hist_addr, va, vb, vc, inner ? a.eb_in : a.eb_wrap, !inner);
+                                if (KIND == kParity4)
+                                    eval_clique<LUT, WEIGHTED>(S, hist_addr, va, vb, vc, inner ? a.eb_in : a.eb_wrap,
+                                                               !inner, wi);
+                                else
+                                    eval_six<TAB6, CNT_LDS, WEIGHTED>(S, hist_addr, va, vb, vc, !inner, wi);
                                 wave_lds_sync();
                             }
                         }
@@ -559,7 +717,10 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
                 ++mine_n;
                 const uint32_t va = (uint32_t)t & 0xFFFFu, vb = (uint32_t)(t >> 16) & 0xFFFFu,
                                vc = (uint32_t)(t >> 32);
-                eval_clique<LUT>(S, hist_addr, va, vb, vc, inner ? a.eb_in : a.eb_wrap, !inner);
+                if (KIND == kParity4)
+                    eval_clique<LUT, WEIGHTED>(S, hist_addr, va, vb, vc, inner ? a.eb_in : a.eb_wrap, !inner, wi);
+                else
+                    eval_six<TAB6, CNT_LDS, WEIGHTED>(S, hist_addr, va, vb, vc, !inner, wi);
             }
             mycl += mine_n;
             if (mine_n) atomicAdd(s_round, mine_n);
@@ -574,7 +735,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     }
 
     __syncthreads();
-    flush4<BLOCK>(a, hist);
+    flush4<BLOCK, WEIGHTED>(a, S, hist);
     if (mycl) atomicAdd(s_cnt, mycl);
     __syncthreads();
     if (tid == 0 && *s_cnt) atomicAdd(a.ncl, *s_cnt);
@@ -586,49 +747,151 @@ __global__ void k_zero4(unsigned long long *p, uint64_t n) {
         p[i] = 0;
 }
 
-template <int BLOCK, bool A, bool LUT>
+template <int BLOCK, int KIND, bool A, int VAR, bool WT>
 void launch4(Ctx &ctx, const C4Args &a, uint32_t lds) {
-    const void *kern = reinterpret_cast<const void *>(&k_count4<BLOCK, A, LUT>);
+    const void *kern = reinterpret_cast<const void *>(&k_count4<BLOCK, KIND, A, VAR, WT>);
     if (lds > 65536)
         GS_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
-    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count4<BLOCK, A, LUT>, BLOCK, lds));
-    if (per_cu < 1) fail(GS_EUNSUPPORTED, "parity kernel does not fit a compute unit");
+    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count4<BLOCK, KIND, A, VAR, WT>, BLOCK, lds));
+    if (per_cu < 1) fail(GS_EUNSUPPORTED, "4-clique kernel does not fit a compute unit");
     if (getenv("GS_PLAN_LOG"))
-        fprintf(stderr, "[gsn] count4 block %d lds %u blocks/CU %d maxdeg %u\n", BLOCK, lds, per_cu, a.maxdeg);
+        fprintf(stderr, "[gsn] count4 kind %d var %d block %d lds %u blocks/CU %d maxdeg %u\n", KIND, VAR, BLOCK,
+                lds, per_cu, a.maxdeg);
     uint32_t grid = (uint32_t)ctx.n_cu * (uint32_t)per_cu;
     grid = (grid + kNumQueues - 1) / kNumQueues * kNumQueues;
-    k_count4<BLOCK, A, LUT><<<dim3(grid), dim3(BLOCK), lds, ctx.stream>>>(a);
+    k_count4<BLOCK, KIND, A, VAR, WT><<<dim3(grid), dim3(BLOCK), lds, ctx.stream>>>(a);
     GS_HIP(hipGetLastError());
+}
+
+template <int BLOCK, int KIND, int VAR>
+void launch4_v(Ctx &ctx, const C4Args &a, uint32_t lds, bool anchored, bool wt) {
+    if (anchored) wt ? launch4<BLOCK, KIND, true, VAR, true>(ctx, a, lds) : launch4<BLOCK, KIND, true, VAR, false>(ctx, a, lds);
+    else wt ? launch4<BLOCK, KIND, false, VAR, true>(ctx, a, lds) : launch4<BLOCK, KIND, false, VAR, false>(ctx, a, lds);
+}
+
+// The 24 relabellings of a clique's four vertices as permutations of its six
+// edges (edge order 01, 02, 03, 12, 13, 23): relabelling by p sends edge
+// {x, y} to edge {p(x), p(y)}.
+std::vector<std::array<int, 6>> edge_perms() {
+    auto eid = [](int x, int y) {
+        if (x > y) std::swap(x, y);
+        static const int id[4][4] = {{-1, 0, 1, 2}, {0, -1, 3, 4}, {1, 3, -1, 5}, {2, 4, 5, -1}};
+        return id[x][y];
+    };
+    static const int ex[6] = {0, 0, 0, 1, 1, 2}, ey[6] = {1, 2, 3, 2, 3, 3};
+    std::array<int, 4> p{0, 1, 2, 3};
+    std::vector<std::array<int, 6>> out;
+    do {
+        std::array<int, 6> m;
+        for (int e = 0; e < 6; ++e) m[e] = eid(p[ex[e]], p[ey[e]]);
+        out.push_back(m);
+    } while (std::next_permutation(p.begin(), p.end()));
+    return out;
 }
 
 }  // namespace
 
-void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_t *neg_out,
-                uint64_t *ncl, const gs_anchor_range *anchors) {
+// Configuration rank of every 6-edge tuple code (code = base-nb digits of the
+// bins of edges 01, 02, 03, 12, 13, 23, most significant first): the
+// configurations are the orbits of tuples under the 24 relabellings, each
+// represented by its smallest code, ranked by that code.
+const std::vector<uint32_t> &config6_table(int nb, uint32_t *n6) {
+    static std::mutex mu;
+    static std::map<int, std::pair<std::vector<uint32_t>, uint32_t>> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(nb);
+    if (it == cache.end()) {
+        const uint32_t n = (uint32_t)nb * nb * nb * nb * nb * nb;
+        std::vector<uint32_t> pw(6);
+        for (int e = 0; e < 6; ++e) {
+            uint32_t v = 1;
+            for (int k = e + 1; k < 6; ++k) v *= (uint32_t)nb;
+            pw[e] = v;
+        }
+        const auto perms = edge_perms();
+        std::vector<uint32_t> minc(n), rank(n);
+        for (uint32_t code = 0; code < n; ++code) {
+            int t[6];
+            uint32_t v = code;
+            for (int e = 5; e >= 0; --e) { t[e] = (int)(v % nb); v /= nb; }
+            uint32_t best = code;
+            for (const auto &m : perms) {
+                // tuple u with u[e] = t[m[e]]
+                uint32_t c = 0;
+                for (int e = 0; e < 6; ++e) c += (uint32_t)t[m[e]] * pw[e];
+                best = std::min(best, c);
+            }
+            minc[code] = best;
+        }
+        uint32_t r = 0;
+        for (uint32_t code = 0; code < n; ++code)
+            if (minc[code] == code) rank[code] = r++;
+        for (uint32_t code = 0; code < n; ++code) rank[code] = rank[minc[code]];
+        it = cache.emplace(nb, std::make_pair(std::move(rank), r)).first;
+    }
+    *n6 = it->second.second;
+    return it->second.first;
+}
+
+// The device copy of the table, kept in the context per bin count.
+static const uint32_t *config6_device(Ctx &ctx, int nb, uint32_t *n6) {
+    const std::vector<uint32_t> &t = config6_table(nb, n6);
+    auto it = ctx.cfg6.find(nb);
+    if (it == ctx.cfg6.end()) {
+        DevBuf b(sizeof(uint32_t) * t.size());
+        GS_HIP(hipMemcpy(b.p, t.data(), sizeof(uint32_t) * t.size(), hipMemcpyHostToDevice));
+        it = ctx.cfg6.emplace(nb, std::move(b)).first;
+    }
+    return it->second.as<uint32_t>();
+}
+
+void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_range *anchors) {
     const int nb = g.nbins;
     const int nconf = (int)n_configs(nb);
+    const bool six = o.kind == kSix4;
+    const bool weighted = o.wsum[0] != nullptr;
     const bool anchored = anchors != nullptr;
     if (anchored && anchors->lo > anchors->hi) fail(GS_EINVAL, "anchor range lo > hi");
+    if (six && nb > kMaxBins6) fail(GS_EUNSUPPORTED, "6-edge counts take at most 12 bins");
     const uint32_t maxdeg = g.max_deg;
-    if (maxdeg > 4096) fail(GS_EUNSUPPORTED, "forward degree above 4096 for parity counts");
+    if (maxdeg > 4096) fail(GS_EUNSUPPORTED, "forward degree above 4096 for 4-clique counts");
     uint32_t H = 64;
     int log2h = 6;
     while (H < 2 * maxdeg) { H <<= 1; ++log2h; }
     const int W = (int)((maxdeg + 31) / 32 > 0 ? (maxdeg + 31) / 32 : 1);
+
+    uint32_t n6 = 0;
+    const uint32_t *cfg6 = six ? config6_device(ctx, nb, &n6) : nullptr;
+    const int ncnt = six ? (int)n6 : 3 * nconf;   // counters of this count
+    const int var = six ? (nb * nb * nb * nb * nb * nb <= kTab6Lds ? 0 : (n6 <= (uint32_t)kCnt6Lds ? 1 : 2))
+                        : (nb <= kLut4MaxBins ? 1 : 0);
+    const int lds_cnt = (!six || var < 2) ? ncnt : 0;
+    const int tab6 = six && var == 0 ? nb * nb * nb * nb * nb * nb : 0;
     // 512 lanes: the footprint above (set by the largest forward degree)
     // usually leaves room for two work groups per compute unit, so the
     // wider group doubles the wavefronts that hide LDS and float64 latency
     int BLOCK = 512;
     if (const char *eb = getenv("GS_BLOCK4")) BLOCK = atoi(eb) == 256 ? 256 : 512;
-    Layout4 L = layout4(BLOCK, H, maxdeg, W, nconf, nb, anchored);
+    Layout4 L = layout4(BLOCK, H, maxdeg, W, lds_cnt, nb, anchored, o.kind, weighted, tab6);
     if ((int)L.total > ctx.max_lds)
-        fail(GS_EUNSUPPORTED, "parity kernel LDS footprint too large (forward degree " +
+        fail(GS_EUNSUPPORTED, "4-clique kernel LDS footprint too large (forward degree " +
                                   std::to_string(maxdeg) + ", " + std::to_string(L.total) + " bytes)");
 
-    const size_t qoff = (3 * (size_t)nconf + 1 + 31) / 32 * 32;   // queues 256-byte aligned
+    // device words: counters, clique total, (weighted) 2 words per counter,
+    // hub queues 256-byte aligned, then the squared thresholds
+    const size_t woff = ((size_t)ncnt + 1 + 31) / 32 * 32;
+    const size_t qoff = weighted ? (woff + 2 * (size_t)ncnt + 31) / 32 * 32 : woff;
     const size_t words = qoff + kQueueWords / 2;
-    unsigned long long *dv = (unsigned long long *)ctx.scratch_get(words * 8 + 256 * 8);
+    const size_t need = words * 8 + 256 * 8;
+    unsigned long long *dv;
+    if (o.scratch) {
+        if (need > o.scratch_bytes) fail(GS_EUNSUPPORTED, "count needs " + std::to_string(need) +
+                                                              " bytes of scratch, more than the static limit");
+        dv = (unsigned long long *)o.scratch;
+    } else {
+        dv = (unsigned long long *)ctx.scratch_get(need);
+    }
     double *dthr = (double *)(dv + words);
     C4Args a{};
     a.rp = g.row_ptr.as<uint64_t>();
@@ -674,8 +937,14 @@ void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_
                                                   2ull * (maxdeg + 1) * (maxdeg + 1) + 4);
     if (a.flush_limit < min_limit || a.flush_limit > 0xFFFFFFFFull) a.flush_limit = 0xFFFFFFFFull;
     a.hist = dv;
-    a.ncl = dv + 3 * (size_t)nconf;
+    a.ncl = dv + ncnt;
+    a.wsum = weighted ? dv + woff : nullptr;
     a.queue = (uint32_t *)(dv + qoff);
+    a.w = weighted ? g.weights.as<double>() : nullptr;
+    a.wmul = weighted ? std::ldexp(1.0, weight_scale(g, 4)) : 1.0;
+    a.cfg6 = cfg6;
+    a.n6 = (int)n6;
+    a.lds_cnt = lds_cnt;
 
     hipStream_t s = ctx.stream;
     GS_HIP(hipEventRecord(ctx.ev[0], s));
@@ -683,26 +952,32 @@ void count4_run(Ctx &ctx, const Graph &g, uint64_t *even, uint64_t *pos, uint64_
     GS_HIP(hipMemcpyAsync(dthr, g.bins.t, sizeof(double) * 256, hipMemcpyHostToDevice, s));
     GS_HIP(hipEventRecord(ctx.ev[2], s));
     if (g.n > 0) {
-        const bool lut = nb <= kLut4MaxBins;
-        if (BLOCK == 512) {
-            if (anchored) lut ? launch4<512, true, true>(ctx, a, L.total) : launch4<512, true, false>(ctx, a, L.total);
-            else lut ? launch4<512, false, true>(ctx, a, L.total) : launch4<512, false, false>(ctx, a, L.total);
+        const uint32_t lds = L.total;
+        if (six) {
+            if (var == 0) launch4_v<512, kSix4, 0>(ctx, a, lds, anchored, weighted);
+            else if (var == 1) launch4_v<512, kSix4, 1>(ctx, a, lds, anchored, weighted);
+            else launch4_v<512, kSix4, 2>(ctx, a, lds, anchored, weighted);
+        } else if (BLOCK == 512) {
+            if (var == 1) launch4_v<512, kParity4, 1>(ctx, a, lds, anchored, weighted);
+            else launch4_v<512, kParity4, 0>(ctx, a, lds, anchored, weighted);
         } else {
-            if (anchored) lut ? launch4<256, true, true>(ctx, a, L.total) : launch4<256, true, false>(ctx, a, L.total);
-            else lut ? launch4<256, false, true>(ctx, a, L.total) : launch4<256, false, false>(ctx, a, L.total);
+            if (var == 1) launch4_v<256, kParity4, 1>(ctx, a, lds, anchored, weighted);
+            else launch4_v<256, kParity4, 0>(ctx, a, lds, anchored, weighted);
         }
     }
     GS_HIP(hipEventRecord(ctx.ev[3], s));
-    std::vector<unsigned long long> h(3 * (size_t)nconf + 1);
-    GS_HIP(hipMemcpyAsync(h.data(), dv, h.size() * 8, hipMemcpyDeviceToHost, s));
+    // results straight into the caller's arrays, one block of counters each
+    const int nblk = six ? 1 : 3;
+    const size_t per = six ? (size_t)n6 : (size_t)nconf;
+    for (int b = 0; b < nblk; ++b) {
+        GS_HIP(hipMemcpyAsync(o.cnt[b], dv + b * per, per * 8, hipMemcpyDeviceToHost, s));
+        if (weighted)
+            GS_HIP(hipMemcpyAsync(o.wsum[b], dv + woff + 2 * b * per, 2 * per * 8, hipMemcpyDeviceToHost, s));
+    }
+    GS_HIP(hipMemcpyAsync(o.ncl, dv + ncnt, 8, hipMemcpyDeviceToHost, s));
     GS_HIP(hipEventRecord(ctx.ev[1], s));
     GS_HIP(hipStreamSynchronize(s));
-    for (int c = 0; c < nconf; ++c) {
-        pos[c] = h[c];
-        neg_out[c] = h[nconf + c];
-        even[c] = h[c] + h[nconf + c] + h[2 * (size_t)nconf + c];
-    }
-    *ncl = h[3 * (size_t)nconf];
+    if (o.wscale) *o.wscale = weighted ? weight_scale(g, 4) : 0;
     float ms = 0, kms = 0;
     GS_HIP(hipEventElapsedTime(&ms, ctx.ev[0], ctx.ev[1]));
     GS_HIP(hipEventElapsedTime(&kms, ctx.ev[2], ctx.ev[3]));

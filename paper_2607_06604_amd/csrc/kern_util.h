@@ -87,6 +87,47 @@ __device__ __forceinline__ uint64_t wg_excl_scan64(uint64_t v, uint64_t *wtot, u
     return off + x - v;
 }
 
+// ---- exact weighted sums ----
+// A tuple's weight term is x = +-(product of weight magnitudes) * 2^s, an
+// integer below 2^87 (the scale s makes the smallest possible product an
+// integer of 53 bits; the weight range check bounds the largest). Sums are
+// signed 128-bit integers kept as (lo, hi) 64-bit words, two's complement.
+
+// 128-bit two's complement add into a (lo, hi) pair of global words.
+__device__ __forceinline__ void add128_words(unsigned long long *dst, __int128 v) {
+    const unsigned long long lo = (unsigned long long)v;
+    unsigned long long hi = (unsigned long long)((unsigned __int128)v >> 64);
+    const unsigned long long old = atomicAdd(&dst[0], lo);
+    if (old + lo < old) hi += 1;
+    if (hi) atomicAdd(&dst[1], hi);
+}
+
+constexpr double kTwo63 = 9223372036854775808.0;
+
+// Narrow terms (magnitude below 2^63) as one signed 64-bit integer.
+__device__ __forceinline__ bool narrow_term(double x) { return x < kTwo63; }
+
+// A term as a signed 128-bit integer: x = h * 2^32 + l with h = trunc(x 2^-32)
+// and l = x - h 2^32, both exact (x is an integer, l < 2^32 is representable).
+__device__ __forceinline__ __int128 wide_term(double x, bool neg) {
+    const double h = trunc(__dmul_rn(x, 0x1.0p-32));
+    const double l = __dsub_rn(x, __dmul_rn(h, 0x1.0p32));
+    const __int128 v = ((__int128)(long long)h << 32) + (__int128)(long long)l;
+    return neg ? -v : v;
+}
+
+// A narrow term into LDS sums: its low 32 bits and its arithmetic high part
+// (term = high * 2^32 + low), each summed in 64 bits (room for 2^32 terms).
+__device__ __forceinline__ void lds_term(unsigned long long *lo, unsigned long long *hi, long long t) {
+    atomicAdd(lo, (unsigned long long)t & 0xFFFFFFFFull);
+    atomicAdd(hi, (unsigned long long)(t >> 32));
+}
+
+// The 128-bit value of a pair of LDS sums.
+__device__ __forceinline__ __int128 lds_sum128(unsigned long long lo, unsigned long long hi) {
+    return ((__int128)(long long)hi << 32) + (__int128)lo;
+}
+
 // Lanes below this one with their bit set in the 64-bit wave mask.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));

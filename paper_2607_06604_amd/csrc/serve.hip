@@ -245,11 +245,18 @@ void count_loop(Server *Sp) {
                 if (r->kind == GS_4PCF_PARITY) {
                     r->pos.assign(nconf, 0);
                     r->neg.assign(nconf, 0);
-                    count4_run(S.cctx, g, r->hist.data(), r->pos.data(), r->neg.data(), &r->ntri, nullptr);
+                    Count4Out o;
+                    o.kind = kParity4;
+                    o.cnt[0] = r->pos.data();
+                    o.cnt[1] = r->neg.data();
+                    o.cnt[2] = r->hist.data();
+                    o.ncl = &r->ntri;
+                    count4_run(S.cctx, g, o, nullptr);
+                    for (int64_t c = 0; c < nconf; ++c) r->hist[c] += r->pos[c] + r->neg[c];
                 } else {
                     r->wsum.assign(2 * nconf, 0);
+                    r->wscale = weight_scale(g, 3);
                     count3_run(S.cctx, g, r->hist.data(), r->wsum.data(), &r->ntri, nullptr);
-                    r->wscale = g.wscale;
                 }
             } catch (const Error &e) {
                 (void)hipStreamSynchronize(S.cstream);
@@ -438,10 +445,7 @@ int gs_poll(gs_ctx *ctx, uint64_t ticket, gs_result *out) {
             if (out->wsum128 && !r.wsum.empty())
                 memcpy(out->wsum128, r.wsum.data(), sizeof(uint64_t) * r.wsum.size());
             if (out->whist && !r.wsum.empty())
-                for (size_t c = 0; c < r.wsum.size() / 2; ++c) {
-                    const unsigned __int128 v = ((unsigned __int128)r.wsum[2 * c + 1] << 64) | r.wsum[2 * c];
-                    out->whist[c] = std::ldexp((double)v, -r.wscale);
-                }
+                for (size_t c = 0; c < r.wsum.size() / 2; ++c) out->whist[c] = sum128_to_double(&r.wsum[2 * c], r.wscale);
         }
         const bool built = r.t_build1 != Clock::time_point{};
         out->t_queue_s = r.t_build0 != Clock::time_point{} ? secs(r.t_submit, r.t_build0) : secs(r.t_submit, r.t_done);

@@ -43,7 +43,8 @@ GS_4PCF_PARITY = 1
 EXPORTS = ["gs_create", "gs_destroy", "gs_build_graph", "gs_graph_info", "gs_graph_export",
            "gs_graph_free", "gs_count_3pcf", "gs_count_4pcf_parity", "gs_count_3pcf_batch",
            "gs_tune_3pcf", "gs_submit", "gs_poll", "gs_cancel", "gs_get_timings", "gs_strerror",
-           "gs_last_error_detail", "gs_ceiling_copy", "gs_ceiling_probe"]
+           "gs_last_error_detail", "gs_ceiling_copy", "gs_ceiling_probe", "gs_count_4pcf_parity_weighted",
+           "gs_count_4pcf_full", "gs_n_configs6", "gs_config6_table", "gs_pair_sums"]
 
 
 class GraphParams(ctypes.Structure):
@@ -122,6 +123,11 @@ def load(path: str = LIB_PATH):
         "gs_graph_free": ([P], i32),
         "gs_count_3pcf": ([P, P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_count_4pcf_parity": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
+        "gs_count_4pcf_parity_weighted": ([P, P, P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
+        "gs_count_4pcf_full": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
+        "gs_n_configs6": ([i32, ctypes.POINTER(ctypes.c_uint32)], i32),
+        "gs_config6_table": ([i32, P], i32),
+        "gs_pair_sums": ([P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_ceiling_copy": ([P, u64, ctypes.POINTER(ctypes.c_double)], i32),
         "gs_ceiling_probe": ([P, i32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, i32, i32, i32,
                               ctypes.POINTER(ctypes.c_double)], i32),
@@ -166,6 +172,33 @@ def _ptr(a):
 
 def n_configs(nbins: int) -> int:
     return (nbins + 2) * (nbins + 1) * nbins // 6
+
+
+def n_configs6(nbins: int) -> int:
+    """6-edge configurations at nbins (gs_n_configs6)."""
+    v = ctypes.c_uint32()
+    _check(load().gs_n_configs6(int(nbins), ctypes.byref(v)), "gs_n_configs6")
+    return int(v.value)
+
+
+def config6_table(nbins: int) -> np.ndarray:
+    """Configuration of every 6-edge bin-tuple code (gs_config6_table)."""
+    t = np.zeros(nbins ** 6, dtype=np.uint32)
+    _check(load().gs_config6_table(int(nbins), _ptr(t)), "gs_config6_table")
+    return t
+
+
+def _anchors(anchors):
+    return None if anchors is None else ctypes.byref(AnchorRange(int(anchors[0]), int(anchors[1])))
+
+
+def _signed128(words) -> list:
+    """(lo, hi) u64 word pairs as Python ints (two's complement 128-bit)."""
+    out = []
+    for lo, hi in np.asarray(words, dtype=np.uint64).reshape(-1, 2):
+        v = int(lo) + (int(hi) << 64)
+        out.append(v - (1 << 128) if v >> 127 else v)
+    return out
 
 
 class Context:
@@ -241,14 +274,40 @@ class Context:
                                     _ptr(ntri), ar), "gs_count_3pcf")
         return Count3(hist, int(ntri[0]), wsum, whist, int(ws[0]) if weighted else None)
 
-    def count_4pcf_parity(self, g: "Graph", anchors=None):
+    def count_4pcf_parity(self, g: "Graph", anchors=None, weighted=False):
         nc = n_configs(g.nbins)
         e, p, m = (np.zeros(nc, dtype=np.uint64) for _ in range(3))
         nk = np.zeros(1, dtype=np.uint64)
-        ar = None if anchors is None else ctypes.byref(AnchorRange(int(anchors[0]), int(anchors[1])))
-        _check(load().gs_count_4pcf_parity(self._h, g.handle, _ptr(e), _ptr(p), _ptr(m), _ptr(nk), ar),
-               "gs_count_4pcf_parity")
-        return Count4(e, p, m, int(nk[0]))
+        if not weighted:
+            _check(load().gs_count_4pcf_parity(self._h, g.handle, _ptr(e), _ptr(p), _ptr(m), _ptr(nk),
+                                               _anchors(anchors)), "gs_count_4pcf_parity")
+            return Count4(e, p, m, int(nk[0]))
+        ws = np.zeros((3, nc, 2), dtype=np.uint64)
+        sc = np.zeros(1, dtype=np.int32)
+        _check(load().gs_count_4pcf_parity_weighted(self._h, g.handle, _ptr(e), _ptr(p), _ptr(m), _ptr(ws),
+                                                    _ptr(sc), _ptr(nk), _anchors(anchors)),
+               "gs_count_4pcf_parity_weighted")
+        return Count4(e, p, m, int(nk[0]), ws, int(sc[0]))
+
+    def count_4pcf_full(self, g: "Graph", anchors=None, weighted=False):
+        """6-edge 4-clique counts (and exact weighted sums)."""
+        n6 = n_configs6(g.nbins)
+        h = np.zeros(n6, dtype=np.uint64)
+        nk = np.zeros(1, dtype=np.uint64)
+        ws = np.zeros((n6, 2), dtype=np.uint64) if weighted else None
+        sc = np.zeros(1, dtype=np.int32) if weighted else None
+        _check(load().gs_count_4pcf_full(self._h, g.handle, _ptr(h), _ptr(ws), _ptr(sc), _ptr(nk),
+                                         _anchors(anchors)), "gs_count_4pcf_full")
+        return Count6(h, int(nk[0]), ws, int(sc[0]) if weighted else None)
+
+    def pair_sums(self, g: "Graph", anchors=None, weighted=False):
+        """Pairs per bin (and exact weighted pair sums)."""
+        pr = np.zeros(g.nbins, dtype=np.uint64)
+        ws = np.zeros((g.nbins, 2), dtype=np.uint64) if weighted else None
+        sc = np.zeros(1, dtype=np.int32) if weighted else None
+        _check(load().gs_pair_sums(self._h, g.handle, _ptr(pr), _ptr(ws), _ptr(sc), _anchors(anchors)),
+               "gs_pair_sums")
+        return Pairs(pr, ws, int(sc[0]) if weighted else None)
 
     def tune_3pcf(self, g: "Graph", weighted=False) -> dict:
         """Autotune the triangle-count schedule on g's shape (kept in this
@@ -347,7 +406,7 @@ class Count3:
     wscale: int | None
 
     def wsum_int(self):
-        return [int(lo) + (int(hi) << 64) for lo, hi in self.wsum]
+        return _signed128(self.wsum)
 
 
 @dataclass
@@ -356,10 +415,36 @@ class Count4:
     pos: np.ndarray
     neg: np.ndarray
     n_cliques: int
+    wsum: np.ndarray | None = None   # (3, nconf, 2): even | pos | neg, 128-bit words
+    wscale: int | None = None
 
     @property
     def odd(self):
         return self.pos.astype(np.int64) - self.neg.astype(np.int64)
+
+    def wsum_int(self, channel: int = 0):
+        return _signed128(self.wsum[channel])
+
+
+@dataclass
+class Count6:
+    hist: np.ndarray
+    n_cliques: int
+    wsum: np.ndarray | None
+    wscale: int | None
+
+    def wsum_int(self):
+        return _signed128(self.wsum)
+
+
+@dataclass
+class Pairs:
+    pairs: np.ndarray
+    wsum: np.ndarray | None
+    wscale: int | None
+
+    def wsum_int(self):
+        return _signed128(self.wsum)
 
 
 class Graph:

@@ -250,7 +250,7 @@ def test_invalid_inputs_rejected(ctx, gsn):
         ctx.build_graph(y, 10.0, 0.0, 2.0, 4)
     assert e.value.code == gsn.GS_EINVAL
     with pytest.raises(gsn.GsError) as e:
-        ctx.build_graph(x, 10.0, 0.0, 2.0, 4, weights=-np.ones(100))
+        ctx.build_graph(x, 10.0, 0.0, 2.0, 4, weights=np.zeros(100))   # weights must be nonzero
     assert e.value.code == gsn.GS_EINVAL
     g = ctx.build_graph(x, 10.0, 0.0, 2.0, 4)
     with pytest.raises(gsn.GsError) as e:
