@@ -291,7 +291,7 @@ class Context:
 
     def count_4pcf_full(self, g: "Graph", anchors=None, weighted=False):
         """6-edge 4-clique counts (and exact weighted sums)."""
-        n6 = n_configs6(g.nbins)
+        n6 = n_configs6(g.nbins) if 1 <= g.nbins <= 12 else 1   # the library refuses other bin counts
         h = np.zeros(n6, dtype=np.uint64)
         nk = np.zeros(1, dtype=np.uint64)
         ws = np.zeros((n6, 2), dtype=np.uint64) if weighted else None
