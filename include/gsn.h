@@ -158,6 +158,20 @@ int gs_count_3pcf(gs_ctx *ctx, const gs_graph *g, uint64_t *hist, uint64_t *wsum
 int gs_count_4pcf_parity(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos,
                          uint64_t *neg, uint64_t *n_cliques, const gs_anchor_range *anchors);
 
+/* The parity count of gs_count_4pcf_parity, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): its counters, clique total, hub queues
+ * and thresholds live in a fixed 64 KiB array of device memory that the
+ * library holds per device until the process ends (its address is taken at
+ * gs_create), so the call allocates nothing; results and errors are those of
+ * gs_count_4pcf_parity. Limit: GS_EUNSUPPORTED when the count needs more
+ * than 64 KiB of scratch (more than 23 bins). Every call on a device shares
+ * that device's array: calls that overlap on one device (other contexts or
+ * threads) race and must be serialised by the caller. The array is cleared
+ * at the start of each call. */
+int gs_count_4pcf_parity_noalloc(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos,
+                                 uint64_t *neg, uint64_t *n_cliques, const gs_anchor_range *anchors);
+
 /* Weighted parity counts (Sec. 3.2 with the signed weights of Sec. 2.1):
  * the counts of gs_count_4pcf_parity, and per configuration the exact sums
  * of each hub contribution's clique weight t = +-((a1*a2)*a3)*a4 (the four

@@ -244,6 +244,7 @@ int gs_create(gs_ctx **out, int device, uint64_t hbm_budget_bytes, void *hip_str
         c->pool = std::make_shared<DevPool>();
         c->pool->device = device;
         c->pool->cap = c->budget / 8;
+        static_scratch_init(device);
     });
     if (rc != GS_OK) {
         if (c) gs_destroy(c);
@@ -396,6 +397,30 @@ int gs_count_4pcf_parity(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_
         o.cnt[1] = neg;
         o.cnt[2] = even;   // the degenerate block, then even = pos + neg + degenerate
         o.ncl = n_cliques;
+        count4_run(*ctx, *g, o, anchors);
+        for (int64_t c = 0; c < nc; ++c) even[c] += pos[c] + neg[c];
+    });
+}
+
+int gs_count_4pcf_parity_noalloc(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos,
+                                 uint64_t *neg, uint64_t *n_cliques, const gs_anchor_range *anchors) {
+    return guarded([&] {
+        if (!ctx || !g || !even || !pos || !neg || !n_cliques) fail(GS_EINVAL, "null argument");
+        if (!(g->flags & GS_KEEP_COORDS)) fail(GS_ENOCOORDS, "parity needs GS_KEEP_COORDS");
+        if (g->n_windows > 1) fail(GS_EUNSUPPORTED, "parity counts need a device-resident graph");
+        if (g->device != ctx->device) fail(GS_EINVAL, "graph and context on different devices");
+        ctx->use();
+        size_t bytes = 0;
+        void *ptr = static_scratch(ctx->device, &bytes);
+        const int64_t nc = n_configs(g->nbins);
+        Count4Out o;
+        o.kind = kParity4;
+        o.cnt[0] = pos;
+        o.cnt[1] = neg;
+        o.cnt[2] = even;
+        o.ncl = n_cliques;
+        o.scratch = ptr;
+        o.scratch_bytes = bytes;
         count4_run(*ctx, *g, o, anchors);
         for (int64_t c = 0; c < nc; ++c) even[c] += pos[c] + neg[c];
     });

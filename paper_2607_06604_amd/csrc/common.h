@@ -309,6 +309,11 @@ struct Count4Out {
     size_t scratch_bytes = 0;
 };
 void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_range *anchors);
+// The allocation-free parity count's device scratch: a file-scope device
+// array (one copy per device); static_scratch_init takes its address on a
+// device once (at context creation), static_scratch returns it.
+void static_scratch_init(int device);
+void *static_scratch(int device, size_t *bytes);
 // Configuration rank of every 6-edge bin-tuple code, and the number of
 // configurations (host table, cached per bin count).
 const std::vector<uint32_t> &config6_table(int nb, uint32_t *n6);

@@ -792,6 +792,38 @@ std::vector<std::array<int, 6>> edge_perms() {
 
 }  // namespace
 
+// Scratch of the allocation-free parity count: counters, the clique total,
+// the hub queues and the thresholds live in this file-scope array, one copy
+// per device, held until the process ends. Host code never passes the
+// array's name to a kernel: it uses the device address that
+// hipGetSymbolAddress gives for the current device.
+constexpr size_t kStaticScratchBytes = 64u << 10;
+static __device__ __align__(256) unsigned long long scratch[kStaticScratchBytes / 8];
+
+static std::mutex g_static_mu;
+static std::map<int, void *> g_static_ptr;   // device -> address of its copy of scratch
+
+void static_scratch_init(int device) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_ptr.count(device)) return;
+    int cur = 0;
+    GS_HIP(hipGetDevice(&cur));
+    GS_HIP(hipSetDevice(device));
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) fail(GS_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_static_ptr[device] = ptr;
+}
+
+void *static_scratch(int device, size_t *bytes) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    auto it = g_static_ptr.find(device);
+    if (it == g_static_ptr.end()) fail(GS_EHIP, "static scratch not set up on this device");
+    *bytes = kStaticScratchBytes;
+    return it->second;
+}
+
 // Configuration rank of every 6-edge tuple code (code = base-nb digits of the
 // bins of edges 01, 02, 03, 12, 13, 23, most significant first): the
 // configurations are the orbits of tuples under the 24 relabellings, each

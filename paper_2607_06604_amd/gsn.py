@@ -44,7 +44,8 @@ EXPORTS = ["gs_create", "gs_destroy", "gs_build_graph", "gs_graph_info", "gs_gra
            "gs_graph_free", "gs_count_3pcf", "gs_count_4pcf_parity", "gs_count_3pcf_batch",
            "gs_tune_3pcf", "gs_submit", "gs_poll", "gs_cancel", "gs_get_timings", "gs_strerror",
            "gs_last_error_detail", "gs_ceiling_copy", "gs_ceiling_probe", "gs_count_4pcf_parity_weighted",
-           "gs_count_4pcf_full", "gs_n_configs6", "gs_config6_table", "gs_pair_sums"]
+           "gs_count_4pcf_full", "gs_n_configs6", "gs_config6_table", "gs_pair_sums",
+           "gs_count_4pcf_parity_noalloc"]
 
 
 class GraphParams(ctypes.Structure):
@@ -124,6 +125,7 @@ def load(path: str = LIB_PATH):
         "gs_count_3pcf": ([P, P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_count_4pcf_parity": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_count_4pcf_parity_weighted": ([P, P, P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
+        "gs_count_4pcf_parity_noalloc": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_count_4pcf_full": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_n_configs6": ([i32, ctypes.POINTER(ctypes.c_uint32)], i32),
         "gs_config6_table": ([i32, P], i32),
@@ -274,13 +276,16 @@ class Context:
                                     _ptr(ntri), ar), "gs_count_3pcf")
         return Count3(hist, int(ntri[0]), wsum, whist, int(ws[0]) if weighted else None)
 
-    def count_4pcf_parity(self, g: "Graph", anchors=None, weighted=False):
+    def count_4pcf_parity(self, g: "Graph", anchors=None, weighted=False, noalloc=False):
+        """Parity counts (weighted: with exact clique-weight sums; noalloc: the
+        entry point that allocates no device memory)."""
         nc = n_configs(g.nbins)
         e, p, m = (np.zeros(nc, dtype=np.uint64) for _ in range(3))
         nk = np.zeros(1, dtype=np.uint64)
         if not weighted:
-            _check(load().gs_count_4pcf_parity(self._h, g.handle, _ptr(e), _ptr(p), _ptr(m), _ptr(nk),
-                                               _anchors(anchors)), "gs_count_4pcf_parity")
+            f = load().gs_count_4pcf_parity_noalloc if noalloc else load().gs_count_4pcf_parity
+            _check(f(self._h, g.handle, _ptr(e), _ptr(p), _ptr(m), _ptr(nk), _anchors(anchors)),
+                   "gs_count_4pcf_parity_noalloc" if noalloc else "gs_count_4pcf_parity")
             return Count4(e, p, m, int(nk[0]))
         ws = np.zeros((3, nc, 2), dtype=np.uint64)
         sc = np.zeros(1, dtype=np.int32)
