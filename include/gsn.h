@@ -209,6 +209,31 @@ int gs_n_configs6(int32_t nbins, uint32_t *n6);
  * above). */
 int gs_config6_table(int32_t nbins, uint32_t *rank);
 
+/* Equilateral triangle counts (the restricted 3pCF kernel of Sec. 3.5):
+ * triangles whose three sides lie in one bin b, per b; equal to the (b,b,b)
+ * configurations of gs_count_3pcf, found without probing candidates whose
+ * spoke-row bin differs from the spoke's.
+ *  hist: host u64[nbins]; wsum128: nullable, host u64[2*nbins], the exact
+ *    signed weighted sums (as gs_count_3pcf); wscale: nullable, out;
+ *  n_triangles: host out (equilateral triangles); anchors: nullable.
+ * Device-resident graphs (GS_EUNSUPPORTED for host-tiled ones). */
+int gs_count_3pcf_equilateral(gs_ctx *ctx, const gs_graph *g, uint64_t *hist, uint64_t *wsum128,
+                              int32_t *wscale, uint64_t *n_triangles, const gs_anchor_range *anchors);
+
+/* mu-binned triangle counts (anisotropic 3pCF, Sec. 6): each triangle counts
+ * into configuration conf * nmu + m, conf the rank of its sorted side bins
+ * and m the bin of mu = |nz|/|n| of its plane's normal n against the line of
+ * sight z, in nmu equal bins [k/nmu, (k+1)/nmu) of [0, 1]. With the vertices
+ * in original-index order p0 < p1 < p2, n = sep(p0,p1) x sep(p0,p2) (cross
+ * product as in gs_count_4pcf_parity), s = (nx*nx + ny*ny) + nz*nz, and m is
+ * the number of k in 1..nmu-1 with (nz*nz)*(nmu*nmu) >= (k*k)*s; a collinear
+ * triangle (s = 0) has m = 0.
+ *  nmu: 1..64; hist: host u64[C(nbins+2,3)*nmu]; wsum128, wscale: nullable
+ *    (as gs_count_3pcf, per counter); n_triangles: host out.
+ * Needs GS_KEEP_COORDS; device-resident graphs. */
+int gs_count_3pcf_mu(gs_ctx *ctx, const gs_graph *g, int32_t nmu, uint64_t *hist, uint64_t *wsum128,
+                     int32_t *wscale, uint64_t *n_triangles, const gs_anchor_range *anchors);
+
 /* Pair counts per bin and exact weighted pair sums (the internal 2pCF that
  * the connected 4pCF of Sec. 3.3 subtracts): every edge once.
  *  pairs: host u64[nbins];

@@ -64,6 +64,8 @@ def _load():
         lib.oracle_pair_sums.argtypes = [P, i64, P, d, d, d, i32, i64, i64, P, P, P]
         lib.oracle_pair_sums.restype = i32
         lib.oracle_count_4pcf_full.restype = i32
+        lib.oracle_count_3pcf_mu.argtypes = [P, i64, P, d, d, d, i32, i32, i64, i64, i32, P, P, P, P, P]
+        lib.oracle_count_3pcf_mu.restype = i32
         _lib = lib
     return _lib
 
@@ -247,6 +249,26 @@ def count_4pcf_parity(xyz, box, rmin, rmax, nbins, anchors=None, threads=0, weig
     if rc:
         raise OracleError(rc)
     return Result4(e, p, m, int(nk[0]), int(used[0]), ws, int(sc[0]) if w is not None else None)
+
+
+def count_3pcf_mu(xyz, box, rmin, rmax, nbins, nmu, weights=None, anchors=None, threads=0) -> Result3:
+    """Triangles binned by sorted side bins and by the mu bin of their plane's
+    normal (counter conf * nmu + mu bin)."""
+    x = _xyz(xyz)
+    n = x.shape[0]
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    lo, hi = (0, n) if anchors is None else anchors
+    nc = n_configs(nbins) * nmu if 1 <= nbins <= 255 and nmu >= 1 else 1
+    hist = np.zeros(nc, dtype=np.uint64)
+    wsum = np.zeros((nc, 2), dtype=np.uint64) if w is not None else None
+    ws = np.zeros(1, dtype=np.int32)
+    nt = np.zeros(1, dtype=np.uint64)
+    used = np.zeros(1, dtype=np.int32)
+    rc = _load().oracle_count_3pcf_mu(_p(x), n, _p(w), box, rmin, rmax, nbins, nmu, lo, hi, threads, _p(hist),
+                                      _p(wsum), _p(ws), _p(nt), _p(used))
+    if rc:
+        raise OracleError(rc)
+    return Result3(hist, int(nt[0]), wsum, int(ws[0]) if w is not None else None, int(used[0]))
 
 
 def n_configs6(nbins: int) -> int:

@@ -53,6 +53,9 @@
  *    configurations are indexed by their rank in lexicographic order among
  *    all such smallest tuples.
  *
+ * D9 mu-binned 3pCF (anisotropy, Sec. 6): each triangle also carries the
+ *    bin of mu = |nz|/|n|, n the normal of its plane (see mu_bin below).
+ *
  * Anchors: only tuples whose smallest original point index lies in
  * [anchor_lo, anchor_hi) are counted.
  */
@@ -556,6 +559,109 @@ static int hub_parity(const params_t *p, const double *xyz, int64_t h, const int
 static i128 clique_weight(const double *w, const int64_t v[4], double scale) {
     const double x[4] = {w[v[0]], w[v[1]], w[v[2]], w[v[3]]};
     return (i128)(signed_product(x, 4) * scale);
+}
+
+/* ------------------------------------------------ mu-binned triangles ---- */
+
+/* D9 mu binning (anisotropic 3pCF, Sec. 6; our reading): a triangle with
+ * vertices p0 < p1 < p2 (original indices) has normal n = sep(p0,p1) x
+ * sep(p0,p2) (the D6 cross product); with s = (nx*nx + ny*ny) + nz*nz and
+ * t = (nz*nz)*(nmu*nmu) its mu bin is the number of k in 1..nmu-1 with
+ * t >= (k*k)*s (mu = |nz|/|n| against the z line of sight, equal bins of
+ * [0, 1]); s = 0 (collinear) gives bin 0. */
+static int mu_bin(const params_t *p, const double *a, const double *b, const double *c, int nmu) {
+    double u[3], v[3];
+    separation(p, a, b, u);
+    separation(p, a, c, v);
+    const double nx = u[1] * v[2] - u[2] * v[1];
+    const double ny = u[2] * v[0] - u[0] * v[2];
+    const double nz = u[0] * v[1] - u[1] * v[0];
+    const double s = (nx * nx + ny * ny) + nz * nz;
+    if (!(s > 0.0)) return 0;
+    const double t = (nz * nz) * (double)(nmu * nmu);
+    int m = 0;
+    for (int k = 1; k < nmu; ++k)
+        if (t >= (double)(k * k) * s) ++m;
+    return m;
+}
+
+/* Triangles binned by sorted side bins and mu bin: counter conf*nmu + mu. */
+int oracle_count_3pcf_mu(const double *xyz, int64_t n, const double *w, double box, double rmin, double rmax,
+                         int nbins, int nmu, int64_t anchor_lo, int64_t anchor_hi, int nthreads, uint64_t *hist,
+                         uint64_t *wsum, int *wscale, uint64_t *n_tri, int *threads_used) {
+    params_t p;
+    int rc = make_params(&p, box, rmin, rmax, nbins);
+    if (rc == OR_OK) rc = check_points(xyz, n, box);
+    if (rc != OR_OK) return rc;
+    if (n >= ((int64_t)1 << 31) || !hist || !n_tri || nmu < 1 || nmu > 64) return OR_EINVAL;
+    int s = 0;
+    if (w) {
+        if (!wsum) return OR_EINVAL;
+        rc = weight_scale(w, n, &s);
+        if (rc != OR_OK) return rc;
+        if (wscale) *wscale = s;
+    }
+    if (anchor_lo < 0) anchor_lo = 0;
+    if (anchor_hi > n) anchor_hi = n;
+    int nt = resolve_threads(nthreads);
+    if (threads_used) *threads_used = nt;
+    rows_t g;
+    rc = rows_for_anchors(&p, xyz, n, nt, anchor_lo, anchor_hi, &g);
+    if (rc != OR_OK) return rc;
+    const int64_t ncnt = binom3(nbins + 2) * nmu;
+    uint64_t *th = (uint64_t *)calloc((size_t)(nt * ncnt), sizeof(uint64_t));
+    i128 *tw = w ? (i128 *)calloc((size_t)(nt * ncnt), sizeof(i128)) : NULL;
+    uint64_t *tn = (uint64_t *)calloc((size_t)nt, sizeof(uint64_t));
+    if (!th || !tn || (w && !tw)) { free(th); free(tw); free(tn); rows_free(&g); return OR_ENOMEM; }
+    const double scale = ldexp(1.0, s);
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = omp_get_thread_num();
+        uint64_t *H = th + (int64_t)tid * ncnt;
+        i128 *Wt = w ? tw + (int64_t)tid * ncnt : NULL;
+        uint64_t cnt = 0;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = anchor_lo; i < anchor_hi; ++i) {
+            for (int64_t a = g.ptr[i]; a < g.ptr[i + 1]; ++a) {
+                int32_t j = g.col[a];
+                if (j <= i) continue;
+                for (int64_t b = a + 1; b < g.ptr[i + 1]; ++b) {
+                    int32_t k = g.col[b];
+                    int64_t f = find(&g, j, k);
+                    if (f < 0) continue;
+                    /* i < j < k: the vertices in original-index order */
+                    int b1 = g.bin[a], b2 = g.bin[b], b3 = g.bin[f];
+                    sort3i(&b1, &b2, &b3);
+                    const int64_t idx = config_index(nbins, b1, b2, b3) * nmu +
+                                        mu_bin(&p, &xyz[3 * i], &xyz[3 * (int64_t)j], &xyz[3 * (int64_t)k], nmu);
+                    H[idx] += 1;
+                    ++cnt;
+                    if (Wt) {
+                        const double v[3] = {w[i], w[j], w[k]};
+                        Wt[idx] += (i128)(signed_product(v, 3) * scale);
+                    }
+                }
+            }
+        }
+        tn[tid] = cnt;
+    }
+    memset(hist, 0, sizeof(uint64_t) * (size_t)ncnt);
+    *n_tri = 0;
+    for (int t = 0; t < nt; ++t) {
+        *n_tri += tn[t];
+        for (int64_t c = 0; c < ncnt; ++c) hist[c] += th[(int64_t)t * ncnt + c];
+    }
+    if (w)
+        for (int64_t c = 0; c < ncnt; ++c) {
+            i128 acc = 0;
+            for (int t = 0; t < nt; ++t) acc += tw[(int64_t)t * ncnt + c];
+            put128(&wsum[2 * c], acc);
+        }
+    free(th);
+    free(tw);
+    free(tn);
+    rows_free(&g);
+    return OR_OK;
 }
 
 /* ------------------------------------------------ 6-edge configurations -- */

@@ -64,6 +64,7 @@ __global__ void k_weights(const double *__restrict__ w, uint32_t n, uint32_t *__
             atomicOr(&flags[0], 2u);
         } else {
             lo = hi = (unsigned long long)__double_as_longlong(v);
+            if (w[i] < 0.0) atomicOr(&flags[0], 4u);
         }
     }
     // wavefront min / max first: one pair of device atomics per wavefront
@@ -681,6 +682,7 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
     if (weighted) {
         memcpy(&g.wmin, &hf.wmin, 8);
         memcpy(&g.wmax, &hf.wmax, 8);
+        g.wneg = (hf.f[0] & 4u) != 0;
         int s3 = 0;
         g.wscale = weight_scale_ok(g, 3, &s3) ? s3 : kNoScale;
     }

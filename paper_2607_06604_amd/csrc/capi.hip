@@ -178,6 +178,13 @@ bool weight_scale_ok(const Graph &g, int k, int *s, int *why) {
     return true;
 }
 
+bool wide_terms(const Graph &g, int k) {
+    const int s = weight_scale(g, k);
+    volatile double thi = g.wmax;
+    for (int j = 1; j < k; ++j) thi = thi * g.wmax;
+    return std::ilogb((double)thi) + s >= 63;
+}
+
 double sum128_to_double(const uint64_t *w, int scale) {
     const __int128 v = (__int128)(((unsigned __int128)w[1] << 64) | w[0]);
     return std::ldexp((double)v, -scale);

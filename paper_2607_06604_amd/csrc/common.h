@@ -192,6 +192,7 @@ struct Graph {
     uint32_t flags = 0;
     int wscale = 0;           // exact-sum scale of weighted triangles (kNoScale: none)
     double wmin = 0, wmax = 0;  // smallest and largest weight magnitude
+    bool wneg = false;          // some weight is negative
     Bins bins;
     uint64_t pair_hist[255] = {};
     uint64_t sum_sq_deg = 0;  // sum over points of (full degree)^2
@@ -242,6 +243,9 @@ Bins make_bins(double rmin, double rmax, int nb);
 constexpr int kNoScale = -100000;
 bool weight_scale_ok(const Graph &g, int k, int *s, int *why = nullptr);
 int weight_scale(const Graph &g, int k);
+// Whether a product of k weights may reach 2^63 at that scale (then some
+// terms need the 128-bit path).
+bool wide_terms(const Graph &g, int k);
 // An exact signed 128-bit sum (lo, hi words, two's complement) in units of
 // 2^-scale, rounded once to float64.
 double sum128_to_double(const uint64_t *w, int scale);

@@ -71,6 +71,8 @@ struct C3Args {
     uint32_t tcap;          // table entries: tmax + padding of one pass
     uint32_t anchor_lo, anchor_hi;
     double wmul;            // 2^wscale
+    int wsigned;            // some weight is negative
+    int wwide;              // some triangle term may reach 2^63
     uint64_t flush_limit;   // flush LDS counters before this many increments
     uint32_t *queue;        // kQueueWords words
     unsigned long long *hist;   // nconf
@@ -230,6 +232,7 @@ struct Walk {
     uint32_t ys, qmask;           // packed keys: bin at bit ys, key bits below
     int log2h, nb, glog;
     double wmul;
+    int wsigned, wwide;
     uint32_t anchor_lo, anchor_hi;
 };
 
@@ -273,19 +276,26 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk,
     }
     if (WEIGHTED) {
         // magnitudes in ascending order, multiplied left to right; the sign
-        // is the product of the three signs
+        // is the product of the three signs. The graph-wide flags (uniform
+        // branches) keep positive weights and narrow terms on the short path.
         const double w0 = c.hw[hub], w1 = c.mw[slot];
-        const bool ng = (w0 < 0.0) ^ (w1 < 0.0) ^ (wk < 0.0);
         double p = fabs(w0), q = fabs(w1), r = fabs(wk), t;
         if (p > q) { t = p; p = q; q = t; }
         if (q > r) { t = q; q = r; r = t; }
         if (p > q) { t = p; p = q; q = t; }
         const double x = __dmul_rn(__dmul_rn(__dmul_rn(p, q), r), c.wmul);
-        if (LDS_HIST && narrow_term(x)) {
-            const long long m = (long long)x;
-            lds_term(&c.wlo[idx], &c.whi[idx], ng ? -m : m);
+        if (LDS_HIST && !c.wwide) {
+            long long m = (long long)x;
+            if (c.wsigned) m = ((w0 < 0.0) ^ (w1 < 0.0) ^ (wk < 0.0)) ? -m : m;
+            lds_term(&c.wlo[idx], &c.whi[idx], m);
         } else {
-            add128_words(&c.wsum[2 * idx], wide_term(x, ng));
+            const bool ng = (w0 < 0.0) ^ (w1 < 0.0) ^ (wk < 0.0);
+            if (LDS_HIST && narrow_term(x)) {
+                const long long m = (long long)x;
+                lds_term(&c.wlo[idx], &c.whi[idx], ng ? -m : m);
+            } else {
+                add128_words(&c.wsum[2 * idx], wide_term(x, ng));
+            }
         }
     }
 }
@@ -487,6 +497,7 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
     c.tab = tab; c.hkey = hkey; c.hbin = hbin; c.ta = ta; c.tb = tb; c.mw = mw;
     c.mperm = mperm; c.sm = sm; c.wlo = wlo; c.whi = whi; c.wsum = a.wsum; c.w = a.w; c.perm = a.perm;
     c.mask = mask; c.hist_addr = smb + L.hist; c.log2h = a.log2h; c.nb = a.nb; c.glog = a.glog; c.wmul = a.wmul;
+    c.wsigned = a.wsigned; c.wwide = a.wwide;
     c.anchor_lo = a.anchor_lo; c.anchor_hi = a.anchor_hi; c.hw = s_hw; c.hp = s_hp;
     c.ys = (uint32_t)a.yshift;
     c.qmask = (1u << a.yshift) - 1u;
@@ -1290,6 +1301,8 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.anchor_lo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
     a.anchor_hi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;
     a.wmul = weighted ? std::ldexp(1.0, weight_scale(g, 3)) : 1.0;
+    a.wsigned = weighted && g.wneg;
+    a.wwide = weighted && wide_terms(g, 3);
     a.flush_limit = flush_limit_for(maxdeg, P.block);
     a.hist = dv;
     a.wsum = dv + nconf;

@@ -45,7 +45,7 @@ EXPORTS = ["gs_create", "gs_destroy", "gs_build_graph", "gs_graph_info", "gs_gra
            "gs_tune_3pcf", "gs_submit", "gs_poll", "gs_cancel", "gs_get_timings", "gs_strerror",
            "gs_last_error_detail", "gs_ceiling_copy", "gs_ceiling_probe", "gs_count_4pcf_parity_weighted",
            "gs_count_4pcf_full", "gs_n_configs6", "gs_config6_table", "gs_pair_sums",
-           "gs_count_4pcf_parity_noalloc"]
+           "gs_count_4pcf_parity_noalloc", "gs_count_3pcf_equilateral", "gs_count_3pcf_mu"]
 
 
 class GraphParams(ctypes.Structure):
@@ -130,6 +130,8 @@ def load(path: str = LIB_PATH):
         "gs_n_configs6": ([i32, ctypes.POINTER(ctypes.c_uint32)], i32),
         "gs_config6_table": ([i32, P], i32),
         "gs_pair_sums": ([P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
+        "gs_count_3pcf_equilateral": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
+        "gs_count_3pcf_mu": ([P, P, i32, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_ceiling_copy": ([P, u64, ctypes.POINTER(ctypes.c_double)], i32),
         "gs_ceiling_probe": ([P, i32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, i32, i32, i32,
                               ctypes.POINTER(ctypes.c_double)], i32),
@@ -304,6 +306,27 @@ class Context:
         _check(load().gs_count_4pcf_full(self._h, g.handle, _ptr(h), _ptr(ws), _ptr(sc), _ptr(nk),
                                          _anchors(anchors)), "gs_count_4pcf_full")
         return Count6(h, int(nk[0]), ws, int(sc[0]) if weighted else None)
+
+    def count_3pcf_equilateral(self, g: "Graph", anchors=None, weighted=False):
+        """Triangles with all three sides in one bin, per bin."""
+        h = np.zeros(g.nbins, dtype=np.uint64)
+        nt = np.zeros(1, dtype=np.uint64)
+        ws = np.zeros((g.nbins, 2), dtype=np.uint64) if weighted else None
+        sc = np.zeros(1, dtype=np.int32) if weighted else None
+        _check(load().gs_count_3pcf_equilateral(self._h, g.handle, _ptr(h), _ptr(ws), _ptr(sc), _ptr(nt),
+                                                _anchors(anchors)), "gs_count_3pcf_equilateral")
+        return Count3(h, int(nt[0]), ws, None, int(sc[0]) if weighted else None)
+
+    def count_3pcf_mu(self, g: "Graph", nmu: int, anchors=None, weighted=False):
+        """Triangles by sorted side bins and mu bin (counter conf * nmu + mu)."""
+        nc = n_configs(g.nbins) * max(1, int(nmu))
+        h = np.zeros(nc, dtype=np.uint64)
+        nt = np.zeros(1, dtype=np.uint64)
+        ws = np.zeros((nc, 2), dtype=np.uint64) if weighted else None
+        sc = np.zeros(1, dtype=np.int32) if weighted else None
+        _check(load().gs_count_3pcf_mu(self._h, g.handle, int(nmu), _ptr(h), _ptr(ws), _ptr(sc), _ptr(nt),
+                                       _anchors(anchors)), "gs_count_3pcf_mu")
+        return Count3(h, int(nt[0]), ws, None, int(sc[0]) if weighted else None)
 
     def pair_sums(self, g: "Graph", anchors=None, weighted=False):
         """Pairs per bin (and exact weighted pair sums)."""

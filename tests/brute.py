@@ -231,3 +231,33 @@ def cliques4_weighted(xyz, L, rmin, rmax, nb, weights):
                             continue
                         (WP if V > 0 else WN)[r] += t
     return W6, WE, WP, WN, s
+
+
+def triangles_mu(xyz, L, rmin, rmax, nb, nmu):
+    """Triangles by (lexicographic rank of sorted side bins) * nmu + mu bin,
+    mu = |n_z| / |n| for n = d(p0,p1) x d(p0,p2), p0 < p1 < p2 the vertices in
+    index order, counted as the number of k in 1..nmu-1 with
+    (n_z n_z)(nmu nmu) >= (k k)((n_x n_x + n_y n_y) + n_z n_z); collinear: 0."""
+    n = len(xyz)
+    d, _, adj, b = pair_matrix(xyz, L, rmin, rmax, nb)
+    rank = lex_configs(nb)
+    hist = np.zeros(len(rank) * nmu, dtype=np.int64)
+    for i in range(n):
+        for j in range(i + 1, n):
+            if not adj[i, j]:
+                continue
+            for k in range(j + 1, n):
+                if not (adj[i, k] and adj[j, k]):
+                    continue
+                u, v = d[i, j], d[i, k]
+                nx = u[1] * v[2] - u[2] * v[1]
+                ny = u[2] * v[0] - u[0] * v[2]
+                nz = u[0] * v[1] - u[1] * v[0]
+                s = (nx * nx + ny * ny) + nz * nz
+                m = 0
+                if s > 0.0:
+                    t = (nz * nz) * float(nmu * nmu)
+                    m = sum(1 for kk in range(1, nmu) if t >= float(kk * kk) * s)
+                c = rank[tuple(sorted((int(b[i, j]), int(b[i, k]), int(b[j, k]))))]
+                hist[c * nmu + m] += 1
+    return hist

@@ -643,3 +643,72 @@ def test_signed_weight_identities():
     assert a6.wsum_int() == b6.wsum_int()
     a4 = oracle.count_4pcf_parity(x, L, 0.0, 2.4, 4, weights=w)
     assert sum(a4.wsum_int(0)) == 4 * sum(a6.wsum_int())
+
+
+# ----------------------------------------------------------- mu binning ----
+# Hand-derived units: one triangle each, its normal n fixed by construction
+# (edge vectors u = p1 - p0, v = p2 - p0 on a dyadic grid, so every
+# separation and product below is exact).
+
+def _mu_unit(u, v, lam=0.25, L=16.0):
+    p0 = np.array([4.0, 5.0, 6.0])
+    return np.array([p0, p0 + lam * np.asarray(u, float), p0 + lam * np.asarray(v, float)])
+
+
+@pytest.mark.parametrize("u,v,nmu,want", [
+    ((1, 0, 0), (0, 1, 0), 4, 3),     # normal along z: mu = 1, the last bin
+    ((1, 0, 0), (0, 0, 1), 4, 0),     # normal along y: mu = 0
+    ((1, 0, 0), (0, 1, -1), 4, 2),    # n = (0, 1, 1): mu = 0.7071, bin [0.5, 0.75)
+    ((0, 1, 0), (3, 0, -4), 5, 3),    # n = (-4, 0, -3): mu = 0.6 exactly, on the edge of bin 3 (half open)
+    ((0, 1, 0), (-4, 0, 3), 5, 4),    # n = (3, 0, 4): mu = 0.8 exactly, the edge of bin 4
+    ((1, 1, 1), (2, 2, 2), 3, 0),     # collinear: no plane, bin 0
+])
+def test_mu_bin_hand_derived_units(u, v, nmu, want):
+    x = _mu_unit(u, v)
+    full = oracle.count_3pcf(x, 16.0, 0.0, 2.0, 4)
+    got = oracle.count_3pcf_mu(x, 16.0, 0.0, 2.0, 4, nmu)
+    assert got.n_triangles == full.n_triangles == 1
+    h = got.hist.reshape(-1, nmu)
+    c = int(np.nonzero(full.hist)[0][0])
+    assert h[c, want] == 1 and int(h.sum()) == 1
+
+
+def test_mu_marginal_and_symmetries():
+    """Summing over mu gives the 3pCF; mu is unchanged by a reflection of z
+    and by a quarter turn about the line of sight (dyadic grid: exact), and
+    it is the z axis that matters (an x-y swap keeps it, an x-z swap does not)."""
+    L = 16.0
+    x = synth.dyadic_uniform(2500, L, 77)
+    nmu = 6
+    base = oracle.count_3pcf_mu(x, L, 0.0, 1.4, 5, nmu)
+    full = oracle.count_3pcf(x, L, 0.0, 1.4, 5)
+    assert np.array_equal(base.hist.reshape(-1, nmu).sum(axis=1), full.hist)
+    zr = x.copy()
+    zr[:, 2] = np.mod(L - zr[:, 2], L)
+    assert np.array_equal(oracle.count_3pcf_mu(zr, L, 0.0, 1.4, 5, nmu).hist, base.hist)
+    rot = np.stack([np.mod(L - x[:, 1], L), x[:, 0], x[:, 2]], axis=1)
+    assert np.array_equal(oracle.count_3pcf_mu(rot, L, 0.0, 1.4, 5, nmu).hist, base.hist)
+    sw = x[:, [2, 1, 0]].copy()
+    assert not np.array_equal(oracle.count_3pcf_mu(sw, L, 0.0, 1.4, 5, nmu).hist, base.hist)
+
+
+def test_mu_isotropic_uniform_bins():
+    """Uniform points: plane normals are isotropic, so mu = |cos| of the
+    normal's angle to z is uniform on [0, 1]: equal counts per mu bin within
+    a few standard errors."""
+    x = synth.uniform(20000, 60.0, 78)
+    nmu = 5
+    h = oracle.count_3pcf_mu(x, 60.0, 0.0, 3.0, 3, nmu).hist.reshape(-1, nmu).sum(axis=0).astype(float)
+    tot = h.sum()
+    exp = tot / nmu
+    # triangles are not independent (they share points): allow 6 sigma of the
+    # multinomial spread
+    assert np.all(np.abs(h - exp) < 6 * math.sqrt(exp))
+
+
+@pytest.mark.parametrize("case", [("uniform", 150, 6.0, 1.8, 4, 5), ("clustered", 160, 8.0, 2.0, 3, 7)])
+def test_oracle_mu_matches_brute_force(case):
+    name, n, L, rmax, nb, nmu = case
+    x = synth.uniform(n, L, 91) if name == "uniform" else synth.neyman_scott(n, 20, 0.6, L, 92)
+    got = oracle.count_3pcf_mu(x, L, 0.0, rmax, nb, nmu)
+    assert np.array_equal(got.hist.astype(np.int64), brute.triangles_mu(x, L, 0.0, rmax, nb, nmu))
