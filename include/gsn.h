@@ -354,6 +354,64 @@ int gs_poll(gs_ctx *ctx, uint64_t ticket, gs_result *out);
  * result discarded if already building or counting. GS_ENOTFOUND if unknown. */
 int gs_cancel(gs_ctx *ctx, uint64_t ticket);
 
+/* ---- estimators (Sec. 2.1 signed weights, Sec. 3.3, Sec. 3.4) ----
+ * A data catalogue and a random catalogue in the same periodic box give the
+ * paper's compute_3pcf / compute_4pcf estimates. Data weights are divided by
+ * their sum (they then sum to +1) and random weights by minus theirs (-1),
+ * each sum taken left to right in index order; the combined catalogue (data,
+ * then randoms) with these signed weights is counted once, and its exact
+ * per-configuration weighted sum is the numerator (NN, NNN, NNNN: the
+ * data-minus-random combination of Landy-Szalay / Szapudi-Szalay). The
+ * denominator (RR, RRR, RRRR) is the same sum over the randoms alone with
+ * their weights divided by their sum. Each exact sum is rounded once to
+ * float64 and every estimate is the quotient (IEEE: 0/0 = NaN). Catalogues
+ * are host arrays; the calls build and free their own graphs (two per call).
+ * p: box, rmin, rmax and nbins of the graphs (flags ignored). */
+typedef struct {
+    const double *xyz;      /* host n x 3 float64 (AoS), in [0, box)        */
+    int64_t n;
+    const double *weights;  /* host n float64 (nullable: all 1); any sign  */
+} gs_catalogue;
+
+/* compute_3pcf: zeta[c] = NNN[c] / RRR[c] per sorted-side configuration.
+ * Caller-set outputs (host, C(nbins+2,3) each; all but zeta nullable):
+ * zeta, nnn and rrr (the rounded sums), nnn128 and rrr128 (2 words per
+ * configuration, exact, units 2^-nnn_scale / 2^-rrr_scale). */
+typedef struct {
+    double *zeta, *nnn, *rrr;
+    uint64_t *nnn128, *rrr128;
+    int32_t nnn_scale, rrr_scale;   /* out */
+} gs_zeta3;
+int gs_compute_3pcf(gs_ctx *ctx, const gs_catalogue *data, const gs_catalogue *randoms,
+                    const gs_graph_params *p, gs_zeta3 *out);
+
+/* compute_4pcf with its parity decomposition and connected part. Caller-set
+ * outputs, every one nullable (host float64):
+ *  per hub configuration (C(nbins+2,3)): zeta_even = NNNN_even / RRRR_even,
+ *    zeta_odd = (NNNN_pos - NNNN_neg) / RRRR_even (the difference taken
+ *    exactly), nnnn_even, nnnn_odd, rrrr_even; zeta_even_disc, the
+ *    disconnected part of the even channel, and zeta_even_conn =
+ *    zeta_even - zeta_even_disc (the odd channel is connected as it is);
+ *  per 6-edge configuration (gs_n_configs6): zeta6 = NNNN6 / RRRR6, its
+ *    disconnected part zeta6_disc = xi(b01) xi(b23) + xi(b02) xi(b13) +
+ *    xi(b03) xi(b12) (Eq. 4 on the configuration's smallest edge tuple,
+ *    added in this order) and zeta6_conn = zeta6 - zeta6_disc (Eq. 5);
+ *  xi (nbins): the internal 2pCF NN / RR on the same graph and bins.
+ * The even channel's disconnected part averages Eq. 4 over the 6-edge
+ * configurations whose hub contributions fall in the configuration: for
+ * each 6-edge configuration c (ascending) and each of its four vertices, the
+ * vertex's sorted edge bins give a hub configuration T, which gains
+ * RRRR6(c) * disc(c); the total for T is divided by RRRR_even(T).
+ * Any 6-edge or connected output needs nbins <= 12 (GS_EUNSUPPORTED). */
+typedef struct {
+    double *zeta_even, *zeta_odd, *nnnn_even, *nnnn_odd, *rrrr_even;
+    double *zeta_even_disc, *zeta_even_conn;
+    double *zeta6, *zeta6_disc, *zeta6_conn;
+    double *xi;
+} gs_zeta4;
+int gs_compute_4pcf(gs_ctx *ctx, const gs_catalogue *data, const gs_catalogue *randoms,
+                    const gs_graph_params *p, gs_zeta4 *out);
+
 /* ---- attainable ceilings (measurement only; no counting) ----
  * Rates the device sustains for the work the counting kernels are made of,
  * timed with HIP events on the context's stream, so that each kernel can be

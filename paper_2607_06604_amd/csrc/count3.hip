@@ -71,8 +71,7 @@ struct C3Args {
     uint32_t tcap;          // table entries: tmax + padding of one pass
     uint32_t anchor_lo, anchor_hi;
     double wmul;            // 2^wscale
-    int wsigned;            // some weight is negative
-    int wwide;              // some triangle term may reach 2^63
+    int wgen;               // some weight is negative or some term may reach 2^63
     uint64_t flush_limit;   // flush LDS counters before this many increments
     uint32_t *queue;        // kQueueWords words
     unsigned long long *hist;   // nconf
@@ -232,7 +231,7 @@ struct Walk {
     uint32_t ys, qmask;           // packed keys: bin at bit ys, key bits below
     int log2h, nb, glog;
     double wmul;
-    int wsigned, wwide;
+    int wgen;
     uint32_t anchor_lo, anchor_hi;
 };
 
@@ -240,7 +239,7 @@ struct Walk {
 // The x term is the LDS byte address of plane x of the ordered-triple
 // counters (kCube) or of row x of the configuration table (kLut), whose
 // entries are counter addresses (or indices); with kRank it is x itself.
-template <int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST>
+template <int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WGEN>
 __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk, uint32_t meta, uint32_t y,
                                           uint32_t z, uint32_t hub, unsigned long long &mytri) {
     // pk, wk: original index and weight of the third vertex (anchored / weighted)
@@ -274,28 +273,38 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk,
         atomicAdd(&c.hout[idx], 1ull);
         ++mytri;
     }
-    if (WEIGHTED) {
-        // magnitudes in ascending order, multiplied left to right; the sign
-        // is the product of the three signs. The graph-wide flags (uniform
-        // branches) keep positive weights and narrow terms on the short path.
+    if (WEIGHTED && !WGEN) {
+        // positive weights whose triangle terms stay below 2^63: the
+        // product of the weights in ascending order as one 64-bit integer
+        double p = c.hw[hub], q = c.mw[slot], r = wk, t;
+        if (p > q) { t = p; p = q; q = t; }
+        if (q > r) { t = q; q = r; r = t; }
+        if (p > q) { t = p; p = q; q = t; }
+        const double prod = __dmul_rn(__dmul_rn(p, q), r);
+        const unsigned long long ti = (unsigned long long)__dmul_rn(prod, c.wmul);
+        if (LDS_HIST) {
+            atomicAdd(&c.wlo[idx], ti & 0xFFFFFFFFull);
+            atomicAdd(&c.whi[idx], ti >> 32);
+        } else {
+            add128_words(&c.wsum[2 * idx], (__int128)ti);
+        }
+    }
+    if (WEIGHTED && WGEN) {
+        // any signs, any terms: magnitudes in ascending order multiplied left
+        // to right, signed by the product of the signs; terms below 2^63 into
+        // the LDS sums, wider ones into the global 128-bit sums
         const double w0 = c.hw[hub], w1 = c.mw[slot];
+        const bool ng = (w0 < 0.0) ^ (w1 < 0.0) ^ (wk < 0.0);
         double p = fabs(w0), q = fabs(w1), r = fabs(wk), t;
         if (p > q) { t = p; p = q; q = t; }
         if (q > r) { t = q; q = r; r = t; }
         if (p > q) { t = p; p = q; q = t; }
         const double x = __dmul_rn(__dmul_rn(__dmul_rn(p, q), r), c.wmul);
-        if (LDS_HIST && !c.wwide) {
-            long long m = (long long)x;
-            if (c.wsigned) m = ((w0 < 0.0) ^ (w1 < 0.0) ^ (wk < 0.0)) ? -m : m;
-            lds_term(&c.wlo[idx], &c.whi[idx], m);
+        if (LDS_HIST && narrow_term(x)) {
+            const long long m = (long long)x;
+            lds_term(&c.wlo[idx], &c.whi[idx], ng ? -m : m);
         } else {
-            const bool ng = (w0 < 0.0) ^ (w1 < 0.0) ^ (wk < 0.0);
-            if (LDS_HIST && narrow_term(x)) {
-                const long long m = (long long)x;
-                lds_term(&c.wlo[idx], &c.whi[idx], ng ? -m : m);
-            } else {
-                add128_words(&c.wsum[2 * idx], wide_term(x, ng));
-            }
+            add128_words(&c.wsum[2 * idx], wide_term(x, ng));
         }
     }
 }
@@ -306,7 +315,7 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk,
 // step. The table is padded with empty steps past nsteps, and lanes past
 // the end of a step load (and ignore) the row slack, so the loads need no
 // branch.
-template <int BLOCK, bool PACK, int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WIDE>
+template <int BLOCK, bool PACK, int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WIDE, bool WGEN>
 __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned long long &mytri) {
     constexpr int U = kUnroll3;
     const uint32_t glog = (uint32_t)c.glog;
@@ -391,25 +400,34 @@ __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned l
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (hit[u])
-                count_hit<MODE, WEIGHTED, ANCHORED, LDS_HIST>(c, pk[u], wk[u], meta[u], yy[u], zz[u],
-                                                              WIDE ? 0u : hub[u], mytri);
+                count_hit<MODE, WEIGHTED, ANCHORED, LDS_HIST, WGEN>(c, pk[u], wk[u], meta[u], yy[u], zz[u],
+                                                                    WIDE ? 0u : hub[u], mytri);
     }
 }
 
-template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WIDE>
-__device__ __forceinline__ void walk3_any(bool packed, int mode, const Walk &c, uint32_t nsteps,
-                                          unsigned long long &mytri) {
+template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WIDE, bool WGEN>
+__device__ __forceinline__ void walk3_modes(bool packed, int mode, const Walk &c, uint32_t nsteps,
+                                            unsigned long long &mytri) {
     // kCube only for unweighted counts into LDS (never selected otherwise)
     constexpr int CUBE = (!WEIGHTED && LDS_HIST) ? kCube : kLut;
     if (packed) {
-        if (mode == kCube) walk3<BLOCK, true, CUBE, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(c, nsteps, mytri);
-        else if (mode == kLut) walk3<BLOCK, true, kLut, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(c, nsteps, mytri);
-        else walk3<BLOCK, true, kRank, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(c, nsteps, mytri);
+        if (mode == kCube) walk3<BLOCK, true, CUBE, WEIGHTED, ANCHORED, LDS_HIST, WIDE, WGEN>(c, nsteps, mytri);
+        else if (mode == kLut) walk3<BLOCK, true, kLut, WEIGHTED, ANCHORED, LDS_HIST, WIDE, WGEN>(c, nsteps, mytri);
+        else walk3<BLOCK, true, kRank, WEIGHTED, ANCHORED, LDS_HIST, WIDE, WGEN>(c, nsteps, mytri);
     } else {
-        if (mode == kCube) walk3<BLOCK, false, CUBE, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(c, nsteps, mytri);
-        else if (mode == kLut) walk3<BLOCK, false, kLut, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(c, nsteps, mytri);
-        else walk3<BLOCK, false, kRank, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(c, nsteps, mytri);
+        if (mode == kCube) walk3<BLOCK, false, CUBE, WEIGHTED, ANCHORED, LDS_HIST, WIDE, WGEN>(c, nsteps, mytri);
+        else if (mode == kLut) walk3<BLOCK, false, kLut, WEIGHTED, ANCHORED, LDS_HIST, WIDE, WGEN>(c, nsteps, mytri);
+        else walk3<BLOCK, false, kRank, WEIGHTED, ANCHORED, LDS_HIST, WIDE, WGEN>(c, nsteps, mytri);
     }
+}
+
+// General weights (negative ones, or terms that may reach 2^63) take their
+// own instance of the walk, so positive narrow weights keep the short one.
+template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WIDE>
+__device__ __forceinline__ void walk3_any(bool packed, int mode, const Walk &c, uint32_t nsteps,
+                                          unsigned long long &mytri) {
+    if (WEIGHTED && c.wgen) walk3_modes<BLOCK, WEIGHTED, ANCHORED, LDS_HIST, WIDE, true>(packed, mode, c, nsteps, mytri);
+    else walk3_modes<BLOCK, WEIGHTED, ANCHORED, LDS_HIST, WIDE, false>(packed, mode, c, nsteps, mytri);
 }
 
 // Plain unbatched counts fit 64 VGPRs: eight wavefronts per SIMD.
@@ -497,7 +515,7 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
     c.tab = tab; c.hkey = hkey; c.hbin = hbin; c.ta = ta; c.tb = tb; c.mw = mw;
     c.mperm = mperm; c.sm = sm; c.wlo = wlo; c.whi = whi; c.wsum = a.wsum; c.w = a.w; c.perm = a.perm;
     c.mask = mask; c.hist_addr = smb + L.hist; c.log2h = a.log2h; c.nb = a.nb; c.glog = a.glog; c.wmul = a.wmul;
-    c.wsigned = a.wsigned; c.wwide = a.wwide;
+    c.wgen = a.wgen;
     c.anchor_lo = a.anchor_lo; c.anchor_hi = a.anchor_hi; c.hw = s_hw; c.hp = s_hp;
     c.ys = (uint32_t)a.yshift;
     c.qmask = (1u << a.yshift) - 1u;
@@ -1301,8 +1319,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.anchor_lo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
     a.anchor_hi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;
     a.wmul = weighted ? std::ldexp(1.0, weight_scale(g, 3)) : 1.0;
-    a.wsigned = weighted && g.wneg;
-    a.wwide = weighted && wide_terms(g, 3);
+    a.wgen = weighted && (g.wneg || wide_terms(g, 3));
     a.flush_limit = flush_limit_for(maxdeg, P.block);
     a.hist = dv;
     a.wsum = dv + nconf;

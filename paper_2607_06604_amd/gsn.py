@@ -45,12 +45,29 @@ EXPORTS = ["gs_create", "gs_destroy", "gs_build_graph", "gs_graph_info", "gs_gra
            "gs_tune_3pcf", "gs_submit", "gs_poll", "gs_cancel", "gs_get_timings", "gs_strerror",
            "gs_last_error_detail", "gs_ceiling_copy", "gs_ceiling_probe", "gs_count_4pcf_parity_weighted",
            "gs_count_4pcf_full", "gs_n_configs6", "gs_config6_table", "gs_pair_sums",
-           "gs_count_4pcf_parity_noalloc", "gs_count_3pcf_equilateral", "gs_count_3pcf_mu"]
+           "gs_count_4pcf_parity_noalloc", "gs_count_3pcf_equilateral", "gs_count_3pcf_mu",
+           "gs_compute_3pcf", "gs_compute_4pcf"]
 
 
 class GraphParams(ctypes.Structure):
     _fields_ = [("box", ctypes.c_double), ("rmin", ctypes.c_double), ("rmax", ctypes.c_double),
                 ("nbins", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Catalogue(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("n", ctypes.c_int64), ("weights", ctypes.c_void_p)]
+
+
+class Zeta3(ctypes.Structure):
+    _fields_ = [("zeta", ctypes.c_void_p), ("nnn", ctypes.c_void_p), ("rrr", ctypes.c_void_p),
+                ("nnn128", ctypes.c_void_p), ("rrr128", ctypes.c_void_p), ("nnn_scale", ctypes.c_int32),
+                ("rrr_scale", ctypes.c_int32)]
+
+
+class Zeta4(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("zeta_even", "zeta_odd", "nnnn_even", "nnnn_odd", "rrrr_even",
+                                              "zeta_even_disc", "zeta_even_conn", "zeta6", "zeta6_disc",
+                                              "zeta6_conn", "xi")]
 
 
 class AnchorRange(ctypes.Structure):
@@ -132,6 +149,10 @@ def load(path: str = LIB_PATH):
         "gs_pair_sums": ([P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_count_3pcf_equilateral": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_count_3pcf_mu": ([P, P, i32, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
+        "gs_compute_3pcf": ([P, ctypes.POINTER(Catalogue), ctypes.POINTER(Catalogue), ctypes.POINTER(GraphParams),
+                             ctypes.POINTER(Zeta3)], i32),
+        "gs_compute_4pcf": ([P, ctypes.POINTER(Catalogue), ctypes.POINTER(Catalogue), ctypes.POINTER(GraphParams),
+                             ctypes.POINTER(Zeta4)], i32),
         "gs_ceiling_copy": ([P, u64, ctypes.POINTER(ctypes.c_double)], i32),
         "gs_ceiling_probe": ([P, i32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, i32, i32, i32,
                               ctypes.POINTER(ctypes.c_double)], i32),
@@ -511,3 +532,111 @@ class Graph:
             self.free()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- estimators
+
+def _catalogue(xyz, w):
+    x = _host(xyz, np.float64)
+    if x.ndim != 2 or x.shape[1] != 3:
+        raise ValueError("positions must be (N,3)")
+    wa = None if w is None else _host(w, np.float64)
+    if wa is not None and wa.shape != (x.shape[0],):
+        raise ValueError("weights must be (N,)")
+    c = Catalogue(ctypes.c_void_p(x.ctypes.data), x.shape[0], None if wa is None else ctypes.c_void_p(wa.ctypes.data))
+    return c, (x, wa)
+
+
+def bin_centres(rmin, rmax, nbins):
+    d = (rmax - rmin) / nbins
+    return np.array([rmin + (k + 0.5) * d for k in range(nbins)])
+
+
+@dataclass
+class Result3pcf:
+    """compute_3pcf result: zeta, NNN, RRR per sorted-side configuration,
+    with the configurations' bin centres r1 <= r2 <= r3."""
+    zeta: np.ndarray
+    NNN: np.ndarray
+    RRR: np.ndarray
+    r1: np.ndarray
+    r2: np.ndarray
+    r3: np.ndarray
+    nnn_exact: list
+    nnn_scale: int
+
+
+def _config_centres(rmin, rmax, nbins):
+    c = bin_centres(rmin, rmax, nbins)
+    t = [(a, b, d) for a in range(nbins) for b in range(a, nbins) for d in range(b, nbins)]
+    return tuple(np.array([c[x[k]] for x in t]) for k in range(3))
+
+
+def compute_3pcf(pos_data, w_data, pos_rand, w_rand, rmin, rmax, nbins, box, ctx=None) -> Result3pcf:
+    """The paper's compute_3pcf (Sec. 3.4) on a periodic box: zeta =
+    NNN / RRR with signed, normalised data-minus-random weights."""
+    own = ctx is None
+    c = Context(0) if own else ctx
+    try:
+        d, keep_d = _catalogue(pos_data, w_data)
+        r, keep_r = _catalogue(pos_rand, w_rand)
+        nc = n_configs(nbins)
+        zeta, nnn, rrr = (np.zeros(nc) for _ in range(3))
+        n128 = np.zeros((nc, 2), dtype=np.uint64)
+        out = Zeta3(zeta.ctypes.data, nnn.ctypes.data, rrr.ctypes.data, n128.ctypes.data, None, 0, 0)
+        p = GraphParams(float(box), float(rmin), float(rmax), int(nbins), 0)
+        _check(load().gs_compute_3pcf(c.handle, ctypes.byref(d), ctypes.byref(r), ctypes.byref(p), ctypes.byref(out)),
+               "gs_compute_3pcf")
+        r1, r2, r3 = _config_centres(rmin, rmax, nbins)
+        return Result3pcf(zeta, nnn, rrr, r1, r2, r3, _signed128(n128), int(out.nnn_scale))
+    finally:
+        if own:
+            c.close()
+
+
+@dataclass
+class Result4pcf:
+    """compute_4pcf result. Parity channels per hub configuration (sorted
+    spoke bins): zeta_even, zeta_odd, their numerators and the even random
+    sum, the even channel's disconnected part and connected remainder;
+    6-edge configurations: zeta6, its disconnected part (Eq. 4) and
+    connected remainder (Eq. 5); xi: the internal 2pCF."""
+    zeta_even: np.ndarray
+    zeta_odd: np.ndarray
+    nnnn_even: np.ndarray
+    nnnn_odd: np.ndarray
+    rrrr_even: np.ndarray
+    zeta_even_disc: np.ndarray | None
+    zeta_even_conn: np.ndarray | None
+    zeta6: np.ndarray | None
+    zeta6_disc: np.ndarray | None
+    zeta6_conn: np.ndarray | None
+    xi: np.ndarray | None
+
+
+def compute_4pcf(pos_data, w_data, pos_rand, w_rand, rmin, rmax, nbins, box, parity=True, connected=True,
+                 ctx=None) -> Result4pcf:
+    """The paper's compute_4pcf (Sec. 3.4) with its parity split (Sec. 3.2)
+    and connected part (Sec. 3.3) on a periodic box."""
+    own = ctx is None
+    c = Context(0) if own else ctx
+    try:
+        d, keep_d = _catalogue(pos_data, w_data)
+        r, keep_r = _catalogue(pos_rand, w_rand)
+        nc = n_configs(nbins)
+        ev, od, ne, no, re_ = (np.zeros(nc) for _ in range(5))
+        arrs = dict(zeta_even=ev, zeta_odd=od, nnnn_even=ne, nnnn_odd=no, rrrr_even=re_)
+        if connected:
+            n6 = n_configs6(nbins)
+            arrs.update(zeta_even_disc=np.zeros(nc), zeta_even_conn=np.zeros(nc), zeta6=np.zeros(n6),
+                        zeta6_disc=np.zeros(n6), zeta6_conn=np.zeros(n6), xi=np.zeros(nbins))
+        out = Zeta4(**{k: v.ctypes.data for k, v in arrs.items()})
+        p = GraphParams(float(box), float(rmin), float(rmax), int(nbins), 0)
+        _check(load().gs_compute_4pcf(c.handle, ctypes.byref(d), ctypes.byref(r), ctypes.byref(p), ctypes.byref(out)),
+               "gs_compute_4pcf")
+        g = arrs.get
+        return Result4pcf(ev, od, ne, no, re_, g("zeta_even_disc"), g("zeta_even_conn"), g("zeta6"),
+                          g("zeta6_disc"), g("zeta6_conn"), g("xi"))
+    finally:
+        if own:
+            c.close()
