@@ -21,7 +21,7 @@
  * Definitions shared by all counts (float64, round to nearest, no fused
  * multiply-add, in this order):
  *  separation a->b, per axis: d = x_b - x_a; d -= L if d > L/2; d += L if
- *    d < -L/2 (periodic box, minimum image);
+ *    d < -L/2 (periodic box, minimum image; with GS_NONPERIODIC d = x_b - x_a);
  *  squared length q = (dx*dx + dy*dy) + dz*dz;
  *  bins: D = (rmax - rmin)/nbins, e_0 = rmin, e_k = rmin + k*D, e_nbins =
  *    rmax, t_k = e_k*e_k; a pair is an edge iff t_0 <= q < t_nbins; its bin
@@ -55,6 +55,10 @@ extern "C" {
 #define GS_WEIGHTED 1u         /* weights given: keep them for weighted 3pCF    */
 #define GS_KEEP_COORDS 2u      /* keep label-ordered coordinates (4pCF parity)  */
 #define GS_INPUT_ON_DEVICE 4u  /* xyz / weights are device pointers             */
+#define GS_NONPERIODIC 8u      /* survey geometry (Sec. 5): no periodic wrap;   */
+                               /* separations are plain differences x_b - x_a,  */
+                               /* box is the extent of the cube holding the     */
+                               /* points, and rmax may take any value > rmin     */
 
 typedef struct gs_ctx gs_ctx;      /* device, stream, budget, tuning, scratch  */
 typedef struct gs_graph gs_graph;  /* forward CSR + labels (+ coords, weights) */
@@ -62,9 +66,10 @@ typedef struct gs_graph gs_graph;  /* forward CSR + labels (+ coords, weights) *
 typedef struct {
     double box;     /* periodic box side L > 0; points in [0, L)^3              */
     double rmin;    /* 0 <= rmin < rmax                                          */
-    double rmax;    /* rmax < L/2                                                 */
+    double rmax;    /* rmax < L/2 (periodic; any finite value with GS_NONPERIODIC) */
     int32_t nbins;  /* 1 .. 255                                                    */
-    uint32_t flags; /* GS_WEIGHTED | GS_KEEP_COORDS | GS_INPUT_ON_DEVICE          */
+    uint32_t flags; /* GS_WEIGHTED | GS_KEEP_COORDS | GS_INPUT_ON_DEVICE |
+                       GS_NONPERIODIC                                              */
 } gs_graph_params;
 
 /* Count only tuples whose smallest ORIGINAL point index lies in [lo, hi).
@@ -366,7 +371,8 @@ int gs_cancel(gs_ctx *ctx, uint64_t ticket);
  * their weights divided by their sum. Each exact sum is rounded once to
  * float64 and every estimate is the quotient (IEEE: 0/0 = NaN). Catalogues
  * are host arrays; the calls build and free their own graphs (two per call).
- * p: box, rmin, rmax and nbins of the graphs (flags ignored). */
+ * p: box, rmin, rmax and nbins of the graphs; of the flags only
+ * GS_NONPERIODIC is used. */
 typedef struct {
     const double *xyz;      /* host n x 3 float64 (AoS), in [0, box)        */
     int64_t n;

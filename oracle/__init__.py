@@ -76,6 +76,12 @@ class OracleError(RuntimeError):
         self.code = code
 
 
+def _box(box, periodic):
+    """The box argument of the C oracle: negative for survey geometry (no
+    periodic wrap, the points in the cube of side box)."""
+    return float(box) if periodic else -float(box)
+
+
 def _p(a):
     return None if a is None else ctypes.c_void_p(a.ctypes.data)
 
@@ -103,18 +109,18 @@ def edge_bin(q: float, box: float, rmin: float, rmax: float, nbins: int) -> int:
     return r
 
 
-def separation(a, b, box: float):
+def separation(a, b, box: float, periodic=True):
     a = np.ascontiguousarray(a, dtype=np.float64)
     b = np.ascontiguousarray(b, dtype=np.float64)
     r = np.empty(3)
     q = np.empty(1)
-    rc = _load().oracle_separation(_p(a), _p(b), box, _p(r), _p(q))
+    rc = _load().oracle_separation(_p(a), _p(b), _box(box, periodic), _p(r), _p(q))
     if rc:
         raise OracleError(rc)
     return r, float(q[0])
 
 
-def graph(xyz, box, rmin, rmax, nbins):
+def graph(xyz, box, rmin, rmax, nbins, periodic=True):
     """Full symmetric rows (row_ptr int64[n+1], col int32[E], bin uint8[E]),
     each row sorted by original index."""
     x = _xyz(xyz)
@@ -123,13 +129,13 @@ def graph(xyz, box, rmin, rmax, nbins):
     ne = np.zeros(1, dtype=np.int64)
     rp = np.zeros(n + 1, dtype=np.int64)
     dummy = np.zeros(1, dtype=np.int32)
-    rc = lib.oracle_graph(_p(x), n, box, rmin, rmax, nbins, _p(rp), _p(dummy), _p(dummy), 0, _p(ne))
+    rc = lib.oracle_graph(_p(x), n, _box(box, periodic), rmin, rmax, nbins, _p(rp), _p(dummy), _p(dummy), 0, _p(ne))
     if rc:
         raise OracleError(rc)
     E = int(ne[0])
     col = np.zeros(max(E, 1), dtype=np.int32)
     b = np.zeros(max(E, 1), dtype=np.uint8)
-    rc = lib.oracle_graph(_p(x), n, box, rmin, rmax, nbins, _p(rp), _p(col), _p(b), E, _p(ne))
+    rc = lib.oracle_graph(_p(x), n, _box(box, periodic), rmin, rmax, nbins, _p(rp), _p(col), _p(b), E, _p(ne))
     if rc:
         raise OracleError(rc)
     return rp, col[:E], b[:E]
@@ -160,7 +166,7 @@ class Result2:
         return signed128(self.wsum)
 
 
-def pair_sums(xyz, box, rmin, rmax, nbins, weights=None, anchors=None) -> Result2:
+def pair_sums(xyz, box, rmin, rmax, nbins, weights=None, anchors=None, periodic=True) -> Result2:
     """Edges per bin and, with weights, the exact per-bin sums of w_i*w_j."""
     x = _xyz(xyz)
     n = x.shape[0]
@@ -169,7 +175,7 @@ def pair_sums(xyz, box, rmin, rmax, nbins, weights=None, anchors=None) -> Result
     pairs = np.zeros(max(nbins, 1), dtype=np.uint64)
     wsum = np.zeros((max(nbins, 1), 2), dtype=np.uint64) if w is not None else None
     ws = np.zeros(1, dtype=np.int32)
-    rc = _load().oracle_pair_sums(_p(x), n, _p(w), box, rmin, rmax, nbins, lo, hi, _p(pairs), _p(wsum), _p(ws))
+    rc = _load().oracle_pair_sums(_p(x), n, _p(w), _box(box, periodic), rmin, rmax, nbins, lo, hi, _p(pairs), _p(wsum), _p(ws))
     if rc:
         raise OracleError(rc)
     return Result2(pairs, wsum, int(ws[0]) if w is not None else None)
@@ -192,7 +198,7 @@ class Result3:
         return rounded(self.wsum_int(), self.wscale)
 
 
-def count_3pcf(xyz, box, rmin, rmax, nbins, weights=None, anchors=None, threads=0) -> Result3:
+def count_3pcf(xyz, box, rmin, rmax, nbins, weights=None, anchors=None, threads=0, periodic=True) -> Result3:
     x = _xyz(xyz)
     n = x.shape[0]
     w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
@@ -205,7 +211,7 @@ def count_3pcf(xyz, box, rmin, rmax, nbins, weights=None, anchors=None, threads=
     ws = np.zeros(1, dtype=np.int32)
     nt = np.zeros(1, dtype=np.uint64)
     used = np.zeros(1, dtype=np.int32)
-    rc = _load().oracle_count_3pcf(_p(x), n, _p(w), box, rmin, rmax, nbins, lo, hi, threads,
+    rc = _load().oracle_count_3pcf(_p(x), n, _p(w), _box(box, periodic), rmin, rmax, nbins, lo, hi, threads,
                                    _p(hist), _p(wsum), _p(ws), _p(nt), _p(used))
     if rc:
         raise OracleError(rc)
@@ -231,7 +237,7 @@ class Result4:
         return signed128(self.wsum[channel])
 
 
-def count_4pcf_parity(xyz, box, rmin, rmax, nbins, anchors=None, threads=0, weights=None) -> Result4:
+def count_4pcf_parity(xyz, box, rmin, rmax, nbins, anchors=None, threads=0, weights=None, periodic=True) -> Result4:
     x = _xyz(xyz)
     n = x.shape[0]
     w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
@@ -244,14 +250,14 @@ def count_4pcf_parity(xyz, box, rmin, rmax, nbins, anchors=None, threads=0, weig
     sc = np.zeros(1, dtype=np.int32)
     nk = np.zeros(1, dtype=np.uint64)
     used = np.zeros(1, dtype=np.int32)
-    rc = _load().oracle_count_4pcf_parity(_p(x), n, _p(w), box, rmin, rmax, nbins, lo, hi, threads,
+    rc = _load().oracle_count_4pcf_parity(_p(x), n, _p(w), _box(box, periodic), rmin, rmax, nbins, lo, hi, threads,
                                           _p(e), _p(p), _p(m), _p(ws), _p(sc), _p(nk), _p(used))
     if rc:
         raise OracleError(rc)
     return Result4(e, p, m, int(nk[0]), int(used[0]), ws, int(sc[0]) if w is not None else None)
 
 
-def count_3pcf_mu(xyz, box, rmin, rmax, nbins, nmu, weights=None, anchors=None, threads=0) -> Result3:
+def count_3pcf_mu(xyz, box, rmin, rmax, nbins, nmu, weights=None, anchors=None, threads=0, periodic=True) -> Result3:
     """Triangles binned by sorted side bins and by the mu bin of their plane's
     normal (counter conf * nmu + mu bin)."""
     x = _xyz(xyz)
@@ -264,7 +270,7 @@ def count_3pcf_mu(xyz, box, rmin, rmax, nbins, nmu, weights=None, anchors=None, 
     ws = np.zeros(1, dtype=np.int32)
     nt = np.zeros(1, dtype=np.uint64)
     used = np.zeros(1, dtype=np.int32)
-    rc = _load().oracle_count_3pcf_mu(_p(x), n, _p(w), box, rmin, rmax, nbins, nmu, lo, hi, threads, _p(hist),
+    rc = _load().oracle_count_3pcf_mu(_p(x), n, _p(w), _box(box, periodic), rmin, rmax, nbins, nmu, lo, hi, threads, _p(hist),
                                       _p(wsum), _p(ws), _p(nt), _p(used))
     if rc:
         raise OracleError(rc)
@@ -302,7 +308,7 @@ class Result6:
         return signed128(self.wsum)
 
 
-def count_4pcf_full(xyz, box, rmin, rmax, nbins, anchors=None, threads=0, weights=None) -> Result6:
+def count_4pcf_full(xyz, box, rmin, rmax, nbins, anchors=None, threads=0, weights=None, periodic=True) -> Result6:
     """Every 4-clique once, binned by the configuration of its six edge bins
     (with weights: the exact sums of ((w1*w2)*w3)*w4, ascending values)."""
     x = _xyz(xyz)
@@ -315,7 +321,7 @@ def count_4pcf_full(xyz, box, rmin, rmax, nbins, anchors=None, threads=0, weight
     sc = np.zeros(1, dtype=np.int32)
     nk = np.zeros(1, dtype=np.uint64)
     used = np.zeros(1, dtype=np.int32)
-    rc = _load().oracle_count_4pcf_full(_p(x), n, _p(w), box, rmin, rmax, nbins, lo, hi, threads, _p(h),
+    rc = _load().oracle_count_4pcf_full(_p(x), n, _p(w), _box(box, periodic), rmin, rmax, nbins, lo, hi, threads, _p(h),
                                         _p(ws), _p(sc), _p(nk), _p(used))
     if rc:
         raise OracleError(rc)

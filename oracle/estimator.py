@@ -59,10 +59,10 @@ class Zeta3:
     rrr: np.ndarray
 
 
-def compute_3pcf(xd, wd, xr, wr, box, rmin, rmax, nbins) -> Zeta3:
+def compute_3pcf(xd, wd, xr, wr, box, rmin, rmax, nbins, periodic=True) -> Zeta3:
     x, w, w_r = catalogues(xd, wd, xr, wr)
-    n = oracle.count_3pcf(x, box, rmin, rmax, nbins, weights=w)
-    r = oracle.count_3pcf(xr, box, rmin, rmax, nbins, weights=w_r)
+    n = oracle.count_3pcf(x, box, rmin, rmax, nbins, weights=w, periodic=periodic)
+    r = oracle.count_3pcf(xr, box, rmin, rmax, nbins, weights=w_r, periodic=periodic)
     N = oracle.rounded(n.wsum_int(), n.wscale)
     R = oracle.rounded(r.wsum_int(), r.wscale)
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -84,10 +84,10 @@ class Zeta4:
     zeta_even_conn: np.ndarray | None = None
 
 
-def compute_4pcf(xd, wd, xr, wr, box, rmin, rmax, nbins, connected=True) -> Zeta4:
+def compute_4pcf(xd, wd, xr, wr, box, rmin, rmax, nbins, connected=True, periodic=True) -> Zeta4:
     x, w, w_r = catalogues(xd, wd, xr, wr)
-    pn = oracle.count_4pcf_parity(x, box, rmin, rmax, nbins, weights=w)
-    pr = oracle.count_4pcf_parity(xr, box, rmin, rmax, nbins, weights=w_r)
+    pn = oracle.count_4pcf_parity(x, box, rmin, rmax, nbins, weights=w, periodic=periodic)
+    pr = oracle.count_4pcf_parity(xr, box, rmin, rmax, nbins, weights=w_r, periodic=periodic)
     evN = oracle.rounded(pn.wsum_int(0), pn.wscale)
     evR = oracle.rounded(pr.wsum_int(0), pr.wscale)
     odd = [a - b for a, b in zip(pn.wsum_int(1), pn.wsum_int(2))]
@@ -97,14 +97,14 @@ def compute_4pcf(xd, wd, xr, wr, box, rmin, rmax, nbins, connected=True) -> Zeta
     if not connected:
         return out
     # internal 2pCF on the same graphs and bins
-    a = oracle.pair_sums(x, box, rmin, rmax, nbins, weights=w)
-    b = oracle.pair_sums(xr, box, rmin, rmax, nbins, weights=w_r)
+    a = oracle.pair_sums(x, box, rmin, rmax, nbins, weights=w, periodic=periodic)
+    b = oracle.pair_sums(xr, box, rmin, rmax, nbins, weights=w_r, periodic=periodic)
     NN = oracle.rounded(a.wsum_int(), a.wscale)
     RR = oracle.rounded(b.wsum_int(), b.wscale)
     with np.errstate(divide="ignore", invalid="ignore"):
         xi = NN / RR
-    fn = oracle.count_4pcf_full(x, box, rmin, rmax, nbins, weights=w)
-    fr = oracle.count_4pcf_full(xr, box, rmin, rmax, nbins, weights=w_r)
+    fn = oracle.count_4pcf_full(x, box, rmin, rmax, nbins, weights=w, periodic=periodic)
+    fr = oracle.count_4pcf_full(xr, box, rmin, rmax, nbins, weights=w_r, periodic=periodic)
     N6 = oracle.rounded(fn.wsum_int(), fn.wscale)
     R6 = oracle.rounded(fr.wsum_int(), fr.wscale)
     n6 = oracle.n_configs6(nbins)

@@ -18,7 +18,7 @@
  * D1 separation a->b: per axis d = x_b - x_a; if d > L/2 then d -= L, else
  *    if d < -L/2 then d += L (periodic box of the paper's test catalogue,
  *    Sec. 4.1; the minimum-image rule is our reading). sep(b,a) = -sep(a,b)
- *    exactly.
+ *    exactly. Survey geometry (Sec. 5; a negative box argument): d = x_b - x_a.
  * D2 squared length q = (dx*dx + dy*dy) + dz*dz.
  * D3 bins: equal-width radial bins from rmin to rmax (Sec. 4.1). With
  *    D = (rmax - rmin)/nb, e_0 = rmin, e_k = rmin + k*D (0<k<nb), e_nb = rmax,
@@ -74,14 +74,20 @@ typedef __int128 i128;
 
 typedef struct {
     double L, half, rmin, rmax;
+    int periodic;  /* 0: survey geometry (a negative box argument), no wrap */
     int nb;
     double t[256]; /* squared bin edges t_0 .. t_nb */
 } params_t;
 
+/* box > 0: periodic cube of side box; box < 0: survey geometry (Sec. 5), the
+ * points in the cube of side -box, separations without any wrap. */
 static int make_params(params_t *p, double box, double rmin, double rmax, int nb) {
+    p->periodic = box > 0;
+    box = fabs(box);
     if (!(box > 0) || !isfinite(box)) return OR_EINVAL;
     if (nb < 1 || nb > 255) return OR_EINVAL;
-    if (!(rmin >= 0) || !(rmin < rmax) || !(rmax < 0.5 * box)) return OR_EINVAL;
+    if (!(rmin >= 0) || !(rmin < rmax) || !isfinite(rmax)) return OR_EINVAL;
+    if (p->periodic && !(rmax < 0.5 * box)) return OR_EINVAL;
     p->L = box;
     p->half = 0.5 * box;
     p->rmin = rmin;
@@ -96,6 +102,7 @@ static int make_params(params_t *p, double box, double rmin, double rmax, int nb
 }
 
 static int check_points(const double *xyz, int64_t n, double box) {
+    box = fabs(box);
     if (n < 0) return OR_EINVAL;
     if (n > 0 && !xyz) return OR_EINVAL;
     for (int64_t i = 0; i < 3 * n; ++i)
@@ -107,8 +114,10 @@ static int check_points(const double *xyz, int64_t n, double box) {
 static void separation(const params_t *p, const double *a, const double *b, double r[3]) {
     for (int c = 0; c < 3; ++c) {
         double d = b[c] - a[c];
-        if (d > p->half) d = d - p->L;
-        else if (d < -p->half) d = d + p->L;
+        if (p->periodic) {
+            if (d > p->half) d = d - p->L;
+            else if (d < -p->half) d = d + p->L;
+        }
         r[c] = d;
     }
 }
@@ -174,7 +183,8 @@ static int build_rows(const params_t *p, const double *xyz, int64_t n, int nthre
     g->n = n;
     int nc = (int)floor(p->L / (p->rmax * (1.0 + 1e-9)));
     if (nc > 128) nc = 128;
-    if (nc < 3) nc = 1;
+    if (p->periodic && nc < 3) nc = 1;   /* fewer would list a cell twice */
+    if (nc < 1) nc = 1;
     int64_t ncell = (int64_t)nc * nc * nc;
     int64_t *cstart = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
     int64_t *cfill = (int64_t *)calloc((size_t)ncell, sizeof(int64_t));
@@ -215,7 +225,14 @@ static int build_rows(const params_t *p, const double *xyz, int64_t n, int nthre
                 for (int dx = -1; dx <= 1; ++dx)
                     for (int dy = -1; dy <= 1; ++dy)
                         for (int dz = -1; dz <= 1; ++dz) {
-                            int x = (cx + dx + nc) % nc, y = (cy + dy + nc) % nc, z = (cz + dz + nc) % nc;
+                            int x = cx + dx, y = cy + dy, z = cz + dz;
+                            if (p->periodic) {
+                                x = (x + nc) % nc;
+                                y = (y + nc) % nc;
+                                z = (z + nc) % nc;
+                            } else if (x < 0 || y < 0 || z < 0 || x >= nc || y >= nc || z >= nc) {
+                                continue;
+                            }
                             cells[ncells++] = ((int64_t)x * nc + y) * nc + z;
                         }
             }
@@ -327,7 +344,7 @@ int oracle_edge_bin(double q, double box, double rmin, double rmax, int nbins) {
 /* D1+D2 for two points (exposed for antisymmetry tests) */
 int oracle_separation(const double *a, const double *b, double box, double *r_out, double *q_out) {
     params_t p;
-    if (make_params(&p, box, 0.0, 0.25 * box, 1) != OR_OK) return OR_EINVAL;
+    if (make_params(&p, box, 0.0, 0.25 * fabs(box), 1) != OR_OK) return OR_EINVAL;
     separation(&p, a, b, r_out);
     *q_out = sqlen(r_out);
     return OR_OK;

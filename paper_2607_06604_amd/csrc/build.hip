@@ -129,6 +129,7 @@ struct EdgeArgs {
     uint32_t l0, l1;    // labels handled by this launch
     uint64_t obase;     // fill pass: rp[l] - obase indexes col / bin
     int nc, nb;
+    int periodic;       // 0: neighbour cells do not wrap and no separation does
     double L, half;
     // count pass
     uint32_t *deg;
@@ -253,8 +254,37 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
         // a cell off the boundary layer with at least 5 cells per axis: its
         // candidates lie in truly adjacent cells, within 2 L / nc <= 0.4 L of
         // the label, so no minimum-image correction can apply
-        s_wf = nc >= 5 && cx >= 1 && cx <= nc - 2 && cy >= 1 && cy <= nc - 2 && cz >= 1 && cz <= nc - 2;
-        if (nc >= 3) {
+        s_wf = !a.periodic ||
+               (nc >= 5 && cx >= 1 && cx <= nc - 2 && cy >= 1 && cy <= nc - 2 && cz >= 1 && cz <= nc - 2);
+        if (!a.periodic) {
+            // survey geometry: the in-range neighbours only, ascending
+            auto range3 = [nc](int v, int *o, int &k) {
+                k = 0;
+                for (int w = v - 1; w <= v + 1; ++w)
+                    if (w >= 0 && w < nc) o[k++] = w;
+            };
+            int kx, ky, kz;
+            range3(cx, ax, kx);
+            range3(cy, ay, ky);
+            range3(cz, az, kz);
+            int nr = 0;
+            uint32_t run = 0;
+            for (int u = 0; u < kx; ++u)
+                for (int v = 0; v < ky; ++v)
+                    for (int w = 0; w < kz; ++w) {
+                        const uint32_t id = ((uint32_t)ax[u] * nc + ay[v]) * nc + az[w];
+                        if (id <= c) continue;
+                        const uint64_t b0 = a.cstart[id], b1 = a.cstart[id + 1];
+                        if (b1 == b0) continue;
+                        rs[nr] = b0;
+                        rq[nr] = run;
+                        run += (uint32_t)(b1 - b0);
+                        ++nr;
+                    }
+            rq[nr] = run;
+            s_nr = nr;
+            na = -1;
+        } else if (nc >= 3) {
             na = 3;
             auto sorted3 = [nc](int v, int *o) {
                 int lo = v == 0 ? nc - 1 : v - 1, hi = v == nc - 1 ? 0 : v + 1;
@@ -283,8 +313,10 @@ __global__ __launch_bounds__(kBlock) void k_edges(EdgeArgs a) {
                     run += (uint32_t)(b1 - b0);
                     ++nr;
                 }
-        rq[nr] = run;
-        s_nr = nr;
+        if (na > 0) {
+            rq[nr] = run;
+            s_nr = nr;
+        }
     }
     __syncthreads();
     const int nr = s_nr;
@@ -554,8 +586,9 @@ EdgeArgs edge_args(const Graph &g, const BuildJob &job) {
     ea.obase = 0;
     ea.nc = job.nc;
     ea.nb = g.nbins;
-    ea.L = g.box;
-    ea.half = 0.5 * g.box;
+    ea.periodic = g.periodic ? 1 : 0;
+    ea.L = g.periodic ? g.box : HUGE_VAL;
+    ea.half = g.periodic ? 0.5 * g.box : HUGE_VAL;
     return ea;
 }
 
@@ -600,7 +633,10 @@ void build_begin(Ctx &ctx, Graph &g, const double *xyz, const double *w, BuildJo
     double ncd = std::floor(g.box / (g.rmax * (1.0 + 1e-9)));
     double cap = std::max(3.0, std::ceil(2.0 * std::cbrt((double)n)));
     ncd = std::min(ncd, std::min(cap, 256.0));
-    int nc = ncd < 3 ? 1 : (int)ncd;
+    // periodic: fewer than 3 cells per axis would make a cell its own
+    // neighbour twice, so such boxes take one cell; survey geometry has no
+    // wrap and takes any count
+    int nc = g.periodic ? (ncd < 3 ? 1 : (int)ncd) : std::max(1, (int)ncd);
     uint64_t ncell = (uint64_t)nc * nc * nc;
 
     const std::shared_ptr<DevPool> &pool = ctx.pool;

@@ -290,8 +290,12 @@ int gs_build_graph(gs_ctx *ctx, const double *xyz, int64_t n, const double *weig
         if (n >= 0xFFFFFFFFll) fail(GS_EOVERFLOW, "n must be below 2^32 - 1");
         if (!(p->box > 0) || !std::isfinite(p->box)) fail(GS_EINVAL, "box must be finite and > 0");
         if (p->nbins < 1 || p->nbins > 255) fail(GS_EINVAL, "nbins must be in 1..255");
-        if (!(p->rmin >= 0) || !(p->rmin < p->rmax) || !(p->rmax < 0.5 * p->box))
-            fail(GS_EINVAL, "need 0 <= rmin < rmax < box/2");
+        const bool periodic = !(p->flags & GS_NONPERIODIC);
+        if (!(p->rmin >= 0) || !(p->rmin < p->rmax) || !std::isfinite(p->rmax) ||
+            (periodic && !(p->rmax < 0.5 * p->box)))
+            fail(GS_EINVAL, periodic ? "need 0 <= rmin < rmax < box/2" : "need 0 <= rmin < rmax, finite");
+        if (p->flags & ~(GS_WEIGHTED | GS_KEEP_COORDS | GS_INPUT_ON_DEVICE | GS_NONPERIODIC))
+            fail(GS_EINVAL, "unknown flags");
         bool weighted = (p->flags & GS_WEIGHTED) != 0;
         if (weighted != (weights != nullptr)) fail(GS_EINVAL, "weights given iff GS_WEIGHTED");
         ctx->use();
@@ -303,6 +307,7 @@ int gs_build_graph(gs_ctx *ctx, const double *xyz, int64_t n, const double *weig
         g->rmax = p->rmax;
         g->nbins = p->nbins;
         g->flags = p->flags;
+        g->periodic = periodic;
         g->bins = make_bins(p->rmin, p->rmax, p->nbins);
         build_run(*ctx, *g, xyz, weights);
     });

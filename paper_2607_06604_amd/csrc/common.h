@@ -188,6 +188,7 @@ struct Graph {
     uint64_t n_edges = 0;     // forward entries
     uint32_t max_deg = 0;     // largest forward degree
     double box = 0, rmin = 0, rmax = 0;
+    bool periodic = true;     // false: GS_NONPERIODIC (plain differences, no wrap)
     int nbins = 0;
     uint32_t flags = 0;
     int wscale = 0;           // exact-sum scale of weighted triangles (kNoScale: none)

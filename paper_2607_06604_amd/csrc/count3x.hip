@@ -364,8 +364,8 @@ void count3x_run(Ctx &ctx, const Graph &g, int kind, int nmu, uint64_t *hist, ui
     const int sc = weighted ? weight_scale(g, 3) : 0;
     a.w = weighted ? g.weights.as<double>() : nullptr;
     a.wmul = std::ldexp(1.0, sc);
-    a.L = g.box;
-    a.half = 0.5 * g.box;
+    a.L = g.periodic ? g.box : HUGE_VAL;
+    a.half = g.periodic ? 0.5 * g.box : HUGE_VAL;
     a.n = (uint32_t)g.n;
     a.maxdeg = maxdeg;
     a.nb = nb;

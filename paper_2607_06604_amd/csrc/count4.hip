@@ -941,8 +941,10 @@ void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_ra
     a.log2h = log2h;
     a.W = W;
     a.maxdeg = maxdeg;
-    a.L = g.box;
-    a.half = 0.5 * g.box;
+    // survey geometry: no wrap anywhere (the minimum image with an infinite
+    // box is the plain difference)
+    a.L = g.periodic ? g.box : HUGE_VAL;
+    a.half = g.periodic ? 0.5 * g.box : HUGE_VAL;
     for (int k = 0; k < 16; ++k) a.tk[k] = g.bins.t[std::min(k + 1, nb)];
     // Hubs at least rmax (with margin) from every face: their clique
     // vertices lie within rmax of the hub, hence unwrapped, and any two of
@@ -959,6 +961,13 @@ void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_ra
         const bool shared = 4.0 * m < g.box;
         a.eb_in = shared ? 1e-13 * m * m * m : HUGE_VAL;
         a.eb_wrap = shared ? 1e-13 * m * m * m + 1e-14 * g.box * m * m : HUGE_VAL;
+        if (!g.periodic) {
+            // every separation is a plain difference of the same points:
+            // every hub is interior and the shared decision always holds
+            a.in_lo = -HUGE_VAL;
+            a.in_hi = HUGE_VAL;
+            a.eb_in = 1e-13 * m * m * m;
+        }
     }
     a.anchor_lo = anchored ? (uint32_t)std::min<uint64_t>(anchors->lo, 0xFFFFFFFFull) : 0;
     a.anchor_hi = anchored ? (uint32_t)std::min<uint64_t>(anchors->hi, 0xFFFFFFFFull) : 0;

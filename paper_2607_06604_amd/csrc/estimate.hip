@@ -65,7 +65,7 @@ void ok(int rc, const char *where) {
 void build_w(gs_ctx *ctx, const double *xyz, int64_t n, const double *w, const gs_graph_params &p, bool coords,
              GraphGuard &gg) {
     gs_graph_params q = p;
-    q.flags = GS_WEIGHTED | (coords ? GS_KEEP_COORDS : 0u);
+    q.flags = GS_WEIGHTED | (coords ? GS_KEEP_COORDS : 0u) | (p.flags & GS_NONPERIODIC);
     ok(gs_build_graph(ctx, xyz, n, w, &q, &gg.g), "gs_build_graph");
 }
 

@@ -125,7 +125,9 @@ void builder(Server *Sp, int k) {
             g.rmin = r->p.rmin;
             g.rmax = r->p.rmax;
             g.nbins = r->p.nbins;
-            g.flags = (r->w.empty() ? 0u : GS_WEIGHTED) | (r->kind == GS_4PCF_PARITY ? GS_KEEP_COORDS : 0u);
+            g.flags = (r->w.empty() ? 0u : GS_WEIGHTED) | (r->kind == GS_4PCF_PARITY ? GS_KEEP_COORDS : 0u) |
+                      (r->p.flags & GS_NONPERIODIC);
+            g.periodic = !(r->p.flags & GS_NONPERIODIC);
             g.bins = make_bins(r->p.rmin, r->p.rmax, r->p.nbins);
             r->job.reset(new BuildJob());
             build_begin(B, g, r->xyz.data(), r->w.empty() ? nullptr : r->w.data(), *r->job);
@@ -392,14 +394,15 @@ int gs_submit(gs_ctx *ctx, const gs_request *req, uint64_t *ticket) {
         if (req->n >= 0xFFFFFFFFll) fail(GS_EOVERFLOW, "n must be below 2^32 - 1");
         if (req->kind != GS_3PCF && req->kind != GS_4PCF_PARITY) fail(GS_EINVAL, "unknown request kind");
         if (p.flags & GS_INPUT_ON_DEVICE) fail(GS_EUNSUPPORTED, "served requests take host input");
-        if (p.flags & ~(GS_WEIGHTED | GS_KEEP_COORDS)) fail(GS_EINVAL, "unknown flags");
+        if (p.flags & ~(GS_WEIGHTED | GS_KEEP_COORDS | GS_NONPERIODIC)) fail(GS_EINVAL, "unknown flags");
         const bool weighted = (p.flags & GS_WEIGHTED) != 0;
         if (weighted != (req->weights != nullptr)) fail(GS_EINVAL, "weights given iff GS_WEIGHTED");
         if (weighted && req->kind != GS_3PCF) fail(GS_EINVAL, "weights apply to triangle counts only");
         if (!(p.box > 0) || !std::isfinite(p.box)) fail(GS_EINVAL, "box must be finite and > 0");
         if (p.nbins < 1 || p.nbins > 255) fail(GS_EINVAL, "nbins must be in 1..255");
-        if (!(p.rmin >= 0) || !(p.rmin < p.rmax) || !(p.rmax < 0.5 * p.box))
-            fail(GS_EINVAL, "need 0 <= rmin < rmax < box/2");
+        const bool periodic = !(p.flags & GS_NONPERIODIC);
+        if (!(p.rmin >= 0) || !(p.rmin < p.rmax) || !std::isfinite(p.rmax) || (periodic && !(p.rmax < 0.5 * p.box)))
+            fail(GS_EINVAL, periodic ? "need 0 <= rmin < rmax < box/2" : "need 0 <= rmin < rmax, finite");
         ctx->use();
         Server &S = server_of(*ctx);
         std::unique_ptr<Request> r(new Request());

@@ -30,6 +30,7 @@ GS_ENOCOORDS = -9
 GS_WEIGHTED = 1
 GS_KEEP_COORDS = 2
 GS_INPUT_ON_DEVICE = 4
+GS_NONPERIODIC = 8
 
 GS_DONE = 0
 GS_PENDING = 1
@@ -258,10 +259,13 @@ class Context:
     def handle(self):
         return self._h
 
-    def build_graph(self, xyz, box, rmin, rmax, nbins, weights=None, keep_coords=False) -> "Graph":
-        """xyz: (N,3) float64 numpy array (host) or torch tensor on the GPU."""
+    def build_graph(self, xyz, box, rmin, rmax, nbins, weights=None, keep_coords=False, periodic=True) -> "Graph":
+        """xyz: (N,3) float64 numpy array (host) or torch tensor on the GPU;
+        periodic=False: survey geometry (no wrap, points in [0, box)^3)."""
         on_dev = hasattr(xyz, "is_cuda") and xyz.is_cuda
         flags = (GS_INPUT_ON_DEVICE if on_dev else 0) | (GS_KEEP_COORDS if keep_coords else 0)
+        if not periodic:
+            flags |= GS_NONPERIODIC
         if weights is not None:
             flags |= GS_WEIGHTED
         if on_dev:
@@ -378,7 +382,7 @@ class Context:
                "gs_count_3pcf_batch")
         return [Count3(hs[k], int(nt[k]), None, None, None) for k in range(ng)]
 
-    def submit(self, xyz, box, rmin, rmax, nbins, weights=None, kind=GS_3PCF) -> int:
+    def submit(self, xyz, box, rmin, rmax, nbins, weights=None, kind=GS_3PCF, periodic=True) -> int:
         """Queue a count of host catalogue xyz (triangles, weighted triangles
         with `weights`, or parity 4-cliques with kind=GS_4PCF_PARITY);
         returns a ticket."""
@@ -391,7 +395,8 @@ class Context:
         req = Request(ctypes.c_void_p(x.ctypes.data), x.shape[0],
                       None if w is None else ctypes.c_void_p(w.ctypes.data),
                       GraphParams(float(box), float(rmin), float(rmax), int(nbins),
-                                  GS_WEIGHTED if w is not None else 0), int(kind), 0)
+                                  (GS_WEIGHTED if w is not None else 0) | (0 if periodic else GS_NONPERIODIC)),
+                      int(kind), 0)
         t = ctypes.c_uint64()
         _check(load().gs_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "gs_submit")
         return int(t.value)
@@ -572,7 +577,8 @@ def _config_centres(rmin, rmax, nbins):
     return tuple(np.array([c[x[k]] for x in t]) for k in range(3))
 
 
-def compute_3pcf(pos_data, w_data, pos_rand, w_rand, rmin, rmax, nbins, box, ctx=None) -> Result3pcf:
+def compute_3pcf(pos_data, w_data, pos_rand, w_rand, rmin, rmax, nbins, box, ctx=None,
+                 periodic=True) -> Result3pcf:
     """The paper's compute_3pcf (Sec. 3.4) on a periodic box: zeta =
     NNN / RRR with signed, normalised data-minus-random weights."""
     own = ctx is None
@@ -584,7 +590,7 @@ def compute_3pcf(pos_data, w_data, pos_rand, w_rand, rmin, rmax, nbins, box, ctx
         zeta, nnn, rrr = (np.zeros(nc) for _ in range(3))
         n128 = np.zeros((nc, 2), dtype=np.uint64)
         out = Zeta3(zeta.ctypes.data, nnn.ctypes.data, rrr.ctypes.data, n128.ctypes.data, None, 0, 0)
-        p = GraphParams(float(box), float(rmin), float(rmax), int(nbins), 0)
+        p = GraphParams(float(box), float(rmin), float(rmax), int(nbins), 0 if periodic else GS_NONPERIODIC)
         _check(load().gs_compute_3pcf(c.handle, ctypes.byref(d), ctypes.byref(r), ctypes.byref(p), ctypes.byref(out)),
                "gs_compute_3pcf")
         r1, r2, r3 = _config_centres(rmin, rmax, nbins)
@@ -615,7 +621,7 @@ class Result4pcf:
 
 
 def compute_4pcf(pos_data, w_data, pos_rand, w_rand, rmin, rmax, nbins, box, parity=True, connected=True,
-                 ctx=None) -> Result4pcf:
+                 ctx=None, periodic=True) -> Result4pcf:
     """The paper's compute_4pcf (Sec. 3.4) with its parity split (Sec. 3.2)
     and connected part (Sec. 3.3) on a periodic box."""
     own = ctx is None
@@ -631,7 +637,7 @@ def compute_4pcf(pos_data, w_data, pos_rand, w_rand, rmin, rmax, nbins, box, par
             arrs.update(zeta_even_disc=np.zeros(nc), zeta_even_conn=np.zeros(nc), zeta6=np.zeros(n6),
                         zeta6_disc=np.zeros(n6), zeta6_conn=np.zeros(n6), xi=np.zeros(nbins))
         out = Zeta4(**{k: v.ctypes.data for k, v in arrs.items()})
-        p = GraphParams(float(box), float(rmin), float(rmax), int(nbins), 0)
+        p = GraphParams(float(box), float(rmin), float(rmax), int(nbins), 0 if periodic else GS_NONPERIODIC)
         _check(load().gs_compute_4pcf(c.handle, ctypes.byref(d), ctypes.byref(r), ctypes.byref(p), ctypes.byref(out)),
                "gs_compute_4pcf")
         g = arrs.get

@@ -16,10 +16,12 @@ import numpy as np
 
 
 def pair_matrix(xyz, L, rmin, rmax, nb):
+    """L > 0: periodic box (minimum image); L < 0: survey geometry, no wrap."""
     x = np.asarray(xyz, dtype=np.float64)
     d = x[None, :, :] - x[:, None, :]          # d[a, b] = x_b - x_a
-    half = 0.5 * L
-    d = np.where(d > half, d - L, np.where(d < -half, d + L, d))
+    if L > 0:
+        half = 0.5 * L
+        d = np.where(d > half, d - L, np.where(d < -half, d + L, d))
     q = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
     D = (rmax - rmin) / nb
     e = [rmin] + [rmin + k * D for k in range(1, nb)] + [rmax]

@@ -712,3 +712,48 @@ def test_oracle_mu_matches_brute_force(case):
     x = synth.uniform(n, L, 91) if name == "uniform" else synth.neyman_scott(n, 20, 0.6, L, 92)
     got = oracle.count_3pcf_mu(x, L, 0.0, rmax, nb, nmu)
     assert np.array_equal(got.hist.astype(np.int64), brute.triangles_mu(x, L, 0.0, rmax, nb, nmu))
+
+
+# ------------------------------------------------------ survey geometry ----
+
+@pytest.mark.parametrize("case", [("uniform", 150, 6.0, 1.8, 4), ("clustered", 140, 8.0, 2.5, 3),
+                                  ("rmax_beyond_half_box", 60, 4.0, 3.0, 5)])
+def test_nonperiodic_matches_brute_force(case):
+    """Survey geometry (no wrap): triangles, parity 4-cliques, 6-edge
+    cliques and mu-binned triangles against brute force with plain
+    differences; rmax may exceed half the box."""
+    name, n, L, rmax, nb = case
+    x = synth.uniform(n, L, 93) if name != "clustered" else synth.neyman_scott(n, 20, 0.6, L, 94)
+    h, nt, _, _ = brute.triangles(x, -L, 0.0, rmax, nb)
+    r = oracle.count_3pcf(x, L, 0.0, rmax, nb, periodic=False)
+    assert r.n_triangles == nt and np.array_equal(r.hist.astype(np.int64), h)
+    e, p, m, nk = brute.cliques4(x, -L, 0.0, rmax, nb)[:4]
+    r4 = oracle.count_4pcf_parity(x, L, 0.0, rmax, nb, periodic=False)
+    assert r4.n_cliques == nk
+    assert np.array_equal(r4.even.astype(np.int64), e) and np.array_equal(r4.pos.astype(np.int64), p)
+    assert np.array_equal(r4.neg.astype(np.int64), m)
+    mu = oracle.count_3pcf_mu(x, L, 0.0, rmax, nb, 4, periodic=False)
+    assert np.array_equal(mu.hist.astype(np.int64), brute.triangles_mu(x, -L, 0.0, rmax, nb, 4))
+
+
+def test_nonperiodic_no_wrap_across_faces():
+    """Two points 0.2 apart across a face: one edge in the periodic box, none
+    without wrap; a catalogue far from every face counts the same either way."""
+    L = 10.0
+    x = np.array([[0.1, 5.0, 5.0], [9.9, 5.0, 5.0]])
+    assert oracle.pair_sums(x, L, 0.0, 1.0, 2).pairs.sum() == 1
+    assert oracle.pair_sums(x, L, 0.0, 1.0, 2, periodic=False).pairs.sum() == 0
+    y = 2.5 + synth.uniform(3000, 5.0, 95)      # inside [2.5, 7.5): at least rmax from the faces
+    a = oracle.count_3pcf(y, L, 0.0, 1.2, 4)
+    b = oracle.count_3pcf(y, L, 0.0, 1.2, 4, periodic=False)
+    assert np.array_equal(a.hist, b.hist) and a.n_triangles == b.n_triangles > 0
+
+
+def test_nonperiodic_all_pairs_when_rmax_exceeds_diagonal():
+    """rmax beyond the cube's diagonal: every pair is an edge, every triple a
+    triangle: C(N, 3) triangles and C(N, 4) 4-cliques."""
+    x = synth.uniform(40, 1.0, 96)
+    r = oracle.count_3pcf(x, 1.0, 0.0, 2.0, 3, periodic=False)
+    assert r.n_triangles == 40 * 39 * 38 // 6
+    r4 = oracle.count_4pcf_parity(x, 1.0, 0.0, 2.0, 3, periodic=False)
+    assert r4.n_cliques == 40 * 39 * 38 * 37 // 24
