@@ -362,6 +362,133 @@ def run_stream(gsn, count, tune=True):
     }
 
 
+def _timed(fn, steps):
+    """Run fn once untimed, then `steps` times; ms per call (wall clock with
+    device synchronisation) and the last result."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = None
+    for _ in range(steps):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, r
+
+
+def run_extras(gsn, ctx):
+    """The paper's further counts and estimators, each on a synthetic
+    stand-in of its workload, timed as build + count per step (graphs built
+    from coordinates already in device memory where the call takes them)."""
+    import numpy as np
+    import torch
+    import synth
+    out = {}
+    dev = torch.device("cuda:0")
+
+    # 6-edge 4-cliques (Sec. 3.3, Sec. 5.3): the 2e5-point clustered
+    # catalogue, 4 bins (276 configurations, the paper's count)
+    c3 = synth.workload("ns_4pcf_parity")
+    x3 = torch.from_numpy(c3.xyz).to(dev)
+
+    def six():
+        g = ctx.build_graph(x3, c3.box, 0.0, c3.rmax, 4, keep_coords=True)
+        r = ctx.count_4pcf_full(g)
+        t = ctx.timings()
+        g.free()
+        return r, t
+    ms, (r, t) = _timed(six, 2)
+    out["ns_4pcf_full"] = {"value": round(r.n_cliques / (ms / 1e3), 1), "unit": "4-cliques/s",
+                           "ms_per_step": round(ms, 3), "kernel_ms": round(t.kernel_ms, 3),
+                           "config": {"workload": "ns_4pcf_full", "n_points": c3.n, "box": c3.box, "rmax": c3.rmax,
+                                      "nbins": 4, "configurations": int(len(r.hist)),
+                                      "cliques_per_step": r.n_cliques}}
+    log("ns_4pcf_full: %.1f ms" % ms)
+
+    # parity from direction pixels (Sec. 3.2 as the paper computes it)
+    def pix():
+        g = ctx.build_graph(x3, c3.box, 0.0, c3.rmax, c3.nbins, keep_coords=True)
+        r = ctx.count_4pcf_pixel(g)
+        t = ctx.timings()
+        g.free()
+        return r, t
+    ms, (r, t) = _timed(pix, 2)
+    out["ns_4pcf_pixel"] = {"value": round(r.n_cliques / (ms / 1e3), 1), "unit": "4-cliques/s",
+                            "ms_per_step": round(ms, 3), "kernel_ms": round(t.kernel_ms, 3),
+                            "config": {"workload": "ns_4pcf_pixel", "n_points": c3.n, "box": c3.box,
+                                       "rmax": c3.rmax, "nbins": c3.nbins, "cliques_per_step": r.n_cliques}}
+    log("ns_4pcf_pixel: %.1f ms" % ms)
+
+    # restricted and anisotropic triangle counts and survey geometry on the
+    # 1e6-point clustered catalogue
+    c2 = synth.workload("ns_3pcf")
+    x2 = torch.from_numpy(c2.xyz).to(dev)
+    for name, mk in (("ns_3pcf_equilateral", lambda g: ctx.count_3pcf_equilateral(g)),
+                     ("ns_3pcf_mu", lambda g: ctx.count_3pcf_mu(g, 5)),
+                     ("ns_3pcf_survey", lambda g: ctx.count_3pcf(g))):
+        def step(mk=mk, name=name):
+            g = ctx.build_graph(x2, c2.box, 0.0, c2.rmax, c2.nbins, keep_coords=name == "ns_3pcf_mu",
+                                periodic=name != "ns_3pcf_survey")
+            r = mk(g)
+            t = ctx.timings()
+            g.free()
+            return r, t
+        ms, (r, t) = _timed(step, 5)
+        out[name] = {"value": round(r.n_triangles / (ms / 1e3), 1), "unit": "triangles/s",
+                     "ms_per_step": round(ms, 3), "kernel_ms": round(t.kernel_ms, 3),
+                     "config": {"workload": name, "n_points": c2.n, "box": c2.box, "rmax": c2.rmax,
+                                "nbins": c2.nbins, "mu_bins": 5 if name == "ns_3pcf_mu" else None,
+                                "periodic": name != "ns_3pcf_survey", "triangles_per_step": r.n_triangles}}
+        log("%s: %.2f ms" % (name, ms))
+
+    # estimators (Sec. 2.1, 3.3, 3.4): data and randoms, signed weights
+    xd = synth.neyman_scott(500_000, 50, 3.0, 1000.0, 21)
+    xr = synth.uniform(500_000, 1000.0, 22)
+    ms, r = _timed(lambda: gsn.compute_3pcf(xd, None, xr, None, 0.0, 30.0, 15, 1000.0, ctx=ctx), 2)
+    out["estimator_3pcf"] = {"value": round(1e3 / ms * 3600.0, 1), "unit": "estimates/hour", "ms_per_step": round(ms, 3),
+                             "config": {"workload": "estimator_3pcf", "data": "500,000 Neyman-Scott points",
+                                        "randoms": "500,000 uniform", "box": 1000.0, "rmax": 30.0, "nbins": 15,
+                                        "counts": "combined catalogue (signed weights) + randoms alone"}}
+    log("estimator_3pcf: %.1f ms" % ms)
+    xd4 = synth.neyman_scott(100_000, 50, 3.0, 400.0, 23)
+    xr4 = synth.uniform(100_000, 400.0, 24)
+    ms, r = _timed(lambda: gsn.compute_4pcf(xd4, None, xr4, None, 0.0, 20.0, 4, 400.0, ctx=ctx), 1)
+    out["estimator_4pcf"] = {"value": round(1e3 / ms * 3600.0, 1), "unit": "estimates/hour", "ms_per_step": round(ms, 3),
+                             "config": {"workload": "estimator_4pcf", "data": "100,000 Neyman-Scott points",
+                                        "randoms": "100,000 uniform", "box": 400.0, "rmax": 20.0, "nbins": 4,
+                                        "outputs": "parity even/odd, 6-edge, connected, internal 2pCF"}}
+    log("estimator_4pcf: %.1f ms" % ms)
+    return out
+
+
+def run_oversubscribed(gsn):
+    """Out of core at the paper's scale (Sec. 3.5.3): 2.25e6 lognormal points,
+    L 2000, rmax 150, 20 bins, weighted, ~9.1e9 directed edges (23 GB of
+    forward CSR) under a 16 GB device budget: host-tiled windows staged over
+    PCIe while counting. One step; the host input is copied in the build."""
+    import synth
+    n, L = 2_250_000, 2000.0
+    x = synth.lognormal(n, L, 7)
+    w = synth.uniform_values(n, 0.5, 1.0, 8)
+    with gsn.Context(0, budget_bytes=16 << 30) as c:
+        t0 = time.perf_counter()
+        g = c.build_graph(x, L, 0.0, 150.0, 20, weights=w)
+        t1 = time.perf_counter()
+        info = g.info()
+        r = c.count_3pcf(g, weighted=True)
+        t2 = time.perf_counter()
+        tm = c.timings()
+        g.free()
+    log("oversubscribed: build %.2f s, count %.2f s, %d windows" % (t1 - t0, t2 - t1, info.n_windows))
+    return {"value": round(r.n_triangles / (t2 - t0), 1), "unit": "triangles/s", "ms_per_step": round((t2 - t0) * 1e3, 1),
+            "count_ms": round((t2 - t1) * 1e3, 1), "build_ms": round((t1 - t0) * 1e3, 1),
+            "kernel_ms": round(tm.kernel_ms, 1),
+            "config": {"workload": "lognormal_w3pcf_oversubscribed", "n_points": n, "box": L, "rmax": 150.0,
+                       "nbins": 20, "directed_edges": 2 * int(info.n_edges), "windows": int(info.n_windows),
+                       "budget_bytes": 16 << 30, "triangles": r.n_triangles,
+                       "note": "host input; step time includes the host-to-device copies of every window"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,6 +561,8 @@ def main():
             others[name] = r
             log("%s: %.3e %s" % (name, r["value"], r["unit"]))
         others["stream_3pcf"] = run_stream(gsn, args.stream_count, tune=tune)
+        others.update(run_extras(gsn, ctx))
+        others["lognormal_w3pcf_oversubscribed"] = run_oversubscribed(gsn)
         line["configs"] = others
     print(json.dumps(line), flush=True)
     ctx.close()

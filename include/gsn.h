@@ -190,6 +190,21 @@ int gs_count_4pcf_parity_weighted(gs_ctx *ctx, const gs_graph *g, uint64_t *even
                                   uint64_t *neg, uint64_t *wsum128, int32_t *wscale, uint64_t *n_cliques,
                                   const gs_anchor_range *anchors);
 
+/* Parity counts from direction pixels (Sec. 3.2 as the paper computes
+ * them): each spoke's direction is quantised to one of 256 pixels and
+ * replaced by the pixel's centre direction, the spokes are taken in
+ * original-index order (j1 < j2 < j3), V = (u1 x u2) . u3 in the operation
+ * order above, and a hub is degenerate iff |V| < 1e-9 (repeated pixels give
+ * V = 0 exactly); even / pos / neg as gs_count_4pcf_parity. Pixels: octant
+ * (bit 2: x < 0, bit 1: y < 0, bit 0: z < 0) * 32 + i*4 + j with s =
+ * (|x|+|y|)+|z|, i = min(7, floor(8 |x|/s)), j = min(3, floor(4 |y|/(|y|+|z|)))
+ * (0 when |y|+|z| = 0), the zero vector pixel 0; centre of (o, i, j): the
+ * direction of (a, (1-a) t, (1-a)(1-t)) with the octant's signs, a =
+ * (i+0.5)/8, t = (j+0.5)/4, divided by sqrt((x*x + y*y) + z*z). Needs
+ * GS_KEEP_COORDS (pixels are taken from the separations in the kernel). */
+int gs_count_4pcf_pixel(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos, uint64_t *neg,
+                        uint64_t *n_cliques, const gs_anchor_range *anchors);
+
 /* Full 6-edge 4-clique counts (Sec. 3.3 and Sec. 5.3, the four-point
  * configurations): every 4-clique counts once into the configuration of its
  * six edge bins up to relabelling of its four vertices. A vertex order

@@ -66,6 +66,12 @@ def _load():
         lib.oracle_count_4pcf_full.restype = i32
         lib.oracle_count_3pcf_mu.argtypes = [P, i64, P, d, d, d, i32, i32, i64, i64, i32, P, P, P, P, P]
         lib.oracle_count_3pcf_mu.restype = i32
+        lib.oracle_count_4pcf_pixel.argtypes = [P, i64, d, d, d, i32, i64, i64, i32, P, P, P, P, P]
+        lib.oracle_count_4pcf_pixel.restype = i32
+        lib.oracle_pixel_of.argtypes = [P]
+        lib.oracle_pixel_of.restype = i32
+        lib.oracle_pixel_centre.argtypes = [i32, P]
+        lib.oracle_pixel_centre.restype = None
         _lib = lib
     return _lib
 
@@ -275,6 +281,35 @@ def count_3pcf_mu(xyz, box, rmin, rmax, nbins, nmu, weights=None, anchors=None, 
     if rc:
         raise OracleError(rc)
     return Result3(hist, int(nt[0]), wsum, int(ws[0]) if w is not None else None, int(used[0]))
+
+
+def pixel_of(r) -> int:
+    """Direction pixel (0..255) of a separation vector."""
+    v = np.ascontiguousarray(r, dtype=np.float64)
+    return int(_load().oracle_pixel_of(_p(v)))
+
+
+def pixel_centre(pix: int) -> np.ndarray:
+    u = np.zeros(3, dtype=np.float64)
+    _load().oracle_pixel_centre(int(pix), _p(u))
+    return u
+
+
+def count_4pcf_pixel(xyz, box, rmin, rmax, nbins, anchors=None, threads=0, periodic=True) -> Result4:
+    """Parity counts with each spoke direction quantised to a pixel and the
+    spokes in original-index order (degenerate iff |V| < 1e-9)."""
+    x = _xyz(xyz)
+    n = x.shape[0]
+    lo, hi = (0, n) if anchors is None else anchors
+    nc = n_configs(nbins) if 1 <= nbins <= 255 else 1
+    e, p, m = (np.zeros(nc, dtype=np.uint64) for _ in range(3))
+    nk = np.zeros(1, dtype=np.uint64)
+    used = np.zeros(1, dtype=np.int32)
+    rc = _load().oracle_count_4pcf_pixel(_p(x), n, _box(box, periodic), rmin, rmax, nbins, lo, hi, threads,
+                                         _p(e), _p(p), _p(m), _p(nk), _p(used))
+    if rc:
+        raise OracleError(rc)
+    return Result4(e, p, m, int(nk[0]), int(used[0]))
 
 
 def n_configs6(nbins: int) -> int:

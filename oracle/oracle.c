@@ -55,6 +55,9 @@
  *
  * D9 mu-binned 3pCF (anisotropy, Sec. 6): each triangle also carries the
  *    bin of mu = |nz|/|n|, n the normal of its plane (see mu_bin below).
+ * D10 parity from direction pixels (Sec. 3.2 as the paper computes it): each
+ *    spoke's direction quantised to a pixel, spokes in original-index order,
+ *    degenerate iff |V| < 1e-9 (see pixel_of, hub_pixel below).
  *
  * Anchors: only tuples whose smallest original point index lies in
  * [anchor_lo, anchor_hi) are counted.
@@ -571,6 +574,64 @@ static int hub_parity(const params_t *p, const double *xyz, int64_t h, const int
     return V > 0 ? 0 : 1;
 }
 
+/* D10 direction pixels (Sec. 3.2: each spoke direction quantised to one byte;
+ * the pixelisation is not given, this is our reading): 8 octants (bit 2 for
+ * x < 0, bit 1 for y < 0, bit 0 for z < 0) x 32 cells. With s = (|x|+|y|)+|z|:
+ * a = |x|/s, i = min(7, floor(8a)); t = |y|/(|y|+|z|) (0 if both vanish),
+ * j = min(3, floor(4t)); pixel = octant*32 + i*4 + j (a zero vector: 0). */
+static int pixel_of(const double r[3]) {
+    const double ax = fabs(r[0]), ay = fabs(r[1]), az = fabs(r[2]);
+    const double s = (ax + ay) + az;
+    if (!(s > 0.0)) return 0;
+    const int oct = (r[0] < 0) * 4 + (r[1] < 0) * 2 + (r[2] < 0);
+    int i = (int)floor(8.0 * (ax / s));
+    if (i > 7) i = 7;
+    const double yz = ay + az;
+    int j = yz > 0.0 ? (int)floor(4.0 * (ay / yz)) : 0;
+    if (j > 3) j = 3;
+    return oct * 32 + i * 4 + j;
+}
+
+/* The unit direction of a pixel's centre: a_c = (i+0.5)/8, t_c = (j+0.5)/4,
+ * v = (a_c, (1-a_c)*t_c, (1-a_c)*(1-t_c)) with the octant's signs, divided
+ * by sqrt((vx*vx + vy*vy) + vz*vz). */
+static void pixel_centre(int pix, double u[3]) {
+    const int oct = pix >> 5, i = (pix >> 2) & 7, j = pix & 3;
+    const double ac = ((double)i + 0.5) / 8.0, tc = ((double)j + 0.5) / 4.0;
+    double v[3] = {ac, (1.0 - ac) * tc, (1.0 - ac) * (1.0 - tc)};
+    if (oct & 4) v[0] = -v[0];
+    if (oct & 2) v[1] = -v[1];
+    if (oct & 1) v[2] = -v[2];
+    const double len = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    for (int c = 0; c < 3; ++c) u[c] = v[c] / len;
+}
+
+/* One hub's contribution with pixel directions (Sec. 3.2 as written): the
+ * spokes to s[0] < s[1] < s[2] (original indices, the paper's index order),
+ * each replaced by its pixel's centre direction; V = (u1 x u2) . u3 (D6
+ * operation order); degenerate iff |V| < 1e-9 (repeated pixels give V = 0
+ * exactly); else pos (V > 0) or neg. The configuration: sorted spoke bins. */
+static int hub_pixel(const params_t *p, const double *xyz, int64_t h, const int64_t s[3], int64_t *idx_out) {
+    double r[3][3], u[3][3];
+    int b[3];
+    for (int k = 0; k < 3; ++k) {
+        separation(p, &xyz[3 * h], &xyz[3 * s[k]], r[k]);
+        b[k] = edge_bin(p, sqlen(r[k]));
+        pixel_centre(pixel_of(r[k]), u[k]);
+    }
+    sort3i(&b[0], &b[1], &b[2]);
+    *idx_out = config_index(p->nb, b[0], b[1], b[2]);
+    const double cx = u[0][1] * u[1][2] - u[0][2] * u[1][1];
+    const double cy = u[0][2] * u[1][0] - u[0][0] * u[1][2];
+    const double cz = u[0][0] * u[1][1] - u[0][1] * u[1][0];
+    const double V = (cx * u[2][0] + cy * u[2][1]) + cz * u[2][2];
+    if (fabs(V) < 1e-9) return 2;
+    return V > 0 ? 0 : 1;
+}
+
+int oracle_pixel_of(const double *r) { return pixel_of(r); }
+void oracle_pixel_centre(int pix, double *u) { pixel_centre(pix, u); }
+
 /* t = +-((a1*a2)*a3)*a4 of a 4-clique's weights (magnitudes ascending, the
  * sign their product's), as an integer multiple of 2^-s (scale = 2^s) */
 static i128 clique_weight(const double *w, const int64_t v[4], double scale) {
@@ -848,6 +909,87 @@ int oracle_count_4pcf_full(const double *xyz, int64_t n, const double *w, double
     free(tH);
     free(tn);
     free(rank);
+    rows_free(&g);
+    return OR_OK;
+}
+
+/* D10 parity with direction pixels: as oracle_count_4pcf_parity, each hub
+ * decided by hub_pixel. */
+int oracle_count_4pcf_pixel(const double *xyz, int64_t n, double box, double rmin, double rmax, int nbins,
+                            int64_t anchor_lo, int64_t anchor_hi, int nthreads, uint64_t *even, uint64_t *pos,
+                            uint64_t *neg, uint64_t *n_cliques, int *threads_used) {
+    params_t p;
+    int rc = make_params(&p, box, rmin, rmax, nbins);
+    if (rc == OR_OK) rc = check_points(xyz, n, box);
+    if (rc != OR_OK) return rc;
+    if (n >= ((int64_t)1 << 31) || !even || !pos || !neg || !n_cliques) return OR_EINVAL;
+    if (anchor_lo < 0) anchor_lo = 0;
+    if (anchor_hi > n) anchor_hi = n;
+    int nt = resolve_threads(nthreads);
+    if (threads_used) *threads_used = nt;
+    rows_t g;
+    rc = rows_for_anchors(&p, xyz, n, nt, anchor_lo, anchor_hi, &g);
+    if (rc != OR_OK) return rc;
+    int64_t nconf = binom3(nbins + 2);
+    uint64_t *tE = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));
+    uint64_t *tP = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));
+    uint64_t *tN = (uint64_t *)calloc((size_t)(nt * nconf), sizeof(uint64_t));
+    uint64_t *tn = (uint64_t *)calloc((size_t)nt, sizeof(uint64_t));
+    if (!tE || !tP || !tN || !tn) {
+        free(tE); free(tP); free(tN); free(tn); rows_free(&g);
+        return OR_ENOMEM;
+    }
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = omp_get_thread_num();
+        uint64_t *E = tE + (int64_t)tid * nconf, *P = tP + (int64_t)tid * nconf,
+                 *N = tN + (int64_t)tid * nconf;
+        uint64_t cnt = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = anchor_lo; i < anchor_hi; ++i) {
+            for (int64_t a = g.ptr[i]; a < g.ptr[i + 1]; ++a) {
+                int32_t j = g.col[a];
+                if (j <= i) continue;
+                for (int64_t b = a + 1; b < g.ptr[i + 1]; ++b) {
+                    int32_t k = g.col[b];
+                    if (find(&g, j, k) < 0) continue;
+                    for (int64_t c = b + 1; c < g.ptr[i + 1]; ++c) {
+                        int32_t l = g.col[c];
+                        if (find(&g, j, l) < 0 || find(&g, k, l) < 0) continue;
+                        ++cnt;
+                        const int64_t v[4] = {i, j, k, l};   /* ascending original indices */
+                        for (int h = 0; h < 4; ++h) {
+                            int64_t sp[3], idx;
+                            int u = 0;
+                            for (int o = 0; o < 4; ++o)
+                                if (o != h) sp[u++] = v[o];
+                            const int ch = hub_pixel(&p, xyz, v[h], sp, &idx);
+                            E[idx] += 1;
+                            if (ch == 0) P[idx] += 1;
+                            if (ch == 1) N[idx] += 1;
+                        }
+                    }
+                }
+            }
+        }
+        tn[tid] = cnt;
+    }
+    memset(even, 0, sizeof(uint64_t) * (size_t)nconf);
+    memset(pos, 0, sizeof(uint64_t) * (size_t)nconf);
+    memset(neg, 0, sizeof(uint64_t) * (size_t)nconf);
+    *n_cliques = 0;
+    for (int t = 0; t < nt; ++t) {
+        *n_cliques += tn[t];
+        for (int64_t c = 0; c < nconf; ++c) {
+            even[c] += tE[(int64_t)t * nconf + c];
+            pos[c] += tP[(int64_t)t * nconf + c];
+            neg[c] += tN[(int64_t)t * nconf + c];
+        }
+    }
+    free(tE);
+    free(tP);
+    free(tN);
+    free(tn);
     rows_free(&g);
     return OR_OK;
 }

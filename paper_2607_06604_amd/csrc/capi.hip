@@ -485,6 +485,24 @@ int gs_count_4pcf_parity_weighted(gs_ctx *ctx, const gs_graph *g, uint64_t *even
     });
 }
 
+int gs_count_4pcf_pixel(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos, uint64_t *neg,
+                        uint64_t *n_cliques, const gs_anchor_range *anchors) {
+    return guarded([&] {
+        if (!ctx || !g || !even || !pos || !neg || !n_cliques) fail(GS_EINVAL, "null argument");
+        check4(ctx, g);
+        ctx->use();
+        const int64_t nc = n_configs(g->nbins);
+        Count4Out o;
+        o.kind = kPixel4;
+        o.cnt[0] = pos;
+        o.cnt[1] = neg;
+        o.cnt[2] = even;
+        o.ncl = n_cliques;
+        count4_run(*ctx, *g, o, anchors);
+        for (int64_t c = 0; c < nc; ++c) even[c] += pos[c] + neg[c];
+    });
+}
+
 int gs_count_4pcf_full(gs_ctx *ctx, const gs_graph *g, uint64_t *hist6, uint64_t *wsum128, int32_t *wscale,
                        uint64_t *n_cliques, const gs_anchor_range *anchors) {
     return guarded([&] {

@@ -296,13 +296,14 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
                 uint32_t sample_hi = 0);
 // Time schedules on a sample of g's hubs and keep the fastest for g's shape.
 void tune3(Ctx &ctx, const Graph &g, bool weighted, gs_plan3 *out);
-// 4-clique counts. kind kParity4: counters in three blocks of C(nb+2,3),
-// pos | neg | degenerate (even = their sum); kSix4: one block of 6-edge
+// 4-clique counts. kind kParity4 (or kPixel4, parity from direction pixels):
+// counters in three blocks of C(nb+2,3), pos | neg | degenerate (even =
+// their sum); kSix4: one block of 6-edge
 // configurations. Each block is copied to host cnt[b]; with wsum[0] set,
 // wsum[b] receives the block's exact signed 128-bit weighted sums (2 words
 // per counter, units 2^-wscale). scratch: device memory of scratch_bytes to
 // use instead of the context's (nothing is allocated then).
-enum { kParity4 = 0, kSix4 = 1 };
+enum { kParity4 = 0, kSix4 = 1, kPixel4 = 2 };
 constexpr int kMaxBins6 = 12;
 struct Count4Out {
     int kind = kParity4;

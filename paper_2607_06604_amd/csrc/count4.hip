@@ -26,7 +26,9 @@
 // configuration's rank), and both counts optionally sum each clique's exact
 // weight product (signed weights of Sec. 2.1) per counter.
 #include <array>
+#include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <cstdlib>
 
 #include "kern_util.h"
@@ -59,12 +61,13 @@ struct C4Args {
     const uint32_t *cfg6;       // 6-edge: configuration of every edge-bin tuple code
     int n6;                     // 6-edge configurations
     int lds_cnt;                // counters held in LDS (0: 6-edge counts go to global memory)
+    const double *pixdir;       // pixel kind: the 256 pixel centre directions (x, y, z each)
 };
 
 
 struct Layout4 {
     uint32_t hkey, hloc, hslot, px, py, pz, sx, sy, sz, pq, pb, pperm, R, rbnd, queue, mstart, mpref, mloc,
-        hist, tab, lut, thr, wtot, misc, pw, wlo, whi, tab6, total;
+        hist, tab, lut, thr, wtot, misc, pw, wlo, whi, tab6, tabp, total;
 };
 
 constexpr int kLut4MaxBins = 16;   // nb^3 u16 counter addresses up to 8 KB
@@ -76,13 +79,13 @@ constexpr int kTab6Lds = 4096;
 // 6-edge counters in LDS up to this many configurations.
 constexpr int kCnt6Lds = 6144;
 
-// kind: kParity4 or kSix4; ncnt: counters held in LDS; tab6: codes of the
-// 6-edge table staged in LDS (0: none).
+// kind: kParity4, kSix4 or kPixel4; ncnt: counters held in LDS; tab6: codes
+// of the 6-edge table staged in LDS (0: none).
 __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxdeg, int W, int ncnt,
                                            int nb, bool anchored, int kind, bool weighted, int tab6) {
     Layout4 L{};
     uint32_t o = 0, d = maxdeg + 1;
-    const bool spokes = kind == kParity4;   // hub spokes and lengths: parity only
+    const bool spokes = kind != kSix4;   // hub spokes and lengths: the parity kinds
     L.px = o;      o = lds_align(o + 8 * d, 16);
     L.py = o;      o = lds_align(o + 8 * d, 16);
     L.pz = o;      o = lds_align(o + 8 * d, 16);
@@ -102,7 +105,8 @@ __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxde
     L.hkey = o;    o = lds_align(o + 4 * H, 16);
     L.R = o;       o = lds_align(o + 4 * d * W, 16);
     L.mpref = o;   o = lds_align(o + 4 * (block + 1), 16);
-    L.pperm = o;   if (anchored) o = lds_align(o + 4 * d, 16);
+    L.pperm = o;   if (anchored || kind == kPixel4) o = lds_align(o + 4 * d, 16);
+    L.tabp = o;    if (kind == kPixel4) o = lds_align(o + 8 * 3 * 256, 16);
     L.hist = o;    o = lds_align(o + 4 * ncnt, 16);
     L.tab = o;     o = lds_align(o + 8 * (nb + 1), 16);
     L.lut = o;     if (spokes && nb <= kLut4MaxBins) o = lds_align(o + 2 * nb * nb * nb, 16);
@@ -225,6 +229,8 @@ struct Stage4 {
     unsigned long long *ghist, *gwsum;  // global counters and sums (6-edge beyond LDS)
     const uint32_t *cfg6;         // 6-edge configuration of a tuple code (global)
     const uint16_t *tab6;         // the same table in LDS (small bin counts)
+    const double *pdir;           // pixel kind: centre directions in LDS (768 doubles)
+    const uint32_t *pperm;        // original indices of N+(i)
 };
 
 // A clique's weight term in units of 2^-s: the four magnitudes in ascending
@@ -433,6 +439,78 @@ __device__ __forceinline__ void eval_six(const Stage4 &S, uint32_t hist_addr, ui
 }
 
 // LDS counters (and weighted sums) into the 64-bit (128-bit) results.
+// ---- parity from direction pixels (Sec. 3.2 as the paper computes it) ----
+// A separation's pixel: octant (bit 2: x < 0, bit 1: y < 0, bit 0: z < 0)
+// times 32 plus the cell i*4 + j, i = min(7, floor(8 |x|/s)) with
+// s = (|x|+|y|)+|z|, j = min(3, floor(4 |y|/(|y|+|z|))) (0 when |y|+|z| = 0);
+// the zero vector is pixel 0. The reverse separation (exactly the negation)
+// has the same cell and the octant of the opposite signs.
+__device__ __forceinline__ void pixel_pair(const P3 &r, uint32_t &fwd, uint32_t &rev) {
+    const double ax = fabs(r.x), ay = fabs(r.y), az = fabs(r.z);
+    const double s = __dadd_rn(__dadd_rn(ax, ay), az);
+    if (!(s > 0.0)) {
+        fwd = rev = 0;
+        return;
+    }
+    const int i = min(7, (int)floor(__dmul_rn(8.0, __ddiv_rn(ax, s))));
+    const double yz = __dadd_rn(ay, az);
+    const int j = yz > 0.0 ? min(3, (int)floor(__dmul_rn(4.0, __ddiv_rn(ay, yz)))) : 0;
+    const uint32_t cell = (uint32_t)(i * 4 + j);
+    fwd = (((r.x < 0.0) ? 4u : 0u) | ((r.y < 0.0) ? 2u : 0u) | ((r.z < 0.0) ? 1u : 0u)) * 32u + cell;
+    rev = (((r.x > 0.0) ? 4u : 0u) | ((r.y > 0.0) ? 2u : 0u) | ((r.z > 0.0) ? 1u : 0u)) * 32u + cell;
+}
+
+// One hub: its three spokes' pixels (o*: the target's original index), the
+// spokes taken in original-index order, V from the pixel centres in the
+// definition's operation order; 2 (degenerate) iff |V| < 1e-9, else 0 pos,
+// 1 neg.
+__device__ __forceinline__ int hub_pixel(const double *pd, uint32_t o0, uint32_t p0, uint32_t o1, uint32_t p1,
+                                         uint32_t o2, uint32_t p2) {
+    uint32_t t;
+    if (o0 > o1) { t = o0; o0 = o1; o1 = t; t = p0; p0 = p1; p1 = t; }
+    if (o1 > o2) { t = o1; o1 = o2; o2 = t; t = p1; p1 = p2; p2 = t; }
+    if (o0 > o1) { t = o0; o0 = o1; o1 = t; t = p0; p0 = p1; p1 = t; }
+    const P3 u{pd[3 * p0], pd[3 * p0 + 1], pd[3 * p0 + 2]};
+    const P3 v{pd[3 * p1], pd[3 * p1 + 1], pd[3 * p1 + 2]};
+    const P3 w{pd[3 * p2], pd[3 * p2 + 1], pd[3 * p2 + 2]};
+    const double V = triple(u, v, w);
+    return fabs(V) < 1e-9 ? 2 : (V > 0.0 ? 0 : 1);
+}
+
+template <bool LUT>
+__device__ __forceinline__ void eval_pixel(const Stage4 &S, uint32_t hist_addr, uint32_t va, uint32_t vb,
+                                           uint32_t vc, bool wrap, uint32_t oi) {
+    const P3 ia{S.sx[va], S.sy[va], S.sz[va]};
+    const P3 ib{S.sx[vb], S.sy[vb], S.sz[vb]};
+    const P3 ic{S.sx[vc], S.sy[vc], S.sz[vc]};
+    P3 ab, ac, bcv;
+    local_seps(S, va, vb, vc, wrap, ab, ac, bcv);
+    int bab, bac, bbc;
+    local_bins(S, va, vb, vc, wrap, bab, bac, bbc);
+    uint32_t fia, ria, fib, rib, fic, ric, fab, rab, fac, rac, fbc, rbc;
+    pixel_pair(ia, fia, ria);
+    pixel_pair(ib, fib, rib);
+    pixel_pair(ic, fic, ric);
+    pixel_pair(ab, fab, rab);
+    pixel_pair(ac, fac, rac);
+    pixel_pair(bcv, fbc, rbc);
+    const uint32_t oa = S.pperm[va], ob = S.pperm[vb], oc = S.pperm[vc];
+    const int ba = S.pb[va], bb = S.pb[vb], bc = S.pb[vc];
+    const int ch0 = hub_pixel(S.pdir, oa, fia, ob, fib, oc, fic);
+    const int ch1 = hub_pixel(S.pdir, oi, ria, ob, fab, oc, fac);
+    const int ch2 = hub_pixel(S.pdir, oi, rib, oa, rab, oc, fbc);
+    const int ch3 = hub_pixel(S.pdir, oi, ric, oa, rac, ob, rbc);
+    const uint32_t blk = 4u * (uint32_t)S.nconf;
+    const uint32_t a0 = conf_addr<LUT>(S, hist_addr, ba, bb, bc) + blk * (uint32_t)ch0;
+    const uint32_t a1 = conf_addr<LUT>(S, hist_addr, ba, bab, bac) + blk * (uint32_t)ch1;
+    const uint32_t a2 = conf_addr<LUT>(S, hist_addr, bb, bab, bbc) + blk * (uint32_t)ch2;
+    const uint32_t a3 = conf_addr<LUT>(S, hist_addr, bc, bac, bbc) + blk * (uint32_t)ch3;
+    __hip_atomic_fetch_add((lds_u32 *)(size_t)a0, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add((lds_u32 *)(size_t)a1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add((lds_u32 *)(size_t)a2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add((lds_u32 *)(size_t)a3, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 template <int BLOCK, bool WEIGHTED>
 __device__ void flush4(const C4Args &a, const Stage4 &S, uint32_t *hist) {
     for (int b = threadIdx.x; b < a.lds_cnt; b += BLOCK) {
@@ -461,7 +539,8 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const uint32_t H = 1u << a.log2h, mask = H - 1;
     const int W = a.W;
-    constexpr bool LUT = KIND == kParity4 && VAR == 1;
+    constexpr bool LUT = KIND != kSix4 && VAR == 1;
+    constexpr bool PERM = ANCHORED || KIND == kPixel4;
     constexpr bool TAB6 = KIND == kSix4 && VAR == 0;
     constexpr bool CNT_LDS = KIND == kParity4 || VAR < 2;
     const Layout4 L = layout4(BLOCK, H, a.maxdeg, W, a.lds_cnt, a.nb, ANCHORED, KIND, WEIGHTED,
@@ -496,6 +575,9 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     double *pw = (double *)(sm + L.pw);
     unsigned long long *wlo = (unsigned long long *)(sm + L.wlo), *whi = (unsigned long long *)(sm + L.whi);
     uint16_t *tab6 = (uint16_t *)(sm + L.tab6);
+    double *pdir = (double *)(sm + L.tabp);
+    if (KIND == kPixel4)
+        for (int t = tid; t < 3 * 256; t += BLOCK) pdir[t] = a.pixdir[t];
 
     for (uint32_t s = tid; s < H; s += BLOCK) hkey[s] = kEmptyKey;
     for (int b = tid; b < a.lds_cnt; b += BLOCK) {
@@ -528,7 +610,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     HubCursor cursor;   // thread 0's claimed run of hubs
     const double Lb = a.L, half = a.half;
     const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, lut, hist, a.nb, a.nconf, a.L, a.half, a.tk,
-                   pw, a.wmul, wlo, whi, a.hist, a.wsum, a.cfg6, tab6};
+                   pw, a.wmul, wlo, whi, a.hist, a.wsum, a.cfg6, tab6, pdir, pperm};
     const uint32_t hist_addr = lds_addr(hist);
 
     while (true) {
@@ -540,7 +622,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
         const uint32_t d = (uint32_t)(a.rp[i + 1] - beg);
         if (d < 3) { __syncthreads(); continue; }
         const double xi = a.X[i], yi = a.Y[i], zi = a.Z[i];
-        const uint32_t pi = ANCHORED ? a.perm[i] : 0;
+        const uint32_t pi = PERM ? a.perm[i] : 0;
         // every vertex of this hub's cliques lies within rmax of the hub and
         // so, away from the faces, no separation among them wraps
         const bool inner = __builtin_amdgcn_readfirstlane((int)(xi >= a.in_lo && xi <= a.in_hi && yi >= a.in_lo &&
@@ -557,7 +639,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
             px[e] = x;
             py[e] = y;
             pz[e] = z;
-            if (KIND == kParity4) {
+            if (KIND != kSix4) {
                 const double dx = min_image(xi, x, Lb, half), dy = min_image(yi, y, Lb, half),
                              dz = min_image(zi, z, Lb, half);
                 sx[e] = dx;
@@ -566,7 +648,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
                 pq[e] = sq_len(dx, dy, dz);
             }
             pb[e] = a.bin[beg + e];
-            if (ANCHORED) pperm[e] = a.perm[k];
+            if (PERM) pperm[e] = a.perm[k];
             if (WEIGHTED) pw[e] = a.w[k];
         }
         const double wi = WEIGHTED ? a.w[i] : 0.0;
@@ -703,6 +785,8 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
                                 if (KIND == kParity4)
                                     eval_clique<LUT, WEIGHTED>(S, hist_addr, va, vb, vc, inner ? a.eb_in : a.eb_wrap,
                                                                !inner, wi);
+                                else if (KIND == kPixel4)
+                                    eval_pixel<LUT>(S, hist_addr, va, vb, vc, !inner, pi);
                                 else
                                     eval_six<TAB6, CNT_LDS, WEIGHTED>(S, hist_addr, va, vb, vc, !inner, wi);
                                 wave_lds_sync();
@@ -719,6 +803,8 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
                                vc = (uint32_t)(t >> 32);
                 if (KIND == kParity4)
                     eval_clique<LUT, WEIGHTED>(S, hist_addr, va, vb, vc, inner ? a.eb_in : a.eb_wrap, !inner, wi);
+                else if (KIND == kPixel4)
+                    eval_pixel<LUT>(S, hist_addr, va, vb, vc, !inner, pi);
                 else
                     eval_six<TAB6, CNT_LDS, WEIGHTED>(S, hist_addr, va, vb, vc, !inner, wi);
             }
@@ -762,6 +848,12 @@ void launch4(Ctx &ctx, const C4Args &a, uint32_t lds) {
     grid = (grid + kNumQueues - 1) / kNumQueues * kNumQueues;
     k_count4<BLOCK, KIND, A, VAR, WT><<<dim3(grid), dim3(BLOCK), lds, ctx.stream>>>(a);
     GS_HIP(hipGetLastError());
+}
+
+template <int VAR>
+void launch4_pixel(Ctx &ctx, const C4Args &a, uint32_t lds, bool anchored) {
+    if (anchored) launch4<512, kPixel4, true, VAR, false>(ctx, a, lds);
+    else launch4<512, kPixel4, false, VAR, false>(ctx, a, lds);
 }
 
 template <int BLOCK, int KIND, int VAR>
@@ -866,6 +958,34 @@ const std::vector<uint32_t> &config6_table(int nb, uint32_t *n6) {
     return it->second.first;
 }
 
+// The 256 pixel centre directions (x, y, z each): a pixel (octant o, cell
+// i*4 + j) is the direction of (a, (1-a) t, (1-a)(1-t)), a = (i+0.5)/8,
+// t = (j+0.5)/4, with the octant's signs (bit 2: x < 0, bit 1: y, bit 0: z),
+// divided by its length sqrt((x*x + y*y) + z*z).
+static const double *pixel_dirs() {
+    static double dirs[3 * 256];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        for (int p = 0; p < 256; ++p) {
+            const int o = p >> 5, i = (p >> 2) & 7, j = p & 3;
+            volatile double a = ((double)i + 0.5) / 8.0, t = ((double)j + 0.5) / 4.0;
+            volatile double na = 1.0 - a, nt = 1.0 - t;
+            volatile double x = a, y = na * t, z = na * nt;
+            if (o & 4) x = -x;
+            if (o & 2) y = -y;
+            if (o & 1) z = -z;
+            volatile double xx = x * x, yy = y * y, zz = z * z;
+            volatile double s2 = xx + yy;
+            s2 = s2 + zz;
+            const double len = std::sqrt((double)s2);
+            dirs[3 * p] = x / len;
+            dirs[3 * p + 1] = y / len;
+            dirs[3 * p + 2] = z / len;
+        }
+    });
+    return dirs;
+}
+
 // The device copy of the table, kept in the context per bin count.
 static const uint32_t *config6_device(Ctx &ctx, int nb, uint32_t *n6) {
     const std::vector<uint32_t> &t = config6_table(nb, n6);
@@ -882,7 +1002,9 @@ void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_ra
     const int nb = g.nbins;
     const int nconf = (int)n_configs(nb);
     const bool six = o.kind == kSix4;
+    const bool pixel = o.kind == kPixel4;
     const bool weighted = o.wsum[0] != nullptr;
+    if (pixel && weighted) fail(GS_EUNSUPPORTED, "pixel parity counts are unweighted");
     const bool anchored = anchors != nullptr;
     if (anchored && anchors->lo > anchors->hi) fail(GS_EINVAL, "anchor range lo > hi");
     if (six && nb > kMaxBins6) fail(GS_EUNSUPPORTED, "6-edge counts take at most 12 bins");
@@ -905,6 +1027,7 @@ void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_ra
     // wider group doubles the wavefronts that hide LDS and float64 latency
     int BLOCK = 512;
     if (const char *eb = getenv("GS_BLOCK4")) BLOCK = atoi(eb) == 256 ? 256 : 512;
+    if (o.kind != kParity4) BLOCK = 512;   // the other kinds are built for 512 lanes only
     Layout4 L = layout4(BLOCK, H, maxdeg, W, lds_cnt, nb, anchored, o.kind, weighted, tab6);
     if ((int)L.total > ctx.max_lds)
         fail(GS_EUNSUPPORTED, "4-clique kernel LDS footprint too large (forward degree " +
@@ -915,7 +1038,7 @@ void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_ra
     const size_t woff = ((size_t)ncnt + 1 + 31) / 32 * 32;
     const size_t qoff = weighted ? (woff + 2 * (size_t)ncnt + 31) / 32 * 32 : woff;
     const size_t words = qoff + kQueueWords / 2;
-    const size_t need = words * 8 + 256 * 8;
+    const size_t need = words * 8 + 256 * 8 + (pixel ? 3 * 256 * 8 : 0);
     unsigned long long *dv;
     if (o.scratch) {
         if (need > o.scratch_bytes) fail(GS_EUNSUPPORTED, "count needs " + std::to_string(need) +
@@ -986,15 +1109,20 @@ void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_ra
     a.cfg6 = cfg6;
     a.n6 = (int)n6;
     a.lds_cnt = lds_cnt;
+    a.pixdir = pixel ? dthr + 256 : nullptr;
 
     hipStream_t s = ctx.stream;
     GS_HIP(hipEventRecord(ctx.ev[0], s));
     k_zero4<<<64, 256, 0, s>>>(dv, words);
     GS_HIP(hipMemcpyAsync(dthr, g.bins.t, sizeof(double) * 256, hipMemcpyHostToDevice, s));
+    if (pixel) GS_HIP(hipMemcpyAsync(dthr + 256, pixel_dirs(), sizeof(double) * 768, hipMemcpyHostToDevice, s));
     GS_HIP(hipEventRecord(ctx.ev[2], s));
     if (g.n > 0) {
         const uint32_t lds = L.total;
-        if (six) {
+        if (pixel) {
+            if (var == 1) launch4_pixel<1>(ctx, a, lds, anchored);
+            else launch4_pixel<0>(ctx, a, lds, anchored);
+        } else if (six) {
             if (var == 0) launch4_v<512, kSix4, 0>(ctx, a, lds, anchored, weighted);
             else if (var == 1) launch4_v<512, kSix4, 1>(ctx, a, lds, anchored, weighted);
             else launch4_v<512, kSix4, 2>(ctx, a, lds, anchored, weighted);

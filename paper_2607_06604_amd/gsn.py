@@ -47,7 +47,7 @@ EXPORTS = ["gs_create", "gs_destroy", "gs_build_graph", "gs_graph_info", "gs_gra
            "gs_last_error_detail", "gs_ceiling_copy", "gs_ceiling_probe", "gs_count_4pcf_parity_weighted",
            "gs_count_4pcf_full", "gs_n_configs6", "gs_config6_table", "gs_pair_sums",
            "gs_count_4pcf_parity_noalloc", "gs_count_3pcf_equilateral", "gs_count_3pcf_mu",
-           "gs_compute_3pcf", "gs_compute_4pcf"]
+           "gs_compute_3pcf", "gs_compute_4pcf", "gs_count_4pcf_pixel"]
 
 
 class GraphParams(ctypes.Structure):
@@ -145,6 +145,7 @@ def load(path: str = LIB_PATH):
         "gs_count_4pcf_parity_weighted": ([P, P, P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_count_4pcf_parity_noalloc": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_count_4pcf_full": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
+        "gs_count_4pcf_pixel": ([P, P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
         "gs_n_configs6": ([i32, ctypes.POINTER(ctypes.c_uint32)], i32),
         "gs_config6_table": ([i32, P], i32),
         "gs_pair_sums": ([P, P, P, P, P, ctypes.POINTER(AnchorRange)], i32),
@@ -320,6 +321,15 @@ class Context:
                                                     _ptr(sc), _ptr(nk), _anchors(anchors)),
                "gs_count_4pcf_parity_weighted")
         return Count4(e, p, m, int(nk[0]), ws, int(sc[0]))
+
+    def count_4pcf_pixel(self, g: "Graph", anchors=None):
+        """Parity counts from direction pixels, spokes in original-index order."""
+        nc = n_configs(g.nbins)
+        e, p, m = (np.zeros(nc, dtype=np.uint64) for _ in range(3))
+        nk = np.zeros(1, dtype=np.uint64)
+        _check(load().gs_count_4pcf_pixel(self._h, g.handle, _ptr(e), _ptr(p), _ptr(m), _ptr(nk), _anchors(anchors)),
+               "gs_count_4pcf_pixel")
+        return Count4(e, p, m, int(nk[0]))
 
     def count_4pcf_full(self, g: "Graph", anchors=None, weighted=False):
         """6-edge 4-clique counts (and exact weighted sums)."""

@@ -263,3 +263,67 @@ def triangles_mu(xyz, L, rmin, rmax, nb, nmu):
                 c = rank[tuple(sorted((int(b[i, j]), int(b[i, k]), int(b[j, k]))))]
                 hist[c * nmu + m] += 1
     return hist
+
+
+def pixel(r):
+    """Direction pixel: octant (x<0: 4, y<0: 2, z<0: 1) * 32 + i * 4 + j with
+    i = min(7, floor(8 |x|/s)), s = (|x|+|y|)+|z|, j = min(3, floor(4 |y|/(|y|+|z|)))."""
+    ax, ay, az = abs(float(r[0])), abs(float(r[1])), abs(float(r[2]))
+    s = (ax + ay) + az
+    if not s > 0.0:
+        return 0
+    o = 4 * (r[0] < 0) + 2 * (r[1] < 0) + (r[2] < 0)
+    i = min(7, math.floor(8.0 * (ax / s)))
+    yz = ay + az
+    j = min(3, math.floor(4.0 * (ay / yz))) if yz > 0.0 else 0
+    return int(o) * 32 + i * 4 + j
+
+
+def pixel_dir(p):
+    o, i, j = p >> 5, (p >> 2) & 7, p & 3
+    ac, tc = (i + 0.5) / 8.0, (j + 0.5) / 4.0
+    v = [ac, (1.0 - ac) * tc, (1.0 - ac) * (1.0 - tc)]
+    for bit, c in ((4, 0), (2, 1), (1, 2)):
+        if o & bit:
+            v[c] = -v[c]
+    n = math.sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2])
+    return [c / n for c in v]
+
+
+def cliques4_pixel(xyz, L, rmin, rmax, nb):
+    """Parity with direction pixels: per clique and hub, spokes in index
+    order, V from pixel centres, degenerate iff |V| < 1e-9."""
+    n = len(xyz)
+    d, q, adj, b = pair_matrix(xyz, L, rmin, rmax, nb)
+    rank = lex_configs(nb)
+    E = np.zeros(len(rank), dtype=np.int64)
+    P = np.zeros_like(E)
+    N = np.zeros_like(E)
+    count = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            if not adj[i, j]:
+                continue
+            for k in range(j + 1, n):
+                if not (adj[i, k] and adj[j, k]):
+                    continue
+                for l in range(k + 1, n):
+                    if not (adj[i, l] and adj[j, l] and adj[k, l]):
+                        continue
+                    count += 1
+                    v = (i, j, k, l)
+                    for h in v:
+                        sp = [s for s in v if s != h]
+                        u = [pixel_dir(pixel(d[h, s])) for s in sp]
+                        cx = u[0][1] * u[1][2] - u[0][2] * u[1][1]
+                        cy = u[0][2] * u[1][0] - u[0][0] * u[1][2]
+                        cz = u[0][0] * u[1][1] - u[0][1] * u[1][0]
+                        V = (cx * u[2][0] + cy * u[2][1]) + cz * u[2][2]
+                        c = rank[tuple(sorted(int(b[h, s]) for s in sp))]
+                        E[c] += 1
+                        if abs(V) >= 1e-9:
+                            if V > 0:
+                                P[c] += 1
+                            else:
+                                N[c] += 1
+    return E, P, N, count

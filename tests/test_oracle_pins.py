@@ -757,3 +757,71 @@ def test_nonperiodic_all_pairs_when_rmax_exceeds_diagonal():
     assert r.n_triangles == 40 * 39 * 38 // 6
     r4 = oracle.count_4pcf_parity(x, 1.0, 0.0, 2.0, 3, periodic=False)
     assert r4.n_cliques == 40 * 39 * 38 * 37 // 24
+
+
+# ---------------------------------------------------- direction pixels ----
+
+@pytest.mark.parametrize("r,want", [
+    ((1.0, 0.0, 0.0), 28),      # octant 0; a = 1 -> i = 7 (capped); |y|+|z| = 0 -> j = 0
+    ((-1.0, 0.0, 0.0), 156),    # x < 0: octant 4 -> 128 + 28
+    ((0.0, 0.0, 1.0), 0),       # a = 0, t = 0
+    ((1.0, 1.0, 1.0), 10),      # a = 1/3 -> i = 2; t = 1/2 -> j = 2
+    ((0.0, -2.0, 0.0), 67),     # y < 0: octant 2 -> 64; a = 0; t = 1 -> j = 3 (capped)
+    ((3.0, 1.0, 0.0), 27),      # a = 3/4 -> i = 6; t = 1 -> j = 3
+    ((1.0, 0.0, -1.0), 48),     # z < 0: octant 1 -> 32; a = 1/2 -> i = 4; t = 0 -> j = 0
+])
+def test_pixel_of_hand_derived(r, want):
+    assert oracle.pixel_of(r) == want
+
+
+def test_pixel_centre_hand_derived():
+    # pixel 10: a_c = 2.5/8 = 0.3125, t_c = 2.5/4 = 0.625 ->
+    # v = (0.3125, 0.6875*0.625, 0.6875*0.375) = (0.3125, 0.4296875, 0.2578125)
+    v = np.array([0.3125, 0.4296875, 0.2578125])
+    u = oracle.pixel_centre(10)
+    assert np.allclose(u, v / np.linalg.norm(v), rtol=0, atol=1e-15)
+    # pixel 170 = octant 5 (x < 0, z < 0), i = 2, j = 2: the mirror of 10 in x and z
+    w = oracle.pixel_centre(5 * 32 + 10)
+    assert np.array_equal(w, u * np.array([-1.0, 1.0, -1.0]))
+
+
+def test_pixel_parity_repeated_pixel_is_degenerate():
+    """Hub O with spokes (1,0,0) and (1,0,0.001) in one pixel: their centre
+    directions coincide, the cross product is exactly zero, the hub takes no
+    odd weight; the clique's other hubs still count in even."""
+    x = np.array([[2.0, 2.0, 2.0], [3.0, 2.0, 2.0], [3.0, 2.0, 2.001], [2.0, 3.0, 2.0]])
+    assert oracle.pixel_of(x[1] - x[0]) == oracle.pixel_of(x[2] - x[0]) == 28
+    r = oracle.count_4pcf_pixel(x, 8.0, 0.0, 2.0, 2)
+    assert r.n_cliques == 1 and int(r.even.sum()) == 4
+    # hub O (index 0): spokes in index order to 1, 2, 3; u1 = u2 -> V = 0
+    e, p, m, _ = brute.cliques4_pixel(x, 8.0, 0.0, 2.0, 2)
+    assert np.array_equal(r.pos.astype(np.int64), p) and np.array_equal(r.neg.astype(np.int64), m)
+    assert int(r.pos.sum() + r.neg.sum()) <= 3
+
+
+@pytest.mark.parametrize("case", [("uniform", 110, 8.0, 2.6, 4), ("clustered", 110, 10.0, 2.0, 3),
+                                  ("survey", 100, 7.0, 2.6, 3)])
+def test_oracle_pixel_parity_matches_brute_force(case):
+    name, n, L, rmax, nb = case
+    x = synth.uniform(n, L, 97) if name != "clustered" else synth.neyman_scott(n, 22, 0.7, L, 98)
+    periodic = name != "survey"
+    r = oracle.count_4pcf_pixel(x, L, 0.0, rmax, nb, periodic=periodic)
+    e, p, m, nk = brute.cliques4_pixel(x, L if periodic else -L, 0.0, rmax, nb)
+    assert r.n_cliques == nk
+    assert np.array_equal(r.even.astype(np.int64), e)
+    assert np.array_equal(r.pos.astype(np.int64), p) and np.array_equal(r.neg.astype(np.int64), m)
+
+
+def test_pixel_parity_reflection_swaps_channels():
+    """x -> L - x on a fine dyadic grid: every pixel mirrors in x (no zero
+    components here), centres negate their x exactly, the index order is
+    kept, so V negates exactly: pos and neg swap, even is unchanged."""
+    L = 16.0
+    x = synth.dyadic_uniform(3000, L, 99)
+    y = x.copy()
+    y[:, 0] = np.mod(L - y[:, 0], L)
+    a = oracle.count_4pcf_pixel(x, L, 0.0, 1.6, 4)
+    b = oracle.count_4pcf_pixel(y, L, 0.0, 1.6, 4)
+    assert a.n_cliques == b.n_cliques > 0
+    assert np.array_equal(a.even, b.even)
+    assert np.array_equal(a.pos, b.neg) and np.array_equal(a.neg, b.pos)
