@@ -72,6 +72,8 @@ def _load():
         lib.oracle_pixel_of.restype = i32
         lib.oracle_pixel_centre.argtypes = [i32, P]
         lib.oracle_pixel_centre.restype = None
+        lib.oracle_hub_pixel_channel.argtypes = [P, d, d, d, i32, i32]
+        lib.oracle_hub_pixel_channel.restype = i32
         _lib = lib
     return _lib
 
@@ -293,6 +295,16 @@ def pixel_centre(pix: int) -> np.ndarray:
     u = np.zeros(3, dtype=np.float64)
     _load().oracle_pixel_centre(int(pix), _p(u))
     return u
+
+
+def hub_pixel_channel(xyz4, box, rmin, rmax, nbins, h) -> int:
+    """Channel of hub h (0 pos, 1 neg, 2 degenerate) of four points under the
+    pixel rule, its spokes to the other three in index order."""
+    x = _xyz(xyz4)
+    r = int(_load().oracle_hub_pixel_channel(_p(x), box, rmin, rmax, nbins, h))
+    if r < 0:
+        raise OracleError(r)
+    return r
 
 
 def count_4pcf_pixel(xyz, box, rmin, rmax, nbins, anchors=None, threads=0, periodic=True) -> Result4:

@@ -630,6 +630,18 @@ static int hub_pixel(const params_t *p, const double *xyz, int64_t h, const int6
 }
 
 int oracle_pixel_of(const double *r) { return pixel_of(r); }
+
+/* hub_pixel for hub h of the four points xyz4 (indices 0..3), its spokes to
+ * the other three in index order: 0 pos, 1 neg, 2 degenerate, <0 error */
+int oracle_hub_pixel_channel(const double *xyz4, double box, double rmin, double rmax, int nbins, int h) {
+    params_t p;
+    if (make_params(&p, box, rmin, rmax, nbins) != OR_OK || h < 0 || h > 3) return OR_EINVAL;
+    int64_t sp[3], idx;
+    int u = 0;
+    for (int o = 0; o < 4; ++o)
+        if (o != h) sp[u++] = o;
+    return hub_pixel(&p, xyz4, h, sp, &idx);
+}
 void oracle_pixel_centre(int pix, double *u) { pixel_centre(pix, u); }
 
 /* t = +-((a1*a2)*a3)*a4 of a 4-clique's weights (magnitudes ascending, the

@@ -825,3 +825,24 @@ def test_pixel_parity_reflection_swaps_channels():
     assert a.n_cliques == b.n_cliques > 0
     assert np.array_equal(a.even, b.even)
     assert np.array_equal(a.pos, b.neg) and np.array_equal(a.neg, b.pos)
+
+
+def test_pixel_threshold_window():
+    """Every volume of three pixel centres is either a rounding residue of an
+    exactly coplanar triple (below 1e-12) or at least 2.3e-5: the 1e-9 rule
+    must make the residues degenerate and keep the smallest true volumes.
+    Pixels 0, 1, 3 share i = 0, so their unnormalised centres (a, (1-a)t,
+    (1-a)(1-t)) all satisfy x(1-a) = a(y+z): a plane through the origin.
+    Pixels 13, 93, 127 span the smallest nonzero volume, |V| = 2.9e-5."""
+    import itertools
+    cen = [oracle.pixel_centre(p) for p in range(256)]
+    o = np.array([50.0, 50.0, 50.0])
+    res = np.array([o, o + 2.0 * cen[0], o + 2.5 * cen[1], o + 3.0 * cen[3]])
+    assert [oracle.pixel_of(res[k] - o) for k in (1, 2, 3)] == [0, 1, 3]
+    assert oracle.hub_pixel_channel(res, 100.0, 0.0, 10.0, 2, 0) == 2
+    small = np.array([o, o + 2.0 * cen[13], o + 2.5 * cen[93], o + 3.0 * cen[127]])
+    assert [oracle.pixel_of(small[k] - o) for k in (1, 2, 3)] == [13, 93, 127]
+    u, v, w = cen[13], cen[93], cen[127]
+    V = ((u[1] * v[2] - u[2] * v[1]) * w[0] + (u[2] * v[0] - u[0] * v[2]) * w[1]) + (u[0] * v[1] - u[1] * v[0]) * w[2]
+    assert 2e-5 < abs(V) < 3e-5
+    assert oracle.hub_pixel_channel(small, 100.0, 0.0, 10.0, 2, 0) == (0 if V > 0 else 1)
