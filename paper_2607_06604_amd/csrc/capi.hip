@@ -394,13 +394,20 @@ int gs_count_3pcf(gs_ctx *ctx, const gs_graph *g, uint64_t *hist, uint64_t *wsum
     });
 }
 
+}  // extern "C"
+
+static void check4(gs_ctx *ctx, const gs_graph *g) {
+    if (!(g->flags & GS_KEEP_COORDS)) fail(GS_ENOCOORDS, "4-clique counts need GS_KEEP_COORDS");
+    if (g->device != ctx->device) fail(GS_EINVAL, "graph and context on different devices");
+}
+
+extern "C" {
+
 int gs_count_4pcf_parity(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos,
                          uint64_t *neg, uint64_t *n_cliques, const gs_anchor_range *anchors) {
     return guarded([&] {
         if (!ctx || !g || !even || !pos || !neg || !n_cliques) fail(GS_EINVAL, "null argument");
-        if (!(g->flags & GS_KEEP_COORDS)) fail(GS_ENOCOORDS, "parity needs GS_KEEP_COORDS");
-        if (g->n_windows > 1) fail(GS_EUNSUPPORTED, "parity counts need a device-resident graph");
-        if (g->device != ctx->device) fail(GS_EINVAL, "graph and context on different devices");
+        check4(ctx, g);
         ctx->use();
         const int64_t nc = n_configs(g->nbins);
         Count4Out o;
@@ -444,12 +451,6 @@ static void add128w(const uint64_t *a, const uint64_t *b, uint64_t *out) {
     const unsigned __int128 z = x + y;
     out[0] = (uint64_t)z;
     out[1] = (uint64_t)(z >> 64);
-}
-
-static void check4(gs_ctx *ctx, const gs_graph *g) {
-    if (!(g->flags & GS_KEEP_COORDS)) fail(GS_ENOCOORDS, "4-clique counts need GS_KEEP_COORDS");
-    if (g->n_windows > 1) fail(GS_EUNSUPPORTED, "4-clique counts need a device-resident graph");
-    if (g->device != ctx->device) fail(GS_EINVAL, "graph and context on different devices");
 }
 
 int gs_count_4pcf_parity_weighted(gs_ctx *ctx, const gs_graph *g, uint64_t *even, uint64_t *pos, uint64_t *neg,

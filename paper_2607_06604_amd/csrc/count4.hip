@@ -62,6 +62,7 @@ struct C4Args {
     int n6;                     // 6-edge configurations
     int lds_cnt;                // counters held in LDS (0: 6-edge counts go to global memory)
     const double *pixdir;       // pixel kind: the 256 pixel centre directions (x, y, z each)
+    uint32_t h0, h1;            // hubs of this launch (a host-tiled graph: one window)
 };
 
 
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     const uint32_t hist_addr = lds_addr(hist);
 
     while (true) {
-        if (tid == 0) *s_hub = next_hub_in(a.queue, 0, a.n, gridDim.x, cursor, 1);
+        if (tid == 0) *s_hub = next_hub_in(a.queue, a.h0, a.h1, gridDim.x, cursor, 1);
         __syncthreads();
         const uint32_t i = *s_hub;
         if (i == kEmptyKey) break;
@@ -1117,7 +1118,9 @@ void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_ra
     GS_HIP(hipMemcpyAsync(dthr, g.bins.t, sizeof(double) * 256, hipMemcpyHostToDevice, s));
     if (pixel) GS_HIP(hipMemcpyAsync(dthr + 256, pixel_dirs(), sizeof(double) * 768, hipMemcpyHostToDevice, s));
     GS_HIP(hipEventRecord(ctx.ev[2], s));
-    if (g.n > 0) {
+    a.h0 = 0;
+    a.h1 = (uint32_t)g.n;
+    auto launch = [&]() {
         const uint32_t lds = L.total;
         if (pixel) {
             if (var == 1) launch4_pixel<1>(ctx, a, lds, anchored);
@@ -1133,6 +1136,52 @@ void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_ra
             if (var == 1) launch4_v<256, kParity4, 1>(ctx, a, lds, anchored, weighted);
             else launch4_v<256, kParity4, 0>(ctx, a, lds, anchored, weighted);
         }
+    };
+    uint64_t launches = 0;
+    if (g.n > 0 && g.n_windows == 1) {
+        launch();
+        launches = 1;
+    } else if (g.n > 0) {
+        // Host-tiled graph: for each hub window, the CSR entries from its
+        // first row through the row of its hubs' largest spoke (every row a
+        // hub or one of its spokes reads) are copied into one device
+        // buffer, and the window's hubs are counted from it. Each clique is
+        // counted at its smallest label, i.e. in exactly one window.
+        const int W = g.n_windows;
+        std::vector<uint64_t> rph((size_t)g.n + 1);
+        GS_HIP(hipMemcpy(rph.data(), g.row_ptr.p, sizeof(uint64_t) * rph.size(), hipMemcpyDeviceToHost));
+        const uint32_t *hc = g.hcol.as<uint32_t>();
+        const uint8_t *hb = g.hbin.as<uint8_t>();
+        std::vector<uint64_t> e0(W), e1(W);
+        uint64_t maxspan = 1;
+        for (int w = 0; w < W; ++w) {
+            uint64_t jmax = g.win[w];
+            for (uint64_t i = g.win[w]; i < g.win[w + 1]; ++i)
+                if (rph[i + 1] > rph[i]) jmax = std::max<uint64_t>(jmax, hc[rph[i + 1] - 1]);
+            e0[w] = rph[g.win[w]];
+            e1[w] = rph[std::max<uint64_t>(jmax, g.win[w + 1] - 1) + 1];
+            maxspan = std::max<uint64_t>(maxspan, e1[w] - e0[w]);
+        }
+        const uint64_t fixed = g.row_ptr.bytes + g.perm.bytes + g.coords.bytes + g.weights.bytes;
+        if (fixed + 5 * (maxspan + kRowSlack) > ctx.budget)
+            fail(GS_EDEVMEM, "a hub window and the rows its hubs read exceed the device budget");
+        DevBuf wc((maxspan + kRowSlack) * 4, ctx.pool), wb(maxspan + kRowSlack, ctx.pool);
+        for (int w = 0; w < W; ++w) {
+            if (g.win[w + 1] <= g.win[w]) continue;
+            const uint64_t ne = e1[w] - e0[w];
+            GS_HIP(hipMemcpyAsync(wc.p, hc + e0[w], ne * 4, hipMemcpyHostToDevice, s));
+            GS_HIP(hipMemcpyAsync(wb.p, hb + e0[w], ne, hipMemcpyHostToDevice, s));
+            // entry e of the graph at buffer position e - e0 (only entries of
+            // [e0, e1) are read)
+            a.col = wc.as<uint32_t>() - e0[w];
+            a.bin = wb.as<uint8_t>() - e0[w];
+            a.h0 = (uint32_t)g.win[w];
+            a.h1 = (uint32_t)g.win[w + 1];
+            k_zero4<<<1, 256, 0, s>>>((unsigned long long *)a.queue, kQueueWords / 2);
+            launch();
+            ++launches;
+        }
+        GS_HIP(hipStreamSynchronize(s));
     }
     GS_HIP(hipEventRecord(ctx.ev[3], s));
     // results straight into the caller's arrays, one block of counters each
@@ -1152,7 +1201,7 @@ void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_ra
     GS_HIP(hipEventElapsedTime(&kms, ctx.ev[2], ctx.ev[3]));
     ctx.t.count_ms = ms;
     ctx.t.kernel_ms = kms;
-    ctx.t.kernel_launches = g.n > 0 ? 1 : 0;
+    ctx.t.kernel_launches = launches;
     ctx.t.alg_bytes = g.stats_ready ? (uint64_t)(2.5 * (double)g.sum_sq_deg) : 0;
 }
 

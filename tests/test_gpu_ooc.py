@@ -91,12 +91,43 @@ def test_budget_cap_forces_tiling(gsn):
     assert np.array_equal(got.hist, ref.hist) and got.n_triangles == ref.n_triangles
 
 
-def test_parity_on_tiled_graph_is_refused(ctx, gsn, monkeypatch):
+@pytest.mark.parametrize("windows", [2, 3, 6])
+def test_four_point_counts_on_tiled_graphs(ctx, monkeypatch, windows):
+    """Parity (plain and weighted), 6-edge and pixel counts on a host-tiled
+    graph: each hub window counted from the CSR range its hubs read, equal to
+    the resident counts and the oracle bit for bit."""
+    x = synth.neyman_scott(12000, 50, 1.2, 70.0, 93)
+    w = synth.uniform_values(len(x), 0.5, 1.0, 94)
+    L, rmax, nb = 70.0, 3.0, 4
+    say("tiled 4-point counts", windows)
+    g = ctx.build_graph(x, L, 0.0, rmax, nb, weights=w, keep_coords=True)
+    res = (ctx.count_4pcf_parity(g, weighted=True), ctx.count_4pcf_full(g), ctx.count_4pcf_pixel(g))
+    g.free()
+    monkeypatch.setenv("GS_WINDOWS", str(windows))
+    gt = ctx.build_graph(x, L, 0.0, rmax, nb, weights=w, keep_coords=True)
+    assert gt.info().n_windows == windows
+    til = (ctx.count_4pcf_parity(gt, weighted=True), ctx.count_4pcf_full(gt), ctx.count_4pcf_pixel(gt),
+           ctx.count_4pcf_parity(gt, anchors=(2000, 7000)))
+    gt.free()
+    for a, b in ((res[0], til[0]), (res[2], til[2])):
+        assert a.n_cliques == b.n_cliques
+        assert np.array_equal(a.even, b.even) and np.array_equal(a.pos, b.pos) and np.array_equal(a.neg, b.neg)
+    for ch in range(3):
+        assert res[0].wsum_int(ch) == til[0].wsum_int(ch)
+    assert np.array_equal(res[1].hist, til[1].hist)
+    ref = oracle.count_4pcf_parity(x, L, 0.0, rmax, nb, weights=w)
+    assert np.array_equal(til[0].even, ref.even) and np.array_equal(til[0].pos, ref.pos)
+    assert til[0].wsum_int(1) == ref.wsum_int(1)
+    refp = oracle.count_4pcf_parity(x, L, 0.0, rmax, nb, anchors=(2000, 7000))
+    assert np.array_equal(til[3].even, refp.even) and np.array_equal(til[3].neg, refp.neg)
+
+
+def test_noalloc_parity_refuses_tiled_graph(ctx, gsn, monkeypatch):
     monkeypatch.setenv("GS_WINDOWS", "2")
-    x = synth.uniform(3000, 20.0, 93)
+    x = synth.uniform(3000, 20.0, 95)
     g = ctx.build_graph(x, 20.0, 0.0, 2.0, 4, keep_coords=True)
     with pytest.raises(gsn.GsError) as e:
-        ctx.count_4pcf_parity(g)
+        ctx.count_4pcf_parity(g, noalloc=True)
     g.free()
     assert e.value.code == gsn.GS_EUNSUPPORTED
 
