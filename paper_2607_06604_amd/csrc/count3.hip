@@ -276,11 +276,11 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk,
     if (WEIGHTED && !WGEN) {
         // positive weights whose triangle terms stay below 2^63: the
         // product of the weights in ascending order as one 64-bit integer
-        double p = c.hw[hub], q = c.mw[slot], r = wk, t;
-        if (p > q) { t = p; p = q; q = t; }
-        if (q > r) { t = q; q = r; r = t; }
-        if (p > q) { t = p; p = q; q = t; }
-        const double prod = __dmul_rn(__dmul_rn(p, q), r);
+        // (ascending by min / max: the smallest, the middle one, the largest)
+        const double p = c.hw[hub], q = c.mw[slot], r = wk;
+        const double pq0 = fmin(p, q), pq1 = fmax(p, q);
+        const double lo = fmin(pq0, r), hi = fmax(pq1, r), mid = fmax(pq0, fmin(pq1, r));
+        const double prod = __dmul_rn(__dmul_rn(lo, mid), hi);
         const unsigned long long ti = (unsigned long long)__dmul_rn(prod, c.wmul);
         if (LDS_HIST) {
             atomicAdd(&c.wlo[idx], ti & 0xFFFFFFFFull);
