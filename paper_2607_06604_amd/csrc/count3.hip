@@ -78,7 +78,8 @@ struct C3Args {
     unsigned long long *wsum;   // 2*nconf (lo, hi)
     unsigned long long *ntri;   // 1
     unsigned long long *probes; // candidates probed (nullable)
-    uint32_t *err;          // bit 0: a hub's spoke rows span too many entries; bit 1: LDS addressing
+    uint32_t *err;          // bit 1: LDS addressing
+    uint64_t wspan;         // WIDE: entries a segment of spoke rows may span from its first row
     const uint16_t *cfg3;   // kLut / kCube: configuration index of ordered triple (x*nb + y)*nb + z
     const uint32_t *tiles;  // hub tiles of about equal cost: tile t = [tiles[t], tiles[t+1]) (or null)
     uint32_t ntiles;
@@ -127,7 +128,7 @@ __host__ __device__ inline Layout3 layout3(int block, uint32_t H, uint32_t maxde
     L.mperm = o;  if (anchored) o = lds_align(o + 4 * block, 16);
     L.rtab = o;   o = lds_align(o + 8 * (nb + 1), 16);
     L.wtot = o;   o = lds_align(o + 8 * (block / 64 + 1), 16);
-    L.misc = o;   o = lds_align(o + 160, 16);
+    L.misc = o;   o = lds_align(o + 176, 16);
     L.hxb = o;    o = lds_align(o + maxdeg, 16);
     L.hbin = o;   if (!packed) o = lds_align(o + H, 16);
     L.total = o;
@@ -498,6 +499,7 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
     // across the loop)
     HubCursor &cursor = *(HubCursor *)(sm + L.misc + 128);
     HubCursor &tcursor = *(HubCursor *)(sm + L.misc + 144);
+    unsigned long long *s_seg = (unsigned long long *)(sm + L.misc + 160);   // WIDE: a segment's first row
     if (tid == 0) {
         cursor = HubCursor();
         tcursor = HubCursor();
@@ -624,17 +626,8 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
         const uint32_t jlo = max(i0 + 1, s0);
         if (D < 2 || jlo >= s1) { __syncthreads(); continue; }
         const uint64_t rb = uniform64(jlo == i0 + 1 ? s_rb[1] : rp[jlo]);
-        if (WIDE) {
-            // a launch with 2^32 or more spoke entries could exceed the
-            // 32-bit entry offsets of one hub (groups are single hubs here)
-            const uint32_t jhi = min(hcol[beg + D - 1], s1 - 1);
-            if (jlo <= jhi && rp[jhi + 1] - rb >= kWideSpan) {
-                if (tid == 0) atomicOr(a.err, 1u);
-                __syncthreads();
-                continue;
-            }
-        }
-        // uniform: the row loads take these as their scalar base
+        // uniform: the row loads take these as their scalar base (a WIDE
+        // launch re-bases them per segment of spokes below)
         c.srow = (gbl_u32 *)uniform64((uint64_t)(scol + (rb - sbase)));
         c.sbrow = (gbl_u8 *)uniform64((uint64_t)(sbinp + (rb - sbase)));
         c.hout = hout;
@@ -674,20 +667,49 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
         // the tile (or of hubs that own no anchored triangle) add nothing
         for (uint32_t c0 = 0; c0 < D; c0 += BLOCK) {
             const uint32_t sidx = c0 + tid;
-            uint32_t len = 0, st = 0, xv = 0, hk = 0;
+            uint32_t len0c = 0, xv = 0, hk = 0;
+            uint64_t rj = 0;   // first entry of the spoke's row
+            bool pending = false;
             if (sidx < D) {
                 hk = (sidx >= ofs1) + (sidx >= ofs2) + (sidx >= ofs3);
                 const uint32_t next = hk == 0 ? ofs1 : hk == 1 ? ofs2 : hk == 2 ? ofs3 : D;
                 const uint32_t j = c0 == 0 ? j0 : hcol[beg + sidx];
                 if (sidx + 1 < next && j >= s0 && j < s1 && (!ANCHORED || s_mk[hk])) {
-                    if (c0 == 0) {
-                        st = st0;
-                        len = len0;
+                    pending = true;
+                    if (c0 == 0 && !WIDE) {
+                        rj = rb + st0;
+                        len0c = len0;
                     } else {
-                        const uint64_t rj = rp[j];
-                        st = (uint32_t)(rj - rb);
-                        len = (uint32_t)(rp[j + 1] - rj);
+                        rj = rp[j];
+                        len0c = (uint32_t)(rp[j + 1] - rj);
                     }
+                    const uint32_t x = hxb[sidx];
+                    xv = a.mode == kCube ? smb + L.cube + 4 * x * (uint32_t)(a.nb * a.nb)
+                         : a.mode == kLut ? smb + L.lut + 2 * x * (uint32_t)(a.nb * a.nb)
+                                          : x;
+                    if (WEIGHTED) mw[tid] = a.w[j];
+                    if (ANCHORED) mperm[tid] = a.perm[j];
+                }
+            }
+            // A WIDE launch addresses spoke rows by 32-bit offsets from a
+            // segment's first row: the chunk's spokes (rows ascending with
+            // the spoke) go in segments whose rows lie within 2^32 entries of
+            // the segment's first row; otherwise one segment based at rb.
+            while (true) {
+                uint64_t base = rb;
+                if (WIDE) {
+                    if (tid == 0) *s_seg = ~0ull;
+                    __syncthreads();
+                    if (pending) atomicMin(s_seg, (unsigned long long)rj);
+                    __syncthreads();
+                    base = uniform64(*s_seg);
+                    c.srow = (gbl_u32 *)uniform64((uint64_t)(scol + (base - sbase)));
+                    c.sbrow = (gbl_u8 *)uniform64((uint64_t)(sbinp + (base - sbase)));
+                }
+                const bool mine = pending && (!WIDE || rj + len0c - base < a.wspan);
+                pending = pending && !mine;
+                uint32_t st = mine ? (uint32_t)(rj - base) : 0u, len = mine ? len0c : 0u;
+                if (mine) {
                     // entries of N+(j) above the largest label of the hub's
                     // row cannot match
                     const uint32_t kmax = s_kmax[hk];
@@ -700,37 +722,32 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
                         }
                         len = lo;
                     }
-                    const uint32_t x = hxb[sidx];
-                    xv = a.mode == kCube ? smb + L.cube + 4 * x * (uint32_t)(a.nb * a.nb)
-                         : a.mode == kLut ? smb + L.lut + 2 * x * (uint32_t)(a.nb * a.nb)
-                                          : x;
-                    if (WEIGHTED) mw[tid] = a.w[j];
-                    if (ANCHORED) mperm[tid] = a.perm[j];
                 }
-            }
-            const uint32_t ns = (len + S - 1) >> glog;
-            // one scan: steps before this spoke (low word), candidates (high);
-            // wtot is next written after a barrier below
-            uint64_t tot64;
-            const uint64_t pre = wg_excl_scan64<BLOCK, false>(((uint64_t)len << 32) | ns, wtot64, tot64);
-            const uint32_t t0 = (uint32_t)pre, T = (uint32_t)tot64;
-            acc += tot64 >> 32;
-            probed += tot64 >> 32;
-            if (T == 0) __syncthreads();   // (the fill barrier guards wtot otherwise)
-            // the table holds tmax steps: fill and walk it as often as needed
-            const uint32_t xhub = WIDE ? 0u : hk << 30;
-            for (uint32_t w0 = 0; w0 < T; w0 += a.tmax) {
-                const uint32_t lo = max(t0, w0), hi = min(t0 + ns, w0 + a.tmax);
-                const uint32_t nfill = min(a.tmax, T - w0);
-                for (uint32_t s = lo; s < hi; ++s) {
-                    const uint32_t r = (s - t0) << glog;
-                    const uint32_t cnt = min(S, len - r);
-                    tab[s - w0] = make_uint2((st + r) | xhub, cnt | ((uint32_t)tid << 7) | (xv << 16));
+                const uint32_t ns = (len + S - 1) >> glog;
+                // one scan: steps before this spoke (low word), candidates (high);
+                // wtot is next written after a barrier below
+                uint64_t tot64;
+                const uint64_t pre = wg_excl_scan64<BLOCK, false>(((uint64_t)len << 32) | ns, wtot64, tot64);
+                const uint32_t t0 = (uint32_t)pre, T = (uint32_t)tot64;
+                acc += tot64 >> 32;
+                probed += tot64 >> 32;
+                if (T == 0) __syncthreads();   // (the fill barrier guards wtot otherwise)
+                // the table holds tmax steps: fill and walk it as often as needed
+                const uint32_t xhub = WIDE ? 0u : hk << 30;
+                for (uint32_t w0 = 0; w0 < T; w0 += a.tmax) {
+                    const uint32_t lo = max(t0, w0), hi = min(t0 + ns, w0 + a.tmax);
+                    const uint32_t nfill = min(a.tmax, T - w0);
+                    for (uint32_t s = lo; s < hi; ++s) {
+                        const uint32_t r = (s - t0) << glog;
+                        const uint32_t cnt = min(S, len - r);
+                        tab[s - w0] = make_uint2((st + r) | xhub, cnt | ((uint32_t)tid << 7) | (xv << 16));
+                    }
+                    for (uint32_t s = tid; s < kUnroll3 * (BLOCK >> glog); s += BLOCK) tab[nfill + s] = make_uint2(0u, 0u);
+                    __syncthreads();
+                    walk3_any<BLOCK, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(a.packed, a.mode, c, nfill, mytri);
+                    __syncthreads();
                 }
-                for (uint32_t s = tid; s < kUnroll3 * (BLOCK >> glog); s += BLOCK) tab[nfill + s] = make_uint2(0u, 0u);
-                __syncthreads();
-                walk3_any<BLOCK, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(a.packed, a.mode, c, nfill, mytri);
-                __syncthreads();
+                if (!WIDE || !__syncthreads_or(pending)) break;
             }
         }
         // the barrier at the top of the loop orders this before the next
@@ -1325,6 +1342,11 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     a.wsum = dv + nconf;
     a.ntri = dv + 3 * (size_t)nconf;
     a.err = (uint32_t *)(dv + 3 * (size_t)nconf + 1);
+    // spoke-row segments of a WIDE launch: 2^32 entries (GS_WIDE_SPAN shrinks
+    // it for tests; a segment always holds at least one whole row)
+    a.wspan = kWideSpan;
+    if (const char *es = getenv("GS_WIDE_SPAN")) a.wspan = std::max<uint64_t>(strtoull(es, nullptr, 10), 1);
+    a.wspan = std::min<uint64_t>(kWideSpan, std::max<uint64_t>(a.wspan, (uint64_t)maxdeg + 1));
     a.probes = dv + 3 * (size_t)nconf + 2;
     a.cfg3 = (const uint16_t *)(dv + coff);
     uint32_t *queues = (uint32_t *)(dv + qoff);
@@ -1463,8 +1485,6 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     GS_HIP(hipMemcpyAsync(h.data(), dv, h.size() * 8, hipMemcpyDeviceToHost, s));
     GS_HIP(hipEventRecord(ctx.ev[1], s));
     GS_HIP(hipStreamSynchronize(s));
-    if (h[3 * (size_t)nconf + 1] & 1)
-        fail(GS_EUNSUPPORTED, "the spoke rows of a hub span 2^32 or more entries");
     if (h[3 * (size_t)nconf + 1] & 2) fail(GS_EUNSUPPORTED, "configuration table beyond 16-bit LDS addresses");
     for (int c = 0; c < nconf; ++c) hist[c] = h[c];
     if (weighted)

@@ -211,6 +211,15 @@ __device__ __forceinline__ int hub_fast(double qP, double qQ, double qR, const S
     return deg ? 2 : (pos ? 0 : 1);
 }
 
+// A hub whose volume test is known to pass: degenerate only on an exact
+// length tie, else the channel of the predicted sign (as hub_fast).
+__device__ __forceinline__ int hub_sign(double qP, double qQ, double qR, double Vc, bool sign0) {
+    const bool tie = (qP == qQ) | (qP == qR) | (qQ == qR);
+    const bool odd = (qP > qQ) ^ (qP > qR) ^ (qQ > qR);
+    const bool pos = (Vc > 0.0) ^ odd ^ !sign0;
+    return tie ? 2 : (pos ? 0 : 1);
+}
+
 // Per-hub LDS state the clique evaluation reads.
 struct Stage4 {
     const double *px, *py, *pz;   // absolute coordinates of N+(i)
@@ -361,13 +370,27 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr,
     sh.x2 = __dmul_rn(x, x);
     sh.y2 = __dmul_rn(y, y);
     int ch[4];
-    bool e0, e1, e2, e3;
-    ch[0] = hub_fast(qa, qb, qc, sh, true, e0);
-    ch[1] = hub_fast(qa, qab, qac, sh, false, e1);
-    ch[2] = hub_fast(qb, qab, qbc, sh, true, e2);
-    ch[3] = hub_fast(qc, qac, qbc, sh, false, e3);
-    const uint32_t mask = (uint32_t)e0 | ((uint32_t)e1 << 1) | ((uint32_t)e2 << 2) | ((uint32_t)e3 << 3);
-    if (mask) exact_hubs(S, va, vb, vc, wrap, mask, ch);
+    // Every hub's limit fl(1e-18 ((q0 q1) q2)) is at most fl(1e-18 ((m m) m)),
+    // m the largest of the six squared lengths (rounding is monotone), so
+    // when (|Vc| - eb)^2 exceeds that bound no hub is degenerate by volume
+    // and only exact length ties decide (the usual case: a clique far from
+    // coplanar); otherwise each hub is decided on its own limit.
+    const double qm = fmax(fmax(fmax(qa, qb), fmax(qc, qab)), fmax(qac, qbc));
+    const double limmax = __dmul_rn(1e-18, __dmul_rn(__dmul_rn(qm, qm), qm));
+    if (sh.xpos && sh.x2 > limmax) {
+        ch[0] = hub_sign(qa, qb, qc, Vc, true);
+        ch[1] = hub_sign(qa, qab, qac, Vc, false);
+        ch[2] = hub_sign(qb, qab, qbc, Vc, true);
+        ch[3] = hub_sign(qc, qac, qbc, Vc, false);
+    } else {
+        bool e0, e1, e2, e3;
+        ch[0] = hub_fast(qa, qb, qc, sh, true, e0);
+        ch[1] = hub_fast(qa, qab, qac, sh, false, e1);
+        ch[2] = hub_fast(qb, qab, qbc, sh, true, e2);
+        ch[3] = hub_fast(qc, qac, qbc, sh, false, e3);
+        const uint32_t mask = (uint32_t)e0 | ((uint32_t)e1 << 1) | ((uint32_t)e2 << 2) | ((uint32_t)e3 << 3);
+        if (mask) exact_hubs(S, va, vb, vc, wrap, mask, ch);
+    }
     const uint32_t blk = 4u * (uint32_t)S.nconf;
     const uint32_t a0 = conf_addr<LUT>(S, hist_addr, ba, bb, bc) + blk * (uint32_t)ch[0];
     const uint32_t a1 = conf_addr<LUT>(S, hist_addr, ba, bab, bac) + blk * (uint32_t)ch[1];

@@ -272,6 +272,11 @@ KERNEL_PLANS = [
     {"GS_BLOCK3": "256", "GS_GLOG": "3", "GS_PACK": "0", "GS_MODE3": "lut", "GS_TRUNC": "0"},
     {"GS_BLOCK3": "256", "GS_GLOG": "3", "GS_WIDE": "1"},
     {"GS_BLOCK3": "512", "GS_GLOG": "5", "GS_WIDE": "1", "GS_PACK": "0", "GS_TRUNC": "1"},
+    # 64-bit addressing with spoke-row segments of at most 3000 entries from
+    # their first row: a hub's spokes go in several segments (as rows more
+    # than 2^32 entries apart do at full size)
+    {"GS_BLOCK3": "256", "GS_GLOG": "4", "GS_WIDE": "1", "GS_WIDE_SPAN": "3000"},
+    {"GS_BLOCK3": "512", "GS_GLOG": "6", "GS_WIDE": "1", "GS_WIDE_SPAN": "1", "GS_TRUNC": "0"},
 ]
 
 
