@@ -277,11 +277,13 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk,
     if (WEIGHTED && !WGEN) {
         // positive weights whose triangle terms stay below 2^63: the
         // product of the weights in ascending order as one 64-bit integer
-        // (ascending by min / max: the smallest, the middle one, the largest)
-        const double p = c.hw[hub], q = c.mw[slot], r = wk;
-        const double pq0 = fmin(p, q), pq1 = fmax(p, q);
-        const double lo = fmin(pq0, r), hi = fmax(pq1, r), mid = fmax(pq0, fmin(pq1, r));
-        const double prod = __dmul_rn(__dmul_rn(lo, mid), hi);
+        // (compare-and-swap: 32-bit selects, cheaper than float64 min / max
+        // with their canonicalisations)
+        double p = c.hw[hub], q = c.mw[slot], r = wk, t;
+        if (p > q) { t = p; p = q; q = t; }
+        if (q > r) { t = q; q = r; r = t; }
+        if (p > q) { t = p; p = q; q = t; }
+        const double prod = __dmul_rn(__dmul_rn(p, q), r);
         const unsigned long long ti = (unsigned long long)__dmul_rn(prod, c.wmul);
         if (LDS_HIST) {
             atomicAdd(&c.wlo[idx], ti & 0xFFFFFFFFull);
@@ -691,13 +693,15 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
                     if (ANCHORED) mperm[tid] = a.perm[j];
                 }
             }
-            // A WIDE launch addresses spoke rows by 32-bit offsets from a
-            // segment's first row: the chunk's spokes (rows ascending with
-            // the spoke) go in segments whose rows lie within 2^32 entries of
-            // the segment's first row; otherwise one segment based at rb.
+            // A WIDE launch addresses rows by 32-bit offsets: a chunk whose
+            // rows all lie within the segment span of the hub's first spoke
+            // row runs from it in one pass; otherwise (seg) the chunk's
+            // spokes (rows ascending with the spoke) go in segments based at
+            // the first row of each.
+            const bool seg = WIDE && __syncthreads_or(pending && rj + len0c - rb >= a.wspan);
+            uint64_t base = rb;
             while (true) {
-                uint64_t base = rb;
-                if (WIDE) {
+                if (seg) {
                     if (tid == 0) *s_seg = ~0ull;
                     __syncthreads();
                     if (pending) atomicMin(s_seg, (unsigned long long)rj);
@@ -706,7 +710,7 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
                     c.srow = (gbl_u32 *)uniform64((uint64_t)(scol + (base - sbase)));
                     c.sbrow = (gbl_u8 *)uniform64((uint64_t)(sbinp + (base - sbase)));
                 }
-                const bool mine = pending && (!WIDE || rj + len0c - base < a.wspan);
+                const bool mine = pending && (!seg || rj + len0c - base < a.wspan);
                 pending = pending && !mine;
                 uint32_t st = mine ? (uint32_t)(rj - base) : 0u, len = mine ? len0c : 0u;
                 if (mine) {
@@ -724,8 +728,8 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
                     }
                 }
                 const uint32_t ns = (len + S - 1) >> glog;
-                // one scan: steps before this spoke (low word), candidates (high);
-                // wtot is next written after a barrier below
+                // one scan: steps before this spoke (low word), candidates
+                // (high); wtot is next written after a barrier below
                 uint64_t tot64;
                 const uint64_t pre = wg_excl_scan64<BLOCK, false>(((uint64_t)len << 32) | ns, wtot64, tot64);
                 const uint32_t t0 = (uint32_t)pre, T = (uint32_t)tot64;
@@ -747,7 +751,12 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
                     walk3_any<BLOCK, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(a.packed, a.mode, c, nfill, mytri);
                     __syncthreads();
                 }
-                if (!WIDE || !__syncthreads_or(pending)) break;
+                if (!seg || !__syncthreads_or(pending)) break;
+            }
+            if (seg) {
+                // the following chunks' rows are addressed from rb again
+                c.srow = (gbl_u32 *)uniform64((uint64_t)(scol + (rb - sbase)));
+                c.sbrow = (gbl_u8 *)uniform64((uint64_t)(sbinp + (rb - sbase)));
             }
         }
         // the barrier at the top of the loop orders this before the next
