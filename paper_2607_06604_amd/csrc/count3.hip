@@ -434,7 +434,10 @@ __device__ __forceinline__ void walk3_any(bool packed, int mode, const Walk &c, 
 }
 
 // Plain unbatched counts fit 64 VGPRs: eight wavefronts per SIMD.
-template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool BATCH, bool WIDE>
+// SEG (with WIDE): a hub's spoke rows may lie more than the segment span
+// apart (graphs of 2^32 or more forward entries), so chunks whose rows spread
+// that far go in segments.
+template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool BATCH, bool WIDE, bool SEG = false>
 __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count3(C3Args a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const uint32_t H = 1u << a.log2h, mask = H - 1;
@@ -698,7 +701,7 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
             // row runs from it in one pass; otherwise (seg) the chunk's
             // spokes (rows ascending with the spoke) go in segments based at
             // the first row of each.
-            const bool seg = WIDE && __syncthreads_or(pending && rj + len0c - rb >= a.wspan);
+            const bool seg = SEG && WIDE && __syncthreads_or(pending && rj + len0c - rb >= a.wspan);
             uint64_t base = rb;
             while (true) {
                 if (seg) {
@@ -892,33 +895,33 @@ __global__ void k_zero_u64(unsigned long long *p, uint64_t n) {
         p[i] = 0;
 }
 
-template <int B, bool W, bool A, bool LH, bool BATCH = false, bool WIDE = false>
+template <int B, bool W, bool A, bool LH, bool BATCH = false, bool WIDE = false, bool SEG = false>
 void launch3(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds) {
-    const void *kern = reinterpret_cast<const void *>(&k_count3<B, W, A, LH, BATCH, WIDE>);
+    const void *kern = reinterpret_cast<const void *>(&k_count3<B, W, A, LH, BATCH, WIDE, SEG>);
     if (lds > 65536)
         GS_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
-    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count3<B, W, A, LH, BATCH, WIDE>, B, lds));
+    GS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count3<B, W, A, LH, BATCH, WIDE, SEG>, B, lds));
     if (per_cu < 1) fail(GS_EUNSUPPORTED, "count kernel does not fit a compute unit");
     uint32_t grid = (uint32_t)ctx.n_cu * (uint32_t)per_cu;
     grid = (grid + kNumQueues - 1) / kNumQueues * kNumQueues;
     if (getenv("GS_PLAN_LOG")) fprintf(stderr, "count3 launch: %d groups per CU, grid %u\n", per_cu, grid);
-    k_count3<B, W, A, LH, BATCH, WIDE><<<dim3(grid), dim3(B), lds, s>>>(a);
+    k_count3<B, W, A, LH, BATCH, WIDE, SEG><<<dim3(grid), dim3(B), lds, s>>>(a);
     GS_HIP(hipGetLastError());
 }
 
-template <int B, bool WIDE>
+template <int B, bool WIDE, bool SEG = false>
 void launch3_bw(Ctx &ctx, hipStream_t s, const C3Args &a, uint32_t lds, bool w, bool an, bool lh) {
     if (lh) {
-        if (!w && !an) launch3<B, false, false, true, false, WIDE>(ctx, s, a, lds);
-        else if (w && !an) launch3<B, true, false, true, false, WIDE>(ctx, s, a, lds);
-        else if (!w && an) launch3<B, false, true, true, false, WIDE>(ctx, s, a, lds);
-        else launch3<B, true, true, true, false, WIDE>(ctx, s, a, lds);
+        if (!w && !an) launch3<B, false, false, true, false, WIDE, SEG>(ctx, s, a, lds);
+        else if (w && !an) launch3<B, true, false, true, false, WIDE, SEG>(ctx, s, a, lds);
+        else if (!w && an) launch3<B, false, true, true, false, WIDE, SEG>(ctx, s, a, lds);
+        else launch3<B, true, true, true, false, WIDE, SEG>(ctx, s, a, lds);
     } else {
-        if (!w && !an) launch3<B, false, false, false, false, WIDE>(ctx, s, a, lds);
-        else if (w && !an) launch3<B, true, false, false, false, WIDE>(ctx, s, a, lds);
-        else if (!w && an) launch3<B, false, true, false, false, WIDE>(ctx, s, a, lds);
-        else launch3<B, true, true, false, false, WIDE>(ctx, s, a, lds);
+        if (!w && !an) launch3<B, false, false, false, false, WIDE, SEG>(ctx, s, a, lds);
+        else if (w && !an) launch3<B, true, false, false, false, WIDE, SEG>(ctx, s, a, lds);
+        else if (!w && an) launch3<B, false, true, false, false, WIDE, SEG>(ctx, s, a, lds);
+        else launch3<B, true, true, false, false, WIDE, SEG>(ctx, s, a, lds);
     }
 }
 
@@ -1049,8 +1052,13 @@ void set_groups(C3Args &a, const Plan3 &P, int nb, bool wide, const Tune3 &tune)
     a.group_cap = std::min<uint64_t>(a.maxdeg, (uint64_t)P.block);
 }
 
-void launch3_any(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P, bool w, bool an, bool wide) {
-    if (wide) {
+void launch3_any(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P, bool w, bool an, bool wide,
+                 bool seg = false) {
+    if (wide && seg) {
+        if (P.block == 512) launch3_bw<512, true, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
+        else if (P.block == 128) launch3_bw<128, true, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
+        else launch3_bw<256, true, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
+    } else if (wide) {
         if (P.block == 512) launch3_bw<512, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
         else if (P.block == 128) launch3_bw<128, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
         else launch3_bw<256, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
@@ -1396,7 +1404,10 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
         }
         const bool wide = wide_rows(g.n_edges);
         set_groups(a, P, nb, wide, tune);
-        launch3_any(ctx, s, a, P, weighted, anchored, wide);
+        // spoke rows of one hub can lie 2^32 entries apart only in graphs
+        // that large (GS_WIDE_SPAN forces segments, for tests)
+        const bool seg = wide && (g.n_edges >= kWideSpan || getenv("GS_WIDE_SPAN") != nullptr);
+        launch3_any(ctx, s, a, P, weighted, anchored, wide, seg);
     } else if (g.n > 0) {
         // host-tiled graph: spoke window S resident, hub windows H <= S
         // streamed through; copies of the next tile's windows overlap the
