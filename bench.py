@@ -90,20 +90,16 @@ def percentile(v, q):
     return float(np.percentile(np.asarray(v, dtype=float), q))
 
 
-def plan_table(info, schedule):
-    """Hash table size and its typical keys for a graph under a schedule:
-    slots 2^k >= 2 maxdeg (load 1/2) or >= maxdeg / 0.7; a group of up to
+def plan_table(info, t):
+    """Hash table size and its typical keys for a graph under the schedule
+    its last count ran with (from the library's timings): a group of up to
     `group` hubs holds about group x mean forward degree keys, at most
-    min(maxdeg, block)."""
+    min(maxdeg, block) and the table's load bound."""
     maxdeg = max(1, int(info.max_deg))
     mean = info.n_edges / max(1, info.n)
-    hl = schedule.get("hash_load", 5) if schedule else 5
-    block = schedule.get("block", 512 if maxdeg >= 1024 else 256) if schedule else (512 if maxdeg >= 1024 else 256)
-    group = schedule.get("group", 4) if schedule else 4
-    log2h = 6
-    while (1 << log2h) < (2 * maxdeg if hl == 5 else maxdeg / 0.7):
-        log2h += 1
-    keys = int(min(group * mean, min(maxdeg, block), 0.69 * (1 << log2h)))
+    log2h, block, group = int(t.table_log2), int(t.block), max(1, int(t.group))
+    load = 0.5 if t.hash_load == 5 else 0.69
+    keys = int(min(group * mean, min(maxdeg, block), load * (1 << log2h)))
     return log2h, max(1, keys), block
 
 
@@ -218,7 +214,7 @@ def run_workload(gsn, ctx, name, steps, warmup, tune=True, windows=0, with_cpu=T
         probes_per_count = probes // steps
         achieved = probes_per_count / (count_kernel_ms / 1e3) / 1e9 if count_kernel_ms > 0 else 0.0
         hit = tuples / max(1, probes_per_count)
-        log2h, keys, block = plan_table(info, schedule)
+        log2h, keys, block = plan_table(info, t)
         weighted = kind == "w3pcf"
         peak = ctx.ceiling_probe(w.nbins, log2h, keys, min(1.0, max(1e-6, hit)), weighted=weighted,
                                  probe=True, block=block) / 1e9

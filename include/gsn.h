@@ -101,6 +101,12 @@ typedef struct {
     uint64_t probes;         /* last triangle count: candidates its hash probes
                                 tested (spoke-row entries up to the hub row's
                                 largest label)                                    */
+    int32_t table_log2;      /* last triangle count's schedule: hub hash table of
+                                2^table_log2 slots,                               */
+    int32_t block;           /* threads per work group,                           */
+    int32_t group;           /* hubs counted together (at most),                  */
+    int32_t hash_load;       /* load bound (5: 1/2, 7: 0.7); all 0 before the first
+                                triangle count                                    */
 } gs_timings;
 
 /* Create a context on HIP device `device`. hbm_budget_bytes = 0 means 90% of

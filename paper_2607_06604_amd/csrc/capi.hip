@@ -606,6 +606,10 @@ int gs_get_timings(const gs_ctx *ctx, gs_timings *out) {
     out->kernel_launches = ctx->t.kernel_launches;
     out->alg_bytes = ctx->t.alg_bytes;
     out->probes = ctx->t.probes;
+    out->table_log2 = ctx->t.table_log2;
+    out->block = ctx->t.block;
+    out->group = ctx->t.group;
+    out->hash_load = ctx->t.hash_load;
     return GS_OK;
 }
 

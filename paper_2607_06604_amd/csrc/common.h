@@ -135,6 +135,7 @@ struct HostBuf {
 struct Timings {
     double build_ms = 0, count_ms = 0, kernel_ms = 0;
     uint64_t kernel_launches = 0, alg_bytes = 0, probes = 0;
+    int32_t table_log2 = 0, block = 0, group = 0, hash_load = 0;   // last triangle count's plan
 };
 
 struct Server;

@@ -1320,6 +1320,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     const Plan3 P = plan3(ctx, maxdeg, nb, weighted, anchored, (uint64_t)g.n, mean_row, tune);
     const int W = g.n_windows;
     const int ntiles = W * (W + 1) / 2;
+    int kused = 1;          // hubs per group of the launches (reported in the timings)
 
     // device staging: hist | wsum | ntri | error word | probes | queue sets,
     // one per tile (256-byte aligned)
@@ -1404,6 +1405,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
         }
         const bool wide = wide_rows(g.n_edges);
         set_groups(a, P, nb, wide, tune);
+        kused = a.kmax;
         // spoke rows of one hub can lie 2^32 entries apart only in graphs
         // that large (GS_WIDE_SPAN forces segments, for tests)
         const bool seg = wide && (g.n_edges >= kWideSpan || getenv("GS_WIDE_SPAN") != nullptr);
@@ -1487,6 +1489,7 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
             }
             const bool wide = wide_rows(maxE);
             set_groups(b, P, nb, wide, tune);
+            kused = b.kmax;
             launch3_any(ctx, s, b, P, weighted, anchored, wide);
             if (t.hslot >= 0) GS_HIP(hipEventRecord(ev_hfree[t.hslot], s));
             if (t.last_of_S) GS_HIP(hipEventRecord(ev_sfree[sk], s));
@@ -1517,6 +1520,10 @@ void count3_run(Ctx &ctx, const Graph &g, uint64_t *hist, uint64_t *wsum, uint64
     ctx.t.kernel_ms = kms;
     ctx.t.kernel_launches = g.n > 0 ? (uint64_t)ntiles : 0;
     ctx.t.probes = h[3 * (size_t)nconf + 2];
+    ctx.t.table_log2 = P.log2h;
+    ctx.t.block = P.block;
+    ctx.t.group = kused;
+    ctx.t.hash_load = P.hload;
     // merge-walk bytes: each hub-spoke step reads both forward half-lists,
     // 5 bytes per entry: 2.5 B x sum_i m_i^2 over full degrees m_i
     ctx.t.alg_bytes = g.stats_ready ? (uint64_t)(2.5 * (double)g.sum_sq_deg) : 0;

@@ -85,7 +85,9 @@ class GraphStats(ctypes.Structure):
 class Timings(ctypes.Structure):
     _fields_ = [("build_ms", ctypes.c_double), ("count_ms", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_uint64),
-                ("alg_bytes", ctypes.c_uint64), ("probes", ctypes.c_uint64)]
+                ("alg_bytes", ctypes.c_uint64), ("probes", ctypes.c_uint64),
+                ("table_log2", ctypes.c_int32), ("block", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("hash_load", ctypes.c_int32)]
 
 
 class Plan3(ctypes.Structure):
