@@ -49,7 +49,8 @@ struct C4Args {
     double L, half;
     double in_lo, in_hi;   // hubs with every coordinate in [in_lo, in_hi] see no wrapped pair
     double eb_in, eb_wrap; // margins on the shared triple product (interior hubs, the others)
-    double tk[16];         // t_1 .. t_15 (bins of up to 16 counted against them directly)
+    float bg_inv, bg_c;    // bin estimate of a squared separation q: sqrt(q) bg_inv - bg_c
+    int bguess;            // that estimate is within one bin (else a search of the thresholds)
     uint32_t anchor_lo, anchor_hi;
     uint64_t flush_limit;
     uint32_t *queue;
@@ -71,7 +72,14 @@ struct Layout4 {
         hist, tab, lut, thr, wtot, misc, pw, wlo, whi, tab6, tabp, total;
 };
 
-constexpr int kLut4MaxBins = 16;   // nb^3 u16 counter addresses up to 8 KB
+constexpr int kLut4MaxBins = 16;   // u16 counter offsets of the ordered bin triples, up to 8 KB
+
+// Bits per bin in the ordered-triple table's index (x << 2s | y << s | z).
+__host__ __device__ inline int lut_shift(int nb) {
+    int s = 0;
+    while ((1 << s) < nb) ++s;
+    return s;
+}
 
 constexpr int kQueue4 = 128;   // clique ring entries per wavefront
 
@@ -110,7 +118,7 @@ __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxde
     L.tabp = o;    if (kind == kPixel4) o = lds_align(o + 8 * 3 * 256, 16);
     L.hist = o;    o = lds_align(o + 4 * ncnt, 16);
     L.tab = o;     o = lds_align(o + 8 * (nb + 1), 16);
-    L.lut = o;     if (spokes && nb <= kLut4MaxBins) o = lds_align(o + 2 * nb * nb * nb, 16);
+    L.lut = o;     if (spokes && nb <= kLut4MaxBins) o = lds_align(o + (2u << (3 * lut_shift(nb))), 16);
     L.tab6 = o;    o = lds_align(o + 2 * tab6, 16);
     L.hloc = o;    o = lds_align(o + 2 * H, 16);
     L.hslot = o;   o = lds_align(o + 2 * d, 16);
@@ -212,12 +220,13 @@ __device__ __forceinline__ int hub_fast(double qP, double qQ, double qR, const S
 }
 
 // A hub whose volume test is known to pass: degenerate only on an exact
-// length tie, else the channel of the predicted sign (as hub_fast).
-__device__ __forceinline__ int hub_sign(double qP, double qQ, double qR, double Vc, bool sign0) {
+// length tie, else the channel of the predicted sign (as hub_fast); returned
+// as the channel's counter block offset (0, blk or 2 blk bytes).
+__device__ __forceinline__ uint32_t hub_sign(double qP, double qQ, double qR, double Vc, bool sign0, uint32_t blk) {
     const bool tie = (qP == qQ) | (qP == qR) | (qQ == qR);
     const bool odd = (qP > qQ) ^ (qP > qR) ^ (qQ > qR);
     const bool pos = (Vc > 0.0) ^ odd ^ !sign0;
-    return tie ? 2 : (pos ? 0 : 1);
+    return tie ? 2 * blk : (pos ? 0u : blk);
 }
 
 // Per-hub LDS state the clique evaluation reads.
@@ -228,11 +237,14 @@ struct Stage4 {
     const uint8_t *pb;            // spoke bins
     const double *thr;            // t_0 .. t_nb
     const int *ta, *tb;           // configuration rank tables
-    const uint16_t *lut;          // nb <= 16: configuration of ordered bin triple (x*nb + y)*nb + z
+    const uint16_t *lut;          // nb <= 16: counter byte offset of ordered bin triple x << 2s | y << s | z
     uint32_t *hist;               // pos | neg | degenerate counters (parity), 6-edge counters
     int nb, nconf;
     double L, half;
-    const double *tk;             // t_1 .. t_15 in the kernel arguments (nb <= 16)
+    float bg_inv, bg_c, bg_top;   // bin estimate (edge_bin); bg_top = nb - 1
+    int bguess;
+    int lsh;                      // s of the ordered-triple table
+    double limR;                  // fl(1e-18 ((t_nb t_nb) t_nb)): no hub's volume limit exceeds it
     const double *pw;             // weights of N+(i) (weighted)
     double wmul;
     unsigned long long *wlo, *whi;  // LDS sums of the terms' low 32 bits / high parts
@@ -242,6 +254,26 @@ struct Stage4 {
     const double *pdir;           // pixel kind: centre directions in LDS (768 doubles)
     const uint32_t *pperm;        // original indices of N+(i)
 };
+
+// Bin of the squared separation q of a graph edge (t_0 <= q < t_nb): the
+// number of thresholds t_1..t_{nb-1} at most q. With linear bins in r
+// (e_k = rmin + k D) the float32 estimate u = sqrt(q)/D - rmin/D lies within
+// (rmax/D) 1.5 2^-22 + 2^-16 of the exact (r - rmin)/D: float32 rounding of
+// q (2^-25 on the root), the square root (one ulp, 2^-23), 1/D and rmin/D
+// (2^-24 each) and the fused step (2^-24 of |u| <= 256). Where
+// nb rmax / (rmax - rmin) <= 2^20 (bguess) that is below 0.4 bin, so floor(u)
+// clamped to [0, nb) is within one bin of the answer and a single float64
+// comparison with each neighbouring threshold settles it (t_0 <= q and
+// q < t_nb make the ends safe). Otherwise a binary search of the thresholds.
+__device__ __forceinline__ int edge_bin(const Stage4 &S, double q) {
+    if (S.bguess) {
+        const float r = __builtin_amdgcn_sqrtf((float)q);
+        const float u = __builtin_amdgcn_fmed3f(__builtin_fmaf(r, S.bg_inv, -S.bg_c), 0.0f, S.bg_top);
+        const int g = (int)u;
+        return g + (int)(q >= S.thr[g + 1]) - (int)(q < S.thr[g]);
+    }
+    return bin_of(S.thr, S.nb, q);
+}
 
 // A clique's weight term in units of 2^-s: the four magnitudes in ascending
 // order multiplied left to right, times 2^s (an integer); neg: the product
@@ -316,7 +348,9 @@ __device__ __forceinline__ void exact_hubs(const Stage4 &S, uint32_t va, uint32_
 // pos block; the neg and degenerate blocks follow at 4 nconf bytes each.
 template <bool LUT>
 __device__ __forceinline__ uint32_t conf_addr(const Stage4 &S, uint32_t hist_addr, int x, int y, int z) {
-    if (LUT) return hist_addr + 4u * (uint32_t)S.lut[((uint32_t)x * (uint32_t)S.nb + (uint32_t)y) * (uint32_t)S.nb + (uint32_t)z];
+    if (LUT)
+        return hist_addr +
+               (uint32_t)S.lut[((uint32_t)x << (2 * S.lsh)) | ((uint32_t)y << S.lsh) | (uint32_t)z];
     const int b0 = min(min(x, y), z), b2 = max(max(x, y), z);
     const int b1 = x + y + z - b0 - b2;
     return hist_addr + 4u * (uint32_t)(S.ta[b0] + S.tb[b1] + b2);
@@ -345,23 +379,7 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr,
         const P3 ic{S.sx[vc], S.sy[vc], S.sz[vc]};
         Vc = triple(ia, ib, ic);
     }
-    int bab, bac, bbc;
-    if (S.nb <= 16) {
-        // the bin is the number of thresholds t_1..t_{nb-1} at most q
-        bab = bac = bbc = 0;
-#pragma unroll
-        for (int k = 0; k < 15; ++k)
-            if (k + 1 < S.nb) {
-                const double t = S.tk[k];
-                bab += qab >= t;
-                bac += qac >= t;
-                bbc += qbc >= t;
-            }
-    } else {
-        bab = bin_of(S.thr, S.nb, qab);
-        bac = bin_of(S.thr, S.nb, qac);
-        bbc = bin_of(S.thr, S.nb, qbc);
-    }
+    const int bab = edge_bin(S, qab), bac = edge_bin(S, qac), bbc = edge_bin(S, qbc);
     Shared4 sh;
     sh.Vc = Vc;
     const double A = fabs(Vc);
@@ -369,20 +387,21 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr,
     sh.xpos = x > 0.0;
     sh.x2 = __dmul_rn(x, x);
     sh.y2 = __dmul_rn(y, y);
-    int ch[4];
-    // Every hub's limit fl(1e-18 ((q0 q1) q2)) is at most fl(1e-18 ((m m) m)),
-    // m the largest of the six squared lengths (rounding is monotone), so
-    // when (|Vc| - eb)^2 exceeds that bound no hub is degenerate by volume
-    // and only exact length ties decide (the usual case: a clique far from
-    // coplanar); otherwise each hub is decided on its own limit.
-    const double qm = fmax(fmax(fmax(qa, qb), fmax(qc, qab)), fmax(qac, qbc));
-    const double limmax = __dmul_rn(1e-18, __dmul_rn(__dmul_rn(qm, qm), qm));
-    if (sh.xpos && sh.x2 > limmax) {
-        ch[0] = hub_sign(qa, qb, qc, Vc, true);
-        ch[1] = hub_sign(qa, qab, qac, Vc, false);
-        ch[2] = hub_sign(qb, qab, qbc, Vc, true);
-        ch[3] = hub_sign(qc, qac, qbc, Vc, false);
+    // Every hub's limit fl(1e-18 ((q0 q1) q2)) is at most limR, formed the
+    // same way from t_nb (rounding is monotone, and all six pairs of a
+    // clique are graph edges, so every squared length is below t_nb): when
+    // (|Vc| - eb)^2 exceeds it no hub is degenerate by volume and only exact
+    // length ties decide (the usual case: a clique far from coplanar);
+    // otherwise each hub is decided on its own limit.
+    const uint32_t blk = 4u * (uint32_t)S.nconf;
+    uint32_t o0, o1, o2, o3;   // counter block offsets of the four hubs' channels
+    if (sh.xpos && sh.x2 > S.limR) {
+        o0 = hub_sign(qa, qb, qc, Vc, true, blk);
+        o1 = hub_sign(qa, qab, qac, Vc, false, blk);
+        o2 = hub_sign(qb, qab, qbc, Vc, true, blk);
+        o3 = hub_sign(qc, qac, qbc, Vc, false, blk);
     } else {
+        int ch[4];
         bool e0, e1, e2, e3;
         ch[0] = hub_fast(qa, qb, qc, sh, true, e0);
         ch[1] = hub_fast(qa, qab, qac, sh, false, e1);
@@ -390,12 +409,15 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr,
         ch[3] = hub_fast(qc, qac, qbc, sh, false, e3);
         const uint32_t mask = (uint32_t)e0 | ((uint32_t)e1 << 1) | ((uint32_t)e2 << 2) | ((uint32_t)e3 << 3);
         if (mask) exact_hubs(S, va, vb, vc, wrap, mask, ch);
+        o0 = blk * (uint32_t)ch[0];
+        o1 = blk * (uint32_t)ch[1];
+        o2 = blk * (uint32_t)ch[2];
+        o3 = blk * (uint32_t)ch[3];
     }
-    const uint32_t blk = 4u * (uint32_t)S.nconf;
-    const uint32_t a0 = conf_addr<LUT>(S, hist_addr, ba, bb, bc) + blk * (uint32_t)ch[0];
-    const uint32_t a1 = conf_addr<LUT>(S, hist_addr, ba, bab, bac) + blk * (uint32_t)ch[1];
-    const uint32_t a2 = conf_addr<LUT>(S, hist_addr, bb, bab, bbc) + blk * (uint32_t)ch[2];
-    const uint32_t a3 = conf_addr<LUT>(S, hist_addr, bc, bac, bbc) + blk * (uint32_t)ch[3];
+    const uint32_t a0 = conf_addr<LUT>(S, hist_addr, ba, bb, bc) + o0;
+    const uint32_t a1 = conf_addr<LUT>(S, hist_addr, ba, bab, bac) + o1;
+    const uint32_t a2 = conf_addr<LUT>(S, hist_addr, bb, bab, bbc) + o2;
+    const uint32_t a3 = conf_addr<LUT>(S, hist_addr, bc, bac, bbc) + o3;
     __hip_atomic_fetch_add((lds_u32 *)(size_t)a0, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_add((lds_u32 *)(size_t)a1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_add((lds_u32 *)(size_t)a2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -418,22 +440,9 @@ __device__ __forceinline__ void local_bins(const Stage4 &S, uint32_t va, uint32_
                                            int &bab, int &bac, int &bbc) {
     P3 ab, ac, bcv;
     local_seps(S, va, vb, vc, wrap, ab, ac, bcv);
-    const double qab = sq_len(ab.x, ab.y, ab.z), qac = sq_len(ac.x, ac.y, ac.z), qbc = sq_len(bcv.x, bcv.y, bcv.z);
-    if (S.nb <= 16) {
-        bab = bac = bbc = 0;
-#pragma unroll
-        for (int k = 0; k < 15; ++k)
-            if (k + 1 < S.nb) {
-                const double t = S.tk[k];
-                bab += qab >= t;
-                bac += qac >= t;
-                bbc += qbc >= t;
-            }
-    } else {
-        bab = bin_of(S.thr, S.nb, qab);
-        bac = bin_of(S.thr, S.nb, qac);
-        bbc = bin_of(S.thr, S.nb, qbc);
-    }
+    bab = edge_bin(S, sq_len(ab.x, ab.y, ab.z));
+    bac = edge_bin(S, sq_len(ac.x, ac.y, ac.z));
+    bbc = edge_bin(S, sq_len(bcv.x, bcv.y, bcv.z));
 }
 
 // 6-edge configuration of the clique {i, a, b, c}: the code of its edge-bin
@@ -619,11 +628,14 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
         ta[b] = rank_a(a.nb, b);
         tb[b] = rank_b(a.nb, b);
     }
+    const int lsh = lut_shift(a.nb);
     if (LUT)
-        for (int t = tid; t < a.nb * a.nb * a.nb; t += BLOCK) {
-            const int x = t / (a.nb * a.nb), y = (t / a.nb) % a.nb, z = t % a.nb;
+        for (int t = tid; t < (1 << (3 * lsh)); t += BLOCK) {
+            const int m = (1 << lsh) - 1;
+            const int x = t >> (2 * lsh), y = (t >> lsh) & m, z = t & m;
             const int b0 = min(min(x, y), z), b2 = max(max(x, y), z), b1 = x + y + z - b0 - b2;
-            lut[t] = (uint16_t)(rank_a(a.nb, b0) + rank_b(a.nb, b1) + b2);
+            lut[t] = (x < a.nb && y < a.nb && z < a.nb) ? (uint16_t)(4 * (rank_a(a.nb, b0) + rank_b(a.nb, b1) + b2))
+                                                       : (uint16_t)0;
         }
     for (int b = tid; b <= a.nb; b += BLOCK) thr[b] = a.thr[b];
     if (tid == 0) *s_cnt = 0;
@@ -633,7 +645,10 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint64_t acc = 0;
     HubCursor cursor;   // thread 0's claimed run of hubs
     const double Lb = a.L, half = a.half;
-    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, lut, hist, a.nb, a.nconf, a.L, a.half, a.tk,
+    const double tn = a.thr[a.nb];
+    const double limR = __dmul_rn(1e-18, __dmul_rn(__dmul_rn(tn, tn), tn));
+    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, lut, hist, a.nb, a.nconf, a.L, a.half,
+                   a.bg_inv, a.bg_c, (float)(a.nb - 1), a.bguess, lsh, limR,
                    pw, a.wmul, wlo, whi, a.hist, a.wsum, a.cfg6, tab6, pdir, pperm};
     const uint32_t hist_addr = lds_addr(hist);
 
@@ -1092,7 +1107,16 @@ void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_ra
     // box is the plain difference)
     a.L = g.periodic ? g.box : HUGE_VAL;
     a.half = g.periodic ? 0.5 * g.box : HUGE_VAL;
-    for (int k = 0; k < 16; ++k) a.tk[k] = g.bins.t[std::min(k + 1, nb)];
+    // bin estimates (edge_bin): exact after one correction while
+    // nb rmax / (rmax - rmin) <= 2^20
+    {
+        const double span = g.rmax - g.rmin;
+        a.bguess = span > 0.0 && g.rmin >= 0.0 && (double)nb * g.rmax <= 1048576.0 * span &&
+                   g.rmax < 1e18 && span >= 1e-12 * nb &&   // float32 range; flushed denormals negligible
+                   getenv("GS_BIN_SEARCH") == nullptr;       // tests: the search path
+        a.bg_inv = a.bguess ? (float)((double)nb / span) : 0.0f;
+        a.bg_c = a.bguess ? (float)(g.rmin * (double)nb / span) : 0.0f;
+    }
     // Hubs at least rmax (with margin) from every face: their clique
     // vertices lie within rmax of the hub, hence unwrapped, and any two of
     // them within 2 rmax < L/2 of each other, so no separation among them

@@ -65,6 +65,7 @@ CASES = [
     ("clustered_mid", lambda: synth.neyman_scott(8000, 50, 1.2, 60.0, 36), 60.0, 0.0, 3.0, 8),
     ("dyadic_ties", lambda: synth.dyadic_uniform(2000, 16.0, 37, bits=5), 16.0, 0.0, 1.6, 4),
     ("many_bins", lambda: synth.uniform(1500, 12.0, 38), 12.0, 0.0, 2.2, 30),
+    ("rmin_bins13", lambda: synth.neyman_scott(5000, 40, 1.0, 30.0, 39), 30.0, 1.1, 3.3, 13),
 ]
 
 
@@ -138,6 +139,17 @@ def test_count4_forced_flushes_identical(ctx, monkeypatch):
     monkeypatch.setenv("GS_FLUSH_LIMIT", str(4 * 256 * 200))
     got = gpu4(ctx, x, 60.0, 0.0, 3.0, 8)
     same(got, ref)
+
+
+def test_count4_bin_search_identical(ctx, monkeypatch):
+    # the local separations' bins by a search of the thresholds instead of
+    # the float32 estimate and its one-step correction
+    x = synth.neyman_scott(8000, 50, 1.2, 60.0, 42)
+    ref = gpu4(ctx, x, 60.0, 0.4, 3.0, 11)
+    monkeypatch.setenv("GS_BIN_SEARCH", "1")
+    got = gpu4(ctx, x, 60.0, 0.4, 3.0, 11)
+    same(got, ref)
+    same(got, oracle.count_4pcf_parity(x, 60.0, 0.4, 3.0, 11))
 
 
 def test_count4_block256_identical(ctx, monkeypatch):
