@@ -68,9 +68,19 @@ struct C4Args {
 
 
 struct Layout4 {
-    uint32_t hkey, hloc, hslot, px, py, pz, sx, sy, sz, pq, pb, pperm, R, rbnd, queue, mstart, mpref, mloc,
-        hist, tab, lut, thr, wtot, misc, pw, wlo, whi, tab6, tabp, total;
+    uint32_t hkey, hloc, hslot, pv, pb, pperm, R, rbnd, queue, mstart, mpref, mloc, hist, tab, lut, thr, wtot,
+        misc, wlo, whi, tab6, tabp, total;
 };
+
+// A staged vertex of N+(i) in LDS, one record per local index: doubles
+// x, y, z, q, sx, sy, sz, w (the parity kinds: position, squared spoke
+// length, spoke from the hub, weight) or x, y, z, w (the 6-edge kind), so a
+// vertex's fields share one address and load in pairs.
+template <int KIND> struct VRec {
+    static constexpr int ST = KIND == kSix4 ? 4 : 8;   // doubles per record
+    static constexpr int W = ST - 1;                    // the weight's slot
+};
+constexpr int kVx = 0, kVq = 3, kVs = 4;   // slots: position, squared length, spoke
 
 constexpr int kLut4MaxBins = 16;   // u16 counter offsets of the ordered bin triples, up to 8 KB
 
@@ -95,14 +105,7 @@ __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxde
     Layout4 L{};
     uint32_t o = 0, d = maxdeg + 1;
     const bool spokes = kind != kSix4;   // hub spokes and lengths: the parity kinds
-    L.px = o;      o = lds_align(o + 8 * d, 16);
-    L.py = o;      o = lds_align(o + 8 * d, 16);
-    L.pz = o;      o = lds_align(o + 8 * d, 16);
-    L.sx = o;      if (spokes) o = lds_align(o + 8 * d, 16);
-    L.sy = o;      if (spokes) o = lds_align(o + 8 * d, 16);
-    L.sz = o;      if (spokes) o = lds_align(o + 8 * d, 16);
-    L.pq = o;      if (spokes) o = lds_align(o + 8 * d, 16);
-    L.pw = o;      if (weighted) o = lds_align(o + 8 * d, 16);
+    L.pv = o;      o = lds_align(o + (spokes ? 64 : 32) * d, 16);
     L.wlo = o;     if (weighted) o = lds_align(o + 8 * ncnt, 16);
     L.whi = o;     if (weighted) o = lds_align(o + 8 * ncnt, 16);
     L.thr = o;     o = lds_align(o + 8 * (nb + 1), 16);
@@ -231,9 +234,7 @@ __device__ __forceinline__ uint32_t hub_sign(double qP, double qQ, double qR, do
 
 // Per-hub LDS state the clique evaluation reads.
 struct Stage4 {
-    const double *px, *py, *pz;   // absolute coordinates of N+(i)
-    const double *sx, *sy, *sz;   // spokes from the hub (minimum image)
-    const double *pq;             // squared spoke lengths
+    const double *pv;             // vertex records of N+(i) (VRec)
     const uint8_t *pb;            // spoke bins
     const double *thr;            // t_0 .. t_nb
     const int *ta, *tb;           // configuration rank tables
@@ -241,11 +242,10 @@ struct Stage4 {
     uint32_t *hist;               // pos | neg | degenerate counters (parity), 6-edge counters
     int nb, nconf;
     double L, half;
-    float bg_inv, bg_c, bg_top;   // bin estimate (edge_bin); bg_top = nb - 1
+    float bg_inv, bg_c, bg_top;   // bin estimate (bin_guess); bg_top = nb - 1
     int bguess;
     int lsh;                      // s of the ordered-triple table
     double limR;                  // fl(1e-18 ((t_nb t_nb) t_nb)): no hub's volume limit exceeds it
-    const double *pw;             // weights of N+(i) (weighted)
     double wmul;
     unsigned long long *wlo, *whi;  // LDS sums of the terms' low 32 bits / high parts
     unsigned long long *ghist, *gwsum;  // global counters and sums (6-edge beyond LDS)
@@ -254,6 +254,19 @@ struct Stage4 {
     const double *pdir;           // pixel kind: centre directions in LDS (768 doubles)
     const uint32_t *pperm;        // original indices of N+(i)
 };
+
+template <int ST> __device__ __forceinline__ P3 vpos(const Stage4 &S, uint32_t v) {
+    const double *r = S.pv + ST * v;
+    return P3{r[kVx], r[kVx + 1], r[kVx + 2]};
+}
+__device__ __forceinline__ P3 vspoke(const Stage4 &S, uint32_t v) {
+    const double *r = S.pv + 8 * v;
+    return P3{r[kVs], r[kVs + 1], r[kVs + 2]};
+}
+__device__ __forceinline__ double vq(const Stage4 &S, uint32_t v) { return S.pv[8 * v + kVq]; }
+template <int ST> __device__ __forceinline__ double vw(const Stage4 &S, uint32_t v) {
+    return S.pv[ST * v + ST - 1];
+}
 
 // Bin of the squared separation q of a graph edge (t_0 <= q < t_nb): the
 // number of thresholds t_1..t_{nb-1} at most q. With linear bins in r
@@ -264,15 +277,27 @@ struct Stage4 {
 // nb rmax / (rmax - rmin) <= 2^20 (bguess) that is below 0.4 bin, so floor(u)
 // clamped to [0, nb) is within one bin of the answer and a single float64
 // comparison with each neighbouring threshold settles it (t_0 <= q and
-// q < t_nb make the ends safe). Otherwise a binary search of the thresholds.
-__device__ __forceinline__ int edge_bin(const Stage4 &S, double q) {
+// q < t_nb make the ends safe). Otherwise a binary search of the thresholds
+// (edge_bins).
+__device__ __forceinline__ int bin_guess(const Stage4 &S, double q) {
+    const float r = __builtin_amdgcn_sqrtf((float)q);
+    const float u = __builtin_amdgcn_fmed3f(__builtin_fmaf(r, S.bg_inv, -S.bg_c), 0.0f, S.bg_top);
+    const int g = (int)u;
+    return g + (int)(q >= S.thr[g + 1]) - (int)(q < S.thr[g]);
+}
+
+// The bins of three squared separations (one branch on bguess for all).
+__device__ __forceinline__ void edge_bins(const Stage4 &S, double q0, double q1, double q2, int &b0, int &b1,
+                                          int &b2) {
     if (S.bguess) {
-        const float r = __builtin_amdgcn_sqrtf((float)q);
-        const float u = __builtin_amdgcn_fmed3f(__builtin_fmaf(r, S.bg_inv, -S.bg_c), 0.0f, S.bg_top);
-        const int g = (int)u;
-        return g + (int)(q >= S.thr[g + 1]) - (int)(q < S.thr[g]);
+        b0 = bin_guess(S, q0);
+        b1 = bin_guess(S, q1);
+        b2 = bin_guess(S, q2);
+    } else {
+        b0 = bin_of(S.thr, S.nb, q0);
+        b1 = bin_of(S.thr, S.nb, q1);
+        b2 = bin_of(S.thr, S.nb, q2);
     }
-    return bin_of(S.thr, S.nb, q);
 }
 
 // A clique's weight term in units of 2^-s: the four magnitudes in ascending
@@ -308,11 +333,10 @@ __device__ __forceinline__ double wrap1(double d, double L, double half) {
 
 // Separations among the clique's non-hub vertices a, b, c: plain differences,
 // corrected by +-L near a face (wrap) as the definition does.
+template <int ST>
 __device__ __forceinline__ void local_seps(const Stage4 &S, uint32_t va, uint32_t vb, uint32_t vc, bool wrap,
                                           P3 &ab, P3 &ac, P3 &bcv) {
-    const P3 A{S.px[va], S.py[va], S.pz[va]};
-    const P3 B{S.px[vb], S.py[vb], S.pz[vb]};
-    const P3 C{S.px[vc], S.py[vc], S.pz[vc]};
+    const P3 A = vpos<ST>(S, va), B = vpos<ST>(S, vb), C = vpos<ST>(S, vc);
     ab = P3{__dsub_rn(B.x, A.x), __dsub_rn(B.y, A.y), __dsub_rn(B.z, A.z)};
     ac = P3{__dsub_rn(C.x, A.x), __dsub_rn(C.y, A.y), __dsub_rn(C.z, A.z)};
     bcv = P3{__dsub_rn(C.x, B.x), __dsub_rn(C.y, B.y), __dsub_rn(C.z, B.z)};
@@ -330,12 +354,10 @@ __device__ __forceinline__ void local_seps(const Stage4 &S, uint32_t va, uint32_
 // operations, hence the same values) so the common path holds no vectors.
 __device__ __forceinline__ void exact_hubs(const Stage4 &S, uint32_t va, uint32_t vb, uint32_t vc, bool wrap,
                                         uint32_t mask, int *ch) {
-    const P3 ia{S.sx[va], S.sy[va], S.sz[va]};
-    const P3 ib{S.sx[vb], S.sy[vb], S.sz[vb]};
-    const P3 ic{S.sx[vc], S.sy[vc], S.sz[vc]};
-    const double qa = S.pq[va], qb = S.pq[vb], qc = S.pq[vc];
+    const P3 ia = vspoke(S, va), ib = vspoke(S, vb), ic = vspoke(S, vc);
+    const double qa = vq(S, va), qb = vq(S, vb), qc = vq(S, vc);
     P3 ab, ac, bcv;
-    local_seps(S, va, vb, vc, wrap, ab, ac, bcv);
+    local_seps<8>(S, va, vb, vc, wrap, ab, ac, bcv);
     const double qab = sq_len(ab.x, ab.y, ab.z), qac = sq_len(ac.x, ac.y, ac.z), qbc = sq_len(bcv.x, bcv.y, bcv.z);
     int idx;
     if (mask & 1u) ch[0] = hub_channel(ia, ib, ic, qa, qb, qc, 0, 0, 0, S.ta, S.tb, &idx);
@@ -365,21 +387,19 @@ __device__ __forceinline__ uint32_t conf_addr(const Stage4 &S, uint32_t hist_add
 template <bool LUT, bool WEIGHTED>
 __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr, uint32_t va, uint32_t vb,
                                             uint32_t vc, double eb, bool wrap, double wi) {
-    const double qa = S.pq[va], qb = S.pq[vb], qc = S.pq[vc];
+    const double qa = vq(S, va), qb = vq(S, vb), qc = vq(S, vc);
     const int ba = S.pb[va], bb = S.pb[vb], bc = S.pb[vc];
     double qab, qac, qbc, Vc;
     {
         P3 ab, ac, bcv;
-        local_seps(S, va, vb, vc, wrap, ab, ac, bcv);
+        local_seps<8>(S, va, vb, vc, wrap, ab, ac, bcv);
         qab = sq_len(ab.x, ab.y, ab.z);
         qac = sq_len(ac.x, ac.y, ac.z);
         qbc = sq_len(bcv.x, bcv.y, bcv.z);
-        const P3 ia{S.sx[va], S.sy[va], S.sz[va]};
-        const P3 ib{S.sx[vb], S.sy[vb], S.sz[vb]};
-        const P3 ic{S.sx[vc], S.sy[vc], S.sz[vc]};
-        Vc = triple(ia, ib, ic);
+        Vc = triple(vspoke(S, va), vspoke(S, vb), vspoke(S, vc));
     }
-    const int bab = edge_bin(S, qab), bac = edge_bin(S, qac), bbc = edge_bin(S, qbc);
+    int bab, bac, bbc;
+    edge_bins(S, qab, qac, qbc, bab, bac, bbc);
     Shared4 sh;
     sh.Vc = Vc;
     const double A = fabs(Vc);
@@ -425,7 +445,7 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr,
     if (WEIGHTED) {
         // every hub contribution carries the clique's weight product
         bool ng;
-        const double x = clique_term(wi, S.pw[va], S.pw[vb], S.pw[vc], S.wmul, ng);
+        const double x = clique_term(wi, vw<8>(S, va), vw<8>(S, vb), vw<8>(S, vc), S.wmul, ng);
         add_term<true>(S, (a0 - hist_addr) >> 2, x, ng);
         add_term<true>(S, (a1 - hist_addr) >> 2, x, ng);
         add_term<true>(S, (a2 - hist_addr) >> 2, x, ng);
@@ -436,13 +456,12 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr,
 // The bins of the three separations among a clique's non-hub vertices
 // (the hub's spoke bins are staged): squared lengths from the staged
 // coordinates, counted against the thresholds.
+template <int ST>
 __device__ __forceinline__ void local_bins(const Stage4 &S, uint32_t va, uint32_t vb, uint32_t vc, bool wrap,
                                            int &bab, int &bac, int &bbc) {
     P3 ab, ac, bcv;
-    local_seps(S, va, vb, vc, wrap, ab, ac, bcv);
-    bab = edge_bin(S, sq_len(ab.x, ab.y, ab.z));
-    bac = edge_bin(S, sq_len(ac.x, ac.y, ac.z));
-    bbc = edge_bin(S, sq_len(bcv.x, bcv.y, bcv.z));
+    local_seps<ST>(S, va, vb, vc, wrap, ab, ac, bcv);
+    edge_bins(S, sq_len(ab.x, ab.y, ab.z), sq_len(ac.x, ac.y, ac.z), sq_len(bcv.x, bcv.y, bcv.z), bab, bac, bbc);
 }
 
 // 6-edge configuration of the clique {i, a, b, c}: the code of its edge-bin
@@ -453,7 +472,7 @@ template <bool TAB6_LDS, bool LDS_CNT, bool WEIGHTED>
 __device__ __forceinline__ void eval_six(const Stage4 &S, uint32_t hist_addr, uint32_t va, uint32_t vb,
                                          uint32_t vc, bool wrap, double wi) {
     int bab, bac, bbc;
-    local_bins(S, va, vb, vc, wrap, bab, bac, bbc);
+    local_bins<4>(S, va, vb, vc, wrap, bab, bac, bbc);
     const uint32_t nb = (uint32_t)S.nb;
     const uint32_t code =
         ((((((uint32_t)S.pb[va] * nb + S.pb[vb]) * nb + S.pb[vc]) * nb + (uint32_t)bab) * nb + (uint32_t)bac) * nb) +
@@ -466,7 +485,7 @@ __device__ __forceinline__ void eval_six(const Stage4 &S, uint32_t hist_addr, ui
         atomicAdd(&S.ghist[cfg], 1ull);
     if (WEIGHTED) {
         bool ng;
-        const double x = clique_term(wi, S.pw[va], S.pw[vb], S.pw[vc], S.wmul, ng);
+        const double x = clique_term(wi, vw<4>(S, va), vw<4>(S, vb), vw<4>(S, vc), S.wmul, ng);
         add_term<LDS_CNT>(S, cfg, x, ng);
     }
 }
@@ -513,13 +532,11 @@ __device__ __forceinline__ int hub_pixel(const double *pd, uint32_t o0, uint32_t
 template <bool LUT>
 __device__ __forceinline__ void eval_pixel(const Stage4 &S, uint32_t hist_addr, uint32_t va, uint32_t vb,
                                            uint32_t vc, bool wrap, uint32_t oi) {
-    const P3 ia{S.sx[va], S.sy[va], S.sz[va]};
-    const P3 ib{S.sx[vb], S.sy[vb], S.sz[vb]};
-    const P3 ic{S.sx[vc], S.sy[vc], S.sz[vc]};
+    const P3 ia = vspoke(S, va), ib = vspoke(S, vb), ic = vspoke(S, vc);
     P3 ab, ac, bcv;
-    local_seps(S, va, vb, vc, wrap, ab, ac, bcv);
+    local_seps<8>(S, va, vb, vc, wrap, ab, ac, bcv);
     int bab, bac, bbc;
-    local_bins(S, va, vb, vc, wrap, bab, bac, bbc);
+    edge_bins(S, sq_len(ab.x, ab.y, ab.z), sq_len(ac.x, ac.y, ac.z), sq_len(bcv.x, bcv.y, bcv.z), bab, bac, bbc);
     uint32_t fia, ria, fib, rib, fic, ric, fab, rab, fac, rac, fbc, rbc;
     pixel_pair(ia, fia, ria);
     pixel_pair(ib, fib, rib);
@@ -581,9 +598,8 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint32_t *hkey = (uint32_t *)(sm + L.hkey);
     uint16_t *hloc = (uint16_t *)(sm + L.hloc);
     uint16_t *hslot = (uint16_t *)(sm + L.hslot);
-    double *px = (double *)(sm + L.px), *py = (double *)(sm + L.py), *pz = (double *)(sm + L.pz);
-    double *sx = (double *)(sm + L.sx), *sy = (double *)(sm + L.sy), *sz = (double *)(sm + L.sz);
-    double *pq = (double *)(sm + L.pq);
+    constexpr int ST = VRec<KIND>::ST;
+    double *pv = (double *)(sm + L.pv);
     uint8_t *pb = (uint8_t *)(sm + L.pb);
     uint32_t *pperm = (uint32_t *)(sm + L.pperm);
     uint32_t *R = (uint32_t *)(sm + L.R);
@@ -605,7 +621,6 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     const int tid = threadIdx.x, lane = tid & 63;
     unsigned long long *ring = (unsigned long long *)(sm + L.queue) + (tid >> 6) * kQueue4;
 
-    double *pw = (double *)(sm + L.pw);
     unsigned long long *wlo = (unsigned long long *)(sm + L.wlo), *whi = (unsigned long long *)(sm + L.whi);
     uint16_t *tab6 = (uint16_t *)(sm + L.tab6);
     double *pdir = (double *)(sm + L.tabp);
@@ -647,9 +662,9 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     const double Lb = a.L, half = a.half;
     const double tn = a.thr[a.nb];
     const double limR = __dmul_rn(1e-18, __dmul_rn(__dmul_rn(tn, tn), tn));
-    const Stage4 S{px, py, pz, sx, sy, sz, pq, pb, thr, ta, tb, lut, hist, a.nb, a.nconf, a.L, a.half,
+    const Stage4 S{pv, pb, thr, ta, tb, lut, hist, a.nb, a.nconf, a.L, a.half,
                    a.bg_inv, a.bg_c, (float)(a.nb - 1), a.bguess, lsh, limR,
-                   pw, a.wmul, wlo, whi, a.hist, a.wsum, a.cfg6, tab6, pdir, pperm};
+                   a.wmul, wlo, whi, a.hist, a.wsum, a.cfg6, tab6, pdir, pperm};
     const uint32_t hist_addr = lds_addr(hist);
 
     while (true) {
@@ -675,20 +690,21 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
             hloc[s] = (uint16_t)e;
             hslot[e] = (uint16_t)s;
             const double x = a.X[k], y = a.Y[k], z = a.Z[k];
-            px[e] = x;
-            py[e] = y;
-            pz[e] = z;
+            double *rec = pv + ST * e;
+            rec[kVx] = x;
+            rec[kVx + 1] = y;
+            rec[kVx + 2] = z;
             if (KIND != kSix4) {
                 const double dx = min_image(xi, x, Lb, half), dy = min_image(yi, y, Lb, half),
                              dz = min_image(zi, z, Lb, half);
-                sx[e] = dx;
-                sy[e] = dy;
-                sz[e] = dz;
-                pq[e] = sq_len(dx, dy, dz);
+                rec[kVs] = dx;
+                rec[kVs + 1] = dy;
+                rec[kVs + 2] = dz;
+                rec[kVq] = sq_len(dx, dy, dz);
             }
             pb[e] = a.bin[beg + e];
             if (PERM) pperm[e] = a.perm[k];
-            if (WEIGHTED) pw[e] = a.w[k];
+            if (WEIGHTED) rec[VRec<KIND>::W] = a.w[k];
         }
         const double wi = WEIGHTED ? a.w[i] : 0.0;
         for (uint32_t w = tid; w < d * W; w += BLOCK) R[w] = 0;
@@ -781,6 +797,27 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
             __syncthreads();
 
             uint32_t qhead = 0, qtail = 0;   // ring positions (wavefront-uniform)
+            // one clique {i, va, vb, vc} from the ring; the interior and the
+            // near-face hubs take separate copies (no wrap test per clique)
+            auto evaluate = [&](unsigned long long t) {
+                const uint32_t va = (uint32_t)t & 0xFFFFu, vb = (uint32_t)(t >> 16) & 0xFFFFu,
+                               vc = (uint32_t)(t >> 32);
+                if (inner) {
+                    if (KIND == kParity4)
+                        eval_clique<LUT, WEIGHTED>(S, hist_addr, va, vb, vc, a.eb_in, false, wi);
+                    else if (KIND == kPixel4)
+                        eval_pixel<LUT>(S, hist_addr, va, vb, vc, false, pi);
+                    else
+                        eval_six<TAB6, CNT_LDS, WEIGHTED>(S, hist_addr, va, vb, vc, false, wi);
+                } else {
+                    if (KIND == kParity4)
+                        eval_clique<LUT, WEIGHTED>(S, hist_addr, va, vb, vc, a.eb_wrap, true, wi);
+                    else if (KIND == kPixel4)
+                        eval_pixel<LUT>(S, hist_addr, va, vb, vc, true, pi);
+                    else
+                        eval_six<TAB6, CNT_LDS, WEIGHTED>(S, hist_addr, va, vb, vc, true, wi);
+                }
+            };
             unsigned long long mine_n = 0;   // cliques this lane evaluated in the round
             while (true) {
                 uint32_t ra = 0;
@@ -819,15 +856,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
                                 const unsigned long long t = ring[(qhead + lane) & (kQueue4 - 1)];
                                 qhead += 64;
                                 ++mine_n;
-                                const uint32_t va = (uint32_t)t & 0xFFFFu, vb = (uint32_t)(t >> 16) & 0xFFFFu,
-                                               vc = (uint32_t)(t >> 32);
-                                if (KIND == kParity4)
-                                    eval_clique<LUT, WEIGHTED>(S, hist_addr, va, vb, vc, inner ? a.eb_in : a.eb_wrap,
-                                                               !inner, wi);
-                                else if (KIND == kPixel4)
-                                    eval_pixel<LUT>(S, hist_addr, va, vb, vc, !inner, pi);
-                                else
-                                    eval_six<TAB6, CNT_LDS, WEIGHTED>(S, hist_addr, va, vb, vc, !inner, wi);
+                                evaluate(t);
                                 wave_lds_sync();
                             }
                         }
@@ -838,14 +867,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
             if ((uint32_t)lane < qtail - qhead) {
                 const unsigned long long t = ring[(qhead + lane) & (kQueue4 - 1)];
                 ++mine_n;
-                const uint32_t va = (uint32_t)t & 0xFFFFu, vb = (uint32_t)(t >> 16) & 0xFFFFu,
-                               vc = (uint32_t)(t >> 32);
-                if (KIND == kParity4)
-                    eval_clique<LUT, WEIGHTED>(S, hist_addr, va, vb, vc, inner ? a.eb_in : a.eb_wrap, !inner, wi);
-                else if (KIND == kPixel4)
-                    eval_pixel<LUT>(S, hist_addr, va, vb, vc, !inner, pi);
-                else
-                    eval_six<TAB6, CNT_LDS, WEIGHTED>(S, hist_addr, va, vb, vc, !inner, wi);
+                evaluate(t);
             }
             mycl += mine_n;
             if (mine_n) atomicAdd(s_round, mine_n);
@@ -1107,7 +1129,7 @@ void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_ra
     // box is the plain difference)
     a.L = g.periodic ? g.box : HUGE_VAL;
     a.half = g.periodic ? 0.5 * g.box : HUGE_VAL;
-    // bin estimates (edge_bin): exact after one correction while
+    // bin estimates (bin_guess): exact after one correction while
     // nb rmax / (rmax - rmin) <= 2^20
     {
         const double span = g.rmax - g.rmin;
