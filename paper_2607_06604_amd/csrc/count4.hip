@@ -73,12 +73,12 @@ struct Layout4 {
 };
 
 // A staged vertex of N+(i) in LDS, one record per local index: doubles
-// x, y, z, q, sx, sy, sz, w (the parity kinds: position, squared spoke
-// length, spoke from the hub, weight) or x, y, z, w (the 6-edge kind), so a
-// vertex's fields share one address and load in pairs.
-template <int KIND> struct VRec {
-    static constexpr int ST = KIND == kSix4 ? 4 : 8;   // doubles per record
-    static constexpr int W = ST - 1;                    // the weight's slot
+// x, y, z, q, sx, sy, sz (the parity kinds: position, squared spoke length,
+// spoke from the hub) or x, y, z (the 6-edge kind), then the weight in
+// weighted counts, so a vertex's fields share one address and load in pairs.
+template <int KIND, bool WEIGHTED> struct VRec {
+    static constexpr int ST = (KIND == kSix4 ? 3 : 7) + (WEIGHTED ? 1 : 0);   // doubles per record
+    static constexpr int W = ST - 1;                                           // the weight's slot
 };
 constexpr int kVx = 0, kVq = 3, kVs = 4;   // slots: position, squared length, spoke
 
@@ -105,7 +105,7 @@ __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxde
     Layout4 L{};
     uint32_t o = 0, d = maxdeg + 1;
     const bool spokes = kind != kSix4;   // hub spokes and lengths: the parity kinds
-    L.pv = o;      o = lds_align(o + (spokes ? 64 : 32) * d, 16);
+    L.pv = o;      o = lds_align(o + 8 * ((spokes ? 7 : 3) + (weighted ? 1 : 0)) * d, 16);
     L.wlo = o;     if (weighted) o = lds_align(o + 8 * ncnt, 16);
     L.whi = o;     if (weighted) o = lds_align(o + 8 * ncnt, 16);
     L.thr = o;     o = lds_align(o + 8 * (nb + 1), 16);
@@ -259,11 +259,11 @@ template <int ST> __device__ __forceinline__ P3 vpos(const Stage4 &S, uint32_t v
     const double *r = S.pv + ST * v;
     return P3{r[kVx], r[kVx + 1], r[kVx + 2]};
 }
-__device__ __forceinline__ P3 vspoke(const Stage4 &S, uint32_t v) {
-    const double *r = S.pv + 8 * v;
+template <int ST> __device__ __forceinline__ P3 vspoke(const Stage4 &S, uint32_t v) {
+    const double *r = S.pv + ST * v;
     return P3{r[kVs], r[kVs + 1], r[kVs + 2]};
 }
-__device__ __forceinline__ double vq(const Stage4 &S, uint32_t v) { return S.pv[8 * v + kVq]; }
+template <int ST> __device__ __forceinline__ double vq(const Stage4 &S, uint32_t v) { return S.pv[ST * v + kVq]; }
 template <int ST> __device__ __forceinline__ double vw(const Stage4 &S, uint32_t v) {
     return S.pv[ST * v + ST - 1];
 }
@@ -352,12 +352,13 @@ __device__ __forceinline__ void local_seps(const Stage4 &S, uint32_t va, uint32_
 // mask: 0 hub i, 1 a, 2 b, 3 c), evaluated as the definition says. The
 // separations are recomputed from the staged coordinates (the same
 // operations, hence the same values) so the common path holds no vectors.
+template <int ST>
 __device__ __forceinline__ void exact_hubs(const Stage4 &S, uint32_t va, uint32_t vb, uint32_t vc, bool wrap,
                                         uint32_t mask, int *ch) {
-    const P3 ia = vspoke(S, va), ib = vspoke(S, vb), ic = vspoke(S, vc);
-    const double qa = vq(S, va), qb = vq(S, vb), qc = vq(S, vc);
+    const P3 ia = vspoke<ST>(S, va), ib = vspoke<ST>(S, vb), ic = vspoke<ST>(S, vc);
+    const double qa = vq<ST>(S, va), qb = vq<ST>(S, vb), qc = vq<ST>(S, vc);
     P3 ab, ac, bcv;
-    local_seps<8>(S, va, vb, vc, wrap, ab, ac, bcv);
+    local_seps<ST>(S, va, vb, vc, wrap, ab, ac, bcv);
     const double qab = sq_len(ab.x, ab.y, ab.z), qac = sq_len(ac.x, ac.y, ac.z), qbc = sq_len(bcv.x, bcv.y, bcv.z);
     int idx;
     if (mask & 1u) ch[0] = hub_channel(ia, ib, ic, qa, qb, qc, 0, 0, 0, S.ta, S.tb, &idx);
@@ -387,16 +388,17 @@ __device__ __forceinline__ uint32_t conf_addr(const Stage4 &S, uint32_t hist_add
 template <bool LUT, bool WEIGHTED>
 __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr, uint32_t va, uint32_t vb,
                                             uint32_t vc, double eb, bool wrap, double wi) {
-    const double qa = vq(S, va), qb = vq(S, vb), qc = vq(S, vc);
+    constexpr int ST = VRec<kParity4, WEIGHTED>::ST;
+    const double qa = vq<ST>(S, va), qb = vq<ST>(S, vb), qc = vq<ST>(S, vc);
     const int ba = S.pb[va], bb = S.pb[vb], bc = S.pb[vc];
     double qab, qac, qbc, Vc;
     {
         P3 ab, ac, bcv;
-        local_seps<8>(S, va, vb, vc, wrap, ab, ac, bcv);
+        local_seps<ST>(S, va, vb, vc, wrap, ab, ac, bcv);
         qab = sq_len(ab.x, ab.y, ab.z);
         qac = sq_len(ac.x, ac.y, ac.z);
         qbc = sq_len(bcv.x, bcv.y, bcv.z);
-        Vc = triple(vspoke(S, va), vspoke(S, vb), vspoke(S, vc));
+        Vc = triple(vspoke<ST>(S, va), vspoke<ST>(S, vb), vspoke<ST>(S, vc));
     }
     int bab, bac, bbc;
     edge_bins(S, qab, qac, qbc, bab, bac, bbc);
@@ -428,7 +430,7 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr,
         ch[2] = hub_fast(qb, qab, qbc, sh, true, e2);
         ch[3] = hub_fast(qc, qac, qbc, sh, false, e3);
         const uint32_t mask = (uint32_t)e0 | ((uint32_t)e1 << 1) | ((uint32_t)e2 << 2) | ((uint32_t)e3 << 3);
-        if (mask) exact_hubs(S, va, vb, vc, wrap, mask, ch);
+        if (mask) exact_hubs<ST>(S, va, vb, vc, wrap, mask, ch);
         o0 = blk * (uint32_t)ch[0];
         o1 = blk * (uint32_t)ch[1];
         o2 = blk * (uint32_t)ch[2];
@@ -445,7 +447,7 @@ __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr,
     if (WEIGHTED) {
         // every hub contribution carries the clique's weight product
         bool ng;
-        const double x = clique_term(wi, vw<8>(S, va), vw<8>(S, vb), vw<8>(S, vc), S.wmul, ng);
+        const double x = clique_term(wi, vw<ST>(S, va), vw<ST>(S, vb), vw<ST>(S, vc), S.wmul, ng);
         add_term<true>(S, (a0 - hist_addr) >> 2, x, ng);
         add_term<true>(S, (a1 - hist_addr) >> 2, x, ng);
         add_term<true>(S, (a2 - hist_addr) >> 2, x, ng);
@@ -472,7 +474,8 @@ template <bool TAB6_LDS, bool LDS_CNT, bool WEIGHTED>
 __device__ __forceinline__ void eval_six(const Stage4 &S, uint32_t hist_addr, uint32_t va, uint32_t vb,
                                          uint32_t vc, bool wrap, double wi) {
     int bab, bac, bbc;
-    local_bins<4>(S, va, vb, vc, wrap, bab, bac, bbc);
+    constexpr int ST = VRec<kSix4, WEIGHTED>::ST;
+    local_bins<ST>(S, va, vb, vc, wrap, bab, bac, bbc);
     const uint32_t nb = (uint32_t)S.nb;
     const uint32_t code =
         ((((((uint32_t)S.pb[va] * nb + S.pb[vb]) * nb + S.pb[vc]) * nb + (uint32_t)bab) * nb + (uint32_t)bac) * nb) +
@@ -485,7 +488,7 @@ __device__ __forceinline__ void eval_six(const Stage4 &S, uint32_t hist_addr, ui
         atomicAdd(&S.ghist[cfg], 1ull);
     if (WEIGHTED) {
         bool ng;
-        const double x = clique_term(wi, vw<4>(S, va), vw<4>(S, vb), vw<4>(S, vc), S.wmul, ng);
+        const double x = clique_term(wi, vw<ST>(S, va), vw<ST>(S, vb), vw<ST>(S, vc), S.wmul, ng);
         add_term<LDS_CNT>(S, cfg, x, ng);
     }
 }
@@ -532,9 +535,10 @@ __device__ __forceinline__ int hub_pixel(const double *pd, uint32_t o0, uint32_t
 template <bool LUT>
 __device__ __forceinline__ void eval_pixel(const Stage4 &S, uint32_t hist_addr, uint32_t va, uint32_t vb,
                                            uint32_t vc, bool wrap, uint32_t oi) {
-    const P3 ia = vspoke(S, va), ib = vspoke(S, vb), ic = vspoke(S, vc);
+    constexpr int ST = VRec<kPixel4, false>::ST;
+    const P3 ia = vspoke<ST>(S, va), ib = vspoke<ST>(S, vb), ic = vspoke<ST>(S, vc);
     P3 ab, ac, bcv;
-    local_seps<8>(S, va, vb, vc, wrap, ab, ac, bcv);
+    local_seps<ST>(S, va, vb, vc, wrap, ab, ac, bcv);
     int bab, bac, bbc;
     edge_bins(S, sq_len(ab.x, ab.y, ab.z), sq_len(ac.x, ac.y, ac.z), sq_len(bcv.x, bcv.y, bcv.z), bab, bac, bbc);
     uint32_t fia, ria, fib, rib, fic, ric, fab, rab, fac, rac, fbc, rbc;
@@ -598,7 +602,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint32_t *hkey = (uint32_t *)(sm + L.hkey);
     uint16_t *hloc = (uint16_t *)(sm + L.hloc);
     uint16_t *hslot = (uint16_t *)(sm + L.hslot);
-    constexpr int ST = VRec<KIND>::ST;
+    constexpr int ST = VRec<KIND, WEIGHTED>::ST;
     double *pv = (double *)(sm + L.pv);
     uint8_t *pb = (uint8_t *)(sm + L.pb);
     uint32_t *pperm = (uint32_t *)(sm + L.pperm);
@@ -704,7 +708,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
             }
             pb[e] = a.bin[beg + e];
             if (PERM) pperm[e] = a.perm[k];
-            if (WEIGHTED) rec[VRec<KIND>::W] = a.w[k];
+            if (WEIGHTED) rec[VRec<KIND, WEIGHTED>::W] = a.w[k];
         }
         const double wi = WEIGHTED ? a.w[i] : 0.0;
         for (uint32_t w = tid; w < d * W; w += BLOCK) R[w] = 0;
@@ -798,22 +802,23 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
 
             uint32_t qhead = 0, qtail = 0;   // ring positions (wavefront-uniform)
             // one clique {i, va, vb, vc} from the ring; the interior and the
-            // near-face hubs take separate copies (no wrap test per clique)
+            // near-face hubs take separate copies of the parity and 6-edge
+            // evaluations (no wrap test per clique)
             auto evaluate = [&](unsigned long long t) {
                 const uint32_t va = (uint32_t)t & 0xFFFFu, vb = (uint32_t)(t >> 16) & 0xFFFFu,
                                vc = (uint32_t)(t >> 32);
-                if (inner) {
+                if (KIND == kPixel4) {
+                    // one copy: a second would raise the register count past
+                    // four wavefronts per SIMD
+                    eval_pixel<LUT>(S, hist_addr, va, vb, vc, !inner, pi);
+                } else if (inner) {
                     if (KIND == kParity4)
                         eval_clique<LUT, WEIGHTED>(S, hist_addr, va, vb, vc, a.eb_in, false, wi);
-                    else if (KIND == kPixel4)
-                        eval_pixel<LUT>(S, hist_addr, va, vb, vc, false, pi);
                     else
                         eval_six<TAB6, CNT_LDS, WEIGHTED>(S, hist_addr, va, vb, vc, false, wi);
                 } else {
                     if (KIND == kParity4)
                         eval_clique<LUT, WEIGHTED>(S, hist_addr, va, vb, vc, a.eb_wrap, true, wi);
-                    else if (KIND == kPixel4)
-                        eval_pixel<LUT>(S, hist_addr, va, vb, vc, true, pi);
                     else
                         eval_six<TAB6, CNT_LDS, WEIGHTED>(S, hist_addr, va, vb, vc, true, wi);
                 }
