@@ -50,6 +50,7 @@ struct C4Args {
     double in_lo, in_hi;   // hubs with every coordinate in [in_lo, in_hi] see no wrapped pair
     double eb_in, eb_wrap; // margins on the shared triple product (interior hubs, the others)
     float bg_inv, bg_c;    // bin estimate of a squared separation q: sqrt(q) bg_inv - bg_c
+    double t3[3];          // t_1, t_2, t_3 (t_nb past nb)
     int bguess;            // that estimate is within one bin (else a search of the thresholds)
     uint32_t anchor_lo, anchor_hi;
     uint64_t flush_limit;
@@ -73,11 +74,14 @@ struct Layout4 {
 };
 
 // A staged vertex of N+(i) in LDS, one record per local index: doubles
-// x, y, z, q, sx, sy, sz (the parity kinds: position, squared spoke length,
-// spoke from the hub) or x, y, z (the 6-edge kind), then the weight in
-// weighted counts, so a vertex's fields share one address and load in pairs.
+// x, y, z, q, sx, sy, sz, w (the parity kinds: position, squared spoke
+// length, spoke from the hub, weight) or x, y, z and, in weighted counts, w
+// (the 6-edge kind), so a vertex's fields share one address and load in
+// pairs.
 template <int KIND, bool WEIGHTED> struct VRec {
-    static constexpr int ST = (KIND == kSix4 ? 3 : 7) + (WEIGHTED ? 1 : 0);   // doubles per record
+    // 64-byte records for the parity kinds (the weight slot unused when
+    // unweighted: the aligned stride measured faster than 56 bytes)
+    static constexpr int ST = KIND == kSix4 ? (WEIGHTED ? 4 : 3) : 8;   // doubles per record
     static constexpr int W = ST - 1;                                           // the weight's slot
 };
 constexpr int kVx = 0, kVq = 3, kVs = 4;   // slots: position, squared length, spoke
@@ -105,7 +109,7 @@ __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxde
     Layout4 L{};
     uint32_t o = 0, d = maxdeg + 1;
     const bool spokes = kind != kSix4;   // hub spokes and lengths: the parity kinds
-    L.pv = o;      o = lds_align(o + 8 * ((spokes ? 7 : 3) + (weighted ? 1 : 0)) * d, 16);
+    L.pv = o;      o = lds_align(o + 8 * (spokes ? 8 : (weighted ? 4 : 3)) * d, 16);
     L.wlo = o;     if (weighted) o = lds_align(o + 8 * ncnt, 16);
     L.whi = o;     if (weighted) o = lds_align(o + 8 * ncnt, 16);
     L.thr = o;     o = lds_align(o + 8 * (nb + 1), 16);
@@ -243,6 +247,7 @@ struct Stage4 {
     int nb, nconf;
     double L, half;
     float bg_inv, bg_c, bg_top;   // bin estimate (bin_guess); bg_top = nb - 1
+    double t3[3];                 // t_1, t_2, t_3 (t_nb past nb): direct counts up to 4 bins
     int bguess;
     int lsh;                      // s of the ordered-triple table
     double limR;                  // fl(1e-18 ((t_nb t_nb) t_nb)): no hub's volume limit exceeds it
@@ -287,9 +292,16 @@ __device__ __forceinline__ int bin_guess(const Stage4 &S, double q) {
 }
 
 // The bins of three squared separations (one branch on bguess for all).
+// SMALL (the 6-edge kind): up to 4 bins the three thresholds t_1..t_3 (t_nb
+// past nb) are compared directly, cheaper than the estimate.
+template <bool SMALL = false>
 __device__ __forceinline__ void edge_bins(const Stage4 &S, double q0, double q1, double q2, int &b0, int &b1,
                                           int &b2) {
-    if (S.bguess) {
+    if (SMALL && S.nb <= 4) {
+        b0 = (int)(q0 >= S.t3[0]) + (int)(q0 >= S.t3[1]) + (int)(q0 >= S.t3[2]);
+        b1 = (int)(q1 >= S.t3[0]) + (int)(q1 >= S.t3[1]) + (int)(q1 >= S.t3[2]);
+        b2 = (int)(q2 >= S.t3[0]) + (int)(q2 >= S.t3[1]) + (int)(q2 >= S.t3[2]);
+    } else if (S.bguess) {
         b0 = bin_guess(S, q0);
         b1 = bin_guess(S, q1);
         b2 = bin_guess(S, q2);
@@ -388,7 +400,7 @@ __device__ __forceinline__ uint32_t conf_addr(const Stage4 &S, uint32_t hist_add
 template <bool LUT, bool WEIGHTED>
 __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr, uint32_t va, uint32_t vb,
                                             uint32_t vc, double eb, bool wrap, double wi) {
-    constexpr int ST = VRec<kParity4, WEIGHTED>::ST;
+    constexpr int ST = VRec<kParity4, WEIGHTED>::ST;   // 8
     const double qa = vq<ST>(S, va), qb = vq<ST>(S, vb), qc = vq<ST>(S, vc);
     const int ba = S.pb[va], bb = S.pb[vb], bc = S.pb[vc];
     double qab, qac, qbc, Vc;
@@ -463,7 +475,8 @@ __device__ __forceinline__ void local_bins(const Stage4 &S, uint32_t va, uint32_
                                            int &bab, int &bac, int &bbc) {
     P3 ab, ac, bcv;
     local_seps<ST>(S, va, vb, vc, wrap, ab, ac, bcv);
-    edge_bins(S, sq_len(ab.x, ab.y, ab.z), sq_len(ac.x, ac.y, ac.z), sq_len(bcv.x, bcv.y, bcv.z), bab, bac, bbc);
+    edge_bins<true>(S, sq_len(ab.x, ab.y, ab.z), sq_len(ac.x, ac.y, ac.z), sq_len(bcv.x, bcv.y, bcv.z), bab, bac,
+                    bbc);
 }
 
 // 6-edge configuration of the clique {i, a, b, c}: the code of its edge-bin
@@ -667,7 +680,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     const double tn = a.thr[a.nb];
     const double limR = __dmul_rn(1e-18, __dmul_rn(__dmul_rn(tn, tn), tn));
     const Stage4 S{pv, pb, thr, ta, tb, lut, hist, a.nb, a.nconf, a.L, a.half,
-                   a.bg_inv, a.bg_c, (float)(a.nb - 1), a.bguess, lsh, limR,
+                   a.bg_inv, a.bg_c, (float)(a.nb - 1), {a.t3[0], a.t3[1], a.t3[2]}, a.bguess, lsh, limR,
                    a.wmul, wlo, whi, a.hist, a.wsum, a.cfg6, tab6, pdir, pperm};
     const uint32_t hist_addr = lds_addr(hist);
 
@@ -1134,6 +1147,7 @@ void count4_run(Ctx &ctx, const Graph &g, const Count4Out &o, const gs_anchor_ra
     // box is the plain difference)
     a.L = g.periodic ? g.box : HUGE_VAL;
     a.half = g.periodic ? 0.5 * g.box : HUGE_VAL;
+    for (int k = 0; k < 3; ++k) a.t3[k] = g.bins.t[std::min(k + 1, nb)];
     // bin estimates (bin_guess): exact after one correction while
     // nb rmax / (rmax - rmin) <= 2^20
     {
