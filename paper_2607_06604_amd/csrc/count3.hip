@@ -86,6 +86,13 @@ struct C3Args {
 };
 
 constexpr int kUnroll3 = 4;              // steps per lane per pass
+// Weighted unanchored counts (no register cap: their LDS allows fewer work
+// groups) keep more row loads in flight: 6 steps per pass (8 would spill,
+// as would 6 with the anchored bookkeeping).
+constexpr int kUnroll3W = 6;
+__host__ __device__ constexpr int unroll3(bool weighted, bool anchored) {
+    return weighted && !anchored ? kUnroll3W : kUnroll3;
+}
 constexpr int kLutMaxBins = 24;          // nb^3 u16 table up to 27 KB
 constexpr int kCubeMaxBins = 16;         // nb^3 u32 counters up to 16 KB
 constexpr int kMaxGroup = 4;             // hubs per group: two bits in a step entry
@@ -320,7 +327,7 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk,
 // branch.
 template <int BLOCK, bool PACK, int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WIDE, bool WGEN>
 __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned long long &mytri) {
-    constexpr int U = kUnroll3;
+    constexpr int U = unroll3(WEIGHTED, ANCHORED);
     const uint32_t glog = (uint32_t)c.glog;
     const uint32_t sub = threadIdx.x & ((1u << glog) - 1u);
     const uint32_t per = (uint32_t)BLOCK >> glog;
@@ -749,7 +756,8 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
                         const uint32_t cnt = min(S, len - r);
                         tab[s - w0] = make_uint2((st + r) | xhub, cnt | ((uint32_t)tid << 7) | (xv << 16));
                     }
-                    for (uint32_t s = tid; s < kUnroll3 * (BLOCK >> glog); s += BLOCK) tab[nfill + s] = make_uint2(0u, 0u);
+                    for (uint32_t s = tid; s < unroll3(WEIGHTED, ANCHORED) * (BLOCK >> glog); s += BLOCK)
+                        tab[nfill + s] = make_uint2(0u, 0u);
                     __syncthreads();
                     walk3_any<BLOCK, WEIGHTED, ANCHORED, LDS_HIST, WIDE>(a.packed, a.mode, c, nfill, mytri);
                     __syncthreads();
@@ -1123,7 +1131,7 @@ Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchore
                 if (tmax_pin && tf) continue;
                 const uint32_t tmax = std::max<uint32_t>(
                     64, std::min<uint32_t>(1 << 16, tmax_pin ? (uint32_t)tmax_pin : (tf ? 1u : 2u) * p.block));
-                const uint32_t tcap = tmax + kUnroll3 * ((uint32_t)p.block >> p.glog);
+                const uint32_t tcap = tmax + unroll3(weighted, anchored) * ((uint32_t)p.block >> p.glog);
                 for (int lh = lds_hist_ok; lh >= 0; --lh) {
                     // the cube lives in LDS; table entries hold 16-bit counter addresses
                     int mode = mode0;
