@@ -75,14 +75,18 @@ struct Layout4 {
 
 // A staged vertex of N+(i) in LDS, one record per local index: doubles
 // x, y, z, q, sx, sy, sz, w (the parity kinds: position, squared spoke
-// length, spoke from the hub, weight) or x, y, z and, in weighted counts, w
-// (the 6-edge kind), so a vertex's fields share one address and load in
-// pairs.
+// length, spoke from the hub, weight; then padding) or x, y, z and, in
+// weighted counts, w (the 6-edge kind), so a vertex's fields share one
+// address and load in pairs.
 template <int KIND, bool WEIGHTED> struct VRec {
-    // 64-byte records for the parity kinds (the weight slot unused when
-    // unweighted: the aligned stride measured faster than 56 bytes)
-    static constexpr int ST = KIND == kSix4 ? (WEIGHTED ? 4 : 3) : 8;   // doubles per record
-    static constexpr int W = ST - 1;                                           // the weight's slot
+    // 80-byte records for the parity kinds (two slots of padding, and the
+    // weight slot unused when unweighted): 16-byte aligned fields load as
+    // 128-bit pairs, and the stride puts the records of 8 consecutive
+    // vertices on 8 distinct 4-bank groups (5 v mod 8). Measured: 80 bytes
+    // 224.5 ms, 64 bytes 232.9 ms, 72 bytes 239.8 ms on the 2e5-point
+    // parity count.
+    static constexpr int ST = KIND == kSix4 ? (WEIGHTED ? 4 : 3) : 10;   // doubles per record
+    static constexpr int W = KIND == kSix4 ? ST - 1 : 7;                       // the weight's slot
 };
 constexpr int kVx = 0, kVq = 3, kVs = 4;   // slots: position, squared length, spoke
 
@@ -109,7 +113,7 @@ __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxde
     Layout4 L{};
     uint32_t o = 0, d = maxdeg + 1;
     const bool spokes = kind != kSix4;   // hub spokes and lengths: the parity kinds
-    L.pv = o;      o = lds_align(o + 8 * (spokes ? 8 : (weighted ? 4 : 3)) * d, 16);
+    L.pv = o;      o = lds_align(o + 8 * (spokes ? 10 : (weighted ? 4 : 3)) * d, 16);
     L.wlo = o;     if (weighted) o = lds_align(o + 8 * ncnt, 16);
     L.whi = o;     if (weighted) o = lds_align(o + 8 * ncnt, 16);
     L.thr = o;     o = lds_align(o + 8 * (nb + 1), 16);
@@ -270,7 +274,7 @@ template <int ST> __device__ __forceinline__ P3 vspoke(const Stage4 &S, uint32_t
 }
 template <int ST> __device__ __forceinline__ double vq(const Stage4 &S, uint32_t v) { return S.pv[ST * v + kVq]; }
 template <int ST> __device__ __forceinline__ double vw(const Stage4 &S, uint32_t v) {
-    return S.pv[ST * v + ST - 1];
+    return S.pv[ST * v + (ST >= 8 ? 7 : ST - 1)];   // VRec::W
 }
 
 // Bin of the squared separation q of a graph edge (t_0 <= q < t_nb): the
@@ -400,7 +404,7 @@ __device__ __forceinline__ uint32_t conf_addr(const Stage4 &S, uint32_t hist_add
 template <bool LUT, bool WEIGHTED>
 __device__ __forceinline__ void eval_clique(const Stage4 &S, uint32_t hist_addr, uint32_t va, uint32_t vb,
                                             uint32_t vc, double eb, bool wrap, double wi) {
-    constexpr int ST = VRec<kParity4, WEIGHTED>::ST;   // 8
+    constexpr int ST = VRec<kParity4, WEIGHTED>::ST;
     const double qa = vq<ST>(S, va), qb = vq<ST>(S, vb), qc = vq<ST>(S, vc);
     const int ba = S.pb[va], bb = S.pb[vb], bc = S.pb[vc];
     double qab, qac, qbc, Vc;
@@ -616,7 +620,7 @@ __global__ __launch_bounds__(BLOCK) void k_count4(C4Args a) {
     uint16_t *hloc = (uint16_t *)(sm + L.hloc);
     uint16_t *hslot = (uint16_t *)(sm + L.hslot);
     constexpr int ST = VRec<KIND, WEIGHTED>::ST;
-    double *pv = (double *)(sm + L.pv);
+    double *pv = (double *)__builtin_assume_aligned(sm + L.pv, 16);   // lds_align(.., 16)
     uint8_t *pb = (uint8_t *)(sm + L.pb);
     uint32_t *pperm = (uint32_t *)(sm + L.pperm);
     uint32_t *R = (uint32_t *)(sm + L.R);
