@@ -75,18 +75,20 @@ struct Layout4 {
 
 // A staged vertex of N+(i) in LDS, one record per local index: doubles
 // x, y, z, q, sx, sy, sz, w (the parity kinds: position, squared spoke
-// length, spoke from the hub, weight; then padding) or x, y, z and, in
-// weighted counts, w (the 6-edge kind), so a vertex's fields share one
-// address and load in pairs.
+// length, spoke from the hub, weight; then padding) or x, y, z, w (the
+// 6-edge kind; then padding), so a vertex's fields share one address and
+// load in pairs (w only in weighted counts).
 template <int KIND, bool WEIGHTED> struct VRec {
-    // 80-byte records for the parity kinds (two slots of padding, and the
-    // weight slot unused when unweighted): 16-byte aligned fields load as
-    // 128-bit pairs, and the stride puts the records of 8 consecutive
-    // vertices on 8 distinct 4-bank groups (5 v mod 8). Measured: 80 bytes
-    // 224.5 ms, 64 bytes 232.9 ms, 72 bytes 239.8 ms on the 2e5-point
-    // parity count.
-    static constexpr int ST = KIND == kSix4 ? (WEIGHTED ? 4 : 3) : 10;   // doubles per record
-    static constexpr int W = KIND == kSix4 ? ST - 1 : 7;                       // the weight's slot
+    // 16-byte aligned records load as 128-bit pairs. The parity kind takes
+    // 80 bytes (two slots of padding; the weight slot unused when
+    // unweighted): the stride puts 8 consecutive records on 8 distinct
+    // 4-bank groups (5 v mod 8); measured 224.5 ms against 232.9 (64 bytes)
+    // and 239.8 (72) on the 2e5-point parity count. The 6-edge kind takes
+    // 48 (3 v mod 8; 159.5 ms against 166.3 for 24), the pixel kind 64
+    // (its LDS holds the pixel directions too: 80 bytes cost it a work
+    // group per CU).
+    static constexpr int ST = KIND == kSix4 ? 6 : (KIND == kPixel4 ? 8 : 10);   // doubles per record
+    static constexpr int W = KIND == kSix4 ? 3 : 7;                               // the weight's slot
 };
 constexpr int kVx = 0, kVq = 3, kVs = 4;   // slots: position, squared length, spoke
 
@@ -113,7 +115,7 @@ __host__ __device__ inline Layout4 layout4(int block, uint32_t H, uint32_t maxde
     Layout4 L{};
     uint32_t o = 0, d = maxdeg + 1;
     const bool spokes = kind != kSix4;   // hub spokes and lengths: the parity kinds
-    L.pv = o;      o = lds_align(o + 8 * (spokes ? 10 : (weighted ? 4 : 3)) * d, 16);
+    L.pv = o;      o = lds_align(o + 8 * (kind == kSix4 ? 6 : (kind == kPixel4 ? 8 : 10)) * d, 16);
     L.wlo = o;     if (weighted) o = lds_align(o + 8 * ncnt, 16);
     L.whi = o;     if (weighted) o = lds_align(o + 8 * ncnt, 16);
     L.thr = o;     o = lds_align(o + 8 * (nb + 1), 16);
@@ -274,7 +276,7 @@ template <int ST> __device__ __forceinline__ P3 vspoke(const Stage4 &S, uint32_t
 }
 template <int ST> __device__ __forceinline__ double vq(const Stage4 &S, uint32_t v) { return S.pv[ST * v + kVq]; }
 template <int ST> __device__ __forceinline__ double vw(const Stage4 &S, uint32_t v) {
-    return S.pv[ST * v + (ST >= 8 ? 7 : ST - 1)];   // VRec::W
+    return S.pv[ST * v + (ST >= 8 ? 7 : 3)];   // VRec::W
 }
 
 // Bin of the squared separation q of a graph edge (t_0 <= q < t_nb): the
