@@ -369,31 +369,44 @@ __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned l
             }
             key[u] = c.hkey[hh[u]];
         }
-        // 3. probe sequences to their ends: hit flag and the bin of (hub, k)
-        bool hit[U];
+        // 3. probe sequences to their ends, the U chains advanced together
+        //    (one LDS round trip per step of the longest, not per chain):
+        //    hit flag and the bin of (hub, k)
+        bool hit[U], live[U];
         uint32_t yy[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            hit[u] = false;
+            const uint32_t kv = key[u];
+            live[u] = ok[u] && (PACK ? ((kv ^ kk[u]) & c.qmask) != 0 : kv != kk[u]) && kv != kEmptyKey;
+        }
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) any |= live[u];
+        while (any) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (live[u]) {
+                    hh[u] = (hh[u] + 1) & c.mask;
+                    key[u] = c.hkey[hh[u]];
+                }
+            any = false;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t kv = key[u];
+                live[u] = live[u] && (PACK ? ((kv ^ kk[u]) & c.qmask) != 0 : kv != kk[u]) && kv != kEmptyKey;
+                any |= live[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t kv = key[u];
+            hit[u] = ok[u] && kv != kEmptyKey && (PACK || kv == kk[u]);
             yy[u] = 0;
-            if (!ok[u]) continue;
-            const uint32_t q = kk[u];
-            uint32_t h = hh[u], kv = key[u];
             if (PACK) {
-                while (((kv ^ q) & c.qmask) != 0 && kv != kEmptyKey) {
-                    h = (h + 1) & c.mask;
-                    kv = c.hkey[h];
-                }
-                hit[u] = kv != kEmptyKey;
                 yy[u] = kv >> c.ys;
-                kk[u] = q & 0xFFFFFFu;
-            } else {
-                while (kv != q && kv != kEmptyKey) {
-                    h = (h + 1) & c.mask;
-                    kv = c.hkey[h];
-                }
-                hit[u] = kv == q;
-                if (hit[u]) yy[u] = c.hbin[h];
+                kk[u] &= 0xFFFFFFu;
+            } else if (hit[u]) {
+                yy[u] = c.hbin[hh[u]];
             }
         }
         // 4. the third vertex's weight / original index, loaded for all hits
