@@ -60,7 +60,10 @@ struct CeilArgs {
     unsigned long long *sink;
 };
 
-constexpr int kCeilU = 4;
+// candidates per lane per pass, and the probe chains: as the triangle
+// count runs them (six steps per pass one chain at a time when weighted,
+// four advanced together otherwise)
+template <bool WEIGHTED> constexpr int ceil_unroll() { return WEIGHTED ? 6 : 4; }
 
 // LDS: configuration-table counter addresses (u16, nb^3) | counters (u32,
 // nconf) | u64 halves (weighted) | hash table (u32, packed bin << 26 | key).
@@ -102,6 +105,7 @@ __global__ __launch_bounds__(BLOCK) void k_ceil_probe(CeilArgs a) {
 
     const uint64_t base = (uint64_t)blockIdx.x * 7919ull * BLOCK;
     const double hw = a.w[blockIdx.x & 1023];
+    constexpr int kCeilU = ceil_unroll<WEIGHTED>();
     for (uint64_t i0 = 0; i0 < a.per_group; i0 += (uint64_t)kCeilU * BLOCK) {
         uint32_t kk[kCeilU], zz[kCeilU], xx[kCeilU], hh[kCeilU], kv[kCeilU];
         // the spoke's bin: one per pass of the work group (uniform)
@@ -126,7 +130,33 @@ __global__ __launch_bounds__(BLOCK) void k_ceil_probe(CeilArgs a) {
                 yy[u] = kk[u] % (uint32_t)nb;
             }
         }
-        if (PROBE) {
+        if (PROBE && !WEIGHTED) {
+            bool live[kCeilU], any = false;
+#pragma unroll
+            for (int u = 0; u < kCeilU; ++u) {
+                live[u] = ((kv[u] ^ kk[u]) & 0x3FFFFFFu) != 0 && kv[u] != kEmptyKey;
+                any |= live[u];
+            }
+            while (any) {
+#pragma unroll
+                for (int u = 0; u < kCeilU; ++u)
+                    if (live[u]) {
+                        hh[u] = (hh[u] + 1) & hmask;
+                        kv[u] = tab[hh[u]];
+                    }
+                any = false;
+#pragma unroll
+                for (int u = 0; u < kCeilU; ++u) {
+                    live[u] = live[u] && ((kv[u] ^ kk[u]) & 0x3FFFFFFu) != 0 && kv[u] != kEmptyKey;
+                    any |= live[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kCeilU; ++u) {
+                hit[u] = kv[u] != kEmptyKey;
+                yy[u] = kv[u] >> 26;
+            }
+        } else if (PROBE) {
 #pragma unroll
             for (int u = 0; u < kCeilU; ++u) {
                 uint32_t h = hh[u], v = kv[u];
@@ -175,7 +205,7 @@ double run_probe(Ctx &ctx, const CeilArgs &a, uint32_t lds) {
     hipStream_t s = ctx.stream;
     // warm-up, then the timed launch
     CeilArgs w = a;
-    w.per_group = std::max<uint64_t>(kCeilU * BLOCK, a.per_group / 16);
+    w.per_group = std::max<uint64_t>((uint64_t)ceil_unroll<WEIGHTED>() * BLOCK, a.per_group / 16);
     k_ceil_probe<BLOCK, PROBE, WEIGHTED><<<grid, BLOCK, lds, s>>>(w);
     GS_HIP(hipGetLastError());
     GS_HIP(hipEventRecord(ctx.ev[0], s));
@@ -185,7 +215,10 @@ double run_probe(Ctx &ctx, const CeilArgs &a, uint32_t lds) {
     GS_HIP(hipEventSynchronize(ctx.ev[1]));
     float ms = 0;
     GS_HIP(hipEventElapsedTime(&ms, ctx.ev[0], ctx.ev[1]));
-    return (double)a.per_group * (double)grid / (ms * 1e-3);
+    // every pass takes U * BLOCK candidates per work group
+    const uint64_t pass = (uint64_t)ceil_unroll<WEIGHTED>() * BLOCK;
+    const uint64_t done = (a.per_group + pass - 1) / pass * pass;
+    return (double)done * (double)grid / (ms * 1e-3);
 }
 
 }  // namespace
