@@ -220,7 +220,7 @@ __device__ __forceinline__ int graph_of(const GDesc *gd, int ng, uint32_t v) {
 
 // What the walk over one step table reads or updates.
 struct Walk {
-    const uint2 *tab;             // steps: (row offset, entries | slot << 7 | x term << 16)
+    const uint2 *tab;             // steps: (row offset, entries - 1 | slot << 6 | x term << 16)
     const uint32_t *hkey;         // hub hash
     const uint8_t *hbin;          // hub bins per slot (unpacked hash)
     const int *ta, *tb;           // rank tables
@@ -251,7 +251,7 @@ template <int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WGEN>
 __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk, uint32_t meta, uint32_t y,
                                           uint32_t z, uint32_t hub, unsigned long long &mytri) {
     // pk, wk: original index and weight of the third vertex (anchored / weighted)
-    const uint32_t slot = (meta >> 7) & 511u;
+    const uint32_t slot = (meta >> 6) & 1023u;
     if (ANCHORED) {
         const uint32_t mm = min(c.hp[hub], min(c.mperm[slot], pk));
         if (mm < c.anchor_lo || mm >= c.anchor_hi) return;
@@ -343,7 +343,7 @@ __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned l
             kk[u] = zz[u] = meta[u] = hub[u] = 0;
             if (base + u * per < nsteps) {
                 const uint2 e = tp[base + u * per];
-                ok[u] = sub < (e.y & 127u);
+                ok[u] = sub <= (e.y & 63u);
                 meta[u] = e.y;
                 if (WIDE) {
                     const uint32_t pos = e.x + sub;
@@ -487,9 +487,10 @@ __device__ __forceinline__ void walk3_any(bool packed, int mode, const Walk &c, 
 // Plain unbatched counts fit 64 VGPRs: eight wavefronts per SIMD.
 // SEG (with WIDE): a hub's spoke rows may lie more than the segment span
 // apart (graphs of 2^32 or more forward entries), so chunks whose rows spread
-// that far go in segments.
+// that far go in segments. Weighted 768-thread groups run two per CU: six
+// wavefronts per SIMD.
 template <int BLOCK, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool BATCH, bool WIDE, bool SEG = false>
-__global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count3(C3Args a) {
+__global__ __launch_bounds__(BLOCK, BLOCK == 768 ? 6 : (WEIGHTED || ANCHORED) ? 1 : 8) void k_count3(C3Args a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const uint32_t H = 1u << a.log2h, mask = H - 1;
     const Layout3 L = layout3(BLOCK, H, a.maxdeg, a.tcap, a.nconf, a.nb, WEIGHTED, ANCHORED, LDS_HIST,
@@ -798,7 +799,7 @@ __global__ __launch_bounds__(BLOCK, (WEIGHTED || ANCHORED) ? 1 : 8) void k_count
                     for (uint32_t s = lo; s < hi; ++s) {
                         const uint32_t r = (s - t0) << glog;
                         const uint32_t cnt = min(S, len - r);
-                        tab[s - w0] = make_uint2((st + r) | xhub, cnt | ((uint32_t)tid << 7) | (xv << 16));
+                        tab[s - w0] = make_uint2((st + r) | xhub, (cnt - 1) | ((uint32_t)tid << 6) | (xv << 16));
                     }
                     for (uint32_t s = tid; s < unroll3(WEIGHTED, ANCHORED) * (BLOCK >> glog); s += BLOCK)
                         tab[nfill + s] = make_uint2(0u, 0u);
@@ -1106,6 +1107,14 @@ void set_groups(C3Args &a, const Plan3 &P, int nb, bool wide, const Tune3 &tune)
 
 void launch3_any(Ctx &ctx, hipStream_t s, const C3Args &a, const Plan3 &P, bool w, bool an, bool wide,
                  bool seg = false) {
+    if (P.block == 768) {
+        // weighted, unanchored, LDS counters only (plan3)
+        if (!w || an || !P.lds_hist) fail(GS_EUNSUPPORTED, "768-thread plan outside weighted LDS counts");
+        if (wide && seg) launch3<768, true, false, true, false, true, true>(ctx, s, a, P.lds);
+        else if (wide) launch3<768, true, false, true, false, true>(ctx, s, a, P.lds);
+        else launch3<768, true, false, true, false, false>(ctx, s, a, P.lds);
+        return;
+    }
     if (wide && seg) {
         if (P.block == 512) launch3_bw<512, true, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
         else if (P.block == 128) launch3_bw<128, true, true>(ctx, s, a, P.lds, w, an, P.lds_hist);
@@ -1136,9 +1145,21 @@ Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchore
     if (const char *ep = getenv("GS_PACK")) p.packed = p.packed && atoi(ep) != 0;
     const int nconf = (int)n_configs(nb);
     if (maxdeg > 16384) fail(GS_EUNSUPPORTED, "forward degree above 16384");
-    if (const char *eb = getenv("GS_BLOCK3")) p.block = atoi(eb) == 512 ? 512 : atoi(eb) == 128 ? 128 : 256;
-    else if (tune.block > 0) p.block = tune.block == 512 ? 512 : 256;
-    else p.block = maxdeg >= 1024 ? 512 : 256;
+    // 768 threads only for weighted unanchored counts with LDS counters
+    // (their LDS allows two groups of 512 per CU where the unweighted plan
+    // fits three: two of 768 restore the wavefronts)
+    const bool lds_hist_ok = nconf <= 8192;
+    const bool w768 = weighted && !anchored && lds_hist_ok;
+    bool block_pin = true;
+    if (const char *eb = getenv("GS_BLOCK3")) {
+        const int b = atoi(eb);
+        p.block = b == 768 && w768 ? 768 : b == 512 || b == 768 ? 512 : b == 128 ? 128 : 256;
+    } else if (tune.block > 0) {
+        p.block = tune.block == 768 && w768 ? 768 : tune.block >= 512 ? 512 : 256;
+    } else {
+        p.block = maxdeg >= 1024 ? 512 : 256;
+        block_pin = false;
+    }
     int tmax_pin = tune.tmax > 0 ? tune.tmax : 0;
     if (const char *em = getenv("GS_TMAX")) tmax_pin = atoi(em);
     // the per-spoke binary search pays off on long rows only
@@ -1148,8 +1169,8 @@ Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchore
     if (const char *et = getenv("GS_TRUNC")) p.trunc = atoi(et) != 0;
     else if (tune.trunc >= 0) p.trunc = tune.trunc != 0;
     else p.trunc = maxdeg >= 32;
-    // per-work-group LDS counters while they fit; global atomics beyond
-    const bool lds_hist_ok = nconf <= 8192;
+    // per-work-group LDS counters while they fit (lds_hist_ok); global
+    // atomics beyond
     int want = nb <= kLutMaxBins ? kLut : kRank;
     bool mode_pin = false;
     if (tune.mode == kRank) want = kRank, mode_pin = true;
@@ -1163,6 +1184,10 @@ Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchore
     }
     const int hload_pin = tune.hload;   // 5: load <= 1/2, 7: load <= 0.7
     int best_waves = -1;
+    const int blocks[2] = {p.block, 768};
+    const int nblocks = !block_pin && w768 && p.block == 512 ? 2 : 1;
+    for (int bi = 0; bi < nblocks; ++bi) {
+    const int blk = blocks[bi];
     for (int hl : {5, 7}) {
         if (hload_pin && hl != hload_pin) continue;
         uint32_t H = 64;
@@ -1174,20 +1199,22 @@ Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchore
             for (int tf = 0; tf < 2; ++tf) {
                 if (tmax_pin && tf) continue;
                 const uint32_t tmax = std::max<uint32_t>(
-                    64, std::min<uint32_t>(1 << 16, tmax_pin ? (uint32_t)tmax_pin : (tf ? 1u : 2u) * p.block));
-                const uint32_t tcap = tmax + unroll3(weighted, anchored) * ((uint32_t)p.block >> p.glog);
+                    64, std::min<uint32_t>(1 << 16, tmax_pin ? (uint32_t)tmax_pin : (tf ? 1u : 2u) * blk));
+                const uint32_t tcap = tmax + unroll3(weighted, anchored) * ((uint32_t)blk >> p.glog);
                 for (int lh = lds_hist_ok; lh >= 0; --lh) {
                     // the cube lives in LDS; table entries hold 16-bit counter addresses
                     int mode = mode0;
                     if (mode == kCube && !lh) mode = nb <= kLutMaxBins ? kLut : kRank;
                     if (mode == kLut && lh && 4 * (uint64_t)nconf + 2 * (uint64_t)nb * nb * nb >= 65536) mode = kRank;
-                    const Layout3 L = layout3(p.block, H, maxdeg, tcap, nconf, nb, weighted, anchored, lh, p.packed,
+                    const Layout3 L = layout3(blk, H, maxdeg, tcap, nconf, nb, weighted, anchored, lh, p.packed,
                                               mode);
                     if ((int)L.total > ctx.max_lds) continue;
+                    if (blk == 768 && !lh) continue;
                     const int groups = std::max(1, ctx.max_lds / (int)L.total);
-                    const int waves = std::min(32, groups * p.block / 64);
+                    const int waves = std::min(32, groups * blk / 64);
                     if (waves > best_waves) {
                         best_waves = waves;
+                        p.block = blk;
                         p.lds_hist = lh;
                         p.mode = mode;
                         p.lds = L.total;
@@ -1200,6 +1227,7 @@ Plan3 plan3(const Ctx &ctx, uint32_t maxdeg, int nb, bool weighted, bool anchore
                 }
             }
         }
+    }
     }
     if (best_waves < 0) fail(GS_EUNSUPPORTED, "LDS footprint too large for this degree");
     if (getenv("GS_PLAN_LOG"))

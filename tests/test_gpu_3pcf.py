@@ -277,6 +277,11 @@ KERNEL_PLANS = [
     # than 2^32 entries apart do at full size)
     {"GS_BLOCK3": "256", "GS_GLOG": "4", "GS_WIDE": "1", "GS_WIDE_SPAN": "3000"},
     {"GS_BLOCK3": "512", "GS_GLOG": "6", "GS_WIDE": "1", "GS_WIDE_SPAN": "1", "GS_TRUNC": "0"},
+    # 768-thread groups (weighted unanchored counts take them; the anchored,
+    # unweighted and batched counts of the same plan fall back to 512)
+    {"GS_BLOCK3": "768", "GS_GLOG": "6"},
+    {"GS_BLOCK3": "768", "GS_GLOG": "3", "GS_TMAX": "100", "GS_MODE3": "rank"},
+    {"GS_BLOCK3": "768", "GS_GLOG": "5", "GS_WIDE": "1", "GS_WIDE_SPAN": "3000"},
 ]
 
 

@@ -212,6 +212,22 @@ def test_weighted_count3_signed_tiled(ctx, monkeypatch):
     assert got.wsum_int() == ref.wsum_int() and np.array_equal(got.hist, ref.hist)
 
 
+@pytest.mark.parametrize("block", ["768", "512"])
+def test_weighted_count3_signed_plans(ctx, monkeypatch, block):
+    # signed and wide terms (the general path) in 768- and 512-thread groups
+    x = synth.neyman_scott(20000, 40, 1.5, 80.0, 565)
+    w = signed_weights(len(x), 566)
+    w[::211] *= 300.0    # some terms beyond 2^63: straight into the 128-bit sums
+    ref = oracle.count_3pcf(x, 80.0, 0.0, 3.5, 10, weights=w)
+    monkeypatch.setenv("GS_BLOCK3", block)
+    monkeypatch.setenv("GS_GLOG", "4")
+    g = ctx.build_graph(x, 80.0, 0.0, 3.5, 10, weights=w)
+    got = ctx.count_3pcf(g, weighted=True)
+    g.free()
+    assert got.wscale == ref.wscale and got.wsum_int() == ref.wsum_int()
+    assert np.array_equal(got.hist, ref.hist)
+
+
 def test_weight_range_limits(ctx, gsn):
     """Magnitudes far apart: most terms fit 64 bits, the widest do not and go
     straight into the 128-bit sums; beyond 2^87 both sides refuse."""
