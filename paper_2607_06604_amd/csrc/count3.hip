@@ -322,16 +322,17 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk,
 // Steps [0, nsteps) of the table: lane group g (2^glog lanes) of the work
 // group takes steps g, g + G, ... (G groups), U of them per pass with their
 // row loads issued back to back; lane s of a group probes entry s of its
-// step. The table is padded with empty steps past nsteps, and lanes past
-// the end of a step load (and ignore) the row slack, so the loads need no
-// branch.
+// step. The table is padded past nsteps (a lane group whose step lies at or
+// past nsteps takes no entries), and lanes past the end of a step load (and
+// ignore) the row slack, so the loads need no branch.
 template <int BLOCK, bool PACK, int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WIDE, bool WGEN>
 __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned long long &mytri) {
     constexpr int U = unroll3(WEIGHTED, ANCHORED);
     const uint32_t glog = (uint32_t)c.glog;
     const uint32_t sub = threadIdx.x & ((1u << glog) - 1u);
     const uint32_t per = (uint32_t)BLOCK >> glog;
-    const uint2 *tp = c.tab + (threadIdx.x >> glog);
+    const uint32_t gsub = threadIdx.x >> glog;   // this lane group's step in a pass slot
+    const uint2 *tp = c.tab + gsub;
     for (uint32_t base = 0; base < nsteps; base += U * per) {
         uint32_t kk[U], zz[U], meta[U], hub[U], hh[U], key[U];
         bool ok[U];
@@ -343,7 +344,8 @@ __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned l
             kk[u] = zz[u] = meta[u] = hub[u] = 0;
             if (base + u * per < nsteps) {
                 const uint2 e = tp[base + u * per];
-                ok[u] = sub <= (e.y & 63u);
+                // steps past the table's end (padding) hold no entries
+                ok[u] = base + u * per + gsub < nsteps && sub <= (e.y & 63u);
                 meta[u] = e.y;
                 if (WIDE) {
                     const uint32_t pos = e.x + sub;
