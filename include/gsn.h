@@ -300,7 +300,7 @@ int gs_count_3pcf_batch(gs_ctx *ctx, const gs_graph *const *graphs, int ng, uint
  *  flags: GS_WEIGHTED tunes weighted counts (g must be weighted);
  *  out: nullable, host: the chosen schedule. Results never depend on it. */
 typedef struct {
-    int32_t block;       /* threads per work group (256 or 512)                 */
+    int32_t block;       /* threads per work group (256, 512, or 768 weighted)   */
     int32_t step_log2;   /* candidates per step = 2^step_log2 (0..6)            */
     int32_t group;       /* hubs per group (1..4)                                */
     int32_t table;       /* step table entries per fill                          */
@@ -454,7 +454,8 @@ int gs_compute_4pcf(gs_ctx *ctx, const gs_catalogue *data, const gs_catalogue *r
  *   nbins^3 configuration table and one LDS atomic (plus, weighted != 0,
  *   the weight gather, the exact triangle integer and two u64 LDS atomics).
  *   probe == 0 skips the hash (every candidate a hit): the LDS-atomic
- *   histogram ceiling at this bin count. block: 256 or 512 threads.
+ *   histogram ceiling at this bin count. block: 256 or 512 threads, or 768
+ *   (weighted only, as weighted counts of long rows run).
  *   *per_s = candidates per second. nbins 1..24. */
 int gs_ceiling_copy(gs_ctx *ctx, uint64_t bytes, double *gbs);
 int gs_ceiling_probe(gs_ctx *ctx, int32_t nbins, uint32_t table_log2, uint32_t keys_in_table,

@@ -67,8 +67,10 @@ template <bool WEIGHTED> constexpr int ceil_unroll() { return WEIGHTED ? 6 : 4; 
 
 // LDS: configuration-table counter addresses (u16, nb^3) | counters (u32,
 // nconf) | u64 halves (weighted) | hash table (u32, packed bin << 26 | key).
+// 768-thread groups (weighted, as the count runs them): six wavefronts per
+// SIMD, two groups per CU.
 template <int BLOCK, bool PROBE, bool WEIGHTED>
-__global__ __launch_bounds__(BLOCK) void k_ceil_probe(CeilArgs a) {
+__global__ __launch_bounds__(BLOCK, BLOCK == 768 ? 6 : 1) void k_ceil_probe(CeilArgs a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const int nb = a.nb, n3 = nb * nb * nb;
     const uint32_t H = 1u << a.log2h, hmask = H - 1;
@@ -259,7 +261,7 @@ int gs_ceiling_probe(gs_ctx *ctx, int32_t nbins, uint32_t table_log2, uint32_t k
     return guarded([&] {
         if (!ctx || !per_s || nbins < 1 || nbins > 24 || table_log2 < 6 || table_log2 > 15 ||
             keys_in_table > (1u << table_log2) * 7 / 10 || !(hit_rate > 0.0 && hit_rate <= 1.0) ||
-            (block != 256 && block != 512))
+            (block != 256 && block != 512 && !(block == 768 && weighted)))
             fail(GS_EINVAL, "bad argument");
         ctx->use();
         const int nconf = (int)n_configs(nbins);
@@ -288,7 +290,9 @@ int gs_ceiling_probe(gs_ctx *ctx, int32_t nbins, uint32_t table_log2, uint32_t k
         lds = lds_align(lds, 16) + 4 * (1u << table_log2);
         double r = 0;
         const bool W = weighted != 0, Pr = probe != 0;
-        if (block == 512) {
+        if (block == 768) {
+            r = Pr ? run_probe<768, true, true>(*ctx, a, lds) : run_probe<768, false, true>(*ctx, a, lds);
+        } else if (block == 512) {
             if (Pr) r = W ? run_probe<512, true, true>(*ctx, a, lds) : run_probe<512, true, false>(*ctx, a, lds);
             else r = W ? run_probe<512, false, true>(*ctx, a, lds) : run_probe<512, false, false>(*ctx, a, lds);
         } else {
