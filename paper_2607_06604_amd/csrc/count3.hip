@@ -220,7 +220,7 @@ __device__ __forceinline__ int graph_of(const GDesc *gd, int ng, uint32_t v) {
 
 // What the walk over one step table reads or updates.
 struct Walk {
-    const uint2 *tab;             // steps: (row offset, entries - 1 | slot << 6 | x term << 16)
+    const uint2 *tab;             // steps: (row offset, entries | slot << 7 | x term << 17)
     const uint32_t *hkey;         // hub hash
     const uint8_t *hbin;          // hub bins per slot (unpacked hash)
     const int *ta, *tb;           // rank tables
@@ -244,32 +244,33 @@ struct Walk {
 };
 
 // One hit: bins x (spoke, in the step's x term), y (hub table), z (row).
-// The x term is the LDS byte address of plane x of the ordered-triple
-// counters (kCube) or of row x of the configuration table (kLut), whose
-// entries are counter addresses (or indices); with kRank it is x itself.
+// The x term is the LDS address, in 2-byte units, of plane x of the
+// ordered-triple counters (kCube) or of row x of the configuration table
+// (kLut), whose entries are counter addresses (or indices); with kRank it is
+// x itself.
 template <int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WGEN>
 __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk, uint32_t meta, uint32_t y,
                                           uint32_t z, uint32_t hub, unsigned long long &mytri) {
     // pk, wk: original index and weight of the third vertex (anchored / weighted)
-    const uint32_t slot = (meta >> 6) & 1023u;
+    const uint32_t slot = (meta >> 7) & 1023u;
     if (ANCHORED) {
         const uint32_t mm = min(c.hp[hub], min(c.mperm[slot], pk));
         if (mm < c.anchor_lo || mm >= c.anchor_hi) return;
     }
     if (MODE == kCube) {
         // y, z < 256 and nb <= 16: 24-bit multiply
-        const uint32_t addr = (meta >> 16) + 4 * ((y & 0xFFu) * ((uint32_t)c.nb & 0xFFu) + z);
+        const uint32_t addr = 2 * (meta >> 17) + 4 * ((y & 0xFFu) * ((uint32_t)c.nb & 0xFFu) + z);
         __hip_atomic_fetch_add((lds_u32 *)(size_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         return;
     }
     uint32_t addr, idx;
     if (MODE == kLut) {
         // y, z < 256 and nb <= 24: 24-bit multiply
-        const uint32_t v = *(lds_u16 *)(size_t)((meta >> 16) + 2 * ((y & 0xFFu) * ((uint32_t)c.nb & 0xFFu) + z));
+        const uint32_t v = *(lds_u16 *)(size_t)(2 * ((meta >> 17) + (y & 0xFFu) * ((uint32_t)c.nb & 0xFFu) + z));
         addr = v;
         idx = LDS_HIST ? (v - c.hist_addr) >> 2 : v;
     } else {
-        const int x = (int)(meta >> 16);
+        const int x = (int)(meta >> 17);
         const int lo = min(x, min((int)y, (int)z)), hi = max(x, max((int)y, (int)z));
         const int mid = x + (int)y + (int)z - lo - hi;
         idx = (uint32_t)(c.ta[lo] + c.tb[mid] + hi);
@@ -322,17 +323,16 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk,
 // Steps [0, nsteps) of the table: lane group g (2^glog lanes) of the work
 // group takes steps g, g + G, ... (G groups), U of them per pass with their
 // row loads issued back to back; lane s of a group probes entry s of its
-// step. The table is padded past nsteps (a lane group whose step lies at or
-// past nsteps takes no entries), and lanes past the end of a step load (and
-// ignore) the row slack, so the loads need no branch.
+// step. The table is padded with empty steps past nsteps, and lanes past
+// the end of a step load (and ignore) the row slack, so the loads need no
+// branch.
 template <int BLOCK, bool PACK, int MODE, bool WEIGHTED, bool ANCHORED, bool LDS_HIST, bool WIDE, bool WGEN>
 __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned long long &mytri) {
     constexpr int U = unroll3(WEIGHTED, ANCHORED);
     const uint32_t glog = (uint32_t)c.glog;
     const uint32_t sub = threadIdx.x & ((1u << glog) - 1u);
     const uint32_t per = (uint32_t)BLOCK >> glog;
-    const uint32_t gsub = threadIdx.x >> glog;   // this lane group's step in a pass slot
-    const uint2 *tp = c.tab + gsub;
+    const uint2 *tp = c.tab + (threadIdx.x >> glog);
     for (uint32_t base = 0; base < nsteps; base += U * per) {
         uint32_t kk[U], zz[U], meta[U], hub[U], hh[U], key[U];
         bool ok[U];
@@ -344,8 +344,7 @@ __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned l
             kk[u] = zz[u] = meta[u] = hub[u] = 0;
             if (base + u * per < nsteps) {
                 const uint2 e = tp[base + u * per];
-                // steps past the table's end (padding) hold no entries
-                ok[u] = base + u * per + gsub < nsteps && sub <= (e.y & 63u);
+                ok[u] = sub < (e.y & 127u);
                 meta[u] = e.y;
                 if (WIDE) {
                     const uint32_t pos = e.x + sub;
@@ -743,8 +742,10 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 768 ? 6 : (WEIGHTED || ANCHORED) ? 
                         len0c = (uint32_t)(rp[j + 1] - rj);
                     }
                     const uint32_t x = hxb[sidx];
-                    xv = a.mode == kCube ? smb + L.cube + 4 * x * (uint32_t)(a.nb * a.nb)
-                         : a.mode == kLut ? smb + L.lut + 2 * x * (uint32_t)(a.nb * a.nb)
+                    // the x term: plane x's LDS address in 2-byte units (15
+                    // bits: LDS addresses are even and below 2^16), or x
+                    xv = a.mode == kCube ? (smb + L.cube + 4 * x * (uint32_t)(a.nb * a.nb)) >> 1
+                         : a.mode == kLut ? (smb + L.lut + 2 * x * (uint32_t)(a.nb * a.nb)) >> 1
                                           : x;
                     if (WEIGHTED) mw[tid] = a.w[j];
                     if (ANCHORED) mperm[tid] = a.perm[j];
@@ -801,7 +802,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 768 ? 6 : (WEIGHTED || ANCHORED) ? 
                     for (uint32_t s = lo; s < hi; ++s) {
                         const uint32_t r = (s - t0) << glog;
                         const uint32_t cnt = min(S, len - r);
-                        tab[s - w0] = make_uint2((st + r) | xhub, (cnt - 1) | ((uint32_t)tid << 6) | (xv << 16));
+                        tab[s - w0] = make_uint2((st + r) | xhub, cnt | ((uint32_t)tid << 7) | (xv << 17));
                     }
                     for (uint32_t s = tid; s < unroll3(WEIGHTED, ANCHORED) * (BLOCK >> glog); s += BLOCK)
                         tab[nfill + s] = make_uint2(0u, 0u);
