@@ -183,7 +183,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 768 ? 6 : 1) void k_ceil_probe(Ceil
                 if (p > q) { t = p; p = q; q = t; }
                 if (q > r) { t = q; q = r; r = t; }
                 if (p > q) { t = p; p = q; q = t; }
-                const unsigned long long ti = (unsigned long long)__dmul_rn(__dmul_rn(__dmul_rn(p, q), r), a.wmul);
+                const unsigned long long ti = big_term_u64(__dmul_rn(__dmul_rn(__dmul_rn(p, q), r), a.wmul));
                 const uint32_t idx = (addr - (smb + o_hist)) >> 2;
                 atomicAdd(&wlo[idx], ti & 0xFFFFFFFFull);
                 atomicAdd(&whi[idx], ti >> 32);

@@ -292,7 +292,7 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk,
         if (q > r) { t = q; q = r; r = t; }
         if (p > q) { t = p; p = q; q = t; }
         const double prod = __dmul_rn(__dmul_rn(p, q), r);
-        const unsigned long long ti = (unsigned long long)__dmul_rn(prod, c.wmul);
+        const unsigned long long ti = big_term_u64(__dmul_rn(prod, c.wmul));
         if (LDS_HIST) {
             atomicAdd(&c.wlo[idx], ti & 0xFFFFFFFFull);
             atomicAdd(&c.whi[idx], ti >> 32);

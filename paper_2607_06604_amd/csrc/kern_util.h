@@ -116,6 +116,17 @@ __device__ __forceinline__ __int128 wide_term(double x, bool neg) {
     return neg ? -v : v;
 }
 
+// A positive term known to lie in [2^52, 2^63) -- the scale puts every
+// product of weight magnitudes at or above 2^52, and narrow terms stay below
+// 2^63 -- as a 64-bit integer: its significand shifted left by its exponent
+// less 52 (0..10). Equal to the truncating conversion on that range, in four
+// integer instructions.
+__device__ __forceinline__ unsigned long long big_term_u64(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const uint32_t sh = (uint32_t)(b >> 52) - 1075u;
+    return ((b & 0xFFFFFFFFFFFFFull) | 0x10000000000000ull) << sh;
+}
+
 // A narrow term into LDS sums: its low 32 bits and its arithmetic high part
 // (term = high * 2^32 + low), each summed in 64 bits (room for 2^32 terms).
 __device__ __forceinline__ void lds_term(unsigned long long *lo, unsigned long long *hi, long long t) {
