@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(PairArgs a) {
                 const double x = __dmul_rn(__dmul_rn(fabs(wi), fabs(wj)), a.wmul);
                 const bool ng = (wi < 0.0) ^ (wj < 0.0);
                 if (narrow_term(x)) {
-                    const long long m = (long long)x;
+                    const long long m = (long long)big_term_u64(x);
                     lds_term(&slo[b], &shi[b], ng ? -m : m);
                 } else {
                     add128_words(&a.wsum[2 * b], wide_term(x, ng));

@@ -312,7 +312,7 @@ __device__ __forceinline__ void count_hit(const Walk &c, uint32_t pk, double wk,
         if (p > q) { t = p; p = q; q = t; }
         const double x = __dmul_rn(__dmul_rn(__dmul_rn(p, q), r), c.wmul);
         if (LDS_HIST && narrow_term(x)) {
-            const long long m = (long long)x;
+            const long long m = (long long)big_term_u64(x);
             lds_term(&c.wlo[idx], &c.whi[idx], ng ? -m : m);
         } else {
             add128_words(&c.wsum[2 * idx], wide_term(x, ng));

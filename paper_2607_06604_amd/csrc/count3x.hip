@@ -276,7 +276,7 @@ __global__ __launch_bounds__(BLOCK) void k_count3x(XArgs a) {
                     if (p > q) { tt = p; p = q; q = tt; }
                     const double xw = __dmul_rn(__dmul_rn(__dmul_rn(p, q), r), a.wmul);
                     if (narrow_term(xw)) {
-                        const long long m = (long long)xw;
+                        const long long m = (long long)big_term_u64(xw);
                         lds_term(&wlo[cnt], &whi[cnt], ng ? -m : m);
                     } else {
                         add128_words(&a.wsum[2 * cnt], wide_term(xw, ng));

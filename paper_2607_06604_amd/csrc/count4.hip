@@ -337,7 +337,7 @@ __device__ __forceinline__ double clique_term(double w0, double w1, double w2, d
 template <bool LDS_CNT>
 __device__ __forceinline__ void add_term(const Stage4 &S, uint32_t k, double x, bool neg) {
     if (LDS_CNT && narrow_term(x)) {
-        const long long m = (long long)x;
+        const long long m = (long long)big_term_u64(x);
         lds_term(&S.wlo[k], &S.whi[k], neg ? -m : m);
     } else {
         add128_words(&S.gwsum[2 * k], wide_term(x, neg));
