@@ -86,9 +86,10 @@ struct C3Args {
 };
 
 constexpr int kUnroll3 = 4;              // steps per lane per pass
-// Weighted unanchored counts (no register cap: their LDS allows fewer work
-// groups) keep more row loads in flight: 6 steps per pass (8 would spill,
-// as would 6 with the anchored bookkeeping).
+// Weighted unanchored counts (six wavefronts per SIMD at most: their LDS
+// allows two groups per CU) keep more row loads in flight: 6 steps per pass
+// (9.22 s on the 2e6-point weighted count against 9.44 with 5 and 9.56 with
+// 4; 7 or 8 would spill, as would 6 with the anchored bookkeeping).
 constexpr int kUnroll3W = 6;
 __host__ __device__ constexpr int unroll3(bool weighted, bool anchored) {
     return weighted && !anchored ? kUnroll3W : kUnroll3;
@@ -374,7 +375,7 @@ __device__ __forceinline__ void walk3(const Walk &c, uint32_t nsteps, unsigned l
         //    Unweighted walks advance the U chains together (one LDS round
         //    trip per step of the longest chain: 6.95 -> 6.84 ms on a 1e6-point
         //    clustered count); weighted walks, six steps per pass, run them
-        //    one after another (together: 11.34 -> 12.28 s on the 2e6-point
+        //    one after another (together: 9.22 -> 10.27 s on the 2e6-point
         //    weighted count).
         bool hit[U];
         uint32_t yy[U];
