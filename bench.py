@@ -503,7 +503,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the counts would shard by hub ranges with one final reduction of the bins).", file=sys.stderr)
         sys.exit(2)
 

@@ -48,7 +48,7 @@ extern "C" {
 #define GS_EHIP (-5)          /* HIP runtime error (see gs_last_error_detail) */
 #define GS_EAGAIN (-6)        /* submit queue full, retry later               */
 #define GS_ENOTFOUND (-7)     /* unknown ticket                               */
-#define GS_EUNSUPPORTED (-8)  /* valid input beyond this build's limits       */
+#define GS_EUNSUPPORTED (-8)  /* valid input beyond the library's limits      */
 #define GS_ENOCOORDS (-9)     /* parity count on a graph built without coords */
 
 /* ---- graph flags (gs_graph_params.flags) ---- */

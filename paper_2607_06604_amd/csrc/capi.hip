@@ -214,7 +214,7 @@ const char *gs_strerror(int code) {
         case GS_EHIP: return "HIP runtime error";
         case GS_EAGAIN: return "queue full, retry";
         case GS_ENOTFOUND: return "unknown ticket";
-        case GS_EUNSUPPORTED: return "input beyond this build's limits";
+        case GS_EUNSUPPORTED: return "input beyond the library's limits";
         case GS_ENOCOORDS: return "graph was built without coordinates";
         default: return "unknown status";
     }
